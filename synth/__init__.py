@@ -1,0 +1,355 @@
+"""Seeded synthetic inputs for the FC-SDNN hot path (geometry, states, weights).
+
+This module is shared by the FP64 oracle, the tests and the benchmark.  It
+holds no arithmetic of the numerical method itself: it only lays out patches,
+evaluates patch mappings and their closed-form inverse Jacobians (metric
+terms), draws initial states and random network weights.  Every draw comes
+from ``numpy.random.default_rng(seed)`` in a fixed order.
+
+Geometry follows the paper's patch description: each patch is the image of
+the unit square under a smooth map (Sec. 3.1, eq. for S-type patches
+M(q1,q2) = l_A(q1) + q2 H nu(q1)); the grid is uniform in parameter space
+(Sec. 3.2.1) with spacing h = 1/(N-1) along each direction; the metric terms
+are the entries of the Jacobian of the inverse map used in the curvilinear
+form of the equations (Sec. 3.3).  Initial states are the uniform Mach-M flow
+(rho, u, v, p) = (1.4, M, 0, 1) of Sec. 7 plus a small seeded perturbation, or
+smooth sinusoidal states on the unit square.
+
+Field layout: every field is one "plane" holding all patches back to back;
+patch p occupies [off[p], off[p] + n1[p]*n2[p]) with element (i, j) at
+off[p] + j*n1[p] + i (i runs along q1 and is contiguous).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+GAMMA = 1.4
+NV = 9          # boundary-vicinity / viscosity fringe width (Sec. 3.2.1, Sec. 3.4)
+NF = 5          # communication fringe width (Sec. 3.4)
+OVERLAP = 2 * NV + 1   # minimum overlap between neighbouring patches (Sec. 3.2.2)
+ALIGN = 64      # patch offsets are rounded up to this many elements
+
+
+def smooth13(n: int) -> bool:
+    for p in (2, 3, 5, 7, 11, 13):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def cont_points(n: int, c_min: int = 27) -> int:
+    """Number C of continuation points for a line of n points.
+
+    Smallest C >= c_min such that the periodic extension length n + C has no
+    prime factor above 13 (so an exact mixed-radix FFT exists).  For n = 64
+    and n = 512 this keeps C = 27 (L = 91 and 539)."""
+    c = c_min
+    while not smooth13(n + c):
+        c += 1
+    return c
+
+
+@dataclass
+class PatchSet:
+    n1: np.ndarray            # int32 [P] points along q1
+    n2: np.ndarray            # int32 [P] points along q2
+    C1: np.ndarray            # int32 [P] continuation points for q1 lines
+    C2: np.ndarray            # int32 [P] continuation points for q2 lines
+    d: int                    # matching points per line end
+    off: np.ndarray           # int64 [P] element offset of each patch in a plane
+    plane: int                # elements per plane (padded)
+    metric: np.ndarray        # float32 [4, plane]: dq1/dx, dq1/dy, dq2/dx, dq2/dy
+    htilde: np.ndarray        # float64 [P] lower bound of the physical grid spacing
+    hhat: np.ndarray          # float64 [P] upper bound of the physical grid spacing
+    internal: np.ndarray      # uint8 [P, 4] internal sides: q1-, q1+, q2-, q2+
+    xy: np.ndarray            # float64 [2, plane] physical coordinates
+    # multi-patch annulus coupling (None for independent patches)
+    nsec: int = 0
+    nshell: int = 0
+    dirichlet: Optional[np.ndarray] = None   # uint8 [plane]: freestream-overwrite points
+
+    @property
+    def npatch(self) -> int:
+        return len(self.n1)
+
+    @property
+    def npoints(self) -> int:
+        return int(np.sum(self.n1.astype(np.int64) * self.n2))
+
+    def view(self, arr: np.ndarray, p: int) -> np.ndarray:
+        """[..., plane] -> [..., n2, n1] view of patch p."""
+        o, a, b = int(self.off[p]), int(self.n1[p]), int(self.n2[p])
+        return arr[..., o:o + a * b].reshape(arr.shape[:-1] + (b, a))
+
+    def patch_of_shell(self, s: int, k: int) -> int:
+        return k * self.nsec + s
+
+
+def _offsets(n1, n2):
+    off = np.zeros(len(n1), np.int64)
+    acc = 0
+    for p in range(len(n1)):
+        off[p] = acc
+        acc += int(n1[p]) * int(n2[p])
+        acc = (acc + ALIGN - 1) // ALIGN * ALIGN
+    return off, acc
+
+
+def _polar_patches(specs, n1, n2, d, c_min):
+    """specs: list of (theta0, htheta, r0, hr) for polar-sector patches.
+
+    Patch map: x = r(q2) (cos t(q1), sin t(q1)), t = theta0 + q1*(n1-1)*htheta,
+    r = r0 + q2*(n2-1)*hr.  Inverse Jacobian in closed form."""
+    n1 = np.asarray(n1, np.int32)
+    n2 = np.asarray(n2, np.int32)
+    off, plane = _offsets(n1, n2)
+    metric = np.zeros((4, plane), np.float64)
+    xy = np.zeros((2, plane), np.float64)
+    htl = np.zeros(len(n1))
+    hht = np.zeros(len(n1))
+    for p, (t0, ht, r0, hr) in enumerate(specs):
+        a, b = int(n1[p]), int(n2[p])
+        th = t0 + ht * np.arange(a)
+        r = r0 + hr * np.arange(b)
+        T, R = np.meshgrid(th, r)          # [b, a]
+        span_t = (a - 1) * ht
+        span_r = (b - 1) * hr
+        o = int(off[p])
+        sl = slice(o, o + a * b)
+        xy[0, sl] = (R * np.cos(T)).ravel()
+        xy[1, sl] = (R * np.sin(T)).ravel()
+        metric[0, sl] = (-np.sin(T) / (R * span_t)).ravel()
+        metric[1, sl] = (np.cos(T) / (R * span_t)).ravel()
+        metric[2, sl] = (np.cos(T) / span_r).ravel()
+        metric[3, sl] = (np.sin(T) / span_r).ravel()
+        htl[p] = min(r0 * ht, hr)
+        hht[p] = max((r0 + span_r) * ht, hr)
+    C1 = np.array([cont_points(int(x), c_min) for x in n1], np.int32)
+    C2 = np.array([cont_points(int(x), c_min) for x in n2], np.int32)
+    return PatchSet(n1=n1, n2=n2, C1=C1, C2=C2, d=d, off=off, plane=plane,
+                    metric=metric.astype(np.float32), htilde=htl, hhat=hht,
+                    internal=np.zeros((len(n1), 4), np.uint8), xy=xy)
+
+
+def annulus(nsec: int, nshell: int, n1: int, n2: int, d: int = 5, c_min: int = 27,
+            r_in: float = 0.5, r_out: float = 2.0) -> PatchSet:
+    """Annulus r in [r_in, r_out] covered by nsec sectors x nshell shells of
+    n1 x n2 points.  Neighbouring sectors (and shells) overlap by 2*NV+1 grid
+    lines and sit on a common global index lattice, so the communication
+    between them is an index copy."""
+    ht = 2 * np.pi / (nsec * (n1 - OVERLAP))
+    hr = (r_out - r_in) / (nshell * (n2 - OVERLAP) + OVERLAP - 1)
+    specs = []
+    for k in range(nshell):
+        for s in range(nsec):
+            specs.append((s * (n1 - OVERLAP) * ht, ht, r_in + k * (n2 - OVERLAP) * hr, hr))
+    ps = _polar_patches(specs, [n1] * len(specs), [n2] * len(specs), d, c_min)
+    ps.nsec, ps.nshell = nsec, nshell
+    for k in range(nshell):
+        for s in range(nsec):
+            p = ps.patch_of_shell(s, k)
+            ps.internal[p] = (nsec > 1, nsec > 1, k > 0, k < nshell - 1)
+    # Dirichlet freestream on the outer circle where the flow enters (x < 0)
+    dm = np.zeros(ps.plane, np.uint8)
+    for s in range(nsec):
+        p = ps.patch_of_shell(s, nshell - 1)
+        v = ps.view(dm, p)
+        x = ps.view(ps.xy[0], p)
+        v[-1, :] = (x[-1, :] < 0).astype(np.uint8)
+    ps.dirichlet = dm
+    return ps
+
+
+def uneven_sectors(npatch: int, nmin: int, nmax: int, seed: int, d: int = 5,
+                   c_min: int = 27) -> PatchSet:
+    """Independent annulus-sector patches with side lengths drawn uniformly
+    from {nmin..nmax}; each spans the angular width of one of 16 overlapping
+    256-point sectors and the radial range [0.5, 2]."""
+    rng = np.random.default_rng(seed)
+    n1 = rng.integers(nmin, nmax + 1, npatch)
+    n2 = rng.integers(nmin, nmax + 1, npatch)
+    t0 = rng.uniform(0, 2 * np.pi, npatch)
+    span = (2 * np.pi / 16) * 255 / 237
+    specs = [(t0[p], span / (n1[p] - 1), 0.5, 1.5 / (n2[p] - 1)) for p in range(npatch)]
+    return _polar_patches(specs, n1, n2, d, c_min)
+
+
+def unit_square(n: int, d: int = 5, C: int = 27) -> PatchSet:
+    """One Cartesian patch on [0,1]^2 (identity metric)."""
+    n1 = np.array([n], np.int32)
+    off, plane = _offsets(n1, n1)
+    g = np.linspace(0, 1, n)
+    X, Y = np.meshgrid(g, g)
+    xy = np.zeros((2, plane))
+    xy[0, :n * n] = X.ravel()
+    xy[1, :n * n] = Y.ravel()
+    metric = np.zeros((4, plane), np.float32)
+    metric[0, :n * n] = 1
+    metric[3, :n * n] = 1
+    h = 1.0 / (n - 1)
+    return PatchSet(n1=n1, n2=n1.copy(), C1=np.array([C], np.int32), C2=np.array([C], np.int32),
+                    d=d, off=off, plane=plane, metric=metric, htilde=np.array([h]),
+                    hhat=np.array([h]), internal=np.zeros((1, 4), np.uint8), xy=xy)
+
+
+# ---------------------------------------------------------------- states
+
+def prim_to_cons(rho, u, v, p, gamma=GAMMA):
+    """Conserved variables (rho, rho u, rho v, E) with E = p/(gamma-1) + rho|u|^2/2
+    (ideal-gas closure, Sec. 2.1)."""
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1) + 0.5 * rho * (u * u + v * v)])
+
+
+@dataclass
+class Perturbation:
+    kappa: np.ndarray   # [K, 2] integer wave vectors in physical coordinates
+    psi: np.ndarray     # [K] phases
+    amp: np.ndarray     # [K] amplitudes a_k
+
+    def modes(self, xy):
+        """phi_k(x) = sin(2 pi kappa_k . x + psi_k), shape [K, npts]."""
+        return np.sin(2 * np.pi * (self.kappa @ xy) + self.psi[:, None])
+
+
+def draw_perturbation(rng, nmodes=16, level=0.01) -> Perturbation:
+    kap = []
+    while len(kap) < nmodes:
+        k = rng.integers(-3, 4, 2)
+        if k[0] or k[1]:
+            kap.append(k)
+    psi = rng.uniform(0, 2 * np.pi, nmodes)
+    amp = level * rng.uniform(-1, 1, nmodes) / nmodes
+    return Perturbation(np.array(kap, np.float64), psi, amp)
+
+
+def mach_state(ps: PatchSet, mach: float, pert: Perturbation):
+    """Uniform Mach flow (1.4, M, 0, 1) with rho <- 1.4 (1 + sum a_k phi_k)."""
+    rho = 1.4 * (1 + pert.amp @ pert.modes(ps.xy))
+    one = np.ones_like(rho)
+    e = prim_to_cons(rho, mach * one, 0 * one, one)
+    return e
+
+
+def freestream(mach: float, gamma=GAMMA):
+    return prim_to_cons(np.float64(1.4), np.float64(mach), np.float64(0), np.float64(1), gamma)
+
+
+def square_state(ps: PatchSet, rng):
+    """rho = 1 + 0.1 sum_4 sin(2 pi (a x + b y) + phi), p likewise,
+    u, v = sum_4 A sin(...) with A ~ U(-0.2, 0.2)."""
+    x, y = ps.xy
+
+    def draw():
+        out = []
+        for _ in range(4):
+            while True:
+                a, b = rng.integers(0, 4, 2)
+                if a or b:
+                    break
+            out.append((a, b, rng.uniform(0, 2 * np.pi)))
+        return out
+
+    def ev(modes, amps):
+        return sum(A * np.sin(2 * np.pi * (a * x + b * y) + ph) for (a, b, ph), A in zip(modes, amps))
+
+    rho = 1 + ev(draw(), [0.1] * 4)
+    p = 1 + ev(draw(), [0.1] * 4)
+    u = ev(draw(), rng.uniform(-0.2, 0.2, 4))
+    v = ev(draw(), rng.uniform(-0.2, 0.2, 4))
+    return prim_to_cons(rho, u, v, p)
+
+
+# ---------------------------------------------------------------- network
+
+def mlp_weights(seed: int, sizes=(16, 64, 64, 4)):
+    """Random-init MLP: W ~ U(+-1/sqrt(fan_in)), b likewise.  W_l has shape
+    [fan_in, fan_out] (row-vector convention y = x W + b)."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for l in range(len(sizes) - 1):
+        lim = 1.0 / np.sqrt(sizes[l])
+        out[f"W{l + 1}"] = rng.uniform(-lim, lim, (sizes[l], sizes[l + 1])).astype(np.float32)
+        out[f"b{l + 1}"] = rng.uniform(-lim, lim, sizes[l + 1]).astype(np.float32)
+    return out
+
+
+# ---------------------------------------------------------------- configs
+
+@dataclass
+class Config:
+    name: str
+    ps: PatchSet
+    u0: np.ndarray                 # float32 [4, plane]
+    ref: np.ndarray                # float64 [4] reference primitive state (rho, u, v, p)
+    mach: float = 0.0
+    pert: Optional[Perturbation] = None
+    mu_const: Optional[float] = None   # constant viscosity (no network)
+    mlp: Optional[dict] = None
+    steps: int = 0
+    cfl: float = 0.5
+    extra: dict = field(default_factory=dict)
+
+
+def _f32(e, ps):
+    out = np.zeros((4, ps.plane), np.float32)
+    for p in range(ps.npatch):
+        o = int(ps.off[p])
+        n = int(ps.n1[p]) * int(ps.n2[p])
+        out[:, o:o + n] = e[:, o:o + n]
+    return out
+
+
+def config(idx: int, n: Optional[int] = None, npatch: Optional[int] = None,
+           nmax: Optional[int] = None, seed: Optional[int] = None) -> Config:
+    """The five workloads.  Optional arguments shrink them for tests:
+    n = points per patch side, npatch = patch count (uneven set), nmax =
+    largest side of the uneven set."""
+    seed = idx if seed is None else seed
+    rng = np.random.default_rng(seed)
+    if idx == 0:
+        ps = unit_square(n or 64)
+        e = square_state(ps, rng)
+        return Config("c0-square-64", ps, _f32(e, ps), np.array([1.0, 0, 0, 1.0]),
+                      mu_const=1e-3, steps=10)
+    if idx in (1, 3):
+        side = n or (256 if idx == 1 else 128)
+        ps = annulus(16, 1, side, side)
+        pert = draw_perturbation(rng)
+        mach = 3.0
+        e = mach_state(ps, mach, pert)
+        return Config(f"c{idx}-annulus-16x{side}", ps, _f32(e, ps),
+                      np.array([1.4, mach, 0, 1.0]), mach=mach, pert=pert,
+                      mlp=mlp_weights(1000 + seed), steps=200 if idx == 1 else 40)
+    if idx == 2:
+        ps = uneven_sectors(npatch or 200, 48, nmax or 512, seed)
+        pert = draw_perturbation(rng)
+        mach = 3.0
+        e = mach_state(ps, mach, pert)
+        return Config(f"c2-uneven-{ps.npatch}", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]),
+                      mach=mach, pert=pert, mlp=mlp_weights(1000 + seed), steps=0)
+    if idx == 4:
+        side = n or 512
+        ps = annulus(16, 4, side, side)
+        pert = draw_perturbation(rng)
+        mach = 5.0
+        e = mach_state(ps, mach, pert)
+        return Config(f"c4-annulus-64x{side}", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]),
+                      mach=mach, pert=pert, mlp=mlp_weights(1000 + seed), steps=100)
+    raise ValueError(idx)
+
+
+def random_lines(rng, nlines: int, n: int, smooth: bool = True):
+    """Seeded test lines: smooth non-periodic functions (sum of a few random
+    low-frequency sinusoids plus a random polynomial) or white noise."""
+    if not smooth:
+        return rng.standard_normal((nlines, n))
+    x = np.linspace(0, 1, n)
+    out = np.zeros((nlines, n))
+    for l in range(nlines):
+        for _ in range(3):
+            out[l] += rng.uniform(-1, 1) * np.sin(2 * np.pi * rng.uniform(0, 4) * x + rng.uniform(0, 6.3))
+        out[l] += np.polyval(rng.uniform(-1, 1, 4), x)
+    return out

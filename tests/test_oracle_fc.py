@@ -1,0 +1,150 @@
+"""Pins of the oracle's FC-Gram continuation and derivative (paper Sec. 2.2)
+against facts that do not come from the oracle itself: brute-force DFT,
+textbook Fourier differentiation, exactness on low-degree polynomials,
+spectral convergence order, the mirror symmetry of the two blends, the
+transpose identity and a dense operator built column by column."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fcgram
+
+
+def test_numpy_fft_matches_bruteforce_dft():
+    rng = np.random.default_rng(0)
+    for L in range(8, 33):
+        x = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+        # brute force written as an explicit double loop, independent of fcgram.dft
+        X = np.array([sum(x[n] * np.exp(-2j * np.pi * k * n / L) for n in range(L)) for k in range(L)])
+        assert np.abs(np.fft.fft(x) - X).max() <= 1e-13 * np.abs(X).max()
+        assert np.abs(fcgram.dft(x) - X).max() <= 1e-13 * np.abs(X).max()
+        assert np.abs(fcgram.dft(X, inverse=True) - x).max() <= 1e-13 * np.abs(x).max()
+
+
+def test_periodic_mode_is_textbook_fourier_derivative():
+    # C = 0: h = 1/N on [0,1), exact for trigonometric polynomials |k| < N/2
+    for N in (16, 31, 64):
+        x = np.arange(N) / N
+        for k in range(1, (N - 1) // 2 + 1):
+            f = np.cos(2 * np.pi * k * x) + 0.5 * np.sin(2 * np.pi * k * x + 0.3)
+            df = 2 * np.pi * k * (-np.sin(2 * np.pi * k * x) + 0.5 * np.cos(2 * np.pi * k * x + 0.3))
+            assert np.abs(fcgram.diff_lines(f[None], 5, 0)[0] - df).max() <= 1e-11 * 2 * np.pi * k
+
+
+@pytest.mark.parametrize("N", [48, 64, 128, 256, 512])
+def test_polynomials_below_degree_d_are_differentiated_exactly(N):
+    d = 5
+    C = synth.cont_points(N)
+    x = np.linspace(0, 1, N)
+    for deg in range(d):
+        f = x ** deg
+        df = deg * x ** (deg - 1) if deg else 0 * x
+        err = np.abs(fcgram.diff_lines(f[None], d, C)[0] - df).max()
+        assert err <= 2e-9 * N / 64, (deg, err)
+
+
+def test_derivative_of_constant_vanishes():
+    for N in (64, 256, 512):
+        e = np.abs(fcgram.diff_lines(np.ones((1, N)), 5, synth.cont_points(N))).max()
+        assert e <= 1e-9
+
+
+def test_spectral_convergence_order_on_smooth_nonperiodic_functions():
+    d = 5
+    funcs = [
+        (lambda x: np.exp(np.sin(5.4 * np.pi * x - 2.7 * np.pi) - np.cos(2 * np.pi * x)),
+         lambda x: np.exp(np.sin(5.4 * np.pi * x - 2.7 * np.pi) - np.cos(2 * np.pi * x))
+         * (5.4 * np.pi * np.cos(5.4 * np.pi * x - 2.7 * np.pi) + 2 * np.pi * np.sin(2 * np.pi * x))),
+        (lambda x: np.sin(3.3 * x + 0.4), lambda x: 3.3 * np.cos(3.3 * x + 0.4)),
+    ]
+    for f, df in funcs:
+        errs = []
+        for N in (128, 256, 512):
+            x = np.linspace(0, 1, N)
+            # C = 27 fixed so the operator family is the same across N
+            errs.append(np.abs(fcgram.diff_lines(f(x)[None], d, 27)[0] - df(x)).max() / np.abs(df(x)).max())
+        order = np.log2(errs[1] / errs[2])
+        assert order >= 3.5 or errs[2] < 1e-9, errs
+    # and the exp-sin case is accurate to better than 1e-5 at N = 256
+    x = np.linspace(0, 1, 256)
+    f, df = funcs[0]
+    assert np.abs(fcgram.diff_lines(f(x)[None], d, 27)[0] - df(x)).max() / np.abs(df(x)).max() < 2e-5
+
+
+def test_mirror_symmetry_of_left_and_right_blends():
+    rng = np.random.default_rng(1)
+    for N in (64, 200):
+        F = synth.random_lines(rng, 4, N)
+        C = synth.cont_points(N)
+        D = fcgram.diff_lines(F, 5, C)
+        Dr = fcgram.diff_lines(F[:, ::-1], 5, C)
+        assert np.abs(Dr + D[:, ::-1]).max() <= 1e-8 * np.abs(D).max()
+
+
+def test_continuation_structure():
+    ArQ = fcgram.continuation_matrix(5, 27)
+    assert ArQ.shape == (27, 5)
+    AlQ = fcgram.left_matrix(ArQ)
+    assert np.array_equal(AlQ[0], ArQ[-1, ::-1])
+    # a line equal to 1 on its last d points and 0 on its first d points
+    # continues smoothly towards 0: the right blend starts near 1, ends near 0
+    ones = ArQ.sum(axis=1)
+    assert abs(ones[0] - 1) < 0.2 and abs(ones[-1]) < 0.2
+    # Q is orthogonal and the Gram polynomials span degree < d
+    Q, Rinv = fcgram.gram_basis(5, 30)
+    Qn = np.array(Q.tolist(), dtype=float)
+    assert np.abs(Qn.T @ Qn - np.eye(5)).max() < 1e-14
+
+
+def test_fft_path_equals_dense_operator_from_direct_dft():
+    # Dense D built column by column with the oracle's O(L^2) DFT and no FFT
+    d = 5
+    for N in (20, 37):
+        C = 27
+        L = N + C
+        h = 1.0 / (N - 1)
+        ArQ = fcgram.continuation_matrix(d, C)
+        k = fcgram.wavenumbers(L)
+        Dd = np.zeros((N, N))
+        for j in range(N):
+            e = np.zeros(N)
+            e[j] = 1
+            ext = fcgram.extend(e, ArQ)
+            X = fcgram.dft(ext) * (2j * np.pi * k / (L * h))
+            Dd[:, j] = np.real(fcgram.dft(X, inverse=True))[:N]
+        rng = np.random.default_rng(2)
+        F = synth.random_lines(rng, 3, N)
+        assert np.abs(F @ Dd.T - fcgram.diff_lines(F, d, C)).max() <= 1e-12 * np.abs(F @ Dd.T).max() * 10
+
+
+def test_adjoint_is_transpose():
+    rng = np.random.default_rng(3)
+    for N, C in ((64, 27), (96, 30), (33, 0)):
+        x = rng.standard_normal((5, N))
+        y = rng.standard_normal((5, N))
+        Dx = fcgram.diff_lines(x, 5, C)
+        lhs = np.sum(Dx * y)
+        rhs = np.sum(x * fcgram.diff_lines_adj(y, 5, C))
+        assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(Dx) * np.abs(y))
+    # continuation adjoint
+    N = 50
+    ArQ = fcgram.continuation_matrix(5, 27)
+    x = rng.standard_normal((3, N))
+    g = rng.standard_normal((3, N + 27))
+    assert abs(np.sum(fcgram.extend(x, ArQ) * g) - np.sum(x * fcgram.extend_adj(g, ArQ, N))) < 1e-9
+
+
+@pytest.mark.slow
+def test_committed_table_matches_fresh_fit():
+    for C in (27, 30):
+        fresh = fcgram.build_continuation(5, C)
+        tab = fcgram.continuation_matrix(5, C)
+        assert np.abs(fresh - tab).max() <= 1e-15 * np.abs(fresh).max()
+
+
+def test_c_rule():
+    assert synth.cont_points(64) == 27 and synth.cont_points(512) == 27
+    assert synth.cont_points(256) == 30 and synth.cont_points(128) == 28
+    for n in range(48, 513):
+        c = synth.cont_points(n)
+        assert 27 <= c <= 45 and synth.smooth13(n + c)

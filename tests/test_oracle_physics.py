@@ -1,0 +1,331 @@
+"""Pins of the oracle's Euler right-hand side, viscous term, SSPRK(5,4)
+stepping, step size, classifier and viscosity operator against closed forms,
+invariants, order conditions and brute force."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import av, euler, fcgram, rk, solver
+
+G = 1.4
+
+
+def periodic_square(n):
+    """Cartesian periodic patch: C = 0 marks plain Fourier mode along both
+    directions; spacing 1/n on [0,1)."""
+    ps = synth.unit_square(n)
+    ps.C1[:] = 0
+    ps.C2[:] = 0
+    g = np.arange(n) / n
+    X, Y = np.meshgrid(g, g)
+    ps.xy[0, :n * n] = X.ravel()
+    ps.xy[1, :n * n] = Y.ravel()
+    return ps
+
+
+def smooth_state(ps, rng, amp=0.1):
+    x, y = ps.xy
+    rho = 1 + amp * np.sin(2 * np.pi * (x + 2 * y) + rng.uniform(0, 6))
+    u = 0.3 + amp * np.cos(2 * np.pi * (2 * x - y) + rng.uniform(0, 6))
+    v = -0.2 + amp * np.sin(2 * np.pi * (x - y) + rng.uniform(0, 6))
+    p = 1 + amp * np.cos(2 * np.pi * (x + y) + rng.uniform(0, 6))
+    return synth.prim_to_cons(rho, u, v, p)
+
+
+def test_fluxes_closed_form():
+    e = synth.prim_to_cons(np.array(2.0), np.array(3.0), np.array(-1.0), np.array(5.0))
+    assert np.allclose(e, [2, 6, -2, 5 / 0.4 + 0.5 * 2 * 10])
+    F, Gf = euler.fluxes(e, G)
+    E = e[3]
+    assert np.allclose(F, [6, 2 * 9 + 5, 2 * 3 * -1, 3 * (E + 5)])
+    assert np.allclose(Gf, [-2, 2 * 3 * -1, 2 * 1 + 5, -1 * (E + 5)])
+    assert np.isclose(euler.sound_speed(e, G), np.sqrt(1.4 * 5 / 2))
+
+
+def test_conservation_in_periodic_mode():
+    rng = np.random.default_rng(0)
+    ps = periodic_square(32)
+    e = smooth_state(ps, rng)
+    mu = 0.01 * (1 + 0.5 * np.sin(2 * np.pi * ps.xy[0]))
+    r = euler.full_rhs(e, ps.metric, mu, ps, G)
+    F, Gf = euler.fluxes(e, G)
+    scale = np.abs(F).max() * 32 * 32 * 2 * np.pi
+    # 1^T S = 0 for the periodic spectral derivative
+    assert np.abs(r.sum(axis=1)).max() <= 1e-12 * scale
+
+
+def test_single_mode_viscous_term():
+    ps = periodic_square(24)
+    x, y = ps.xy
+    k = 3
+    e = np.stack([np.sin(2 * np.pi * k * x), np.cos(2 * np.pi * k * y), np.sin(2 * np.pi * (x + y)), 0 * x + 1])
+    mu = 0.02 * np.ones(ps.plane)
+    t = euler.av_term(e, ps.metric, mu, ps)
+    lap = np.stack([-(2 * np.pi * k) ** 2 * e[0], -(2 * np.pi * k) ** 2 * e[1],
+                    -2 * (2 * np.pi) ** 2 * e[2], 0 * x])
+    assert np.abs(t - 0.02 * lap).max() <= 1e-9 * 0.02 * (2 * np.pi * k) ** 2
+
+
+def test_free_stream_preservation_on_curvilinear_annulus():
+    ps = synth.annulus(4, 1, 64, 48)
+    fs = synth.freestream(3.0)
+    e = np.repeat(fs[:, None], ps.plane, axis=1)
+    r = euler.full_rhs(e, ps.metric, 0.01 * np.ones(ps.plane), ps, G)
+    F, Gf = euler.fluxes(fs, G)
+    scale = np.abs(F).max() * np.abs(ps.metric).max()
+    assert np.abs(r).max() <= 1e-8 * scale
+
+
+def test_rotation_symmetry_on_square():
+    rng = np.random.default_rng(5)
+    ps = synth.unit_square(40)
+    n = 40
+    e = smooth_state(ps, rng)
+    mu = 0.01 + 0.005 * ps.xy[0] * ps.xy[1]
+    r = euler.full_rhs(e, ps.metric, mu, ps, G)
+    # swap x <-> y (transpose the grid) and u <-> v
+    def tr(a):
+        return a[..., :n * n].reshape(a.shape[:-1] + (n, n)).swapaxes(-1, -2).reshape(a.shape[:-1] + (n * n,))
+    e2 = tr(e)[[0, 2, 1, 3]]
+    r2 = euler.full_rhs(np.pad(e2, ((0, 0), (0, ps.plane - n * n))), ps.metric,
+                        np.pad(tr(mu), (0, ps.plane - n * n)), ps, G)
+    want = tr(r)[[0, 2, 1, 3]]
+    assert np.abs(r2[:, :n * n] - want).max() <= 1e-10 * np.abs(r).max()
+
+
+def test_flux_vjp_matches_finite_differences():
+    rng = np.random.default_rng(6)
+    e = synth.prim_to_cons(1 + 0.2 * rng.random(7), rng.standard_normal(7), rng.standard_normal(7), 1 + rng.random(7))
+    Fb, Gb = rng.standard_normal((4, 7)), rng.standard_normal((4, 7))
+    eb = euler.fluxes_vjp(e, G, Fb, Gb)
+    de = rng.standard_normal((4, 7))
+    h = 1e-6
+    Fp, Gp = euler.fluxes(e + h * de, G)
+    Fm, Gm = euler.fluxes(e - h * de, G)
+    fd = np.sum((Fp - Fm) * Fb + (Gp - Gm) * Gb) / (2 * h)
+    assert abs(fd - np.sum(eb * de)) <= 1e-7 * abs(fd)
+
+
+def test_rhs_vjp_matches_finite_differences():
+    rng = np.random.default_rng(7)
+    ps = synth.annulus(3, 1, 40, 28)
+    e = synth.mach_state(ps, 2.0, synth.draw_perturbation(rng, level=0.05))
+    mu = 0.002 * (1 + 0.3 * np.sin(ps.xy[0]))
+    rb = rng.standard_normal((4, ps.plane))
+    eb, mub = euler.full_rhs_vjp(e, ps.metric, mu, ps, G, rb)
+    de = rng.standard_normal((4, ps.plane)) * 1e-2
+    dm = rng.standard_normal(ps.plane) * 1e-4
+    h = 1e-4
+    fp = np.sum(euler.full_rhs(e + h * de, ps.metric, mu + h * dm, ps, G) * rb)
+    fm = np.sum(euler.full_rhs(e - h * de, ps.metric, mu - h * dm, ps, G) * rb)
+    fd = (fp - fm) / (2 * h)
+    an = np.sum(eb * de) + np.sum(mub * dm)
+    assert abs(fd - an) <= 1e-6 * abs(fd)
+
+
+# ------------------------------------------------------------------ SSPRK(5,4)
+
+def test_ssprk_order_conditions():
+    A, b, c = rk.butcher()
+    conds = [
+        (b.sum(), 1.0),
+        (b @ c, 1 / 2),
+        (b @ c ** 2, 1 / 3),
+        (b @ A @ c, 1 / 6),
+        (b @ c ** 3, 1 / 4),
+        (b @ (c * (A @ c)), 1 / 8),
+        (b @ A @ c ** 2, 1 / 12),
+        (b @ A @ A @ c, 1 / 24),
+    ]
+    for got, want in conds:
+        assert abs(got - want) <= 1e-14
+    for i, row in enumerate(rk.ALPHA):
+        assert abs(sum(row) - 1) <= 1e-14
+        assert all(a >= 0 for a in row) and all(x >= 0 for x in rk.BETA[i])
+    # explicit: A strictly lower triangular
+    assert np.allclose(np.triu(A), 0)
+
+
+def test_ssprk_observed_order_four():
+    lam = -1.3 + 0.7j
+    errs = []
+    for n in (20, 40, 80):
+        dt = 1.0 / n
+        y = np.array([1.0 + 0j])
+        for _ in range(n):
+            y, _, _ = rk.ssprk_step(y, dt, lambda u, s: lam * u)
+        errs.append(abs(y[0] - np.exp(lam)))
+    assert np.log2(errs[0] / errs[1]) > 3.8 and np.log2(errs[1] / errs[2]) > 3.8
+    # nonlinear: y' = -y^2, y(0) = 1 -> y = 1/(1+t)
+    errs = []
+    for n in (10, 20, 40):
+        y = np.array([1.0])
+        for _ in range(n):
+            y, _, _ = rk.ssprk_step(y, 1.0 / n, lambda u, s: -u * u)
+        errs.append(abs(y[0] - 0.5))
+    assert np.log2(errs[1] / errs[2]) > 3.7
+
+
+def test_cfl_closed_form_for_uniform_state():
+    cfg = synth.config(0)
+    ps = cfg.ps
+    e = np.repeat(synth.prim_to_cons(np.float64(1), np.float64(0), np.float64(0), np.float64(1))[:, None], ps.plane, 1)
+    mu = 1e-3 * np.ones(ps.plane)
+    dt = rk.cfl_dt(e, mu, ps, 0.5, G)
+    assert np.isclose(dt, (0.5 / np.pi) / (63 * np.sqrt(1.4) + 1e-3 * 63 ** 2), rtol=1e-14)
+
+
+# ------------------------------------------------------------------ AV
+
+def test_window_weights():
+    w = av.window_weights()
+    assert len(w) == 17 and np.isclose(w.sum(), 9.0, atol=1e-14)
+    assert np.isclose(w[8], 1.0) and np.isclose(np.cos(np.pi * 9 / 18) ** 2, 0, atol=1e-30)
+    assert np.all(np.diff(w[8:]) < 0)
+
+
+def test_partition_of_unity():
+    for ps in (synth.uneven_sectors(3, 30, 60, 0), synth.annulus(3, 2, 44, 40)):
+        mu = av.smooth_blend(np.full(ps.plane, 2.5), ps)
+        for p in range(ps.npatch):
+            assert np.allclose(ps.view(mu, p), 2.5, rtol=1e-14)
+
+
+def test_lambda_matches_bruteforce_definition():
+    """Explicit normalised sum over every patch's D~ points of the product
+    window, patch by patch and point by point (eqs. W, multipatch_W_norm,
+    Lambda), on a tiny 3x2 annulus."""
+    ps = synth.annulus(3, 2, 30, 26)
+    rng = np.random.default_rng(8)
+    muh = rng.random(ps.plane)
+    for p in range(ps.npatch):
+        ps.view(muh, p)[~av.dtilde_mask(ps, p)] = 0
+    fast = av.smooth_blend(muh, ps)
+    wt = lambda k: np.cos(np.pi * k / 18) ** 2 if abs(k) <= 8 else 0.0
+    ring = 3 * (30 - 19)
+
+    def gidx(p, i, j):
+        s, k = p % 3, p // 3
+        return ((s * 11 + i) % ring, k * 7 + j)
+
+    # map global index -> list of (patch, i, j)
+    where = {}
+    for p in range(ps.npatch):
+        for j in range(26):
+            for i in range(30):
+                where.setdefault(gidx(p, i, j), []).append((p, i, j))
+    for (p0, i0, j0) in [(0, 0, 0), (1, 15, 20), (4, 29, 3), (5, 3, 25), (2, 10, 12)]:
+        gx = gidx(p0, i0, j0)
+        num = den = 0.0
+        for (p, i1, j1) in where[gx]:           # patches containing x, x = (i1, j1) in patch p
+            m = av.dtilde_mask(ps, p)
+            for j in range(26):
+                for i in range(30):
+                    if m[j, i]:
+                        w = wt(i1 - i) * wt(j1 - j)
+                        num += w * ps.view(muh, p)[j, i]
+                        den += w
+        assert np.isclose(ps.view(fast, p0)[j0, i0], num / den, rtol=1e-12)
+
+
+def test_stencil_max_bruteforce():
+    rng = np.random.default_rng(9)
+    S = rng.random((9, 11))
+    mx, arg = av.stencil_max(S)
+    for j in range(9):
+        for i in range(11):
+            blk = S[max(0, j - 3):j + 4, max(0, i - 3):i + 4]
+            assert mx[j, i] == blk.max()
+            assert S.ravel()[arg[j, i]] == blk.max()
+
+
+def test_mlp_matches_naive_loops():
+    W = synth.mlp_weights(3)
+    rng = np.random.default_rng(10)
+    x = rng.uniform(-1, 1, (5, 16))
+    out = av.mlp_logits(x, W)
+    for r in range(5):
+        h1 = [max(0.0, sum(x[r, i] * float(W["W1"][i, j]) for i in range(16)) + float(W["b1"][j])) for j in range(64)]
+        h2 = [max(0.0, sum(h1[i] * float(W["W2"][i, j]) for i in range(64)) + float(W["b2"][j])) for j in range(64)]
+        o = [sum(h2[i] * float(W["W3"][i, j]) for i in range(64)) + float(W["b3"][j]) for j in range(4)]
+        assert np.allclose(out[r], o, rtol=1e-12, atol=1e-12)
+
+
+def test_features():
+    lines = np.array([np.arange(40, dtype=float), np.full(40, 3.0)])
+    f = av.features_lines(lines)
+    assert np.allclose(f[0, 20], np.linspace(-1, 1, 16))
+    assert np.all(f[1] == 0)
+    # clamped at the left end: window of point 0 repeats sample 0 eight times
+    assert np.all(f[0, 0, :9] == -1) and f[0, 0, -1] == 1
+
+
+def test_preliminary_viscosity_values():
+    cfg = synth.config(1, n=40)
+    ps = cfg.ps
+    tau = np.zeros(ps.plane, np.int8)
+    for p in range(ps.npatch):
+        m = av.dtilde_mask(ps, p)
+        ps.view(tau, p)[m] = 1 + (np.arange(m.sum()) % 4)
+    muh, arg = av.preliminary(cfg.u0, tau, ps, G)
+    S = rk.wave_speed(cfg.u0, G)
+    p = 3
+    m = av.dtilde_mask(ps, p)
+    j, i = np.argwhere(m)[17]
+    blk = ps.view(S, p)[max(0, j - 3):j + 4, max(0, i - 3):i + 4].max()
+    t = ps.view(tau, p)[j, i]
+    assert np.isclose(ps.view(muh, p)[j, i], [1.5, 1, 0.5, 0][t - 1] * blk * ps.hhat[p], rtol=1e-14)
+    assert np.all(ps.view(muh, p)[~m] == 0)
+
+
+def test_viscosity_vjp_matches_finite_differences():
+    cfg = synth.config(1, n=36)
+    ps = cfg.ps
+    e = np.array(cfg.u0, np.float64)
+    mu, tau, arg = av.viscosity(e, ps, cfg.mlp, G)
+    rng = np.random.default_rng(11)
+    mb = rng.standard_normal(ps.plane)
+    eb = av.viscosity_vjp(e, tau, arg, ps, G, mb)
+    de = rng.standard_normal((4, ps.plane)) * 1e-3
+    h = 1e-5
+    # frozen decisions: recompute mu^ with the recorded tau and argmax
+    def mu_frozen(ee):
+        S = rk.wave_speed(ee, G)
+        muh = np.zeros(ps.plane)
+        for p in range(ps.npatch):
+            t = ps.view(tau, p).astype(int)
+            r = np.where(t > 0, av.R_TABLE[np.clip(t - 1, 0, 3)], 0.0)
+            muh_p = r * ps.view(S, p).ravel()[ps.view(arg, p)] * ps.hhat[p]
+            ps.view(muh, p)[...] = np.where(av.dtilde_mask(ps, p), muh_p, 0)
+        return av.smooth_blend(muh, ps)
+    assert np.allclose(mu_frozen(e), mu, rtol=1e-13)
+    fd = np.sum((mu_frozen(e + h * de) - mu_frozen(e - h * de)) * mb) / (2 * h)
+    assert abs(fd - np.sum(eb * de)) <= 1e-6 * abs(fd)
+    # Lambda transpose: dot-product identity
+    x, y = rng.random(ps.plane), rng.random(ps.plane)
+    for p in range(ps.npatch):
+        ps.view(x, p)[~av.dtilde_mask(ps, p)] = 0
+    assert np.isclose(np.sum(av.smooth_blend(x, ps) * y), np.sum(x * av.smooth_blend_adj(y, ps)), rtol=1e-12)
+
+
+# ------------------------------------------------------------------ glue
+
+def test_glue_copies_same_physical_point():
+    ps = synth.annulus(4, 3, 40, 30)
+    f = lambda xy: np.sin(1.3 * xy[0] + 0.2) * np.cos(0.7 * xy[1])
+    e = np.zeros((4, ps.plane))
+    e[0] = f(ps.xy)
+    e[1:] = 7.0
+    ref = e.copy()
+    # scramble fringes, then glue must restore the values of f at those points
+    for p in range(ps.npatch):
+        v = ps.view(e, p)
+        v[:, :, :5] = -1
+        v[:, :, -5:] = -1
+        v[:, :5, :] = -1 if p >= 4 else v[:, :5, :]
+        if p < 8:
+            v[:, -5:, :] = -1
+    solver.glue(e, ps, 3.0)
+    d = ps.dirichlet.astype(bool)
+    assert np.allclose(e[0, ~d], ref[0, ~d], atol=1e-12)
+    assert np.allclose(e[:, d], synth.freestream(3.0)[:, None])
