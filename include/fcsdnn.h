@@ -1,0 +1,277 @@
+/*
+ * fcsdnn.h -- C ABI of the MI355X FC-SDNN hot path (libfcsdnn.so).
+ *
+ * Method: Bruno & Leibovici, "General-domain FC-based shock-dynamics solver
+ * I: Basic elements".  Conserved variables e = (rho, rho u, rho v, E) live
+ * on logically rectangular patches (Sec. 3.1); every patch is advanced with
+ * FC-Gram spectral derivatives along its two parameter directions (Sec. 2.2),
+ * the curvilinear chain rule with the inverse-Jacobian metric terms
+ * (Sec. 3.3), the network-driven smooth artificial viscosity (Secs. 2.3, 5)
+ * and a five-stage SSP Runge-Kutta scheme (Sec. 4.1).
+ *
+ * Conventions for every entry point below:
+ *   - Return value: FCSD_OK or an error code; nothing aborts or throws.  The
+ *     message of the last error of a context is fcsd_last_error(ctx).
+ *   - Pointers named in/out/u/... are DEVICE pointers owned by the caller
+ *     (FP32 unless stated).  The library owns only its context and patch
+ *     sets (and the device tables inside them).
+ *   - All work is enqueued asynchronously on the context's HIP stream; no
+ *     entry point synchronises the device except the *_create functions.
+ *   - Plane layout: a "plane" holds one scalar field of all patches.  Patch p
+ *     occupies elements [off_p, off_p + n1_p*n2_p) with element (i, j) at
+ *     off_p + j*n1_p + i (i along q1 is contiguous).  Multi-field arrays
+ *     store field f at base + f*plane.  State field order (rho, rho u, rho v,
+ *     E); metric order (dq1/dx, dq1/dy, dq2/dx, dq2/dy).
+ *   - Argument errors (null pointers, bad sizes, unsupported FFT lengths)
+ *     return FCSD_EINVAL / FCSD_EUNSUPPORTED before anything is launched.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef FCSDNN_H
+#define FCSDNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FCSD_OK = 0,
+  FCSD_EINVAL = 1,       /* invalid argument */
+  FCSD_ENOMEM = 2,       /* host or device allocation failed */
+  FCSD_EDEVICE = 3,      /* no usable HIP device */
+  FCSD_EHIP = 4,         /* a HIP runtime call failed */
+  FCSD_EUNSUPPORTED = 5, /* valid but unsupported (e.g. L = N + C not 13-smooth) */
+  FCSD_ENONFINITE = 6    /* the state monitor saw a non-finite or non-positive value */
+} fcsd_status;
+
+typedef struct fcsd_ctx fcsd_ctx;
+typedef struct fcsd_set fcsd_set;
+
+/* One patch (Sec. 3.2.1): n1 x n2 parameter-space points with spacing
+ * h = 1/(n-1) along each direction; C1 / C2 continuation points for lines
+ * along q1 / q2 (C = 0: the direction is periodic, plain Fourier
+ * differentiation with h = 1/n); hhat / htilde the upper / lower bounds of
+ * the physical grid spacing (Sec. 5.1 item 6, eq. CFL); internal[s] != 0
+ * marks side s = (q1-, q1+, q2-, q2+) as internal (Sec. 3.4), which removes
+ * the n_v = 9 nearest lines from the viscosity-generation subgrid (eq.
+ * viscosity_generation). */
+typedef struct {
+  int32_t n1, n2;
+  int32_t C1, C2;
+  int64_t off;
+  double hhat, htilde;
+  uint8_t internal[4];
+  int32_t reserved;
+} fcsd_patch_desc;
+
+/* Create a context on HIP device `device` that enqueues on `stream` (a
+ * hipStream_t; NULL = a new non-blocking stream owned by the context).
+ * FCSD_EDEVICE when no device is present.  Synchronises once. */
+fcsd_status fcsd_ctx_create(int device, void* stream, fcsd_ctx** out);
+fcsd_status fcsd_ctx_destroy(fcsd_ctx* ctx);
+/* Replace the stream of a context (e.g. torch's current stream). */
+fcsd_status fcsd_ctx_set_stream(fcsd_ctx* ctx, void* stream);
+/* Message of the last failure on ctx ("" if none).  Owned by ctx. */
+const char* fcsd_last_error(const fcsd_ctx* ctx);
+/* The hipStream_t the context enqueues on (its own non-blocking stream when
+ * created with stream = NULL). */
+void* fcsd_ctx_stream(fcsd_ctx* ctx);
+/* Block the host until the context's stream is idle. */
+fcsd_status fcsd_ctx_sync(fcsd_ctx* ctx);
+
+/* Build a patch set: validates the descriptors (n >= 2d+1, n <= 4096,
+ * 0 <= C <= 256, 1 <= d <= 8, patches inside [0, plane) and disjoint),
+ * factors every extension length L = n + C into radices {2,3,4,5,7,8,11,13}
+ * (FCSD_EUNSUPPORTED otherwise), computes the FC-Gram continuation matrices
+ * (Sec. 2.2, eq. continuation) in binary128 arithmetic, the FP32 twiddle
+ * and derivative-multiplier tables and the tile schedules, and uploads them.
+ * `ring_sectors` / `ring_shells` > 0 declare the index-aligned annulus
+ * layout (sector s of shell k is patch k*ring_sectors + s, neighbours overlap
+ * by 2 n_v + 1 = 19 lines) used by the fringe exchange and by the
+ * multi-patch smoothing-blending operator; 0 means independent patches. */
+fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_patch_desc* patches,
+                            int d, int64_t plane, int ring_sectors, int ring_shells,
+                            fcsd_set** out);
+fcsd_status fcsd_set_destroy(fcsd_set* set);
+
+/* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
+enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3 };
+fcsd_status fcsd_workspace_size(const fcsd_set* set, int op, size_t* bytes);
+
+/* ---- FC-Gram line operators (Sec. 2.2) --------------------------------- */
+
+/* Continuation along direction dir (1: q1 lines = rows, 2: q2 lines =
+ * columns), eq. continuation: for every line of every patch writes the N
+ * samples followed by the C continuation values
+ *     tail = A_l Q^T F_l + A_r Q^T F_r.
+ * ext holds, per field, the lines of patch 0, then patch 1, ..., each line
+ * L = N + C floats; ext_plane = fcsd_ext_size(set, dir) floats per field. */
+fcsd_status fcsd_ext_size(const fcsd_set* set, int dir, int64_t* floats);
+fcsd_status fc_continue(fcsd_ctx* ctx, const fcsd_set* set, int dir, int nf,
+                        const float* in, int64_t plane, float* ext, int64_t ext_plane);
+/* Transpose of fc_continue: in_bar += E^T ext_bar. */
+fcsd_status fc_continue_adj(fcsd_ctx* ctx, const fcsd_set* set, int dir, int nf,
+                            const float* ext_bar, int64_t ext_plane, float* in_bar, int64_t plane);
+
+/* FC derivative d/dq^dir of nf fields (eq. fc_der): continuation, FFT of
+ * length L, multiplication by 2 pi i k / beta (beta = L h, h = 1/(N-1);
+ * Nyquist of even L set to zero), inverse FFT, restriction to N points.
+ * out may not alias in. */
+fcsd_status fc_diff(fcsd_ctx* ctx, const fcsd_set* set, int dir, int nf,
+                    const float* in, float* out, int64_t plane);
+/* Transpose: in_bar += D^T out_bar, D^T = E^T (-S) R^T. */
+fcsd_status fc_diff_adj(fcsd_ctx* ctx, const fcsd_set* set, int dir, int nf,
+                        const float* out_bar, float* in_bar, int64_t plane);
+
+/* ---- right-hand side (Secs. 2.1, 2.3, 3.3) ------------------------------ */
+
+/* rhs = - div_x f(u) (eq. general_curvilinear, chain-rule form
+ * sum_{m,a} dq^m/dx_a d/dq^m f_a).  ref = reference primitive state
+ * (rho, u, v, p): fluxes are differentiated in deviation form
+ * f(u) - f(u_ref), which leaves the result unchanged up to the FC
+ * derivative of a constant.  ws: fcsd_workspace_size(FCSD_WS_RHS) bytes. */
+fcsd_status euler_rhs(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* metric,
+                      const float ref[4], float gamma, float* rhs, int64_t plane,
+                      void* ws, size_t ws_bytes);
+/* rhs += div_x (mu grad_x u) for all four components (eqs. f_visc,
+ * convection diffusion eqn). */
+fcsd_status av_apply(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* metric,
+                     const float* mu, const float ref[4], float* rhs, int64_t plane,
+                     void* ws, size_t ws_bytes);
+/* rhs = - div_x f(u) + div_x (mu grad_x u) in one pass sequence (mu may be
+ * NULL: inviscid). */
+fcsd_status fcsd_rhs(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* metric,
+                     const float* mu, const float ref[4], float gamma, float* rhs, int64_t plane,
+                     void* ws, size_t ws_bytes);
+/* Reverse mode of fcsd_rhs at the point (u, mu): u_bar += (dL/du)^T rhs_bar,
+ * mu_bar += (dL/dmu)^T rhs_bar (mu_bar may be NULL; mu NULL = inviscid). */
+fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* metric,
+                         const float* mu, const float ref[4], float gamma, const float* rhs_bar,
+                         float* u_bar, float* mu_bar, int64_t plane, void* ws, size_t ws_bytes);
+
+/* ---- time stepping (Sec. 4.1) ------------------------------------------ */
+
+/* One stage s = 0..4 of the five-stage fourth-order SSP Runge-Kutta scheme
+ * in three-register form on 4 fields:
+ *   s=0: uout = u0 + b0 dt r
+ *   s=1: uout = a10 u0 + a11 ui + b1 dt r
+ *   s=2: uout = a20 u0 + a22 ui + b2 dt r ;  acc  = a42 ui
+ *   s=3: uout = a30 u0 + a33 ui + b3 dt r ;  acc += a43 ui + b43 dt r
+ *   s=4: uout = acc + a44 ui + b4 dt r
+ * (ui = output of the previous stage, r = L(ui), dt read from dt_dev).
+ * uout may alias u0 at s = 4 only. */
+fcsd_status rk_stage(fcsd_ctx* ctx, const fcsd_set* set, int stage, const float* dt_dev,
+                     const float* rhs, const float* u0, const float* ui, float* acc, float* uout,
+                     int64_t plane);
+/* Reverse of rk_stage: given uout_bar (and acc_bar for s <= 3 after s = 4),
+ * accumulates u0_bar, ui_bar, rhs_bar (= dt-scaled) and acc_bar in place. */
+fcsd_status rk_stage_adj(fcsd_ctx* ctx, const fcsd_set* set, int stage, const float* dt_dev,
+                         const float* uout_bar, float* u0_bar, float* ui_bar, float* acc_bar,
+                         float* rhs_bar, int64_t plane);
+
+/* dt = (1/pi) min_p cfl / (max S/h~_p + max mu/h~_p^2), S = |u|+|v|+a
+ * (eq. CFL); written to dt_dev[0].  mu may be NULL. */
+fcsd_status fcsd_cfl_dt(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* mu,
+                        float cfl, float gamma, float* dt_dev, int64_t plane,
+                        void* ws, size_t ws_bytes);
+
+/* ---- network-driven viscosity (Sec. 5) ---------------------------------- */
+
+/* Network weights (device FP32, row-vector convention y = x W + b):
+ * W1 [16][64], b1 [64], W2 [64][64], b2 [64], W3 [64][4], b3 [4]. */
+typedef struct {
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+} fcsd_mlp;
+
+/* Smoothness classes tau (int8 plane; 0 outside the viscosity-generation
+ * subgrid) from the proxy Phi = |u| sqrt(rho/(gamma p)) (Sec. 5.1): per
+ * point and direction, the 16-sample window of Phi at offsets -8..7 (indices
+ * clamped to the line) rescaled to [-1, 1] feeds the 16-64-64-4 ReLU
+ * network; tau = 1 + argmax (lowest index on ties), 2D class = min of the two
+ * directions.  logits (nullable): FP32 [2][plane][4] network outputs.
+ * ws: fcsd_workspace_size(FCSD_WS_AV) bytes. */
+fcsd_status sdnn_infer(fcsd_ctx* ctx, const fcsd_set* set, const float* u, float gamma,
+                       const fcsd_mlp* w, int8_t* tau, float* logits, int64_t plane,
+                       void* ws, size_t ws_bytes);
+
+/* mu = Lambda[mu^], mu^ = R(tau) max_{7x7} S h^ on the viscosity-generation
+ * subgrid (eqs. V2D_unscaled, W, multipatch_W_norm, Lambda), R = (1.5, 1,
+ * 0.5, 0), window cos^2(pi k/18), |k| <= 8.  argmax (nullable): int32 plane
+ * of the patch-local flat index of each 7x7 maximiser (first in row-major
+ * order on ties).  ws: fcsd_workspace_size(FCSD_WS_AV). */
+fcsd_status av_viscosity(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const int8_t* tau,
+                         float gamma, float* mu, int32_t* argmax, int64_t plane,
+                         void* ws, size_t ws_bytes);
+/* u_bar += (dmu/du)^T mu_bar with tau and argmax frozen. */
+fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const int8_t* tau,
+                             const int32_t* argmax, float gamma, const float* mu_bar, float* u_bar,
+                             int64_t plane, void* ws, size_t ws_bytes);
+
+/* ---- multi-patch glue (Secs. 3.4, 4.2) ---------------------------------- */
+
+/* In-place fringe copy (n_f = 5 lines from the index-aligned neighbour;
+ * sectors first, then shells) followed by the Dirichlet overwrite with
+ * `dirichlet_state` (4 floats, host) on the points flagged in the uint8
+ * plane `dirichlet_mask` (nullable).  No-op for independent patches. */
+fcsd_status fcsd_glue(fcsd_ctx* ctx, const fcsd_set* set, float* u, int64_t plane,
+                      const uint8_t* dirichlet_mask, const float dirichlet_state[4]);
+
+/* ---- fused stage and step ------------------------------------------------ */
+
+/* One fused SSPRK stage: right-hand side of ui (with viscosity mu, NULL =
+ * inviscid) and the register update of rk_stage, batched over all patches
+ * (4 passes, one launch each). */
+fcsd_status fcsd_stage(fcsd_ctx* ctx, const fcsd_set* set, int stage, const float* u0,
+                       const float* ui, float* acc, float* uout, const float* metric,
+                       const float* mu, const float ref[4], float gamma, const float* dt_dev,
+                       int64_t plane, void* ws, size_t ws_bytes);
+
+/* Per-patch plain variant of fcsd_stage: the same kernels launched once per
+ * patch (npatch launches per pass). */
+fcsd_status fcsd_stage_per_patch(fcsd_ctx* ctx, const fcsd_set* set, int stage, const float* u0,
+                                 const float* ui, float* acc, float* uout, const float* metric,
+                                 const float* mu, const float ref[4], float gamma,
+                                 const float* dt_dev, int64_t plane, void* ws, size_t ws_bytes);
+
+/* Step state kept by the library for fcsd_step. */
+typedef struct {
+  float* u;             /* [4][plane] state, advanced in place */
+  const float* metric;  /* [4][plane] */
+  float* mu;            /* [plane] viscosity (output when w != NULL, else input) */
+  int8_t* tau;          /* [plane] classes (used when w != NULL) */
+  int32_t* argmax;      /* [plane] 7x7 maximisers (nullable) */
+  float* dt_dev;        /* [1] step size (output unless fixed_dt) */
+  const uint8_t* dirichlet_mask;  /* nullable */
+  float dirichlet_state[4];
+  float ref[4];
+  float gamma, cfl;
+  int fixed_dt;         /* 1: use *dt_dev as given */
+  const fcsd_mlp* w;    /* NULL: mu given */
+} fcsd_step_args;
+
+/* One full time step (Algorithm 1): glue, network classes and viscosity
+ * (when w != NULL), step size, five fused stages with glue on every stage
+ * input.  use_graph = 1 captures the step once into a hipGraph and replays
+ * it on later calls with identical arguments. */
+fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* a,
+                      int64_t plane, void* ws, size_t ws_bytes, int use_graph);
+
+/* ---- host-only helpers (no device needed) ------------------------------- */
+
+/* FC-Gram continuation matrix A_r Q^T (C x d, row-major FP64) exactly as the
+ * library builds it; A_l Q^T[m][j] = A_r Q^T[C-1-m][d-1-j]. */
+fcsd_status fcsd_fc_matrix(int d, int C, double* out);
+/* Checks a patch table exactly as fcsd_set_create does, without a device;
+ * writes a message into msg (msglen bytes) on failure. */
+fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* patches, int d, int64_t plane,
+                                  int ring_sectors, int ring_shells, char* msg, int msglen);
+/* Radix factorisation of L (returns FCSD_EUNSUPPORTED if none). */
+fcsd_status fcsd_fft_plan(int L, int* nstages, int radices[8]);
+const char* fcsd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCSDNN_H */

@@ -1,0 +1,283 @@
+"""Torch-facing wrappers of the C ABI (same names as include/fcsdnn.h).
+
+Torch supplies device memory and streams only.  A ``Context`` owns the
+library context and its HIP stream (wrapped as a torch ExternalStream);
+every call orders itself after torch's current stream and makes torch's
+current stream wait for it, so tensors can be used freely on either side.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from ._lib import (FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP, lib,
+                   patch_descs)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _f4(vals):
+    return (ctypes.c_float * 4)(*[float(v) for v in vals])
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise FcsdError(3, "no HIP device")
+        torch.cuda.set_device(device)
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = lib().fcsd_ctx_create(device, None, ctypes.byref(h))
+        if rc:
+            raise FcsdError(rc, "fcsd_ctx_create")
+        self.h = h
+        self.stream = torch.cuda.ExternalStream(lib().fcsd_ctx_stream(h), device=torch.device("cuda", device))
+
+    def check(self, rc, what):
+        if rc:
+            raise FcsdError(rc, f"{what}: {lib().fcsd_last_error(self.h).decode()}")
+
+    def enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+
+    def leave(self):
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def sync(self):
+        self.check(lib().fcsd_ctx_sync(self.h), "sync")
+
+    def close(self):
+        if self.h:
+            lib().fcsd_ctx_destroy(self.h)
+            self.h = None
+
+
+class PatchSet:
+    """Device-side patch set built from plain arrays (n1, n2, C1, C2, off,
+    hhat, htilde, internal) and the plane size."""
+
+    def __init__(self, ctx: Context, n1, n2, C1, C2, off, hhat, htilde, internal, d: int, plane: int,
+                 ring_sectors: int = 0, ring_shells: int = 0):
+        self.ctx = ctx
+        self.plane = int(plane)
+        self.npatch = len(n1)
+        self.npoints = int(np.sum(np.asarray(n1, np.int64) * np.asarray(n2, np.int64)))
+        self.descs = patch_descs(n1, n2, C1, C2, off, hhat, htilde, internal)
+        h = ctypes.c_void_p()
+        ctx.check(lib().fcsd_set_create(ctx.h, self.npatch, self.descs, d, self.plane, ring_sectors,
+                                        ring_shells, ctypes.byref(h)), "fcsd_set_create")
+        self.h = h
+        self._ws = {}
+
+    @classmethod
+    def from_layout(cls, ctx, ps):
+        """From any object with the attributes of synth.PatchSet."""
+        return cls(ctx, ps.n1, ps.n2, ps.C1, ps.C2, ps.off, ps.hhat, ps.htilde, ps.internal, ps.d,
+                   ps.plane, ps.nsec, ps.nshell)
+
+    def workspace_size(self, op: int) -> int:
+        b = ctypes.c_size_t()
+        self.ctx.check(lib().fcsd_workspace_size(self.h, op, ctypes.byref(b)), "workspace_size")
+        return b.value
+
+    def workspace(self, op: int) -> torch.Tensor:
+        if op not in self._ws:
+            n = (self.workspace_size(op) + 3) // 4
+            self._ws[op] = torch.empty(n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        return self._ws[op]
+
+    def ext_size(self, direction: int) -> int:
+        v = ctypes.c_int64()
+        self.ctx.check(lib().fcsd_ext_size(self.h, direction, ctypes.byref(v)), "ext_size")
+        return v.value
+
+    def close(self):
+        if self.h:
+            lib().fcsd_set_destroy(self.h)
+            self.h = None
+
+
+def _call(s: PatchSet, name, *args):
+    ctx = s.ctx
+    ctx.enter()
+    rc = getattr(lib(), name)(ctx.h, s.h, *args)
+    ctx.leave()
+    ctx.check(rc, name)
+
+
+def _chk(t, dtype=torch.float32, numel=None, name="tensor"):
+    if t is None:
+        return
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise FcsdError(1, f"{name}: needs a contiguous {dtype} device tensor")
+    if numel is not None and t.numel() < numel:
+        raise FcsdError(1, f"{name}: has {t.numel()} elements, needs {numel}")
+
+
+# ------------------------------------------------------------------ line operators
+
+def fc_diff(s, direction, inp, out, nf=None):
+    nf = nf or inp.numel() // s.plane
+    _chk(inp, numel=nf * s.plane, name="in"), _chk(out, numel=nf * s.plane, name="out")
+    _call(s, "fc_diff", direction, nf, _p(inp), _p(out), s.plane)
+
+
+def fc_diff_adj(s, direction, out_bar, in_bar, nf=None):
+    nf = nf or out_bar.numel() // s.plane
+    _chk(out_bar, numel=nf * s.plane), _chk(in_bar, numel=nf * s.plane)
+    _call(s, "fc_diff_adj", direction, nf, _p(out_bar), _p(in_bar), s.plane)
+
+
+def fc_continue(s, direction, inp, ext, nf=None):
+    nf = nf or inp.numel() // s.plane
+    ep = s.ext_size(direction)
+    _chk(inp, numel=nf * s.plane), _chk(ext, numel=nf * ep)
+    _call(s, "fc_continue", direction, nf, _p(inp), s.plane, _p(ext), ep)
+
+
+def fc_continue_adj(s, direction, ext_bar, in_bar, nf=None):
+    ep = s.ext_size(direction)
+    nf = nf or ext_bar.numel() // ep
+    _chk(ext_bar, numel=nf * ep), _chk(in_bar, numel=nf * s.plane)
+    _call(s, "fc_continue_adj", direction, nf, _p(ext_bar), ep, _p(in_bar), s.plane)
+
+
+# ------------------------------------------------------------------ right-hand side
+
+def euler_rhs(s, u, metric, ref, gamma, rhs):
+    _chk(u, numel=4 * s.plane), _chk(metric, numel=4 * s.plane), _chk(rhs, numel=4 * s.plane)
+    ws = s.workspace(WS_RHS)
+    _call(s, "euler_rhs", _p(u), _p(metric), _f4(ref), float(gamma), _p(rhs), s.plane, _p(ws), ws.numel() * 4)
+
+
+def av_apply(s, u, metric, mu, ref, rhs):
+    _chk(u, numel=4 * s.plane), _chk(mu, numel=s.plane), _chk(rhs, numel=4 * s.plane)
+    ws = s.workspace(WS_RHS)
+    _call(s, "av_apply", _p(u), _p(metric), _p(mu), _f4(ref), _p(rhs), s.plane, _p(ws), ws.numel() * 4)
+
+
+def fcsd_rhs(s, u, metric, mu, ref, gamma, rhs):
+    _chk(u, numel=4 * s.plane), _chk(metric, numel=4 * s.plane), _chk(mu, numel=s.plane)
+    _chk(rhs, numel=4 * s.plane)
+    ws = s.workspace(WS_RHS)
+    _call(s, "fcsd_rhs", _p(u), _p(metric), _p(mu), _f4(ref), float(gamma), _p(rhs), s.plane, _p(ws),
+          ws.numel() * 4)
+
+
+def fcsd_rhs_adj(s, u, metric, mu, ref, gamma, rhs_bar, u_bar, mu_bar=None):
+    _chk(u, numel=4 * s.plane), _chk(rhs_bar, numel=4 * s.plane), _chk(u_bar, numel=4 * s.plane)
+    _chk(mu, numel=s.plane), _chk(mu_bar, numel=s.plane)
+    ws = s.workspace(WS_RHS_ADJ)
+    _call(s, "fcsd_rhs_adj", _p(u), _p(metric), _p(mu), _f4(ref), float(gamma), _p(rhs_bar), _p(u_bar),
+          _p(mu_bar), s.plane, _p(ws), ws.numel() * 4)
+
+
+# ------------------------------------------------------------------ stepping
+
+def rk_stage(s, stage, dt_dev, rhs, u0, ui, acc, uout):
+    for t in (rhs, u0, ui, uout):
+        _chk(t, numel=4 * s.plane)
+    _chk(acc, numel=4 * s.plane), _chk(dt_dev, numel=1)
+    _call(s, "rk_stage", int(stage), _p(dt_dev), _p(rhs), _p(u0), _p(ui), _p(acc), _p(uout), s.plane)
+
+
+def rk_stage_adj(s, stage, dt_dev, uout_bar, u0_bar, ui_bar, acc_bar, rhs_bar):
+    _call(s, "rk_stage_adj", int(stage), _p(dt_dev), _p(uout_bar), _p(u0_bar), _p(ui_bar), _p(acc_bar),
+          _p(rhs_bar), s.plane)
+
+
+def fcsd_cfl_dt(s, u, mu, cfl, gamma, dt_dev):
+    _chk(u, numel=4 * s.plane), _chk(mu, numel=s.plane), _chk(dt_dev, numel=1)
+    ws = s.workspace(WS_AV)
+    _call(s, "fcsd_cfl_dt", _p(u), _p(mu), float(cfl), float(gamma), _p(dt_dev), s.plane, _p(ws),
+          ws.numel() * 4)
+
+
+# ------------------------------------------------------------------ viscosity
+
+def mlp_struct(W: dict):
+    m = Mlp()
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        _chk(W[k], name=k)
+        setattr(m, k, W[k].data_ptr())
+    return m
+
+
+def sdnn_infer(s, u, gamma, W, tau, logits=None):
+    _chk(u, numel=4 * s.plane), _chk(tau, torch.int8, s.plane), _chk(logits, numel=8 * s.plane)
+    m = mlp_struct(W)
+    ws = s.workspace(WS_AV)
+    _call(s, "sdnn_infer", _p(u), float(gamma), ctypes.byref(m), _p(tau), _p(logits), s.plane, _p(ws),
+          ws.numel() * 4)
+
+
+def av_viscosity(s, u, tau, gamma, mu, argmax=None):
+    _chk(u, numel=4 * s.plane), _chk(tau, torch.int8, s.plane), _chk(mu, numel=s.plane)
+    _chk(argmax, torch.int32, s.plane)
+    ws = s.workspace(WS_AV)
+    _call(s, "av_viscosity", _p(u), _p(tau), float(gamma), _p(mu), _p(argmax), s.plane, _p(ws), ws.numel() * 4)
+
+
+def av_viscosity_adj(s, u, tau, argmax, gamma, mu_bar, u_bar):
+    _chk(u, numel=4 * s.plane), _chk(tau, torch.int8, s.plane), _chk(argmax, torch.int32, s.plane)
+    _chk(mu_bar, numel=s.plane), _chk(u_bar, numel=4 * s.plane)
+    ws = s.workspace(WS_AV)
+    _call(s, "av_viscosity_adj", _p(u), _p(tau), _p(argmax), float(gamma), _p(mu_bar), _p(u_bar), s.plane,
+          _p(ws), ws.numel() * 4)
+
+
+def fcsd_glue(s, u, mask=None, state=(0, 0, 0, 0)):
+    _chk(u, numel=4 * s.plane), _chk(mask, torch.uint8, s.plane)
+    _call(s, "fcsd_glue", _p(u), s.plane, _p(mask), _f4(state))
+
+
+# ------------------------------------------------------------------ fused
+
+def fcsd_stage(s, stage, u0, ui, acc, uout, metric, mu, ref, gamma, dt_dev, per_patch=False):
+    for t in (u0, ui, acc, uout, metric):
+        _chk(t, numel=4 * s.plane)
+    _chk(mu, numel=s.plane), _chk(dt_dev, numel=1)
+    ws = s.workspace(WS_RHS)
+    name = "fcsd_stage_per_patch" if per_patch else "fcsd_stage"
+    _call(s, name, int(stage), _p(u0), _p(ui), _p(acc), _p(uout), _p(metric), _p(mu), _f4(ref),
+          float(gamma), _p(dt_dev), s.plane, _p(ws), ws.numel() * 4)
+
+
+class Stepper:
+    """Holds the buffers of fcsd_step (state advanced in place)."""
+
+    def __init__(self, s: PatchSet, u, metric, ref, gamma=1.4, cfl=0.5, W=None, mu=None,
+                 dirichlet_mask=None, dirichlet_state=(0, 0, 0, 0), fixed_dt=None):
+        dev = u.device
+        self.s = s
+        self.u, self.metric = u, metric
+        self.W = W
+        self.mu = mu if mu is not None else torch.zeros(s.plane, device=dev)
+        self.tau = torch.zeros(s.plane, dtype=torch.int8, device=dev)
+        self.argmax = torch.zeros(s.plane, dtype=torch.int32, device=dev)
+        self.dt = torch.zeros(1, device=dev)
+        self.mask = dirichlet_mask
+        a = StepArgs()
+        a.u, a.metric, a.mu = u.data_ptr(), metric.data_ptr(), self.mu.data_ptr()
+        a.tau, a.argmax, a.dt_dev = self.tau.data_ptr(), self.argmax.data_ptr(), self.dt.data_ptr()
+        a.dirichlet_mask = dirichlet_mask.data_ptr() if dirichlet_mask is not None else None
+        a.dirichlet_state = _f4(dirichlet_state)
+        a.ref = _f4(ref)
+        a.gamma, a.cfl = float(gamma), float(cfl)
+        a.fixed_dt = 0
+        if fixed_dt is not None:
+            self.dt.fill_(float(fixed_dt))
+            a.fixed_dt = 1
+        self.mlp = mlp_struct(W) if W is not None else None
+        a.w = ctypes.cast(ctypes.pointer(self.mlp), ctypes.c_void_p) if W is not None else None
+        self.args = a
+        self.ws = s.workspace(WS_STEP)
+
+    def step(self, use_graph=False):
+        _call(self.s, "fcsd_step", ctypes.byref(self.args), self.s.plane, _p(self.ws), self.ws.numel() * 4,
+              1 if use_graph else 0)

@@ -1,0 +1,189 @@
+// Host-side precomputation for the FC line engine (compiled with g++).
+//
+//  * FC-Gram continuation matrix A_r Q^T (paper Sec. 2.2, eq. "continuation").
+//    The right blend of the d end samples is the least-squares
+//    trigonometric polynomial (period P = 2(d + C) grid intervals, modes
+//    0..K, K = 18) that matches the degree-(d-1) interpolant of the samples
+//    on the matching interval [0, d-1] and vanishes on [d+C, 2d+C-1], both
+//    sampled 20 times per interval; its values at d..d+C-1 form the tail.
+//    The operator is linear in the samples, so column j of A_r Q^T is the
+//    blend of the j-th Lagrange basis polynomial of the matching points.  (In
+//    the Gram basis the same matrix factors as A_r Q^T; the Lagrange form
+//    needs no orthogonalisation.)  The fit is solved by Householder QR in
+//    IEEE binary128 (__float128), then rounded to double.
+//  * Mixed-radix factorisation of the extension length L = N + C and the
+//    FP32 twiddle table exp(-2 pi i n / L), computed in binary128.
+#include <quadmath.h>
+
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+typedef __float128 qf;
+
+const int kModes = 18;
+const int kOversample = 20;
+
+// cos and sin of 2 pi num / den with exact integer range reduction
+void cis2pi(int64_t num, int64_t den, qf* c, qf* s) {
+  num %= den;
+  if (num < 0) num += den;
+  qf a = 2 * M_PIq * (qf)num / (qf)den;
+  *c = cosq(a);
+  *s = sinq(a);
+}
+
+}  // namespace
+
+extern "C" int fcsd_host_fc_matrix(int d, int C, double* out) {
+  if (d < 1 || d > 8 || C < 1 || C > 256 || !out) return 1;
+  const int P = 2 * (d + C);           // period in grid intervals
+  const int ncol = 2 * kModes + 1;
+  const int per = (d - 1) * kOversample + 1;
+  const int nrow = (d == 1) ? 2 : 2 * per;
+  // sample points in units of 1/kOversample grid intervals
+  std::vector<int64_t> pts;
+  for (int i = 0; i < per; ++i) pts.push_back(i);
+  for (int i = 0; i < per; ++i) pts.push_back((int64_t)(d + C) * kOversample + i);
+  const int m = (int)pts.size();
+  (void)nrow;
+  const int64_t den = (int64_t)P * kOversample;  // angle = 2 pi n s / (P * os)
+  std::vector<qf> A((size_t)m * ncol);
+  for (int r = 0; r < m; ++r) {
+    A[(size_t)r * ncol] = 1;
+    for (int n = 1; n <= kModes; ++n) {
+      qf c, s;
+      cis2pi((int64_t)n * pts[r], den, &c, &s);
+      A[(size_t)r * ncol + 2 * n - 1] = c;
+      A[(size_t)r * ncol + 2 * n] = s;
+    }
+  }
+  // right-hand sides: Lagrange basis polynomial j on the matching interval, 0 on the zero interval
+  std::vector<qf> B((size_t)m * d, 0);
+  for (int r = 0; r < per; ++r) {
+    qf t = (qf)pts[r] / kOversample;
+    for (int j = 0; j < d; ++j) {
+      qf v = 1;
+      for (int k = 0; k < d; ++k)
+        if (k != j) v *= (t - k) / (qf)(j - k);
+      B[(size_t)r * d + j] = v;
+    }
+  }
+  // Householder QR of A applied to B
+  for (int k = 0; k < ncol; ++k) {
+    qf nrm = 0;
+    for (int r = k; r < m; ++r) nrm += A[(size_t)r * ncol + k] * A[(size_t)r * ncol + k];
+    nrm = sqrtq(nrm);
+    if (nrm == 0) return 2;
+    qf akk = A[(size_t)k * ncol + k];
+    qf alpha = akk > 0 ? -nrm : nrm;
+    std::vector<qf> v(m - k);
+    v[0] = akk - alpha;
+    for (int r = k + 1; r < m; ++r) v[r - k] = A[(size_t)r * ncol + k];
+    qf vv = 0;
+    for (qf x : v) vv += x * x;
+    if (vv == 0) continue;
+    for (int c = k; c < ncol; ++c) {
+      qf dot = 0;
+      for (int r = k; r < m; ++r) dot += v[r - k] * A[(size_t)r * ncol + c];
+      qf f = 2 * dot / vv;
+      for (int r = k; r < m; ++r) A[(size_t)r * ncol + c] -= f * v[r - k];
+    }
+    for (int c = 0; c < d; ++c) {
+      qf dot = 0;
+      for (int r = k; r < m; ++r) dot += v[r - k] * B[(size_t)r * d + c];
+      qf f = 2 * dot / vv;
+      for (int r = k; r < m; ++r) B[(size_t)r * d + c] -= f * v[r - k];
+    }
+  }
+  // back substitution R x = (Q^T B)[:ncol]
+  std::vector<qf> X((size_t)ncol * d);
+  for (int c = 0; c < d; ++c) {
+    for (int i = ncol - 1; i >= 0; --i) {
+      qf acc = B[(size_t)i * d + c];
+      for (int j = i + 1; j < ncol; ++j) acc -= A[(size_t)i * ncol + j] * X[(size_t)j * d + c];
+      X[(size_t)i * d + c] = acc / A[(size_t)i * ncol + i];
+    }
+  }
+  // evaluate at the continuation points t = d .. d+C-1
+  for (int mm = 0; mm < C; ++mm) {
+    int64_t t = (int64_t)(d + mm) * kOversample;
+    for (int c = 0; c < d; ++c) {
+      qf acc = X[c];
+      for (int n = 1; n <= kModes; ++n) {
+        qf cs, sn;
+        cis2pi((int64_t)n * t, den, &cs, &sn);
+        acc += X[(size_t)(2 * n - 1) * d + c] * cs + X[(size_t)(2 * n) * d + c] * sn;
+      }
+      out[(size_t)mm * d + c] = (double)acc;
+    }
+  }
+  return 0;
+}
+
+// Twiddle table w[n] = exp(-2 pi i n / L), n < L, interleaved (re, im) FP32.
+extern "C" void fcsd_host_twiddles(int L, float* out) {
+  for (int n = 0; n < L; ++n) {
+    qf c, s;
+    cis2pi(n, L, &c, &s);
+    out[2 * n] = (float)c;
+    out[2 * n + 1] = (float)(-s);
+  }
+}
+
+// Factor L into supported radices (largest first among 13, 11, 7, 5, 3 then
+// 8/4/2 for the power of two).  Returns the number of stages or 0 if L has
+// another prime factor or needs more than 8 stages.
+extern "C" int fcsd_host_factor(int L, int* rad) {
+  int n = L, k = 0;
+  const int odd[5] = {13, 11, 7, 5, 3};
+  for (int p : odd)
+    while (n % p == 0) {
+      if (k >= 8) return 0;
+      rad[k++] = p;
+      n /= p;
+    }
+  while (n % 8 == 0 && n != 16) {  // prefer 4*4 over 8*2 for 16
+    if (k >= 8) return 0;
+    rad[k++] = 8;
+    n /= 8;
+  }
+  while (n % 4 == 0) {
+    if (k >= 8) return 0;
+    rad[k++] = 4;
+    n /= 4;
+  }
+  while (n % 2 == 0) {
+    if (k >= 8) return 0;
+    rad[k++] = 2;
+    n /= 2;
+  }
+  return n == 1 ? k : 0;
+}
+
+// Position -> signed wavenumber map of the in-place decimation-in-frequency
+// output: position p = sum_s q_s m_s (m_s = L / (r_0 ... r_s)) holds the
+// coefficient of frequency k = sum_s q_s (r_0 ... r_{s-1}).  Fills the
+// derivative multiplier 2 pi k (N-1) / L^2 (the FFT normalisation 1/L and
+// the period beta = L/(N-1) folded in); Nyquist of even L is zero.
+extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic) {
+  for (int p = 0; p < L; ++p) {
+    int rem = p, M = L;
+    int64_t k = 0, place = 1;
+    for (int s = 0; s < nst; ++s) {
+      int m = M / rad[s];
+      int q = rem / m;
+      rem -= q * m;
+      k += (int64_t)q * place;
+      place *= rad[s];
+      M = m;
+    }
+    int64_t ks = (k <= L / 2) ? k : k - L;
+    if (L % 2 == 0 && k == L / 2) ks = 0;
+    // derivative w.r.t. q in [0, 1]: beta = L h, h = 1/(N-1); periodic mode h = 1/N, beta = 1
+    qf scale = periodic ? 2 * M_PIq / L : 2 * M_PIq * (N - 1) / ((qf)L * L);
+    out[p] = (float)(scale * (qf)ks);
+  }
+}

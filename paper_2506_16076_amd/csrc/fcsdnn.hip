@@ -1,0 +1,1014 @@
+// libfcsdnn: host side of the C ABI declared in include/fcsdnn.h.
+#include "../../include/fcsdnn.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels2.h"
+
+using namespace fcsd;
+
+extern "C" int fcsd_host_fc_matrix(int d, int C, double* out);
+extern "C" void fcsd_host_twiddles(int L, float* out);
+extern "C" int fcsd_host_factor(int L, int* rad);
+extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic);
+
+namespace {
+
+constexpr size_t kLdsBudget = 65536;  // bytes of LDS per line-engine workgroup
+
+struct GraphEntry {
+  std::vector<unsigned char> key;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct fcsd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+};
+
+namespace {
+
+struct DirPlan {
+  std::vector<PlanDev> plans;             // one per patch
+  std::vector<TileDev> tiles;             // LPT order
+  std::vector<TileDev> tiles_by_patch;    // patch-contiguous
+  std::vector<int> patch_begin;           // npatch + 1
+  std::vector<size_t> patch_lds;          // per patch
+  std::vector<long long> ext_off;         // per plan
+  long long ext_plane = 0;
+  size_t lds = 0;
+  PlanDev* d_plans = nullptr;
+  TileDev* d_tiles = nullptr;
+  TileDev* d_tiles_bp = nullptr;
+  long long* d_ext_off = nullptr;
+};
+
+}  // namespace
+
+struct fcsd_set {
+  fcsd_ctx* ctx = nullptr;
+  int npatch = 0, d = 0;
+  long long plane = 0;
+  long long npoints = 0;
+  std::vector<fcsd_patch_desc> desc;
+  DirPlan dir[2];
+  float2* d_tw = nullptr;
+  float* d_km = nullptr;
+  double* d_aq = nullptr;
+  PatchDev* d_patches = nullptr;
+  ChunkDev* d_chunks = nullptr;
+  int nchunks = 0;
+  std::vector<int> patch_chunk_begin;
+  LatDev* d_lats = nullptr;
+  ChunkDev* d_lchunks = nullptr;
+  int nlchunks = 0;
+  long long lat_size = 0;
+  int annulus = 0;
+  AnnulusDev an{};
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+fcsd_status fail(fcsd_ctx* c, fcsd_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, FCSD_EHIP, std::string(#call ": ") + hipGetErrorString(e_));    \
+  } while (0)
+
+template <class T>
+fcsd_status upload(fcsd_ctx* ctx, T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return FCSD_OK;
+  HIPCHK(ctx, hipMalloc((void**)dst, v.size() * sizeof(T)));
+  HIPCHK(ctx, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FCSD_OK;
+}
+
+fcsd_status launch_check(fcsd_ctx* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, FCSD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return FCSD_OK;
+}
+
+PassArgs base_args(const fcsd_set* s, int dir) {
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.plans = s->dir[dir - 1].d_plans;
+  a.tiles = s->dir[dir - 1].d_tiles;
+  a.tw = s->d_tw;
+  a.km = s->d_km;
+  a.aq = s->d_aq;
+  a.d = s->d;
+  a.plane = s->plane;
+  return a;
+}
+
+void set_ref(PassArgs& a, const float ref[4], float gamma) {
+  a.gamma = gamma;
+  for (int k = 0; k < 4; ++k) a.pref[k] = ref[k];
+  const double r = ref[0], u = ref[1], v = ref[2], p = ref[3];
+  a.eref[0] = (float)r;
+  a.eref[1] = (float)(r * u);
+  a.eref[2] = (float)(r * v);
+  a.eref[3] = (float)(p / (gamma - 1.0) + 0.5 * r * (u * u + v * v));
+}
+
+unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// launch a line-engine kernel over the batched tile list or one patch's tiles
+template <class K>
+fcsd_status launch_lines(const fcsd_set* s, int dir, K kern, PassArgs a, int patch = -1) {
+  const DirPlan& D = s->dir[dir - 1];
+  unsigned grid;
+  size_t lds;
+  if (patch < 0) {
+    a.tiles = D.d_tiles;
+    grid = (unsigned)D.tiles.size();
+    lds = D.lds;
+  } else {
+    a.tiles = D.d_tiles_bp + D.patch_begin[patch];
+    grid = (unsigned)(D.patch_begin[patch + 1] - D.patch_begin[patch]);
+    lds = D.patch_lds[patch];
+  }
+  if (grid == 0) return FCSD_OK;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s->ctx->stream, a);
+  return launch_check(s->ctx, "line kernel");
+}
+
+fcsd_status check_set(fcsd_ctx* ctx, const fcsd_set* s, int64_t plane) {
+  if (!ctx) return FCSD_EINVAL;
+  if (!s) return fail(ctx, FCSD_EINVAL, "null patch set");
+  if (s->ctx != ctx) return fail(ctx, FCSD_EINVAL, "patch set belongs to another context");
+  if (plane != s->plane) return fail(ctx, FCSD_EINVAL, "plane size differs from the patch set's");
+  return FCSD_OK;
+}
+
+size_t ws_planes(const fcsd_set* s, int op) {
+  switch (op) {
+    case FCSD_WS_RHS: return 16;
+    case FCSD_WS_AV: return 11;
+    case FCSD_WS_STEP: return 16 + 12 + 11;
+    case FCSD_WS_RHS_ADJ: return 24;
+    default: return 0;
+  }
+}
+
+size_t ws_bytes_of(const fcsd_set* s, int op) {
+  size_t b = ws_planes(s, op) * (size_t)s->plane * sizeof(float);
+  if (op == FCSD_WS_AV || op == FCSD_WS_STEP) b += 2 * sizeof(unsigned) * (size_t)(s->npatch + 64);
+  return b;
+}
+
+}  // namespace
+
+// ======================================================================== context
+
+extern "C" fcsd_status fcsd_ctx_create(int device, void* stream, fcsd_ctx** out) {
+  if (!out) return FCSD_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return FCSD_EDEVICE;
+  if (device < 0 || device >= n) return FCSD_EINVAL;
+  std::unique_ptr<fcsd_ctx> c(new fcsd_ctx);
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) return FCSD_EDEVICE;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return FCSD_EHIP;
+    c->own_stream = true;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return FCSD_EHIP;
+  *out = c.release();
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_ctx_destroy(fcsd_ctx* ctx) {
+  if (!ctx) return FCSD_EINVAL;
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_ctx_set_stream(fcsd_ctx* ctx, void* stream) {
+  if (!ctx) return FCSD_EINVAL;
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  ctx->own_stream = false;
+  ctx->stream = (hipStream_t)stream;
+  return FCSD_OK;
+}
+
+extern "C" void* fcsd_ctx_stream(fcsd_ctx* ctx) { return ctx ? (void*)ctx->stream : nullptr; }
+
+extern "C" fcsd_status fcsd_ctx_sync(fcsd_ctx* ctx) {
+  if (!ctx) return FCSD_EINVAL;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return FCSD_OK;
+}
+
+extern "C" const char* fcsd_last_error(const fcsd_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+extern "C" const char* fcsd_version(void) { return "fcsdnn 0.1 gfx950"; }
+
+// ======================================================================== host-only helpers
+
+extern "C" fcsd_status fcsd_fc_matrix(int d, int C, double* out) {
+  if (!out || d < 1 || d > 8 || C < 1 || C > 256) return FCSD_EINVAL;
+  return fcsd_host_fc_matrix(d, C, out) == 0 ? FCSD_OK : FCSD_EUNSUPPORTED;
+}
+
+extern "C" fcsd_status fcsd_fft_plan(int L, int* nst, int rad[8]) {
+  if (!nst || !rad || L < 2) return FCSD_EINVAL;
+  int k = fcsd_host_factor(L, rad);
+  *nst = k;
+  return k ? FCSD_OK : FCSD_EUNSUPPORTED;
+}
+
+// Validate a patch table without a device (also used by fcsd_set_create).
+extern "C" fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* p, int d, int64_t plane,
+                                             int ring_sectors, int ring_shells, char* msg, int msglen) {
+  auto say = [&](const std::string& m) {
+    if (msg && msglen > 0) snprintf(msg, (size_t)msglen, "%s", m.c_str());
+  };
+  if (npatch <= 0 || !p) return say("no patches"), FCSD_EINVAL;
+  if (d < 1 || d > 8) return say("d must be in 1..8"), FCSD_EINVAL;
+  std::vector<std::pair<long long, long long>> iv;
+  for (int i = 0; i < npatch; ++i) {
+    const fcsd_patch_desc& q = p[i];
+    char b[160];
+    if (q.n1 < 2 * d + 1 || q.n2 < 2 * d + 1 || q.n1 > 4096 || q.n2 > 4096) {
+      snprintf(b, sizeof b, "patch %d: sides must be in [2d+1, 4096]", i);
+      return say(b), FCSD_EINVAL;
+    }
+    if (q.C1 < 0 || q.C2 < 0 || q.C1 > 256 || q.C2 > 256) {
+      snprintf(b, sizeof b, "patch %d: C must be in [0, 256]", i);
+      return say(b), FCSD_EINVAL;
+    }
+    if (q.off < 0 || q.off + (long long)q.n1 * q.n2 > plane) {
+      snprintf(b, sizeof b, "patch %d lies outside the plane", i);
+      return say(b), FCSD_EINVAL;
+    }
+    if (!(q.htilde > 0) || !(q.hhat > 0)) {
+      snprintf(b, sizeof b, "patch %d: spacing bounds must be positive", i);
+      return say(b), FCSD_EINVAL;
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+      const int N = dir ? q.n2 : q.n1, C = dir ? q.C2 : q.C1, L = N + C;
+      int rad[8];
+      if (L > 4096 || fcsd_host_factor(L, rad) == 0) {
+        snprintf(b, sizeof b, "patch %d: extension length %d has a prime factor above 13", i, L);
+        return say(b), FCSD_EUNSUPPORTED;
+      }
+    }
+    iv.push_back({q.off, q.off + (long long)q.n1 * q.n2});
+  }
+  std::sort(iv.begin(), iv.end());
+  for (size_t i = 1; i < iv.size(); ++i)
+    if (iv[i].first < iv[i - 1].second) return say("patches overlap in the plane"), FCSD_EINVAL;
+  if (ring_sectors < 0 || ring_shells < 0) return say("negative ring layout"), FCSD_EINVAL;
+  if (ring_sectors > 0) {
+    if (ring_shells <= 0 || ring_sectors * ring_shells != npatch)
+      return say("ring layout must cover all patches"), FCSD_EINVAL;
+    for (int i = 0; i < npatch; ++i)
+      if (p[i].n1 != p[0].n1 || p[i].n2 != p[0].n2 || p[0].n1 < 2 * kOvl || p[0].n2 < 2 * kOvl)
+        return say("ring patches must share n1, n2 >= 38"), FCSD_EINVAL;
+  }
+  return FCSD_OK;
+}
+
+// ======================================================================== patch set
+
+extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_patch_desc* patches, int d,
+                                       int64_t plane, int ring_sectors, int ring_shells, fcsd_set** out) {
+  if (!ctx || !out) return FCSD_EINVAL;
+  *out = nullptr;
+  char msg[256] = {0};
+  fcsd_status st = fcsd_validate_patches(npatch, patches, d, plane, ring_sectors, ring_shells, msg, 256);
+  if (st != FCSD_OK) return fail(ctx, st, msg);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::unique_ptr<fcsd_set> s(new fcsd_set);
+  s->ctx = ctx;
+  s->npatch = npatch;
+  s->d = d;
+  s->plane = plane;
+  s->desc.assign(patches, patches + npatch);
+  // pools
+  std::vector<float2> tw;
+  std::vector<float> km;
+  std::vector<double> aq;
+  std::map<int, int> tw_of_L, aq_of_C;
+  std::map<std::tuple<int, int, int>, int> km_of;
+  for (int dir = 1; dir <= 2; ++dir) {
+    DirPlan& D = s->dir[dir - 1];
+    D.patch_begin.assign(1, 0);
+    long long eo = 0;
+    for (int p = 0; p < npatch; ++p) {
+      const fcsd_patch_desc& q = patches[p];
+      PlanDev P;
+      memset(&P, 0, sizeof(P));
+      P.N = dir == 1 ? q.n1 : q.n2;
+      P.C = dir == 1 ? q.C1 : q.C2;
+      P.L = P.N + P.C;
+      P.periodic = P.C == 0;
+      P.nst = fcsd_host_factor(P.L, P.rad);
+      P.nlines = dir == 1 ? q.n2 : q.n1;
+      P.n1 = q.n1;
+      P.n2 = q.n2;
+      P.patch = p;
+      P.off = q.off;
+      if (!tw_of_L.count(P.L)) {
+        tw_of_L[P.L] = (int)tw.size();
+        std::vector<float> t(2 * P.L);
+        fcsd_host_twiddles(P.L, t.data());
+        for (int n = 0; n < P.L; ++n) tw.push_back(make_float2(t[2 * n], t[2 * n + 1]));
+      }
+      P.tw = tw_of_L[P.L];
+      auto key = std::make_tuple(P.N, P.L, P.periodic);
+      if (!km_of.count(key)) {
+        km_of[key] = (int)km.size();
+        std::vector<float> t(P.L);
+        fcsd_host_kmul(P.N, P.L, P.nst, P.rad, t.data(), P.periodic);
+        km.insert(km.end(), t.begin(), t.end());
+      }
+      P.km = km_of[key];
+      if (!P.periodic) {
+        if (!aq_of_C.count(P.C)) {
+          aq_of_C[P.C] = (int)aq.size();
+          std::vector<double> m((size_t)P.C * d);
+          if (fcsd_host_fc_matrix(d, P.C, m.data()) != 0)
+            return fail(ctx, FCSD_EUNSUPPORTED, "continuation fit failed");
+          aq.insert(aq.end(), m.begin(), m.end());
+        }
+        P.aq = aq_of_C[P.C];
+      }
+      D.plans.push_back(P);
+      D.ext_off.push_back(eo);
+      eo += (long long)P.nlines * P.L;
+      // tiles
+      int nlmax = (int)(kLdsBudget / (8 * (size_t)P.L)) - 1;
+      nlmax = std::max(1, std::min(kMaxTile, nlmax));
+      const int nt = (P.nlines + nlmax - 1) / nlmax;
+      const int nl = (P.nlines + nt - 1) / nt;
+      size_t plds = 0;
+      for (int t = 0; t < nt; ++t) {
+        TileDev T;
+        T.plan = p;
+        T.line0 = t * nl;
+        T.nl = std::min(nl, P.nlines - T.line0);
+        if (T.nl <= 0) continue;
+        T.ld = T.nl | 1;
+        D.tiles_by_patch.push_back(T);
+        plds = std::max(plds, (size_t)P.L * T.ld * sizeof(float2));
+      }
+      D.patch_begin.push_back((int)D.tiles_by_patch.size());
+      D.patch_lds.push_back(plds);
+      D.lds = std::max(D.lds, plds);
+    }
+    D.ext_plane = eo;
+    D.tiles = D.tiles_by_patch;
+    std::stable_sort(D.tiles.begin(), D.tiles.end(), [&](const TileDev& a, const TileDev& b) {
+      const PlanDev &pa = D.plans[a.plan], &pb = D.plans[b.plan];
+      return (long long)pa.L * a.nl > (long long)pb.L * b.nl;
+    });
+  }
+  // per-patch descriptors and point chunks
+  std::vector<PatchDev> pd;
+  std::vector<ChunkDev> ch;
+  for (int p = 0; p < npatch; ++p) {
+    const fcsd_patch_desc& q = patches[p];
+    PatchDev P;
+    P.n1 = q.n1;
+    P.n2 = q.n2;
+    P.off = q.off;
+    P.hhat = (float)q.hhat;
+    P.htilde = (float)q.htilde;
+    P.internal = (q.internal[0] ? 1 : 0) | (q.internal[1] ? 2 : 0) | (q.internal[2] ? 4 : 0) | (q.internal[3] ? 8 : 0);
+    P.pad = 0;
+    pd.push_back(P);
+    s->patch_chunk_begin.push_back((int)ch.size());
+    for (int k = 0; k < q.n1 * q.n2; k += kChunk) ch.push_back(ChunkDev{p, k});
+    s->npoints += (long long)q.n1 * q.n2;
+  }
+  s->patch_chunk_begin.push_back((int)ch.size());
+  s->nchunks = (int)ch.size();
+  // smoothing-blending lattice
+  std::vector<LatDev> lat;
+  std::vector<ChunkDev> lch;
+  if (ring_sectors > 0) {
+    s->annulus = 1;
+    AnnulusDev& A = s->an;
+    A.nsec = ring_sectors;
+    A.nshell = ring_shells;
+    A.n1 = patches[0].n1;
+    A.n2 = patches[0].n2;
+    A.st1 = A.n1 - kOvl;
+    A.st2 = A.n2 - kOvl;
+    A.ring = A.nsec * A.st1;
+    A.nJ = A.nshell * A.st2 + kOvl;
+    LatDev Lt{A.ring, A.nJ, 1, 0, 0};
+    lat.push_back(Lt);
+    for (long long k = 0; k < (long long)A.ring * A.nJ; k += kChunk) lch.push_back(ChunkDev{0, (int)k});
+    s->lat_size = (long long)A.ring * A.nJ;
+    if (s->lat_size > plane) return fail(ctx, FCSD_EINVAL, "annulus lattice larger than a plane");
+  } else {
+    for (int p = 0; p < npatch; ++p) {
+      LatDev Lt{patches[p].n1, patches[p].n2, 0, 0, patches[p].off};
+      lat.push_back(Lt);
+    }
+    lch = ch;
+    s->lat_size = plane;
+  }
+  s->nlchunks = (int)lch.size();
+  fcsd_status r;
+  if ((r = upload(ctx, &s->d_tw, tw)) || (r = upload(ctx, &s->d_km, km)) || (r = upload(ctx, &s->d_aq, aq)) ||
+      (r = upload(ctx, &s->d_patches, pd)) || (r = upload(ctx, &s->d_chunks, ch)) ||
+      (r = upload(ctx, &s->d_lats, lat)) || (r = upload(ctx, &s->d_lchunks, lch)))
+    return r;
+  if (aq.empty()) {  // keep a valid pointer for kernels
+    std::vector<double> one(1, 0.0);
+    if ((r = upload(ctx, &s->d_aq, one))) return r;
+  }
+  for (int dir = 0; dir < 2; ++dir) {
+    DirPlan& D = s->dir[dir];
+    if ((r = upload(ctx, &D.d_plans, D.plans)) || (r = upload(ctx, &D.d_tiles, D.tiles)) ||
+        (r = upload(ctx, &D.d_tiles_bp, D.tiles_by_patch)) || (r = upload(ctx, &D.d_ext_off, D.ext_off)))
+      return r;
+  }
+  HIPCHK(ctx, hipDeviceSynchronize());
+  *out = s.release();
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
+  if (!s) return FCSD_EINVAL;
+  hipStreamSynchronize(s->ctx->stream);
+  for (auto& g : s->graphs)
+    if (g.exec) hipGraphExecDestroy(g.exec);
+  for (int dir = 0; dir < 2; ++dir) {
+    hipFree(s->dir[dir].d_plans);
+    hipFree(s->dir[dir].d_tiles);
+    hipFree(s->dir[dir].d_tiles_bp);
+    hipFree(s->dir[dir].d_ext_off);
+  }
+  hipFree(s->d_tw);
+  hipFree(s->d_km);
+  hipFree(s->d_aq);
+  hipFree(s->d_patches);
+  hipFree(s->d_chunks);
+  hipFree(s->d_lats);
+  hipFree(s->d_lchunks);
+  delete s;
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_workspace_size(const fcsd_set* s, int op, size_t* bytes) {
+  if (!s || !bytes || op < 0 || op > 3) return FCSD_EINVAL;
+  *bytes = ws_bytes_of(s, op);
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_ext_size(const fcsd_set* s, int dir, int64_t* floats) {
+  if (!s || !floats || (dir != 1 && dir != 2)) return FCSD_EINVAL;
+  *floats = s->dir[dir - 1].ext_plane;
+  return FCSD_OK;
+}
+
+// ======================================================================== line operators
+
+extern "C" fcsd_status fc_diff(fcsd_ctx* ctx, const fcsd_set* s, int dir, int nf, const float* in, float* out,
+                               int64_t plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if ((dir != 1 && dir != 2) || nf < 1 || !in || !out) return fail(ctx, FCSD_EINVAL, "fc_diff: bad arguments");
+  if (in == out) return fail(ctx, FCSD_EINVAL, "fc_diff: out aliases in");
+  PassArgs a = base_args(s, dir);
+  a.nf = nf;
+  a.in = in;
+  a.out = out;
+  return dir == 1 ? launch_lines(s, 1, k_fcdiff<1, false>, a) : launch_lines(s, 2, k_fcdiff<2, false>, a);
+}
+
+extern "C" fcsd_status fc_diff_adj(fcsd_ctx* ctx, const fcsd_set* s, int dir, int nf, const float* out_bar,
+                                   float* in_bar, int64_t plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if ((dir != 1 && dir != 2) || nf < 1 || !out_bar || !in_bar)
+    return fail(ctx, FCSD_EINVAL, "fc_diff_adj: bad arguments");
+  if (out_bar == in_bar) return fail(ctx, FCSD_EINVAL, "fc_diff_adj: in_bar aliases out_bar");
+  PassArgs a = base_args(s, dir);
+  a.nf = nf;
+  a.in = out_bar;
+  a.out = in_bar;
+  return dir == 1 ? launch_lines(s, 1, k_fcdiff<1, true>, a) : launch_lines(s, 2, k_fcdiff<2, true>, a);
+}
+
+extern "C" fcsd_status fc_continue(fcsd_ctx* ctx, const fcsd_set* s, int dir, int nf, const float* in,
+                                   int64_t plane, float* ext, int64_t ext_plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if ((dir != 1 && dir != 2) || nf < 1 || !in || !ext) return fail(ctx, FCSD_EINVAL, "fc_continue: bad arguments");
+  if (ext_plane < s->dir[dir - 1].ext_plane) return fail(ctx, FCSD_EINVAL, "fc_continue: ext_plane too small");
+  PassArgs a = base_args(s, dir);
+  a.nf = nf;
+  a.in = in;
+  a.out = ext;
+  a.ext_plane = ext_plane;
+  a.ext_off = s->dir[dir - 1].d_ext_off;
+  return dir == 1 ? launch_lines(s, 1, k_fccont<1, false>, a) : launch_lines(s, 2, k_fccont<2, false>, a);
+}
+
+extern "C" fcsd_status fc_continue_adj(fcsd_ctx* ctx, const fcsd_set* s, int dir, int nf, const float* ext_bar,
+                                       int64_t ext_plane, float* in_bar, int64_t plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if ((dir != 1 && dir != 2) || nf < 1 || !in_bar || !ext_bar)
+    return fail(ctx, FCSD_EINVAL, "fc_continue_adj: bad arguments");
+  if (ext_plane < s->dir[dir - 1].ext_plane) return fail(ctx, FCSD_EINVAL, "fc_continue_adj: ext_plane too small");
+  PassArgs a = base_args(s, dir);
+  a.nf = nf;
+  a.in = ext_bar;
+  a.out = in_bar;
+  a.ext_plane = ext_plane;
+  a.ext_off = s->dir[dir - 1].d_ext_off;
+  return dir == 1 ? launch_lines(s, 1, k_fccont<1, true>, a) : launch_lines(s, 2, k_fccont<2, true>, a);
+}
+
+// ======================================================================== right-hand side
+
+namespace {
+
+struct RhsWs {
+  float *d1e, *H, *r2;
+};
+
+RhsWs carve_rhs(const fcsd_set* s, void* ws) {
+  float* w = (float*)ws;
+  const long long pl = s->plane;
+  return RhsWs{w, w + 4 * pl, w + 12 * pl};
+}
+
+// flux: FLUX_FULL, FLUX_VISC, FLUX_INVISCID ; out: MODE_SET / MODE_ADD / MODE_RK
+fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric, const float* mu,
+                       const float ref[4], float gamma, int flux, int outmode, float* rhs, int stage,
+                       const float* u0, float* acc, float* uout, const float* dtp, void* ws, int patch) {
+  RhsWs W = carve_rhs(s, ws);
+  PassArgs a = base_args(s, 1);
+  set_ref(a, ref, gamma);
+  a.u = u;
+  a.metric = metric;
+  a.mu = mu;
+  a.d1e = W.d1e;
+  a.H = W.H;
+  a.r2 = W.r2;
+  fcsd_status st;
+  if (flux == FLUX_INVISCID) {
+    if (patch < 0) {
+      hipLaunchKernelGGL(k_passH, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, a, (long long)s->plane);
+    } else {
+      const fcsd_patch_desc& q = s->desc[patch];
+      PassArgs b = a;
+      b.u = u + q.off;
+      b.H = W.H + q.off;
+      const long long n = (long long)q.n1 * q.n2;
+      hipLaunchKernelGGL(k_passH, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, b, n);
+    }
+    if ((st = launch_check(ctx, "pass H"))) return st;
+  } else {
+    a.plans = s->dir[0].d_plans;
+    if ((st = launch_lines(s, 1, k_passA, a, patch))) return st;
+    PassArgs b = a;
+    b.plans = s->dir[1].d_plans;
+    b.mode = flux;
+    if ((st = launch_lines(s, 2, k_passB1, b, patch))) return st;
+  }
+  PassArgs c = a;
+  c.plans = s->dir[1].d_plans;
+  if ((st = launch_lines(s, 2, k_passB2, c, patch))) return st;
+  PassArgs e = a;
+  e.plans = s->dir[0].d_plans;
+  e.mode = outmode;
+  e.rhs = rhs;
+  e.stage = stage;
+  e.u0 = u0;
+  e.ui = u;
+  e.acc = acc;
+  e.uout = uout;
+  e.dt = dtp;
+  return launch_lines(s, 1, k_passC, e, patch);
+}
+
+}  // namespace
+
+extern "C" fcsd_status fcsd_rhs(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
+                                const float* mu, const float ref[4], float gamma, float* rhs, int64_t plane,
+                                void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !metric || !ref || !rhs || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_rhs: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS)) return fail(ctx, FCSD_EINVAL, "fcsd_rhs: workspace too small");
+  return rhs_passes(ctx, s, u, metric, mu, ref, gamma, mu ? FLUX_FULL : FLUX_INVISCID, MODE_SET, rhs, 0, nullptr,
+                    nullptr, nullptr, nullptr, ws, -1);
+}
+
+extern "C" fcsd_status euler_rhs(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
+                                 const float ref[4], float gamma, float* rhs, int64_t plane, void* ws,
+                                 size_t ws_bytes) {
+  return fcsd_rhs(ctx, s, u, metric, nullptr, ref, gamma, rhs, plane, ws, ws_bytes);
+}
+
+extern "C" fcsd_status av_apply(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
+                                const float* mu, const float ref[4], float* rhs, int64_t plane, void* ws,
+                                size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !metric || !mu || !ref || !rhs || !ws) return fail(ctx, FCSD_EINVAL, "av_apply: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS)) return fail(ctx, FCSD_EINVAL, "av_apply: workspace too small");
+  return rhs_passes(ctx, s, u, metric, mu, ref, 1.4f, FLUX_VISC, MODE_ADD, rhs, 0, nullptr, nullptr, nullptr,
+                    nullptr, ws, -1);
+}
+
+// ======================================================================== stepping
+
+extern "C" fcsd_status rk_stage(fcsd_ctx* ctx, const fcsd_set* s, int stage, const float* dt_dev, const float* rhs,
+                                const float* u0, const float* ui, float* acc, float* uout, int64_t plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (stage < 0 || stage > 4 || !dt_dev || !rhs || !u0 || !ui || !uout || (stage >= 2 && !acc))
+    return fail(ctx, FCSD_EINVAL, "rk_stage: bad arguments");
+  if (uout == u0 && stage != 4) return fail(ctx, FCSD_EINVAL, "rk_stage: uout may alias u0 only at stage 4");
+  const long long n4 = 4 * (long long)s->plane;
+  hipLaunchKernelGGL(k_rk, dim3(blocks_for(n4)), dim3(kBlock), 0, ctx->stream, stage, dt_dev, rhs, u0, ui, acc,
+                     uout, n4);
+  return launch_check(ctx, "rk_stage");
+}
+
+extern "C" fcsd_status rk_stage_adj(fcsd_ctx* ctx, const fcsd_set* s, int stage, const float* dt_dev,
+                                    const float* uout_bar, float* u0_bar, float* ui_bar, float* acc_bar,
+                                    float* rhs_bar, int64_t plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (stage < 0 || stage > 4 || !dt_dev || !uout_bar || !u0_bar || !rhs_bar || (stage > 0 && !ui_bar) ||
+      (stage >= 2 && !acc_bar))
+    return fail(ctx, FCSD_EINVAL, "rk_stage_adj: bad arguments");
+  const long long n4 = 4 * (long long)s->plane;
+  hipLaunchKernelGGL(k_rk_adj, dim3(blocks_for(n4)), dim3(kBlock), 0, ctx->stream, stage, dt_dev, uout_bar, u0_bar,
+                     ui_bar, acc_bar, rhs_bar, n4);
+  return launch_check(ctx, "rk_stage_adj");
+}
+
+namespace {
+
+fcsd_status cfl_dt_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* mu, float cfl, float gamma,
+                        float* dt_dev, unsigned* red) {
+  const int np = s->npatch;
+  unsigned* smax = red;
+  unsigned* mmax = red + np;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(2 * np)), dim3(kBlock), 0, ctx->stream, (float*)red, 0.f,
+                     (long long)(2 * np));
+  hipLaunchKernelGGL(k_dt_reduce, dim3(s->nchunks), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->d_patches, u, mu,
+                     (long long)s->plane, gamma, smax, mmax);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(kBlock), 0, ctx->stream, s->d_patches, np, smax, mmax, cfl, dt_dev);
+  return launch_check(ctx, "cfl_dt");
+}
+
+}  // namespace
+
+extern "C" fcsd_status fcsd_cfl_dt(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* mu, float cfl,
+                                   float gamma, float* dt_dev, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !dt_dev || !ws || !(cfl > 0)) return fail(ctx, FCSD_EINVAL, "fcsd_cfl_dt: bad arguments");
+  if (ws_bytes < 2 * sizeof(unsigned) * (size_t)s->npatch)
+    return fail(ctx, FCSD_EINVAL, "fcsd_cfl_dt: workspace too small");
+  return cfl_dt_impl(ctx, s, u, mu, cfl, gamma, dt_dev, (unsigned*)ws);
+}
+
+// ======================================================================== viscosity
+
+namespace {
+
+struct AvWs {
+  float *phi, *S, *rmax, *muh, *num, *den, *t0, *t1, *tp;
+  int* rarg;
+  unsigned* red;
+};
+
+AvWs carve_av(const fcsd_set* s, void* ws) {
+  float* w = (float*)ws;
+  const long long pl = s->plane;
+  AvWs A;
+  A.phi = w;
+  A.S = w + pl;
+  A.rmax = w + 2 * pl;
+  A.rarg = (int*)(w + 3 * pl);
+  A.muh = w + 4 * pl;
+  A.num = w + 5 * pl;
+  A.den = w + 6 * pl;
+  A.t0 = w + 7 * pl;
+  A.t1 = w + 8 * pl;
+  A.tp = w + 9 * pl;
+  A.red = (unsigned*)(w + 11 * pl);
+  return A;
+}
+
+fcsd_status sdnn_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float gamma, const fcsd_mlp* w,
+                      int8_t* tau, float* logits, float* phi) {
+  hipLaunchKernelGGL(k_proxy, dim3(s->nchunks), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->d_patches, u,
+                     (long long)s->plane, gamma, phi, (float*)nullptr);
+  MlpPtr m{w->W1, w->b1, w->W2, w->b2, w->W3, w->b3};
+  hipLaunchKernelGGL(k_sdnn, dim3(s->nchunks), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->d_patches,
+                     (const float*)phi, m, (signed char*)tau, logits, (long long)s->plane);
+  return launch_check(ctx, "sdnn_infer");
+}
+
+// forward Lambda denominators (den = conv of the D~ indicator) into A.t1
+fcsd_status lambda_forward(fcsd_ctx* ctx, const fcsd_set* s, const AvWs& A, const float* muh, float* mu) {
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_lat_gather, dim3(s->nlchunks), dim3(kBlock), 0, st, s->d_lchunks, s->d_lats, s->d_patches,
+                     s->an, muh, A.num, A.den, s->annulus, 0);
+  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, st, s->d_lchunks, s->d_lats,
+                     (const float*)A.num, (const float*)A.den, A.t0, A.t1, 0);
+  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, st, s->d_lchunks, s->d_lats,
+                     (const float*)A.t0, (const float*)A.t1, A.num, A.den, 1);
+  if (mu)
+    hipLaunchKernelGGL(k_lat_scatter, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches, s->an,
+                       s->annulus, (const float*)A.num, (const float*)A.den, mu);
+  return launch_check(ctx, "lambda");
+}
+
+fcsd_status viscosity_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const int8_t* tau, float gamma,
+                           float* mu, int32_t* argmax, const AvWs& A) {
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_proxy, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches, u,
+                     (long long)s->plane, gamma, (float*)nullptr, A.S);
+  hipLaunchKernelGGL(k_rowmax, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches, (const float*)A.S,
+                     A.rmax, A.rarg);
+  hipLaunchKernelGGL(k_muhat, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches,
+                     (const float*)A.rmax, (const int*)A.rarg, (const signed char*)tau, A.muh, (int*)argmax);
+  fcsd_status r = launch_check(ctx, "mu hat");
+  if (r) return r;
+  return lambda_forward(ctx, s, A, A.muh, mu);
+}
+
+}  // namespace
+
+extern "C" fcsd_status sdnn_infer(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float gamma, const fcsd_mlp* w,
+                                  int8_t* tau, float* logits, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !w || !tau || !ws || !w->W1 || !w->b1 || !w->W2 || !w->b2 || !w->W3 || !w->b3)
+    return fail(ctx, FCSD_EINVAL, "sdnn_infer: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_AV)) return fail(ctx, FCSD_EINVAL, "sdnn_infer: workspace too small");
+  return sdnn_impl(ctx, s, u, gamma, w, tau, logits, carve_av(s, ws).phi);
+}
+
+extern "C" fcsd_status av_viscosity(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const int8_t* tau, float gamma,
+                                    float* mu, int32_t* argmax, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !tau || !mu || !ws) return fail(ctx, FCSD_EINVAL, "av_viscosity: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_AV)) return fail(ctx, FCSD_EINVAL, "av_viscosity: workspace too small");
+  return viscosity_impl(ctx, s, u, tau, gamma, mu, argmax, carve_av(s, ws));
+}
+
+extern "C" fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const int8_t* tau,
+                                        const int32_t* argmax, float gamma, const float* mu_bar, float* u_bar,
+                                        int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !tau || !argmax || !mu_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "av_viscosity_adj: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_AV)) return fail(ctx, FCSD_EINVAL, "av_viscosity_adj: workspace too small");
+  AvWs A = carve_av(s, ws);
+  hipStream_t sm = ctx->stream;
+  // denominators of the forward operator (indicator only; num unused)
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(s->plane)), dim3(kBlock), 0, sm, A.muh, 0.f, (long long)s->plane);
+  if ((st = lambda_forward(ctx, s, A, A.muh, nullptr))) return st;
+  // t = mu_bar / den at every point, gathered into the lattice, window sum
+  hipLaunchKernelGGL(k_lat_divide_pts, dim3(s->nchunks), dim3(kBlock), 0, sm, s->d_chunks, s->d_patches, s->an,
+                     s->annulus, mu_bar, (const float*)A.den, A.tp);
+  hipLaunchKernelGGL(k_lat_gather, dim3(s->nlchunks), dim3(kBlock), 0, sm, s->d_lchunks, s->d_lats, s->d_patches,
+                     s->an, (const float*)A.tp, A.t0, (float*)nullptr, s->annulus, 1);
+  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, sm, s->d_lchunks, s->d_lats,
+                     (const float*)A.t0, (const float*)nullptr, A.t1, (float*)nullptr, 0);
+  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, sm, s->d_lchunks, s->d_lats,
+                     (const float*)A.t1, (const float*)nullptr, A.t0, (float*)nullptr, 1);
+  hipLaunchKernelGGL(k_route_S, dim3(s->nchunks), dim3(kBlock), 0, sm, s->d_chunks, s->d_patches, s->an, s->annulus,
+                     (const float*)A.t0, (const signed char*)tau, argmax, A.S);
+  hipLaunchKernelGGL(k_speed_vjp, dim3(s->nchunks), dim3(kBlock), 0, sm, s->d_chunks, s->d_patches, u,
+                     (long long)s->plane, gamma, (const float*)A.S, u_bar);
+  return launch_check(ctx, "av_viscosity_adj");
+}
+
+// ======================================================================== glue
+
+namespace {
+
+fcsd_status glue_impl(fcsd_ctx* ctx, const fcsd_set* s, float* u, const uint8_t* mask, const float* st4) {
+  if (s->annulus) {
+    const AnnulusDev& A = s->an;
+    if (A.nsec > 1) {
+      const long long n = (long long)A.n2 * 2 * kNf * A.nsec * A.nshell;
+      hipLaunchKernelGGL(k_glue_sectors, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, s->d_patches, A, u,
+                         (long long)s->plane);
+    }
+    if (A.nshell > 1) {
+      const long long n = (long long)A.n1 * 2 * kNf * A.nsec * A.nshell;
+      hipLaunchKernelGGL(k_glue_shells, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, s->d_patches, A, u,
+                         (long long)s->plane);
+    }
+  }
+  if (mask)
+    hipLaunchKernelGGL(k_dirichlet, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, mask, u,
+                       (long long)s->plane, st4[0], st4[1], st4[2], st4[3]);
+  return launch_check(ctx, "glue");
+}
+
+}  // namespace
+
+extern "C" fcsd_status fcsd_glue(fcsd_ctx* ctx, const fcsd_set* s, float* u, int64_t plane,
+                                 const uint8_t* dirichlet_mask, const float dirichlet_state[4]) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || (dirichlet_mask && !dirichlet_state)) return fail(ctx, FCSD_EINVAL, "fcsd_glue: null argument");
+  return glue_impl(ctx, s, u, dirichlet_mask, dirichlet_state);
+}
+
+// ======================================================================== fused stage / step
+
+extern "C" fcsd_status fcsd_stage(fcsd_ctx* ctx, const fcsd_set* s, int stage, const float* u0, const float* ui,
+                                  float* acc, float* uout, const float* metric, const float* mu, const float ref[4],
+                                  float gamma, const float* dt_dev, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (stage < 0 || stage > 4 || !u0 || !ui || !uout || !metric || !ref || !dt_dev || !ws || (stage >= 2 && !acc))
+    return fail(ctx, FCSD_EINVAL, "fcsd_stage: bad arguments");
+  if (uout == ui || (uout == u0 && stage != 4)) return fail(ctx, FCSD_EINVAL, "fcsd_stage: output aliases an input");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS)) return fail(ctx, FCSD_EINVAL, "fcsd_stage: workspace too small");
+  return rhs_passes(ctx, s, ui, metric, mu, ref, gamma, mu ? FLUX_FULL : FLUX_INVISCID, MODE_RK, nullptr, stage, u0,
+                    acc, uout, dt_dev, ws, -1);
+}
+
+extern "C" fcsd_status fcsd_stage_per_patch(fcsd_ctx* ctx, const fcsd_set* s, int stage, const float* u0,
+                                            const float* ui, float* acc, float* uout, const float* metric,
+                                            const float* mu, const float ref[4], float gamma, const float* dt_dev,
+                                            int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (stage < 0 || stage > 4 || !u0 || !ui || !uout || !metric || !ref || !dt_dev || !ws || (stage >= 2 && !acc))
+    return fail(ctx, FCSD_EINVAL, "fcsd_stage_per_patch: bad arguments");
+  if (uout == ui || (uout == u0 && stage != 4))
+    return fail(ctx, FCSD_EINVAL, "fcsd_stage_per_patch: output aliases an input");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_per_patch: workspace too small");
+  for (int p = 0; p < s->npatch; ++p) {
+    st = rhs_passes(ctx, s, ui, metric, mu, ref, gamma, mu ? FLUX_FULL : FLUX_INVISCID, MODE_RK, nullptr, stage, u0,
+                    acc, uout, dt_dev, ws, p);
+    if (st) return st;
+  }
+  return FCSD_OK;
+}
+
+namespace {
+
+fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a, void* ws) {
+  const long long pl = s->plane;
+  float* w = (float*)ws;
+  void* rhs_ws = w;
+  float* Ua = w + 16 * pl;
+  float* Ub = w + 20 * pl;
+  float* ACC = w + 24 * pl;
+  void* av_ws = w + 28 * pl;
+  AvWs A = carve_av(s, av_ws);
+  fcsd_status st;
+  if ((st = glue_impl(ctx, s, a->u, a->dirichlet_mask, a->dirichlet_state))) return st;
+  if (a->w) {
+    if ((st = sdnn_impl(ctx, s, a->u, a->gamma, a->w, a->tau, nullptr, A.phi))) return st;
+    if ((st = viscosity_impl(ctx, s, a->u, a->tau, a->gamma, a->mu, a->argmax, A))) return st;
+  }
+  if (!a->fixed_dt)
+    if ((st = cfl_dt_impl(ctx, s, a->u, a->mu, a->cfl, a->gamma, a->dt_dev, A.red))) return st;
+  const float* ins[5] = {a->u, Ua, Ub, Ua, Ub};
+  float* outs[5] = {Ua, Ub, Ua, Ub, a->u};
+  for (int k = 0; k < 5; ++k) {
+    if (k > 0)
+      if ((st = glue_impl(ctx, s, const_cast<float*>(ins[k]), a->dirichlet_mask, a->dirichlet_state))) return st;
+    st = rhs_passes(ctx, s, ins[k], a->metric, a->mu, a->ref, a->gamma, a->mu ? FLUX_FULL : FLUX_INVISCID, MODE_RK,
+                    nullptr, k, a->u, ACC, outs[k], a->dt_dev, rhs_ws, -1);
+    if (st) return st;
+  }
+  return FCSD_OK;
+}
+
+}  // namespace
+
+extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a, int64_t plane, void* ws,
+                                 size_t ws_bytes, int use_graph) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!a || !a->u || !a->metric || !a->dt_dev || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_step: null argument");
+  if (a->w && (!a->tau || !a->mu)) return fail(ctx, FCSD_EINVAL, "fcsd_step: network needs tau and mu buffers");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP)) return fail(ctx, FCSD_EINVAL, "fcsd_step: workspace too small");
+  if (!use_graph) return step_body(ctx, s, a, ws);
+  if (!ctx->stream) return fail(ctx, FCSD_EINVAL, "fcsd_step: graph capture needs a non-default stream");
+  std::vector<unsigned char> key(sizeof(*a) + sizeof(void*) + (a->w ? sizeof(fcsd_mlp) : 0));
+  memcpy(key.data(), a, sizeof(*a));
+  memcpy(key.data() + sizeof(*a), &ws, sizeof(void*));
+  if (a->w) memcpy(key.data() + sizeof(*a) + sizeof(void*), a->w, sizeof(fcsd_mlp));
+  fcsd_set* ms = const_cast<fcsd_set*>(s);
+  for (auto& g : ms->graphs)
+    if (g.key == key) {
+      HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
+      return FCSD_OK;
+    }
+  hipGraph_t graph;
+  HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  st = step_body(ctx, s, a, ws);
+  hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  if (st) return st;
+  if (e != hipSuccess) return fail(ctx, FCSD_EHIP, std::string("capture: ") + hipGetErrorString(e));
+  GraphEntry g;
+  g.key = key;
+  e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ctx, FCSD_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+  ms->graphs.push_back(g);
+  HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
+  return FCSD_OK;
+}
+
+// ======================================================================== reverse mode of the RHS
+
+extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
+                                    const float* mu, const float ref[4], float gamma, const float* rhs_bar,
+                                    float* u_bar, float* mu_bar, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !metric || !ref || !rhs_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: workspace too small");
+  const long long pl = s->plane;
+  float* w = (float*)ws;
+  float* d1e = w;
+  float* d2e = w + 4 * pl;
+  float* Hb = w + 8 * pl;
+  float* G1 = w + 16 * pl;
+  float* G2 = w + 20 * pl;
+  const int visc = mu != nullptr;
+  PassArgs a = base_args(s, 1);
+  set_ref(a, ref, gamma);
+  a.u = u;
+  a.metric = metric;
+  a.mu = mu;
+  a.mode = FLUX_FULL;
+  if (visc) {
+    PassArgs b = a;
+    b.out = d1e;
+    b.plans = s->dir[0].d_plans;
+    if ((st = launch_lines(s, 1, k_dev_diff<1>, b))) return st;
+    b.out = d2e;
+    b.plans = s->dir[1].d_plans;
+    if ((st = launch_lines(s, 2, k_dev_diff<2>, b))) return st;
+  }
+  {
+    const DirPlan& D = s->dir[0];
+    PassArgs b = a;
+    b.plans = D.d_plans;
+    b.tiles = D.d_tiles;
+    hipLaunchKernelGGL(k_adjHb<1>, dim3((unsigned)D.tiles.size()), dim3(kBlock), D.lds, ctx->stream, b, rhs_bar, Hb,
+                       (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
+    if ((st = launch_check(ctx, "adj C"))) return st;
+  }
+  {
+    const DirPlan& D = s->dir[1];
+    PassArgs b = a;
+    b.plans = D.d_plans;
+    b.tiles = D.d_tiles;
+    hipLaunchKernelGGL(k_adjHb<2>, dim3((unsigned)D.tiles.size()), dim3(kBlock), D.lds, ctx->stream, b, rhs_bar, Hb,
+                       (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
+    if ((st = launch_check(ctx, "adj B2"))) return st;
+  }
+  if (visc) {
+    // u_bar += D2^T G2 + D1^T G1 (deviation form: the constant reference has no adjoint)
+    if ((st = fc_diff_adj(ctx, s, 2, 4, G2, u_bar, plane))) return st;
+    if ((st = fc_diff_adj(ctx, s, 1, 4, G1, u_bar, plane))) return st;
+  }
+  return FCSD_OK;
+}

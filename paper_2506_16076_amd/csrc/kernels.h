@@ -1,0 +1,410 @@
+// Batched pass kernels of the FC-SDNN right-hand side and stage update.
+//
+// Right-hand side (paper eq. general_curvilinear with the viscous flux of
+// eq. f_visc, chain-rule reading):
+//     r = sum_{m,a} m[m,a] d/dq^m ( mu d/dx_a e - f_a(e) )
+// with d/dx_a e = sum_m m[m,a] d/dq^m e.  Writing H_a = mu d/dx_a e - f'_a
+// (f' = f(e) - f(e_ref), the deviation flux; the derivative of the constant
+// f(e_ref) is the FC derivative of a constant, ~1e-11) the inviscid and
+// viscous divergences share their derivatives, so one stage needs
+//   A  (q1 lines): d1 e                                  4 derivatives
+//   B1 (q2 lines): d2 e -> H_x, H_y (8 fields)          4 derivatives
+//   B2 (q2 lines): r2 = m2x d2 H_x + m2y d2 H_y          8 derivatives
+//   C  (q1 lines): r = m1x d1 H_x + m1y d1 H_y + r2, then the SSPRK update
+//                                                        8 derivatives
+// Every pass is one launch over a tile list covering all patches.
+#pragma once
+#include "engine.h"
+
+namespace fcsd {
+
+struct PassArgs {
+  const PlanDev* plans;
+  const TileDev* tiles;
+  const float2* tw;
+  const float* km;
+  const double* aq;
+  int d;
+  long long plane;
+  int nf;
+  int mode;
+  // generic line operator
+  const float* in;
+  float* out;
+  long long ext_plane;
+  const long long* ext_off;   // per plan: offset of the plan's first line in ext
+  // right-hand side
+  const float* u;
+  const float* metric;
+  const float* mu;
+  const float* d1e;
+  float* H;
+  float* r2;
+  float* rhs;
+  // stage update
+  const float* u0;
+  const float* ui;
+  float* acc;
+  float* uout;
+  const float* dt;
+  int stage;
+  float eref[4];   // reference conserved state
+  float pref[4];   // reference primitive state (rho, u, v, p)
+  float gamma;
+};
+
+enum { MODE_SET = 0, MODE_ADD = 1, MODE_RK = 2 };
+enum { FLUX_FULL = 0, FLUX_VISC = 1, FLUX_INVISCID = 2 };
+
+// SSPRK(5,4) Shu-Osher coefficients (five stages, fourth order)
+struct RkCoef {
+  float a0, ai, b, acc_i, acc_b;
+};
+__device__ __forceinline__ RkCoef rk_coef(int s) {
+  switch (s) {
+    case 0: return RkCoef{1.0f, 0.0f, 0.391752226571890f, 0.f, 0.f};
+    case 1: return RkCoef{0.444370493651235f, 0.555629506348765f, 0.368410593050371f, 0.f, 0.f};
+    case 2: return RkCoef{0.620101851488403f, 0.379898148511597f, 0.251891774271694f, 0.517231671970585f, 0.f};
+    case 3: return RkCoef{0.178079954393132f, 0.821920045606868f, 0.544974750228521f, 0.096059710526147f, 0.063692468666290f};
+    default: return RkCoef{0.0f, 0.386708617503269f, 0.226007483236906f, 0.f, 0.f};
+  }
+}
+
+// Deviation fluxes f(e) - f(e_ref), free of cancellation: every term is a
+// product with a deviation (de, du, dv, dp).
+__device__ __forceinline__ void dev_flux(const float e[4], const float er[4], const float pr[4],
+                                         float g, float dF[4], float dG[4]) {
+  const float dr = e[0] - er[0], dm = e[1] - er[1], dn = e[2] - er[2], dE = e[3] - er[3];
+  const float irho = 1.0f / e[0];
+  const float u = e[1] * irho, v = e[2] * irho;
+  const float du = (dm - pr[1] * dr) * irho;
+  const float dv = (dn - pr[2] * dr) * irho;
+  const float mr = er[1], nr = er[2];
+  const float dp = (g - 1.0f) * (dE - 0.5f * (dm * u + mr * du + dn * v + nr * dv));
+  const float H = e[3] + pr[3] + dp;  // E + p
+  dF[0] = dm;
+  dF[1] = dm * u + mr * du + dp;
+  dF[2] = dm * v + mr * dv;
+  dF[3] = du * H + pr[1] * (dE + dp);
+  dG[0] = dn;
+  dG[1] = dn * u + nr * du;
+  dG[2] = dn * v + nr * dv + dp;
+  dG[3] = dv * H + pr[2] * (dE + dp);
+}
+
+// position / line of a tile element and its plane index
+template <int DIR>
+__device__ __forceinline__ long long gindex(const PlanDev& P, const TileDev& T, int pos, int c) {
+  return DIR == 1 ? P.off + (long long)(T.line0 + c) * P.n1 + pos
+                  : P.off + (long long)pos * P.n1 + (T.line0 + c);
+}
+// enumerate N*nl elements in the order that coalesces the global access
+template <int DIR>
+__device__ __forceinline__ void elem(int it, int N, int nl, int& pos, int& c) {
+  if (DIR == 1) {
+    c = it / N;
+    pos = it - c * N;
+  } else {
+    pos = it / nl;
+    c = it - pos * nl;
+  }
+}
+
+extern __shared__ float2 lds_z[];
+
+// ---------------------------------------------------------------- generic line ops
+
+// fc_diff / fc_diff_adj on nf fields, packed two per complex line.
+template <int DIR, bool ADJ>
+__global__ void __launch_bounds__(kBlock) k_fcdiff(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  for (int f = 0; f < a.nf; f += 2) {
+    const bool two = f + 1 < a.nf;
+    const float* A = a.in + (long long)f * a.plane;
+    const float* B = a.in + (long long)(f + 1) * a.plane;
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<DIR>(it, N, nl, pos, c);
+      const long long g = gindex<DIR>(P, T, pos, c);
+      z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
+    }
+    __syncthreads();
+    line_derivative<ADJ>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    float* OA = a.out + (long long)f * a.plane;
+    float* OB = a.out + (long long)(f + 1) * a.plane;
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<DIR>(it, N, nl, pos, c);
+      const long long g = gindex<DIR>(P, T, pos, c);
+      const float2 v = z[pos * ld + c];
+      if (ADJ) {
+        OA[g] += v.x;
+        if (two) OB[g] += v.y;
+      } else {
+        OA[g] = v.x;
+        if (two) OB[g] = v.y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// fc_continue (FWD) and its transpose: ext lines of length L per plan.
+template <int DIR, bool ADJ>
+__global__ void __launch_bounds__(kBlock) k_fccont(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, L = P.L, nl = T.nl, ld = T.ld;
+  const long long e0 = a.ext_off[T.plan] + (long long)T.line0 * L;
+  for (int f = 0; f < a.nf; f += 2) {
+    const bool two = f + 1 < a.nf;
+    if (!ADJ) {
+      const float* A = a.in + (long long)f * a.plane;
+      const float* B = a.in + (long long)(f + 1) * a.plane;
+      for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+        int pos, c;
+        elem<DIR>(it, N, nl, pos, c);
+        const long long g = gindex<DIR>(P, T, pos, c);
+        z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
+      }
+      __syncthreads();
+      if (!P.periodic) fc_tail(z, ld, nl, P, a.aq + P.aq, a.d);
+      __syncthreads();
+      float* OA = a.out + (long long)f * a.ext_plane + e0;
+      float* OB = a.out + (long long)(f + 1) * a.ext_plane + e0;
+      for (int it = threadIdx.x; it < L * nl; it += blockDim.x) {
+        const int c = it / L, pos = it - c * L;
+        const float2 v = z[pos * ld + c];
+        OA[(long long)c * L + pos] = v.x;
+        if (two) OB[(long long)c * L + pos] = v.y;
+      }
+    } else {
+      const float* A = a.in + (long long)f * a.ext_plane + e0;
+      const float* B = a.in + (long long)(f + 1) * a.ext_plane + e0;
+      for (int it = threadIdx.x; it < L * nl; it += blockDim.x) {
+        const int c = it / L, pos = it - c * L;
+        z[pos * ld + c] = make_float2(A[(long long)c * L + pos], two ? B[(long long)c * L + pos] : 0.f);
+      }
+      __syncthreads();
+      if (!P.periodic) fold_tail(z, ld, nl, P, a.aq + P.aq, a.d);
+      __syncthreads();
+      float* OA = a.out + (long long)f * a.plane;
+      float* OB = a.out + (long long)(f + 1) * a.plane;
+      for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+        int pos, c;
+        elem<DIR>(it, N, nl, pos, c);
+        const long long g = gindex<DIR>(P, T, pos, c);
+        const float2 v = z[pos * ld + c];
+        OA[g] += v.x;
+        if (two) OB[g] += v.y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- RHS passes
+
+// Pass A (q1 lines): d1e = D1 (e - e_ref), four fields.
+__global__ void __launch_bounds__(kBlock) k_passA(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  for (int f = 0; f < 4; f += 2) {
+    const float* A = a.u + (long long)f * a.plane;
+    const float* B = a.u + (long long)(f + 1) * a.plane;
+    const float ra = a.eref[f], rb = a.eref[f + 1];
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<1>(it, N, nl, pos, c);
+      const long long g = gindex<1>(P, T, pos, c);
+      z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
+    }
+    __syncthreads();
+    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    float* OA = const_cast<float*>(a.d1e) + (long long)f * a.plane;
+    float* OB = const_cast<float*>(a.d1e) + (long long)(f + 1) * a.plane;
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<1>(it, N, nl, pos, c);
+      const long long g = gindex<1>(P, T, pos, c);
+      const float2 v = z[pos * ld + c];
+      OA[g] = v.x;
+      OB[g] = v.y;
+    }
+    __syncthreads();
+  }
+}
+
+// H fields from e, d1e, d2e (two components f, f+1 at a time) at one point.
+__device__ __forceinline__ void make_H(const PassArgs& a, long long g, int f, float2 d2, int flux,
+                                       float hx[2], float hy[2]) {
+  const long long pl = a.plane;
+  const float m1x = a.metric[g], m1y = a.metric[pl + g], m2x = a.metric[2 * pl + g], m2y = a.metric[3 * pl + g];
+  float vx[2] = {0.f, 0.f}, vy[2] = {0.f, 0.f};
+  if (flux != FLUX_INVISCID) {
+    const float mu = a.mu[g];
+    const float d1a = a.d1e[(long long)f * pl + g], d1b = a.d1e[(long long)(f + 1) * pl + g];
+    vx[0] = mu * (m1x * d1a + m2x * d2.x);
+    vy[0] = mu * (m1y * d1a + m2y * d2.x);
+    vx[1] = mu * (m1x * d1b + m2x * d2.y);
+    vy[1] = mu * (m1y * d1b + m2y * d2.y);
+  }
+  if (flux != FLUX_VISC) {
+    float e[4], dF[4], dG[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = a.u[(long long)k * pl + g];
+    dev_flux(e, a.eref, a.pref, a.gamma, dF, dG);
+    vx[0] -= dF[f];
+    vy[0] -= dG[f];
+    vx[1] -= dF[f + 1];
+    vy[1] -= dG[f + 1];
+  }
+  hx[0] = vx[0];
+  hy[0] = vy[0];
+  hx[1] = vx[1];
+  hy[1] = vy[1];
+}
+
+// Pass B1 (q2 lines): d2e, then H = mu grad_x e - f' (mode FLUX_FULL /
+// FLUX_VISC).  H layout: field 2c = H_x component c, 2c+1 = H_y component c.
+__global__ void __launch_bounds__(kBlock) k_passB1(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  for (int f = 0; f < 4; f += 2) {
+    const float* A = a.u + (long long)f * a.plane;
+    const float* B = a.u + (long long)(f + 1) * a.plane;
+    const float ra = a.eref[f], rb = a.eref[f + 1];
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<2>(it, N, nl, pos, c);
+      const long long g = gindex<2>(P, T, pos, c);
+      z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
+    }
+    __syncthreads();
+    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<2>(it, N, nl, pos, c);
+      const long long g = gindex<2>(P, T, pos, c);
+      float hx[2], hy[2];
+      make_H(a, g, f, z[pos * ld + c], a.mode, hx, hy);
+      a.H[(long long)(2 * f) * a.plane + g] = hx[0];
+      a.H[(long long)(2 * f + 1) * a.plane + g] = hy[0];
+      a.H[(long long)(2 * f + 2) * a.plane + g] = hx[1];
+      a.H[(long long)(2 * f + 3) * a.plane + g] = hy[1];
+    }
+    __syncthreads();
+  }
+}
+
+// Inviscid H = -f' (pointwise, no derivative needed).
+__global__ void __launch_bounds__(kBlock) k_passH(PassArgs a, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float e[4], dF[4], dG[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) e[k] = a.u[(long long)k * a.plane + g];
+  if (!(e[0] > 0.f)) {  // padding between patches: leave H at zero
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a.H[(long long)k * a.plane + g] = 0.f;
+    return;
+  }
+  dev_flux(e, a.eref, a.pref, a.gamma, dF, dG);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a.H[(long long)(2 * k) * a.plane + g] = -dF[k];
+    a.H[(long long)(2 * k + 1) * a.plane + g] = -dG[k];
+  }
+}
+
+// Pass B2 (q2 lines): r2_c = m2x d2 H_x,c + m2y d2 H_y,c.
+__global__ void __launch_bounds__(kBlock) k_passB2(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  for (int comp = 0; comp < 4; ++comp) {
+    const float* A = a.H + (long long)(2 * comp) * pl;
+    const float* B = a.H + (long long)(2 * comp + 1) * pl;
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<2>(it, N, nl, pos, c);
+      const long long g = gindex<2>(P, T, pos, c);
+      z[pos * ld + c] = make_float2(A[g], B[g]);
+    }
+    __syncthreads();
+    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<2>(it, N, nl, pos, c);
+      const long long g = gindex<2>(P, T, pos, c);
+      const float2 v = z[pos * ld + c];
+      a.r2[(long long)comp * pl + g] = a.metric[2 * pl + g] * v.x + a.metric[3 * pl + g] * v.y;
+    }
+    __syncthreads();
+  }
+}
+
+// Pass C (q1 lines): r = m1x d1 H_x + m1y d1 H_y + r2, then store (SET/ADD)
+// or the SSPRK register update (RK).
+__global__ void __launch_bounds__(kBlock) k_passC(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  float dt = 0.f;
+  RkCoef K = rk_coef(a.stage);
+  if (a.mode == MODE_RK) dt = a.dt[0];
+  for (int comp = 0; comp < 4; ++comp) {
+    const float* A = a.H + (long long)(2 * comp) * pl;
+    const float* B = a.H + (long long)(2 * comp + 1) * pl;
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<1>(it, N, nl, pos, c);
+      const long long g = gindex<1>(P, T, pos, c);
+      z[pos * ld + c] = make_float2(A[g], B[g]);
+    }
+    __syncthreads();
+    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    const long long fo = (long long)comp * pl;
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<1>(it, N, nl, pos, c);
+      const long long g = gindex<1>(P, T, pos, c);
+      const float2 v = z[pos * ld + c];
+      const float r = a.metric[g] * v.x + a.metric[pl + g] * v.y + a.r2[fo + g];
+      if (a.mode == MODE_SET) {
+        a.rhs[fo + g] = r;
+      } else if (a.mode == MODE_ADD) {
+        a.rhs[fo + g] += r;
+      } else {
+        const float ui = a.ui[fo + g];
+        const float dr = dt * r;
+        if (a.stage <= 1) {
+          a.uout[fo + g] = K.a0 * a.u0[fo + g] + K.ai * ui + K.b * dr;
+        } else if (a.stage == 2) {
+          a.uout[fo + g] = K.a0 * a.u0[fo + g] + K.ai * ui + K.b * dr;
+          a.acc[fo + g] = K.acc_i * ui;
+        } else if (a.stage == 3) {
+          a.uout[fo + g] = K.a0 * a.u0[fo + g] + K.ai * ui + K.b * dr;
+          a.acc[fo + g] += K.acc_i * ui + K.acc_b * dr;
+        } else {
+          a.uout[fo + g] = a.acc[fo + g] + K.ai * ui + K.b * dr;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace fcsd

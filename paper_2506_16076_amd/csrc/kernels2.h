@@ -1,0 +1,754 @@
+// Pointwise and stencil kernels: SSPRK register update, step size, proxy and
+// network classifier, preliminary viscosity, smoothing-blending operator,
+// multi-patch glue and the reverse-mode passes of the right-hand side.
+#pragma once
+#include "kernels.h"
+
+namespace fcsd {
+
+constexpr int kChunk = 256;  // points per chunk of the pointwise kernels
+
+struct PatchDev {
+  int n1, n2;
+  long long off;
+  float hhat, htilde;
+  int internal;  // bit s set: side s (q1-, q1+, q2-, q2+) internal
+  int pad;
+};
+
+struct ChunkDev {
+  int patch;  // patch (or lattice group) index
+  int start;  // first point (row-major within the patch)
+};
+
+// lattice of the smoothing-blending operator: independent patches are their
+// own lattice; the index-aligned annulus is one periodic (G, J) lattice
+struct LatDev {
+  int W, H, periodic, pad;
+  long long base;
+};
+
+struct AnnulusDev {
+  int nsec, nshell, st1, st2;  // sectors, shells, n1 - 19, n2 - 19
+  int n1, n2, ring, nJ;
+};
+
+constexpr int kNv = 9;      // viscosity fringe width
+constexpr int kNf = 5;      // communication fringe width
+constexpr int kOvl = 19;    // overlap between neighbouring patches
+
+__device__ __forceinline__ bool in_dtilde(const PatchDev& P, int i, int j) {
+  if ((P.internal & 1) && i < kNv) return false;
+  if ((P.internal & 2) && i >= P.n1 - kNv) return false;
+  if ((P.internal & 4) && j < kNv) return false;
+  if ((P.internal & 8) && j >= P.n2 - kNv) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------- SSPRK
+
+__global__ void __launch_bounds__(kBlock) k_rk(int stage, const float* dtp, const float* rhs,
+                                               const float* u0, const float* ui, float* acc,
+                                               float* uout, long long n4) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n4) return;
+  const RkCoef K = rk_coef(stage);
+  const float dr = dtp[0] * rhs[g];
+  const float x = ui[g];
+  if (stage <= 1) {
+    uout[g] = K.a0 * u0[g] + K.ai * x + K.b * dr;
+  } else if (stage == 2) {
+    uout[g] = K.a0 * u0[g] + K.ai * x + K.b * dr;
+    acc[g] = K.acc_i * x;
+  } else if (stage == 3) {
+    uout[g] = K.a0 * u0[g] + K.ai * x + K.b * dr;
+    acc[g] += K.acc_i * x + K.acc_b * dr;
+  } else {
+    uout[g] = acc[g] + K.ai * x + K.b * dr;
+  }
+}
+
+// reverse of k_rk; rhs_bar is overwritten (each stage's r is used once)
+__global__ void __launch_bounds__(kBlock) k_rk_adj(int stage, const float* dtp, const float* ob,
+                                                   float* u0b, float* uib, float* accb, float* rb,
+                                                   long long n4) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n4) return;
+  const RkCoef K = rk_coef(stage);
+  const float dt = dtp[0];
+  const float y = ob[g];
+  if (stage == 0) {
+    u0b[g] += y;
+    rb[g] = K.b * dt * y;
+  } else if (stage == 1) {
+    u0b[g] += K.a0 * y;
+    uib[g] += K.ai * y;
+    rb[g] = K.b * dt * y;
+  } else if (stage == 2) {
+    const float ab = accb[g];
+    u0b[g] += K.a0 * y;
+    uib[g] += K.ai * y + K.acc_i * ab;
+    rb[g] = K.b * dt * y;
+    accb[g] = 0.f;
+  } else if (stage == 3) {
+    const float ab = accb[g];
+    u0b[g] += K.a0 * y;
+    uib[g] += K.ai * y + K.acc_i * ab;
+    rb[g] = dt * (K.b * y + K.acc_b * ab);
+  } else {
+    accb[g] += y;
+    uib[g] += K.ai * y;
+    rb[g] = K.b * dt * y;
+  }
+}
+
+// ---------------------------------------------------------------- proxy, S
+
+__device__ __forceinline__ void prim(const float* u, long long pl, long long g, float gam, float& rho,
+                                     float& vx, float& vy, float& p) {
+  rho = u[g];
+  const float ir = 1.0f / rho;
+  vx = u[pl + g] * ir;
+  vy = u[2 * pl + g] * ir;
+  p = (gam - 1.0f) * (u[3 * pl + g] - 0.5f * rho * (vx * vx + vy * vy));
+}
+
+// Phi = |u| sqrt(rho/(gamma p)) and S = |u| + |v| + a on every patch point
+__global__ void __launch_bounds__(kBlock) k_proxy(const ChunkDev* chunks, const PatchDev* patches,
+                                                  const float* u, long long pl, float gam, float* phi,
+                                                  float* S) {
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const long long g = P.off + k;
+  float rho, vx, vy, p;
+  prim(u, pl, g, gam, rho, vx, vy, p);
+  const float a = sqrtf(gam * p / rho);
+  if (phi) phi[g] = sqrtf(vx * vx + vy * vy) / a;
+  if (S) S[g] = fabsf(vx) + fabsf(vy) + a;
+}
+
+// ---------------------------------------------------------------- network
+
+struct MlpPtr {
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+};
+constexpr int kMlpFloats = 16 * 64 + 64 + 64 * 64 + 64 + 64 * 4 + 4;
+
+__device__ __noinline__ int mlp_argmax(const float* __restrict__ w, const float x[16],
+                                          float* out4) {
+  const float* W1 = w;
+  const float* b1 = W1 + 16 * 64;
+  const float* W2 = b1 + 64;
+  const float* b2 = W2 + 64 * 64;
+  const float* W3 = b2 + 64;
+  const float* b3 = W3 + 64 * 4;
+  float h1[64];
+#pragma unroll
+  for (int j = 0; j < 64; j += 4) {
+    float4 s = *reinterpret_cast<const float4*>(b1 + j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float4 wv = *reinterpret_cast<const float4*>(W1 + i * 64 + j);
+      s.x = fmaf(x[i], wv.x, s.x);
+      s.y = fmaf(x[i], wv.y, s.y);
+      s.z = fmaf(x[i], wv.z, s.z);
+      s.w = fmaf(x[i], wv.w, s.w);
+    }
+    h1[j] = fmaxf(s.x, 0.f);
+    h1[j + 1] = fmaxf(s.y, 0.f);
+    h1[j + 2] = fmaxf(s.z, 0.f);
+    h1[j + 3] = fmaxf(s.w, 0.f);
+  }
+  float o0 = b3[0], o1 = b3[1], o2 = b3[2], o3 = b3[3];
+#pragma unroll 1
+  for (int k = 0; k < 64; k += 4) {
+    float s0 = b2[k], s1 = b2[k + 1], s2 = b2[k + 2], s3 = b2[k + 3];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+      const float4 wv = *reinterpret_cast<const float4*>(W2 + j * 64 + k);
+      s0 = fmaf(h1[j], wv.x, s0);
+      s1 = fmaf(h1[j], wv.y, s1);
+      s2 = fmaf(h1[j], wv.z, s2);
+      s3 = fmaf(h1[j], wv.w, s3);
+    }
+    const float hs[4] = {fmaxf(s0, 0.f), fmaxf(s1, 0.f), fmaxf(s2, 0.f), fmaxf(s3, 0.f)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 w3 = *reinterpret_cast<const float4*>(W3 + (k + q) * 4);
+      o0 = fmaf(hs[q], w3.x, o0);
+      o1 = fmaf(hs[q], w3.y, o1);
+      o2 = fmaf(hs[q], w3.z, o2);
+      o3 = fmaf(hs[q], w3.w, o3);
+    }
+  }
+  if (out4) {
+    out4[0] = o0;
+    out4[1] = o1;
+    out4[2] = o2;
+    out4[3] = o3;
+  }
+  int best = 0;
+  float bv = o0;
+  if (o1 > bv) { best = 1; bv = o1; }
+  if (o2 > bv) { best = 2; bv = o2; }
+  if (o3 > bv) { best = 3; bv = o3; }
+  return best;
+}
+
+// features of the 16-sample window at offsets -8..7 (clamped) along a line
+__device__ __forceinline__ void window_features(const float* __restrict__ phi, long long base,
+                                                long long step, int pos, int n, float x[16]) {
+  float lo = 3.4e38f, hi = -3.4e38f;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    int k = pos - 8 + t;
+    k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+    x[t] = phi[base + (long long)k * step];
+    lo = fminf(lo, x[t]);
+    hi = fmaxf(hi, x[t]);
+  }
+  const float rng = hi - lo;
+  if (rng <= 1e-6f * fmaxf(1.0f, fabsf(hi))) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = 0.f;
+  } else {
+    const float s = 2.0f / rng;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (x[t] - lo) * s - 1.0f;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* chunks, const PatchDev* patches,
+                                                 const float* phi, MlpPtr w, signed char* tau,
+                                                 float* logits, long long pl) {
+  __shared__ float wl[kMlpFloats];
+  {
+    const float* srcs[6] = {w.W1, w.b1, w.W2, w.b2, w.W3, w.b3};
+    const int lens[6] = {16 * 64, 64, 64 * 64, 64, 64 * 4, 4};
+    int o = 0;
+    for (int s = 0; s < 6; ++s) {
+      for (int k = threadIdx.x; k < lens[s]; k += blockDim.x) wl[o + k] = srcs[s][k];
+      o += lens[s];
+    }
+  }
+  __syncthreads();
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const int j = k / P.n1, i = k - j * P.n1;
+  const long long g = P.off + k;
+  if (!in_dtilde(P, i, j)) {
+    tau[g] = 0;
+    if (logits) {
+      for (int q = 0; q < 4; ++q) {
+        logits[4 * g + q] = 0.f;
+        logits[4 * (pl + g) + q] = 0.f;
+      }
+    }
+    return;
+  }
+  float x[16];
+  window_features(phi, P.off + (long long)j * P.n1, 1, i, P.n1, x);
+  const int a1 = mlp_argmax(wl, x, logits ? logits + 4 * g : nullptr);
+  window_features(phi, P.off + i, P.n1, j, P.n2, x);
+  const int a2 = mlp_argmax(wl, x, logits ? logits + 4 * (pl + g) : nullptr);
+  tau[g] = (signed char)(1 + (a1 < a2 ? a1 : a2));
+}
+
+// ---------------------------------------------------------------- 7x7 max
+
+// max over i-3..i+3 (clamped) with the first maximiser
+__global__ void __launch_bounds__(kBlock) k_rowmax(const ChunkDev* chunks, const PatchDev* patches,
+                                                   const float* S, float* rmax, int* rarg) {
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const int j = k / P.n1, i = k - j * P.n1;
+  const long long row = P.off + (long long)j * P.n1;
+  const int lo = i - 3 < 0 ? 0 : i - 3, hi = i + 3 > P.n1 - 1 ? P.n1 - 1 : i + 3;
+  float best = S[row + lo];
+  int bi = lo;
+  for (int t = lo + 1; t <= hi; ++t) {
+    const float v = S[row + t];
+    if (v > best) {
+      best = v;
+      bi = t;
+    }
+  }
+  rmax[P.off + k] = best;
+  rarg[P.off + k] = bi;
+}
+
+// column pass of the 7x7 max and mu^ = R(tau) max S h^ on D~ (0 elsewhere)
+__global__ void __launch_bounds__(kBlock) k_muhat(const ChunkDev* chunks, const PatchDev* patches,
+                                                  const float* rmax, const int* rarg,
+                                                  const signed char* tau, float* muh, int* argmax) {
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const int j = k / P.n1, i = k - j * P.n1;
+  const int lo = j - 3 < 0 ? 0 : j - 3, hi = j + 3 > P.n2 - 1 ? P.n2 - 1 : j + 3;
+  float best = rmax[P.off + (long long)lo * P.n1 + i];
+  int bj = lo;
+  for (int t = lo + 1; t <= hi; ++t) {
+    const float v = rmax[P.off + (long long)t * P.n1 + i];
+    if (v > best) {
+      best = v;
+      bj = t;
+    }
+  }
+  const long long g = P.off + k;
+  if (argmax) argmax[g] = bj * P.n1 + rarg[P.off + (long long)bj * P.n1 + i];
+  float m = 0.f;
+  if (in_dtilde(P, i, j)) {
+    const int t = tau[g];
+    const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
+    m = R * best * P.hhat;
+  }
+  muh[g] = m;
+}
+
+// ---------------------------------------------------------------- Lambda
+
+__device__ __forceinline__ float win(int k) {
+  // cos^2(pi k / 18), |k| <= 8 (values in double, rounded once)
+  constexpr float w[9] = {
+      (float)(1.0),
+      (float)(0.96984631039295421),
+      (float)(0.88302222155948906),
+      (float)(0.75),
+      (float)(0.58682408883346517),
+      (float)(0.41317591116653483),
+      (float)(0.25),
+      (float)(0.11697777844051099),
+      (float)(0.030153689607045786)};
+  return w[k < 0 ? -k : k];
+}
+
+// gather mu^ and the D~ indicator into the lattice.  Independent patches:
+// the lattice is the patch itself.  Annulus: cell (G, J) collects every
+// patch point with that global index (<= 2 sectors x 2 shells).
+__global__ void __launch_bounds__(kBlock) k_lat_gather(const ChunkDev* lchunks, const LatDev* lats,
+                                                       const PatchDev* patches, AnnulusDev an,
+                                                       const float* muh, float* num, float* den,
+                                                       int annulus, int transpose_src) {
+  const ChunkDev ck = lchunks[blockIdx.x];
+  const LatDev Lt = lats[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= Lt.W * Lt.H) return;
+  const long long cell = Lt.base + k;
+  if (!annulus) {
+    const PatchDev P = patches[ck.patch];
+    const int j = k / P.n1, i = k - j * P.n1;
+    const bool in = transpose_src ? true : in_dtilde(P, i, j);
+    num[cell] = in ? muh[P.off + k] : 0.f;
+    if (den) den[cell] = in ? 1.f : 0.f;
+    return;
+  }
+  const int J = k / Lt.W, G = k - J * Lt.W;
+  float sn = 0.f, sd = 0.f;
+  int k0 = J / an.st2;
+  if (k0 > an.nshell - 1) k0 = an.nshell - 1;
+  for (int kk = k0 - 1; kk <= k0; ++kk) {
+    if (kk < 0) continue;
+    const int jj = J - kk * an.st2;
+    if (jj < 0 || jj >= an.n2) continue;
+    const int s0 = G / an.st1;
+    for (int ss = s0 - 1; ss <= s0; ++ss) {
+      const int s = (ss + an.nsec) % an.nsec;
+      int ii = G - ss * an.st1;
+      if (ii < 0 || ii >= an.n1) continue;
+      const int p = kk * an.nsec + s;
+      const PatchDev P = patches[p];
+      if (!transpose_src && !in_dtilde(P, ii, jj)) continue;
+      sn += muh[P.off + (long long)jj * P.n1 + ii];
+      sd += 1.f;
+    }
+  }
+  num[cell] = sn;
+  if (den) den[cell] = sd;
+}
+
+// separable 17-tap window sum along G (dir 0, periodic or zero padded) or J
+__global__ void __launch_bounds__(kBlock) k_lat_conv(const ChunkDev* lchunks, const LatDev* lats,
+                                                     const float* in0, const float* in1, float* out0,
+                                                     float* out1, int dir) {
+  const ChunkDev ck = lchunks[blockIdx.x];
+  const LatDev Lt = lats[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= Lt.W * Lt.H) return;
+  const int J = k / Lt.W, G = k - J * Lt.W;
+  float s0 = 0.f, s1 = 0.f;
+  for (int l = -8; l <= 8; ++l) {
+    int gg = G, jj = J;
+    if (dir == 0) {
+      gg = G + l;
+      if (Lt.periodic) {
+        gg = (gg % Lt.W + Lt.W) % Lt.W;
+      } else if (gg < 0 || gg >= Lt.W) {
+        continue;
+      }
+    } else {
+      jj = J + l;
+      if (jj < 0 || jj >= Lt.H) continue;
+    }
+    const long long c = Lt.base + (long long)jj * Lt.W + gg;
+    const float w = win(l);
+    s0 = fmaf(w, in0[c], s0);
+    if (in1) s1 = fmaf(w, in1[c], s1);
+  }
+  out0[Lt.base + k] = s0;
+  if (out1) out1[Lt.base + k] = s1;
+}
+
+__device__ __forceinline__ long long lat_cell(const PatchDev& P, int p, int i, int j, int annulus,
+                                              const AnnulusDev& an) {
+  if (!annulus) return P.off + (long long)j * P.n1 + i;
+  const int s = p % an.nsec, kk = p / an.nsec;
+  const int G = (s * an.st1 + i) % an.ring;
+  const int J = kk * an.st2 + j;
+  return (long long)J * an.ring + G;
+}
+
+// mu = num / den at every patch point (mode 0), or the transpose
+// gather-scatter of Lambda^T: out = mu_bar / den at every point (mode 1)
+__global__ void __launch_bounds__(kBlock) k_lat_scatter(const ChunkDev* chunks, const PatchDev* patches,
+                                                        AnnulusDev an, int annulus, const float* num,
+                                                        const float* den, float* mu) {
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const int j = k / P.n1, i = k - j * P.n1;
+  const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
+  mu[P.off + k] = num[c] / den[c];
+}
+
+// Lambda^T first step: t = mu_bar / den (per patch point, into a plane)
+__global__ void __launch_bounds__(kBlock) k_lat_divide_pts(const ChunkDev* chunks, const PatchDev* patches,
+                                                           AnnulusDev an, int annulus, const float* mub,
+                                                           const float* den, float* t) {
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const int j = k / P.n1, i = k - j * P.n1;
+  const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
+  t[P.off + k] = mub[P.off + k] / den[c];
+}
+
+// Lambda^T last step + mu^ -> S routing: sbar(x) = sum over points y in
+// the 7x7 neighbourhood of x whose maximiser is x of R(tau_y) h^ mu^bar(y),
+// with mu^bar(y) = conv(acc)(cell of y) on D~.
+__global__ void __launch_bounds__(kBlock) k_route_S(const ChunkDev* chunks, const PatchDev* patches,
+                                                    AnnulusDev an, int annulus, const float* accconv,
+                                                    const signed char* tau, const int* argmax,
+                                                    float* sbar) {
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const int j = k / P.n1, i = k - j * P.n1;
+  float s = 0.f;
+  for (int dj = -3; dj <= 3; ++dj) {
+    const int yj = j + dj;
+    if (yj < 0 || yj >= P.n2) continue;
+    for (int di = -3; di <= 3; ++di) {
+      const int yi = i + di;
+      if (yi < 0 || yi >= P.n1) continue;
+      const long long gy = P.off + (long long)yj * P.n1 + yi;
+      if (argmax[gy] != k || !in_dtilde(P, yi, yj)) continue;
+      const int t = tau[gy];
+      const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
+      s += R * P.hhat * accconv[lat_cell(P, ck.patch, yi, yj, annulus, an)];
+    }
+  }
+  sbar[P.off + k] = s;
+}
+
+// u_bar += (dS/du)^T sbar, S = |u| + |v| + sqrt(gamma p / rho)
+__global__ void __launch_bounds__(kBlock) k_speed_vjp(const ChunkDev* chunks, const PatchDev* patches,
+                                                      const float* u, long long pl, float gam,
+                                                      const float* sbar, float* ub) {
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  if (k >= P.n1 * P.n2) return;
+  const long long g = P.off + k;
+  const float sb = sbar[g];
+  if (sb == 0.f) return;
+  float rho, vx, vy, p;
+  prim(u, pl, g, gam, rho, vx, vy, p);
+  const float ir = 1.0f / rho;
+  const float a = sqrtf(gam * p / rho);
+  const float su = vx > 0.f ? 1.f : (vx < 0.f ? -1.f : 0.f);
+  const float sv = vy > 0.f ? 1.f : (vy < 0.f ? -1.f : 0.f);
+  // da/dp = gamma/(2 a rho), da/drho|_p = -a/(2 rho)
+  const float ap = gam / (2.f * a * rho) * sb;
+  const float g1 = gam - 1.f;
+  ub[g] += sb * (-(su * vx + sv * vy) * ir - a * 0.5f * ir) + ap * g1 * 0.5f * (vx * vx + vy * vy);
+  ub[pl + g] += sb * su * ir - ap * g1 * vx;
+  ub[2 * pl + g] += sb * sv * ir - ap * g1 * vy;
+  ub[3 * pl + g] += ap * g1;
+}
+
+// ---------------------------------------------------------------- step size
+
+__global__ void __launch_bounds__(kBlock) k_fill(float* p, float v, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) p[g] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_dt_reduce(const ChunkDev* chunks, const PatchDev* patches,
+                                                      const float* u, const float* mu, long long pl,
+                                                      float gam, unsigned* smax, unsigned* mmax) {
+  __shared__ float rs[kBlock / 64], rm[kBlock / 64];
+  const ChunkDev ck = chunks[blockIdx.x];
+  const PatchDev P = patches[ck.patch];
+  const int k = ck.start + threadIdx.x;
+  float s = 0.f, m = 0.f;
+  if (k < P.n1 * P.n2) {
+    const long long g = P.off + k;
+    float rho, vx, vy, p;
+    prim(u, pl, g, gam, rho, vx, vy, p);
+    s = fabsf(vx) + fabsf(vy) + sqrtf(gam * p / rho);
+    if (mu) m = mu[g];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s = fmaxf(s, __shfl_xor(s, o));
+    m = fmaxf(m, __shfl_xor(m, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    rs[threadIdx.x >> 6] = s;
+    rm[threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      s = fmaxf(s, rs[w]);
+      m = fmaxf(m, rm[w]);
+    }
+    // non-negative floats order like their bit patterns
+    atomicMax(smax + ck.patch, __float_as_uint(fmaxf(s, 0.f)));
+    atomicMax(mmax + ck.patch, __float_as_uint(fmaxf(m, 0.f)));
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_dt_final(const PatchDev* patches, int np, const unsigned* smax,
+                                                     const unsigned* mmax, float cfl, float* dt) {
+  __shared__ float red[kBlock / 64];
+  float best = 3.4e38f;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    const double h = patches[p].htilde;
+    const double den = (double)__uint_as_float(smax[p]) / h + (double)__uint_as_float(mmax[p]) / (h * h);
+    best = fminf(best, (float)(cfl / den));
+  }
+  for (int o = 32; o > 0; o >>= 1) best = fminf(best, __shfl_xor(best, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) best = fminf(best, red[w]);
+    dt[0] = (float)((double)best / 3.14159265358979323846);
+  }
+}
+
+// ---------------------------------------------------------------- glue
+
+// sector pass: receivers i < 5 (from the left neighbour's column i + st1) and
+// i >= n1 - 5 (from the right neighbour's column i - st1), all rows, 4 fields
+__global__ void __launch_bounds__(kBlock) k_glue_sectors(const PatchDev* patches, AnnulusDev an, float* u,
+                                                         long long pl) {
+  const long long per = (long long)an.n2 * 2 * kNf;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = per * an.nsec * an.nshell;
+  if (t >= total) return;
+  const int p = (int)(t / per);
+  long long r = t - (long long)p * per;
+  const int j = (int)(r / (2 * kNf));
+  const int q = (int)(r - (long long)j * 2 * kNf);
+  const int s = p % an.nsec, kk = p / an.nsec;
+  int i, src, si;
+  if (q < kNf) {
+    i = q;
+    src = kk * an.nsec + (s - 1 + an.nsec) % an.nsec;
+    si = i + an.st1;
+  } else {
+    i = an.n1 - 2 * kNf + q;
+    src = kk * an.nsec + (s + 1) % an.nsec;
+    si = i - an.st1;
+  }
+  const long long d = patches[p].off + (long long)j * an.n1 + i;
+  const long long sg = patches[src].off + (long long)j * an.n1 + si;
+  for (int f = 0; f < 4; ++f) u[f * pl + d] = u[f * pl + sg];
+}
+
+__global__ void __launch_bounds__(kBlock) k_glue_shells(const PatchDev* patches, AnnulusDev an, float* u,
+                                                        long long pl) {
+  const long long per = (long long)an.n1 * 2 * kNf;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = per * an.nsec * an.nshell;
+  if (t >= total) return;
+  const int p = (int)(t / per);
+  long long r = t - (long long)p * per;
+  const int q = (int)(r / an.n1);
+  const int i = (int)(r - (long long)q * an.n1);
+  const int s = p % an.nsec, kk = p / an.nsec;
+  int j, src, sj;
+  if (q < kNf) {
+    if (kk == 0) return;
+    j = q;
+    src = (kk - 1) * an.nsec + s;
+    sj = j + an.st2;
+  } else {
+    if (kk == an.nshell - 1) return;
+    j = an.n2 - 2 * kNf + q;
+    src = (kk + 1) * an.nsec + s;
+    sj = j - an.st2;
+  }
+  const long long d = patches[p].off + (long long)j * an.n1 + i;
+  const long long sg = patches[src].off + (long long)sj * an.n1 + i;
+  for (int f = 0; f < 4; ++f) u[f * pl + d] = u[f * pl + sg];
+}
+
+__global__ void __launch_bounds__(kBlock) k_dirichlet(const unsigned char* mask, float* u, long long pl,
+                                                      float s0, float s1, float s2, float s3) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= pl || !mask[g]) return;
+  u[g] = s0;
+  u[pl + g] = s1;
+  u[2 * pl + g] = s2;
+  u[3 * pl + g] = s3;
+}
+
+// ---------------------------------------------------------------- RHS reverse mode
+
+// (dF/de)^T fb + (dG/de)^T gb at one point (primitive chain rule)
+__device__ __forceinline__ void flux_vjp(const float e[4], float gam, const float fb[4], const float gb[4],
+                                         float out[4]) {
+  const float rho = e[0], ir = 1.0f / rho;
+  const float u = e[1] * ir, v = e[2] * ir;
+  const float g1 = gam - 1.0f;
+  const float p = g1 * (e[3] - 0.5f * rho * (u * u + v * v));
+  const float Hh = e[3] + p;
+  const float Pb = fb[1] + gb[2] + fb[3] * u + gb[3] * v;
+  const float Ub = fb[1] * e[1] + fb[3] * Hh + gb[1] * e[2];
+  const float Vb = fb[2] * e[1] + gb[2] * e[2] + gb[3] * Hh;
+  const float Mb = fb[0] + fb[1] * u + fb[2] * v;
+  const float Nb = gb[0] + gb[1] * u + gb[2] * v;
+  const float Eb = fb[3] * u + gb[3] * v;
+  out[0] = -(Ub * u + Vb * v) * ir + Pb * g1 * 0.5f * (u * u + v * v);
+  out[1] = Mb + Ub * ir - Pb * g1 * u;
+  out[2] = Nb + Vb * ir - Pb * g1 * v;
+  out[3] = Eb + Pb * g1;
+}
+
+// Pass A for either direction: out = D_dir (e - e_ref)
+template <int DIR>
+__global__ void __launch_bounds__(kBlock) k_dev_diff(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  for (int f = 0; f < 4; f += 2) {
+    const float* A = a.u + (long long)f * a.plane;
+    const float* B = a.u + (long long)(f + 1) * a.plane;
+    const float ra = a.eref[f], rb = a.eref[f + 1];
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<DIR>(it, N, nl, pos, c);
+      const long long g = gindex<DIR>(P, T, pos, c);
+      z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
+    }
+    __syncthreads();
+    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<DIR>(it, N, nl, pos, c);
+      const long long g = gindex<DIR>(P, T, pos, c);
+      const float2 v = z[pos * ld + c];
+      a.out[(long long)f * a.plane + g] = v.x;
+      a.out[(long long)(f + 1) * a.plane + g] = v.y;
+    }
+    __syncthreads();
+  }
+}
+
+// Reverse of pass C / B2: Hb (+)= D_dir^T (m_dir,x rb, m_dir,y rb).
+// DIR = 2 additionally finishes H_bar and applies the pointwise reverse of
+// H = mu grad e - f': G1/G2 = mu-weighted metric products (for D^T later),
+// mu_bar += H_bar . grad e, u_bar += flux VJP of -H_bar.
+template <int DIR>
+__global__ void __launch_bounds__(kBlock) k_adjHb(PassArgs a, const float* rb, float* Hb,
+                                                  const float* d1e, const float* d2e, float* G1,
+                                                  float* G2, float* mub, float* ub, int visc) {
+  const TileDev T = a.tiles[blockIdx.x];
+  const PlanDev P = a.plans[T.plan];
+  float2* z = lds_z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  const int mx = DIR == 1 ? 0 : 2, my = DIR == 1 ? 1 : 3;
+  for (int comp = 0; comp < 4; ++comp) {
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<DIR>(it, N, nl, pos, c);
+      const long long g = gindex<DIR>(P, T, pos, c);
+      const float r = rb[(long long)comp * pl + g];
+      z[pos * ld + c] = make_float2(a.metric[mx * pl + g] * r, a.metric[my * pl + g] * r);
+    }
+    __syncthreads();
+    line_derivative<true>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<DIR>(it, N, nl, pos, c);
+      const long long g = gindex<DIR>(P, T, pos, c);
+      const float2 v = z[pos * ld + c];
+      const long long ix = (long long)(2 * comp) * pl + g, iy = (long long)(2 * comp + 1) * pl + g;
+      if (DIR == 1) {
+        Hb[ix] = v.x;
+        Hb[iy] = v.y;
+      } else {
+        const float hx = Hb[ix] + v.x, hy = Hb[iy] + v.y;
+        Hb[ix] = hx;
+        Hb[iy] = hy;
+        if (visc) {
+          const float m1x = a.metric[g], m1y = a.metric[pl + g], m2x = a.metric[2 * pl + g],
+                      m2y = a.metric[3 * pl + g];
+          const float mu = a.mu[g];
+          const long long fo = (long long)comp * pl + g;
+          G1[fo] = mu * (m1x * hx + m1y * hy);
+          G2[fo] = mu * (m2x * hx + m2y * hy);
+          if (mub) {
+            const float ex = m1x * d1e[fo] + m2x * d2e[fo];
+            const float ey = m1y * d1e[fo] + m2y * d2e[fo];
+            mub[g] += hx * ex + hy * ey;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (DIR == 2 && a.mode != FLUX_VISC) {
+    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
+      int pos, c;
+      elem<DIR>(it, N, nl, pos, c);
+      const long long g = gindex<DIR>(P, T, pos, c);
+      float e[4], fb[4], gb[4], o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        e[q] = a.u[(long long)q * pl + g];
+        fb[q] = -Hb[(long long)(2 * q) * pl + g];
+        gb[q] = -Hb[(long long)(2 * q + 1) * pl + g];
+      }
+      flux_vjp(e, a.gamma, fb, gb, o);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ub[(long long)q * pl + g] += o[q];
+    }
+  }
+}
+
+}  // namespace fcsd

@@ -1,0 +1,165 @@
+"""CPU checks of libfcsdnn.so: it loads, exports every symbol the header
+declares, and its host-side precomputation (continuation matrices, radix
+plans, digit-reversed multiplier tables, patch validation) agrees with the
+oracle and with a plain numpy DFT.  No device is needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fcgram
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fcsdnn.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2506_16076_amd import _lib
+    return _lib
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:fcsd_status|const char\*|void\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function(L):
+    lib = L.lib()
+    declared = header_functions()
+    assert len(declared) >= 30
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(L.EXPORTS)
+    assert lib.fcsd_version().startswith(b"fcsdnn")
+
+
+def test_context_without_device_reports_edevice(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    assert L.lib().fcsd_ctx_create(0, None, ctypes.byref(h)) == 3
+
+
+@pytest.mark.parametrize("C", list(range(27, 46)))
+def test_continuation_matrix_matches_oracle(L, C):
+    lib_m = L.fc_matrix(5, C)
+    ora = fcgram.continuation_matrix(5, C)
+    assert np.abs(lib_m - ora).max() <= 1e-12 * np.abs(ora).max()
+
+
+def test_fft_plans(L):
+    for Lx in range(8, 600):
+        if not synth.smooth13(Lx):
+            with pytest.raises(L.FcsdError):
+                L.fft_plan(Lx)
+            continue
+        r = L.fft_plan(Lx)
+        assert int(np.prod(r)) == Lx and set(r) <= {2, 3, 4, 5, 7, 8, 11, 13}
+
+
+def _twiddles(lib, n):
+    out = np.zeros(2 * n, np.float32)
+    lib.fcsd_host_twiddles(ctypes.c_int(n), out.ctypes.data_as(ctypes.c_void_p))
+    return out[0::2].astype(np.float64) + 1j * out[1::2]
+
+
+def _kmul(lib, N, n, rad, periodic=0):
+    out = np.zeros(n, np.float32)
+    r = (ctypes.c_int * 8)(*rad)
+    lib.fcsd_host_kmul(ctypes.c_int(N), ctypes.c_int(n), ctypes.c_int(len(rad)), r,
+                       out.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(periodic))
+    return out
+
+
+def emulate_engine(x, rad, tw, inverse):
+    """numpy replay of the device stage loop: in-place decimation in
+    frequency (forward) / in time (inverse) with the library's twiddles."""
+    z = np.array(x, np.complex128)
+    n = len(z)
+    order = range(len(rad)) if not inverse else range(len(rad) - 1, -1, -1)
+    Ms = []
+    M = n
+    for r in rad:
+        Ms.append(M)
+        M //= r
+    for s in order:
+        R, M = rad[s], Ms[s]
+        m, stride = M // R, n // M
+        W = np.exp((1j if inverse else -1j) * 2 * np.pi * np.outer(np.arange(R), np.arange(R)) / R)
+        for b in range(n // R):
+            blk, j = divmod(b, m)
+            idx = blk * M + j + m * np.arange(R)
+            v = z[idx]
+            tws = tw[(stride * j * np.arange(R)) % n]
+            if inverse:
+                v = W @ (v * np.conj(tws))
+            else:
+                v = (W @ v) * tws
+            z[idx] = v
+    return z
+
+
+@pytest.mark.parametrize("Lx,N", [(91, 64), (156, 128), (286, 256), (539, 512), (64, 64), (120, 93)])
+def test_digit_reversed_engine_and_multiplier_table(L, Lx, N):
+    lib = L.lib()
+    rad = L.fft_plan(Lx)
+    tw = _twiddles(lib, Lx)
+    assert np.abs(tw - np.exp(-2j * np.pi * np.arange(Lx) / Lx)).max() < 1e-7
+    rng = np.random.default_rng(Lx)
+    x = rng.standard_normal(Lx) + 1j * rng.standard_normal(Lx)
+    X = np.fft.fft(x)
+    Y = emulate_engine(x, rad, np.exp(-2j * np.pi * np.arange(Lx) / Lx), False)
+    km = _kmul(lib, N, Lx, rad).astype(np.float64)
+    # recover the wavenumber of every position from the multiplier table
+    scale = 2 * np.pi * (N - 1) / Lx ** 2
+    k = np.rint(km / scale).astype(int)
+    kk = np.where(k < 0, k + Lx, k)
+    if Lx % 2 == 0:
+        assert np.sum(k == 0) == 2          # k = 0 and the zeroed Nyquist
+        ok = ~((k == 0) & (np.abs(Y - X[0]) > 1e-9 * np.abs(X).max()))
+    else:
+        ok = np.ones(Lx, bool)
+        assert sorted(kk) == list(range(Lx))
+    assert np.abs(Y[ok] - X[kk[ok]]).max() <= 1e-10 * np.abs(X).max()
+    # the inverse pass returns L x in natural order
+    back = emulate_engine(Y, rad, np.exp(-2j * np.pi * np.arange(Lx) / Lx), True)
+    assert np.abs(back / Lx - x).max() <= 1e-12 * np.abs(x).max()
+    # derivative through the emulated engine equals the oracle's FC derivative
+    if Lx > N:
+        C = Lx - N
+        F = synth.random_lines(rng, 2, N)
+        ArQ = L.fc_matrix(5, C)
+        ext = fcgram.extend(F[0] + 1j * F[1], ArQ)
+        Z = emulate_engine(ext, rad, tw, False)
+        Z = 1j * km * Z
+        d = emulate_engine(Z, rad, tw, True)[:N]
+        want = fcgram.diff_lines(F, 5, C)
+        assert np.abs(d.real - want[0]).max() <= 2e-5 * np.abs(want[0]).max()
+        assert np.abs(d.imag - want[1]).max() <= 2e-5 * np.abs(want[1]).max()
+
+
+def test_patch_validation(L):
+    ps = synth.uneven_sectors(5, 48, 120, 3)
+    descs = L.patch_descs(ps.n1, ps.n2, ps.C1, ps.C2, ps.off, ps.hhat, ps.htilde, ps.internal)
+    assert L.validate_patches(descs, 5, ps.plane)[0] == 0
+    end = int(ps.off[-1] + ps.n1[-1] * ps.n2[-1])
+    assert L.validate_patches(descs, 5, end)[0] == 0
+    assert L.validate_patches(descs, 5, end - 1)[0] == 1                  # outside the plane
+    bad = L.patch_descs(ps.n1, ps.n2, np.full(5, 17 * 7 - 48), ps.C2, ps.off, ps.hhat, ps.htilde, ps.internal)
+    rc, msg = L.validate_patches(bad, 5, ps.plane)
+    assert rc in (1, 5)
+    over = L.patch_descs(ps.n1, ps.n2, ps.C1, ps.C2, np.zeros(5, np.int64), ps.hhat, ps.htilde, ps.internal)
+    assert L.validate_patches(over, 5, ps.plane)[0] == 1                  # overlapping patches
+    tiny = L.patch_descs([9], [40], [27], [27], [0], [0.1], [0.1], [[0, 0, 0, 0]])
+    assert L.validate_patches(tiny, 5, 10000)[0] == 1                     # n < 2d + 1
+    ann = synth.annulus(4, 2, 48, 40)
+    descs = L.patch_descs(ann.n1, ann.n2, ann.C1, ann.C2, ann.off, ann.hhat, ann.htilde, ann.internal)
+    assert L.validate_patches(descs, 5, ann.plane, 4, 2)[0] == 0
+    assert L.validate_patches(descs, 5, ann.plane, 3, 2)[0] == 1
