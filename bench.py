@@ -1,0 +1,221 @@
+"""Throughput of the FC-SDNN hot path on one MI355X.
+
+Workload: 200 independent annulus-sector patches with side lengths drawn
+uniformly from 48..512 (seed 2), Mach-3 flow with a seeded 1% density
+perturbation, FP32 state, network classifier and smooth artificial
+viscosity every step, SSPRK(5,4) (five stages per step).  A timed "step" is
+one full time step of the hot path: glue, network classes, preliminary
+viscosity and smoothing-blending operator, CFL step size and five fused
+stages, replayed as one captured hipGraph.
+
+Metric: grid-point RK stages per second = points x 5 x steps / time.  Also
+reported: the per-patch plain variant of the stages, the dominant kernel's
+achieved algorithmic bandwidth against the HBM peak (HIP events around
+repeated launches of that pass on the library's stream) and the FP64 oracle
+timed on a bounded sample of the same workload on the host CPU.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_bytes(stage):
+    """Algorithmic HBM bytes per grid point of each pass of one stage (FP32).
+    A: read e (16), write d1e (16).  B1: read e, d1e, metric, mu (52), write H
+    (32).  B2: read H (32), metric q2 row (8), write r2 (16).  C: read H (32),
+    r2 (16), metric q1 row (8), register reads/writes of the stage."""
+    rk_read = {0: 16, 1: 32, 2: 32, 3: 48, 4: 32}[stage]
+    rk_write = {0: 16, 1: 16, 2: 32, 3: 32, 4: 16}[stage]
+    return {"A": 32, "B1": 84, "B2": 56, "C": 32 + 16 + 8 + rk_read + rk_write}
+
+
+def cpu_baseline(cfg, budget_s=20.0):
+    """The oracle (FP64 numpy) on a bounded sample: the first patches of the
+    workload until ~budget_s of work, one full step (network, viscosity, dt,
+    five stages).  Single thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import synth
+    from oracle import solver
+
+    ps = cfg.ps
+    # sample: a subset of patches (timed per patch to stay in budget)
+    order = list(range(ps.npatch))
+    pts, secs, used = 0, 0.0, 0
+    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        for p in order:
+            # rebuild a one-patch layout with patch p's geometry
+            n1, n2 = int(ps.n1[p]), int(ps.n2[p])
+            sub = synth._polar_patches([(0.3 * p, ((2 * np.pi / 16) * 255 / 237) / (n1 - 1), 0.5, 1.5 / (n2 - 1))],
+                                       [n1], [n2], ps.d, 27)
+            e = synth.mach_state(sub, cfg.mach, cfg.pert)
+            c = synth.Config("sample", sub, synth._f32(e, sub), cfg.ref, mach=cfg.mach, pert=cfg.pert,
+                             mlp=cfg.mlp)
+            run = solver.Run(c)
+            t0 = time.perf_counter()
+            run.step()
+            secs += time.perf_counter() - t0
+            pts += n1 * n2
+            used += 1
+            if secs > budget_s:
+                break
+    finally:
+        if ctxm is not None:
+            ctxm.__exit__(None, None, None)
+    return {"value": pts * 5 / secs, "unit": "grid-pt RK-stages/s", "cores": 1, "kind": "oracle",
+            "sample": f"{used} of {ps.npatch} patches ({pts} points), one full step each, FP64 numpy, "
+                      f"{secs:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--npatch", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding by whole patches is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2506_16076_amd import api
+
+    cfg = synth.config(2, npatch=args.npatch)
+    ps = cfg.ps
+    ctx = api.Context(0)
+    s = api.PatchSet.from_layout(ctx, ps)
+    dev = "cuda:0"
+
+    def t(a, dtype=None):
+        x = torch.from_numpy(np.ascontiguousarray(a).reshape(-1))
+        return (x.to(dtype) if dtype else x).to(dev).contiguous()
+
+    u = t(cfg.u0)
+    metric = t(ps.metric)
+    W = {k: t(v) for k, v in cfg.mlp.items()}
+    st = api.Stepper(s, u, metric, cfg.ref, W=W)
+    npts = ps.npoints
+
+    # ---------------- full step, graph replay
+    for _ in range(args.warmup):
+        st.step(use_graph=True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(ctx.stream):
+        ev0.record(ctx.stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st.step(use_graph=True)
+    with torch.cuda.stream(ctx.stream):
+        ev1.record(ctx.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / args.steps
+    value = npts * 5 * args.steps / (ms / 1e3)
+    finite = bool(torch.isfinite(u).all().item())
+
+    # ---------------- stages only: batched vs per-patch (same state, frozen mu, dt)
+    mu = st.mu
+    dtd = st.dt
+    acc = torch.zeros_like(u)
+    ua = torch.zeros_like(u)
+    ub = torch.zeros_like(u)
+
+    uc = torch.zeros_like(u)
+
+    def stages(per_patch):
+        ins, outs = [u, ua, ub, ua, ub], [ua, ub, ua, ub, uc]
+        for k in range(5):
+            api.fcsd_stage(s, k, u, ins[k], acc, outs[k], metric, mu, cfg.ref, 1.4, dtd, per_patch=per_patch)
+
+    def time_stages(per_patch, reps):
+        stages(per_patch)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            stages(per_patch)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_batched = time_stages(False, 3)
+    ms_pp = time_stages(True, 2)
+
+    # ---------------- per-pass timing (dominant kernel)
+    passes = {}
+    for pid, name in enumerate(["A", "B1", "B2", "C"]):
+        def run_pass():
+            api.fcsd_stage_pass(s, pid, 1, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
+        # prerequisites so every pass reads defined data
+        for q in range(pid + 1):
+            api.fcsd_stage_pass(s, q, 1, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            run_pass()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        passes[name] = e0.elapsed_time(e1) / reps
+    pb = pass_bytes(1)
+    dom = max(passes, key=passes.get)
+    achieved = pb[dom] * npts / (passes[dom] / 1e3) / 1e9
+    stage_bytes = sum(pb.values())
+
+    out = {
+        "metric": "grid-pt RK-stages/s fwd & adjoint, batched vs per-patch, % HBM peak",
+        "value": value,
+        "unit": "grid-pt RK-stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"uneven-{ps.npatch}-patches-48to512 (seed 2), Mach 3 +-1% density, "
+                               "network classifier + smooth AV every step, SSPRK(5,4), batched hipGraph step",
+                   "points": npts, "patches": ps.npatch},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"pass {dom}",
+                     "bytes_per_point": pb[dom], "ms": passes[dom]},
+        "stage_ms": {"batched": ms_batched / 5, "per_patch": ms_pp / 5,
+                     "batched_over_per_patch": ms_pp / ms_batched},
+        "pass_ms": passes,
+        "stage_bytes_per_point": stage_bytes,
+        "stage_effective_GBs": stage_bytes * npts / (ms_batched / 5 / 1e3) / 1e9,
+        "wall_s": wall,
+        "finite": finite,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

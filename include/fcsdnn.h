@@ -228,6 +228,16 @@ fcsd_status fcsd_stage(fcsd_ctx* ctx, const fcsd_set* set, int stage, const floa
                        const float* mu, const float ref[4], float gamma, const float* dt_dev,
                        int64_t plane, void* ws, size_t ws_bytes);
 
+/* One of the four passes of fcsd_stage (0: q1 derivatives of the state,
+ * 1: q2 derivatives and the combined fluxes H, 2: q2 derivatives of H,
+ * 3: q1 derivatives of H and the register update), for timing and
+ * profiling.  Running passes 0..3 in order equals one fcsd_stage call; with
+ * mu == NULL passes 0 and 1 together are the pointwise inviscid H. */
+fcsd_status fcsd_stage_pass(fcsd_ctx* ctx, const fcsd_set* set, int pass, int stage, const float* u0,
+                            const float* ui, float* acc, float* uout, const float* metric,
+                            const float* mu, const float ref[4], float gamma, const float* dt_dev,
+                            int64_t plane, void* ws, size_t ws_bytes);
+
 /* Per-patch plain variant of fcsd_stage: the same kernels launched once per
  * patch (npatch launches per pass). */
 fcsd_status fcsd_stage_per_patch(fcsd_ctx* ctx, const fcsd_set* set, int stage, const float* u0,

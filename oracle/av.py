@@ -41,6 +41,47 @@ STENCIL = 3          # 7x7 stencil half-width
 FEAT = 16
 
 
+def proxy_speed_f32(e, gamma):
+    """Phi and S evaluated in IEEE FP32 from an FP32 state, one rounding per
+    operation in this order: rho, ir = 1/rho, vx = m ir, vy = n ir,
+    q = vx vx + vy vy, p = (gamma-1) (E - (rho/2) q), a = sqrt((gamma p)/rho),
+    Phi = sqrt(q)/a, S = (|vx| + |vy|) + a.  Reading for decisions: the
+    classifier argmax and the 7x7 argmax are integer results decided by
+    floating point, so the oracle takes them in the kernel's precision
+    (FP32); every value downstream of a decision is FP64."""
+    f = np.float32
+    e = np.asarray(e).astype(f)
+    with np.errstate(all="ignore"):
+        rho = e[0]
+        ir = f(1) / rho
+        vx = e[1] * ir
+        vy = e[2] * ir
+        q = vx * vx + vy * vy
+        g = f(gamma)
+        p = (g - f(1)) * (e[3] - (f(0.5) * rho) * q)
+        a = np.sqrt((g * p) / rho)
+        phi = np.sqrt(q) / a
+        S = (np.abs(vx) + np.abs(vy)) + a
+    return phi, S
+
+
+def features_lines_f32(phi_lines):
+    """features_lines in IEEE FP32: x = (w - lo) (2/(hi - lo)) - 1."""
+    f = np.float32
+    phi_lines = np.asarray(phi_lines, f)
+    nl, n = phi_lines.shape
+    idx = np.clip(np.arange(n)[:, None] + np.arange(-8, 8)[None, :], 0, n - 1)
+    w = phi_lines[:, idx]
+    lo = w.min(axis=-1, keepdims=True)
+    hi = w.max(axis=-1, keepdims=True)
+    rng = hi - lo
+    flat = rng <= f(1e-6) * np.maximum(f(1), np.abs(hi))
+    with np.errstate(all="ignore"):
+        s = f(2) / rng
+        x = (w - lo) * s - f(1)
+    return np.where(flat, f(0), x).astype(f)
+
+
 def window_weights():
     k = np.arange(-WIN_HALF, WIN_HALF + 1)
     return np.cos(np.pi * k / 18.0) ** 2
@@ -87,15 +128,18 @@ def mlp_logits(x, W):
     return h @ W["W3"].astype(np.float64) + W["b3"].astype(np.float64)
 
 
-def classify(e, ps, W, gamma, return_logits=False):
-    """tau plane (int8, 0 outside D~) and optionally the per-direction logits."""
-    phi = proxy(e, gamma)
+def classify(e, ps, W, gamma, return_logits=False, fp32=True):
+    """tau plane (int8, 0 outside D~) and optionally the per-direction logits.
+    fp32: proxy and features in FP32 (decision precision of the kernel, see
+    proxy_speed_f32), network in FP64; fp32=False: everything in FP64."""
+    phi = proxy_speed_f32(e, gamma)[0] if fp32 else proxy(e, gamma)
+    feats = features_lines_f32 if fp32 else features_lines
     tau = np.zeros(ps.plane, np.int8)
     logits = {}
     for p in range(ps.npatch):
         ph = ps.view(phi, p)                       # [n2, n1]
-        l1 = mlp_logits(features_lines(ph), W)                       # lines along q1
-        l2 = np.swapaxes(mlp_logits(features_lines(ph.T), W), 0, 1)  # lines along q2 -> [n2, n1, 4]
+        l1 = mlp_logits(feats(ph).astype(np.float64), W)                       # lines along q1
+        l2 = np.swapaxes(mlp_logits(feats(ph.T).astype(np.float64), W), 0, 1)  # lines along q2 -> [n2, n1, 4]
         t = np.minimum(np.argmax(l1, -1), np.argmax(l2, -1)) + 1
         t = np.where(dtilde_mask(ps, p), t, 0)
         ps.view(tau, p)[...] = t
@@ -121,10 +165,12 @@ def stencil_max(S2d):
     return best, arg
 
 
-def preliminary(e, tau, ps, gamma):
-    """mu^ plane (0 outside D~) and the argmax plane (patch-local flat index)."""
+def preliminary(e, tau, ps, gamma, fp32=True):
+    """mu^ plane (0 outside D~) and the argmax plane (patch-local flat index).
+    fp32: the 7x7 maximum and its position are taken on S evaluated in FP32
+    (decision precision of the kernel); mu^ itself is formed in FP64."""
     from oracle.rk import wave_speed
-    S = wave_speed(e, gamma)
+    S = proxy_speed_f32(e, gamma)[1].astype(np.float64) if fp32 else wave_speed(e, gamma)
     muh = np.zeros(ps.plane)
     arg = np.zeros(ps.plane, np.int64)
     for p in range(ps.npatch):
@@ -204,12 +250,12 @@ def _sep_conv(a, w, periodic_cols=False):
     return res
 
 
-def viscosity(e, ps, W, gamma, tau=None):
+def viscosity(e, ps, W, gamma, tau=None, fp32=True):
     """Full per-step viscosity: classifier, preliminary, Lambda.  Returns
     (mu, tau, argmax)."""
     if tau is None:
-        tau = classify(e, ps, W, gamma)
-    muh, arg = preliminary(e, tau, ps, gamma)
+        tau = classify(e, ps, W, gamma, fp32=fp32)
+    muh, arg = preliminary(e, tau, ps, gamma, fp32=fp32)
     return smooth_blend(muh, ps), tau, arg
 
 

@@ -83,6 +83,7 @@ def lib():
             "fcsd_glue": [vp, vp, vp, i64, vp, P(f32)],
             "fcsd_stage": [vp, vp, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
             "fcsd_stage_per_patch": [vp, vp, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
+            "fcsd_stage_pass": [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
             "fcsd_step": [vp, vp, P(StepArgs), i64, vp, sz, i32],
             "fcsd_fc_matrix": [i32, i32, P(ctypes.c_double)],
             "fcsd_fft_plan": [i32, P(i32), P(i32)],
@@ -107,7 +108,7 @@ EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_l
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
            "rk_stage_adj", "fcsd_cfl_dt", "sdnn_infer", "av_viscosity", "av_viscosity_adj",
-           "fcsd_glue", "fcsd_stage", "fcsd_stage_per_patch", "fcsd_step", "fcsd_fc_matrix",
+           "fcsd_glue", "fcsd_stage", "fcsd_stage_per_patch", "fcsd_stage_pass", "fcsd_step", "fcsd_fc_matrix",
            "fcsd_validate_patches", "fcsd_fft_plan", "fcsd_version"]
 
 

@@ -248,6 +248,12 @@ def fcsd_stage(s, stage, u0, ui, acc, uout, metric, mu, ref, gamma, dt_dev, per_
           float(gamma), _p(dt_dev), s.plane, _p(ws), ws.numel() * 4)
 
 
+def fcsd_stage_pass(s, pass_id, stage, u0, ui, acc, uout, metric, mu, ref, gamma, dt_dev):
+    ws = s.workspace(WS_RHS)
+    _call(s, "fcsd_stage_pass", int(pass_id), int(stage), _p(u0), _p(ui), _p(acc), _p(uout), _p(metric), _p(mu),
+          _f4(ref), float(gamma), _p(dt_dev), s.plane, _p(ws), ws.numel() * 4)
+
+
 class Stepper:
     """Holds the buffers of fcsd_step (state advanced in place)."""
 

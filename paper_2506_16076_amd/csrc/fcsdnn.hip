@@ -570,7 +570,8 @@ RhsWs carve_rhs(const fcsd_set* s, void* ws) {
 // flux: FLUX_FULL, FLUX_VISC, FLUX_INVISCID ; out: MODE_SET / MODE_ADD / MODE_RK
 fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric, const float* mu,
                        const float ref[4], float gamma, int flux, int outmode, float* rhs, int stage,
-                       const float* u0, float* acc, float* uout, const float* dtp, void* ws, int patch) {
+                       const float* u0, float* acc, float* uout, const float* dtp, void* ws, int patch,
+                       unsigned passes = 15u) {
   RhsWs W = carve_rhs(s, ws);
   PassArgs a = base_args(s, 1);
   set_ref(a, ref, gamma);
@@ -581,7 +582,7 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
   a.H = W.H;
   a.r2 = W.r2;
   fcsd_status st;
-  if (flux == FLUX_INVISCID) {
+  if (flux == FLUX_INVISCID && (passes & 3u)) {
     if (patch < 0) {
       hipLaunchKernelGGL(k_passH, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, a, (long long)s->plane);
     } else {
@@ -593,17 +594,21 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
       hipLaunchKernelGGL(k_passH, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, b, n);
     }
     if ((st = launch_check(ctx, "pass H"))) return st;
-  } else {
+  } else if (flux != FLUX_INVISCID) {
     a.plans = s->dir[0].d_plans;
-    if ((st = launch_lines(s, 1, k_passA, a, patch))) return st;
+    if (passes & 1u)
+      if ((st = launch_lines(s, 1, k_passA, a, patch))) return st;
     PassArgs b = a;
     b.plans = s->dir[1].d_plans;
     b.mode = flux;
-    if ((st = launch_lines(s, 2, k_passB1, b, patch))) return st;
+    if (passes & 2u)
+      if ((st = launch_lines(s, 2, k_passB1, b, patch))) return st;
   }
   PassArgs c = a;
   c.plans = s->dir[1].d_plans;
-  if ((st = launch_lines(s, 2, k_passB2, c, patch))) return st;
+  if (passes & 4u)
+    if ((st = launch_lines(s, 2, k_passB2, c, patch))) return st;
+  if (!(passes & 8u)) return FCSD_OK;
   PassArgs e = a;
   e.plans = s->dir[0].d_plans;
   e.mode = outmode;
@@ -885,6 +890,21 @@ extern "C" fcsd_status fcsd_stage_per_patch(fcsd_ctx* ctx, const fcsd_set* s, in
     if (st) return st;
   }
   return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_stage_pass(fcsd_ctx* ctx, const fcsd_set* s, int pass, int stage, const float* u0,
+                                       const float* ui, float* acc, float* uout, const float* metric, const float* mu,
+                                       const float ref[4], float gamma, const float* dt_dev, int64_t plane, void* ws,
+                                       size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (pass < 0 || pass > 3 || stage < 0 || stage > 4 || !u0 || !ui || !uout || !metric || !ref || !dt_dev || !ws ||
+      (stage >= 2 && !acc))
+    return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: bad arguments");
+  if (uout == ui || (uout == u0 && stage != 4)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: output aliases an input");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: workspace too small");
+  return rhs_passes(ctx, s, ui, metric, mu, ref, gamma, mu ? FLUX_FULL : FLUX_INVISCID, MODE_RK, nullptr, stage, u0,
+                    acc, uout, dt_dev, ws, -1, 1u << pass);
 }
 
 namespace {

@@ -104,8 +104,12 @@ __global__ void __launch_bounds__(kBlock) k_rk_adj(int stage, const float* dtp, 
 
 // ---------------------------------------------------------------- proxy, S
 
+// Primitive variables with one IEEE rounding per operation in a fixed order
+// (no contraction): the network classes and the 7x7 maximiser are integer
+// decisions taken on these FP32 values.
 __device__ __forceinline__ void prim(const float* u, long long pl, long long g, float gam, float& rho,
                                      float& vx, float& vy, float& p) {
+#pragma clang fp contract(off)
   rho = u[g];
   const float ir = 1.0f / rho;
   vx = u[pl + g] * ir;
@@ -122,11 +126,14 @@ __global__ void __launch_bounds__(kBlock) k_proxy(const ChunkDev* chunks, const 
   const int k = ck.start + threadIdx.x;
   if (k >= P.n1 * P.n2) return;
   const long long g = P.off + k;
-  float rho, vx, vy, p;
-  prim(u, pl, g, gam, rho, vx, vy, p);
-  const float a = sqrtf(gam * p / rho);
-  if (phi) phi[g] = sqrtf(vx * vx + vy * vy) / a;
-  if (S) S[g] = fabsf(vx) + fabsf(vy) + a;
+  {
+#pragma clang fp contract(off)
+    float rho, vx, vy, p;
+    prim(u, pl, g, gam, rho, vx, vy, p);
+    const float a = sqrtf((gam * p) / rho);
+    if (phi) phi[g] = sqrtf(vx * vx + vy * vy) / a;
+    if (S) S[g] = (fabsf(vx) + fabsf(vy)) + a;
+  }
 }
 
 // ---------------------------------------------------------------- network
@@ -200,6 +207,7 @@ __device__ __noinline__ int mlp_argmax(const float* __restrict__ w, const float 
 // features of the 16-sample window at offsets -8..7 (clamped) along a line
 __device__ __forceinline__ void window_features(const float* __restrict__ phi, long long base,
                                                 long long step, int pos, int n, float x[16]) {
+#pragma clang fp contract(off)
   float lo = 3.4e38f, hi = -3.4e38f;
 #pragma unroll
   for (int t = 0; t < 16; ++t) {

@@ -251,6 +251,19 @@ def test_mlp_matches_naive_loops():
         assert np.allclose(out[r], o, rtol=1e-12, atol=1e-12)
 
 
+def test_fp32_decision_path_matches_fp64_values():
+    cfg = synth.config(1, n=40)
+    e = cfg.u0
+    phi32, S32 = av.proxy_speed_f32(e, G)
+    ps = cfg.ps
+    for p in range(ps.npatch):
+        assert np.allclose(ps.view(phi32, p), ps.view(av.proxy(e, G), p), rtol=1e-6)
+        assert np.allclose(ps.view(S32, p), ps.view(rk.wave_speed(e, G), p), rtol=1e-6)
+    t64 = av.classify(e, ps, cfg.mlp, G, fp32=False)
+    t32 = av.classify(e, ps, cfg.mlp, G, fp32=True)
+    assert np.mean(t64 == t32) > 0.99
+
+
 def test_features():
     lines = np.array([np.arange(40, dtype=float), np.full(40, 3.0)])
     f = av.features_lines(lines)
@@ -267,7 +280,7 @@ def test_preliminary_viscosity_values():
     for p in range(ps.npatch):
         m = av.dtilde_mask(ps, p)
         ps.view(tau, p)[m] = 1 + (np.arange(m.sum()) % 4)
-    muh, arg = av.preliminary(cfg.u0, tau, ps, G)
+    muh, arg = av.preliminary(cfg.u0, tau, ps, G, fp32=False)
     S = rk.wave_speed(cfg.u0, G)
     p = 3
     m = av.dtilde_mask(ps, p)
@@ -282,7 +295,7 @@ def test_viscosity_vjp_matches_finite_differences():
     cfg = synth.config(1, n=36)
     ps = cfg.ps
     e = np.array(cfg.u0, np.float64)
-    mu, tau, arg = av.viscosity(e, ps, cfg.mlp, G)
+    mu, tau, arg = av.viscosity(e, ps, cfg.mlp, G, fp32=False)
     rng = np.random.default_rng(11)
     mb = rng.standard_normal(ps.plane)
     eb = av.viscosity_vjp(e, tau, arg, ps, G, mb)
