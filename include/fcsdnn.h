@@ -95,6 +95,12 @@ fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_patch_desc* pa
                             int d, int64_t plane, int ring_sectors, int ring_shells,
                             fcsd_set** out);
 fcsd_status fcsd_set_destroy(fcsd_set* set);
+/* Re-split the line tiles of a set for a workgroup LDS budget in bytes
+ * (8 KB .. 160 KB; default 64 KB or the FCSD_LDS_BUDGET environment
+ * variable at creation).  Smaller budgets mean fewer lines per tile and
+ * more workgroups per compute unit.  Synchronises the context's stream and
+ * drops captured step graphs.  Used by the autotuner. */
+fcsd_status fcsd_set_tune(fcsd_set* set, int lds_budget_bytes);
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
 enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3 };

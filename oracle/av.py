@@ -165,11 +165,22 @@ def stencil_max(S2d):
     return best, arg
 
 
-def preliminary(e, tau, ps, gamma, fp32=True):
+def preliminary(e, tau, ps, gamma, fp32=True, arg=None):
     """mu^ plane (0 outside D~) and the argmax plane (patch-local flat index).
     fp32: the 7x7 maximum and its position are taken on S evaluated in FP32
-    (decision precision of the kernel); mu^ itself is formed in FP64."""
+    (decision precision of the kernel); mu^ itself is formed in FP64.
+    arg: replay recorded maximiser positions (frozen decision) and take S
+    there, in FP64."""
     from oracle.rk import wave_speed
+    if arg is not None:
+        S = wave_speed(e, gamma)
+        muh = np.zeros(ps.plane)
+        for p in range(ps.npatch):
+            mx = ps.view(S, p).ravel()[ps.view(arg, p)]
+            t = ps.view(tau, p).astype(np.int64)
+            r = np.where(t > 0, R_TABLE[np.clip(t - 1, 0, 3)], 0.0)
+            ps.view(muh, p)[...] = np.where(dtilde_mask(ps, p), r * mx * ps.hhat[p], 0.0)
+        return muh, arg
     S = proxy_speed_f32(e, gamma)[1].astype(np.float64) if fp32 else wave_speed(e, gamma)
     muh = np.zeros(ps.plane)
     arg = np.zeros(ps.plane, np.int64)
@@ -250,12 +261,12 @@ def _sep_conv(a, w, periodic_cols=False):
     return res
 
 
-def viscosity(e, ps, W, gamma, tau=None, fp32=True):
+def viscosity(e, ps, W, gamma, tau=None, fp32=True, arg=None):
     """Full per-step viscosity: classifier, preliminary, Lambda.  Returns
-    (mu, tau, argmax)."""
+    (mu, tau, argmax).  tau / arg given: replayed decisions."""
     if tau is None:
         tau = classify(e, ps, W, gamma, fp32=fp32)
-    muh, arg = preliminary(e, tau, ps, gamma, fp32=fp32)
+    muh, arg = preliminary(e, tau, ps, gamma, fp32=fp32, arg=arg)
     return smooth_blend(muh, ps), tau, arg
 
 

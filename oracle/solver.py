@@ -83,18 +83,23 @@ class Run:
             return mu, None, None
         return av.viscosity(e, ps, self.cfg.mlp, self.gamma)
 
-    def step(self, dt=None, tau=None):
+    def step(self, dt=None, tau=None, arg=None, record=False):
+        """One step; dt, tau, arg replay recorded decisions.  record keeps
+        the glued stage inputs for the discrete adjoint."""
         ps, g = self.ps, self.gamma
         e = self.u
         glue(e, ps, self.mach, g)
-        if self.cfg.mu_const is None and tau is not None:
-            mu, tau_used, arg = av.viscosity(e, ps, self.cfg.mlp, g, tau=tau)
+        if self.cfg.mu_const is None and (tau is not None or arg is not None):
+            mu, tau_used, arg = av.viscosity(e, ps, self.cfg.mlp, g, tau=tau, arg=arg)
         else:
             mu, tau_used, arg = self.viscosity(e)
         if dt is None:
             dt = rk.cfl_dt(e, mu, ps, self.cfg.cfl, g)
         L = lambda u, s: euler.full_rhs(u, ps.metric, mu, ps, g)
         new, stages, rhs = rk.ssprk_step(e, dt, L, glue=lambda u, s: glue(u, ps, self.mach, g))
-        self.log.append(dict(dt=dt, tau=tau_used, arg=arg, mu=mu))
+        entry = dict(dt=dt, tau=tau_used, arg=arg, mu=mu)
+        if record:
+            entry["stages"] = [np.array(x) for x in stages[:-1]]
+        self.log.append(entry)
         self.u = new
         return new

@@ -64,6 +64,7 @@ def lib():
             "fcsd_ctx_sync": [vp],
             "fcsd_set_create": [vp, i32, P(PatchDesc), i32, i64, i32, i32, P(vp)],
             "fcsd_set_destroy": [vp],
+            "fcsd_set_tune": [vp, i32],
             "fcsd_workspace_size": [vp, i32, P(sz)],
             "fcsd_ext_size": [vp, i32, P(i64)],
             "fc_continue": [vp, vp, i32, i32, vp, i64, vp, i64],
@@ -104,7 +105,7 @@ def lib():
 
 # the names every header declaration exports (checked by the CPU tests)
 EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_last_error",
-           "fcsd_ctx_stream", "fcsd_ctx_sync", "fcsd_set_create", "fcsd_set_destroy",
+           "fcsd_ctx_stream", "fcsd_ctx_sync", "fcsd_set_create", "fcsd_set_destroy", "fcsd_set_tune",
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
            "rk_stage_adj", "fcsd_cfl_dt", "sdnn_infer", "av_viscosity", "av_viscosity_adj",

@@ -91,6 +91,9 @@ class PatchSet:
             self._ws[op] = torch.empty(n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
         return self._ws[op]
 
+    def tune(self, lds_budget_bytes: int):
+        self.ctx.check(lib().fcsd_set_tune(self.h, int(lds_budget_bytes)), "fcsd_set_tune")
+
     def ext_size(self, direction: int) -> int:
         v = ctypes.c_int64()
         self.ctx.check(lib().fcsd_ext_size(self.h, direction, ctypes.byref(v)), "ext_size")

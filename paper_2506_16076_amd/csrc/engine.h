@@ -46,88 +46,142 @@ struct TileDev {
   int ld;     // LDS stride in float2 (odd, >= nl)
 };
 
-// n = q*d + r for 0 <= n < 2^23 using a float reciprocal and one correction
-struct FastDiv {
-  int d;
-  float r;
+// Per-thread view of a tile in LDS.  Layout of the dynamic LDS block:
+//   z   [L * ld] float2   the lines, z[pos * ld + c]
+//   tw  [L]      float2   exp(-2 pi i n / L)
+//   km  [L]      float    derivative multipliers by digit-reversed position
+// Thread t works on line c = t % nl and on butterflies t / nl, t / nl + BS,
+// ... of every stage (BS = blockDim / nl), so consecutive lanes touch
+// consecutive lines (conflict-free LDS rows) and share their twiddle
+// (broadcast).  Threads t >= BS * nl only take part in the element loops.
+struct LineCtx {
+  float2* z;
+  const float2* tw;
+  const float* km;
+  int ld, nl, c, b0, BS;
+  bool active;
 };
-__device__ __forceinline__ FastDiv make_div(int d) { return FastDiv{d, 1.0f / (float)d}; }
-__device__ __forceinline__ int divq(int n, FastDiv f, int& rem) {
-  int q = (int)((float)n * f.r);
-  int r = n - q * f.d;
-  if (r < 0) {
-    --q;
-    r += f.d;
-  } else if (r >= f.d) {
-    ++q;
-    r -= f.d;
+
+__device__ __forceinline__ size_t tile_lds_bytes(int L, int ld) {
+  return (size_t)L * ld * sizeof(float2) + (size_t)L * (sizeof(float2) + sizeof(float));
+}
+
+// Copy the plan's twiddles and multipliers into LDS; the caller syncs.
+__device__ __forceinline__ LineCtx line_setup(float2* lds, const TileDev& T, const PlanDev& P,
+                                              const float2* __restrict__ twg, const float* __restrict__ kmg) {
+  LineCtx X;
+  X.z = lds;
+  float2* tw = lds + (size_t)P.L * T.ld;
+  float* km = reinterpret_cast<float*>(tw + P.L);
+  for (int i = threadIdx.x; i < P.L; i += blockDim.x) {
+    tw[i] = twg[P.tw + i];
+    km[i] = kmg[P.km + i];
   }
-  rem = r;
-  return q;
+  X.tw = tw;
+  X.km = km;
+  X.ld = T.ld;
+  X.nl = T.nl;
+  X.BS = blockDim.x / T.nl;
+  X.c = threadIdx.x % T.nl;
+  X.b0 = threadIdx.x / T.nl;
+  X.active = X.b0 < X.BS;
+  return X;
+}
+
+// Visit the N x nl elements of a tile, f(pos, c), in the order that
+// coalesces global memory: q1 lines (DIR 1) pos-fastest, q2 lines (DIR 2)
+// line-fastest.  Index steps are incremental (no division in the loop).
+template <int DIR, class F>
+__device__ __forceinline__ void for_elems(int N, int nl, F&& f) {
+  const int na = DIR == 1 ? N : nl;
+  const int nbb = DIR == 1 ? nl : N;
+  int a = threadIdx.x % na, b = threadIdx.x / na;
+  const int sa = blockDim.x % na, sb = blockDim.x / na;
+  while (b < nbb) {
+    if (DIR == 1)
+      f(a, b);
+    else
+      f(b, a);
+    a += sa;
+    b += sb;
+    if (a >= na) {
+      a -= na;
+      ++b;
+    }
+  }
 }
 
 // One radix-R stage.  Forward (DIF): block of M points, m = M/R, butterfly j
 // reads x_t = z[base + j + t m], y = DFT_R(x), y_q *= w_M^(j q), stores back.
-// Inverse (DIT): the exact reverse with conjugate twiddles.
-template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(float2* __restrict__ z, int ld, int nl, int L, int M,
-                                          const float2* __restrict__ tw) {
+// Inverse (DIT): the exact reverse with conjugate twiddles.  MUL (last
+// forward stage, M = R): multiply the outputs by i * mulsign * km[pos].
+template <int R, bool INV, bool MUL>
+__device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M, float mulsign) {
+  if (!X.active) return;
   const int m = M / R;
   const int stride = L / M;
-  const int items = (L / R) * nl;
-  const FastDiv fnl = make_div(nl), fm = make_div(m);
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    int c;
-    const int b = divq(it, fnl, c);
-    int j;
-    const int blk = divq(b, fm, j);
+  const int nb = L / R;
+  const int ld = X.ld, c = X.c;
+  float2* __restrict__ z = X.z;
+  int b = X.b0;
+  int blk = b / m, j = b - blk * m;
+  const int dblk = X.BS / m, dj = X.BS - dblk * m;
+  for (; b < nb; b += X.BS) {
     const int base = blk * M + j;
     float2 x[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) x[t] = z[(base + t * m) * ld + c];
     if (!INV) {
       Dft<R, false>::run(x);
-      if (j) {
+      if (MUL) {
 #pragma unroll
-        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], tw[stride * j * q]);
+        for (int q = 0; q < R; ++q) {
+          const float k = mulsign * X.km[base + q];
+          x[q] = make_float2(-k * x[q].y, k * x[q].x);
+        }
+      } else if (j) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], X.tw[stride * j * q]);
       }
     } else {
       if (j) {
 #pragma unroll
-        for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], tw[stride * j * q]);
+        for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], X.tw[stride * j * q]);
       }
       Dft<R, true>::run(x);
     }
 #pragma unroll
     for (int t = 0; t < R; ++t) z[(base + t * m) * ld + c] = x[t];
+    j += dj;
+    blk += dblk;
+    if (j >= m) {
+      j -= m;
+      ++blk;
+    }
   }
 }
 
-template <bool INV>
-__device__ __forceinline__ void fft_dispatch(int R, float2* z, int ld, int nl, int L, int M,
-                                             const float2* tw) {
+template <bool INV, bool MUL>
+__device__ __forceinline__ void fft_dispatch(int R, const LineCtx& X, int L, int M, float mulsign) {
   switch (R) {
-    case 2: fft_stage<2, INV>(z, ld, nl, L, M, tw); break;
-    case 3: fft_stage<3, INV>(z, ld, nl, L, M, tw); break;
-    case 4: fft_stage<4, INV>(z, ld, nl, L, M, tw); break;
-    case 5: fft_stage<5, INV>(z, ld, nl, L, M, tw); break;
-    case 7: fft_stage<7, INV>(z, ld, nl, L, M, tw); break;
-    case 8: fft_stage<8, INV>(z, ld, nl, L, M, tw); break;
-    case 11: fft_stage<11, INV>(z, ld, nl, L, M, tw); break;
-    case 13: fft_stage<13, INV>(z, ld, nl, L, M, tw); break;
+    case 2: fft_stage<2, INV, MUL>(X, L, M, mulsign); break;
+    case 3: fft_stage<3, INV, MUL>(X, L, M, mulsign); break;
+    case 4: fft_stage<4, INV, MUL>(X, L, M, mulsign); break;
+    case 5: fft_stage<5, INV, MUL>(X, L, M, mulsign); break;
+    case 7: fft_stage<7, INV, MUL>(X, L, M, mulsign); break;
+    case 8: fft_stage<8, INV, MUL>(X, L, M, mulsign); break;
+    case 11: fft_stage<11, INV, MUL>(X, L, M, mulsign); break;
+    case 13: fft_stage<13, INV, MUL>(X, L, M, mulsign); break;
     default: break;
   }
 }
 
 // Tail of every line (continuation); periodic plans have no tail.
-__device__ __forceinline__ void fc_tail(float2* __restrict__ z, int ld, int nl, const PlanDev& P,
-                                        const double* __restrict__ aq, int d) {
-  const int N = P.N, C = P.C;
-  const int items = C * nl;
-  const FastDiv fnl = make_div(nl);
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    int c;
-    const int m = divq(it, fnl, c);
+__device__ __forceinline__ void fc_tail(const LineCtx& X, const PlanDev& P, const double* __restrict__ aq, int d) {
+  if (!X.active) return;
+  const int N = P.N, C = P.C, ld = X.ld, c = X.c;
+  float2* __restrict__ z = X.z;
+  for (int m = X.b0; m < C; m += X.BS) {
     double sx = 0.0, sy = 0.0;
     const double* ar = aq + m * d;                 // right blend row m
     const double* al = aq + (C - 1 - m) * d;       // mirrored row for the left blend
@@ -144,28 +198,13 @@ __device__ __forceinline__ void fc_tail(float2* __restrict__ z, int ld, int nl, 
   }
 }
 
-// z <- i * kmul[pos] * z (sign -1 for the transpose)
-__device__ __forceinline__ void spectral_mul(float2* __restrict__ z, int ld, int nl, int L,
-                                             const float* __restrict__ km, float sign) {
-  const int items = L * nl;
-  const FastDiv fnl = make_div(nl);
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    int c;
-    const int p = divq(it, fnl, c);
-    const float k = sign * km[p];
-    const float2 v = z[p * ld + c];
-    z[p * ld + c] = make_float2(-k * v.y, k * v.x);
-  }
-}
-
 // E^T of the continuation: add sum_m (A Q^T)[m][j] tail[m] to the 2d end
 // samples (reads positions N.., writes positions < N; distinct for N >= 2d).
-__device__ __forceinline__ void fold_tail(float2* __restrict__ z, int ld, int nl, const PlanDev& P,
-                                          const double* __restrict__ aq, int d) {
-  const int items = 2 * d * nl;
-  const int N = P.N, C = P.C;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int e = it / nl, c = it - e * nl;
+__device__ __forceinline__ void fold_tail(const LineCtx& X, const PlanDev& P, const double* __restrict__ aq, int d) {
+  if (!X.active) return;
+  const int N = P.N, C = P.C, ld = X.ld, c = X.c;
+  float2* __restrict__ z = X.z;
+  for (int e = X.b0; e < 2 * d; e += X.BS) {
     double sx = 0.0, sy = 0.0;
     int pos;
     if (e < d) {  // right end sample j = e at N-d+e: sum_m ArQ[m][j] tail[m]
@@ -190,23 +229,16 @@ __device__ __forceinline__ void fold_tail(float2* __restrict__ z, int ld, int nl
   }
 }
 
-// Derivative of the tile in place (steps 2-4); the caller has filled
-// positions 0..N-1 and synchronised.  adj = transpose (zero tail, -i k).
+// Derivative of the tile in place; the caller has filled positions 0..N-1
+// and synchronised.  ADJ = transpose (zero tail, -i k, fold).
 template <bool ADJ>
-__device__ void line_derivative(float2* __restrict__ z, int ld, int nl, const PlanDev* __restrict__ Pg,
-                                const PlanDev& P,
-                                const float2* __restrict__ twp, const float* __restrict__ kmp,
+__device__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
                                 const double* __restrict__ aqp, int d) {
-  const float2* tw = twp + P.tw;
   if (!P.periodic) {
     if (!ADJ) {
-      fc_tail(z, ld, nl, P, aqp + P.aq, d);
-    } else {
-      const int items = P.C * nl;
-      for (int it = threadIdx.x; it < items; it += blockDim.x) {
-        const int m = it / nl, c = it - m * nl;
-        z[(P.N + m) * ld + c] = make_float2(0.f, 0.f);
-      }
+      fc_tail(X, P, aqp + P.aq, d);
+    } else if (X.active) {
+      for (int m = X.b0; m < P.C; m += X.BS) X.z[(P.N + m) * X.ld + X.c] = make_float2(0.f, 0.f);
     }
     __syncthreads();
   }
@@ -214,24 +246,26 @@ __device__ void line_derivative(float2* __restrict__ z, int ld, int nl, const Pl
   // array indexed by the stage counter would live in scratch
   const int* rad = Pg->rad;
   const int nst = P.nst;
+  const float sign = ADJ ? -1.f : 1.f;
   int M = P.L;
   for (int s = 0; s < nst; ++s) {
     const int R = rad[s];
-    fft_dispatch<false>(R, z, ld, nl, P.L, M, tw);
+    if (s == nst - 1)
+      fft_dispatch<false, true>(R, X, P.L, M, sign);
+    else
+      fft_dispatch<false, false>(R, X, P.L, M, sign);
     M /= R;
     __syncthreads();
   }
-  spectral_mul(z, ld, nl, P.L, kmp + P.km, ADJ ? -1.f : 1.f);
-  __syncthreads();
   M = 1;
   for (int s = nst - 1; s >= 0; --s) {
     const int R = rad[s];
     M *= R;
-    fft_dispatch<true>(R, z, ld, nl, P.L, M, tw);
+    fft_dispatch<true, false>(R, X, P.L, M, sign);
     __syncthreads();
   }
   if (ADJ && !P.periodic) {
-    fold_tail(z, ld, nl, P, aqp + P.aq, d);
+    fold_tail(X, P, aqp + P.aq, d);
     __syncthreads();
   }
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -79,6 +80,7 @@ struct fcsd_set {
   int annulus = 0;
   AnnulusDev an{};
   std::vector<GraphEntry> graphs;
+  size_t lds_budget = 0;
 };
 
 namespace {
@@ -296,6 +298,53 @@ extern "C" fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* 
   return FCSD_OK;
 }
 
+namespace {
+
+size_t default_lds_budget() {
+  const char* e = getenv("FCSD_LDS_BUDGET");
+  long v = e ? atol(e) : 0;
+  return (v >= 8192 && v <= 160 * 1024) ? (size_t)v : kLdsBudget;
+}
+
+// Split every patch's lines into tiles that fit `budget` bytes of LDS
+// (lines + twiddle and multiplier tables), balanced per patch, and order the
+// batched list longest-first.
+void build_tiles(DirPlan& D, size_t budget) {
+  D.tiles_by_patch.clear();
+  D.patch_begin.assign(1, 0);
+  D.patch_lds.clear();
+  D.lds = 0;
+  for (size_t p = 0; p < D.plans.size(); ++p) {
+    const PlanDev& P = D.plans[p];
+    const size_t tables = (size_t)P.L * (sizeof(float2) + sizeof(float));
+    int nlmax = budget > tables ? (int)((budget - tables) / (sizeof(float2) * (size_t)P.L)) - 1 : 1;
+    nlmax = std::max(1, std::min(kMaxTile, nlmax));
+    const int nt = (P.nlines + nlmax - 1) / nlmax;
+    const int nl = (P.nlines + nt - 1) / nt;
+    size_t plds = 0;
+    for (int t = 0; t < nt; ++t) {
+      TileDev T;
+      T.plan = (int)p;
+      T.line0 = t * nl;
+      T.nl = std::min(nl, P.nlines - T.line0);
+      if (T.nl <= 0) continue;
+      T.ld = T.nl | 1;
+      D.tiles_by_patch.push_back(T);
+      plds = std::max(plds, (size_t)P.L * T.ld * sizeof(float2) + tables);
+    }
+    D.patch_begin.push_back((int)D.tiles_by_patch.size());
+    D.patch_lds.push_back(plds);
+    D.lds = std::max(D.lds, plds);
+  }
+  D.tiles = D.tiles_by_patch;
+  std::stable_sort(D.tiles.begin(), D.tiles.end(), [&](const TileDev& a, const TileDev& b) {
+    const PlanDev &pa = D.plans[a.plan], &pb = D.plans[b.plan];
+    return (long long)pa.L * a.nl > (long long)pb.L * b.nl;
+  });
+}
+
+}  // namespace
+
 // ======================================================================== patch set
 
 extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_patch_desc* patches, int d,
@@ -320,7 +369,6 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   std::map<std::tuple<int, int, int>, int> km_of;
   for (int dir = 1; dir <= 2; ++dir) {
     DirPlan& D = s->dir[dir - 1];
-    D.patch_begin.assign(1, 0);
     long long eo = 0;
     for (int p = 0; p < npatch; ++p) {
       const fcsd_patch_desc& q = patches[p];
@@ -364,33 +412,11 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
       D.plans.push_back(P);
       D.ext_off.push_back(eo);
       eo += (long long)P.nlines * P.L;
-      // tiles
-      int nlmax = (int)(kLdsBudget / (8 * (size_t)P.L)) - 1;
-      nlmax = std::max(1, std::min(kMaxTile, nlmax));
-      const int nt = (P.nlines + nlmax - 1) / nlmax;
-      const int nl = (P.nlines + nt - 1) / nt;
-      size_t plds = 0;
-      for (int t = 0; t < nt; ++t) {
-        TileDev T;
-        T.plan = p;
-        T.line0 = t * nl;
-        T.nl = std::min(nl, P.nlines - T.line0);
-        if (T.nl <= 0) continue;
-        T.ld = T.nl | 1;
-        D.tiles_by_patch.push_back(T);
-        plds = std::max(plds, (size_t)P.L * T.ld * sizeof(float2));
-      }
-      D.patch_begin.push_back((int)D.tiles_by_patch.size());
-      D.patch_lds.push_back(plds);
-      D.lds = std::max(D.lds, plds);
     }
     D.ext_plane = eo;
-    D.tiles = D.tiles_by_patch;
-    std::stable_sort(D.tiles.begin(), D.tiles.end(), [&](const TileDev& a, const TileDev& b) {
-      const PlanDev &pa = D.plans[a.plan], &pb = D.plans[b.plan];
-      return (long long)pa.L * a.nl > (long long)pb.L * b.nl;
-    });
   }
+  s->lds_budget = default_lds_budget();
+  for (int dir = 0; dir < 2; ++dir) build_tiles(s->dir[dir], s->lds_budget);
   // per-patch descriptors and point chunks
   std::vector<PatchDev> pd;
   std::vector<ChunkDev> ch;
@@ -478,6 +504,27 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_lats);
   hipFree(s->d_lchunks);
   delete s;
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, int lds_budget_bytes) {
+  if (!s) return FCSD_EINVAL;
+  fcsd_ctx* ctx = s->ctx;
+  if (lds_budget_bytes < 8192 || lds_budget_bytes > 160 * 1024)
+    return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget must be in [8 KB, 160 KB]");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& g : s->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
+  s->lds_budget = (size_t)lds_budget_bytes;
+  for (int dir = 0; dir < 2; ++dir) {
+    DirPlan& D = s->dir[dir];
+    build_tiles(D, s->lds_budget);
+    (void)hipFree(D.d_tiles);
+    (void)hipFree(D.d_tiles_bp);
+    fcsd_status r;
+    if ((r = upload(ctx, &D.d_tiles, D.tiles)) || (r = upload(ctx, &D.d_tiles_bp, D.tiles_by_patch))) return r;
+  }
   return FCSD_OK;
 }
 
@@ -596,8 +643,9 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
     if ((st = launch_check(ctx, "pass H"))) return st;
   } else if (flux != FLUX_INVISCID) {
     a.plans = s->dir[0].d_plans;
+    a.out = W.d1e;
     if (passes & 1u)
-      if ((st = launch_lines(s, 1, k_passA, a, patch))) return st;
+      if ((st = launch_lines(s, 1, k_dev_diff<1>, a, patch))) return st;
     PassArgs b = a;
     b.plans = s->dir[1].d_plans;
     b.mode = flux;

@@ -92,52 +92,46 @@ __device__ __forceinline__ void dev_flux(const float e[4], const float er[4], co
   dG[3] = dv * H + pr[2] * (dE + dp);
 }
 
-// position / line of a tile element and its plane index
+// plane index of element (pos, c) of a tile
 template <int DIR>
 __device__ __forceinline__ long long gindex(const PlanDev& P, const TileDev& T, int pos, int c) {
   return DIR == 1 ? P.off + (long long)(T.line0 + c) * P.n1 + pos
                   : P.off + (long long)pos * P.n1 + (T.line0 + c);
 }
-// enumerate N*nl elements in the order that coalesces the global access
-template <int DIR>
-__device__ __forceinline__ void elem(int it, int N, int nl, int& pos, int& c) {
-  if (DIR == 1) {
-    c = it / N;
-    pos = it - c * N;
-  } else {
-    pos = it / nl;
-    c = it - pos * nl;
-  }
-}
 
 extern __shared__ float2 lds_z[];
+
+// tile prologue common to every line kernel: tile, plan, LDS tables
+#define FCSD_TILE_BEGIN(a)                                                   \
+  const TileDev T = (a).tiles[blockIdx.x];                                   \
+  const PlanDev P = (a).plans[T.plan];                                       \
+  const PlanDev* Pg = (a).plans + T.plan;                                    \
+  const LineCtx X = line_setup(lds_z, T, P, (a).tw, (a).km);                 \
+  float2* __restrict__ z = X.z;                                              \
+  const int N = P.N, nl = T.nl, ld = T.ld;                                   \
+  (void)Pg;                                                                  \
+  (void)nl;                                                                  \
+  __syncthreads();
 
 // ---------------------------------------------------------------- generic line ops
 
 // fc_diff / fc_diff_adj on nf fields, packed two per complex line.
 template <int DIR, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_fcdiff(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, nl = T.nl, ld = T.ld;
+  FCSD_TILE_BEGIN(a)
   for (int f = 0; f < a.nf; f += 2) {
     const bool two = f + 1 < a.nf;
     const float* A = a.in + (long long)f * a.plane;
     const float* B = a.in + (long long)(f + 1) * a.plane;
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<DIR>(it, N, nl, pos, c);
+    for_elems<DIR>(N, nl, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
-    }
+    });
     __syncthreads();
-    line_derivative<ADJ>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    line_derivative<ADJ>(X, Pg, P, a.aq, a.d);
     float* OA = a.out + (long long)f * a.plane;
     float* OB = a.out + (long long)(f + 1) * a.plane;
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<DIR>(it, N, nl, pos, c);
+    for_elems<DIR>(N, nl, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       if (ADJ) {
@@ -147,7 +141,7 @@ __global__ void __launch_bounds__(kBlock) k_fcdiff(PassArgs a) {
         OA[g] = v.x;
         if (two) OB[g] = v.y;
       }
-    }
+    });
     __syncthreads();
   }
 }
@@ -155,53 +149,45 @@ __global__ void __launch_bounds__(kBlock) k_fcdiff(PassArgs a) {
 // fc_continue (FWD) and its transpose: ext lines of length L per plan.
 template <int DIR, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_fccont(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, L = P.L, nl = T.nl, ld = T.ld;
+  FCSD_TILE_BEGIN(a)
+  const int L = P.L;
   const long long e0 = a.ext_off[T.plan] + (long long)T.line0 * L;
   for (int f = 0; f < a.nf; f += 2) {
     const bool two = f + 1 < a.nf;
     if (!ADJ) {
       const float* A = a.in + (long long)f * a.plane;
       const float* B = a.in + (long long)(f + 1) * a.plane;
-      for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-        int pos, c;
-        elem<DIR>(it, N, nl, pos, c);
+      for_elems<DIR>(N, nl, [&](int pos, int c) {
         const long long g = gindex<DIR>(P, T, pos, c);
         z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
-      }
+      });
       __syncthreads();
-      if (!P.periodic) fc_tail(z, ld, nl, P, a.aq + P.aq, a.d);
+      if (!P.periodic) fc_tail(X, P, a.aq + P.aq, a.d);
       __syncthreads();
       float* OA = a.out + (long long)f * a.ext_plane + e0;
       float* OB = a.out + (long long)(f + 1) * a.ext_plane + e0;
-      for (int it = threadIdx.x; it < L * nl; it += blockDim.x) {
-        const int c = it / L, pos = it - c * L;
+      for_elems<1>(L, nl, [&](int pos, int c) {
         const float2 v = z[pos * ld + c];
         OA[(long long)c * L + pos] = v.x;
         if (two) OB[(long long)c * L + pos] = v.y;
-      }
+      });
     } else {
       const float* A = a.in + (long long)f * a.ext_plane + e0;
       const float* B = a.in + (long long)(f + 1) * a.ext_plane + e0;
-      for (int it = threadIdx.x; it < L * nl; it += blockDim.x) {
-        const int c = it / L, pos = it - c * L;
+      for_elems<1>(L, nl, [&](int pos, int c) {
         z[pos * ld + c] = make_float2(A[(long long)c * L + pos], two ? B[(long long)c * L + pos] : 0.f);
-      }
+      });
       __syncthreads();
-      if (!P.periodic) fold_tail(z, ld, nl, P, a.aq + P.aq, a.d);
+      if (!P.periodic) fold_tail(X, P, a.aq + P.aq, a.d);
       __syncthreads();
       float* OA = a.out + (long long)f * a.plane;
       float* OB = a.out + (long long)(f + 1) * a.plane;
-      for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-        int pos, c;
-        elem<DIR>(it, N, nl, pos, c);
+      for_elems<DIR>(N, nl, [&](int pos, int c) {
         const long long g = gindex<DIR>(P, T, pos, c);
         const float2 v = z[pos * ld + c];
         OA[g] += v.x;
         if (two) OB[g] += v.y;
-      }
+      });
     }
     __syncthreads();
   }
@@ -209,34 +195,28 @@ __global__ void __launch_bounds__(kBlock) k_fccont(PassArgs a) {
 
 // ---------------------------------------------------------------- RHS passes
 
-// Pass A (q1 lines): d1e = D1 (e - e_ref), four fields.
-__global__ void __launch_bounds__(kBlock) k_passA(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, nl = T.nl, ld = T.ld;
+// d_DIR (e - e_ref) of the four state fields into out (pass A for DIR 1).
+template <int DIR>
+__global__ void __launch_bounds__(kBlock) k_dev_diff(PassArgs a) {
+  FCSD_TILE_BEGIN(a)
   for (int f = 0; f < 4; f += 2) {
     const float* A = a.u + (long long)f * a.plane;
     const float* B = a.u + (long long)(f + 1) * a.plane;
     const float ra = a.eref[f], rb = a.eref[f + 1];
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<1>(it, N, nl, pos, c);
-      const long long g = gindex<1>(P, T, pos, c);
+    for_elems<DIR>(N, nl, [&](int pos, int c) {
+      const long long g = gindex<DIR>(P, T, pos, c);
       z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
-    }
+    });
     __syncthreads();
-    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
-    float* OA = const_cast<float*>(a.d1e) + (long long)f * a.plane;
-    float* OB = const_cast<float*>(a.d1e) + (long long)(f + 1) * a.plane;
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<1>(it, N, nl, pos, c);
-      const long long g = gindex<1>(P, T, pos, c);
+    line_derivative<false>(X, Pg, P, a.aq, a.d);
+    float* OA = a.out + (long long)f * a.plane;
+    float* OB = a.out + (long long)(f + 1) * a.plane;
+    for_elems<DIR>(N, nl, [&](int pos, int c) {
+      const long long g = gindex<DIR>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       OA[g] = v.x;
       OB[g] = v.y;
-    }
+    });
     __syncthreads();
   }
 }
@@ -274,25 +254,18 @@ __device__ __forceinline__ void make_H(const PassArgs& a, long long g, int f, fl
 // Pass B1 (q2 lines): d2e, then H = mu grad_x e - f' (mode FLUX_FULL /
 // FLUX_VISC).  H layout: field 2c = H_x component c, 2c+1 = H_y component c.
 __global__ void __launch_bounds__(kBlock) k_passB1(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, nl = T.nl, ld = T.ld;
+  FCSD_TILE_BEGIN(a)
   for (int f = 0; f < 4; f += 2) {
     const float* A = a.u + (long long)f * a.plane;
     const float* B = a.u + (long long)(f + 1) * a.plane;
     const float ra = a.eref[f], rb = a.eref[f + 1];
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<2>(it, N, nl, pos, c);
+    for_elems<2>(N, nl, [&](int pos, int c) {
       const long long g = gindex<2>(P, T, pos, c);
       z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
-    }
+    });
     __syncthreads();
-    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<2>(it, N, nl, pos, c);
+    line_derivative<false>(X, Pg, P, a.aq, a.d);
+    for_elems<2>(N, nl, [&](int pos, int c) {
       const long long g = gindex<2>(P, T, pos, c);
       float hx[2], hy[2];
       make_H(a, g, f, z[pos * ld + c], a.mode, hx, hy);
@@ -300,7 +273,7 @@ __global__ void __launch_bounds__(kBlock) k_passB1(PassArgs a) {
       a.H[(long long)(2 * f + 1) * a.plane + g] = hy[0];
       a.H[(long long)(2 * f + 2) * a.plane + g] = hx[1];
       a.H[(long long)(2 * f + 3) * a.plane + g] = hy[1];
-    }
+    });
     __syncthreads();
   }
 }
@@ -327,29 +300,22 @@ __global__ void __launch_bounds__(kBlock) k_passH(PassArgs a, long long n) {
 
 // Pass B2 (q2 lines): r2_c = m2x d2 H_x,c + m2y d2 H_y,c.
 __global__ void __launch_bounds__(kBlock) k_passB2(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, nl = T.nl, ld = T.ld;
+  FCSD_TILE_BEGIN(a)
   const long long pl = a.plane;
   for (int comp = 0; comp < 4; ++comp) {
     const float* A = a.H + (long long)(2 * comp) * pl;
     const float* B = a.H + (long long)(2 * comp + 1) * pl;
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<2>(it, N, nl, pos, c);
+    for_elems<2>(N, nl, [&](int pos, int c) {
       const long long g = gindex<2>(P, T, pos, c);
       z[pos * ld + c] = make_float2(A[g], B[g]);
-    }
+    });
     __syncthreads();
-    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<2>(it, N, nl, pos, c);
+    line_derivative<false>(X, Pg, P, a.aq, a.d);
+    for_elems<2>(N, nl, [&](int pos, int c) {
       const long long g = gindex<2>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       a.r2[(long long)comp * pl + g] = a.metric[2 * pl + g] * v.x + a.metric[3 * pl + g] * v.y;
-    }
+    });
     __syncthreads();
   }
 }
@@ -357,29 +323,22 @@ __global__ void __launch_bounds__(kBlock) k_passB2(PassArgs a) {
 // Pass C (q1 lines): r = m1x d1 H_x + m1y d1 H_y + r2, then store (SET/ADD)
 // or the SSPRK register update (RK).
 __global__ void __launch_bounds__(kBlock) k_passC(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, nl = T.nl, ld = T.ld;
+  FCSD_TILE_BEGIN(a)
   const long long pl = a.plane;
   float dt = 0.f;
-  RkCoef K = rk_coef(a.stage);
+  const RkCoef K = rk_coef(a.stage);
   if (a.mode == MODE_RK) dt = a.dt[0];
   for (int comp = 0; comp < 4; ++comp) {
     const float* A = a.H + (long long)(2 * comp) * pl;
     const float* B = a.H + (long long)(2 * comp + 1) * pl;
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<1>(it, N, nl, pos, c);
+    for_elems<1>(N, nl, [&](int pos, int c) {
       const long long g = gindex<1>(P, T, pos, c);
       z[pos * ld + c] = make_float2(A[g], B[g]);
-    }
+    });
     __syncthreads();
-    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
+    line_derivative<false>(X, Pg, P, a.aq, a.d);
     const long long fo = (long long)comp * pl;
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<1>(it, N, nl, pos, c);
+    for_elems<1>(N, nl, [&](int pos, int c) {
       const long long g = gindex<1>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       const float r = a.metric[g] * v.x + a.metric[pl + g] * v.y + a.r2[fo + g];
@@ -402,7 +361,7 @@ __global__ void __launch_bounds__(kBlock) k_passC(PassArgs a) {
           a.uout[fo + g] = a.acc[fo + g] + K.ai * ui + K.b * dr;
         }
       }
-    }
+    });
     __syncthreads();
   }
 }

@@ -655,37 +655,6 @@ __device__ __forceinline__ void flux_vjp(const float e[4], float gam, const floa
   out[3] = Eb + Pb * g1;
 }
 
-// Pass A for either direction: out = D_dir (e - e_ref)
-template <int DIR>
-__global__ void __launch_bounds__(kBlock) k_dev_diff(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, nl = T.nl, ld = T.ld;
-  for (int f = 0; f < 4; f += 2) {
-    const float* A = a.u + (long long)f * a.plane;
-    const float* B = a.u + (long long)(f + 1) * a.plane;
-    const float ra = a.eref[f], rb = a.eref[f + 1];
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<DIR>(it, N, nl, pos, c);
-      const long long g = gindex<DIR>(P, T, pos, c);
-      z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
-    }
-    __syncthreads();
-    line_derivative<false>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<DIR>(it, N, nl, pos, c);
-      const long long g = gindex<DIR>(P, T, pos, c);
-      const float2 v = z[pos * ld + c];
-      a.out[(long long)f * a.plane + g] = v.x;
-      a.out[(long long)(f + 1) * a.plane + g] = v.y;
-    }
-    __syncthreads();
-  }
-}
-
 // Reverse of pass C / B2: Hb (+)= D_dir^T (m_dir,x rb, m_dir,y rb).
 // DIR = 2 additionally finishes H_bar and applies the pointwise reverse of
 // H = mu grad e - f': G1/G2 = mu-weighted metric products (for D^T later),
@@ -694,25 +663,18 @@ template <int DIR>
 __global__ void __launch_bounds__(kBlock) k_adjHb(PassArgs a, const float* rb, float* Hb,
                                                   const float* d1e, const float* d2e, float* G1,
                                                   float* G2, float* mub, float* ub, int visc) {
-  const TileDev T = a.tiles[blockIdx.x];
-  const PlanDev P = a.plans[T.plan];
-  float2* z = lds_z;
-  const int N = P.N, nl = T.nl, ld = T.ld;
+  FCSD_TILE_BEGIN(a)
   const long long pl = a.plane;
   const int mx = DIR == 1 ? 0 : 2, my = DIR == 1 ? 1 : 3;
   for (int comp = 0; comp < 4; ++comp) {
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<DIR>(it, N, nl, pos, c);
+    for_elems<DIR>(N, nl, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float r = rb[(long long)comp * pl + g];
       z[pos * ld + c] = make_float2(a.metric[mx * pl + g] * r, a.metric[my * pl + g] * r);
-    }
+    });
     __syncthreads();
-    line_derivative<true>(z, ld, nl, a.plans + T.plan, P, a.tw, a.km, a.aq, a.d);
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<DIR>(it, N, nl, pos, c);
+    line_derivative<true>(X, Pg, P, a.aq, a.d);
+    for_elems<DIR>(N, nl, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       const long long ix = (long long)(2 * comp) * pl + g, iy = (long long)(2 * comp + 1) * pl + g;
@@ -737,13 +699,11 @@ __global__ void __launch_bounds__(kBlock) k_adjHb(PassArgs a, const float* rb, f
           }
         }
       }
-    }
+    });
     __syncthreads();
   }
   if (DIR == 2 && a.mode != FLUX_VISC) {
-    for (int it = threadIdx.x; it < N * nl; it += blockDim.x) {
-      int pos, c;
-      elem<DIR>(it, N, nl, pos, c);
+    for_elems<DIR>(N, nl, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       float e[4], fb[4], gb[4], o[4];
 #pragma unroll
@@ -755,7 +715,7 @@ __global__ void __launch_bounds__(kBlock) k_adjHb(PassArgs a, const float* rb, f
       flux_vjp(e, a.gamma, fb, gb, o);
 #pragma unroll
       for (int q = 0; q < 4; ++q) ub[(long long)q * pl + g] += o[q];
-    }
+    });
   }
 }
 
