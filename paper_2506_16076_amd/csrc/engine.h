@@ -4,17 +4,29 @@
 // ld odd so that both the line-fastest FFT accesses and the pos-fastest
 // row-tile loads are bank-conflict free).
 //
-// FC derivative of every line (paper Sec. 2.2, eqs. continuation and fc_der):
-//   1. tail: z[N + m] = sum_j ArQ[m][j] z[N-d+j] + ArQ[C-1-m][d-1-j] z[j]
-//      (FP64 accumulation: the matrix entries reach 1e4 while the tail is of
-//      the size of the data);
-//   2. forward FFT of length L = N + C: in-place mixed-radix decimation in
+// FC derivative of every line (paper Sec. 2.2, eqs. continuation and fc_der).
+// The extension ext = [f; A_l Q^T f_l + A_r Q^T f_r] of length L = N + C is
+// periodic; its derivative is the circulant operator F^-1 diag(i w_k) F.
+// Because every circulant commutes with the cyclic first difference
+// (Delta x)[n] = x[n+1] - x[n], whose symbol is exp(2 pi i k / L) - 1, the
+// engine transforms Delta ext and multiplies by i w_k / (exp(2 pi i k/L) - 1)
+// instead: the same operator in exact arithmetic, but FP32 rounding in the
+// forward FFT now scales with |Delta ext| ~ h |f'| instead of |f|, and the
+// multiplier is bounded by pi / (2 h) at every k instead of growing to
+// pi / h, so the derivative keeps a relative accuracy of a few ulp.
+//   1. differences: Delta ext[n] for n < N-1 in FP32 (exact for close
+//      neighbours), the C + 1 differences that involve the tail in FP64 from
+//      the differenced continuation rows (matrix entries reach 1e4 while the
+//      tail is of the size of the data);
+//   2. forward FFT of length L: in-place mixed-radix decimation in
 //      frequency, output in digit-reversed order;
-//   3. multiplication by i k 2 pi / beta / L (table kmul, indexed by the
-//      digit-reversed position, Nyquist zeroed);
+//   3. complex multiplier (table kmul, indexed by the digit-reversed
+//      position; k = 0 and the Nyquist zeroed);
 //   4. inverse FFT: in-place decimation in time from digit-reversed input to
 //      natural order.
 // Positions 0..N-1 then hold the derivatives (re of line A, im of line B).
+// The transpose applies Delta^T to the zero-padded cotangent, the conjugate
+// multipliers and the transposed continuation (fold of the tail).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -30,8 +42,9 @@ struct PlanDev {
   int N, L, C, nst;
   int rad[kMaxStages];
   int tw;        // offset of the twiddle table (float2) for this L
-  int km;        // offset of the multiplier table (float) for this (N, L)
+  int km;        // offset of the multiplier table (float2) for this (N, L)
   int aq;        // offset of A_r Q^T (double) for this C, C*d entries
+  int dq;        // offset of the differenced rows (double), (C+1)*2d entries
   int nlines;    // lines along this direction
   int n1, n2;    // patch shape
   int patch;     // patch index
@@ -49,7 +62,7 @@ struct TileDev {
 // Per-thread view of a tile in LDS.  Layout of the dynamic LDS block:
 //   z   [L * ld] float2   the lines, z[pos * ld + c]
 //   tw  [L]      float2   exp(-2 pi i n / L)
-//   km  [L]      float    derivative multipliers by digit-reversed position
+//   km  [L]      float2   derivative multipliers by digit-reversed position
 // Thread t works on line c = t % nl and on butterflies t / nl, t / nl + BS,
 // ... of every stage (BS = blockDim / nl), so consecutive lanes touch
 // consecutive lines (conflict-free LDS rows) and share their twiddle
@@ -57,22 +70,22 @@ struct TileDev {
 struct LineCtx {
   float2* z;
   const float2* tw;
-  const float* km;
+  const float2* km;
   int ld, nl, c, b0, BS;
   bool active;
 };
 
 __device__ __forceinline__ size_t tile_lds_bytes(int L, int ld) {
-  return (size_t)L * ld * sizeof(float2) + (size_t)L * (sizeof(float2) + sizeof(float));
+  return (size_t)L * ld * sizeof(float2) + (size_t)L * 2 * sizeof(float2);
 }
 
 // Copy the plan's twiddles and multipliers into LDS; the caller syncs.
 __device__ __forceinline__ LineCtx line_setup(float2* lds, const TileDev& T, const PlanDev& P,
-                                              const float2* __restrict__ twg, const float* __restrict__ kmg) {
+                                              const float2* __restrict__ twg, const float2* __restrict__ kmg) {
   LineCtx X;
   X.z = lds;
   float2* tw = lds + (size_t)P.L * T.ld;
-  float* km = reinterpret_cast<float*>(tw + P.L);
+  float2* km = tw + P.L;
   for (int i = threadIdx.x; i < P.L; i += blockDim.x) {
     tw[i] = twg[P.tw + i];
     km[i] = kmg[P.km + i];
@@ -114,9 +127,10 @@ __device__ __forceinline__ void for_elems(int N, int nl, F&& f) {
 // One radix-R stage.  Forward (DIF): block of M points, m = M/R, butterfly j
 // reads x_t = z[base + j + t m], y = DFT_R(x), y_q *= w_M^(j q), stores back.
 // Inverse (DIT): the exact reverse with conjugate twiddles.  MUL (last
-// forward stage, M = R): multiply the outputs by i * mulsign * km[pos].
-template <int R, bool INV, bool MUL>
-__device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M, float mulsign) {
+// forward stage, M = R): multiply the outputs by km[pos] (CONJ: by its
+// conjugate, the transposed operator).
+template <int R, bool INV, bool MUL, bool CONJ>
+__device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
   if (!X.active) return;
   const int m = M / R;
   const int stride = L / M;
@@ -135,10 +149,7 @@ __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M, float 
       Dft<R, false>::run(x);
       if (MUL) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const float k = mulsign * X.km[base + q];
-          x[q] = make_float2(-k * x[q].y, k * x[q].x);
-        }
+        for (int q = 0; q < R; ++q) x[q] = CONJ ? cmulc(x[q], X.km[base + q]) : cmul(x[q], X.km[base + q]);
       } else if (j) {
 #pragma unroll
         for (int q = 1; q < R; ++q) x[q] = cmul(x[q], X.tw[stride * j * q]);
@@ -161,17 +172,17 @@ __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M, float 
   }
 }
 
-template <bool INV, bool MUL>
-__device__ __forceinline__ void fft_dispatch(int R, const LineCtx& X, int L, int M, float mulsign) {
+template <bool INV, bool MUL, bool CONJ>
+__device__ __forceinline__ void fft_dispatch(int R, const LineCtx& X, int L, int M) {
   switch (R) {
-    case 2: fft_stage<2, INV, MUL>(X, L, M, mulsign); break;
-    case 3: fft_stage<3, INV, MUL>(X, L, M, mulsign); break;
-    case 4: fft_stage<4, INV, MUL>(X, L, M, mulsign); break;
-    case 5: fft_stage<5, INV, MUL>(X, L, M, mulsign); break;
-    case 7: fft_stage<7, INV, MUL>(X, L, M, mulsign); break;
-    case 8: fft_stage<8, INV, MUL>(X, L, M, mulsign); break;
-    case 11: fft_stage<11, INV, MUL>(X, L, M, mulsign); break;
-    case 13: fft_stage<13, INV, MUL>(X, L, M, mulsign); break;
+    case 2: fft_stage<2, INV, MUL, CONJ>(X, L, M); break;
+    case 3: fft_stage<3, INV, MUL, CONJ>(X, L, M); break;
+    case 4: fft_stage<4, INV, MUL, CONJ>(X, L, M); break;
+    case 5: fft_stage<5, INV, MUL, CONJ>(X, L, M); break;
+    case 7: fft_stage<7, INV, MUL, CONJ>(X, L, M); break;
+    case 8: fft_stage<8, INV, MUL, CONJ>(X, L, M); break;
+    case 11: fft_stage<11, INV, MUL, CONJ>(X, L, M); break;
+    case 13: fft_stage<13, INV, MUL, CONJ>(X, L, M); break;
     default: break;
   }
 }
@@ -229,31 +240,117 @@ __device__ __forceinline__ void fold_tail(const LineCtx& X, const PlanDev& P, co
   }
 }
 
+// Delta ext in place (forward operator).  Positions 0..N-1 hold f; the
+// C + 1 differences that involve the tail (or, for a periodic plan, the
+// wrap f[0] - f[N-1]) come from the end samples, the N - 1 interior ones
+// from a walk over a contiguous chunk of the line per thread.  Phase 1 reads
+// every sample that another thread overwrites in phase 2 (the end samples,
+// the first sample after each chunk); positions N.. are free and written at
+// once.  Two barriers; every thread of the block must call this.
+__device__ __forceinline__ void difference_ext(const LineCtx& X, const PlanDev& P, const double* __restrict__ dq,
+                                               int d) {
+  const int N = P.N, C = P.C, ld = X.ld, c = X.c;
+  float2* __restrict__ z = X.z;
+  const int K = (N - 1 + X.BS - 1) / X.BS;
+  const int s0 = X.b0 * K;
+  const int e0 = min(s0 + K, N - 1);
+  float2 nxt = make_float2(0.f, 0.f), keep = make_float2(0.f, 0.f);
+  if (X.active) {
+    if (s0 < e0) nxt = z[e0 * ld + c];
+    if (P.periodic) {
+      if (X.b0 == 0) {
+        const float2 a = z[c], b = z[(N - 1) * ld + c];
+        keep = make_float2(a.x - b.x, a.y - b.y);
+      }
+    } else {
+      for (int r = X.b0; r <= C; r += X.BS) {
+        const double* q = dq + (size_t)r * 2 * d;
+        double sx = 0.0, sy = 0.0;
+        for (int j = 0; j < d; ++j) {
+          const float2 fr = z[(N - d + j) * ld + c];
+          const float2 fl = z[j * ld + c];
+          sx = fma(q[j], (double)fr.x, sx);
+          sy = fma(q[j], (double)fr.y, sy);
+          sx = fma(q[d + j], (double)fl.x, sx);
+          sy = fma(q[d + j], (double)fl.y, sy);
+        }
+        const float2 v = make_float2((float)sx, (float)sy);
+        if (r == 0)
+          keep = v;  // position N-1 is still read in this phase
+        else
+          z[(N - 1 + r) * ld + c] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (X.active) {
+    if (s0 < e0) {
+      float2 cur = z[s0 * ld + c];
+      for (int n = s0; n < e0; ++n) {
+        const float2 nx = (n + 1 < e0) ? z[(n + 1) * ld + c] : nxt;
+        z[n * ld + c] = make_float2(nx.x - cur.x, nx.y - cur.y);
+        cur = nx;
+      }
+    }
+    if (X.b0 == 0) z[(N - 1) * ld + c] = keep;
+  }
+  __syncthreads();
+}
+
+// Delta^T of the zero-padded cotangent in place (transposed operator):
+// (Delta^T x)[n] = x[n-1] - x[n], cyclic, with x = [y; 0].  Positions N.. are
+// written in phase 1 (y[N-1] at N, zeros after), the first N in phase 2 from
+// chunk walks that carry the sample before each chunk, read in phase 1.
+__device__ __forceinline__ void difference_adj(const LineCtx& X, const PlanDev& P) {
+  const int N = P.N, L = P.L, ld = X.ld, c = X.c;
+  float2* __restrict__ z = X.z;
+  const int K = (N + X.BS - 1) / X.BS;
+  const int s0 = X.b0 * K;
+  const int e0 = min(s0 + K, N);
+  float2 prv = make_float2(0.f, 0.f);
+  if (X.active) {
+    if (s0 < e0) {
+      if (s0 > 0)
+        prv = z[(s0 - 1) * ld + c];
+      else if (P.periodic)
+        prv = z[(N - 1) * ld + c];
+    }
+    if (!P.periodic) {
+      for (int n = N + X.b0; n < L; n += X.BS)
+        z[n * ld + c] = (n == N) ? z[(N - 1) * ld + c] : make_float2(0.f, 0.f);
+    }
+  }
+  __syncthreads();
+  if (X.active && s0 < e0) {
+    for (int n = s0; n < e0; ++n) {
+      const float2 cur = z[n * ld + c];
+      z[n * ld + c] = make_float2(prv.x - cur.x, prv.y - cur.y);
+      prv = cur;
+    }
+  }
+  __syncthreads();
+}
+
 // Derivative of the tile in place; the caller has filled positions 0..N-1
-// and synchronised.  ADJ = transpose (zero tail, -i k, fold).
+// and synchronised.  ADJ = transpose (Delta^T, conjugate multipliers, fold).
 template <bool ADJ>
 __device__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
-                                const double* __restrict__ aqp, int d) {
-  if (!P.periodic) {
-    if (!ADJ) {
-      fc_tail(X, P, aqp + P.aq, d);
-    } else if (X.active) {
-      for (int m = X.b0; m < P.C; m += X.BS) X.z[(P.N + m) * X.ld + X.c] = make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-  }
+                                const double* __restrict__ aqp, const double* __restrict__ dqp, int d) {
+  if (!ADJ)
+    difference_ext(X, P, dqp + P.dq, d);
+  else
+    difference_adj(X, P);
   // radices are read from the (uniform) plan in global memory: a private
   // array indexed by the stage counter would live in scratch
   const int* rad = Pg->rad;
   const int nst = P.nst;
-  const float sign = ADJ ? -1.f : 1.f;
   int M = P.L;
   for (int s = 0; s < nst; ++s) {
     const int R = rad[s];
     if (s == nst - 1)
-      fft_dispatch<false, true>(R, X, P.L, M, sign);
+      fft_dispatch<false, true, ADJ>(R, X, P.L, M);
     else
-      fft_dispatch<false, false>(R, X, P.L, M, sign);
+      fft_dispatch<false, false, ADJ>(R, X, P.L, M);
     M /= R;
     __syncthreads();
   }
@@ -261,7 +358,7 @@ __device__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg
   for (int s = nst - 1; s >= 0; --s) {
     const int R = rad[s];
     M *= R;
-    fft_dispatch<true, false>(R, X, P.L, M, sign);
+    fft_dispatch<true, false, ADJ>(R, X, P.L, M);
     __syncthreads();
   }
   if (ADJ && !P.periodic) {

@@ -11,8 +11,11 @@
 //    the Gram basis the same matrix factors as A_r Q^T; the Lagrange form
 //    needs no orthogonalisation.)  The fit is solved by Householder QR in
 //    IEEE binary128 (__float128), then rounded to double.
-//  * Mixed-radix factorisation of the extension length L = N + C and the
-//    FP32 twiddle table exp(-2 pi i n / L), computed in binary128.
+//  * The same rows differenced along the extension (the device derivative
+//    transforms the first differences of the extension, see engine.h).
+//  * Mixed-radix factorisation of the extension length L = N + C, the FP32
+//    twiddle table exp(-2 pi i n / L) and the derivative multipliers,
+//    computed in binary128.
 #include <quadmath.h>
 
 #include <cstdint>
@@ -35,10 +38,9 @@ void cis2pi(int64_t num, int64_t den, qf* c, qf* s) {
   *s = sinq(a);
 }
 
-}  // namespace
-
-extern "C" int fcsd_host_fc_matrix(int d, int C, double* out) {
-  if (d < 1 || d > 8 || C < 1 || C > 256 || !out) return 1;
+// A_r Q^T in binary128, C rows of d entries.
+int fc_matrix_q(int d, int C, std::vector<qf>& out) {
+  if (d < 1 || d > 8 || C < 1 || C > 256) return 1;
   const int P = 2 * (d + C);           // period in grid intervals
   const int ncol = 2 * kModes + 1;
   const int per = (d - 1) * kOversample + 1;
@@ -117,8 +119,52 @@ extern "C" int fcsd_host_fc_matrix(int d, int C, double* out) {
         cis2pi((int64_t)n * t, den, &cs, &sn);
         acc += X[(size_t)(2 * n - 1) * d + c] * cs + X[(size_t)(2 * n) * d + c] * sn;
       }
-      out[(size_t)mm * d + c] = (double)acc;
+      out[(size_t)mm * d + c] = acc;
     }
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int fcsd_host_fc_matrix(int d, int C, double* out) {
+  if (!out) return 1;
+  std::vector<qf> q((size_t)C * d > 0 ? (size_t)C * d : 1);
+  const int r = fc_matrix_q(d, C, q);
+  if (r) return r;
+  for (size_t i = 0; i < (size_t)C * d; ++i) out[i] = (double)q[i];
+  return 0;
+}
+
+// Differenced continuation rows.  With e_0 = f[N-1], e_{1+m} = tail[m]
+// (m < C) and e_{C+1} = f[0] (the periodic wrap), row r = 0..C holds the
+// coefficients of e_{r+1} - e_r on the 2d end samples: entries 0..d-1 act
+// on f[N-d+j], entries d..2d-1 on f[j].  Differences are taken in binary128
+// before rounding to double.
+extern "C" int fcsd_host_fc_dmatrix(int d, int C, double* out) {
+  if (!out) return 1;
+  std::vector<qf> q((size_t)C * d > 0 ? (size_t)C * d : 1);
+  const int rc = fc_matrix_q(d, C, q);
+  if (rc) return rc;
+  std::vector<qf> a(2 * d), b(2 * d);
+  auto row = [&](int rr, std::vector<qf>& v) {
+    for (auto& x : v) x = 0;
+    if (rr == 0) {
+      v[d - 1] = 1;
+    } else if (rr == C + 1) {
+      v[d] = 1;
+    } else {
+      const int m = rr - 1;
+      for (int j = 0; j < d; ++j) {
+        v[j] = q[(size_t)m * d + j];
+        v[d + j] = q[(size_t)(C - 1 - m) * d + (d - 1 - j)];
+      }
+    }
+  };
+  for (int r = 0; r <= C; ++r) {
+    row(r + 1, a);
+    row(r, b);
+    for (int k = 0; k < 2 * d; ++k) out[(size_t)r * 2 * d + k] = (double)(a[k] - b[k]);
   }
   return 0;
 }
@@ -165,9 +211,12 @@ extern "C" int fcsd_host_factor(int L, int* rad) {
 
 // Position -> signed wavenumber map of the in-place decimation-in-frequency
 // output: position p = sum_s q_s m_s (m_s = L / (r_0 ... r_s)) holds the
-// coefficient of frequency k = sum_s q_s (r_0 ... r_{s-1}).  Fills the
-// derivative multiplier 2 pi k (N-1) / L^2 (the FFT normalisation 1/L and
-// the period beta = L/(N-1) folded in); Nyquist of even L is zero.
+// coefficient of frequency k = sum_s q_s (r_0 ... r_{s-1}).  Fills, as
+// interleaved (re, im) pairs, the multiplier that turns the DFT of the
+// differenced extension into that of the derivative: i w_k / (exp(2 pi i k
+// / L) - 1) with w_k = 2 pi k (N-1) / L^2 (the FFT normalisation 1/L and
+// the period beta = L/(N-1) folded in); k = 0 and the Nyquist of even L are
+// zero.
 extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic) {
   for (int p = 0; p < L; ++p) {
     int rem = p, M = L;
@@ -183,7 +232,20 @@ extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out
     int64_t ks = (k <= L / 2) ? k : k - L;
     if (L % 2 == 0 && k == L / 2) ks = 0;
     // derivative w.r.t. q in [0, 1]: beta = L h, h = 1/(N-1); periodic mode h = 1/N, beta = 1
-    qf scale = periodic ? 2 * M_PIq / L : 2 * M_PIq * (N - 1) / ((qf)L * L);
-    out[p] = (float)(scale * (qf)ks);
+    const qf scale = periodic ? 2 * M_PIq / L : 2 * M_PIq * (N - 1) / ((qf)L * L);
+    const qf w = scale * (qf)ks;
+    // the engine transforms the differenced extension, whose DFT is
+    // (exp(2 pi i k / L) - 1) times that of the extension:
+    //   i w / (exp(i theta) - 1) = w exp(-i theta / 2) / (2 sin(theta / 2)),  theta = 2 pi k / L
+    qf re = 0, im = 0;
+    if (ks != 0) {
+      qf c, sn;
+      cis2pi(k, 2 * (int64_t)L, &c, &sn);
+      const qf a = w / (2 * sn);
+      re = a * c;
+      im = -a * sn;
+    }
+    out[2 * p] = (float)re;
+    out[2 * p + 1] = (float)im;
   }
 }

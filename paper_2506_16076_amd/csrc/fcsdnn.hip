@@ -18,6 +18,7 @@
 using namespace fcsd;
 
 extern "C" int fcsd_host_fc_matrix(int d, int C, double* out);
+extern "C" int fcsd_host_fc_dmatrix(int d, int C, double* out);
 extern "C" void fcsd_host_twiddles(int L, float* out);
 extern "C" int fcsd_host_factor(int L, int* rad);
 extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic);
@@ -67,8 +68,9 @@ struct fcsd_set {
   std::vector<fcsd_patch_desc> desc;
   DirPlan dir[2];
   float2* d_tw = nullptr;
-  float* d_km = nullptr;
+  float2* d_km = nullptr;
   double* d_aq = nullptr;
+  double* d_dq = nullptr;
   PatchDev* d_patches = nullptr;
   ChunkDev* d_chunks = nullptr;
   int nchunks = 0;
@@ -120,6 +122,7 @@ PassArgs base_args(const fcsd_set* s, int dir) {
   a.tw = s->d_tw;
   a.km = s->d_km;
   a.aq = s->d_aq;
+  a.dq = s->d_dq;
   a.d = s->d;
   a.plane = s->plane;
   return a;
@@ -316,7 +319,7 @@ void build_tiles(DirPlan& D, size_t budget) {
   D.lds = 0;
   for (size_t p = 0; p < D.plans.size(); ++p) {
     const PlanDev& P = D.plans[p];
-    const size_t tables = (size_t)P.L * (sizeof(float2) + sizeof(float));
+    const size_t tables = (size_t)P.L * 2 * sizeof(float2);
     int nlmax = budget > tables ? (int)((budget - tables) / (sizeof(float2) * (size_t)P.L)) - 1 : 1;
     nlmax = std::max(1, std::min(kMaxTile, nlmax));
     const int nt = (P.nlines + nlmax - 1) / nlmax;
@@ -363,9 +366,9 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   s->desc.assign(patches, patches + npatch);
   // pools
   std::vector<float2> tw;
-  std::vector<float> km;
-  std::vector<double> aq;
-  std::map<int, int> tw_of_L, aq_of_C;
+  std::vector<float2> km;
+  std::vector<double> aq, dq;
+  std::map<int, int> tw_of_L, aq_of_C, dq_of_C;
   std::map<std::tuple<int, int, int>, int> km_of;
   for (int dir = 1; dir <= 2; ++dir) {
     DirPlan& D = s->dir[dir - 1];
@@ -394,9 +397,9 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
       auto key = std::make_tuple(P.N, P.L, P.periodic);
       if (!km_of.count(key)) {
         km_of[key] = (int)km.size();
-        std::vector<float> t(P.L);
+        std::vector<float> t(2 * P.L);
         fcsd_host_kmul(P.N, P.L, P.nst, P.rad, t.data(), P.periodic);
-        km.insert(km.end(), t.begin(), t.end());
+        for (int n = 0; n < P.L; ++n) km.push_back(make_float2(t[2 * n], t[2 * n + 1]));
       }
       P.km = km_of[key];
       if (!P.periodic) {
@@ -406,8 +409,14 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
           if (fcsd_host_fc_matrix(d, P.C, m.data()) != 0)
             return fail(ctx, FCSD_EUNSUPPORTED, "continuation fit failed");
           aq.insert(aq.end(), m.begin(), m.end());
+          dq_of_C[P.C] = (int)dq.size();
+          std::vector<double> r((size_t)(P.C + 1) * 2 * d);
+          if (fcsd_host_fc_dmatrix(d, P.C, r.data()) != 0)
+            return fail(ctx, FCSD_EUNSUPPORTED, "continuation fit failed");
+          dq.insert(dq.end(), r.begin(), r.end());
         }
         P.aq = aq_of_C[P.C];
+        P.dq = dq_of_C[P.C];
       }
       D.plans.push_back(P);
       D.ext_off.push_back(eo);
@@ -467,12 +476,13 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   s->nlchunks = (int)lch.size();
   fcsd_status r;
   if ((r = upload(ctx, &s->d_tw, tw)) || (r = upload(ctx, &s->d_km, km)) || (r = upload(ctx, &s->d_aq, aq)) ||
+      (r = upload(ctx, &s->d_dq, dq)) ||
       (r = upload(ctx, &s->d_patches, pd)) || (r = upload(ctx, &s->d_chunks, ch)) ||
       (r = upload(ctx, &s->d_lats, lat)) || (r = upload(ctx, &s->d_lchunks, lch)))
     return r;
   if (aq.empty()) {  // keep a valid pointer for kernels
     std::vector<double> one(1, 0.0);
-    if ((r = upload(ctx, &s->d_aq, one))) return r;
+    if ((r = upload(ctx, &s->d_aq, one)) || (r = upload(ctx, &s->d_dq, one))) return r;
   }
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
@@ -499,6 +509,7 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_tw);
   hipFree(s->d_km);
   hipFree(s->d_aq);
+  hipFree(s->d_dq);
   hipFree(s->d_patches);
   hipFree(s->d_chunks);
   hipFree(s->d_lats);

@@ -22,8 +22,9 @@ struct PassArgs {
   const PlanDev* plans;
   const TileDev* tiles;
   const float2* tw;
-  const float* km;
+  const float2* km;
   const double* aq;
+  const double* dq;
   int d;
   long long plane;
   int nf;
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_fcdiff(PassArgs a) {
       z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
     });
     __syncthreads();
-    line_derivative<ADJ>(X, Pg, P, a.aq, a.d);
+    line_derivative<ADJ>(X, Pg, P, a.aq, a.dq, a.d);
     float* OA = a.out + (long long)f * a.plane;
     float* OB = a.out + (long long)(f + 1) * a.plane;
     for_elems<DIR>(N, nl, [&](int pos, int c) {
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_dev_diff(PassArgs a) {
       z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
     });
     __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.d);
+    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
     float* OA = a.out + (long long)f * a.plane;
     float* OB = a.out + (long long)(f + 1) * a.plane;
     for_elems<DIR>(N, nl, [&](int pos, int c) {
@@ -264,7 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_passB1(PassArgs a) {
       z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
     });
     __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.d);
+    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
     for_elems<2>(N, nl, [&](int pos, int c) {
       const long long g = gindex<2>(P, T, pos, c);
       float hx[2], hy[2];
@@ -310,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_passB2(PassArgs a) {
       z[pos * ld + c] = make_float2(A[g], B[g]);
     });
     __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.d);
+    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
     for_elems<2>(N, nl, [&](int pos, int c) {
       const long long g = gindex<2>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
@@ -336,7 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_passC(PassArgs a) {
       z[pos * ld + c] = make_float2(A[g], B[g]);
     });
     __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.d);
+    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
     const long long fo = (long long)comp * pl;
     for_elems<1>(N, nl, [&](int pos, int c) {
       const long long g = gindex<1>(P, T, pos, c);

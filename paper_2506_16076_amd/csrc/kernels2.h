@@ -673,7 +673,7 @@ __global__ void __launch_bounds__(kBlock) k_adjHb(PassArgs a, const float* rb, f
       z[pos * ld + c] = make_float2(a.metric[mx * pl + g] * r, a.metric[my * pl + g] * r);
     });
     __syncthreads();
-    line_derivative<true>(X, Pg, P, a.aq, a.d);
+    line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
     for_elems<DIR>(N, nl, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float2 v = z[pos * ld + c];

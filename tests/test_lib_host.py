@@ -71,11 +71,35 @@ def _twiddles(lib, n):
 
 
 def _kmul(lib, N, n, rad, periodic=0):
-    out = np.zeros(n, np.float32)
+    out = np.zeros(2 * n, np.float32)
     r = (ctypes.c_int * 8)(*rad)
     lib.fcsd_host_kmul(ctypes.c_int(N), ctypes.c_int(n), ctypes.c_int(len(rad)), r,
                        out.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(periodic))
-    return out
+    return out[0::2].astype(np.float64) + 1j * out[1::2]
+
+
+def _dmatrix(lib, d, C):
+    out = np.zeros((C + 1) * 2 * d)
+    assert lib.fcsd_host_fc_dmatrix(ctypes.c_int(d), ctypes.c_int(C), out.ctypes.data_as(ctypes.c_void_p)) == 0
+    return out.reshape(C + 1, 2 * d)
+
+
+@pytest.mark.parametrize("C", [27, 31, 45])
+def test_differenced_continuation_rows(L, C):
+    """Row r of the differenced table applied to the 2d end samples equals
+    ext[N+r] - ext[N-1+r] of the oracle's extension (ext[L] = ext[0])."""
+    lib = L.lib()
+    Dq = _dmatrix(lib, 5, C)
+    rng = np.random.default_rng(C)
+    F = synth.random_lines(rng, 3, 40)
+    ArQ = L.fc_matrix(5, C)
+    for f in F:
+        ext = fcgram.extend(f, ArQ)
+        N = len(f)
+        per = np.concatenate([ext, ext[:1]])
+        want = per[N:] - per[N - 1:-1]
+        got = Dq @ np.concatenate([f[N - 5:], f[:5]])
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(ext).max() * np.abs(ArQ).max()
 
 
 def emulate_engine(x, rad, tw, inverse):
@@ -116,33 +140,62 @@ def test_digit_reversed_engine_and_multiplier_table(L, Lx, N):
     x = rng.standard_normal(Lx) + 1j * rng.standard_normal(Lx)
     X = np.fft.fft(x)
     Y = emulate_engine(x, rad, np.exp(-2j * np.pi * np.arange(Lx) / Lx), False)
-    km = _kmul(lib, N, Lx, rad).astype(np.float64)
-    # recover the wavenumber of every position from the multiplier table
+    km = _kmul(lib, N, Lx, rad)
+    # the multiplier is i w_k / (exp(2 pi i k / L) - 1), w_k = 2 pi k (N-1) / L^2:
+    # recover the wavenumber of every position from it
     scale = 2 * np.pi * (N - 1) / Lx ** 2
-    k = np.rint(km / scale).astype(int)
-    kk = np.where(k < 0, k + Lx, k)
+    kk = np.zeros(Lx, int)
+    for p in range(Lx):
+        if km[p] == 0:
+            continue
+        cand = np.arange(1, Lx)
+        ks = np.where(cand <= Lx // 2, cand, cand - Lx)
+        sym = 1j * scale * ks / (np.exp(2j * np.pi * cand / Lx) - 1)
+        i = int(np.argmin(np.abs(sym - km[p])))
+        assert abs(sym[i] - km[p]) <= 1e-6 * abs(sym[i])
+        kk[p] = cand[i]
+    zero = km == 0
     if Lx % 2 == 0:
-        assert np.sum(k == 0) == 2          # k = 0 and the zeroed Nyquist
-        ok = ~((k == 0) & (np.abs(Y - X[0]) > 1e-9 * np.abs(X).max()))
+        assert zero.sum() == 2          # k = 0 and the zeroed Nyquist
     else:
-        ok = np.ones(Lx, bool)
-        assert sorted(kk) == list(range(Lx))
+        assert zero.sum() == 1 and sorted(kk[~zero]) == list(range(1, Lx))
+    ok = ~zero
     assert np.abs(Y[ok] - X[kk[ok]]).max() <= 1e-10 * np.abs(X).max()
     # the inverse pass returns L x in natural order
     back = emulate_engine(Y, rad, np.exp(-2j * np.pi * np.arange(Lx) / Lx), True)
     assert np.abs(back / Lx - x).max() <= 1e-12 * np.abs(x).max()
-    # derivative through the emulated engine equals the oracle's FC derivative
+    # derivative through the emulated engine (differenced extension, complex
+    # multipliers) equals the oracle's FC derivative, and the transposed
+    # sequence (Delta^T, conjugate multipliers, fold) its transpose
     if Lx > N:
         C = Lx - N
         F = synth.random_lines(rng, 2, N)
         ArQ = L.fc_matrix(5, C)
-        ext = fcgram.extend(F[0] + 1j * F[1], ArQ)
-        Z = emulate_engine(ext, rad, tw, False)
-        Z = 1j * km * Z
-        d = emulate_engine(Z, rad, tw, True)[:N]
+        Dq = _dmatrix(lib, 5, C)
+        f = F[0] + 1j * F[1]
+        dz = np.concatenate([f[1:] - f[:-1], Dq @ np.concatenate([f[N - 5:], f[:5]])])
+        Z = emulate_engine(dz, rad, tw, False)
+        d = emulate_engine(km * Z, rad, tw, True)[:N]
         want = fcgram.diff_lines(F, 5, C)
-        assert np.abs(d.real - want[0]).max() <= 2e-5 * np.abs(want[0]).max()
-        assert np.abs(d.imag - want[1]).max() <= 2e-5 * np.abs(want[1]).max()
+        assert np.abs(d.real - want[0]).max() <= 1e-5 * np.abs(want[0]).max()
+        assert np.abs(d.imag - want[1]).max() <= 1e-5 * np.abs(want[1]).max()
+        # the transpose amplifies table rounding by |A_r Q^T| ~ 1e4 at the
+        # folded samples: check the sequence with exact tables
+        ks = np.where(kk <= Lx // 2, kk, kk - Lx)
+        with np.errstate(all="ignore"):
+            km_ex = np.where(zero, 0, 1j * scale * ks / (np.exp(2j * np.pi * kk / Lx) - 1))
+        tw_ex = np.exp(-2j * np.pi * np.arange(Lx) / Lx)
+        y = synth.random_lines(rng, 2, N)
+        yz = np.concatenate([y[0] + 1j * y[1], np.zeros(C)])
+        dty = np.roll(yz, 1) - yz
+        t = emulate_engine(np.conj(km_ex) * emulate_engine(dty, rad, tw_ex, False), rad, tw_ex, True)
+        want_adj = fcgram.diff_lines_adj(y, 5, C)
+        got = t[:N].copy()
+        tail = t[N:]
+        got[N - 5:] += ArQ.T @ tail
+        got[:5] += fcgram.left_matrix(ArQ).T @ tail
+        assert np.abs(got.real - want_adj[0]).max() <= 1e-9 * np.abs(want_adj[0]).max()
+        assert np.abs(got.imag - want_adj[1]).max() <= 1e-9 * np.abs(want_adj[1]).max()
 
 
 def test_patch_validation(L):
