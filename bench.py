@@ -14,9 +14,17 @@ achieved algorithmic bandwidth against the HBM peak (HIP events around
 repeated launches of that pass on the library's stream) and the FP64 oracle
 timed on a bounded sample of the same workload on the host CPU.
 
+HBM traffic of the dominant kernel comes from rocprofv3 FETCH_SIZE and
+WRITE_SIZE counter runs of this script (recorded in profiles/traffic.txt
+together with a digest of the kernel sources; reported as null when the
+sources have changed since).  --copy-calib adds a plain device copy of known
+size to the run, whose counter readings give the scale factor.
+
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--no-per-patch] [--copy-calib]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +36,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["engine.h", "kernels.h", "kernels2.h", "radix.h", "radix_gen.h", "fcsdnn.hip"]
+COPY_MIB = 256
+
+
+def source_digest():
+    """sha256 over the device sources, to tie counter readings to a build."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2506_16076_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, npts):
+    """HBM bytes per launch of `kernel` from profiles/traffic.txt (lines
+    key=value), scaled by the copy-kernel factor; None if absent or stale."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("#") or "=" not in line:
+                continue
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("source_digest") != source_digest() or rec.get("kernel") != kernel or \
+            int(rec.get("points", -1)) != npts:
+        return None
+    fetch = float(rec["fetch_kib"]) * 1024 / float(rec["copy_fetch_factor"])
+    write = float(rec["write_kib"]) * 1024 / float(rec["copy_write_factor"])
+    return fetch + write
+
+
+PASS_KERNEL = {"A": "k_dev_diff<1>", "B1": "k_passB1", "B2": "k_passB2", "C": "k_passC"}
 
 
 def pass_bytes(stage):
@@ -88,6 +132,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--npatch", type=int, default=200)
+    ap.add_argument("--no-per-patch", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -112,8 +158,13 @@ def main():
     u = t(cfg.u0)
     metric = t(ps.metric)
     W = {k: t(v) for k, v in cfg.mlp.items()}
-    st = api.Stepper(s, u, metric, cfg.ref, W=W)
     npts = ps.npoints
+    # schedule: autotuned tile split and launch order (outside the timed region)
+    from paper_2506_16076_amd import autotune
+    mu0 = torch.full((ps.plane,), 1e-3, device=dev)
+    tuning = autotune.autotune(s, u, metric, mu0, cfg.ref, 1.4)
+    print("autotune:", json.dumps(tuning), file=sys.stderr, flush=True)
+    st = api.Stepper(s, u, metric, cfg.ref, W=W)
 
     # ---------------- full step, graph replay
     for _ in range(args.warmup):
@@ -161,7 +212,7 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     ms_batched = time_stages(False, 3)
-    ms_pp = time_stages(True, 2)
+    ms_pp = None if args.no_per_patch else time_stages(True, 2)
 
     # ---------------- per-pass timing (dominant kernel)
     passes = {}
@@ -184,6 +235,16 @@ def main():
     dom = max(passes, key=passes.get)
     achieved = pb[dom] * npts / (passes[dom] / 1e3) / 1e9
     stage_bytes = sum(pb.values())
+    traffic = recorded_traffic(PASS_KERNEL[dom], npts)
+
+    if args.copy_calib:
+        # plain copy of known size for the counter scale factor: reads and
+        # writes COPY_MIB MiB once per launch
+        x = torch.ones(COPY_MIB * 2 ** 18, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
 
     out = {
         "metric": "grid-pt RK-stages/s fwd & adjoint, batched vs per-patch, % HBM peak",
@@ -202,11 +263,12 @@ def main():
                                "network classifier + smooth AV every step, SSPRK(5,4), batched hipGraph step",
                    "points": npts, "patches": ps.npatch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"pass {dom}",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": PASS_KERNEL[dom],
                      "bytes_per_point": pb[dom], "ms": passes[dom]},
-        "stage_ms": {"batched": ms_batched / 5, "per_patch": ms_pp / 5,
-                     "batched_over_per_patch": ms_pp / ms_batched},
+        "stage_ms": {"batched": ms_batched / 5, "per_patch": None if ms_pp is None else ms_pp / 5,
+                     "batched_over_per_patch": None if ms_pp is None else ms_pp / ms_batched},
         "pass_ms": passes,
+        "schedule": {k: v for k, v in tuning.items() if k != "table"},
         "stage_bytes_per_point": stage_bytes,
         "stage_effective_GBs": stage_bytes * npts / (ms_batched / 5 / 1e3) / 1e9,
         "wall_s": wall,

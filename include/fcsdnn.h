@@ -95,12 +95,21 @@ fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_patch_desc* pa
                             int d, int64_t plane, int ring_sectors, int ring_shells,
                             fcsd_set** out);
 fcsd_status fcsd_set_destroy(fcsd_set* set);
-/* Re-split the line tiles of a set for a workgroup LDS budget in bytes
- * (8 KB .. 160 KB; default 64 KB or the FCSD_LDS_BUDGET environment
- * variable at creation).  Smaller budgets mean fewer lines per tile and
- * more workgroups per compute unit.  Synchronises the context's stream and
- * drops captured step graphs.  Used by the autotuner. */
-fcsd_status fcsd_set_tune(fcsd_set* set, int lds_budget_bytes);
+/* Launch order of the batched line tiles. */
+enum {
+  FCSD_ORDER_LPT = 0, /* longest tile first over all patches */
+  FCSD_ORDER_XCD = 1  /* whole patches dealt to the 8 dies (one L2 each),
+                         balanced by work; the default */
+};
+/* Re-split the line tiles of a set: workgroup LDS budgets in bytes for the
+ * q1-line passes and the q2-line passes (8 KB .. 160 KB each; default 64 KB
+ * or the FCSD_LDS_BUDGET environment variable at creation) and the launch
+ * order.  Smaller budgets mean fewer lines per tile and more workgroups per
+ * compute unit; wider q2 tiles read longer contiguous row segments.
+ * Synchronises the context's stream and drops captured step graphs.
+ * Returns FCSD_EINVAL for an out-of-range budget or order.  Used by the
+ * autotuner. */
+fcsd_status fcsd_set_tune(fcsd_set* set, int lds_budget_q1, int lds_budget_q2, int order);
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
 enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3 };

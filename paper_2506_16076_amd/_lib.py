@@ -64,7 +64,7 @@ def lib():
             "fcsd_ctx_sync": [vp],
             "fcsd_set_create": [vp, i32, P(PatchDesc), i32, i64, i32, i32, P(vp)],
             "fcsd_set_destroy": [vp],
-            "fcsd_set_tune": [vp, i32],
+            "fcsd_set_tune": [vp, i32, i32, i32],
             "fcsd_workspace_size": [vp, i32, P(sz)],
             "fcsd_ext_size": [vp, i32, P(i64)],
             "fc_continue": [vp, vp, i32, i32, vp, i64, vp, i64],

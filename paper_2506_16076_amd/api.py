@@ -91,8 +91,16 @@ class PatchSet:
             self._ws[op] = torch.empty(n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
         return self._ws[op]
 
-    def tune(self, lds_budget_bytes: int):
-        self.ctx.check(lib().fcsd_set_tune(self.h, int(lds_budget_bytes)), "fcsd_set_tune")
+    ORDER_LPT, ORDER_XCD = 0, 1
+
+    def tune(self, lds_budget_q1: int, lds_budget_q2: int = None, order: int = 1):
+        """Tile split (LDS budget per workgroup for q1-line and q2-line passes)
+        and launch order (ORDER_LPT or ORDER_XCD)."""
+        if lds_budget_q2 is None:
+            lds_budget_q2 = lds_budget_q1
+        self.ctx.check(lib().fcsd_set_tune(self.h, int(lds_budget_q1), int(lds_budget_q2), int(order)),
+                       "fcsd_set_tune")
+        self.tuning = (int(lds_budget_q1), int(lds_budget_q2), int(order))
 
     def ext_size(self, direction: int) -> int:
         v = ctypes.c_int64()

@@ -45,7 +45,7 @@ namespace {
 
 struct DirPlan {
   std::vector<PlanDev> plans;             // one per patch
-  std::vector<TileDev> tiles;             // LPT order
+  std::vector<TileDev> tiles;             // launch order (LPT or XCD-grouped)
   std::vector<TileDev> tiles_by_patch;    // patch-contiguous
   std::vector<int> patch_begin;           // npatch + 1
   std::vector<size_t> patch_lds;          // per patch
@@ -82,7 +82,8 @@ struct fcsd_set {
   int annulus = 0;
   AnnulusDev an{};
   std::vector<GraphEntry> graphs;
-  size_t lds_budget = 0;
+  size_t lds_budget[2] = {0, 0};
+  int tile_order = FCSD_ORDER_XCD;
 };
 
 namespace {
@@ -312,11 +313,16 @@ size_t default_lds_budget() {
 // Split every patch's lines into tiles that fit `budget` bytes of LDS
 // (lines + twiddle and multiplier tables), balanced per patch, and order the
 // batched list longest-first.
-void build_tiles(DirPlan& D, size_t budget) {
+// Workgroups of a launch go to the accelerator dies (XCDs, each with its own
+// L2) round-robin by workgroup index.
+constexpr int kXcd = 8;
+
+void build_tiles(DirPlan& D, size_t budget, int order) {
   D.tiles_by_patch.clear();
   D.patch_begin.assign(1, 0);
   D.patch_lds.clear();
   D.lds = 0;
+  std::vector<long long> pcost;
   for (size_t p = 0; p < D.plans.size(); ++p) {
     const PlanDev& P = D.plans[p];
     const size_t tables = (size_t)P.L * 2 * sizeof(float2);
@@ -325,6 +331,7 @@ void build_tiles(DirPlan& D, size_t budget) {
     const int nt = (P.nlines + nlmax - 1) / nlmax;
     const int nl = (P.nlines + nt - 1) / nt;
     size_t plds = 0;
+    long long cost = 0;
     for (int t = 0; t < nt; ++t) {
       TileDev T;
       T.plan = (int)p;
@@ -334,16 +341,48 @@ void build_tiles(DirPlan& D, size_t budget) {
       T.ld = T.nl | 1;
       D.tiles_by_patch.push_back(T);
       plds = std::max(plds, (size_t)P.L * T.ld * sizeof(float2) + tables);
+      cost += (long long)P.L * T.nl;
     }
     D.patch_begin.push_back((int)D.tiles_by_patch.size());
     D.patch_lds.push_back(plds);
     D.lds = std::max(D.lds, plds);
+    pcost.push_back(cost);
   }
-  D.tiles = D.tiles_by_patch;
-  std::stable_sort(D.tiles.begin(), D.tiles.end(), [&](const TileDev& a, const TileDev& b) {
-    const PlanDev &pa = D.plans[a.plan], &pb = D.plans[b.plan];
-    return (long long)pa.L * a.nl > (long long)pb.L * b.nl;
-  });
+  if (order == FCSD_ORDER_LPT) {
+    // longest tile first over all patches
+    D.tiles = D.tiles_by_patch;
+    std::stable_sort(D.tiles.begin(), D.tiles.end(), [&](const TileDev& a, const TileDev& b) {
+      const PlanDev &pa = D.plans[a.plan], &pb = D.plans[b.plan];
+      return (long long)pa.L * a.nl > (long long)pb.L * b.nl;
+    });
+    return;
+  }
+  // XCD-grouped: whole patches are dealt to the dies by longest-first
+  // greedy balancing of their work, so that the tiles of one patch, which
+  // share cache lines at their column edges (q2 lines) and metric rows, run
+  // on one L2.  Slot b of the launch belongs to die b % kXcd; dies with
+  // fewer tiles get empty tiles (nl = 0, the kernels return at once).
+  const int np = (int)D.plans.size();
+  std::vector<int> porder(np);
+  for (int p = 0; p < np; ++p) porder[p] = p;
+  std::stable_sort(porder.begin(), porder.end(), [&](int a, int b) { return pcost[a] > pcost[b]; });
+  std::vector<long long> load(kXcd, 0);
+  std::vector<std::vector<TileDev>> lst(kXcd);
+  for (int p : porder) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += pcost[p];
+    for (int t = D.patch_begin[p]; t < D.patch_begin[p + 1]; ++t) lst[x].push_back(D.tiles_by_patch[t]);
+  }
+  size_t mx = 0;
+  for (auto& l : lst) mx = std::max(mx, l.size());
+  TileDev empty;
+  empty.plan = 0;
+  empty.line0 = 0;
+  empty.nl = 0;
+  empty.ld = 1;
+  D.tiles.assign(mx * kXcd, empty);
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t k = 0; k < lst[x].size(); ++k) D.tiles[k * kXcd + x] = lst[x][k];
 }
 
 }  // namespace
@@ -424,8 +463,8 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
     }
     D.ext_plane = eo;
   }
-  s->lds_budget = default_lds_budget();
-  for (int dir = 0; dir < 2; ++dir) build_tiles(s->dir[dir], s->lds_budget);
+  s->lds_budget[0] = s->lds_budget[1] = default_lds_budget();
+  for (int dir = 0; dir < 2; ++dir) build_tiles(s->dir[dir], s->lds_budget[dir], s->tile_order);
   // per-patch descriptors and point chunks
   std::vector<PatchDev> pd;
   std::vector<ChunkDev> ch;
@@ -518,19 +557,26 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   return FCSD_OK;
 }
 
-extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, int lds_budget_bytes) {
+extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, int lds_budget_q1, int lds_budget_q2, int order) {
   if (!s) return FCSD_EINVAL;
   fcsd_ctx* ctx = s->ctx;
-  if (lds_budget_bytes < 8192 || lds_budget_bytes > 160 * 1024)
-    return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget must be in [8 KB, 160 KB]");
+  const int bud[2] = {lds_budget_q1, lds_budget_q2};
+  for (int b : bud)
+    if (b < 8192 || b > 160 * 1024) return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget must be in [8 KB, 160 KB]");
+  if (order != FCSD_ORDER_LPT && order != FCSD_ORDER_XCD) return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: bad order");
+  int maxlds = 0;
+  HIPCHK(ctx, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+  for (int b : bud)
+    if (b > maxlds) return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget above the device's LDS per workgroup");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& g : s->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   s->graphs.clear();
-  s->lds_budget = (size_t)lds_budget_bytes;
+  s->tile_order = order;
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
-    build_tiles(D, s->lds_budget);
+    s->lds_budget[dir] = (size_t)bud[dir];
+    build_tiles(D, s->lds_budget[dir], order);
     (void)hipFree(D.d_tiles);
     (void)hipFree(D.d_tiles_bp);
     fcsd_status r;

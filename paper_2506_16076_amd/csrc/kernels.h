@@ -105,6 +105,7 @@ extern __shared__ float2 lds_z[];
 // tile prologue common to every line kernel: tile, plan, LDS tables
 #define FCSD_TILE_BEGIN(a)                                                   \
   const TileDev T = (a).tiles[blockIdx.x];                                   \
+  if (T.nl == 0) return; /* padding slot of the launch order */              \
   const PlanDev P = (a).plans[T.plan];                                       \
   const PlanDev* Pg = (a).plans + T.plan;                                    \
   const LineCtx X = line_setup(lds_z, T, P, (a).tw, (a).km);                 \

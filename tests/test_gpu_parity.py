@@ -447,3 +447,44 @@ def test_viscosity_reverse_mode(env):
     say("viscosity adjoint", err)
     assert np.all(err < 1e-5)
     s.close()
+
+
+# ------------------------------------------------------------------ schedules
+
+def test_tiling_and_order_do_not_change_results(env):
+    """Every line is transformed by the same arithmetic whatever its tile and
+    launch slot: the right-hand side is bit-identical across LDS budgets and
+    launch orders."""
+    api, ctx, torch = env
+    ps, u, mu, ref = rhs_case("uneven")
+    s = api.PatchSet.from_layout(ctx, ps)
+    metric = dev(torch, ps.metric)
+    ud, mud = dev(torch, u), dev(torch, mu)
+    outs = []
+    for q1, q2, order in [(65536, 65536, 1), (16384, 131072, 0), (32768, 24576, 1), (98304, 16384, 0)]:
+        say("tiling", q1, q2, order)
+        s.tune(q1, q2, order)
+        rhs = torch.zeros(4 * ps.plane, device="cuda:0")
+        api.fcsd_rhs(s, ud, metric, mud, ref, G, rhs)
+        outs.append(host(rhs))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    s.close()
+
+
+def test_autotuner_picks_a_schedule(env):
+    from paper_2506_16076_amd import autotune
+    api, ctx, torch = env
+    ps, u, mu, ref = rhs_case("uneven")
+    s = api.PatchSet.from_layout(ctx, ps)
+    metric = dev(torch, ps.metric)
+    ud, mud = dev(torch, u), dev(torch, mu)
+    res = autotune.autotune(s, ud, metric, mud, ref, G, budgets=(16384, 32768, 65536), reps=1)
+    say("autotune", {k: v for k, v in res.items() if k != "table"})
+    assert res["q1_budget"] in (16384, 32768, 65536) and res["q2_budget"] in (16384, 32768, 65536)
+    assert s.tuning == (res["q1_budget"], res["q2_budget"], 1 if res["order"] == "xcd" else 0)
+    rhs = torch.zeros(4 * ps.plane, device="cuda:0")
+    api.fcsd_rhs(s, ud, metric, mud, ref, G, rhs)
+    want = euler.full_rhs(u.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G)
+    assert np.all(relerr_phys(ps, host(rhs), want) < RHS_TOL)
+    s.close()
