@@ -21,7 +21,7 @@ sources have changed since).  --copy-calib adds a plain device copy of known
 size to the run, whose counter readings give the scale factor.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--no-per-patch] [--copy-calib]
+                       [--no-per-patch] [--copy-calib] [--schedule auto|Q1,Q2,ORDER]
 """
 import argparse
 import hashlib
@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["engine.h", "kernels.h", "kernels2.h", "radix.h", "radix_gen.h", "fcsdnn.hip"]
-COPY_MIB = 256
+COPY_MIB = 1024
 
 
 def source_digest():
@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--npatch", type=int, default=200)
     ap.add_argument("--no-per-patch", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--schedule", default="auto",
+                    help="auto (autotuner) or Q1_BUDGET,Q2_BUDGET,lpt|xcd")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -160,10 +162,15 @@ def main():
     W = {k: t(v) for k, v in cfg.mlp.items()}
     npts = ps.npoints
     # schedule: autotuned tile split and launch order (outside the timed region)
-    from paper_2506_16076_amd import autotune
-    mu0 = torch.full((ps.plane,), 1e-3, device=dev)
-    tuning = autotune.autotune(s, u, metric, mu0, cfg.ref, 1.4)
-    print("autotune:", json.dumps(tuning), file=sys.stderr, flush=True)
+    if args.schedule == "auto":
+        from paper_2506_16076_amd import autotune
+        mu0 = torch.full((ps.plane,), 1e-3, device=dev)
+        tuning = autotune.autotune(s, u, metric, mu0, cfg.ref, 1.4)
+        print("autotune:", json.dumps(tuning), file=sys.stderr, flush=True)
+    else:
+        q1, q2, order = args.schedule.split(",")
+        s.tune(int(q1), int(q2), {"lpt": 0, "xcd": 1}[order])
+        tuning = {"q1_budget": int(q1), "q2_budget": int(q2), "order": order, "given": True}
     st = api.Stepper(s, u, metric, cfg.ref, W=W)
 
     # ---------------- full step, graph replay
@@ -214,37 +221,45 @@ def main():
     ms_batched = time_stages(False, 3)
     ms_pp = None if args.no_per_patch else time_stages(True, 2)
 
-    # ---------------- per-pass timing (dominant kernel)
-    passes = {}
-    for pid, name in enumerate(["A", "B1", "B2", "C"]):
-        def run_pass():
-            api.fcsd_stage_pass(s, pid, 1, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
-        # prerequisites so every pass reads defined data
-        for q in range(pid + 1):
-            api.fcsd_stage_pass(s, q, 1, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 5
-        e0.record(ctx.stream)
-        for _ in range(reps):
-            run_pass()
-        e1.record(ctx.stream)
-        torch.cuda.synchronize()
-        passes[name] = e0.elapsed_time(e1) / reps
-    pb = pass_bytes(1)
+    # ---------------- per-pass timing (dominant kernel), every pass at each
+    # of the five stages (pass C's register traffic depends on the stage)
+    names = ["A", "B1", "B2", "C"]
+    passes, pass_gb = {}, {}
+    for pid, name in enumerate(names):
+        tot_ms, tot_bytes = 0.0, 0.0
+        for stage in range(5):
+            # prerequisites so every pass reads defined data
+            for q in range(pid + 1):
+                api.fcsd_stage_pass(s, q, stage, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 4
+            e0.record(ctx.stream)
+            for _ in range(reps):
+                api.fcsd_stage_pass(s, pid, stage, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
+            e1.record(ctx.stream)
+            torch.cuda.synchronize()
+            tot_ms += e0.elapsed_time(e1) / reps
+            tot_bytes += pass_bytes(stage)[name] * npts
+        passes[name] = tot_ms / 5
+        pass_gb[name] = tot_bytes / 5 / 1e9
     dom = max(passes, key=passes.get)
-    achieved = pb[dom] * npts / (passes[dom] / 1e3) / 1e9
-    stage_bytes = sum(pb.values())
+    achieved = pass_gb[dom] / (passes[dom] / 1e3)
+    stage_bytes = sum(pass_gb.values()) * 1e9 / npts
     traffic = recorded_traffic(PASS_KERNEL[dom], npts)
 
     if args.copy_calib:
-        # plain copy of known size for the counter scale factor: reads and
-        # writes COPY_MIB MiB once per launch
+        # plain copy of known size for the counter scale factors: reads and
+        # writes COPY_MIB MiB once per launch, after a fill of another buffer
+        # of that size has evicted the source from the caches
         x = torch.ones(COPY_MIB * 2 ** 18, device=dev)
         y = torch.empty_like(x)
         for _ in range(3):
+            y.fill_(0.0)
+            torch.cuda.synchronize()
             y.copy_(x)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+        del x, y
 
     out = {
         "metric": "grid-pt RK-stages/s fwd & adjoint, batched vs per-patch, % HBM peak",
@@ -264,7 +279,9 @@ def main():
                    "points": npts, "patches": ps.npatch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": PASS_KERNEL[dom],
-                     "bytes_per_point": pb[dom], "ms": passes[dom]},
+                     "bytes_per_point": pass_gb[dom] * 1e9 / npts, "ms": passes[dom],
+                     "note": "achieved = algorithmic bytes of the kernel averaged over the five stages / "
+                             "its mean launch time (HIP events on the library stream)"},
         "stage_ms": {"batched": ms_batched / 5, "per_patch": None if ms_pp is None else ms_pp / 5,
                      "batched_over_per_patch": None if ms_pp is None else ms_pp / ms_batched},
         "pass_ms": passes,
