@@ -124,6 +124,48 @@ __device__ __forceinline__ void for_elems(int N, int nl, F&& f) {
   }
 }
 
+// Batched variant of for_elems for memory-latency-bound phases: pre(pos, c)
+// issues the loads of U consecutive elements of the thread, then post(pos,
+// c, value) consumes them.  pre runs unconditionally (elements past the end
+// read element (0, 0) of the tile and are dropped), so the loads are
+// straight-line code and all U are in flight together; pre should only
+// load, and leave arithmetic to post.
+template <int DIR, int U, class Pre, class Post>
+__device__ __forceinline__ void for_elems_b(int N, int nl, Pre&& pre, Post&& post) {
+  using T = decltype(pre(0, 0));
+  const int na = DIR == 1 ? N : nl;
+  const int nbb = DIR == 1 ? nl : N;
+  int a = threadIdx.x % na, b = threadIdx.x / na;
+  const int sa = blockDim.x % na, sb = blockDim.x / na;
+  while (b < nbb) {
+    T v[U];
+    int ia[U], ib[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ia[u] = a;
+      ib[u] = b;
+      const bool ok = b < nbb;
+      const int ca = ok ? a : 0, cb = ok ? b : 0;
+      v[u] = DIR == 1 ? pre(ca, cb) : pre(cb, ca);
+      a += sa;
+      b += sb;
+      if (a >= na) {
+        a -= na;
+        ++b;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ib[u] < nbb) {
+        if (DIR == 1)
+          post(ia[u], ib[u], v[u]);
+        else
+          post(ib[u], ia[u], v[u]);
+      }
+    }
+  }
+}
+
 // One radix-R stage.  Forward (DIF): block of M points, m = M/R, butterfly j
 // reads x_t = z[base + j + t m], y = DFT_R(x), y_q *= w_M^(j q), stores back.
 // Inverse (DIT): the exact reverse with conjugate twiddles.  MUL (last

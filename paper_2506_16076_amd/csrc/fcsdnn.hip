@@ -43,18 +43,25 @@ struct fcsd_ctx {
 
 namespace {
 
-struct DirPlan {
-  std::vector<PlanDev> plans;             // one per patch
+// Tiles of one direction for kernels that hold `fields` complex lines per
+// grid line in LDS (1, or 2 for the H pass, which transforms all four state
+// components at once).
+struct TileSet {
   std::vector<TileDev> tiles;             // launch order (LPT or XCD-grouped)
   std::vector<TileDev> tiles_by_patch;    // patch-contiguous
   std::vector<int> patch_begin;           // npatch + 1
   std::vector<size_t> patch_lds;          // per patch
-  std::vector<long long> ext_off;         // per plan
-  long long ext_plane = 0;
   size_t lds = 0;
-  PlanDev* d_plans = nullptr;
   TileDev* d_tiles = nullptr;
   TileDev* d_tiles_bp = nullptr;
+};
+
+struct DirPlan {
+  std::vector<PlanDev> plans;             // one per patch
+  TileSet ts[2];                          // one / two complex lines per grid line
+  std::vector<long long> ext_off;         // per plan
+  long long ext_plane = 0;
+  PlanDev* d_plans = nullptr;
   long long* d_ext_off = nullptr;
 };
 
@@ -119,7 +126,7 @@ PassArgs base_args(const fcsd_set* s, int dir) {
   PassArgs a;
   memset(&a, 0, sizeof(a));
   a.plans = s->dir[dir - 1].d_plans;
-  a.tiles = s->dir[dir - 1].d_tiles;
+  a.tiles = s->dir[dir - 1].ts[0].d_tiles;
   a.tw = s->d_tw;
   a.km = s->d_km;
   a.aq = s->d_aq;
@@ -143,8 +150,8 @@ unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock);
 
 // launch a line-engine kernel over the batched tile list or one patch's tiles
 template <class K>
-fcsd_status launch_lines(const fcsd_set* s, int dir, K kern, PassArgs a, int patch = -1) {
-  const DirPlan& D = s->dir[dir - 1];
+fcsd_status launch_lines(const fcsd_set* s, int dir, K kern, PassArgs a, int patch = -1, int fields = 1) {
+  const TileSet& D = s->dir[dir - 1].ts[fields - 1];
   unsigned grid;
   size_t lds;
   if (patch < 0) {
@@ -317,17 +324,18 @@ size_t default_lds_budget() {
 // L2) round-robin by workgroup index.
 constexpr int kXcd = 8;
 
-void build_tiles(DirPlan& D, size_t budget, int order) {
+void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget, int order, int fields) {
   D.tiles_by_patch.clear();
   D.patch_begin.assign(1, 0);
   D.patch_lds.clear();
   D.lds = 0;
   std::vector<long long> pcost;
-  for (size_t p = 0; p < D.plans.size(); ++p) {
-    const PlanDev& P = D.plans[p];
+  for (size_t p = 0; p < plans.size(); ++p) {
+    const PlanDev& P = plans[p];
     const size_t tables = (size_t)P.L * 2 * sizeof(float2);
     int nlmax = budget > tables ? (int)((budget - tables) / (sizeof(float2) * (size_t)P.L)) - 1 : 1;
-    nlmax = std::max(1, std::min(kMaxTile, nlmax));
+    nlmax = std::max(1, std::min(kMaxTile, nlmax)) / fields;
+    nlmax = std::max(1, nlmax);
     const int nt = (P.nlines + nlmax - 1) / nlmax;
     const int nl = (P.nlines + nt - 1) / nt;
     size_t plds = 0;
@@ -338,7 +346,7 @@ void build_tiles(DirPlan& D, size_t budget, int order) {
       T.line0 = t * nl;
       T.nl = std::min(nl, P.nlines - T.line0);
       if (T.nl <= 0) continue;
-      T.ld = T.nl | 1;
+      T.ld = (fields * T.nl) | 1;
       D.tiles_by_patch.push_back(T);
       plds = std::max(plds, (size_t)P.L * T.ld * sizeof(float2) + tables);
       cost += (long long)P.L * T.nl;
@@ -352,7 +360,7 @@ void build_tiles(DirPlan& D, size_t budget, int order) {
     // longest tile first over all patches
     D.tiles = D.tiles_by_patch;
     std::stable_sort(D.tiles.begin(), D.tiles.end(), [&](const TileDev& a, const TileDev& b) {
-      const PlanDev &pa = D.plans[a.plan], &pb = D.plans[b.plan];
+      const PlanDev &pa = plans[a.plan], &pb = plans[b.plan];
       return (long long)pa.L * a.nl > (long long)pb.L * b.nl;
     });
     return;
@@ -362,7 +370,7 @@ void build_tiles(DirPlan& D, size_t budget, int order) {
   // share cache lines at their column edges (q2 lines) and metric rows, run
   // on one L2.  Slot b of the launch belongs to die b % kXcd; dies with
   // fewer tiles get empty tiles (nl = 0, the kernels return at once).
-  const int np = (int)D.plans.size();
+  const int np = (int)plans.size();
   std::vector<int> porder(np);
   for (int p = 0; p < np; ++p) porder[p] = p;
   std::stable_sort(porder.begin(), porder.end(), [&](int a, int b) { return pcost[a] > pcost[b]; });
@@ -383,6 +391,21 @@ void build_tiles(DirPlan& D, size_t budget, int order) {
   D.tiles.assign(mx * kXcd, empty);
   for (int x = 0; x < kXcd; ++x)
     for (size_t k = 0; k < lst[x].size(); ++k) D.tiles[k * kXcd + x] = lst[x][k];
+}
+
+void build_tiles(DirPlan& D, size_t budget, int order) {
+  for (int f = 0; f < 2; ++f) build_tileset(D.plans, D.ts[f], budget, order, f + 1);
+}
+
+fcsd_status upload_tiles(fcsd_ctx* ctx, DirPlan& D) {
+  for (auto& t : D.ts) {
+    (void)hipFree(t.d_tiles);
+    (void)hipFree(t.d_tiles_bp);
+    t.d_tiles = t.d_tiles_bp = nullptr;
+    fcsd_status r;
+    if ((r = upload(ctx, &t.d_tiles, t.tiles)) || (r = upload(ctx, &t.d_tiles_bp, t.tiles_by_patch))) return r;
+  }
+  return FCSD_OK;
 }
 
 }  // namespace
@@ -525,8 +548,8 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   }
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
-    if ((r = upload(ctx, &D.d_plans, D.plans)) || (r = upload(ctx, &D.d_tiles, D.tiles)) ||
-        (r = upload(ctx, &D.d_tiles_bp, D.tiles_by_patch)) || (r = upload(ctx, &D.d_ext_off, D.ext_off)))
+    if ((r = upload(ctx, &D.d_plans, D.plans)) || (r = upload_tiles(ctx, D)) ||
+        (r = upload(ctx, &D.d_ext_off, D.ext_off)))
       return r;
   }
   HIPCHK(ctx, hipDeviceSynchronize());
@@ -540,10 +563,12 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   for (auto& g : s->graphs)
     if (g.exec) hipGraphExecDestroy(g.exec);
   for (int dir = 0; dir < 2; ++dir) {
-    hipFree(s->dir[dir].d_plans);
-    hipFree(s->dir[dir].d_tiles);
-    hipFree(s->dir[dir].d_tiles_bp);
-    hipFree(s->dir[dir].d_ext_off);
+    (void)hipFree(s->dir[dir].d_plans);
+    for (auto& t : s->dir[dir].ts) {
+      (void)hipFree(t.d_tiles);
+      (void)hipFree(t.d_tiles_bp);
+    }
+    (void)hipFree(s->dir[dir].d_ext_off);
   }
   hipFree(s->d_tw);
   hipFree(s->d_km);
@@ -577,10 +602,8 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, int lds_budget_q1, int lds_bud
     DirPlan& D = s->dir[dir];
     s->lds_budget[dir] = (size_t)bud[dir];
     build_tiles(D, s->lds_budget[dir], order);
-    (void)hipFree(D.d_tiles);
-    (void)hipFree(D.d_tiles_bp);
     fcsd_status r;
-    if ((r = upload(ctx, &D.d_tiles, D.tiles)) || (r = upload(ctx, &D.d_tiles_bp, D.tiles_by_patch))) return r;
+    if ((r = upload_tiles(ctx, D))) return r;
   }
   return FCSD_OK;
 }
@@ -707,7 +730,7 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
     b.plans = s->dir[1].d_plans;
     b.mode = flux;
     if (passes & 2u)
-      if ((st = launch_lines(s, 2, k_passB1, b, patch))) return st;
+      if ((st = launch_lines(s, 2, k_passB1, b, patch, 2))) return st;
   }
   PassArgs c = a;
   c.plans = s->dir[1].d_plans;
@@ -1116,8 +1139,8 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
     const DirPlan& D = s->dir[0];
     PassArgs b = a;
     b.plans = D.d_plans;
-    b.tiles = D.d_tiles;
-    hipLaunchKernelGGL(k_adjHb<1>, dim3((unsigned)D.tiles.size()), dim3(kBlock), D.lds, ctx->stream, b, rhs_bar, Hb,
+    b.tiles = D.ts[0].d_tiles;
+    hipLaunchKernelGGL(k_adjHb<1>, dim3((unsigned)D.ts[0].tiles.size()), dim3(kBlock), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
                        (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
     if ((st = launch_check(ctx, "adj C"))) return st;
   }
@@ -1125,8 +1148,8 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
     const DirPlan& D = s->dir[1];
     PassArgs b = a;
     b.plans = D.d_plans;
-    b.tiles = D.d_tiles;
-    hipLaunchKernelGGL(k_adjHb<2>, dim3((unsigned)D.tiles.size()), dim3(kBlock), D.lds, ctx->stream, b, rhs_bar, Hb,
+    b.tiles = D.ts[0].d_tiles;
+    hipLaunchKernelGGL(k_adjHb<2>, dim3((unsigned)D.ts[0].tiles.size()), dim3(kBlock), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
                        (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
     if ((st = launch_check(ctx, "adj B2"))) return st;
   }

@@ -55,6 +55,15 @@ struct PassArgs {
 };
 
 enum { MODE_SET = 0, MODE_ADD = 1, MODE_RK = 2 };
+
+// Line kernels: 256 threads, registers capped for five waves per SIMD (the
+// butterflies fit in ~96 VGPRs without spilling; five 32 KB tiles fill the LDS)
+#define FCSD_LINE_BOUNDS __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+
+// elements per thread whose loads are in flight together
+constexpr int kLoadBatch = 16;  // load phases (two floats each)
+constexpr int kEpiBatch = 8;    // epilogues (point inputs)
+constexpr int kEpiBatchH = 4;   // H epilogue (thirteen inputs per point)
 enum { FLUX_FULL = 0, FLUX_VISC = 1, FLUX_INVISCID = 2 };
 
 // SSPRK(5,4) Shu-Osher coefficients (five stages, fourth order)
@@ -119,16 +128,20 @@ extern __shared__ float2 lds_z[];
 
 // fc_diff / fc_diff_adj on nf fields, packed two per complex line.
 template <int DIR, bool ADJ>
-__global__ void __launch_bounds__(kBlock) k_fcdiff(PassArgs a) {
+__global__ void FCSD_LINE_BOUNDS k_fcdiff(PassArgs a) {
   FCSD_TILE_BEGIN(a)
   for (int f = 0; f < a.nf; f += 2) {
     const bool two = f + 1 < a.nf;
     const float* A = a.in + (long long)f * a.plane;
     const float* B = a.in + (long long)(f + 1) * a.plane;
-    for_elems<DIR>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<DIR>(P, T, pos, c);
-      z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
-    });
+    const float* Bs = two ? B : A;
+    for_elems_b<DIR, 8>(
+        N, nl,
+        [&](int pos, int c) {
+          const long long g = gindex<DIR>(P, T, pos, c);
+          return make_float2(A[g], Bs[g]);
+        },
+        [&](int pos, int c, float2 v) { z[pos * ld + c] = make_float2(v.x, two ? v.y : 0.f); });
     __syncthreads();
     line_derivative<ADJ>(X, Pg, P, a.aq, a.dq, a.d);
     float* OA = a.out + (long long)f * a.plane;
@@ -150,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_fcdiff(PassArgs a) {
 
 // fc_continue (FWD) and its transpose: ext lines of length L per plan.
 template <int DIR, bool ADJ>
-__global__ void __launch_bounds__(kBlock) k_fccont(PassArgs a) {
+__global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
   FCSD_TILE_BEGIN(a)
   const int L = P.L;
   const long long e0 = a.ext_off[T.plan] + (long long)T.line0 * L;
@@ -199,16 +212,19 @@ __global__ void __launch_bounds__(kBlock) k_fccont(PassArgs a) {
 
 // d_DIR (e - e_ref) of the four state fields into out (pass A for DIR 1).
 template <int DIR>
-__global__ void __launch_bounds__(kBlock) k_dev_diff(PassArgs a) {
+__global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
   FCSD_TILE_BEGIN(a)
   for (int f = 0; f < 4; f += 2) {
     const float* A = a.u + (long long)f * a.plane;
     const float* B = a.u + (long long)(f + 1) * a.plane;
     const float ra = a.eref[f], rb = a.eref[f + 1];
-    for_elems<DIR>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<DIR>(P, T, pos, c);
-      z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
-    });
+    for_elems_b<DIR, kLoadBatch>(
+        N, nl,
+        [&](int pos, int c) {
+          const long long g = gindex<DIR>(P, T, pos, c);
+          return make_float2(A[g], B[g]);
+        },
+        [&](int pos, int c, float2 v) { z[pos * ld + c] = make_float2(v.x - ra, v.y - rb); });
     __syncthreads();
     line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
     float* OA = a.out + (long long)f * a.plane;
@@ -223,61 +239,83 @@ __global__ void __launch_bounds__(kBlock) k_dev_diff(PassArgs a) {
   }
 }
 
-// H fields from e, d1e, d2e (two components f, f+1 at a time) at one point.
-__device__ __forceinline__ void make_H(const PassArgs& a, long long g, int f, float2 d2, int flux,
-                                       float hx[2], float hy[2]) {
+// Point inputs of all eight H fields (loaded once per point; inputs a flux
+// mode does not use read the metric instead, so every load is issued).
+struct HIn4 {
+  float m1x, m1y, m2x, m2y, mu;
+  float d1[4];
+  float e[4];
+};
+
+__device__ __forceinline__ HIn4 load_H4_inputs(const PassArgs& a, long long g, int flux) {
   const long long pl = a.plane;
-  const float m1x = a.metric[g], m1y = a.metric[pl + g], m2x = a.metric[2 * pl + g], m2y = a.metric[3 * pl + g];
-  float vx[2] = {0.f, 0.f}, vy[2] = {0.f, 0.f};
-  if (flux != FLUX_INVISCID) {
-    const float mu = a.mu[g];
-    const float d1a = a.d1e[(long long)f * pl + g], d1b = a.d1e[(long long)(f + 1) * pl + g];
-    vx[0] = mu * (m1x * d1a + m2x * d2.x);
-    vy[0] = mu * (m1y * d1a + m2y * d2.x);
-    vx[1] = mu * (m1x * d1b + m2x * d2.y);
-    vy[1] = mu * (m1y * d1b + m2y * d2.y);
-  }
-  if (flux != FLUX_VISC) {
-    float e[4], dF[4], dG[4];
+  const bool visc = flux != FLUX_INVISCID, inv = flux != FLUX_VISC;
+  const float* mu = visc ? a.mu : a.metric;
+  const float* d1 = visc ? a.d1e : a.metric;
+  const long long ds = visc ? pl : 0;
+  const float* e = inv ? a.u : a.metric;
+  const long long es = inv ? pl : 0;
+  HIn4 q;
+  q.m1x = a.metric[g];
+  q.m1y = a.metric[pl + g];
+  q.m2x = a.metric[2 * pl + g];
+  q.m2y = a.metric[3 * pl + g];
+  q.mu = mu[g];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] = a.u[(long long)k * pl + g];
-    dev_flux(e, a.eref, a.pref, a.gamma, dF, dG);
-    vx[0] -= dF[f];
-    vy[0] -= dG[f];
-    vx[1] -= dF[f + 1];
-    vy[1] -= dG[f + 1];
-  }
-  hx[0] = vx[0];
-  hy[0] = vy[0];
-  hx[1] = vx[1];
-  hy[1] = vy[1];
+  for (int k = 0; k < 4; ++k) q.d1[k] = d1[k * ds + g];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q.e[k] = e[k * es + g];
+  return q;
 }
 
-// Pass B1 (q2 lines): d2e, then H = mu grad_x e - f' (mode FLUX_FULL /
-// FLUX_VISC).  H layout: field 2c = H_x component c, 2c+1 = H_y component c.
-__global__ void __launch_bounds__(kBlock) k_passB1(PassArgs a) {
-  FCSD_TILE_BEGIN(a)
-  for (int f = 0; f < 4; f += 2) {
-    const float* A = a.u + (long long)f * a.plane;
-    const float* B = a.u + (long long)(f + 1) * a.plane;
-    const float ra = a.eref[f], rb = a.eref[f + 1];
-    for_elems<2>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<2>(P, T, pos, c);
-      z[pos * ld + c] = make_float2(A[g] - ra, B[g] - rb);
-    });
-    __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
-    for_elems<2>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<2>(P, T, pos, c);
-      float hx[2], hy[2];
-      make_H(a, g, f, z[pos * ld + c], a.mode, hx, hy);
-      a.H[(long long)(2 * f) * a.plane + g] = hx[0];
-      a.H[(long long)(2 * f + 1) * a.plane + g] = hy[0];
-      a.H[(long long)(2 * f + 2) * a.plane + g] = hx[1];
-      a.H[(long long)(2 * f + 3) * a.plane + g] = hy[1];
-    });
-    __syncthreads();
-  }
+// Pass B1 (q2 lines): d2 e of all four components at once (two complex
+// lines per grid line: components 0,1 at z[pos][c], 2,3 at z[pos][nl + c]),
+// then H = mu grad_x e - f' (mode FLUX_FULL / FLUX_VISC).  H layout: field
+// 2c = H_x component c, 2c+1 = H_y component c.
+__global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T2 = T;
+  T2.nl = 2 * T.nl;
+  const LineCtx X = line_setup(lds_z, T2, P, a.tw, a.km);
+  float2* __restrict__ z = X.z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  __syncthreads();
+  for_elems_b<2, kLoadBatch / 2>(
+      N, nl,
+      [&](int pos, int c) {
+        const long long g = gindex<2>(P, T, pos, c);
+        return make_float4(a.u[g], a.u[pl + g], a.u[2 * pl + g], a.u[3 * pl + g]);
+      },
+      [&](int pos, int c, float4 v) {
+        z[pos * ld + c] = make_float2(v.x - a.eref[0], v.y - a.eref[1]);
+        z[pos * ld + nl + c] = make_float2(v.z - a.eref[2], v.w - a.eref[3]);
+      });
+  __syncthreads();
+  line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
+  const int flux = a.mode;
+  for_elems_b<2, kEpiBatchH>(
+      N, nl, [&](int pos, int c) { return load_H4_inputs(a, gindex<2>(P, T, pos, c), flux); },
+      [&](int pos, int c, const HIn4& q) {
+        const long long g = gindex<2>(P, T, pos, c);
+        const float2 za = z[pos * ld + c], zb = z[pos * ld + nl + c];
+        const float d2[4] = {za.x, za.y, zb.x, zb.y};
+        float dF[4] = {0.f, 0.f, 0.f, 0.f}, dG[4] = {0.f, 0.f, 0.f, 0.f};
+        if (flux != FLUX_VISC) dev_flux(q.e, a.eref, a.pref, a.gamma, dF, dG);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float vx = 0.f, vy = 0.f;
+          if (flux != FLUX_INVISCID) {
+            vx = q.mu * (q.m1x * q.d1[k] + q.m2x * d2[k]);
+            vy = q.mu * (q.m1y * q.d1[k] + q.m2y * d2[k]);
+          }
+          a.H[(long long)(2 * k) * pl + g] = vx - dF[k];
+          a.H[(long long)(2 * k + 1) * pl + g] = vy - dG[k];
+        }
+      });
 }
 
 // Inviscid H = -f' (pointwise, no derivative needed).
@@ -301,30 +339,39 @@ __global__ void __launch_bounds__(kBlock) k_passH(PassArgs a, long long n) {
 }
 
 // Pass B2 (q2 lines): r2_c = m2x d2 H_x,c + m2y d2 H_y,c.
-__global__ void __launch_bounds__(kBlock) k_passB2(PassArgs a) {
+__global__ void FCSD_LINE_BOUNDS k_passB2(PassArgs a) {
   FCSD_TILE_BEGIN(a)
   const long long pl = a.plane;
   for (int comp = 0; comp < 4; ++comp) {
     const float* A = a.H + (long long)(2 * comp) * pl;
     const float* B = a.H + (long long)(2 * comp + 1) * pl;
-    for_elems<2>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<2>(P, T, pos, c);
-      z[pos * ld + c] = make_float2(A[g], B[g]);
-    });
+    for_elems_b<2, kLoadBatch>(
+        N, nl,
+        [&](int pos, int c) {
+          const long long g = gindex<2>(P, T, pos, c);
+          return make_float2(A[g], B[g]);
+        },
+        [&](int pos, int c, float2 v) { z[pos * ld + c] = v; });
     __syncthreads();
     line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
-    for_elems<2>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<2>(P, T, pos, c);
-      const float2 v = z[pos * ld + c];
-      a.r2[(long long)comp * pl + g] = a.metric[2 * pl + g] * v.x + a.metric[3 * pl + g] * v.y;
-    });
+    for_elems_b<2, kLoadBatch>(
+        N, nl,
+        [&](int pos, int c) {
+          const long long g = gindex<2>(P, T, pos, c);
+          return make_float2(a.metric[2 * pl + g], a.metric[3 * pl + g]);
+        },
+        [&](int pos, int c, float2 m) {
+          const long long g = gindex<2>(P, T, pos, c);
+          const float2 v = z[pos * ld + c];
+          a.r2[(long long)comp * pl + g] = m.x * v.x + m.y * v.y;
+        });
     __syncthreads();
   }
 }
 
 // Pass C (q1 lines): r = m1x d1 H_x + m1y d1 H_y + r2, then store (SET/ADD)
 // or the SSPRK register update (RK).
-__global__ void __launch_bounds__(kBlock) k_passC(PassArgs a) {
+__global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
   FCSD_TILE_BEGIN(a)
   const long long pl = a.plane;
   float dt = 0.f;
@@ -333,37 +380,63 @@ __global__ void __launch_bounds__(kBlock) k_passC(PassArgs a) {
   for (int comp = 0; comp < 4; ++comp) {
     const float* A = a.H + (long long)(2 * comp) * pl;
     const float* B = a.H + (long long)(2 * comp + 1) * pl;
-    for_elems<1>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<1>(P, T, pos, c);
-      z[pos * ld + c] = make_float2(A[g], B[g]);
-    });
+    for_elems_b<1, kLoadBatch>(
+        N, nl,
+        [&](int pos, int c) {
+          const long long g = gindex<1>(P, T, pos, c);
+          return make_float2(A[g], B[g]);
+        },
+        [&](int pos, int c, float2 v) { z[pos * ld + c] = v; });
     __syncthreads();
     line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
     const long long fo = (long long)comp * pl;
-    for_elems<1>(N, nl, [&](int pos, int c) {
-      const long long g = gindex<1>(P, T, pos, c);
-      const float2 v = z[pos * ld + c];
-      const float r = a.metric[g] * v.x + a.metric[pl + g] * v.y + a.r2[fo + g];
-      if (a.mode == MODE_SET) {
-        a.rhs[fo + g] = r;
-      } else if (a.mode == MODE_ADD) {
-        a.rhs[fo + g] += r;
-      } else {
-        const float ui = a.ui[fo + g];
-        const float dr = dt * r;
-        if (a.stage <= 1) {
-          a.uout[fo + g] = K.a0 * a.u0[fo + g] + K.ai * ui + K.b * dr;
-        } else if (a.stage == 2) {
-          a.uout[fo + g] = K.a0 * a.u0[fo + g] + K.ai * ui + K.b * dr;
-          a.acc[fo + g] = K.acc_i * ui;
-        } else if (a.stage == 3) {
-          a.uout[fo + g] = K.a0 * a.u0[fo + g] + K.ai * ui + K.b * dr;
-          a.acc[fo + g] += K.acc_i * ui + K.acc_b * dr;
-        } else {
-          a.uout[fo + g] = a.acc[fo + g] + K.ai * ui + K.b * dr;
-        }
-      }
-    });
+    // point inputs: the q1 metric row, r2 and the SSPRK registers of the
+    // stage; every load is issued (registers the stage does not use read r2)
+    const float* r2c = a.r2 + fo;
+    const bool rk = a.mode == MODE_RK;
+    const float* uic = rk ? a.ui + fo : r2c;
+    const float* wc = a.mode == MODE_ADD ? a.rhs + fo : ((rk && a.stage >= 3) ? a.acc + fo : r2c);
+    const float* u0c = (rk && a.stage <= 3) ? a.u0 + fo : r2c;
+    struct CIn {
+      float m1x, m1y, r2, ui, w, u0;
+    };
+    for_elems_b<1, kEpiBatch>(
+        N, nl,
+        [&](int pos, int c) {
+          const long long g = gindex<1>(P, T, pos, c);
+          CIn q;
+          q.m1x = a.metric[g];
+          q.m1y = a.metric[pl + g];
+          q.r2 = r2c[g];
+          q.ui = uic[g];
+          q.w = wc[g];
+          q.u0 = u0c[g];
+          return q;
+        },
+        [&](int pos, int c, const CIn& q) {
+          const long long g = gindex<1>(P, T, pos, c);
+          const float2 v = z[pos * ld + c];
+          const float r = q.m1x * v.x + q.m1y * v.y + q.r2;
+          if (a.mode == MODE_SET) {
+            a.rhs[fo + g] = r;
+          } else if (a.mode == MODE_ADD) {
+            a.rhs[fo + g] = q.w + r;
+          } else {
+            const float ui = q.ui;
+            const float dr = dt * r;
+            if (a.stage <= 1) {
+              a.uout[fo + g] = K.a0 * q.u0 + K.ai * ui + K.b * dr;
+            } else if (a.stage == 2) {
+              a.uout[fo + g] = K.a0 * q.u0 + K.ai * ui + K.b * dr;
+              a.acc[fo + g] = K.acc_i * ui;
+            } else if (a.stage == 3) {
+              a.uout[fo + g] = K.a0 * q.u0 + K.ai * ui + K.b * dr;
+              a.acc[fo + g] = q.w + (K.acc_i * ui + K.acc_b * dr);
+            } else {
+              a.uout[fo + g] = q.w + K.ai * ui + K.b * dr;
+            }
+          }
+        });
     __syncthreads();
   }
 }

@@ -660,7 +660,7 @@ __device__ __forceinline__ void flux_vjp(const float e[4], float gam, const floa
 // H = mu grad e - f': G1/G2 = mu-weighted metric products (for D^T later),
 // mu_bar += H_bar . grad e, u_bar += flux VJP of -H_bar.
 template <int DIR>
-__global__ void __launch_bounds__(kBlock) k_adjHb(PassArgs a, const float* rb, float* Hb,
+__global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
                                                   const float* d1e, const float* d2e, float* G1,
                                                   float* G2, float* mub, float* ub, int visc) {
   FCSD_TILE_BEGIN(a)
