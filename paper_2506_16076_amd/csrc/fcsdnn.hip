@@ -869,7 +869,9 @@ fcsd_status sdnn_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float ga
   hipLaunchKernelGGL(k_proxy, dim3(s->nchunks), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->d_patches, u,
                      (long long)s->plane, gamma, phi, (float*)nullptr);
   MlpPtr m{w->W1, w->b1, w->W2, w->b2, w->W3, w->b3};
-  hipLaunchKernelGGL(k_sdnn, dim3(s->nchunks), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->d_patches,
+  // blocks stride over the chunks so each loads the weights into LDS once
+  const int grid = std::min(s->nchunks, 2048);
+  hipLaunchKernelGGL(k_sdnn, dim3(grid), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->nchunks, s->d_patches,
                      (const float*)phi, m, (signed char*)tau, logits, (long long)s->plane);
   return launch_check(ctx, "sdnn_infer");
 }

@@ -141,129 +141,157 @@ __global__ void __launch_bounds__(kBlock) k_proxy(const ChunkDev* chunks, const 
 struct MlpPtr {
   const float *W1, *b1, *W2, *b2, *W3, *b3;
 };
-constexpr int kMlpFloats = 16 * 64 + 64 + 64 * 64 + 64 + 64 * 4 + 4;
 
-__device__ __noinline__ int mlp_argmax(const float* __restrict__ w, const float x[16],
-                                          float* out4) {
-  const float* W1 = w;
-  const float* b1 = W1 + 16 * 64;
-  const float* W2 = b1 + 64;
-  const float* b2 = W2 + 64 * 64;
-  const float* W3 = b2 + 64;
-  const float* b3 = W3 + 64 * 4;
-  float h1[64];
-#pragma unroll
-  for (int j = 0; j < 64; j += 4) {
-    float4 s = *reinterpret_cast<const float4*>(b1 + j);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const float4 wv = *reinterpret_cast<const float4*>(W1 + i * 64 + j);
-      s.x = fmaf(x[i], wv.x, s.x);
-      s.y = fmaf(x[i], wv.y, s.y);
-      s.z = fmaf(x[i], wv.z, s.z);
-      s.w = fmaf(x[i], wv.w, s.w);
-    }
-    h1[j] = fmaxf(s.x, 0.f);
-    h1[j + 1] = fmaxf(s.y, 0.f);
-    h1[j + 2] = fmaxf(s.z, 0.f);
-    h1[j + 3] = fmaxf(s.w, 0.f);
+// The 16-64-64-4 classifier on MFMA (v_mfma_f32_16x16x4f32, FP32 in, FP32
+// accumulate).  A wavefront evaluates 16 windows at once, as the transposed
+// products H1^T = W1^T X^T, H2^T = W2^T relu(H1^T), O^T = W3^T relu(H2^T)
+// with windows along the columns.  Lane l = 16 g + r holds column r (window
+// r) and, after each product, rows 4 g + v (v = 0..3) of every 16-row tile
+// -- exactly the B operand the next product needs when its K step k = 0..3
+// is read as unit 16 t + 4 k + v: activations never leave the registers.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kW2S = 68;  // padded LDS row stride of W2 (floats)
+
+struct MlpLds {
+  float W1[16 * 64];
+  float b1[64];
+  float W2[64 * kW2S];
+  float b2[64];
+  float W3[64 * 4];
+  float b3[4];
+};
+
+__device__ __forceinline__ void mlp_load(MlpLds& L, const MlpPtr& w) {
+  for (int k = threadIdx.x; k < 16 * 64; k += blockDim.x) L.W1[k] = w.W1[k];
+  for (int k = threadIdx.x; k < 64 * 64; k += blockDim.x) L.W2[(k >> 6) * kW2S + (k & 63)] = w.W2[k];
+  for (int k = threadIdx.x; k < 64 * 4; k += blockDim.x) L.W3[k] = w.W3[k];
+  for (int k = threadIdx.x; k < 64; k += blockDim.x) {
+    L.b1[k] = w.b1[k];
+    L.b2[k] = w.b2[k];
   }
-  float o0 = b3[0], o1 = b3[1], o2 = b3[2], o3 = b3[3];
-#pragma unroll 1
-  for (int k = 0; k < 64; k += 4) {
-    float s0 = b2[k], s1 = b2[k + 1], s2 = b2[k + 2], s3 = b2[k + 3];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) {
-      const float4 wv = *reinterpret_cast<const float4*>(W2 + j * 64 + k);
-      s0 = fmaf(h1[j], wv.x, s0);
-      s1 = fmaf(h1[j], wv.y, s1);
-      s2 = fmaf(h1[j], wv.z, s2);
-      s3 = fmaf(h1[j], wv.w, s3);
-    }
-    const float hs[4] = {fmaxf(s0, 0.f), fmaxf(s1, 0.f), fmaxf(s2, 0.f), fmaxf(s3, 0.f)};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 w3 = *reinterpret_cast<const float4*>(W3 + (k + q) * 4);
-      o0 = fmaf(hs[q], w3.x, o0);
-      o1 = fmaf(hs[q], w3.y, o1);
-      o2 = fmaf(hs[q], w3.z, o2);
-      o3 = fmaf(hs[q], w3.w, o3);
-    }
-  }
-  if (out4) {
-    out4[0] = o0;
-    out4[1] = o1;
-    out4[2] = o2;
-    out4[3] = o3;
-  }
-  int best = 0;
-  float bv = o0;
-  if (o1 > bv) { best = 1; bv = o1; }
-  if (o2 > bv) { best = 2; bv = o2; }
-  if (o3 > bv) { best = 3; bv = o3; }
-  return best;
+  if (threadIdx.x < 4) L.b3[threadIdx.x] = w.b3[threadIdx.x];
 }
 
-// features of the 16-sample window at offsets -8..7 (clamped) along a line
-__device__ __forceinline__ void window_features(const float* __restrict__ phi, long long base,
-                                                long long step, int pos, int n, float x[16]) {
+// Logits of 16 windows; lane 16 g + r supplies features 4 s + g (s = 0..3)
+// of window r in x[s]; lanes 0..15 receive the four logits of window r.
+__device__ __forceinline__ floatx4 mlp16(const MlpLds& L, const float x[4], int g, int r) {
+  floatx4 h1[4], h2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    h1[t] = floatx4{L.b1[16 * t + 4 * g], L.b1[16 * t + 4 * g + 1], L.b1[16 * t + 4 * g + 2],
+                    L.b1[16 * t + 4 * g + 3]};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      h1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.W1[(4 * s + g) * 64 + 16 * t + r], x[s], h1[t], 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h1[t][v] = fmaxf(h1[t][v], 0.f);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    h2[mt] = floatx4{L.b2[16 * mt + 4 * g], L.b2[16 * mt + 4 * g + 1], L.b2[16 * mt + 4 * g + 2],
+                     L.b2[16 * mt + 4 * g + 3]};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        h2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.W2[(16 * t + 4 * g + v) * kW2S + 16 * mt + r], h1[t][v],
+                                                      h2[mt], 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h2[mt][v] = fmaxf(h2[mt][v], 0.f);
+  }
+  floatx4 o = g == 0 ? floatx4{L.b3[0], L.b3[1], L.b3[2], L.b3[3]} : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float a = r < 4 ? L.W3[(16 * mt + 4 * g + v) * 4 + r] : 0.f;
+      o = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h2[mt][v], o, 0, 0, 0);
+    }
+  return o;
+}
+
+// This lane's samples t = g + 4 s (s = 0..3) of the 16-sample window at
+// offsets -8..7 (clamped) along a line, rescaled to [-1, 1] with the min and
+// max of the whole window (exchanged among the window's four lanes; min/max
+// are exact, so the features equal a sequential evaluation's).
+__device__ __forceinline__ void window4(const float* __restrict__ phi, long long base, long long step, int pos,
+                                        int n, int g, float x[4]) {
 #pragma clang fp contract(off)
   float lo = 3.4e38f, hi = -3.4e38f;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    int k = pos - 8 + t;
+  for (int s = 0; s < 4; ++s) {
+    int k = pos - 8 + g + 4 * s;
     k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
-    x[t] = phi[base + (long long)k * step];
-    lo = fminf(lo, x[t]);
-    hi = fmaxf(hi, x[t]);
+    x[s] = phi[base + (long long)k * step];
+    lo = fminf(lo, x[s]);
+    hi = fmaxf(hi, x[s]);
   }
+  lo = fminf(lo, __shfl_xor(lo, 16));
+  hi = fmaxf(hi, __shfl_xor(hi, 16));
+  lo = fminf(lo, __shfl_xor(lo, 32));
+  hi = fmaxf(hi, __shfl_xor(hi, 32));
   const float rng = hi - lo;
   if (rng <= 1e-6f * fmaxf(1.0f, fabsf(hi))) {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) x[t] = 0.f;
+    for (int s = 0; s < 4; ++s) x[s] = 0.f;
   } else {
-    const float s = 2.0f / rng;
+    const float sc = 2.0f / rng;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) x[t] = (x[t] - lo) * s - 1.0f;
+    for (int s = 0; s < 4; ++s) x[s] = (x[s] - lo) * sc - 1.0f;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* chunks, const PatchDev* patches,
+__device__ __forceinline__ int argmax4(floatx4 o) {
+  int best = 0;
+  float bv = o[0];
+  if (o[1] > bv) { best = 1; bv = o[1]; }
+  if (o[2] > bv) { best = 2; bv = o[2]; }
+  if (o[3] > bv) { best = 3; bv = o[3]; }
+  return best;
+}
+
+// Network classes of every point: tau = 1 + min over the two directions of
+// the argmax class (0 outside D~).  Blocks stride over the point chunks; each
+// wavefront takes 16 consecutive points of a chunk at a time.
+__global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                  const float* phi, MlpPtr w, signed char* tau,
                                                  float* logits, long long pl) {
-  __shared__ float wl[kMlpFloats];
-  {
-    const float* srcs[6] = {w.W1, w.b1, w.W2, w.b2, w.W3, w.b3};
-    const int lens[6] = {16 * 64, 64, 64 * 64, 64, 64 * 4, 4};
-    int o = 0;
-    for (int s = 0; s < 6; ++s) {
-      for (int k = threadIdx.x; k < lens[s]; k += blockDim.x) wl[o + k] = srcs[s][k];
-      o += lens[s];
-    }
-  }
+  __shared__ MlpLds L;
+  mlp_load(L, w);
   __syncthreads();
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
-  const int j = k / P.n1, i = k - j * P.n1;
-  const long long g = P.off + k;
-  if (!in_dtilde(P, i, j)) {
-    tau[g] = 0;
-    if (logits) {
-      for (int q = 0; q < 4; ++q) {
-        logits[4 * g + q] = 0.f;
-        logits[4 * (pl + g) + q] = 0.f;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {
+    const ChunkDev ck = chunks[cb];
+    const PatchDev P = patches[ck.patch];
+    const int np = P.n1 * P.n2;
+    for (int q = wv; q < kChunk / 16; q += kBlock / 64) {
+      const int k0 = ck.start + 16 * q;
+      if (k0 >= np) break;  // uniform across the wavefront
+      const int kk = k0 + r;
+      const bool valid = kk < np;
+      const int k = valid ? kk : np - 1;
+      const int j = k / P.n1, i = k - j * P.n1;
+      float x[4];
+      window4(phi, P.off + (long long)j * P.n1, 1, i, P.n1, g, x);
+      const floatx4 o1 = mlp16(L, x, g, r);
+      window4(phi, P.off + i, P.n1, j, P.n2, g, x);
+      const floatx4 o2 = mlp16(L, x, g, r);
+      if (g == 0 && valid) {
+        const long long gi = P.off + k;
+        const bool in = in_dtilde(P, i, j);
+        const int a1 = argmax4(o1), a2 = argmax4(o2);
+        tau[gi] = in ? (signed char)(1 + (a1 < a2 ? a1 : a2)) : (signed char)0;
+        if (logits) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            logits[4 * gi + v] = in ? o1[v] : 0.f;
+            logits[4 * (pl + gi) + v] = in ? o2[v] : 0.f;
+          }
+        }
       }
     }
-    return;
   }
-  float x[16];
-  window_features(phi, P.off + (long long)j * P.n1, 1, i, P.n1, x);
-  const int a1 = mlp_argmax(wl, x, logits ? logits + 4 * g : nullptr);
-  window_features(phi, P.off + i, P.n1, j, P.n2, x);
-  const int a2 = mlp_argmax(wl, x, logits ? logits + 4 * (pl + g) : nullptr);
-  tau[g] = (signed char)(1 + (a1 < a2 ? a1 : a2));
 }
 
 // ---------------------------------------------------------------- 7x7 max
