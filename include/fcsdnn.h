@@ -112,7 +112,7 @@ enum {
 fcsd_status fcsd_set_tune(fcsd_set* set, int lds_budget_q1, int lds_budget_q2, int order);
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
-enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3 };
+enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3, FCSD_WS_STEP_ADJ = 4 };
 fcsd_status fcsd_workspace_size(const fcsd_set* set, int op, size_t* bytes);
 
 /* ---- FC-Gram line operators (Sec. 2.2) --------------------------------- */
@@ -232,6 +232,14 @@ fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u,
  * plane `dirichlet_mask` (nullable).  No-op for independent patches. */
 fcsd_status fcsd_glue(fcsd_ctx* ctx, const fcsd_set* set, float* u, int64_t plane,
                       const uint8_t* dirichlet_mask, const float dirichlet_state[4]);
+/* Transpose of fcsd_glue on a cotangent u_bar (in place): the Dirichlet
+ * points' cotangent is dotted with dstate_dparam (4 floats, host) into
+ * dparam_dev[0] (device FP64, incremented) and zeroed; then every fringe
+ * receiver's cotangent moves onto its donor (shells, then sectors).
+ * dstate_dparam / dparam_dev may be NULL without a mask. */
+fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* set, float* u_bar, int64_t plane,
+                          const uint8_t* dirichlet_mask, const float dstate_dparam[4],
+                          double* dparam_dev);
 
 /* ---- fused stage and step ------------------------------------------------ */
 
@@ -273,7 +281,9 @@ typedef struct {
   float ref[4];
   float gamma, cfl;
   int fixed_dt;         /* 1: use *dt_dev as given */
-  const fcsd_mlp* w;    /* NULL: mu given */
+  const fcsd_mlp* w;    /* NULL: mu given (unless fixed_tau) */
+  int fixed_tau;        /* 1: classes given in tau (network not run), mu
+                           computed from them: replays a recorded step */
 } fcsd_step_args;
 
 /* One full time step (Algorithm 1): glue, network classes and viscosity
@@ -282,6 +292,24 @@ typedef struct {
  * it on later calls with identical arguments. */
 fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* a,
                       int64_t plane, void* ws, size_t ws_bytes, int use_graph);
+
+/* Reverse mode of fcsd_step with the step's decisions frozen (classes tau,
+ * step size *dt_dev; the 7x7 maximisers are recomputed and equal the
+ * recorded ones): given the cotangent of the step output in u_bar, replaces
+ * it by the cotangent of the step input u_in (the state before the first
+ * glue; not modified).  The forward step is recomputed from u_in into the
+ * workspace.  With a Dirichlet mask, dparam_dev[0] (device FP64) is
+ * incremented by u_bar_glued . dstate_dparam summed over the flagged points
+ * of every glue, i.e. the derivative through the boundary state with
+ * respect to a scalar parameter whose state derivative (4 floats, host) is
+ * dstate_dparam.  Classes and viscosity follow a->w / a->fixed_tau as in
+ * fcsd_step (tau, mu, argmax buffers required then; mu is rewritten);
+ * constant mu (a->w == NULL, fixed_tau == 0) is not differentiated.
+ * ws: fcsd_workspace_size(FCSD_WS_STEP_ADJ) bytes (paper Sec. 4, Algorithm 1,
+ * transposed stage by stage). */
+fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* a,
+                          const float* u_in, float* u_bar, const float dstate_dparam[4],
+                          double* dparam_dev, int64_t plane, void* ws, size_t ws_bytes);
 
 /* ---- host-only helpers (no device needed) ------------------------------- */
 

@@ -142,12 +142,13 @@ def initial_state(ps, mach, amp, pert, gamma=1.4):
     return e, de_dM, de_da
 
 
-def gradient(cfg, steps):
+def gradient(cfg, steps, replay=None):
     """Loss and its gradient with respect to (M, a_1..a_K) through `steps`
-    steps, decisions frozen at the base run.  Returns (L, g, base_run)."""
+    steps, decisions frozen at the base run (or at `replay`, recorded dt /
+    tau / arg per step).  Returns (L, g, base_run)."""
     ps = cfg.ps
     e0, de_dM, de_da = initial_state(ps, cfg.mach, cfg.pert.amp, cfg.pert)
-    run = forward(cfg, steps, u0=e0, mach=cfg.mach)
+    run = forward(cfg, steps, u0=e0, mach=cfg.mach, replay=replay)
     L, ub = outer_density_loss(ps, run.u)
     dM_bc = 0.0
     for k in range(steps - 1, -1, -1):

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcsdnn.so")
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EHIP", 5: "EUNSUPPORTED", 6: "ENONFINITE"}
-WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ = 0, 1, 2, 3
+WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ = 0, 1, 2, 3, 4
 
 
 class FcsdError(RuntimeError):
@@ -42,7 +42,7 @@ class StepArgs(ctypes.Structure):
                 ("tau", ctypes.c_void_p), ("argmax", ctypes.c_void_p), ("dt_dev", ctypes.c_void_p),
                 ("dirichlet_mask", ctypes.c_void_p), ("dirichlet_state", ctypes.c_float * 4),
                 ("ref", ctypes.c_float * 4), ("gamma", ctypes.c_float), ("cfl", ctypes.c_float),
-                ("fixed_dt", ctypes.c_int), ("w", ctypes.c_void_p)]
+                ("fixed_dt", ctypes.c_int), ("w", ctypes.c_void_p), ("fixed_tau", ctypes.c_int)]
 
 
 _lib = None
@@ -82,6 +82,8 @@ def lib():
             "av_viscosity": [vp, vp, vp, vp, f32, vp, vp, i64, vp, sz],
             "av_viscosity_adj": [vp, vp, vp, vp, vp, f32, vp, vp, i64, vp, sz],
             "fcsd_glue": [vp, vp, vp, i64, vp, P(f32)],
+            "fcsd_glue_adj": [vp, vp, vp, i64, vp, P(f32), vp],
+            "fcsd_step_adj": [vp, vp, P(StepArgs), vp, vp, P(f32), vp, i64, vp, sz],
             "fcsd_stage": [vp, vp, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
             "fcsd_stage_per_patch": [vp, vp, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
             "fcsd_stage_pass": [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
@@ -109,7 +111,7 @@ EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_l
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
            "rk_stage_adj", "fcsd_cfl_dt", "sdnn_infer", "av_viscosity", "av_viscosity_adj",
-           "fcsd_glue", "fcsd_stage", "fcsd_stage_per_patch", "fcsd_stage_pass", "fcsd_step", "fcsd_fc_matrix",
+           "fcsd_glue", "fcsd_glue_adj", "fcsd_step_adj", "fcsd_stage", "fcsd_stage_per_patch", "fcsd_stage_pass", "fcsd_step", "fcsd_fc_matrix",
            "fcsd_validate_patches", "fcsd_fft_plan", "fcsd_version"]
 
 

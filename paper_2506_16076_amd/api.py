@@ -13,7 +13,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import (FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP, lib,
+from ._lib import (FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP, WS_STEP_ADJ, lib,
                    patch_descs)
 
 
@@ -247,6 +247,13 @@ def fcsd_glue(s, u, mask=None, state=(0, 0, 0, 0)):
     _call(s, "fcsd_glue", _p(u), s.plane, _p(mask), _f4(state))
 
 
+def fcsd_glue_adj(s, u_bar, mask=None, dstate=(0, 0, 0, 0), dparam=None):
+    """Transpose of fcsd_glue in place; dparam (float64 device, 1 element)
+    is incremented by the Dirichlet points' cotangent dotted with dstate."""
+    _chk(u_bar, numel=4 * s.plane), _chk(mask, torch.uint8, s.plane), _chk(dparam, torch.float64, 1)
+    _call(s, "fcsd_glue_adj", _p(u_bar), s.plane, _p(mask), _f4(dstate), _p(dparam))
+
+
 # ------------------------------------------------------------------ fused
 
 def fcsd_stage(s, stage, u0, ui, acc, uout, metric, mu, ref, gamma, dt_dev, per_patch=False):
@@ -287,6 +294,7 @@ class Stepper:
         a.ref = _f4(ref)
         a.gamma, a.cfl = float(gamma), float(cfl)
         a.fixed_dt = 0
+        a.fixed_tau = 0
         if fixed_dt is not None:
             self.dt.fill_(float(fixed_dt))
             a.fixed_dt = 1
@@ -298,3 +306,34 @@ class Stepper:
     def step(self, use_graph=False):
         _call(self.s, "fcsd_step", ctypes.byref(self.args), self.s.plane, _p(self.ws), self.ws.numel() * 4,
               1 if use_graph else 0)
+
+    def replay(self, tau, dt, use_graph=False):
+        """One step with recorded decisions: classes `tau` (int8 plane) and
+        step size `dt` (1-element tensor) instead of the network and CFL."""
+        a = self.args
+        self.tau.copy_(tau)
+        self.dt.copy_(dt)
+        fd, ft = a.fixed_dt, a.fixed_tau
+        a.fixed_dt, a.fixed_tau = 1, 1 if self.W is not None else 0
+        try:
+            self.step(use_graph=use_graph)
+        finally:
+            a.fixed_dt, a.fixed_tau = fd, ft
+
+    def step_adj(self, u_in, u_bar, tau, dt, dstate=(0, 0, 0, 0), dparam=None):
+        """Reverse mode of a step from state u_in with recorded decisions:
+        u_bar (cotangent of the step output) becomes the cotangent of u_in;
+        dparam (float64, 1 element) gathers the boundary-state derivative."""
+        _chk(u_in, numel=4 * self.s.plane), _chk(u_bar, numel=4 * self.s.plane)
+        _chk(dparam, torch.float64, 1)
+        a = self.args
+        self.tau.copy_(tau)
+        self.dt.copy_(dt)
+        fd, ft = a.fixed_dt, a.fixed_tau
+        a.fixed_dt, a.fixed_tau = 1, 1 if self.W is not None else 0
+        ws = self.s.workspace(WS_STEP_ADJ)
+        try:
+            _call(self.s, "fcsd_step_adj", ctypes.byref(a), _p(u_in), _p(u_bar), _f4(dstate), _p(dparam),
+                  self.s.plane, _p(ws), ws.numel() * 4)
+        finally:
+            a.fixed_dt, a.fixed_tau = fd, ft

@@ -176,19 +176,26 @@ fcsd_status check_set(fcsd_ctx* ctx, const fcsd_set* s, int64_t plane) {
   return FCSD_OK;
 }
 
+// step reverse mode: 5 stage inputs (20), forward registers (8), cotangents
+// of the stage output, stage input, step input, acc and rhs (20), mu_bar (1),
+// the right-hand-side reverse workspace (24) and the viscosity one (11)
+constexpr size_t kStepAdjPlanes = 20 + 8 + 20 + 1 + 24 + 11;
+
 size_t ws_planes(const fcsd_set* s, int op) {
   switch (op) {
     case FCSD_WS_RHS: return 16;
     case FCSD_WS_AV: return 11;
     case FCSD_WS_STEP: return 16 + 12 + 11;
     case FCSD_WS_RHS_ADJ: return 24;
+    case FCSD_WS_STEP_ADJ: return kStepAdjPlanes;
     default: return 0;
   }
 }
 
 size_t ws_bytes_of(const fcsd_set* s, int op) {
   size_t b = ws_planes(s, op) * (size_t)s->plane * sizeof(float);
-  if (op == FCSD_WS_AV || op == FCSD_WS_STEP) b += 2 * sizeof(unsigned) * (size_t)(s->npatch + 64);
+  if (op == FCSD_WS_AV || op == FCSD_WS_STEP || op == FCSD_WS_STEP_ADJ)
+    b += 2 * sizeof(unsigned) * (size_t)(s->npatch + 64);
   return b;
 }
 
@@ -609,7 +616,7 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, int lds_budget_q1, int lds_bud
 }
 
 extern "C" fcsd_status fcsd_workspace_size(const fcsd_set* s, int op, size_t* bytes) {
-  if (!s || !bytes || op < 0 || op > 3) return FCSD_EINVAL;
+  if (!s || !bytes || op < 0 || op > FCSD_WS_STEP_ADJ) return FCSD_EINVAL;
   *bytes = ws_bytes_of(s, op);
   return FCSD_OK;
 }
@@ -978,7 +985,39 @@ fcsd_status glue_impl(fcsd_ctx* ctx, const fcsd_set* s, float* u, const uint8_t*
   return launch_check(ctx, "glue");
 }
 
+// transpose of glue_impl: Dirichlet, shells, sectors
+fcsd_status glue_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, float* ub, const uint8_t* mask, const float* ds4,
+                          double* dparam) {
+  if (mask)
+    hipLaunchKernelGGL(k_dirichlet_adj, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, mask, ub,
+                       (long long)s->plane, ds4[0], ds4[1], ds4[2], ds4[3], dparam);
+  if (s->annulus) {
+    const AnnulusDev& A = s->an;
+    if (A.nshell > 1) {
+      const long long n = (long long)A.n1 * 2 * kNf * A.nsec * A.nshell;
+      hipLaunchKernelGGL(k_glue_shells_adj, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, s->d_patches, A, ub,
+                         (long long)s->plane);
+    }
+    if (A.nsec > 1) {
+      const long long n = (long long)A.n2 * 2 * kNf * A.nsec * A.nshell;
+      hipLaunchKernelGGL(k_glue_sectors_adj, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, s->d_patches, A, ub,
+                         (long long)s->plane);
+    }
+  }
+  return launch_check(ctx, "glue_adj");
+}
+
 }  // namespace
+
+extern "C" fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* s, float* u_bar, int64_t plane,
+                                     const uint8_t* dirichlet_mask, const float dstate_dparam[4],
+                                     double* dparam_dev) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u_bar || (dirichlet_mask && (!dstate_dparam || !dparam_dev)))
+    return fail(ctx, FCSD_EINVAL, "fcsd_glue_adj: null argument");
+  return glue_adj_impl(ctx, s, u_bar, dirichlet_mask, dstate_dparam, dparam_dev);
+}
 
 extern "C" fcsd_status fcsd_glue(fcsd_ctx* ctx, const fcsd_set* s, float* u, int64_t plane,
                                  const uint8_t* dirichlet_mask, const float dirichlet_state[4]) {
@@ -1050,10 +1089,10 @@ fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a,
   AvWs A = carve_av(s, av_ws);
   fcsd_status st;
   if ((st = glue_impl(ctx, s, a->u, a->dirichlet_mask, a->dirichlet_state))) return st;
-  if (a->w) {
+  if (a->w && !a->fixed_tau)
     if ((st = sdnn_impl(ctx, s, a->u, a->gamma, a->w, a->tau, nullptr, A.phi))) return st;
+  if (a->w || a->fixed_tau)
     if ((st = viscosity_impl(ctx, s, a->u, a->tau, a->gamma, a->mu, a->argmax, A))) return st;
-  }
   if (!a->fixed_dt)
     if ((st = cfl_dt_impl(ctx, s, a->u, a->mu, a->cfl, a->gamma, a->dt_dev, A.red))) return st;
   const float* ins[5] = {a->u, Ua, Ub, Ua, Ub};
@@ -1075,7 +1114,8 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   fcsd_status st = check_set(ctx, s, plane);
   if (st) return st;
   if (!a || !a->u || !a->metric || !a->dt_dev || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_step: null argument");
-  if (a->w && (!a->tau || !a->mu)) return fail(ctx, FCSD_EINVAL, "fcsd_step: network needs tau and mu buffers");
+  if ((a->w || a->fixed_tau) && (!a->tau || !a->mu))
+    return fail(ctx, FCSD_EINVAL, "fcsd_step: network needs tau and mu buffers");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP)) return fail(ctx, FCSD_EINVAL, "fcsd_step: workspace too small");
   if (!use_graph) return step_body(ctx, s, a, ws);
   if (!ctx->stream) return fail(ctx, FCSD_EINVAL, "fcsd_step: graph capture needs a non-default stream");
@@ -1161,4 +1201,83 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
     if ((st = fc_diff_adj(ctx, s, 1, 4, G1, u_bar, plane))) return st;
   }
   return FCSD_OK;
+}
+
+// ======================================================================== reverse mode of a step
+
+extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a, const float* u_in,
+                                     float* u_bar, const float dstate_dparam[4], double* dparam_dev, int64_t plane,
+                                     void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!a || !a->metric || !a->dt_dev || !u_in || !u_bar || !ws)
+    return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: null argument");
+  if (a->dirichlet_mask && (!dstate_dparam || !dparam_dev))
+    return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: Dirichlet data needs dstate_dparam and dparam_dev");
+  const bool visc_net = a->w != nullptr || a->fixed_tau;
+  if (visc_net && (!a->tau || !a->mu || !a->argmax))
+    return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: classes need tau, mu and argmax buffers");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: workspace too small");
+  const long long pl = s->plane, n4 = 4 * pl;
+  float* w = (float*)ws;
+  float* STG = w;           // glued stage inputs 0..4
+  float* ACC = w + 20 * pl;
+  float* OUT = w + 24 * pl;
+  float* YB = w + 28 * pl;  // cotangent of the current stage output
+  float* UIB = w + 32 * pl; // cotangent of the current stage input
+  float* U0B = w + 36 * pl; // cotangent of the glued step input
+  float* ACCB = w + 40 * pl;
+  float* RB = w + 44 * pl;
+  float* MUB = w + 48 * pl;
+  float* RWS = w + 49 * pl;  // 24 planes
+  AvWs A = carve_av(s, w + 73 * pl);
+  hipStream_t sm = ctx->stream;
+  auto stg = [&](int k) { return STG + (long long)k * n4; };
+  // forward recomputation with the recorded classes and step size
+  HIPCHK(ctx, hipMemcpyAsync(stg(0), u_in, n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
+  if ((st = glue_impl(ctx, s, stg(0), a->dirichlet_mask, a->dirichlet_state))) return st;
+  if (visc_net)
+    if ((st = viscosity_impl(ctx, s, stg(0), a->tau, a->gamma, a->mu, a->argmax, A))) return st;
+  const float* mu = a->mu;
+  const int flux = mu ? FLUX_FULL : FLUX_INVISCID;
+  for (int k = 0; k < 5; ++k) {
+    if (k > 0)
+      if ((st = glue_impl(ctx, s, stg(k), a->dirichlet_mask, a->dirichlet_state))) return st;
+    float* out = k < 4 ? stg(k + 1) : OUT;
+    if ((st = rhs_passes(ctx, s, stg(k), a->metric, mu, a->ref, a->gamma, flux, MODE_RK, nullptr, k, stg(0), ACC, out,
+                         a->dt_dev, RWS, -1)))
+      return st;
+  }
+  // reverse sweep over the stages (register form, exact transpose)
+  const unsigned b4 = blocks_for(n4);
+  hipLaunchKernelGGL(k_fill, dim3(b4), dim3(kBlock), 0, sm, U0B, 0.f, n4);
+  hipLaunchKernelGGL(k_fill, dim3(b4), dim3(kBlock), 0, sm, ACCB, 0.f, n4);
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(pl)), dim3(kBlock), 0, sm, MUB, 0.f, pl);
+  hipLaunchKernelGGL(k_fill, dim3(b4), dim3(kBlock), 0, sm, YB, 0.f, n4);
+  hipLaunchKernelGGL(k_axpy, dim3(b4), dim3(kBlock), 0, sm, 1.f, (const float*)u_bar, YB, n4);
+  float* yb = YB;
+  float* uib = UIB;
+  for (int k = 4; k >= 0; --k) {
+    float* tgt = k > 0 ? uib : U0B;
+    if (k > 0) hipLaunchKernelGGL(k_fill, dim3(b4), dim3(kBlock), 0, sm, uib, 0.f, n4);
+    hipLaunchKernelGGL(k_rk_adj, dim3(b4), dim3(kBlock), 0, sm, k, a->dt_dev, (const float*)yb, U0B, uib, ACCB, RB,
+                       n4);
+    if ((st = launch_check(ctx, "step_adj rk"))) return st;
+    if ((st = fcsd_rhs_adj(ctx, s, stg(k), a->metric, mu, a->ref, a->gamma, RB, tgt, mu ? MUB : nullptr, plane, RWS,
+                           24 * (size_t)pl * sizeof(float))))
+      return st;
+    if (k > 0) {
+      if ((st = glue_adj_impl(ctx, s, uib, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;
+      float* t = yb;
+      yb = uib;
+      uib = t;
+    }
+  }
+  if (visc_net)
+    if ((st = av_viscosity_adj(ctx, s, stg(0), a->tau, a->argmax, a->gamma, MUB, U0B, plane, w + 73 * pl,
+                               ws_bytes_of(s, FCSD_WS_AV))))
+      return st;
+  if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;
+  HIPCHK(ctx, hipMemcpyAsync(u_bar, U0B, n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
+  return launch_check(ctx, "fcsd_step_adj");
 }

@@ -661,6 +661,104 @@ __global__ void __launch_bounds__(kBlock) k_dirichlet(const unsigned char* mask,
   u[3 * pl + g] = s3;
 }
 
+// ---------------------------------------------------------------- glue reverse mode
+//
+// Transpose of the fringe copies: every receiver's cotangent moves onto its
+// donor (donors are never receivers within a pass and have one receiver
+// each, so the updates do not race); run in the reverse order of the
+// forward (Dirichlet, shells, sectors).
+
+__global__ void __launch_bounds__(kBlock) k_glue_sectors_adj(const PatchDev* patches, AnnulusDev an, float* ub,
+                                                             long long pl) {
+  const long long per = (long long)an.n2 * 2 * kNf;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = per * an.nsec * an.nshell;
+  if (t >= total) return;
+  const int p = (int)(t / per);
+  long long r = t - (long long)p * per;
+  const int j = (int)(r / (2 * kNf));
+  const int q = (int)(r - (long long)j * 2 * kNf);
+  const int s = p % an.nsec, kk = p / an.nsec;
+  int i, src, si;
+  if (q < kNf) {
+    i = q;
+    src = kk * an.nsec + (s - 1 + an.nsec) % an.nsec;
+    si = i + an.st1;
+  } else {
+    i = an.n1 - 2 * kNf + q;
+    src = kk * an.nsec + (s + 1) % an.nsec;
+    si = i - an.st1;
+  }
+  const long long d = patches[p].off + (long long)j * an.n1 + i;
+  const long long sg = patches[src].off + (long long)j * an.n1 + si;
+  for (int f = 0; f < 4; ++f) {
+    ub[f * pl + sg] += ub[f * pl + d];
+    ub[f * pl + d] = 0.f;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_glue_shells_adj(const PatchDev* patches, AnnulusDev an, float* ub,
+                                                            long long pl) {
+  const long long per = (long long)an.n1 * 2 * kNf;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = per * an.nsec * an.nshell;
+  if (t >= total) return;
+  const int p = (int)(t / per);
+  long long r = t - (long long)p * per;
+  const int q = (int)(r / an.n1);
+  const int i = (int)(r - (long long)q * an.n1);
+  const int s = p % an.nsec, kk = p / an.nsec;
+  int j, src, sj;
+  if (q < kNf) {
+    if (kk == 0) return;
+    j = q;
+    src = (kk - 1) * an.nsec + s;
+    sj = j + an.st2;
+  } else {
+    if (kk == an.nshell - 1) return;
+    j = an.n2 - 2 * kNf + q;
+    src = (kk + 1) * an.nsec + s;
+    sj = j - an.st2;
+  }
+  const long long d = patches[p].off + (long long)j * an.n1 + i;
+  const long long sg = patches[src].off + (long long)sj * an.n1 + i;
+  for (int f = 0; f < 4; ++f) {
+    ub[f * pl + sg] += ub[f * pl + d];
+    ub[f * pl + d] = 0.f;
+  }
+}
+
+// Dirichlet transpose: dparam += sum over flagged points of ub . dstate,
+// then ub = 0 there.  Wavefront shuffles reduce each block to one FP64
+// atomic add.
+__global__ void __launch_bounds__(kBlock) k_dirichlet_adj(const unsigned char* mask, float* ub, long long pl,
+                                                          float d0, float d1, float d2, float d3, double* dparam) {
+  __shared__ double part[kBlock / 64];
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (g < pl && mask[g]) {
+    v = (double)ub[g] * d0 + (double)ub[pl + g] * d1 + (double)ub[2 * pl + g] * d2 + (double)ub[3 * pl + g] * d3;
+    ub[g] = 0.f;
+    ub[pl + g] = 0.f;
+    ub[2 * pl + g] = 0.f;
+    ub[3 * pl + g] = 0.f;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) t += part[k];
+    if (t != 0.0) atomicAdd(dparam, t);
+  }
+}
+
+// ub[k] += alpha ubar (k < n), used by the step reverse mode
+__global__ void __launch_bounds__(kBlock) k_axpy(float alpha, const float* x, float* y, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) y[g] += alpha * x[g];
+}
+
 // ---------------------------------------------------------------- RHS reverse mode
 
 // (dF/de)^T fb + (dG/de)^T gb at one point (primitive chain rule)
