@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--npatch", type=int, default=200)
     ap.add_argument("--no-per-patch", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=8, help="steps of the timed reverse sweep (0: skip)")
+    ap.add_argument("--adj-every", type=int, default=4, help="checkpoint spacing of the reverse sweep")
     ap.add_argument("--schedule", default="auto",
                     help="auto (autotuner) or Q1_BUDGET,Q2_BUDGET,lpt|xcd")
     args = ap.parse_args()
@@ -248,6 +250,28 @@ def main():
     stage_bytes = sum(pass_gb.values()) * 1e9 / npts
     traffic = recorded_traffic(PASS_KERNEL[dom], npts)
 
+    # ---------------- reverse mode: checkpointed adjoint of K steps
+    adjoint = None
+    if args.adj_steps > 0:
+        from paper_2506_16076_amd import autodiff
+        K, every = args.adj_steps, args.adj_every
+        u_start = u.clone()
+        u0 = u_start.clone().requires_grad_(True)
+        par = torch.zeros((), device=dev, requires_grad=True)
+        uT = autodiff.rollout(st, u0, par, K, every)
+        torch.cuda.synchronize()
+        gseed = torch.ones_like(uT)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        uT.backward(gseed)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms_adj = e0.elapsed_time(e1)
+        adjoint = {"value": npts * 5 * K / (ms_adj / 1e3), "unit": "grid-pt RK-stages/s (reverse, incl. "
+                   "checkpoint recomputation)", "steps": K, "checkpoint_every": every, "ms_per_step": ms_adj / K,
+                   "finite": bool(torch.isfinite(u0.grad).all().item())}
+        u.copy_(u_start)
+
     if args.copy_calib:
         # plain copy of known size for the counter scale factors: reads and
         # writes COPY_MIB MiB once per launch, after a fill of another buffer
@@ -285,6 +309,7 @@ def main():
         "stage_ms": {"batched": ms_batched / 5, "per_patch": None if ms_pp is None else ms_pp / 5,
                      "batched_over_per_patch": None if ms_pp is None else ms_pp / ms_batched},
         "pass_ms": passes,
+        "adjoint": adjoint,
         "schedule": {k: v for k, v in tuning.items() if k != "table"},
         "stage_bytes_per_point": stage_bytes,
         "stage_effective_GBs": stage_bytes * npts / (ms_batched / 5 / 1e3) / 1e9,
