@@ -561,3 +561,76 @@ def test_rollout_gradient_full_size(env):
     """The differentiation workload at its stated size: 16 patches of
     128 x 128, 40 steps, checkpoints every 8."""
     _rollout_gradient_check(env, 128, 40, 8)
+
+
+# ------------------------------------------------------------------ full sizes, sampled patches
+
+def _subset(ps, plist):
+    """The oracle's view of a few patches of a layout (same planes)."""
+    import dataclasses
+    idx = np.asarray(plist)
+    return dataclasses.replace(ps, n1=ps.n1[idx], n2=ps.n2[idx], C1=ps.C1[idx], C2=ps.C2[idx], off=ps.off[idx],
+                               htilde=ps.htilde[idx], hhat=ps.hhat[idx], internal=ps.internal[idx],
+                               nsec=0, nshell=0, dirichlet=None)
+
+
+@pytest.mark.parametrize("idx", [1, 2, 4])
+def test_full_size_rhs_sampled_patches(env, idx):
+    """The full right-hand side (convective + viscous) of the workloads at
+    their stated sizes (c1 16 x 256^2, c2 200 uneven patches 48..512, c4
+    64 x 512^2), computed on the GPU for every patch in the schedule the
+    bench uses (autotuned tiles), against the oracle on five sampled
+    patches (first, last, largest, two seeded); bar 1e-5 per component."""
+    from paper_2506_16076_amd import autotune
+    api, ctx, torch = env
+    cfg = synth.config(idx)
+    ps = cfg.ps
+    say("full-size rhs", cfg.name, ps.npatch, "patches", ps.npoints, "points")
+    s = api.PatchSet.from_layout(ctx, ps)
+    metric = dev(torch, ps.metric)
+    ud = dev(torch, cfg.u0)
+    mu = (0.002 * (1.5 + np.sin(3 * ps.xy[0]) * np.cos(2 * ps.xy[1]))).astype(np.float32)
+    mud = dev(torch, mu)
+    res = autotune.autotune(s, ud, metric, mud, cfg.ref, G, reps=1)
+    say("  schedule", {k: v for k, v in res.items() if k != "table"})
+    rhs = torch.zeros(4 * ps.plane, device="cuda:0")
+    api.fcsd_rhs(s, ud, metric, mud, cfg.ref, G, rhs)
+    got = host(rhs).reshape(4, -1)
+    sizes = ps.n1.astype(np.int64) * ps.n2
+    rng = np.random.default_rng(idx)
+    plist = sorted({0, ps.npatch - 1, int(np.argmax(sizes)), *rng.choice(ps.npatch, 2, replace=False).tolist()})
+    sub = _subset(ps, plist)
+    want = euler.full_rhs(cfg.u0.astype(np.float64), ps.metric, mu.astype(np.float64), sub, G)
+    err = relerr_phys(sub, got, want)
+    say("  patches", plist, "rel L2", err)
+    assert np.all(err < RHS_TOL)
+    s.close()
+
+
+def test_hundred_steps_annulus_replayed(env):
+    """100 full steps (network, viscosity, step size, five stages, glue and
+    inflow boundary) of the 16-sector annulus at 48 x 48 per patch; the
+    oracle replays the GPU's decisions (classes, maximisers, step sizes) so
+    the comparison measures arithmetic only.  Bar: 1e-4 relative L2 per
+    component after 100 steps."""
+    api, ctx, torch = env
+    cfg = synth.config(1, n=48)
+    ps = cfg.ps
+    s = api.PatchSet.from_layout(ctx, ps)
+    u = dev(torch, cfg.u0)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    st = api.Stepper(s, u, dev(torch, ps.metric), cfg.ref, W=W, dirichlet_mask=dev(torch, ps.dirichlet),
+                     dirichlet_state=synth.freestream(cfg.mach))
+    run = solver.Run(cfg)
+    for k in range(100):
+        st.step(use_graph=True)
+        run.step(dt=float(host(st.dt)[0]), tau=host(st.tau), arg=host(st.argmax))
+        if k % 20 == 19:
+            say("  step", k + 1)
+    got = host(u).reshape(4, -1)
+    err = relerr_phys(ps, got, run.u)
+    chg = relerr_phys(ps, got - cfg.u0, run.u - cfg.u0)
+    say("100 steps annulus: state rel L2", err, "change", chg)
+    assert np.all(np.isfinite(got))
+    assert np.all(err < STEP_TOL)
+    s.close()
