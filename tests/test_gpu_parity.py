@@ -509,8 +509,8 @@ def _rollout_gradient_check(env, n, steps, every):
     amplitudes, through torch.autograd and the hand-written step reverse
     mode, against the FP64 oracle's discrete adjoint with the same recorded
     decisions (classes, maximisers, step sizes).  Bar: relative L2 over the
-    gradient vector <= 1e-3 and 1e-2 on the Mach component (FP32 forward and
-    reverse sweeps over 5 x steps stages)."""
+    gradient vector <= 1e-4 and 1e-2 on the small Mach component (FP32
+    forward and reverse sweeps over 5 x steps stages)."""
     from paper_2506_16076_amd import autodiff
     from oracle import adjoint
     api, ctx, torch = env
@@ -545,7 +545,7 @@ def _rollout_gradient_check(env, n, steps, every):
     say("  loss gpu", float(loss), "oracle", L, "grad rel L2", err)
     say("  dL/dM gpu", g_gpu[0], "oracle", g_or[0])
     assert abs(float(loss) - L) <= 1e-5 * abs(L)
-    assert err <= 1e-3
+    assert err <= 1e-4
     assert abs(g_gpu[0] - g_or[0]) <= 1e-2 * abs(g_or[0])
     s.close()
 
