@@ -21,7 +21,8 @@ sources have changed since).  --copy-calib adds a plain device copy of known
 size to the run, whose counter readings give the scale factor.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--no-per-patch] [--copy-calib] [--schedule auto|Q1,Q2,ORDER]
+                       [--no-per-patch] [--copy-calib] [--layout rows|blocked]
+                       [--schedule auto|B0,B1,B2,T0,T1,T2,ORDER]
 """
 import argparse
 import hashlib
@@ -134,10 +135,13 @@ def main():
     ap.add_argument("--npatch", type=int, default=200)
     ap.add_argument("--no-per-patch", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--layout", default="blocked", choices=["rows", "blocked"],
+                    help="plane storage: row-major or 8x4 blocks (default)")
     ap.add_argument("--adj-steps", type=int, default=8, help="steps of the timed reverse sweep (0: skip)")
     ap.add_argument("--adj-every", type=int, default=4, help="checkpoint spacing of the reverse sweep")
     ap.add_argument("--schedule", default="auto",
-                    help="auto (autotuner) or Q1_BUDGET,Q2_BUDGET,lpt|xcd")
+                    help="auto (autotuner) or B_q1,B_q2,B_q2wide,T_q1,T_q2,T_q2wide,lpt|xcd (LDS budgets in "
+                         "bytes, workgroup sizes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -152,27 +156,30 @@ def main():
     cfg = synth.config(2, npatch=args.npatch)
     ps = cfg.ps
     ctx = api.Context(0)
-    s = api.PatchSet.from_layout(ctx, ps)
+    layout = {"rows": 0, "blocked": 1}[args.layout]
+    s = api.PatchSet.from_layout(ctx, ps, layout)
     dev = "cuda:0"
 
     def t(a, dtype=None):
         x = torch.from_numpy(np.ascontiguousarray(a).reshape(-1))
         return (x.to(dtype) if dtype else x).to(dev).contiguous()
 
-    u = t(cfg.u0)
-    metric = t(ps.metric)
+    u = s.to_device(cfg.u0)
+    metric = s.to_device(ps.metric)
     W = {k: t(v) for k, v in cfg.mlp.items()}
     npts = ps.npoints
     # schedule: autotuned tile split and launch order (outside the timed region)
     if args.schedule == "auto":
         from paper_2506_16076_amd import autotune
-        mu0 = torch.full((ps.plane,), 1e-3, device=dev)
+        mu0 = torch.full((s.plane,), 1e-3, device=dev)
         tuning = autotune.autotune(s, u, metric, mu0, cfg.ref, 1.4)
         print("autotune:", json.dumps(tuning), file=sys.stderr, flush=True)
     else:
-        q1, q2, order = args.schedule.split(",")
-        s.tune(int(q1), int(q2), {"lpt": 0, "xcd": 1}[order])
-        tuning = {"q1_budget": int(q1), "q2_budget": int(q2), "order": order, "given": True}
+        # B0,B1,B2,T0,T1,T2,ORDER: LDS budgets and workgroup sizes of the three tile sets
+        f = args.schedule.split(",")
+        bud, thr, order = [int(x) for x in f[0:3]], [int(x) for x in f[3:6]], f[6]
+        s.tune(bud, thr, {"lpt": 0, "xcd": 1}[order])
+        tuning = {"budgets": bud, "threads": thr, "order": order, "given": True}
     st = api.Stepper(s, u, metric, cfg.ref, W=W)
 
     # ---------------- full step, graph replay
@@ -300,6 +307,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"uneven-{ps.npatch}-patches-48to512 (seed 2), Mach 3 +-1% density, "
                                "network classifier + smooth AV every step, SSPRK(5,4), batched hipGraph step",
+                   "layout": args.layout,
                    "points": npts, "patches": ps.npatch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": PASS_KERNEL[dom],

@@ -81,6 +81,17 @@ void* fcsd_ctx_stream(fcsd_ctx* ctx);
 /* Block the host until the context's stream is idle. */
 fcsd_status fcsd_ctx_sync(fcsd_ctx* ctx);
 
+/* Plane storage of the patches of a set (every plane an entry point takes:
+ * state, metric, viscosity, masks, classes, outputs, workspaces). */
+enum {
+  /* point (i, j) of patch p at off_p + j n1_p + i */
+  FCSD_LAYOUT_ROWS = 0,
+  /* 8 x 4 blocks (8 points along q1, 4 along q2; 128 bytes): point (i, j)
+   * at off_p + 32 ((j/4) nb1_p + i/8) + 8 (j%4) + i%8, nb1_p = ceil(n1_p/8);
+   * a patch occupies ceil8(n1_p) ceil4(n2_p) elements, off_p a multiple of
+   * 32.  Line tiles along both directions then read whole cache lines. */
+  FCSD_LAYOUT_B8X4 = 1
+};
 /* Build a patch set: validates the descriptors (n >= 2d+1, n <= 4096,
  * 0 <= C <= 256, 1 <= d <= 8, patches inside [0, plane) and disjoint),
  * factors every extension length L = n + C into radices {2,3,4,5,7,8,11,13}
@@ -90,10 +101,13 @@ fcsd_status fcsd_ctx_sync(fcsd_ctx* ctx);
  * `ring_sectors` / `ring_shells` > 0 declare the index-aligned annulus
  * layout (sector s of shell k is patch k*ring_sectors + s, neighbours overlap
  * by 2 n_v + 1 = 19 lines) used by the fringe exchange and by the
- * multi-patch smoothing-blending operator; 0 means independent patches. */
+ * multi-patch smoothing-blending operator; 0 means independent patches.
+ * `layout` (FCSD_LAYOUT_*) fixes the storage of every plane passed to the
+ * set's entry points; the blocked layout needs offsets that are multiples of
+ * 32 and room for the padded patch. */
 fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_patch_desc* patches,
                             int d, int64_t plane, int ring_sectors, int ring_shells,
-                            fcsd_set** out);
+                            int layout, fcsd_set** out);
 fcsd_status fcsd_set_destroy(fcsd_set* set);
 /* Launch order of the batched line tiles. */
 enum {
@@ -101,15 +115,17 @@ enum {
   FCSD_ORDER_XCD = 1  /* whole patches dealt to the 8 dies (one L2 each),
                          balanced by work; the default */
 };
-/* Re-split the line tiles of a set: workgroup LDS budgets in bytes for the
- * q1-line passes and the q2-line passes (8 KB .. 160 KB each; default 64 KB
- * or the FCSD_LDS_BUDGET environment variable at creation) and the launch
- * order.  Smaller budgets mean fewer lines per tile and more workgroups per
- * compute unit; wider q2 tiles read longer contiguous row segments.
- * Synchronises the context's stream and drops captured step graphs.
- * Returns FCSD_EINVAL for an out-of-range budget or order.  Used by the
- * autotuner. */
-fcsd_status fcsd_set_tune(fcsd_set* set, int lds_budget_q1, int lds_budget_q2, int order);
+/* Re-split the line tiles of a set.  Three tile sets: [0] q1 lines (passes
+ * A, C), [1] q2 lines (pass B2, transposes), [2] q2 lines holding two
+ * complex lines per grid line (pass B1).  For each, the workgroup LDS
+ * budget in bytes (8 KB .. 160 KB; default 64 KB or the FCSD_LDS_BUDGET
+ * environment variable at creation) and the workgroup size (64, 128, 256,
+ * 512 or 1024 threads; default 256); and the launch order of all tiles.
+ * Larger budgets mean more lines per tile, fewer workgroups per compute
+ * unit; larger workgroups put more threads on each line.  Synchronises the
+ * context's stream and drops captured step graphs.  Returns FCSD_EINVAL for
+ * an out-of-range argument.  Used by the autotuner. */
+fcsd_status fcsd_set_tune(fcsd_set* set, const int lds_budget[3], const int threads[3], int order);
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
 enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3, FCSD_WS_STEP_ADJ = 4 };
@@ -319,7 +335,8 @@ fcsd_status fcsd_fc_matrix(int d, int C, double* out);
 /* Checks a patch table exactly as fcsd_set_create does, without a device;
  * writes a message into msg (msglen bytes) on failure. */
 fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* patches, int d, int64_t plane,
-                                  int ring_sectors, int ring_shells, char* msg, int msglen);
+                                  int ring_sectors, int ring_shells, int layout, char* msg,
+                                  int msglen);
 /* Radix factorisation of L (returns FCSD_EUNSUPPORTED if none). */
 fcsd_status fcsd_fft_plan(int L, int* nstages, int radices[8]);
 const char* fcsd_version(void);

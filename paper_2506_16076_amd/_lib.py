@@ -18,6 +18,30 @@ LIB_PATH = os.path.join(HERE, "libfcsdnn.so")
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EHIP", 5: "EUNSUPPORTED", 6: "ENONFINITE"}
 WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ = 0, 1, 2, 3, 4
+LAYOUT_ROWS, LAYOUT_B8X4 = 0, 1
+
+
+def blocked_layout(n1, n2, base_off=None):
+    """Offsets and plane size of the 8x4-blocked storage of patches n1 x n2
+    (patches back to back, each padded to whole blocks)."""
+    off, o = [], 0
+    for a, b in zip(n1, n2):
+        off.append(o)
+        o += ((int(a) + 7) // 8 * 8) * ((int(b) + 3) // 4 * 4)
+    return np.asarray(off, np.int64), (o + 63) // 64 * 64
+
+
+def layout_index(n1, n2, off_rows, off_blk):
+    """Plane indices (rows, blocked) of every patch point, for converting
+    planes between the two storages."""
+    rows, blk = [], []
+    for a, b, orow, oblk in zip(n1, n2, off_rows, off_blk):
+        a, b = int(a), int(b)
+        j, i = np.meshgrid(np.arange(b), np.arange(a), indexing="ij")
+        rows.append(int(orow) + j * a + i)
+        nb1 = (a + 7) // 8
+        blk.append(int(oblk) + ((j // 4) * nb1 + i // 8) * 32 + (j % 4) * 8 + i % 8)
+    return np.concatenate([r.ravel() for r in rows]), np.concatenate([q.ravel() for q in blk])
 
 
 class FcsdError(RuntimeError):
@@ -62,9 +86,9 @@ def lib():
             "fcsd_ctx_destroy": [vp],
             "fcsd_ctx_set_stream": [vp, vp],
             "fcsd_ctx_sync": [vp],
-            "fcsd_set_create": [vp, i32, P(PatchDesc), i32, i64, i32, i32, P(vp)],
+            "fcsd_set_create": [vp, i32, P(PatchDesc), i32, i64, i32, i32, i32, P(vp)],
             "fcsd_set_destroy": [vp],
-            "fcsd_set_tune": [vp, i32, i32, i32],
+            "fcsd_set_tune": [vp, P(i32), P(i32), i32],
             "fcsd_workspace_size": [vp, i32, P(sz)],
             "fcsd_ext_size": [vp, i32, P(i64)],
             "fc_continue": [vp, vp, i32, i32, vp, i64, vp, i64],
@@ -90,7 +114,7 @@ def lib():
             "fcsd_step": [vp, vp, P(StepArgs), i64, vp, sz, i32],
             "fcsd_fc_matrix": [i32, i32, P(ctypes.c_double)],
             "fcsd_fft_plan": [i32, P(i32), P(i32)],
-            "fcsd_validate_patches": [i32, P(PatchDesc), i32, i64, i32, i32, ctypes.c_char_p, i32],
+            "fcsd_validate_patches": [i32, P(PatchDesc), i32, i64, i32, i32, i32, ctypes.c_char_p, i32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -148,7 +172,7 @@ def fft_plan(L: int):
     return [r[i] for i in range(n.value)]
 
 
-def validate_patches(descs, d, plane, ring_sectors=0, ring_shells=0):
+def validate_patches(descs, d, plane, ring_sectors=0, ring_shells=0, layout=0):
     buf = ctypes.create_string_buffer(256)
-    rc = lib().fcsd_validate_patches(len(descs), descs, d, plane, ring_sectors, ring_shells, buf, 256)
+    rc = lib().fcsd_validate_patches(len(descs), descs, d, plane, ring_sectors, ring_shells, layout, buf, 256)
     return rc, buf.value.decode()

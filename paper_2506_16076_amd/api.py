@@ -13,8 +13,8 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import (FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP, WS_STEP_ADJ, lib,
-                   patch_descs)
+from ._lib import (LAYOUT_B8X4, LAYOUT_ROWS, FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP,
+                   WS_STEP_ADJ, blocked_layout, layout_index, lib, patch_descs)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -59,26 +59,70 @@ class Context:
 
 class PatchSet:
     """Device-side patch set built from plain arrays (n1, n2, C1, C2, off,
-    hhat, htilde, internal) and the plane size."""
+    hhat, htilde, internal), the plane size and the storage layout."""
 
     def __init__(self, ctx: Context, n1, n2, C1, C2, off, hhat, htilde, internal, d: int, plane: int,
-                 ring_sectors: int = 0, ring_shells: int = 0):
+                 ring_sectors: int = 0, ring_shells: int = 0, layout: int = LAYOUT_ROWS):
         self.ctx = ctx
         self.plane = int(plane)
+        self.layout = int(layout)
         self.npatch = len(n1)
         self.npoints = int(np.sum(np.asarray(n1, np.int64) * np.asarray(n2, np.int64)))
         self.descs = patch_descs(n1, n2, C1, C2, off, hhat, htilde, internal)
         h = ctypes.c_void_p()
         ctx.check(lib().fcsd_set_create(ctx.h, self.npatch, self.descs, d, self.plane, ring_sectors,
-                                        ring_shells, ctypes.byref(h)), "fcsd_set_create")
+                                        ring_shells, self.layout, ctypes.byref(h)), "fcsd_set_create")
         self.h = h
         self._ws = {}
+        self._map = None
 
     @classmethod
-    def from_layout(cls, ctx, ps):
-        """From any object with the attributes of synth.PatchSet."""
-        return cls(ctx, ps.n1, ps.n2, ps.C1, ps.C2, ps.off, ps.hhat, ps.htilde, ps.internal, ps.d,
-                   ps.plane, ps.nsec, ps.nshell)
+    def from_layout(cls, ctx, ps, layout: int = LAYOUT_ROWS):
+        """From any object with the attributes of synth.PatchSet (row-major
+        planes).  With LAYOUT_B8X4 the device planes are blocked; to_device /
+        to_host convert the row-major host planes."""
+        if layout == LAYOUT_ROWS:
+            s = cls(ctx, ps.n1, ps.n2, ps.C1, ps.C2, ps.off, ps.hhat, ps.htilde, ps.internal, ps.d,
+                    ps.plane, ps.nsec, ps.nshell)
+            s.host_plane = ps.plane
+            return s
+        off, plane = blocked_layout(ps.n1, ps.n2)
+        s = cls(ctx, ps.n1, ps.n2, ps.C1, ps.C2, off, ps.hhat, ps.htilde, ps.internal, ps.d, plane, ps.nsec,
+                ps.nshell, layout)
+        rows, blk = layout_index(ps.n1, ps.n2, ps.off, off)
+        dev = f"cuda:{ctx.device}"
+        s._map = (torch.from_numpy(rows).to(dev), torch.from_numpy(blk).to(dev))
+        s.host_plane = ps.plane
+        return s
+
+    def to_device(self, arr, dtype=None) -> torch.Tensor:
+        """Row-major host planes [..., host_plane] -> flat device planes in
+        the set's storage (padding zero)."""
+        a = np.ascontiguousarray(arr)
+        lead = a.shape[:-1]
+        t = torch.from_numpy(a.reshape(-1, a.shape[-1]))
+        if dtype is not None:
+            t = t.to(dtype)
+        dev = f"cuda:{self.ctx.device}"
+        if self._map is None:
+            return t.reshape(-1).to(dev).contiguous()
+        rows, blk = self._map
+        src = t.to(dev)
+        out = torch.zeros((src.shape[0], self.plane), dtype=src.dtype, device=dev)
+        out[:, blk] = src[:, rows]
+        return out.reshape(-1).contiguous()
+
+    def to_host(self, t: torch.Tensor, nf: int = None) -> np.ndarray:
+        """Flat device planes in the set's storage -> row-major host planes
+        [nf, host_plane]."""
+        nf = nf or t.numel() // self.plane
+        src = t.reshape(nf, -1)[:, :self.plane]
+        if self._map is None:
+            return src.cpu().numpy()
+        rows, blk = self._map
+        out = torch.zeros((nf, self.host_plane), dtype=src.dtype, device=src.device)
+        out[:, rows] = src[:, blk]
+        return out.cpu().numpy()
 
     def workspace_size(self, op: int) -> int:
         b = ctypes.c_size_t()
@@ -93,14 +137,19 @@ class PatchSet:
 
     ORDER_LPT, ORDER_XCD = 0, 1
 
-    def tune(self, lds_budget_q1: int, lds_budget_q2: int = None, order: int = 1):
-        """Tile split (LDS budget per workgroup for q1-line and q2-line passes)
-        and launch order (ORDER_LPT or ORDER_XCD)."""
-        if lds_budget_q2 is None:
-            lds_budget_q2 = lds_budget_q1
-        self.ctx.check(lib().fcsd_set_tune(self.h, int(lds_budget_q1), int(lds_budget_q2), int(order)),
-                       "fcsd_set_tune")
-        self.tuning = (int(lds_budget_q1), int(lds_budget_q2), int(order))
+    def tune(self, budgets, threads=(256, 256, 256), order: int = 1):
+        """Tile split and workgroup size of the three tile sets (q1 lines:
+        passes A, C; q2 lines: pass B2; q2 lines with two complex lines per
+        grid line: pass B1) and the launch order (ORDER_LPT or ORDER_XCD).
+        budgets / threads: one int (all sets) or three."""
+        if isinstance(budgets, int):
+            budgets = (budgets,) * 3
+        if isinstance(threads, int):
+            threads = (threads,) * 3
+        b = (ctypes.c_int * 3)(*[int(x) for x in budgets])
+        t = (ctypes.c_int * 3)(*[int(x) for x in threads])
+        self.ctx.check(lib().fcsd_set_tune(self.h, b, t, int(order)), "fcsd_set_tune")
+        self.tuning = (tuple(int(x) for x in budgets), tuple(int(x) for x in threads), int(order))
 
     def ext_size(self, direction: int) -> int:
         v = ctypes.c_int64()

@@ -1,14 +1,15 @@
 """Autotuner of the batched line-tile schedule.
 
-The tile split of a patch set decides how many lines share a workgroup (and
-so how many threads work on each line: 256 / lines) and how long the
-contiguous row segments of the q2-line passes are; the launch order decides
-which die (L2) runs which tiles.  Results do not depend on either: every
-line is transformed by the same arithmetic whatever its tile.  The tuner
-times the four passes of one stage through fcsd_stage_pass with HIP events
-on the library's stream, picks the fastest LDS budget for the q1-line passes
-(A, C) and for the q2-line passes (B1, B2) under each launch order, and
-keeps the order with the smallest stage time.
+The tile split of a patch set decides how many lines share a workgroup,
+the workgroup size how many threads work on each line, and the launch order
+which die (L2) runs which tiles.  Results do not depend on any of them:
+every line is transformed by the same arithmetic whatever its tile.  There
+are three tile sets -- q1 lines (passes A, C), q2 lines (pass B2), q2 lines
+with two complex lines per grid line (pass B1) -- each with its own LDS
+budget and workgroup size.  The tuner times the four passes of one stage
+through fcsd_stage_pass with HIP events on the library's stream for every
+(budget, workgroup size) candidate under each launch order, picks the best
+candidate per tile set and keeps the order with the smallest stage time.
 """
 from __future__ import annotations
 
@@ -16,9 +17,9 @@ import torch
 
 from . import api
 
-Q1_PASSES = (0, 3)   # A, C
-Q2_PASSES = (1, 2)   # B1, B2
-DEFAULT_BUDGETS = (16384, 24576, 32768, 49152, 65536, 98304, 131072, 163840)
+SET_PASSES = ((0, 3), (2,), (1,))   # tile set -> passes timed (A+C, B2, B1)
+DEFAULT_BUDGETS = (24576, 32768, 49152, 65536, 81920, 98304, 131072, 163840)
+DEFAULT_THREADS = (256, 512, 1024)
 
 
 def time_passes(s, bufs, passes, reps=3):
@@ -42,10 +43,10 @@ def time_passes(s, bufs, passes, reps=3):
     return out
 
 
-def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS,
+def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS, threads=DEFAULT_THREADS,
              orders=(api.PatchSet.ORDER_LPT, api.PatchSet.ORDER_XCD), reps=3):
-    """Choose (q1 budget, q2 budget, order) for patch set `s` on state `u`;
-    applies the choice and returns it with the timing table."""
+    """Choose the schedule of patch set `s` on state `u`; applies the choice
+    and returns it with the timing table."""
     dev = u.device
     ui = torch.empty_like(u).copy_(u)
     acc = torch.zeros_like(u)
@@ -53,30 +54,32 @@ def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS,
     if dt is None:
         dt = torch.full((1,), 1e-6, device=dev)
     bufs = (u, ui, acc, uout, metric, mu, ref, gamma, dt)
-    table = {}
-    usable = []
-    for b in budgets:
-        try:
-            s.tune(b, b, orders[0])
-            usable.append(b)
-        except api.FcsdError:      # above the device's LDS per workgroup
-            pass
-    budgets = tuple(usable)
-    for order in orders:
+    cands = []
+    for t in threads:
         for b in budgets:
-            s.tune(b, b, order)
-            t = time_passes(s, bufs, Q1_PASSES + Q2_PASSES, reps)
-            table[(order, b)] = t
+            try:
+                s.tune(b, t, orders[0])
+                cands.append((b, t))
+            except api.FcsdError:      # above the device's LDS per workgroup
+                pass
+    table = {}
+    for order in orders:
+        for (b, t) in cands:
+            s.tune(b, t, order)
+            table[(order, b, t)] = time_passes(s, bufs, (0, 1, 2, 3), reps)
     best = None
     for order in orders:
-        b1 = min(budgets, key=lambda b: sum(table[(order, b)][p] for p in Q1_PASSES))
-        b2 = min(budgets, key=lambda b: sum(table[(order, b)][p] for p in Q2_PASSES))
-        ms = sum(table[(order, b1)][p] for p in Q1_PASSES) + sum(table[(order, b2)][p] for p in Q2_PASSES)
-        if best is None or ms < best[3]:
-            best = (b1, b2, order, ms)
-    s.tune(best[0], best[1], best[2])
-    return {"q1_budget": best[0], "q2_budget": best[1], "order": "xcd" if best[2] else "lpt",
-            "stage_passes_ms": best[3],
-            "table": {f"{'xcd' if o else 'lpt'}-{b // 1024}K": {["A", "B1", "B2", "C"][p]: round(v, 4)
-                                                              for p, v in t.items()}
-                      for (o, b), t in table.items()}}
+        pick, ms = [], 0.0
+        for passes in SET_PASSES:
+            c = min(cands, key=lambda bt: sum(table[(order,) + bt][p] for p in passes))
+            pick.append(c)
+            ms += sum(table[(order,) + c][p] for p in passes)
+        if best is None or ms < best[2]:
+            best = (pick, order, ms)
+    pick, order, ms = best
+    s.tune([c[0] for c in pick], [c[1] for c in pick], order)
+    return {"budgets": [c[0] for c in pick], "threads": [c[1] for c in pick],
+            "order": "xcd" if order else "lpt", "stage_passes_ms": ms,
+            "table": {f"{'xcd' if o else 'lpt'}-{b // 1024}K-{t}": {["A", "B1", "B2", "C"][p]: round(v, 4)
+                                                                   for p, v in tm.items()}
+                      for (o, b, t), tm in table.items()}}

@@ -49,6 +49,7 @@ struct PlanDev {
   int n1, n2;    // patch shape
   int patch;     // patch index
   int periodic;  // C == 0
+  int nb1;       // 0: row-major patch storage; else 8x4 blocks, nb1 per block row
   long long off; // patch offset in a plane
 };
 
@@ -63,6 +64,7 @@ struct TileDev {
 //   z   [L * ld] float2   the lines, z[pos * ld + c]
 //   tw  [L]      float2   exp(-2 pi i n / L)
 //   km  [L]      float2   derivative multipliers by digit-reversed position
+//   side[2d * ld] float2  end samples of every line (differencing loads)
 // Thread t works on line c = t % nl and on butterflies t / nl, t / nl + BS,
 // ... of every stage (BS = blockDim / nl), so consecutive lanes touch
 // consecutive lines (conflict-free LDS rows) and share their twiddle
@@ -71,12 +73,15 @@ struct LineCtx {
   float2* z;
   const float2* tw;
   const float2* km;
+  float2* side;  // [2 kMaxD][ld]: the 2d end samples of every line (loads that difference)
   int ld, nl, c, b0, BS;
   bool active;
 };
 
-__device__ __forceinline__ size_t tile_lds_bytes(int L, int ld) {
-  return (size_t)L * ld * sizeof(float2) + (size_t)L * 2 * sizeof(float2);
+constexpr int kMaxD = 8;
+
+__device__ __forceinline__ size_t tile_lds_bytes(int L, int ld, int d) {
+  return (size_t)L * ld * sizeof(float2) + (size_t)L * 2 * sizeof(float2) + (size_t)2 * d * ld * sizeof(float2);
 }
 
 // Copy the plan's twiddles and multipliers into LDS; the caller syncs.
@@ -92,6 +97,7 @@ __device__ __forceinline__ LineCtx line_setup(float2* lds, const TileDev& T, con
   }
   X.tw = tw;
   X.km = km;
+  X.side = km + P.L;
   X.ld = T.ld;
   X.nl = T.nl;
   X.BS = blockDim.x / T.nl;
@@ -101,76 +107,123 @@ __device__ __forceinline__ LineCtx line_setup(float2* lds, const TileDev& T, con
   return X;
 }
 
-// Visit the N x nl elements of a tile, f(pos, c), in the order that
-// coalesces global memory: q1 lines (DIR 1) pos-fastest, q2 lines (DIR 2)
-// line-fastest.  Index steps are incremental (no division in the loop).
-template <int DIR, class F>
-__device__ __forceinline__ void for_elems(int N, int nl, F&& f) {
-  const int na = DIR == 1 ? N : nl;
-  const int nbb = DIR == 1 ? nl : N;
-  int a = threadIdx.x % na, b = threadIdx.x / na;
-  const int sa = blockDim.x % na, sb = blockDim.x / na;
-  while (b < nbb) {
-    if (DIR == 1)
-      f(a, b);
-    else
-      f(b, a);
-    a += sa;
-    b += sb;
-    if (a >= na) {
-      a -= na;
-      ++b;
+// Elements (pos, c) of a tile in the order that coalesces global memory,
+// visited by thread t at steps t, t + blockDim, ... with incremental index
+// updates (no division per element).  Row-major storage: q1 lines (DIR 1)
+// pos-fastest, q2 lines (DIR 2) line-fastest.  8x4-blocked storage (tiles
+// start on block boundaries): storage order, whole 128-byte blocks -- for q1
+// tiles, strips of 4 lines block by block along the line; for q2 tiles,
+// groups of 4 samples by column blocks of 8 lines.  blockDim is a multiple
+// of 32, so a thread keeps its place w inside a block and only the block
+// index advances.
+template <int DIR>
+struct ElemIter {
+  bool blocked;
+  int N, nl;
+  // row-major: element (a, b) along the fast / slow extents
+  int a = 0, b = 0, na = 1, nbb = 0, sa = 0, sb = 0;
+  // blocked: block (slow, fast), place w in the block (every member is
+  // initialised on both paths so the iterator stays in registers)
+  int slow = 0, fast = 0, nbf = 1, nslow = 0, dslow = 0, dfast = 0, w = 0;
+
+  __device__ __forceinline__ ElemIter(int N_, int nl_, int nb1, int e0) : blocked(nb1 != 0), N(N_), nl(nl_) {
+    if (!blocked) {
+      na = DIR == 1 ? N : nl;
+      nbb = DIR == 1 ? nl : N;
+      a = e0 % na;
+      b = e0 / na;
+      sa = blockDim.x % na;
+      sb = blockDim.x / na;
+    } else {
+      nbf = DIR == 1 ? (N + 7) >> 3 : (nl + 7) >> 3;     // blocks along the fast block axis
+      nslow = DIR == 1 ? (nl + 3) >> 2 : (N + 3) >> 2;   // strips (DIR 1) / sample groups (DIR 2)
+      const int blk = e0 >> 5, db = blockDim.x >> 5;
+      w = e0 & 31;
+      slow = blk / nbf;
+      fast = blk - slow * nbf;
+      dslow = db / nbf;
+      dfast = db - dslow * nbf;
     }
   }
-}
-
-// Batched variant of for_elems for memory-latency-bound phases: pre(pos, c)
-// issues the loads of U consecutive elements of the thread, then post(pos,
-// c, value) consumes them.  pre runs unconditionally (elements past the end
-// read element (0, 0) of the tile and are dropped), so the loads are
-// straight-line code and all U are in flight together; pre should only
-// load, and leave arithmetic to post.
-template <int DIR, int U, class Pre, class Post>
-__device__ __forceinline__ void for_elems_b(int N, int nl, Pre&& pre, Post&& post) {
-  using T = decltype(pre(0, 0));
-  const int na = DIR == 1 ? N : nl;
-  const int nbb = DIR == 1 ? nl : N;
-  int a = threadIdx.x % na, b = threadIdx.x / na;
-  const int sa = blockDim.x % na, sb = blockDim.x / na;
-  while (b < nbb) {
-    T v[U];
-    int ia[U], ib[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      ia[u] = a;
-      ib[u] = b;
-      const bool ok = b < nbb;
-      const int ca = ok ? a : 0, cb = ok ? b : 0;
-      v[u] = DIR == 1 ? pre(ca, cb) : pre(cb, ca);
+  __device__ __forceinline__ bool more() const { return blocked ? slow < nslow : b < nbb; }
+  // current element; false if it lies past the tile's lines or samples
+  __device__ __forceinline__ bool get(int& pos, int& c) const {
+    if (!blocked) {
+      pos = DIR == 1 ? a : b;
+      c = DIR == 1 ? b : a;
+      return b < nbb;
+    }
+    if (DIR == 1) {
+      c = (slow << 2) + (w >> 3);
+      pos = (fast << 3) + (w & 7);
+    } else {
+      c = (fast << 3) + (w & 7);
+      pos = (slow << 2) + (w >> 3);
+    }
+    return slow < nslow && c < nl && pos < N;
+  }
+  __device__ __forceinline__ void next() {
+    if (!blocked) {
       a += sa;
       b += sb;
       if (a >= na) {
         a -= na;
         ++b;
       }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (ib[u] < nbb) {
-        if (DIR == 1)
-          post(ia[u], ib[u], v[u]);
-        else
-          post(ib[u], ia[u], v[u]);
+    } else {
+      fast += dfast;
+      slow += dslow;
+      if (fast >= nbf) {
+        fast -= nbf;
+        ++slow;
       }
     }
+  }
+};
+
+// Visit the elements of a tile, f(pos, c), in the coalescing order.
+template <int DIR, class F>
+__device__ __forceinline__ void for_elems(int N, int nl, int nb1, F&& f) {
+  ElemIter<DIR> it(N, nl, nb1, threadIdx.x);
+  for (; it.more(); it.next()) {
+    int pos, c;
+    if (it.get(pos, c)) f(pos, c);
+  }
+}
+
+// Batched variant for memory-latency-bound phases: pre(pos, c) issues the
+// loads of U elements of the thread, then post(pos, c, value) consumes
+// them.  pre runs unconditionally (elements past the end read element
+// (0, 0) of the tile and are dropped), so the loads are straight-line code
+// and all U are in flight together; pre should only load, and leave
+// arithmetic to post.
+template <int DIR, int U, class Pre, class Post>
+__device__ __forceinline__ void for_elems_b(int N, int nl, int nb1, Pre&& pre, Post&& post) {
+  using T = decltype(pre(0, 0));
+  ElemIter<DIR> it(N, nl, nb1, threadIdx.x);
+  while (it.more()) {
+    T v[U];
+    int ps[U], cs[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ok[u] = it.get(ps[u], cs[u]);
+      v[u] = pre(ok[u] ? ps[u] : 0, ok[u] ? cs[u] : 0);
+      it.next();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) post(ps[u], cs[u], v[u]);
   }
 }
 
 // One radix-R stage.  Forward (DIF): block of M points, m = M/R, butterfly j
 // reads x_t = z[base + j + t m], y = DFT_R(x), y_q *= w_M^(j q), stores back.
 // Inverse (DIT): the exact reverse with conjugate twiddles.  MUL (last
-// forward stage, M = R): multiply the outputs by km[pos] (CONJ: by its
-// conjugate, the transposed operator).
+// forward stage, M = R, m = 1, no twiddles): multiply the outputs by
+// km[pos] (CONJ: by its conjugate, the transposed operator) and apply the
+// first inverse stage, which works on the same R contiguous samples without
+// twiddles, before storing: one LDS round trip and one barrier fewer.
 template <int R, bool INV, bool MUL, bool CONJ>
 __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
   if (!X.active) return;
@@ -192,6 +245,7 @@ __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
       if (MUL) {
 #pragma unroll
         for (int q = 0; q < R; ++q) x[q] = CONJ ? cmulc(x[q], X.km[base + q]) : cmul(x[q], X.km[base + q]);
+        Dft<R, true>::run(x);
       } else if (j) {
 #pragma unroll
         for (int q = 1; q < R; ++q) x[q] = cmul(x[q], X.tw[stride * j * q]);
@@ -339,6 +393,66 @@ __device__ __forceinline__ void difference_ext(const LineCtx& X, const PlanDev& 
   __syncthreads();
 }
 
+// Load a pair of planes (A, B) along the tile's lines (complex line
+// c0 + c holds line c of A in re, of B in im) and write the interior of the
+// differenced extension at once: z[n] = f[n+1] - f[n] for n < N-1 (the
+// second sample comes from the same or the next cache line).  The 2d end
+// samples, minus the reference (ra, rb), go to the side buffer for
+// diff_tail.  Replaces a load followed by difference_ext: one LDS pass and
+// two barriers fewer.  The caller syncs, runs diff_tail, syncs.
+template <int DIR, int U, class G>
+__device__ __forceinline__ void load_differenced(const LineCtx& X, const PlanDev& P, int nl, int c0, G&& gidx,
+                                                 const float* __restrict__ A, const float* __restrict__ B,
+                                                 float ra, float rb, int d) {
+  const int N = P.N, ld = X.ld;
+  float2* __restrict__ z = X.z;
+  float2* __restrict__ side = X.side;
+  for_elems_b<DIR, U>(
+      N, nl, P.nb1,
+      [&](int pos, int c) {
+        const long long g = gidx(pos, c);
+        const long long g2 = gidx(pos + 1 < N ? pos + 1 : pos, c);
+        return make_float4(A[g], B[g], A[g2], B[g2]);
+      },
+      [&](int pos, int c, float4 v) {
+        const int cc = c0 + c;
+        if (pos < N - 1) z[pos * ld + cc] = make_float2(v.z - v.x, v.w - v.y);
+        if (pos < d) side[pos * ld + cc] = make_float2(v.x - ra, v.y - rb);
+        if (pos >= N - d) side[(pos - N + 2 * d) * ld + cc] = make_float2(v.x - ra, v.y - rb);
+      });
+}
+
+// The C + 1 differences that involve the tail (FP64 rows of the
+// differenced continuation table applied to the end samples in the side
+// buffer), or the periodic wrap f[0] - f[N-1], written to positions
+// N-1 .. L-1 of every line of the tile.
+__device__ __forceinline__ void diff_tail(const LineCtx& X, const PlanDev& P, const double* __restrict__ dq, int d) {
+  if (!X.active) return;
+  const int N = P.N, C = P.C, ld = X.ld, c = X.c;
+  float2* __restrict__ z = X.z;
+  const float2* __restrict__ side = X.side;
+  if (P.periodic) {
+    if (X.b0 == 0) {
+      const float2 a = side[c], b = side[(2 * d - 1) * ld + c];
+      z[(N - 1) * ld + c] = make_float2(a.x - b.x, a.y - b.y);
+    }
+    return;
+  }
+  for (int r = X.b0; r <= C; r += X.BS) {
+    const double* q = dq + (size_t)r * 2 * d;
+    double sx = 0.0, sy = 0.0;
+    for (int j = 0; j < d; ++j) {
+      const float2 fr = side[(d + j) * ld + c];
+      const float2 fl = side[j * ld + c];
+      sx = fma(q[j], (double)fr.x, sx);
+      sy = fma(q[j], (double)fr.y, sy);
+      sx = fma(q[d + j], (double)fl.x, sx);
+      sy = fma(q[d + j], (double)fl.y, sy);
+    }
+    z[(N - 1 + r) * ld + c] = make_float2((float)sx, (float)sy);
+  }
+}
+
 // Delta^T of the zero-padded cotangent in place (transposed operator):
 // (Delta^T x)[n] = x[n-1] - x[n], cyclic, with x = [y; 0].  Positions N.. are
 // written in phase 1 (y[N-1] at N, zeros after), the first N in phase 2 from
@@ -373,15 +487,12 @@ __device__ __forceinline__ void difference_adj(const LineCtx& X, const PlanDev& 
   __syncthreads();
 }
 
-// Derivative of the tile in place; the caller has filled positions 0..N-1
-// and synchronised.  ADJ = transpose (Delta^T, conjugate multipliers, fold).
+// FFT part of the derivative: forward stages (the last one fused with the
+// multiplier and the first inverse stage), inverse stages.  The caller has
+// written the differenced extension (or, for ADJ, Delta^T of the padded
+// cotangent) and synchronised.
 template <bool ADJ>
-__device__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
-                                const double* __restrict__ aqp, const double* __restrict__ dqp, int d) {
-  if (!ADJ)
-    difference_ext(X, P, dqp + P.dq, d);
-  else
-    difference_adj(X, P);
+__device__ __forceinline__ void fft_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P) {
   // radices are read from the (uniform) plan in global memory: a private
   // array indexed by the stage counter would live in scratch
   const int* rad = Pg->rad;
@@ -396,13 +507,26 @@ __device__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg
     M /= R;
     __syncthreads();
   }
-  M = 1;
-  for (int s = nst - 1; s >= 0; --s) {
+  // the last forward stage already applied the first inverse stage
+  M = rad[nst - 1];
+  for (int s = nst - 2; s >= 0; --s) {
     const int R = rad[s];
     M *= R;
     fft_dispatch<true, false, ADJ>(R, X, P.L, M);
     __syncthreads();
   }
+}
+
+// Derivative of the tile in place; the caller has filled positions 0..N-1
+// and synchronised.  ADJ = transpose (Delta^T, conjugate multipliers, fold).
+template <bool ADJ>
+__device__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
+                                const double* __restrict__ aqp, const double* __restrict__ dqp, int d) {
+  if (!ADJ)
+    difference_ext(X, P, dqp + P.dq, d);
+  else
+    difference_adj(X, P);
+  fft_derivative<ADJ>(X, Pg, P);
   if (ADJ && !P.periodic) {
     fold_tail(X, P, aqp + P.aq, d);
     __syncthreads();

@@ -47,6 +47,8 @@ namespace {
 // grid line in LDS (1, or 2 for the H pass, which transforms all four state
 // components at once).
 struct TileSet {
+  size_t budget = 0;                      // LDS budget per workgroup (bytes)
+  int threads = kBlock;                   // workgroup size
   std::vector<TileDev> tiles;             // launch order (LPT or XCD-grouped)
   std::vector<TileDev> tiles_by_patch;    // patch-contiguous
   std::vector<int> patch_begin;           // npatch + 1
@@ -89,7 +91,9 @@ struct fcsd_set {
   int annulus = 0;
   AnnulusDev an{};
   std::vector<GraphEntry> graphs;
-  size_t lds_budget[2] = {0, 0};
+
+  int layout = FCSD_LAYOUT_ROWS;
+
   int tile_order = FCSD_ORDER_XCD;
 };
 
@@ -164,7 +168,7 @@ fcsd_status launch_lines(const fcsd_set* s, int dir, K kern, PassArgs a, int pat
     lds = D.patch_lds[patch];
   }
   if (grid == 0) return FCSD_OK;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s->ctx->stream, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(D.threads), lds, s->ctx->stream, a);
   return launch_check(s->ctx, "line kernel");
 }
 
@@ -174,6 +178,12 @@ fcsd_status check_set(fcsd_ctx* ctx, const fcsd_set* s, int64_t plane) {
   if (s->ctx != ctx) return fail(ctx, FCSD_EINVAL, "patch set belongs to another context");
   if (plane != s->plane) return fail(ctx, FCSD_EINVAL, "plane size differs from the patch set's");
   return FCSD_OK;
+}
+
+// elements of a patch's storage (blocked: padded to whole 8x4 blocks)
+long long patch_storage(int n1, int n2, int layout) {
+  if (layout == FCSD_LAYOUT_B8X4) return (long long)((n1 + 7) & ~7) * ((n2 + 3) & ~3);
+  return (long long)n1 * n2;
 }
 
 // step reverse mode: 5 stage inputs (20), forward registers (8), cotangents
@@ -266,12 +276,14 @@ extern "C" fcsd_status fcsd_fft_plan(int L, int* nst, int rad[8]) {
 
 // Validate a patch table without a device (also used by fcsd_set_create).
 extern "C" fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* p, int d, int64_t plane,
-                                             int ring_sectors, int ring_shells, char* msg, int msglen) {
+                                             int ring_sectors, int ring_shells, int layout, char* msg,
+                                             int msglen) {
   auto say = [&](const std::string& m) {
     if (msg && msglen > 0) snprintf(msg, (size_t)msglen, "%s", m.c_str());
   };
   if (npatch <= 0 || !p) return say("no patches"), FCSD_EINVAL;
   if (d < 1 || d > 8) return say("d must be in 1..8"), FCSD_EINVAL;
+  if (layout != FCSD_LAYOUT_ROWS && layout != FCSD_LAYOUT_B8X4) return say("unknown layout"), FCSD_EINVAL;
   std::vector<std::pair<long long, long long>> iv;
   for (int i = 0; i < npatch; ++i) {
     const fcsd_patch_desc& q = p[i];
@@ -284,8 +296,13 @@ extern "C" fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* 
       snprintf(b, sizeof b, "patch %d: C must be in [0, 256]", i);
       return say(b), FCSD_EINVAL;
     }
-    if (q.off < 0 || q.off + (long long)q.n1 * q.n2 > plane) {
+    const long long store = patch_storage(q.n1, q.n2, layout);
+    if (q.off < 0 || q.off + store > plane) {
       snprintf(b, sizeof b, "patch %d lies outside the plane", i);
+      return say(b), FCSD_EINVAL;
+    }
+    if (layout == FCSD_LAYOUT_B8X4 && q.off % 32 != 0) {
+      snprintf(b, sizeof b, "patch %d: blocked storage needs an offset that is a multiple of 32", i);
       return say(b), FCSD_EINVAL;
     }
     if (!(q.htilde > 0) || !(q.hhat > 0)) {
@@ -300,7 +317,7 @@ extern "C" fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* 
         return say(b), FCSD_EUNSUPPORTED;
       }
     }
-    iv.push_back({q.off, q.off + (long long)q.n1 * q.n2});
+    iv.push_back({q.off, q.off + store});
   }
   std::sort(iv.begin(), iv.end());
   for (size_t i = 1; i < iv.size(); ++i)
@@ -331,7 +348,8 @@ size_t default_lds_budget() {
 // L2) round-robin by workgroup index.
 constexpr int kXcd = 8;
 
-void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget, int order, int fields) {
+void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget, int order, int fields, int align,
+                   int d) {
   D.tiles_by_patch.clear();
   D.patch_begin.assign(1, 0);
   D.patch_lds.clear();
@@ -339,12 +357,14 @@ void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget,
   std::vector<long long> pcost;
   for (size_t p = 0; p < plans.size(); ++p) {
     const PlanDev& P = plans[p];
+    // LDS: lines (L x ld), twiddle and multiplier tables (2 L), end samples (2d x ld)
     const size_t tables = (size_t)P.L * 2 * sizeof(float2);
-    int nlmax = budget > tables ? (int)((budget - tables) / (sizeof(float2) * (size_t)P.L)) - 1 : 1;
+    const size_t per_ld = sizeof(float2) * ((size_t)P.L + 2 * (size_t)d);
+    int nlmax = budget > tables ? (int)((budget - tables) / per_ld) - 1 : 1;
     nlmax = std::max(1, std::min(kMaxTile, nlmax)) / fields;
-    nlmax = std::max(1, nlmax);
+    nlmax = std::max(align, nlmax / align * align);  // blocked storage: tiles start on block edges
     const int nt = (P.nlines + nlmax - 1) / nlmax;
-    const int nl = (P.nlines + nt - 1) / nt;
+    const int nl = ((P.nlines + nt - 1) / nt + align - 1) / align * align;
     size_t plds = 0;
     long long cost = 0;
     for (int t = 0; t < nt; ++t) {
@@ -355,7 +375,7 @@ void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget,
       if (T.nl <= 0) continue;
       T.ld = (fields * T.nl) | 1;
       D.tiles_by_patch.push_back(T);
-      plds = std::max(plds, (size_t)P.L * T.ld * sizeof(float2) + tables);
+      plds = std::max(plds, per_ld * T.ld + tables);
       cost += (long long)P.L * T.nl;
     }
     D.patch_begin.push_back((int)D.tiles_by_patch.size());
@@ -400,9 +420,12 @@ void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget,
     for (size_t k = 0; k < lst[x].size(); ++k) D.tiles[k * kXcd + x] = lst[x][k];
 }
 
-void build_tiles(DirPlan& D, size_t budget, int order) {
-  for (int f = 0; f < 2; ++f) build_tileset(D.plans, D.ts[f], budget, order, f + 1);
+// align: lines per tile a multiple of it (blocked storage: 4 q1 lines, 8 q2 lines)
+void build_tiles(DirPlan& D, int order, int align, int d) {
+  for (int f = 0; f < 2; ++f) build_tileset(D.plans, D.ts[f], D.ts[f].budget, order, f + 1, align, d);
 }
+
+int tile_align(int layout, int dir) { return layout == FCSD_LAYOUT_B8X4 ? (dir == 0 ? 4 : 8) : 1; }
 
 fcsd_status upload_tiles(fcsd_ctx* ctx, DirPlan& D) {
   for (auto& t : D.ts) {
@@ -420,11 +443,12 @@ fcsd_status upload_tiles(fcsd_ctx* ctx, DirPlan& D) {
 // ======================================================================== patch set
 
 extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_patch_desc* patches, int d,
-                                       int64_t plane, int ring_sectors, int ring_shells, fcsd_set** out) {
+                                       int64_t plane, int ring_sectors, int ring_shells, int layout,
+                                       fcsd_set** out) {
   if (!ctx || !out) return FCSD_EINVAL;
   *out = nullptr;
   char msg[256] = {0};
-  fcsd_status st = fcsd_validate_patches(npatch, patches, d, plane, ring_sectors, ring_shells, msg, 256);
+  fcsd_status st = fcsd_validate_patches(npatch, patches, d, plane, ring_sectors, ring_shells, layout, msg, 256);
   if (st != FCSD_OK) return fail(ctx, st, msg);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   std::unique_ptr<fcsd_set> s(new fcsd_set);
@@ -432,6 +456,7 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   s->npatch = npatch;
   s->d = d;
   s->plane = plane;
+  s->layout = layout;
   s->desc.assign(patches, patches + npatch);
   // pools
   std::vector<float2> tw;
@@ -455,6 +480,7 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
       P.n1 = q.n1;
       P.n2 = q.n2;
       P.patch = p;
+      P.nb1 = layout == FCSD_LAYOUT_B8X4 ? (q.n1 + 7) >> 3 : 0;
       P.off = q.off;
       if (!tw_of_L.count(P.L)) {
         tw_of_L[P.L] = (int)tw.size();
@@ -493,8 +519,10 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
     }
     D.ext_plane = eo;
   }
-  s->lds_budget[0] = s->lds_budget[1] = default_lds_budget();
-  for (int dir = 0; dir < 2; ++dir) build_tiles(s->dir[dir], s->lds_budget[dir], s->tile_order);
+  for (int dir = 0; dir < 2; ++dir) {
+    for (auto& t : s->dir[dir].ts) t.budget = default_lds_budget();
+    build_tiles(s->dir[dir], s->tile_order, tile_align(layout, dir), d);
+  }
   // per-patch descriptors and point chunks
   std::vector<PatchDev> pd;
   std::vector<ChunkDev> ch;
@@ -507,10 +535,11 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
     P.hhat = (float)q.hhat;
     P.htilde = (float)q.htilde;
     P.internal = (q.internal[0] ? 1 : 0) | (q.internal[1] ? 2 : 0) | (q.internal[2] ? 4 : 0) | (q.internal[3] ? 8 : 0);
-    P.pad = 0;
+    P.nb1 = layout == FCSD_LAYOUT_B8X4 ? (q.n1 + 7) >> 3 : 0;
     pd.push_back(P);
     s->patch_chunk_begin.push_back((int)ch.size());
-    for (int k = 0; k < q.n1 * q.n2; k += kChunk) ch.push_back(ChunkDev{p, k});
+    const long long store = patch_storage(q.n1, q.n2, layout);
+    for (long long k = 0; k < store; k += kChunk) ch.push_back(ChunkDev{p, (int)k});
     s->npoints += (long long)q.n1 * q.n2;
   }
   s->patch_chunk_begin.push_back((int)ch.size());
@@ -589,26 +618,38 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   return FCSD_OK;
 }
 
-extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, int lds_budget_q1, int lds_budget_q2, int order) {
-  if (!s) return FCSD_EINVAL;
+extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const int threads[3], int order) {
+  if (!s || !lds_budget || !threads) return FCSD_EINVAL;
   fcsd_ctx* ctx = s->ctx;
-  const int bud[2] = {lds_budget_q1, lds_budget_q2};
-  for (int b : bud)
-    if (b < 8192 || b > 160 * 1024) return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget must be in [8 KB, 160 KB]");
-  if (order != FCSD_ORDER_LPT && order != FCSD_ORDER_XCD) return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: bad order");
   int maxlds = 0;
   HIPCHK(ctx, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-  for (int b : bud)
-    if (b > maxlds) return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget above the device's LDS per workgroup");
+  for (int k = 0; k < 3; ++k) {
+    if (lds_budget[k] < 8192 || lds_budget[k] > 160 * 1024)
+      return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget must be in [8 KB, 160 KB]");
+    if (lds_budget[k] > maxlds)
+      return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: budget above the device's LDS per workgroup");
+    const int t = threads[k];
+    if (t != 64 && t != 128 && t != 256 && t != 512 && t != 1024)
+      return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: threads must be 64, 128, 256, 512 or 1024");
+  }
+  if (order != FCSD_ORDER_LPT && order != FCSD_ORDER_XCD) return fail(ctx, FCSD_EINVAL, "fcsd_set_tune: bad order");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& g : s->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   s->graphs.clear();
   s->tile_order = order;
+  // tile sets: q1 lines; q2 lines; q2 lines with two complex lines per grid line
+  s->dir[0].ts[0].budget = (size_t)lds_budget[0];
+  s->dir[0].ts[0].threads = threads[0];
+  s->dir[0].ts[1].budget = (size_t)lds_budget[0];
+  s->dir[0].ts[1].threads = threads[0];
+  s->dir[1].ts[0].budget = (size_t)lds_budget[1];
+  s->dir[1].ts[0].threads = threads[1];
+  s->dir[1].ts[1].budget = (size_t)lds_budget[2];
+  s->dir[1].ts[1].threads = threads[2];
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
-    s->lds_budget[dir] = (size_t)bud[dir];
-    build_tiles(D, s->lds_budget[dir], order);
+    build_tiles(D, order, tile_align(s->layout, dir), s->d);
     fcsd_status r;
     if ((r = upload_tiles(ctx, D))) return r;
   }
@@ -1182,7 +1223,7 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
     PassArgs b = a;
     b.plans = D.d_plans;
     b.tiles = D.ts[0].d_tiles;
-    hipLaunchKernelGGL(k_adjHb<1>, dim3((unsigned)D.ts[0].tiles.size()), dim3(kBlock), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
+    hipLaunchKernelGGL(k_adjHb<1>, dim3((unsigned)D.ts[0].tiles.size()), dim3(D.ts[0].threads), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
                        (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
     if ((st = launch_check(ctx, "adj C"))) return st;
   }
@@ -1191,7 +1232,7 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
     PassArgs b = a;
     b.plans = D.d_plans;
     b.tiles = D.ts[0].d_tiles;
-    hipLaunchKernelGGL(k_adjHb<2>, dim3((unsigned)D.ts[0].tiles.size()), dim3(kBlock), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
+    hipLaunchKernelGGL(k_adjHb<2>, dim3((unsigned)D.ts[0].tiles.size()), dim3(D.ts[0].threads), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
                        (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
     if ((st = launch_check(ctx, "adj B2"))) return st;
   }

@@ -58,12 +58,14 @@ enum { MODE_SET = 0, MODE_ADD = 1, MODE_RK = 2 };
 
 // Line kernels: 256 threads, registers capped for five waves per SIMD (the
 // butterflies fit in ~96 VGPRs without spilling; five 32 KB tiles fill the LDS)
-#define FCSD_LINE_BOUNDS __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+#define FCSD_LINE_BOUNDS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
 
 // elements per thread whose loads are in flight together
-constexpr int kLoadBatch = 16;  // load phases (two floats each)
+constexpr int kLoadBatch = 12;  // load phases (two floats each)
 constexpr int kEpiBatch = 8;    // epilogues (point inputs)
 constexpr int kEpiBatchH = 4;   // H epilogue (thirteen inputs per point)
+constexpr int kEpiBatchC = 6;   // stage-update epilogue (six inputs per point)
+constexpr int kDiffBatch = 6;   // differencing loads (four floats each)
 enum { FLUX_FULL = 0, FLUX_VISC = 1, FLUX_INVISCID = 2 };
 
 // SSPRK(5,4) Shu-Osher coefficients (five stages, fourth order)
@@ -105,8 +107,10 @@ __device__ __forceinline__ void dev_flux(const float e[4], const float er[4], co
 // plane index of element (pos, c) of a tile
 template <int DIR>
 __device__ __forceinline__ long long gindex(const PlanDev& P, const TileDev& T, int pos, int c) {
-  return DIR == 1 ? P.off + (long long)(T.line0 + c) * P.n1 + pos
-                  : P.off + (long long)pos * P.n1 + (T.line0 + c);
+  const int i = DIR == 1 ? pos : T.line0 + c;
+  const int j = DIR == 1 ? T.line0 + c : pos;
+  if (P.nb1 == 0) return P.off + (long long)j * P.n1 + i;
+  return P.off + ((((long long)(j >> 2)) * P.nb1 + (i >> 3)) << 5) + ((j & 3) << 3) + (i & 7);
 }
 
 extern __shared__ float2 lds_z[];
@@ -124,6 +128,14 @@ extern __shared__ float2 lds_z[];
   (void)nl;                                                                  \
   __syncthreads();
 
+// Forward derivative of pairs already loaded by load_differenced: tail
+// differences, then the FFT part.
+#define FCSD_DIFF_AND_TRANSFORM(a)                                           \
+  __syncthreads();                                                           \
+  diff_tail(X, P, (a).dq + P.dq, (a).d);                                     \
+  __syncthreads();                                                           \
+  fft_derivative<false>(X, Pg, P);
+
 // ---------------------------------------------------------------- generic line ops
 
 // fc_diff / fc_diff_adj on nf fields, packed two per complex line.
@@ -135,18 +147,24 @@ __global__ void FCSD_LINE_BOUNDS k_fcdiff(PassArgs a) {
     const float* A = a.in + (long long)f * a.plane;
     const float* B = a.in + (long long)(f + 1) * a.plane;
     const float* Bs = two ? B : A;
-    for_elems_b<DIR, 8>(
-        N, nl,
-        [&](int pos, int c) {
-          const long long g = gindex<DIR>(P, T, pos, c);
-          return make_float2(A[g], Bs[g]);
-        },
-        [&](int pos, int c, float2 v) { z[pos * ld + c] = make_float2(v.x, two ? v.y : 0.f); });
-    __syncthreads();
-    line_derivative<ADJ>(X, Pg, P, a.aq, a.dq, a.d);
+    if (!ADJ) {
+      load_differenced<DIR, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<DIR>(P, T, pos, c); }, A, Bs,
+                               0.f, 0.f, a.d);
+      FCSD_DIFF_AND_TRANSFORM(a)
+    } else {
+      for_elems_b<DIR, 8>(
+          N, nl, P.nb1,
+          [&](int pos, int c) {
+            const long long g = gindex<DIR>(P, T, pos, c);
+            return make_float2(A[g], Bs[g]);
+          },
+          [&](int pos, int c, float2 v) { z[pos * ld + c] = make_float2(v.x, two ? v.y : 0.f); });
+      __syncthreads();
+      line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
+    }
     float* OA = a.out + (long long)f * a.plane;
     float* OB = a.out + (long long)(f + 1) * a.plane;
-    for_elems<DIR>(N, nl, [&](int pos, int c) {
+    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       if (ADJ) {
@@ -172,7 +190,7 @@ __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
     if (!ADJ) {
       const float* A = a.in + (long long)f * a.plane;
       const float* B = a.in + (long long)(f + 1) * a.plane;
-      for_elems<DIR>(N, nl, [&](int pos, int c) {
+      for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
         const long long g = gindex<DIR>(P, T, pos, c);
         z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
       });
@@ -181,7 +199,7 @@ __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
       __syncthreads();
       float* OA = a.out + (long long)f * a.ext_plane + e0;
       float* OB = a.out + (long long)(f + 1) * a.ext_plane + e0;
-      for_elems<1>(L, nl, [&](int pos, int c) {
+      for_elems<1>(L, nl, 0, [&](int pos, int c) {
         const float2 v = z[pos * ld + c];
         OA[(long long)c * L + pos] = v.x;
         if (two) OB[(long long)c * L + pos] = v.y;
@@ -189,7 +207,7 @@ __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
     } else {
       const float* A = a.in + (long long)f * a.ext_plane + e0;
       const float* B = a.in + (long long)(f + 1) * a.ext_plane + e0;
-      for_elems<1>(L, nl, [&](int pos, int c) {
+      for_elems<1>(L, nl, 0, [&](int pos, int c) {
         z[pos * ld + c] = make_float2(A[(long long)c * L + pos], two ? B[(long long)c * L + pos] : 0.f);
       });
       __syncthreads();
@@ -197,7 +215,7 @@ __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
       __syncthreads();
       float* OA = a.out + (long long)f * a.plane;
       float* OB = a.out + (long long)(f + 1) * a.plane;
-      for_elems<DIR>(N, nl, [&](int pos, int c) {
+      for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
         const long long g = gindex<DIR>(P, T, pos, c);
         const float2 v = z[pos * ld + c];
         OA[g] += v.x;
@@ -217,19 +235,14 @@ __global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
   for (int f = 0; f < 4; f += 2) {
     const float* A = a.u + (long long)f * a.plane;
     const float* B = a.u + (long long)(f + 1) * a.plane;
-    const float ra = a.eref[f], rb = a.eref[f + 1];
-    for_elems_b<DIR, kLoadBatch>(
-        N, nl,
-        [&](int pos, int c) {
-          const long long g = gindex<DIR>(P, T, pos, c);
-          return make_float2(A[g], B[g]);
-        },
-        [&](int pos, int c, float2 v) { z[pos * ld + c] = make_float2(v.x - ra, v.y - rb); });
-    __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
+    // constant indices: a runtime index into the argument array would live in scratch
+    const float ra = f == 0 ? a.eref[0] : a.eref[2], rb = f == 0 ? a.eref[1] : a.eref[3];
+    load_differenced<DIR, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<DIR>(P, T, pos, c); }, A, B,
+                                      ra, rb, a.d);
+    FCSD_DIFF_AND_TRANSFORM(a)
     float* OA = a.out + (long long)f * a.plane;
     float* OB = a.out + (long long)(f + 1) * a.plane;
-    for_elems<DIR>(N, nl, [&](int pos, int c) {
+    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       OA[g] = v.x;
@@ -284,21 +297,13 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
   const int N = P.N, nl = T.nl, ld = T.ld;
   const long long pl = a.plane;
   __syncthreads();
-  for_elems_b<2, kLoadBatch / 2>(
-      N, nl,
-      [&](int pos, int c) {
-        const long long g = gindex<2>(P, T, pos, c);
-        return make_float4(a.u[g], a.u[pl + g], a.u[2 * pl + g], a.u[3 * pl + g]);
-      },
-      [&](int pos, int c, float4 v) {
-        z[pos * ld + c] = make_float2(v.x - a.eref[0], v.y - a.eref[1]);
-        z[pos * ld + nl + c] = make_float2(v.z - a.eref[2], v.w - a.eref[3]);
-      });
-  __syncthreads();
-  line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
+  auto gi = [&](int pos, int c) { return gindex<2>(P, T, pos, c); };
+  load_differenced<2, kDiffBatch>(X, P, nl, 0, gi, a.u, a.u + pl, a.eref[0], a.eref[1], a.d);
+  load_differenced<2, kDiffBatch>(X, P, nl, nl, gi, a.u + 2 * pl, a.u + 3 * pl, a.eref[2], a.eref[3], a.d);
+  FCSD_DIFF_AND_TRANSFORM(a)
   const int flux = a.mode;
   for_elems_b<2, kEpiBatchH>(
-      N, nl, [&](int pos, int c) { return load_H4_inputs(a, gindex<2>(P, T, pos, c), flux); },
+      N, nl, P.nb1, [&](int pos, int c) { return load_H4_inputs(a, gindex<2>(P, T, pos, c), flux); },
       [&](int pos, int c, const HIn4& q) {
         const long long g = gindex<2>(P, T, pos, c);
         const float2 za = z[pos * ld + c], zb = z[pos * ld + nl + c];
@@ -345,17 +350,11 @@ __global__ void FCSD_LINE_BOUNDS k_passB2(PassArgs a) {
   for (int comp = 0; comp < 4; ++comp) {
     const float* A = a.H + (long long)(2 * comp) * pl;
     const float* B = a.H + (long long)(2 * comp + 1) * pl;
+    load_differenced<2, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<2>(P, T, pos, c); }, A, B,
+                                    0.f, 0.f, a.d);
+    FCSD_DIFF_AND_TRANSFORM(a)
     for_elems_b<2, kLoadBatch>(
-        N, nl,
-        [&](int pos, int c) {
-          const long long g = gindex<2>(P, T, pos, c);
-          return make_float2(A[g], B[g]);
-        },
-        [&](int pos, int c, float2 v) { z[pos * ld + c] = v; });
-    __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
-    for_elems_b<2, kLoadBatch>(
-        N, nl,
+        N, nl, P.nb1,
         [&](int pos, int c) {
           const long long g = gindex<2>(P, T, pos, c);
           return make_float2(a.metric[2 * pl + g], a.metric[3 * pl + g]);
@@ -380,15 +379,9 @@ __global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
   for (int comp = 0; comp < 4; ++comp) {
     const float* A = a.H + (long long)(2 * comp) * pl;
     const float* B = a.H + (long long)(2 * comp + 1) * pl;
-    for_elems_b<1, kLoadBatch>(
-        N, nl,
-        [&](int pos, int c) {
-          const long long g = gindex<1>(P, T, pos, c);
-          return make_float2(A[g], B[g]);
-        },
-        [&](int pos, int c, float2 v) { z[pos * ld + c] = v; });
-    __syncthreads();
-    line_derivative<false>(X, Pg, P, a.aq, a.dq, a.d);
+    load_differenced<1, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<1>(P, T, pos, c); }, A, B,
+                                    0.f, 0.f, a.d);
+    FCSD_DIFF_AND_TRANSFORM(a)
     const long long fo = (long long)comp * pl;
     // point inputs: the q1 metric row, r2 and the SSPRK registers of the
     // stage; every load is issued (registers the stage does not use read r2)
@@ -400,8 +393,8 @@ __global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
     struct CIn {
       float m1x, m1y, r2, ui, w, u0;
     };
-    for_elems_b<1, kEpiBatch>(
-        N, nl,
+    for_elems_b<1, kEpiBatchC>(
+        N, nl, P.nb1,
         [&](int pos, int c) {
           const long long g = gindex<1>(P, T, pos, c);
           CIn q;

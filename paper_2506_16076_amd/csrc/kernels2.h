@@ -13,12 +13,41 @@ struct PatchDev {
   long long off;
   float hhat, htilde;
   int internal;  // bit s set: side s (q1-, q1+, q2-, q2+) internal
-  int pad;
+  int nb1;       // 0: row-major patch storage; else 8x4-blocked with nb1 blocks per block row
 };
+
+// Plane index of point (i, j) of a patch.  Row-major: off + j n1 + i.
+// 8x4-blocked: blocks of 8 points along q1 by 4 along q2 (128 bytes, one
+// cache line), block (i/8, j/4) at off + 32 (j/4 nb1 + i/8), row-major
+// inside the block.  A column tile of 8 q2 lines and a row tile of 4 q1
+// lines then both read whole cache lines.
+__device__ __forceinline__ long long pidx(const PatchDev& P, int i, int j) {
+  if (P.nb1 == 0) return P.off + (long long)j * P.n1 + i;
+  return P.off + ((((long long)(j >> 2)) * P.nb1 + (i >> 3)) << 5) + ((j & 3) << 3) + (i & 7);
+}
+
+// elements of patch storage (padded to whole blocks when blocked)
+__device__ __forceinline__ int pstore(const PatchDev& P) {
+  return P.nb1 == 0 ? P.n1 * P.n2 : (P.nb1 << 3) * ((P.n2 + 3) & ~3);
+}
+
+// point (i, j) stored at storage index k of the patch; false for padding
+__device__ __forceinline__ bool pdecode(const PatchDev& P, int k, int& i, int& j) {
+  if (P.nb1 == 0) {
+    j = k / P.n1;
+    i = k - j * P.n1;
+    return true;
+  }
+  const int blk = k >> 5, w = k & 31;
+  const int bj = blk / P.nb1, bi = blk - bj * P.nb1;
+  i = (bi << 3) + (w & 7);
+  j = (bj << 2) + (w >> 3);
+  return i < P.n1 && j < P.n2;
+}
 
 struct ChunkDev {
   int patch;  // patch (or lattice group) index
-  int start;  // first point (row-major within the patch)
+  int start;  // first storage index within the patch (lattice: row-major)
 };
 
 // lattice of the smoothing-blending operator: independent patches are their
@@ -124,7 +153,8 @@ __global__ void __launch_bounds__(kBlock) k_proxy(const ChunkDev* chunks, const 
   const ChunkDev ck = chunks[blockIdx.x];
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
   const long long g = P.off + k;
   {
 #pragma clang fp contract(off)
@@ -214,15 +244,17 @@ __device__ __forceinline__ floatx4 mlp16(const MlpLds& L, const float x[4], int 
 // offsets -8..7 (clamped) along a line, rescaled to [-1, 1] with the min and
 // max of the whole window (exchanged among the window's four lanes; min/max
 // are exact, so the features equal a sequential evaluation's).
-__device__ __forceinline__ void window4(const float* __restrict__ phi, long long base, long long step, int pos,
-                                        int n, int g, float x[4]) {
+template <int DIR>
+__device__ __forceinline__ void window4(const float* __restrict__ phi, const PatchDev& P, int i, int j, int g,
+                                        float x[4]) {
 #pragma clang fp contract(off)
   float lo = 3.4e38f, hi = -3.4e38f;
+  const int pos = DIR == 1 ? i : j, n = DIR == 1 ? P.n1 : P.n2;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     int k = pos - 8 + g + 4 * s;
     k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
-    x[s] = phi[base + (long long)k * step];
+    x[s] = phi[DIR == 1 ? pidx(P, k, j) : pidx(P, i, k)];
     lo = fminf(lo, x[s]);
     hi = fmaxf(hi, x[s]);
   }
@@ -264,21 +296,24 @@ __global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* chunks, int nch
   for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {
     const ChunkDev ck = chunks[cb];
     const PatchDev P = patches[ck.patch];
-    const int np = P.n1 * P.n2;
+    const int np = pstore(P);
     for (int q = wv; q < kChunk / 16; q += kBlock / 64) {
       const int k0 = ck.start + 16 * q;
       if (k0 >= np) break;  // uniform across the wavefront
       const int kk = k0 + r;
-      const bool valid = kk < np;
-      const int k = valid ? kk : np - 1;
-      const int j = k / P.n1, i = k - j * P.n1;
+      int i = 0, j = 0;
+      const bool valid = kk < np && pdecode(P, kk, i, j);
+      // lanes without a point evaluate a valid one (every lane takes part
+      // in the matrix products) and write nothing
+      i = i < P.n1 ? i : P.n1 - 1;
+      j = j < P.n2 ? j : P.n2 - 1;
       float x[4];
-      window4(phi, P.off + (long long)j * P.n1, 1, i, P.n1, g, x);
+      window4<1>(phi, P, i, j, g, x);
       const floatx4 o1 = mlp16(L, x, g, r);
-      window4(phi, P.off + i, P.n1, j, P.n2, g, x);
+      window4<2>(phi, P, i, j, g, x);
       const floatx4 o2 = mlp16(L, x, g, r);
       if (g == 0 && valid) {
-        const long long gi = P.off + k;
+        const long long gi = P.off + kk;
         const bool in = in_dtilde(P, i, j);
         const int a1 = argmax4(o1), a2 = argmax4(o2);
         tau[gi] = in ? (signed char)(1 + (a1 < a2 ? a1 : a2)) : (signed char)0;
@@ -302,14 +337,13 @@ __global__ void __launch_bounds__(kBlock) k_rowmax(const ChunkDev* chunks, const
   const ChunkDev ck = chunks[blockIdx.x];
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
-  const int j = k / P.n1, i = k - j * P.n1;
-  const long long row = P.off + (long long)j * P.n1;
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
   const int lo = i - 3 < 0 ? 0 : i - 3, hi = i + 3 > P.n1 - 1 ? P.n1 - 1 : i + 3;
-  float best = S[row + lo];
+  float best = S[pidx(P, lo, j)];
   int bi = lo;
   for (int t = lo + 1; t <= hi; ++t) {
-    const float v = S[row + t];
+    const float v = S[pidx(P, t, j)];
     if (v > best) {
       best = v;
       bi = t;
@@ -326,20 +360,20 @@ __global__ void __launch_bounds__(kBlock) k_muhat(const ChunkDev* chunks, const 
   const ChunkDev ck = chunks[blockIdx.x];
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
-  const int j = k / P.n1, i = k - j * P.n1;
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
   const int lo = j - 3 < 0 ? 0 : j - 3, hi = j + 3 > P.n2 - 1 ? P.n2 - 1 : j + 3;
-  float best = rmax[P.off + (long long)lo * P.n1 + i];
+  float best = rmax[pidx(P, i, lo)];
   int bj = lo;
   for (int t = lo + 1; t <= hi; ++t) {
-    const float v = rmax[P.off + (long long)t * P.n1 + i];
+    const float v = rmax[pidx(P, i, t)];
     if (v > best) {
       best = v;
       bj = t;
     }
   }
   const long long g = P.off + k;
-  if (argmax) argmax[g] = bj * P.n1 + rarg[P.off + (long long)bj * P.n1 + i];
+  if (argmax) argmax[g] = bj * P.n1 + rarg[pidx(P, i, bj)];
   float m = 0.f;
   if (in_dtilde(P, i, j)) {
     const int t = tau[g];
@@ -382,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_lat_gather(const ChunkDev* lchunks, 
     const PatchDev P = patches[ck.patch];
     const int j = k / P.n1, i = k - j * P.n1;
     const bool in = transpose_src ? true : in_dtilde(P, i, j);
-    num[cell] = in ? muh[P.off + k] : 0.f;
+    num[cell] = in ? muh[pidx(P, i, j)] : 0.f;
     if (den) den[cell] = in ? 1.f : 0.f;
     return;
   }
@@ -402,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_lat_gather(const ChunkDev* lchunks, 
       const int p = kk * an.nsec + s;
       const PatchDev P = patches[p];
       if (!transpose_src && !in_dtilde(P, ii, jj)) continue;
-      sn += muh[P.off + (long long)jj * P.n1 + ii];
+      sn += muh[pidx(P, ii, jj)];
       sd += 1.f;
     }
   }
@@ -444,7 +478,7 @@ __global__ void __launch_bounds__(kBlock) k_lat_conv(const ChunkDev* lchunks, co
 
 __device__ __forceinline__ long long lat_cell(const PatchDev& P, int p, int i, int j, int annulus,
                                               const AnnulusDev& an) {
-  if (!annulus) return P.off + (long long)j * P.n1 + i;
+  if (!annulus) return P.off + (long long)j * P.n1 + i;  // lattice cells are row-major
   const int s = p % an.nsec, kk = p / an.nsec;
   const int G = (s * an.st1 + i) % an.ring;
   const int J = kk * an.st2 + j;
@@ -459,8 +493,8 @@ __global__ void __launch_bounds__(kBlock) k_lat_scatter(const ChunkDev* chunks, 
   const ChunkDev ck = chunks[blockIdx.x];
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
-  const int j = k / P.n1, i = k - j * P.n1;
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
   const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
   mu[P.off + k] = num[c] / den[c];
 }
@@ -472,8 +506,8 @@ __global__ void __launch_bounds__(kBlock) k_lat_divide_pts(const ChunkDev* chunk
   const ChunkDev ck = chunks[blockIdx.x];
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
-  const int j = k / P.n1, i = k - j * P.n1;
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
   const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
   t[P.off + k] = mub[P.off + k] / den[c];
 }
@@ -488,8 +522,9 @@ __global__ void __launch_bounds__(kBlock) k_route_S(const ChunkDev* chunks, cons
   const ChunkDev ck = chunks[blockIdx.x];
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
-  const int j = k / P.n1, i = k - j * P.n1;
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+  const int kr = j * P.n1 + i;  // patch-local row-major index, as argmax stores it
   float s = 0.f;
   for (int dj = -3; dj <= 3; ++dj) {
     const int yj = j + dj;
@@ -497,8 +532,8 @@ __global__ void __launch_bounds__(kBlock) k_route_S(const ChunkDev* chunks, cons
     for (int di = -3; di <= 3; ++di) {
       const int yi = i + di;
       if (yi < 0 || yi >= P.n1) continue;
-      const long long gy = P.off + (long long)yj * P.n1 + yi;
-      if (argmax[gy] != k || !in_dtilde(P, yi, yj)) continue;
+      const long long gy = pidx(P, yi, yj);
+      if (argmax[gy] != kr || !in_dtilde(P, yi, yj)) continue;
       const int t = tau[gy];
       const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
       s += R * P.hhat * accconv[lat_cell(P, ck.patch, yi, yj, annulus, an)];
@@ -514,7 +549,8 @@ __global__ void __launch_bounds__(kBlock) k_speed_vjp(const ChunkDev* chunks, co
   const ChunkDev ck = chunks[blockIdx.x];
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
-  if (k >= P.n1 * P.n2) return;
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
   const long long g = P.off + k;
   const float sb = sbar[g];
   if (sb == 0.f) return;
@@ -548,7 +584,8 @@ __global__ void __launch_bounds__(kBlock) k_dt_reduce(const ChunkDev* chunks, co
   const PatchDev P = patches[ck.patch];
   const int k = ck.start + threadIdx.x;
   float s = 0.f, m = 0.f;
-  if (k < P.n1 * P.n2) {
+  int i, j;
+  if (k < pstore(P) && pdecode(P, k, i, j)) {
     const long long g = P.off + k;
     float rho, vx, vy, p;
     prim(u, pl, g, gam, rho, vx, vy, p);
@@ -618,8 +655,8 @@ __global__ void __launch_bounds__(kBlock) k_glue_sectors(const PatchDev* patches
     src = kk * an.nsec + (s + 1) % an.nsec;
     si = i - an.st1;
   }
-  const long long d = patches[p].off + (long long)j * an.n1 + i;
-  const long long sg = patches[src].off + (long long)j * an.n1 + si;
+  const long long d = pidx(patches[p], i, j);
+  const long long sg = pidx(patches[src], si, j);
   for (int f = 0; f < 4; ++f) u[f * pl + d] = u[f * pl + sg];
 }
 
@@ -646,8 +683,8 @@ __global__ void __launch_bounds__(kBlock) k_glue_shells(const PatchDev* patches,
     src = (kk + 1) * an.nsec + s;
     sj = j - an.st2;
   }
-  const long long d = patches[p].off + (long long)j * an.n1 + i;
-  const long long sg = patches[src].off + (long long)sj * an.n1 + i;
+  const long long d = pidx(patches[p], i, j);
+  const long long sg = pidx(patches[src], i, sj);
   for (int f = 0; f < 4; ++f) u[f * pl + d] = u[f * pl + sg];
 }
 
@@ -689,8 +726,8 @@ __global__ void __launch_bounds__(kBlock) k_glue_sectors_adj(const PatchDev* pat
     src = kk * an.nsec + (s + 1) % an.nsec;
     si = i - an.st1;
   }
-  const long long d = patches[p].off + (long long)j * an.n1 + i;
-  const long long sg = patches[src].off + (long long)j * an.n1 + si;
+  const long long d = pidx(patches[p], i, j);
+  const long long sg = pidx(patches[src], si, j);
   for (int f = 0; f < 4; ++f) {
     ub[f * pl + sg] += ub[f * pl + d];
     ub[f * pl + d] = 0.f;
@@ -720,8 +757,8 @@ __global__ void __launch_bounds__(kBlock) k_glue_shells_adj(const PatchDev* patc
     src = (kk + 1) * an.nsec + s;
     sj = j - an.st2;
   }
-  const long long d = patches[p].off + (long long)j * an.n1 + i;
-  const long long sg = patches[src].off + (long long)sj * an.n1 + i;
+  const long long d = pidx(patches[p], i, j);
+  const long long sg = pidx(patches[src], i, sj);
   for (int f = 0; f < 4; ++f) {
     ub[f * pl + sg] += ub[f * pl + d];
     ub[f * pl + d] = 0.f;
@@ -793,14 +830,14 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
   const long long pl = a.plane;
   const int mx = DIR == 1 ? 0 : 2, my = DIR == 1 ? 1 : 3;
   for (int comp = 0; comp < 4; ++comp) {
-    for_elems<DIR>(N, nl, [&](int pos, int c) {
+    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float r = rb[(long long)comp * pl + g];
       z[pos * ld + c] = make_float2(a.metric[mx * pl + g] * r, a.metric[my * pl + g] * r);
     });
     __syncthreads();
     line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
-    for_elems<DIR>(N, nl, [&](int pos, int c) {
+    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       const float2 v = z[pos * ld + c];
       const long long ix = (long long)(2 * comp) * pl + g, iy = (long long)(2 * comp + 1) * pl + g;
@@ -829,7 +866,7 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
     __syncthreads();
   }
   if (DIR == 2 && a.mode != FLUX_VISC) {
-    for_elems<DIR>(N, nl, [&](int pos, int c) {
+    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
       const long long g = gindex<DIR>(P, T, pos, c);
       float e[4], fb[4], gb[4], o[4];
 #pragma unroll

@@ -52,6 +52,24 @@ def host(t, shape=None):
     return a.reshape(shape) if shape is not None else a
 
 
+def mkset(api, ctx, ps, layout):
+    """Patch set in a storage layout with converters: D(host planes) ->
+    device planes, H(device planes) -> flat row-major host planes."""
+    s = api.PatchSet.from_layout(ctx, ps, layout)
+
+    def D(a, dtype=None):
+        a = np.asarray(a)
+        return s.to_device(a.reshape(-1, ps.plane), dtype)
+
+    def H(t):
+        return s.to_host(t).reshape(-1)
+
+    return s, D, H
+
+
+LAYOUTS = [0, 1]
+
+
 def relerr(ps, got, want):
     """relative L2 per leading field over valid patch points"""
     got = np.asarray(got, np.float64).reshape(-1, ps.plane)
@@ -100,17 +118,18 @@ def uneven(seed=11, npatch=6, nmax=160):
 
 # ------------------------------------------------------------------ FC line operators
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("direction", [1, 2])
-def test_fc_diff_uneven_patches(env, direction):
+def test_fc_diff_uneven_patches(env, direction, layout):
     api, ctx, torch = env
     ps = uneven()
-    say("fc_diff uneven", direction, list(zip(ps.n1, ps.n2)))
-    s = api.PatchSet.from_layout(ctx, ps)
+    say("fc_diff uneven", direction, "layout", layout, list(zip(ps.n1, ps.n2)))
+    s, D, H = mkset(api, ctx, ps, layout)
     F = smooth_fields(ps, 3, 1)
-    out = torch.zeros(3 * ps.plane, device="cuda:0")
-    api.fc_diff(s, direction, dev(torch, F), out, nf=3)
+    out = torch.zeros(3 * s.plane, device="cuda:0")
+    api.fc_diff(s, direction, D(F), out, nf=3)
     want = fcgram.diff_plane(F.astype(np.float64), ps, direction)
-    err = relerr(ps, host(out), want)
+    err = relerr(ps, H(out), want)
     say("  rel L2", err)
     assert np.all(err < RHS_TOL)
     s.close()
@@ -197,25 +216,26 @@ def rhs_case(name):
     raise KeyError(name)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("case", ["square64", "annulus", "shells", "uneven"])
-def test_full_rhs(env, case):
+def test_full_rhs(env, case, layout):
     api, ctx, torch = env
     ps, u, mu, ref = rhs_case(case)
-    say("fcsd_rhs", case, ps.npatch, "patches", ps.npoints, "points")
-    s = api.PatchSet.from_layout(ctx, ps)
-    metric = dev(torch, ps.metric)
-    ud, mud = dev(torch, u), dev(torch, mu)
-    rhs = torch.zeros(4 * ps.plane, device="cuda:0")
+    say("fcsd_rhs", case, "layout", layout, ps.npatch, "patches", ps.npoints, "points")
+    s, D, H = mkset(api, ctx, ps, layout)
+    metric = D(ps.metric)
+    ud, mud = D(u), D(mu)
+    rhs = torch.zeros(4 * s.plane, device="cuda:0")
     api.fcsd_rhs(s, ud, metric, mud, ref, G, rhs)
     want = euler.full_rhs(u.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G)
-    err = relerr_phys(ps, host(rhs), want)
+    err = relerr_phys(ps, H(rhs), want)
     # inviscid and viscous parts through their own entry points
-    r1 = torch.zeros(4 * ps.plane, device="cuda:0")
+    r1 = torch.zeros(4 * s.plane, device="cuda:0")
     api.euler_rhs(s, ud, metric, ref, G, r1)
     w1 = euler.euler_rhs(u.astype(np.float64), ps.metric, ps, G)
-    e1 = relerr_phys(ps, host(r1), w1)
+    e1 = relerr_phys(ps, H(r1), w1)
     api.av_apply(s, ud, metric, mud, ref, r1)
-    e2 = relerr_phys(ps, host(r1), want)
+    e2 = relerr_phys(ps, H(r1), want)
     say("  full rhs rel L2", err, "euler_rhs", e1, "euler_rhs + av_apply", e2)
     assert np.all(err < RHS_TOL)
     assert np.all(e1 < RHS_TOL) and np.all(e2 < RHS_TOL)
@@ -297,23 +317,24 @@ def test_network_classes(env):
     s.close()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("case", ["annulus", "shells", "uneven"])
-def test_viscosity_operator(env, case):
+def test_viscosity_operator(env, case, layout):
     api, ctx, torch = env
     ps, u, _, ref = rhs_case(case)
-    s = api.PatchSet.from_layout(ctx, ps)
+    s, D, H = mkset(api, ctx, ps, layout)
     rng = np.random.default_rng(15)
     tau = np.zeros(ps.plane, np.int8)
     for p in range(ps.npatch):
         m = av.dtilde_mask(ps, p)
         ps.view(tau, p)[m] = rng.integers(1, 5, m.sum())
-    mu = torch.zeros(ps.plane, device="cuda:0")
-    amax = torch.zeros(ps.plane, dtype=torch.int32, device="cuda:0")
-    api.av_viscosity(s, dev(torch, u), dev(torch, tau), G, mu, amax)
+    mu = torch.zeros(s.plane, device="cuda:0")
+    amax = torch.zeros(s.plane, dtype=torch.int32, device="cuda:0")
+    api.av_viscosity(s, D(u), D(tau), G, mu, amax)
     muh, arg = av.preliminary(u.astype(np.float64), tau, ps, G)
     want = av.smooth_blend(muh, ps)
-    err = relerr(ps, host(mu), want)
-    ga = host(amax)
+    err = relerr(ps, H(mu), want)
+    ga = H(amax)
     for p in range(ps.npatch):
         assert np.array_equal(ps.view(ga, p), ps.view(arg, p))
     say("av_viscosity", case, err)
@@ -341,21 +362,22 @@ def test_glue(env):
 
 # ------------------------------------------------------------------ fused stage, step
 
-def test_fused_stage_and_per_patch_equal(env):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_fused_stage_and_per_patch_equal(env, layout):
     api, ctx, torch = env
     ps, u, mu, ref = rhs_case("uneven")
-    s = api.PatchSet.from_layout(ctx, ps)
+    s, D, H = mkset(api, ctx, ps, layout)
     dt = 2e-2
     dtd = dev(torch, np.array([dt], np.float32))
-    metric, mud = dev(torch, ps.metric), dev(torch, mu)
-    u0 = dev(torch, u)
-    ui = dev(torch, u * np.float32(1.0001))
+    metric, mud = D(ps.metric), D(mu)
+    u0 = D(u)
+    ui = D(u * np.float32(1.0001))
     outs = []
     for per in (False, True):
-        acc = torch.zeros(4 * ps.plane, device="cuda:0")
-        uo = torch.zeros(4 * ps.plane, device="cuda:0")
+        acc = torch.zeros(4 * s.plane, device="cuda:0")
+        uo = torch.zeros(4 * s.plane, device="cuda:0")
         api.fcsd_stage(s, 1, u0, ui, acc, uo, metric, mud, ref, G, dtd, per_patch=per)
-        outs.append(host(uo))
+        outs.append(H(uo))
     assert np.array_equal(outs[0], outs[1])
     ui64 = (u * np.float32(1.0001)).astype(np.float64)
     r = euler.full_rhs(ui64, ps.metric, mu.astype(np.float64), ps, G)
@@ -386,23 +408,24 @@ def test_ten_steps_square(env):
     s.close()
 
 
-def test_steps_annulus_with_network(env):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_steps_annulus_with_network(env, layout):
     api, ctx, torch = env
     cfg = synth.config(1, n=48)
     ps = cfg.ps
-    s = api.PatchSet.from_layout(ctx, ps)
-    u = dev(torch, cfg.u0)
+    s, D, H = mkset(api, ctx, ps, layout)
+    u = D(cfg.u0)
     W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
-    st = api.Stepper(s, u, dev(torch, ps.metric), cfg.ref, W=W, dirichlet_mask=dev(torch, ps.dirichlet),
+    st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W, dirichlet_mask=D(ps.dirichlet),
                      dirichlet_state=synth.freestream(cfg.mach))
     run = solver.Run(cfg)
     for k in range(3):
         st.step()
         run.step()
-        same = np.mean(host(st.tau) == run.log[-1]["tau"])
-        say("step", k, "tau agreement", same, "dt", float(host(st.dt)[0]), run.log[-1]["dt"])
+        same = np.mean(H(st.tau) == run.log[-1]["tau"])
+        say("step", k, "layout", layout, "tau agreement", same, "dt", float(host(st.dt)[0]), run.log[-1]["dt"])
         assert same > 0.999
-    got = host(u).reshape(4, -1)
+    got = H(u).reshape(4, -1)
     err = relerr_phys(ps, got, run.u)
     chg = relerr_phys(ps, got - cfg.u0, run.u - cfg.u0)
     say("3 steps annulus: state rel L2", err, "change", chg)
@@ -462,9 +485,11 @@ def test_tiling_and_order_do_not_change_results(env):
     metric = dev(torch, ps.metric)
     ud, mud = dev(torch, u), dev(torch, mu)
     outs = []
-    for q1, q2, order in [(65536, 65536, 1), (16384, 131072, 0), (32768, 24576, 1), (98304, 16384, 0)]:
-        say("tiling", q1, q2, order)
-        s.tune(q1, q2, order)
+    for budgets, threads, order in [((65536,) * 3, (256,) * 3, 1), ((16384, 131072, 98304), (256, 1024, 512), 0),
+                                    ((32768, 24576, 163840), (512, 256, 1024), 1),
+                                    ((98304, 16384, 49152), (1024, 128, 256), 0)]:
+        say("tiling", budgets, threads, order)
+        s.tune(budgets, threads, order)
         rhs = torch.zeros(4 * ps.plane, device="cuda:0")
         api.fcsd_rhs(s, ud, metric, mud, ref, G, rhs)
         outs.append(host(rhs))
@@ -480,10 +505,10 @@ def test_autotuner_picks_a_schedule(env):
     s = api.PatchSet.from_layout(ctx, ps)
     metric = dev(torch, ps.metric)
     ud, mud = dev(torch, u), dev(torch, mu)
-    res = autotune.autotune(s, ud, metric, mud, ref, G, budgets=(16384, 32768, 65536), reps=1)
+    res = autotune.autotune(s, ud, metric, mud, ref, G, budgets=(16384, 32768, 65536), threads=(256, 512), reps=1)
     say("autotune", {k: v for k, v in res.items() if k != "table"})
-    assert res["q1_budget"] in (16384, 32768, 65536) and res["q2_budget"] in (16384, 32768, 65536)
-    assert s.tuning == (res["q1_budget"], res["q2_budget"], 1 if res["order"] == "xcd" else 0)
+    assert all(b in (16384, 32768, 65536) for b in res["budgets"]) and all(t in (256, 512) for t in res["threads"])
+    assert s.tuning == (tuple(res["budgets"]), tuple(res["threads"]), 1 if res["order"] == "xcd" else 0)
     rhs = torch.zeros(4 * ps.plane, device="cuda:0")
     api.fcsd_rhs(s, ud, metric, mud, ref, G, rhs)
     want = euler.full_rhs(u.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G)
@@ -493,16 +518,16 @@ def test_autotuner_picks_a_schedule(env):
 
 # ------------------------------------------------------------------ time-stepping reverse mode
 
-def _annulus_ic(torch, ps, pert, M, amp):
+def _annulus_ic(torch, ps, pert, M, amp, s):
     """rho = 1.4 (1 + sum a_k phi_k), m = rho M, n = 0, E = 1/(gamma-1) + rho M^2/2 (FP64 on the
-    device, differentiable in M and amp), returned as the FP32 state."""
-    phi = torch.from_numpy(pert.modes(ps.xy)).to("cuda:0")
+    device, differentiable in M and amp), returned as the FP32 state in the set's storage."""
+    phi = s.to_device(pert.modes(ps.xy)).reshape(len(pert.amp), -1)
     rho = 1.4 * (1 + amp @ phi)
     e = torch.stack([rho, rho * M, 0 * rho, 1 / (G - 1) + 0.5 * rho * M * M])
     return e.to(torch.float32).reshape(-1)
 
 
-def _rollout_gradient_check(env, n, steps, every):
+def _rollout_gradient_check(env, n, steps, every, layout=0):
     """Gradient of the outer-row density norm after `steps` steps
     (checkpoints every `every`) on the 16-sector annulus with n x n patches,
     with respect to the inflow Mach number and the 16 perturbation
@@ -516,27 +541,28 @@ def _rollout_gradient_check(env, n, steps, every):
     api, ctx, torch = env
     cfg = synth.config(3, n=n)
     ps = cfg.ps
-    s = api.PatchSet.from_layout(ctx, ps)
+    s, D, H = mkset(api, ctx, ps, layout)
     W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
-    metric = dev(torch, ps.metric)
-    mask = dev(torch, ps.dirichlet)
+    metric = D(ps.metric)
+    mask = D(ps.dirichlet)
     M = torch.tensor(cfg.mach, dtype=torch.float64, device="cuda:0", requires_grad=True)
     amp = torch.tensor(cfg.pert.amp, dtype=torch.float64, device="cuda:0", requires_grad=True)
-    ubuf = torch.zeros(4 * ps.plane, device="cuda:0")
+    ubuf = torch.zeros(4 * s.plane, device="cuda:0")
     st = api.Stepper(s, ubuf, metric, cfg.ref, W=W, dirichlet_mask=mask,
                      dirichlet_state=synth.freestream(cfg.mach))
     # recorded decisions of the forward run, for the oracle
-    u0 = _annulus_ic(torch, ps, cfg.pert, M, amp)
+    u0 = _annulus_ic(torch, ps, cfg.pert, M, amp, s)
     ubuf.copy_(u0.detach())
     rec = []
     for _ in range(steps):
         st.step()
-        rec.append(dict(dt=float(host(st.dt)[0]), tau=host(st.tau).copy(), arg=host(st.argmax).copy()))
+        rec.append(dict(dt=float(host(st.dt)[0]), tau=H(st.tau).copy(), arg=H(st.argmax).copy()))
     say("rollout", steps, "steps, checkpoints every", every)
     uT = autodiff.rollout(st, u0, M.to(torch.float32), steps, every, autodiff.freestream_dmach(cfg.mach))
-    rows = np.concatenate([int(ps.off[p]) + (int(ps.n2[p]) - 1) * int(ps.n1[p]) + np.arange(int(ps.n1[p]))
-                           for p in range(ps.npatch)])
-    idx = torch.from_numpy(rows).to("cuda:0")
+    rows = np.zeros(ps.plane, np.float32)
+    for p in range(ps.npatch):
+        ps.view(rows, p)[-1, :] = 1
+    idx = torch.nonzero(D(rows) > 0).reshape(-1)
     loss = torch.sqrt(torch.sum(uT[idx].double() ** 2))
     loss.backward()
     g_gpu = np.concatenate([[float(M.grad)], host(amp.grad)])
@@ -550,9 +576,10 @@ def _rollout_gradient_check(env, n, steps, every):
     s.close()
 
 
-def test_rollout_gradient_matches_oracle_adjoint(env):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rollout_gradient_matches_oracle_adjoint(env, layout):
     # 10 steps with checkpoints every 4: a ragged last segment
-    _rollout_gradient_check(env, 48, 10, 4)
+    _rollout_gradient_check(env, 48, 10, 4, layout)
 
 
 @pytest.mark.skipif(os.environ.get("FCSD_FULL") != "1", reason="full-size gradient check (minutes of FP64 "
@@ -560,7 +587,7 @@ def test_rollout_gradient_matches_oracle_adjoint(env):
 def test_rollout_gradient_full_size(env):
     """The differentiation workload at its stated size: 16 patches of
     128 x 128, 40 steps, checkpoints every 8."""
-    _rollout_gradient_check(env, 128, 40, 8)
+    _rollout_gradient_check(env, 128, 40, 8, 1)
 
 
 # ------------------------------------------------------------------ full sizes, sampled patches
@@ -578,24 +605,25 @@ def _subset(ps, plist):
 def test_full_size_rhs_sampled_patches(env, idx):
     """The full right-hand side (convective + viscous) of the workloads at
     their stated sizes (c1 16 x 256^2, c2 200 uneven patches 48..512, c4
-    64 x 512^2), computed on the GPU for every patch in the schedule the
-    bench uses (autotuned tiles), against the oracle on five sampled
-    patches (first, last, largest, two seeded); bar 1e-5 per component."""
+    64 x 512^2), computed on the GPU for every patch in the configuration
+    the bench uses (blocked storage, autotuned tiles), against the oracle on
+    five sampled patches (first, last, largest, two seeded); bar 1e-5 per
+    component."""
     from paper_2506_16076_amd import autotune
     api, ctx, torch = env
     cfg = synth.config(idx)
     ps = cfg.ps
     say("full-size rhs", cfg.name, ps.npatch, "patches", ps.npoints, "points")
-    s = api.PatchSet.from_layout(ctx, ps)
-    metric = dev(torch, ps.metric)
-    ud = dev(torch, cfg.u0)
+    s, D, H = mkset(api, ctx, ps, 1)
+    metric = D(ps.metric)
+    ud = D(cfg.u0)
     mu = (0.002 * (1.5 + np.sin(3 * ps.xy[0]) * np.cos(2 * ps.xy[1]))).astype(np.float32)
-    mud = dev(torch, mu)
+    mud = D(mu)
     res = autotune.autotune(s, ud, metric, mud, cfg.ref, G, reps=1)
     say("  schedule", {k: v for k, v in res.items() if k != "table"})
-    rhs = torch.zeros(4 * ps.plane, device="cuda:0")
+    rhs = torch.zeros(4 * s.plane, device="cuda:0")
     api.fcsd_rhs(s, ud, metric, mud, cfg.ref, G, rhs)
-    got = host(rhs).reshape(4, -1)
+    got = H(rhs).reshape(4, -1)
     sizes = ps.n1.astype(np.int64) * ps.n2
     rng = np.random.default_rng(idx)
     plist = sorted({0, ps.npatch - 1, int(np.argmax(sizes)), *rng.choice(ps.npatch, 2, replace=False).tolist()})

@@ -216,3 +216,29 @@ def test_patch_validation(L):
     descs = L.patch_descs(ann.n1, ann.n2, ann.C1, ann.C2, ann.off, ann.hhat, ann.htilde, ann.internal)
     assert L.validate_patches(descs, 5, ann.plane, 4, 2)[0] == 0
     assert L.validate_patches(descs, 5, ann.plane, 3, 2)[0] == 1
+
+
+def test_blocked_layout_tables(L):
+    """8x4-blocked storage: offsets and plane of blocked_layout pass the
+    library's validation, misaligned offsets do not, and the row <-> block
+    index maps are bijections onto distinct in-range positions that follow
+    the documented address (32 (j/4 nb1 + i/8) + 8 (j%4) + i%8)."""
+    ps = synth.uneven_sectors(6, 48, 130, 5)
+    off, plane = L.blocked_layout(ps.n1, ps.n2)
+    descs = L.patch_descs(ps.n1, ps.n2, ps.C1, ps.C2, off, ps.hhat, ps.htilde, ps.internal)
+    assert L.validate_patches(descs, 5, plane, layout=1)[0] == 0
+    assert L.validate_patches(descs, 5, plane, layout=7)[0] == 1
+    bad = L.patch_descs(ps.n1, ps.n2, ps.C1, ps.C2, off + 8, ps.hhat, ps.htilde, ps.internal)
+    assert L.validate_patches(bad, 5, plane + 64, layout=1)[0] == 1          # not a multiple of 32
+    tight = int(off[-1]) + int(ps.n1[-1]) * int(ps.n2[-1])
+    assert L.validate_patches(descs, 5, tight, layout=1)[0] == 1              # padded patch does not fit
+    rows, blk = L.layout_index(ps.n1, ps.n2, ps.off, off)
+    assert len(np.unique(rows)) == len(rows) == ps.npoints
+    assert len(np.unique(blk)) == len(blk) and blk.max() < plane
+    p = 3
+    n1, n2 = int(ps.n1[p]), int(ps.n2[p])
+    nb1 = (n1 + 7) // 8
+    i, j = n1 - 1, n2 - 2
+    want = int(off[p]) + 32 * ((j // 4) * nb1 + i // 8) + 8 * (j % 4) + i % 8
+    k = int(np.sum(ps.n1[:p].astype(np.int64) * ps.n2[:p])) + j * n1 + i
+    assert rows[k] == int(ps.off[p]) + j * n1 + i and blk[k] == want
