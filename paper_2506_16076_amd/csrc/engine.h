@@ -107,113 +107,180 @@ __device__ __forceinline__ LineCtx line_setup(float2* lds, const TileDev& T, con
   return X;
 }
 
-// Elements (pos, c) of a tile in the order that coalesces global memory,
-// visited by thread t at steps t, t + blockDim, ... with incremental index
-// updates (no division per element).  Row-major storage: q1 lines (DIR 1)
-// pos-fastest, q2 lines (DIR 2) line-fastest.  8x4-blocked storage (tiles
-// start on block boundaries): storage order, whole 128-byte blocks -- for q1
-// tiles, strips of 4 lines block by block along the line; for q2 tiles,
-// groups of 4 samples by column blocks of 8 lines.  blockDim is a multiple
-// of 32, so a thread keeps its place w inside a block and only the block
-// index advances.
-template <int DIR>
-struct ElemIter {
-  bool blocked;
-  int N, nl;
-  // row-major: element (a, b) along the fast / slow extents
-  int a = 0, b = 0, na = 1, nbb = 0, sa = 0, sb = 0;
-  // blocked: block (slow, fast), place w in the block (every member is
-  // initialised on both paths so the iterator stays in registers)
-  int slow = 0, fast = 0, nbf = 1, nslow = 0, dslow = 0, dfast = 0, w = 0;
+// Walk over the elements (pos, c) of a tile in global-memory storage order.
+// Thread t visits elements t, t + blockDim, ... of the tile's storage and
+// carries, per element, two byte offsets updated by uniform increments:
+//   g: from the tile's first stored element, the same in every plane (the
+//      caller adds it to a per-plane tile base pointer, which stays uniform:
+//      loads and stores take a scalar base and one vector offset);
+//   l: of z[pos * ld + c] in LDS.
+// Storage of a patch (element (i, j), i along q1, off = patch offset):
+//   row-major:  off + j n1 + i
+//   8x4 blocks: off + 32 ((j/4) nb1 + i/8) + 8 (j%4) + i%8, nb1 = ceil(n1/8);
+//               tiles start on block boundaries (q1 tiles: line0 % 4 = 0,
+//               q2 tiles: line0 % 8 = 0), so a thread keeps its place w in a
+//               block (blockDim % 32 = 0) and steps whole blocks.
+// The walk splits the tile into blocks of W elements (W = 32 blocked, 1
+// row-major) arranged slow x fast; (fast, slow) advance by (dF, dS) blocks
+// per step with one carry.  Padding elements of the blocked storage (pos >=
+// N or c >= nl) lie inside the patch's storage and are skipped by valid().
+struct Walk {
+  unsigned g, l;            // byte offsets of the current element
+  int fast, slow;           // block coordinates
+  int flim, slim;           // valid while fast < flim and slow < slim
+  int nbf, nslow, dF, dS;   // uniform: blocks along fast, slow extent, step
+  unsigned dG, dL, wG, wL;  // uniform: offset steps, extra on carry
+  unsigned gnext;           // byte distance to the next sample along the line
 
-  __device__ __forceinline__ ElemIter(int N_, int nl_, int nb1, int e0) : blocked(nb1 != 0), N(N_), nl(nl_) {
-    if (!blocked) {
-      na = DIR == 1 ? N : nl;
-      nbb = DIR == 1 ? nl : N;
-      a = e0 % na;
-      b = e0 / na;
-      sa = blockDim.x % na;
-      sb = blockDim.x / na;
-    } else {
-      nbf = DIR == 1 ? (N + 7) >> 3 : (nl + 7) >> 3;     // blocks along the fast block axis
-      nslow = DIR == 1 ? (nl + 3) >> 2 : (N + 3) >> 2;   // strips (DIR 1) / sample groups (DIR 2)
-      const int blk = e0 >> 5, db = blockDim.x >> 5;
-      w = e0 & 31;
-      slow = blk / nbf;
-      fast = blk - slow * nbf;
-      dslow = db / nbf;
-      dfast = db - dslow * nbf;
-    }
-  }
-  __device__ __forceinline__ bool more() const { return blocked ? slow < nslow : b < nbb; }
-  // current element; false if it lies past the tile's lines or samples
-  __device__ __forceinline__ bool get(int& pos, int& c) const {
-    if (!blocked) {
-      pos = DIR == 1 ? a : b;
-      c = DIR == 1 ? b : a;
-      return b < nbb;
-    }
-    if (DIR == 1) {
-      c = (slow << 2) + (w >> 3);
-      pos = (fast << 3) + (w & 7);
-    } else {
-      c = (fast << 3) + (w & 7);
-      pos = (slow << 2) + (w >> 3);
-    }
-    return slow < nslow && c < nl && pos < N;
-  }
-  __device__ __forceinline__ void next() {
-    if (!blocked) {
-      a += sa;
-      b += sb;
-      if (a >= na) {
-        a -= na;
-        ++b;
-      }
-    } else {
-      fast += dfast;
-      slow += dslow;
-      if (fast >= nbf) {
-        fast -= nbf;
-        ++slow;
-      }
+  __host__ __device__ __forceinline__ bool more() const { return slow < nslow; }
+  __host__ __device__ __forceinline__ bool valid() const { return fast < flim && slow < slim; }
+  __host__ __device__ __forceinline__ void next() {
+    fast += dF;
+    slow += dS;
+    g += dG;
+    l += dL;
+    if (fast >= nbf) {
+      fast -= nbf;
+      ++slow;
+      g += wG;
+      l += wL;
     }
   }
 };
 
-// Visit the elements of a tile, f(pos, c), in the coalescing order.
-template <int DIR, class F>
-__device__ __forceinline__ void for_elems(int N, int nl, int nb1, F&& f) {
-  ElemIter<DIR> it(N, nl, nb1, threadIdx.x);
-  for (; it.more(); it.next()) {
-    int pos, c;
-    if (it.get(pos, c)) f(pos, c);
+// Walk of thread t of bd (a multiple of 32) over a tile of nl lines of N
+// samples along direction DIR (1: lines are rows i = pos, j = line0 + c;
+// 2: columns i = line0 + c, j = pos); nb1 = 0 for row-major storage with
+// row length n1.
+template <int DIR>
+__host__ __device__ __forceinline__ Walk make_walk_t(int t, int bd, int N, int nl, int ld, int nb1, int n1) {
+  Walk w;
+  int gf, gs, lf, ls, b0, wq = 0, gw, lw;  // element steps along fast/slow, first block, place in block
+  if (nb1) {
+    wq = t & 31;
+    b0 = t >> 5;
+    bd >>= 5;
+    gf = 32;
+    gs = 32 * nb1;
+    gw = wq;
+    if (DIR == 1) {  // fast: blocks of 8 samples, slow: strips of 4 lines
+      w.nbf = (N + 7) >> 3;
+      w.nslow = (nl + 3) >> 2;
+      w.flim = (N - (wq & 7) + 7) >> 3;
+      w.slim = (nl - (wq >> 3) + 3) >> 2;
+      lf = 8 * ld;
+      ls = 4;
+      lw = (wq & 7) * ld + (wq >> 3);
+      w.gnext = 4u * ((wq & 7) < 7 ? 1u : 25u);
+    } else {         // fast: blocks of 8 lines, slow: groups of 4 samples
+      w.nbf = (nl + 7) >> 3;
+      w.nslow = (N + 3) >> 2;
+      w.flim = (nl - (wq & 7) + 7) >> 3;
+      w.slim = (N - (wq >> 3) + 3) >> 2;
+      lf = 8;
+      ls = 4 * ld;
+      lw = (wq >> 3) * ld + (wq & 7);
+      w.gnext = 4u * ((wq >> 3) < 3 ? 8u : (unsigned)(32 * nb1 - 24));
+    }
+  } else {
+    b0 = t;
+    gf = 1;
+    gs = n1;
+    gw = 0;
+    lw = 0;
+    if (DIR == 1) {  // fast: samples, slow: lines
+      w.nbf = N;
+      w.nslow = nl;
+      lf = ld;
+      ls = 1;
+      w.gnext = 4u;
+    } else {         // fast: lines, slow: samples
+      w.nbf = nl;
+      w.nslow = N;
+      lf = 1;
+      ls = ld;
+      w.gnext = 4u * (unsigned)n1;
+    }
+    w.flim = w.nbf;
+    w.slim = w.nslow;
   }
+  w.fast = b0 % w.nbf;
+  w.slow = b0 / w.nbf;
+  w.dF = bd % w.nbf;
+  w.dS = bd / w.nbf;
+  w.g = 4u * (unsigned)(w.slow * gs + w.fast * gf + gw);
+  w.l = 8u * (unsigned)(w.fast * lf + w.slow * ls + lw);
+  w.dG = 4u * (unsigned)(w.dS * gs + w.dF * gf);
+  w.dL = 8u * (unsigned)(w.dF * lf + w.dS * ls);
+  w.wG = 4u * (unsigned)(gs - w.nbf * gf);
+  w.wL = 8u * (unsigned)(ls - w.nbf * lf);
+  return w;
 }
 
-// Batched variant for memory-latency-bound phases: pre(pos, c) issues the
-// loads of U elements of the thread, then post(pos, c, value) consumes
-// them.  pre runs unconditionally (elements past the end read element
-// (0, 0) of the tile and are dropped), so the loads are straight-line code
-// and all U are in flight together; pre should only load, and leave
-// arithmetic to post.
-template <int DIR, int U, class Pre, class Post>
-__device__ __forceinline__ void for_elems_b(int N, int nl, int nb1, Pre&& pre, Post&& post) {
-  using T = decltype(pre(0, 0));
-  ElemIter<DIR> it(N, nl, nb1, threadIdx.x);
-  while (it.more()) {
+template <int DIR>
+__device__ __forceinline__ Walk make_walk(int N, int nl, int ld, int nb1, int n1) {
+  return make_walk_t<DIR>(threadIdx.x, blockDim.x, N, nl, ld, nb1, n1);
+}
+
+// Element offset of the tile's first stored element from the patch offset.
+template <int DIR>
+__host__ __device__ __forceinline__ long long tile_first(int line0, int nb1, int n1) {
+  if (nb1) return DIR == 1 ? 32LL * nb1 * (line0 >> 2) : 32LL * (line0 >> 3);
+  return DIR == 1 ? (long long)line0 * n1 : (long long)line0;
+}
+
+// Elements of a patch's storage.
+__host__ __device__ __forceinline__ long long patch_storage(int n1, int n2, int nb1) {
+  return nb1 ? 32LL * nb1 * ((n2 + 3) >> 2) : (long long)n1 * n2;
+}
+
+// Byte offset of element (pos, c) from the tile's first stored element.
+template <int DIR>
+__host__ __device__ __forceinline__ unsigned tile_goff(int pos, int c, int nb1, int n1) {
+  const int i = DIR == 1 ? pos : c, j = DIR == 1 ? c : pos;
+  if (nb1) return 4u * (unsigned)(32 * ((j >> 2) * nb1 + (i >> 3)) + 8 * (j & 3) + (i & 7));
+  return 4u * (unsigned)(j * n1 + i);
+}
+
+template <class T>
+__device__ __forceinline__ T& at(T* base, unsigned byte_off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* base, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// Visit the valid elements of a walk: f(g, l).
+template <class F>
+__device__ __forceinline__ void walk(Walk w, F&& f) {
+  for (; w.more(); w.next())
+    if (w.valid()) f(w.g, w.l);
+}
+
+// Batched walk for memory-latency-bound phases: pre(g) issues the loads of
+// U elements of the thread, then post(g, l, value) consumes them.  pre runs
+// unconditionally (elements that are not valid read the tile's first
+// element and are dropped), so the loads are straight-line code and all U
+// are in flight together; pre should only load, and leave arithmetic to post.
+template <int U, class Pre, class Post>
+__device__ __forceinline__ void walk_b(Walk w, Pre&& pre, Post&& post) {
+  using T = decltype(pre(0u));
+  while (w.more()) {
     T v[U];
-    int ps[U], cs[U];
+    unsigned gs[U], ls[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ok[u] = it.get(ps[u], cs[u]);
-      v[u] = pre(ok[u] ? ps[u] : 0, ok[u] ? cs[u] : 0);
-      it.next();
+      ok[u] = w.valid();
+      gs[u] = ok[u] ? w.g : 0u;
+      ls[u] = w.l;
+      v[u] = pre(gs[u]);
+      w.next();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (ok[u]) post(ps[u], cs[u], v[u]);
+      if (ok[u]) post(gs[u], ls[u], v[u]);
   }
 }
 
@@ -393,33 +460,35 @@ __device__ __forceinline__ void difference_ext(const LineCtx& X, const PlanDev& 
   __syncthreads();
 }
 
-// Load a pair of planes (A, B) along the tile's lines (complex line
-// c0 + c holds line c of A in re, of B in im) and write the interior of the
-// differenced extension at once: z[n] = f[n+1] - f[n] for n < N-1 (the
-// second sample comes from the same or the next cache line).  The 2d end
-// samples, minus the reference (ra, rb), go to the side buffer for
-// diff_tail.  Replaces a load followed by difference_ext: one LDS pass and
-// two barriers fewer.  The caller syncs, runs diff_tail, syncs.
-template <int DIR, int U, class G>
-__device__ __forceinline__ void load_differenced(const LineCtx& X, const PlanDev& P, int nl, int c0, G&& gidx,
-                                                 const float* __restrict__ A, const float* __restrict__ B,
-                                                 float ra, float rb, int d) {
-  const int N = P.N, ld = X.ld;
-  float2* __restrict__ z = X.z;
-  float2* __restrict__ side = X.side;
-  for_elems_b<DIR, U>(
-      N, nl, P.nb1,
-      [&](int pos, int c) {
-        const long long g = gidx(pos, c);
-        const long long g2 = gidx(pos + 1 < N ? pos + 1 : pos, c);
-        return make_float4(A[g], B[g], A[g2], B[g2]);
+// Load a pair of planes along the tile's lines (complex line c0 + c holds
+// line c of A in re, of B in im; A, B point at the tile's first stored
+// element) and write the interior of the differenced extension at once:
+// z[n] = f[n+1] - f[n] (the second sample comes from the same or the next
+// storage block; at n = N-1 it is any element of the patch, gmax bounds it,
+// and position N-1 is rewritten by diff_tail).  The 2d end samples, minus
+// the reference (ra, rb), go to the side buffer for diff_tail.  Replaces a
+// load followed by difference_ext: one LDS pass and two barriers fewer.  The
+// caller syncs, runs diff_tail, syncs.
+template <int DIR, int U>
+__device__ __forceinline__ void load_differenced(const LineCtx& X, const Walk& w, unsigned gmax, int N, int nl,
+                                                 int c0, int nb1, int n1, const float* __restrict__ A,
+                                                 const float* __restrict__ B, float ra, float rb, int d) {
+  float2* __restrict__ z = X.z + c0;
+  const unsigned gn = w.gnext;
+  walk_b<U>(
+      w,
+      [&](unsigned g) {
+        const unsigned g2 = min(g + gn, gmax);
+        return make_float4(at(A, g), at(B, g), at(A, g2), at(B, g2));
       },
-      [&](int pos, int c, float4 v) {
-        const int cc = c0 + c;
-        if (pos < N - 1) z[pos * ld + cc] = make_float2(v.z - v.x, v.w - v.y);
-        if (pos < d) side[pos * ld + cc] = make_float2(v.x - ra, v.y - rb);
-        if (pos >= N - d) side[(pos - N + 2 * d) * ld + cc] = make_float2(v.x - ra, v.y - rb);
-      });
+      [&](unsigned, unsigned l, float4 v) { at(z, l) = make_float2(v.z - v.x, v.w - v.y); });
+  const int ld = X.ld;
+  for (int i = threadIdx.x; i < 2 * d * nl; i += blockDim.x) {
+    const int k = i / nl, c = i - k * nl;
+    const int pos = k < d ? k : N - 2 * d + k;
+    const unsigned g = tile_goff<DIR>(pos, c, nb1, n1);
+    X.side[k * ld + c0 + c] = make_float2(at(A, g) - ra, at(B, g) - rb);
+  }
 }
 
 // The C + 1 differences that involve the tail (FP64 rows of the

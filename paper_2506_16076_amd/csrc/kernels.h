@@ -104,13 +104,23 @@ __device__ __forceinline__ void dev_flux(const float e[4], const float er[4], co
   dG[3] = dv * H + pr[2] * (dE + dp);
 }
 
-// plane index of element (pos, c) of a tile
+// Global side of a tile: its element walk, the element offset of its first
+// stored element in a plane, and the byte offset (from that element) of the
+// last element of the patch's storage.
+struct TileMem {
+  Walk w;
+  long long base;
+  unsigned gmax;
+};
+
 template <int DIR>
-__device__ __forceinline__ long long gindex(const PlanDev& P, const TileDev& T, int pos, int c) {
-  const int i = DIR == 1 ? pos : T.line0 + c;
-  const int j = DIR == 1 ? T.line0 + c : pos;
-  if (P.nb1 == 0) return P.off + (long long)j * P.n1 + i;
-  return P.off + ((((long long)(j >> 2)) * P.nb1 + (i >> 3)) << 5) + ((j & 3) << 3) + (i & 7);
+__device__ __forceinline__ TileMem tile_mem(const PlanDev& P, const TileDev& T, int nl, int ld) {
+  TileMem m;
+  m.w = make_walk<DIR>(P.N, nl, ld, P.nb1, P.n1);
+  const long long first = tile_first<DIR>(T.line0, P.nb1, P.n1);
+  m.base = P.off + first;
+  m.gmax = 4u * (unsigned)(patch_storage(P.n1, P.n2, P.nb1) - 1 - first);
+  return m;
 }
 
 extern __shared__ float2 lds_z[];
@@ -126,6 +136,7 @@ extern __shared__ float2 lds_z[];
   const int N = P.N, nl = T.nl, ld = T.ld;                                   \
   (void)Pg;                                                                  \
   (void)nl;                                                                  \
+  (void)N;                                                                   \
   __syncthreads();
 
 // Forward derivative of pairs already loaded by load_differenced: tail
@@ -142,84 +153,75 @@ extern __shared__ float2 lds_z[];
 template <int DIR, bool ADJ>
 __global__ void FCSD_LINE_BOUNDS k_fcdiff(PassArgs a) {
   FCSD_TILE_BEGIN(a)
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
   for (int f = 0; f < a.nf; f += 2) {
     const bool two = f + 1 < a.nf;
-    const float* A = a.in + (long long)f * a.plane;
-    const float* B = a.in + (long long)(f + 1) * a.plane;
-    const float* Bs = two ? B : A;
+    const float* A = a.in + (long long)f * a.plane + M.base;
+    const float* B = two ? a.in + (long long)(f + 1) * a.plane + M.base : A;
     if (!ADJ) {
-      load_differenced<DIR, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<DIR>(P, T, pos, c); }, A, Bs,
-                               0.f, 0.f, a.d);
+      load_differenced<DIR, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, A, B, 0.f, 0.f, a.d);
       FCSD_DIFF_AND_TRANSFORM(a)
     } else {
-      for_elems_b<DIR, 8>(
-          N, nl, P.nb1,
-          [&](int pos, int c) {
-            const long long g = gindex<DIR>(P, T, pos, c);
-            return make_float2(A[g], Bs[g]);
-          },
-          [&](int pos, int c, float2 v) { z[pos * ld + c] = make_float2(v.x, two ? v.y : 0.f); });
+      walk_b<8>(
+          M.w, [&](unsigned g) { return make_float2(at(A, g), at(B, g)); },
+          [&](unsigned, unsigned l, float2 v) { at(z, l) = make_float2(v.x, two ? v.y : 0.f); });
       __syncthreads();
       line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
     }
-    float* OA = a.out + (long long)f * a.plane;
-    float* OB = a.out + (long long)(f + 1) * a.plane;
-    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
-      const long long g = gindex<DIR>(P, T, pos, c);
-      const float2 v = z[pos * ld + c];
+    float* OA = a.out + (long long)f * a.plane + M.base;
+    float* OB = two ? a.out + (long long)(f + 1) * a.plane + M.base : OA;
+    walk(M.w, [&](unsigned g, unsigned l) {
+      const float2 v = at(z, l);
       if (ADJ) {
-        OA[g] += v.x;
-        if (two) OB[g] += v.y;
+        at(OA, g) += v.x;
+        if (two) at(OB, g) += v.y;
       } else {
-        OA[g] = v.x;
-        if (two) OB[g] = v.y;
+        at(OA, g) = v.x;
+        if (two) at(OB, g) = v.y;
       }
     });
     __syncthreads();
   }
 }
 
-// fc_continue (FWD) and its transpose: ext lines of length L per plan.
+// fc_continue (FWD) and its transpose: ext lines of length L per plan
+// (line c of the tile at ext offset e0 + c L, row-major).
 template <int DIR, bool ADJ>
 __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
   FCSD_TILE_BEGIN(a)
   const int L = P.L;
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  const Walk we = make_walk<1>(L, nl, ld, 0, L);
   const long long e0 = a.ext_off[T.plan] + (long long)T.line0 * L;
   for (int f = 0; f < a.nf; f += 2) {
     const bool two = f + 1 < a.nf;
     if (!ADJ) {
-      const float* A = a.in + (long long)f * a.plane;
-      const float* B = a.in + (long long)(f + 1) * a.plane;
-      for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
-        const long long g = gindex<DIR>(P, T, pos, c);
-        z[pos * ld + c] = make_float2(A[g], two ? B[g] : 0.f);
-      });
+      const float* A = a.in + (long long)f * a.plane + M.base;
+      const float* B = two ? a.in + (long long)(f + 1) * a.plane + M.base : A;
+      walk(M.w, [&](unsigned g, unsigned l) { at(z, l) = make_float2(at(A, g), two ? at(B, g) : 0.f); });
       __syncthreads();
       if (!P.periodic) fc_tail(X, P, a.aq + P.aq, a.d);
       __syncthreads();
       float* OA = a.out + (long long)f * a.ext_plane + e0;
-      float* OB = a.out + (long long)(f + 1) * a.ext_plane + e0;
-      for_elems<1>(L, nl, 0, [&](int pos, int c) {
-        const float2 v = z[pos * ld + c];
-        OA[(long long)c * L + pos] = v.x;
-        if (two) OB[(long long)c * L + pos] = v.y;
+      float* OB = two ? a.out + (long long)(f + 1) * a.ext_plane + e0 : OA;
+      walk(we, [&](unsigned g, unsigned l) {
+        const float2 v = at(z, l);
+        at(OA, g) = v.x;
+        if (two) at(OB, g) = v.y;
       });
     } else {
       const float* A = a.in + (long long)f * a.ext_plane + e0;
-      const float* B = a.in + (long long)(f + 1) * a.ext_plane + e0;
-      for_elems<1>(L, nl, 0, [&](int pos, int c) {
-        z[pos * ld + c] = make_float2(A[(long long)c * L + pos], two ? B[(long long)c * L + pos] : 0.f);
-      });
+      const float* B = two ? a.in + (long long)(f + 1) * a.ext_plane + e0 : A;
+      walk(we, [&](unsigned g, unsigned l) { at(z, l) = make_float2(at(A, g), two ? at(B, g) : 0.f); });
       __syncthreads();
       if (!P.periodic) fold_tail(X, P, a.aq + P.aq, a.d);
       __syncthreads();
-      float* OA = a.out + (long long)f * a.plane;
-      float* OB = a.out + (long long)(f + 1) * a.plane;
-      for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
-        const long long g = gindex<DIR>(P, T, pos, c);
-        const float2 v = z[pos * ld + c];
-        OA[g] += v.x;
-        if (two) OB[g] += v.y;
+      float* OA = a.out + (long long)f * a.plane + M.base;
+      float* OB = two ? a.out + (long long)(f + 1) * a.plane + M.base : OA;
+      walk(M.w, [&](unsigned g, unsigned l) {
+        const float2 v = at(z, l);
+        at(OA, g) += v.x;
+        if (two) at(OB, g) += v.y;
       });
     }
     __syncthreads();
@@ -232,21 +234,21 @@ __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
 template <int DIR>
 __global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
   FCSD_TILE_BEGIN(a)
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  const long long pl = a.plane;
   for (int f = 0; f < 4; f += 2) {
-    const float* A = a.u + (long long)f * a.plane;
-    const float* B = a.u + (long long)(f + 1) * a.plane;
+    const float* A = a.u + f * pl + M.base;
+    const float* B = a.u + (f + 1) * pl + M.base;
     // constant indices: a runtime index into the argument array would live in scratch
     const float ra = f == 0 ? a.eref[0] : a.eref[2], rb = f == 0 ? a.eref[1] : a.eref[3];
-    load_differenced<DIR, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<DIR>(P, T, pos, c); }, A, B,
-                                      ra, rb, a.d);
+    load_differenced<DIR, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, A, B, ra, rb, a.d);
     FCSD_DIFF_AND_TRANSFORM(a)
-    float* OA = a.out + (long long)f * a.plane;
-    float* OB = a.out + (long long)(f + 1) * a.plane;
-    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
-      const long long g = gindex<DIR>(P, T, pos, c);
-      const float2 v = z[pos * ld + c];
-      OA[g] = v.x;
-      OB[g] = v.y;
+    float* OA = a.out + f * pl + M.base;
+    float* OB = a.out + (f + 1) * pl + M.base;
+    walk(M.w, [&](unsigned g, unsigned l) {
+      const float2 v = at(z, l);
+      at(OA, g) = v.x;
+      at(OB, g) = v.y;
     });
     __syncthreads();
   }
@@ -260,24 +262,53 @@ struct HIn4 {
   float e[4];
 };
 
-__device__ __forceinline__ HIn4 load_H4_inputs(const PassArgs& a, long long g, int flux) {
+// Tile base pointers of those inputs (uniform).
+struct HSrc {
+  const float *m1x, *m1y, *m2x, *m2y, *mu;
+  const float *d10, *d11, *d12, *d13;
+  const float *e0, *e1, *e2, *e3;
+};
+
+__device__ __forceinline__ HSrc h_sources(const PassArgs& a, long long base, int flux) {
   const long long pl = a.plane;
   const bool visc = flux != FLUX_INVISCID, inv = flux != FLUX_VISC;
-  const float* mu = visc ? a.mu : a.metric;
-  const float* d1 = visc ? a.d1e : a.metric;
+  const float* mt = a.metric + base;
+  const float* d1 = (visc ? a.d1e : a.metric) + base;
   const long long ds = visc ? pl : 0;
-  const float* e = inv ? a.u : a.metric;
+  const float* e = (inv ? a.u : a.metric) + base;
   const long long es = inv ? pl : 0;
+  HSrc h;
+  h.m1x = mt;
+  h.m1y = mt + pl;
+  h.m2x = mt + 2 * pl;
+  h.m2y = mt + 3 * pl;
+  h.mu = (visc ? a.mu : a.metric) + base;
+  h.d10 = d1;
+  h.d11 = d1 + ds;
+  h.d12 = d1 + 2 * ds;
+  h.d13 = d1 + 3 * ds;
+  h.e0 = e;
+  h.e1 = e + es;
+  h.e2 = e + 2 * es;
+  h.e3 = e + 3 * es;
+  return h;
+}
+
+__device__ __forceinline__ HIn4 load_H4_inputs(const HSrc& h, unsigned g) {
   HIn4 q;
-  q.m1x = a.metric[g];
-  q.m1y = a.metric[pl + g];
-  q.m2x = a.metric[2 * pl + g];
-  q.m2y = a.metric[3 * pl + g];
-  q.mu = mu[g];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) q.d1[k] = d1[k * ds + g];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) q.e[k] = e[k * es + g];
+  q.m1x = at(h.m1x, g);
+  q.m1y = at(h.m1y, g);
+  q.m2x = at(h.m2x, g);
+  q.m2y = at(h.m2y, g);
+  q.mu = at(h.mu, g);
+  q.d1[0] = at(h.d10, g);
+  q.d1[1] = at(h.d11, g);
+  q.d1[2] = at(h.d12, g);
+  q.d1[3] = at(h.d13, g);
+  q.e[0] = at(h.e0, g);
+  q.e[1] = at(h.e1, g);
+  q.e[2] = at(h.e2, g);
+  q.e[3] = at(h.e3, g);
   return q;
 }
 
@@ -296,18 +327,22 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
   float2* __restrict__ z = X.z;
   const int N = P.N, nl = T.nl, ld = T.ld;
   const long long pl = a.plane;
+  const TileMem M = tile_mem<2>(P, T, nl, ld);
   __syncthreads();
-  auto gi = [&](int pos, int c) { return gindex<2>(P, T, pos, c); };
-  load_differenced<2, kDiffBatch>(X, P, nl, 0, gi, a.u, a.u + pl, a.eref[0], a.eref[1], a.d);
-  load_differenced<2, kDiffBatch>(X, P, nl, nl, gi, a.u + 2 * pl, a.u + 3 * pl, a.eref[2], a.eref[3], a.d);
+  const float* u = a.u + M.base;
+  load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, u, u + pl, a.eref[0], a.eref[1], a.d);
+  load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, nl, P.nb1, P.n1, u + 2 * pl, u + 3 * pl, a.eref[2],
+                                  a.eref[3], a.d);
   FCSD_DIFF_AND_TRANSFORM(a)
   const int flux = a.mode;
-  for_elems_b<2, kEpiBatchH>(
-      N, nl, P.nb1, [&](int pos, int c) { return load_H4_inputs(a, gindex<2>(P, T, pos, c), flux); },
-      [&](int pos, int c, const HIn4& q) {
-        const long long g = gindex<2>(P, T, pos, c);
-        const float2 za = z[pos * ld + c], zb = z[pos * ld + nl + c];
-        const float d2[4] = {za.x, za.y, zb.x, zb.y};
+  const HSrc hs = h_sources(a, M.base, flux);
+  float* H = a.H + M.base;
+  const float2* zb = z + nl;
+  walk_b<kEpiBatchH>(
+      M.w, [&](unsigned g) { return load_H4_inputs(hs, g); },
+      [&](unsigned g, unsigned l, const HIn4& q) {
+        const float2 za = at(z, l), zq = at(zb, l);
+        const float d2[4] = {za.x, za.y, zq.x, zq.y};
         float dF[4] = {0.f, 0.f, 0.f, 0.f}, dG[4] = {0.f, 0.f, 0.f, 0.f};
         if (flux != FLUX_VISC) dev_flux(q.e, a.eref, a.pref, a.gamma, dF, dG);
 #pragma unroll
@@ -317,8 +352,8 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
             vx = q.mu * (q.m1x * q.d1[k] + q.m2x * d2[k]);
             vy = q.mu * (q.m1y * q.d1[k] + q.m2y * d2[k]);
           }
-          a.H[(long long)(2 * k) * pl + g] = vx - dF[k];
-          a.H[(long long)(2 * k + 1) * pl + g] = vy - dG[k];
+          at(H + (2 * k) * pl, g) = vx - dF[k];
+          at(H + (2 * k + 1) * pl, g) = vy - dG[k];
         }
       });
 }
@@ -346,23 +381,21 @@ __global__ void __launch_bounds__(kBlock) k_passH(PassArgs a, long long n) {
 // Pass B2 (q2 lines): r2_c = m2x d2 H_x,c + m2y d2 H_y,c.
 __global__ void FCSD_LINE_BOUNDS k_passB2(PassArgs a) {
   FCSD_TILE_BEGIN(a)
+  const TileMem M = tile_mem<2>(P, T, nl, ld);
   const long long pl = a.plane;
+  const float* m2x = a.metric + 2 * pl + M.base;
+  const float* m2y = a.metric + 3 * pl + M.base;
   for (int comp = 0; comp < 4; ++comp) {
-    const float* A = a.H + (long long)(2 * comp) * pl;
-    const float* B = a.H + (long long)(2 * comp + 1) * pl;
-    load_differenced<2, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<2>(P, T, pos, c); }, A, B,
-                                    0.f, 0.f, a.d);
+    const float* A = a.H + (2 * comp) * pl + M.base;
+    const float* B = a.H + (2 * comp + 1) * pl + M.base;
+    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, A, B, 0.f, 0.f, a.d);
     FCSD_DIFF_AND_TRANSFORM(a)
-    for_elems_b<2, kLoadBatch>(
-        N, nl, P.nb1,
-        [&](int pos, int c) {
-          const long long g = gindex<2>(P, T, pos, c);
-          return make_float2(a.metric[2 * pl + g], a.metric[3 * pl + g]);
-        },
-        [&](int pos, int c, float2 m) {
-          const long long g = gindex<2>(P, T, pos, c);
-          const float2 v = z[pos * ld + c];
-          a.r2[(long long)comp * pl + g] = m.x * v.x + m.y * v.y;
+    float* r2 = a.r2 + comp * pl + M.base;
+    walk_b<kLoadBatch>(
+        M.w, [&](unsigned g) { return make_float2(at(m2x, g), at(m2y, g)); },
+        [&](unsigned g, unsigned l, float2 m) {
+          const float2 v = at(z, l);
+          at(r2, g) = m.x * v.x + m.y * v.y;
         });
     __syncthreads();
   }
@@ -372,17 +405,19 @@ __global__ void FCSD_LINE_BOUNDS k_passB2(PassArgs a) {
 // or the SSPRK register update (RK).
 __global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
   FCSD_TILE_BEGIN(a)
+  const TileMem M = tile_mem<1>(P, T, nl, ld);
   const long long pl = a.plane;
   float dt = 0.f;
   const RkCoef K = rk_coef(a.stage);
   if (a.mode == MODE_RK) dt = a.dt[0];
+  const float* m1x = a.metric + M.base;
+  const float* m1y = a.metric + pl + M.base;
   for (int comp = 0; comp < 4; ++comp) {
-    const float* A = a.H + (long long)(2 * comp) * pl;
-    const float* B = a.H + (long long)(2 * comp + 1) * pl;
-    load_differenced<1, kDiffBatch>(X, P, nl, 0, [&](int pos, int c) { return gindex<1>(P, T, pos, c); }, A, B,
-                                    0.f, 0.f, a.d);
+    const float* A = a.H + (2 * comp) * pl + M.base;
+    const float* B = a.H + (2 * comp + 1) * pl + M.base;
+    load_differenced<1, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, A, B, 0.f, 0.f, a.d);
     FCSD_DIFF_AND_TRANSFORM(a)
-    const long long fo = (long long)comp * pl;
+    const long long fo = comp * pl + M.base;
     // point inputs: the q1 metric row, r2 and the SSPRK registers of the
     // stage; every load is issued (registers the stage does not use read r2)
     const float* r2c = a.r2 + fo;
@@ -390,43 +425,44 @@ __global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
     const float* uic = rk ? a.ui + fo : r2c;
     const float* wc = a.mode == MODE_ADD ? a.rhs + fo : ((rk && a.stage >= 3) ? a.acc + fo : r2c);
     const float* u0c = (rk && a.stage <= 3) ? a.u0 + fo : r2c;
+    float* rhs = a.rhs + fo;
+    float* uout = a.uout + fo;
+    float* acc = a.acc + fo;
     struct CIn {
       float m1x, m1y, r2, ui, w, u0;
     };
-    for_elems_b<1, kEpiBatchC>(
-        N, nl, P.nb1,
-        [&](int pos, int c) {
-          const long long g = gindex<1>(P, T, pos, c);
+    walk_b<kEpiBatchC>(
+        M.w,
+        [&](unsigned g) {
           CIn q;
-          q.m1x = a.metric[g];
-          q.m1y = a.metric[pl + g];
-          q.r2 = r2c[g];
-          q.ui = uic[g];
-          q.w = wc[g];
-          q.u0 = u0c[g];
+          q.m1x = at(m1x, g);
+          q.m1y = at(m1y, g);
+          q.r2 = at(r2c, g);
+          q.ui = at(uic, g);
+          q.w = at(wc, g);
+          q.u0 = at(u0c, g);
           return q;
         },
-        [&](int pos, int c, const CIn& q) {
-          const long long g = gindex<1>(P, T, pos, c);
-          const float2 v = z[pos * ld + c];
+        [&](unsigned g, unsigned l, const CIn& q) {
+          const float2 v = at(z, l);
           const float r = q.m1x * v.x + q.m1y * v.y + q.r2;
           if (a.mode == MODE_SET) {
-            a.rhs[fo + g] = r;
+            at(rhs, g) = r;
           } else if (a.mode == MODE_ADD) {
-            a.rhs[fo + g] = q.w + r;
+            at(rhs, g) = q.w + r;
           } else {
             const float ui = q.ui;
             const float dr = dt * r;
             if (a.stage <= 1) {
-              a.uout[fo + g] = K.a0 * q.u0 + K.ai * ui + K.b * dr;
+              at(uout, g) = K.a0 * q.u0 + K.ai * ui + K.b * dr;
             } else if (a.stage == 2) {
-              a.uout[fo + g] = K.a0 * q.u0 + K.ai * ui + K.b * dr;
-              a.acc[fo + g] = K.acc_i * ui;
+              at(uout, g) = K.a0 * q.u0 + K.ai * ui + K.b * dr;
+              at(acc, g) = K.acc_i * ui;
             } else if (a.stage == 3) {
-              a.uout[fo + g] = K.a0 * q.u0 + K.ai * ui + K.b * dr;
-              a.acc[fo + g] = q.w + (K.acc_i * ui + K.acc_b * dr);
+              at(uout, g) = K.a0 * q.u0 + K.ai * ui + K.b * dr;
+              at(acc, g) = q.w + (K.acc_i * ui + K.acc_b * dr);
             } else {
-              a.uout[fo + g] = q.w + K.ai * ui + K.b * dr;
+              at(uout, g) = q.w + K.ai * ui + K.b * dr;
             }
           }
         });

@@ -827,38 +827,41 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
                                                   const float* d1e, const float* d2e, float* G1,
                                                   float* G2, float* mub, float* ub, int visc) {
   FCSD_TILE_BEGIN(a)
-  const long long pl = a.plane;
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  const long long pl = a.plane, bo = M.base;
   const int mx = DIR == 1 ? 0 : 2, my = DIR == 1 ? 1 : 3;
+  const float* mdx = a.metric + mx * pl + bo;
+  const float* mdy = a.metric + my * pl + bo;
   for (int comp = 0; comp < 4; ++comp) {
-    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
-      const long long g = gindex<DIR>(P, T, pos, c);
-      const float r = rb[(long long)comp * pl + g];
-      z[pos * ld + c] = make_float2(a.metric[mx * pl + g] * r, a.metric[my * pl + g] * r);
+    const float* rbc = rb + comp * pl + bo;
+    walk(M.w, [&](unsigned g, unsigned l) {
+      const float r = at(rbc, g);
+      at(z, l) = make_float2(at(mdx, g) * r, at(mdy, g) * r);
     });
     __syncthreads();
     line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
-    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
-      const long long g = gindex<DIR>(P, T, pos, c);
-      const float2 v = z[pos * ld + c];
-      const long long ix = (long long)(2 * comp) * pl + g, iy = (long long)(2 * comp + 1) * pl + g;
+    float* hbx = Hb + (2 * comp) * pl + bo;
+    float* hby = Hb + (2 * comp + 1) * pl + bo;
+    const long long fo = comp * pl + bo;
+    walk(M.w, [&](unsigned g, unsigned l) {
+      const float2 v = at(z, l);
       if (DIR == 1) {
-        Hb[ix] = v.x;
-        Hb[iy] = v.y;
+        at(hbx, g) = v.x;
+        at(hby, g) = v.y;
       } else {
-        const float hx = Hb[ix] + v.x, hy = Hb[iy] + v.y;
-        Hb[ix] = hx;
-        Hb[iy] = hy;
+        const float hx = at(hbx, g) + v.x, hy = at(hby, g) + v.y;
+        at(hbx, g) = hx;
+        at(hby, g) = hy;
         if (visc) {
-          const float m1x = a.metric[g], m1y = a.metric[pl + g], m2x = a.metric[2 * pl + g],
-                      m2y = a.metric[3 * pl + g];
-          const float mu = a.mu[g];
-          const long long fo = (long long)comp * pl + g;
-          G1[fo] = mu * (m1x * hx + m1y * hy);
-          G2[fo] = mu * (m2x * hx + m2y * hy);
+          const float m1x = at(a.metric + bo, g), m1y = at(a.metric + pl + bo, g),
+                      m2x = at(a.metric + 2 * pl + bo, g), m2y = at(a.metric + 3 * pl + bo, g);
+          const float mu = at(a.mu + bo, g);
+          at(G1 + fo, g) = mu * (m1x * hx + m1y * hy);
+          at(G2 + fo, g) = mu * (m2x * hx + m2y * hy);
           if (mub) {
-            const float ex = m1x * d1e[fo] + m2x * d2e[fo];
-            const float ey = m1y * d1e[fo] + m2y * d2e[fo];
-            mub[g] += hx * ex + hy * ey;
+            const float ex = m1x * at(d1e + fo, g) + m2x * at(d2e + fo, g);
+            const float ey = m1y * at(d1e + fo, g) + m2y * at(d2e + fo, g);
+            at(mub + bo, g) += hx * ex + hy * ey;
           }
         }
       }
@@ -866,18 +869,17 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
     __syncthreads();
   }
   if (DIR == 2 && a.mode != FLUX_VISC) {
-    for_elems<DIR>(N, nl, P.nb1, [&](int pos, int c) {
-      const long long g = gindex<DIR>(P, T, pos, c);
+    walk(M.w, [&](unsigned g, unsigned) {
       float e[4], fb[4], gb[4], o[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        e[q] = a.u[(long long)q * pl + g];
-        fb[q] = -Hb[(long long)(2 * q) * pl + g];
-        gb[q] = -Hb[(long long)(2 * q + 1) * pl + g];
+        e[q] = at(a.u + q * pl + bo, g);
+        fb[q] = -at(Hb + (2 * q) * pl + bo, g);
+        gb[q] = -at(Hb + (2 * q + 1) * pl + bo, g);
       }
       flux_vjp(e, a.gamma, fb, gb, o);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ub[(long long)q * pl + g] += o[q];
+      for (int q = 0; q < 4; ++q) at(ub + q * pl + bo, g) += o[q];
     });
   }
 }
