@@ -297,40 +297,55 @@ __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
   const int m = M / R;
   const int stride = L / M;
   const int nb = L / R;
-  const int ld = X.ld, c = X.c;
-  float2* __restrict__ z = X.z;
-  int b = X.b0;
-  int blk = b / m, j = b - blk * m;
+  const int ld = X.ld;
+  // butterfly b of the thread: block blk = b / m, index j = b % m; every
+  // offset below is in bytes and advances by a uniform step per iteration,
+  // with one correction when j passes m
   const int dblk = X.BS / m, dj = X.BS - dblk * m;
+  const unsigned leg = 8u * (unsigned)(m * ld);                     // between the R legs
+  const unsigned da = 8u * (unsigned)((dblk * M + dj) * ld);        // leg 0, per iteration
+  const unsigned wa = 8u * (unsigned)((M - m) * ld);                // leg 0, when j wraps
+  const unsigned dtw = 8u * (unsigned)(stride * dj), wtw = 8u * (unsigned)(stride * m);
+  const unsigned dk = 8u * (unsigned)(X.BS * R);
+  int b = X.b0;
+  const int blk = b / m;
+  int j = b - blk * m;
+  unsigned a = 8u * (unsigned)((blk * M + j) * ld + X.c);
+  unsigned tq = 8u * (unsigned)(stride * j);  // twiddle w^(j) of leg 1; leg q reads q tq
+  unsigned kq = 8u * (unsigned)(b * R);       // MUL (m = 1): multipliers of positions b R ..
   for (; b < nb; b += X.BS) {
-    const int base = blk * M + j;
     float2 x[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) x[t] = z[(base + t * m) * ld + c];
+    for (int t = 0; t < R; ++t) x[t] = at(X.z, a + t * leg);
+    // j = 0 reads twiddle 1 + 0i: the product is exact, so no branch
     if (!INV) {
       Dft<R, false>::run(x);
       if (MUL) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) x[q] = CONJ ? cmulc(x[q], X.km[base + q]) : cmul(x[q], X.km[base + q]);
+        for (int q = 0; q < R; ++q) {
+          const float2 k = at(X.km, kq + 8u * q);
+          x[q] = CONJ ? cmulc(x[q], k) : cmul(x[q], k);
+        }
         Dft<R, true>::run(x);
-      } else if (j) {
+      } else {
 #pragma unroll
-        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], X.tw[stride * j * q]);
+        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], at(X.tw, q * tq));
       }
     } else {
-      if (j) {
 #pragma unroll
-        for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], X.tw[stride * j * q]);
-      }
+      for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], at(X.tw, q * tq));
       Dft<R, true>::run(x);
     }
 #pragma unroll
-    for (int t = 0; t < R; ++t) z[(base + t * m) * ld + c] = x[t];
+    for (int t = 0; t < R; ++t) at(X.z, a + t * leg) = x[t];
+    a += da;
+    tq += dtw;
+    kq += dk;
     j += dj;
-    blk += dblk;
     if (j >= m) {
       j -= m;
-      ++blk;
+      a += wa;
+      tq -= wtw;
     }
   }
 }
@@ -343,7 +358,14 @@ __device__ __forceinline__ void fft_dispatch(int R, const LineCtx& X, int L, int
     case 4: fft_stage<4, INV, MUL, CONJ>(X, L, M); break;
     case 5: fft_stage<5, INV, MUL, CONJ>(X, L, M); break;
     case 7: fft_stage<7, INV, MUL, CONJ>(X, L, M); break;
+    case 6: fft_stage<6, INV, MUL, CONJ>(X, L, M); break;
     case 8: fft_stage<8, INV, MUL, CONJ>(X, L, M); break;
+    case 9: fft_stage<9, INV, MUL, CONJ>(X, L, M); break;
+    case 10: fft_stage<10, INV, MUL, CONJ>(X, L, M); break;
+    case 12: fft_stage<12, INV, MUL, CONJ>(X, L, M); break;
+    case 14: fft_stage<14, INV, MUL, CONJ>(X, L, M); break;
+    case 15: fft_stage<15, INV, MUL, CONJ>(X, L, M); break;
+    case 16: fft_stage<16, INV, MUL, CONJ>(X, L, M); break;
     case 11: fft_stage<11, INV, MUL, CONJ>(X, L, M); break;
     case 13: fft_stage<13, INV, MUL, CONJ>(X, L, M); break;
     default: break;
@@ -589,7 +611,7 @@ __device__ __forceinline__ void fft_derivative(const LineCtx& X, const PlanDev* 
 // Derivative of the tile in place; the caller has filled positions 0..N-1
 // and synchronised.  ADJ = transpose (Delta^T, conjugate multipliers, fold).
 template <bool ADJ>
-__device__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
+__device__ __forceinline__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
                                 const double* __restrict__ aqp, const double* __restrict__ dqp, int d) {
   if (!ADJ)
     difference_ext(X, P, dqp + P.dq, d);

@@ -20,6 +20,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
+#include <array>
 #include <vector>
 
 namespace {
@@ -179,34 +181,73 @@ extern "C" void fcsd_host_twiddles(int L, float* out) {
   }
 }
 
-// Factor L into supported radices (largest first among 13, 11, 7, 5, 3 then
-// 8/4/2 for the power of two).  Returns the number of stages or 0 if L has
-// another prime factor or needs more than 8 stages.
+// Radix plan of a transform of length L: the radices r_0 .. r_{s-1} (product
+// L, at most 8) of the in-place stages.  The engine runs stages 0 .. s-2
+// forward and again inverse, each with twiddles, and the last one fused with
+// the multiplier and the first inverse butterfly, so a plan costs
+// 2 sum_{i < s-1} c(r_i) + c_f(r_{s-1}).  c and c_f are the vector
+// instructions per point of one stage of the generated code for gfx950 plus a
+// fixed charge for the LDS round trip and the barrier of a stage; the search
+// is exhaustive over the divisors of L.  Returns the number of stages, or 0 if
+// L has a prime factor above 13 or needs more than 8 stages.
+namespace {
+struct RadixCost {
+  int r;
+  double stage, fused;
+};
+constexpr double kStageCharge = 4.0;
+constexpr RadixCost kRadixCost[] = {
+    {2, 13.0, 15.0},  {3, 13.3, 17.0},  {4, 12.75, 16.0}, {5, 15.4, 21.8},  {6, 13.7, 19.0},
+    {7, 16.9, 25.6},  {8, 13.75, 19.5}, {9, 16.9, 25.9},  {10, 16.2, 24.6}, {11, 20.5, 33.4},
+    {12, 14.8, 22.0}, {13, 22.5, 37.3}, {14, 18.1, 28.7}, {15, 17.9, 28.2}, {16, 16.4, 25.3},
+};
+}  // namespace
+
 extern "C" int fcsd_host_factor(int L, int* rad) {
-  int n = L, k = 0;
-  const int odd[5] = {13, 11, 7, 5, 3};
-  for (int p : odd)
-    while (n % p == 0) {
-      if (k >= 8) return 0;
-      rad[k++] = p;
-      n /= p;
+  if (L < 2) return 0;
+  const double inf = 1e300;
+  // best[n][k]: cheapest k twiddle stages with product n (forward + inverse)
+  std::vector<std::array<double, 8>> best(L + 1);
+  std::vector<std::array<int, 8>> pick(L + 1);
+  for (int n = 0; n <= L; ++n) {
+    best[n].fill(inf);
+    pick[n].fill(0);
+  }
+  best[1][0] = 0.0;
+  for (int n = 2; n <= L; ++n) {
+    if (L % n) continue;
+    for (int k = 1; k < 8; ++k)
+      for (const RadixCost& c : kRadixCost) {
+        if (n % c.r || best[n / c.r][k - 1] >= inf) continue;
+        const double v = best[n / c.r][k - 1] + 2.0 * (c.stage + kStageCharge);
+        if (v < best[n][k]) {
+          best[n][k] = v;
+          pick[n][k] = c.r;
+        }
+      }
+  }
+  double top = inf;
+  int last = 0, kk = -1;
+  for (const RadixCost& c : kRadixCost) {
+    if (L % c.r) continue;
+    for (int k = 0; k < 8; ++k) {
+      const double v = best[L / c.r][k] + c.fused + kStageCharge;
+      if (v < top) {
+        top = v;
+        last = c.r;
+        kk = k;
+      }
     }
-  while (n % 8 == 0 && n != 16) {  // prefer 4*4 over 8*2 for 16
-    if (k >= 8) return 0;
-    rad[k++] = 8;
-    n /= 8;
   }
-  while (n % 4 == 0) {
-    if (k >= 8) return 0;
-    rad[k++] = 4;
-    n /= 4;
+  if (kk < 0) return 0;
+  int n = L / last, s = 0;
+  for (int k = kk; k > 0; --k) {
+    rad[s++] = pick[n][k];
+    n /= pick[n][k];
   }
-  while (n % 2 == 0) {
-    if (k >= 8) return 0;
-    rad[k++] = 2;
-    n /= 2;
-  }
-  return n == 1 ? k : 0;
+  std::sort(rad, rad + s, [](int a, int b) { return a > b; });
+  rad[s++] = last;
+  return s;
 }
 
 // Position -> signed wavenumber map of the in-place decimation-in-frequency

@@ -58,7 +58,7 @@ enum { MODE_SET = 0, MODE_ADD = 1, MODE_RK = 2 };
 
 // Line kernels: 256 threads, registers capped for five waves per SIMD (the
 // butterflies fit in ~96 VGPRs without spilling; five 32 KB tiles fill the LDS)
-#define FCSD_LINE_BOUNDS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
+#define FCSD_LINE_BOUNDS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 
 // elements per thread whose loads are in flight together
 constexpr int kLoadBatch = 12;  // load phases (two floats each)

@@ -61,7 +61,14 @@ def test_fft_plans(L):
                 L.fft_plan(Lx)
             continue
         r = L.fft_plan(Lx)
-        assert int(np.prod(r)) == Lx and set(r) <= {2, 3, 4, 5, 7, 8, 11, 13}
+        assert int(np.prod(r)) == Lx and set(r) <= set(range(2, 17)) and 1 <= len(r) <= 8
+        # composite radices: never more stages than the prime factorisation
+        n, primes = Lx, 0
+        for p in (2, 3, 5, 7, 11, 13):
+            while n % p == 0:
+                n //= p
+                primes += 1
+        assert len(r) <= primes
 
 
 def _twiddles(lib, n):
