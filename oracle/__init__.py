@@ -19,6 +19,8 @@ Modules
   rk       SSPRK(5,4) time stepping and the CFL step size (Sec. 4.1)
   av       proxy variable, network classifier, preliminary viscosity and the
            smoothing-blending operator (Secs. 5.1, 5.2)
+  filter   spectral filter of FC expansions and the per-step state filter
+           (Sec. 4.3.1)
   solver   multi-patch time stepping with fringe exchange and boundary
            overwrite (Secs. 3.4, 4.2, Algorithm 1)
   adjoint  hand-written discrete adjoints (reverse mode) of all of the above

@@ -3,10 +3,11 @@
 Test infrastructure only (see oracle/__init__.py).
 
 Per time step (Algorithm 1): evaluate the viscosity mu (network classifier,
-preliminary viscosity, smoothing-blending; or a given constant), evaluate
-the step size dt (eq. CFL), then advance the five SSPRK stages, enforcing
-boundary conditions and patch communication on every stage input (Sec. 4.2).
-The spectral filter of Sec. 4.3 is not part of this path.
+preliminary viscosity, smoothing-blending; or a given constant), optionally
+apply the spectral filter of Sec. 4.3.1 to the state (then glue again),
+evaluate the step size dt (eq. CFL), then advance the five SSPRK stages,
+enforcing boundary conditions and patch communication on every stage input
+(Sec. 4.2).
 
 Readings for the index-aligned annulus used by the synthetic workloads:
   * communication = copy of the n_f = 5 fringe lines from the neighbour's
@@ -23,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle import av, euler, rk
+from oracle import av, euler, filter as spectral_filter, rk
 
 NF = 5
 OVL = 19
@@ -83,9 +84,10 @@ class Run:
             return mu, None, None
         return av.viscosity(e, ps, self.cfg.mlp, self.gamma)
 
-    def step(self, dt=None, tau=None, arg=None, record=False):
+    def step(self, dt=None, tau=None, arg=None, record=False, filt=None):
         """One step; dt, tau, arg replay recorded decisions.  record keeps
-        the glued stage inputs for the discrete adjoint."""
+        the glued stage inputs for the discrete adjoint.  filt = (alpha, p)
+        applies the spectral filter after the viscosity."""
         ps, g = self.ps, self.gamma
         e = self.u
         glue(e, ps, self.mach, g)
@@ -93,6 +95,9 @@ class Run:
             mu, tau_used, arg = av.viscosity(e, ps, self.cfg.mlp, g, tau=tau, arg=arg)
         else:
             mu, tau_used, arg = self.viscosity(e)
+        if filt is not None:
+            e = spectral_filter.filter_state(e, ps, filt[0], filt[1], g)
+            glue(e, ps, self.mach, g)
         if dt is None:
             dt = rk.cfl_dt(e, mu, ps, self.cfg.cfl, g)
         L = lambda u, s: euler.full_rhs(u, ps.metric, mu, ps, g)
