@@ -86,3 +86,62 @@ def filter_state(e: np.ndarray, ps, alpha: float, p: int, gamma: float) -> np.nd
         src = ps.view(np.asarray(e, np.float64), k)
         ps.view(out, k)[...] = filter_state_patch(src, ps.d, int(ps.C1[k]), int(ps.C2[k]), alpha, p, gamma)
     return out
+
+
+# ------------------------------------------------------------ reverse mode
+
+def filter_lines_adj(Y: np.ndarray, d: int, C: int, alpha: float, p: int) -> np.ndarray:
+    """Transpose of filter_lines.  The line filter is R S E (E the extension,
+    S = F^-1 diag(sigma) F the real symmetric circulant, R the restriction to
+    N points), so its transpose is E^T S R^T: zero-pad, filter the padded
+    line, fold the tail back through the continuation matrix."""
+    Y = np.asarray(Y, np.float64)
+    if C == 0:
+        return filter_lines(Y, d, 0, alpha, p)
+    N = Y.shape[-1]
+    pad = np.concatenate([Y, np.zeros(Y.shape[:-1] + (C,))], axis=-1)
+    X = np.fft.fft(pad, axis=-1) * sigma(N + C, alpha, p)
+    g = np.real(np.fft.ifft(X, axis=-1))
+    return fcgram.extend_adj(g, fcgram.continuation_matrix(d, C), N)
+
+
+def filter_patch_adj(y: np.ndarray, d: int, C1: int, C2: int, alpha: float, p: int) -> np.ndarray:
+    """Transpose of filter_patch: the q^2 pass transposed, then the q^1 pass."""
+    t = np.swapaxes(filter_lines_adj(np.swapaxes(y, -1, -2), d, C2, alpha, p), -1, -2)
+    return filter_lines_adj(t, d, C1, alpha, p)
+
+
+def filter_state_patch_vjp(e: np.ndarray, eb: np.ndarray, d: int, C1: int, C2: int, alpha: float, p: int,
+                           gamma: float) -> np.ndarray:
+    """Cotangent of the state filter's input e given that of its output."""
+    e = np.asarray(e, np.float64)
+    eb = np.asarray(eb, np.float64)
+    g1 = gamma - 1.0
+    rho, m, n, E = e
+    q = np.stack([rho, m, n, theta_of(e, gamma)])
+    f = filter_patch(q, d, C1, C2, alpha, p)
+    rf, mf, nf, tf = f
+    # E' = rho' theta' / (gamma - 1) + (m'^2 + n'^2) / (2 rho')
+    Eb = eb[3]
+    qb = np.stack([eb[0] + Eb * (tf / g1 - 0.5 * (mf * mf + nf * nf) / (rf * rf)),
+                   eb[1] + Eb * mf / rf,
+                   eb[2] + Eb * nf / rf,
+                   Eb * rf / g1])
+    b = filter_patch_adj(qb, d, C1, C2, alpha, p)
+    # theta = (gamma - 1) (E / rho - (m^2 + n^2) / (2 rho^2))
+    tb = b[3]
+    return np.stack([b[0] + tb * g1 * (-E / (rho * rho) + (m * m + n * n) / rho ** 3),
+                     b[1] - tb * g1 * m / (rho * rho),
+                     b[2] - tb * g1 * n / (rho * rho),
+                     tb * g1 / rho])
+
+
+def filter_state_vjp(e: np.ndarray, eb: np.ndarray, ps, alpha: float, p: int, gamma: float) -> np.ndarray:
+    """Cotangent of filter_state's input (padding between patches passes
+    through unchanged, as the forward map leaves it)."""
+    out = np.array(eb, np.float64, copy=True)
+    for k in range(ps.npatch):
+        ps.view(out, k)[...] = filter_state_patch_vjp(ps.view(np.asarray(e, np.float64), k),
+                                                      ps.view(np.asarray(eb, np.float64), k), ps.d,
+                                                      int(ps.C1[k]), int(ps.C2[k]), alpha, p, gamma)
+    return out

@@ -13,6 +13,9 @@ against closed forms and invariants that do not restate its code:
   periodic extension and change the line at the 1e-3 level), while a line
   with a jump loses its high frequencies;
 * alpha = 0 is the identity;
+* reverse mode: <F x, y> = <x, F^T y> for the two-dimensional filter
+  (periodic and FC directions), and the state filter's vector-Jacobian
+  product against central differences;
 * the state filter on a doubly periodic patch with constant velocity and
   single-mode rho and theta = p / rho: rho and theta are filtered as single
   modes, rho u = u rho stays u times the filtered rho, and E is
@@ -115,3 +118,40 @@ def test_state_filter_constant_velocity_closed_form():
                      rho_f * theta_f / (gamma - 1) + 0.5 * rho_f * (u * u + v * v)])
     got = flt.filter_state_patch(e, 5, 0, 0, ALPHA, P, gamma)
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+# ------------------------------------------------------------ reverse mode
+
+@pytest.mark.parametrize("C1,C2", [(0, 0), (27, 30), (31, 0)])
+def test_patch_filter_transpose_dot_product(C1, C2):
+    rng = np.random.default_rng(C1 + 7 * C2)
+    n1, n2 = 40, 33
+    x = rng.standard_normal((n2, n1))
+    y = rng.standard_normal((n2, n1))
+    lhs = np.sum(flt.filter_patch(x, 5, C1, C2, ALPHA, P) * y)
+    rhs = np.sum(x * flt.filter_patch_adj(y, 5, C1, C2, ALPHA, P))
+    # random lines have extension tails up to |A_r Q^T| ~ 1e4 times their
+    # size, so FP64 rounding of the FFT pair reaches ~1e-11 here
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_state_filter_vjp_central_differences():
+    gamma = 1.4
+    rng = np.random.default_rng(5)
+    n1, n2 = 36, 30
+    j2, j1 = np.meshgrid(np.arange(n2) / (n2 - 1), np.arange(n1) / (n1 - 1), indexing="ij")
+    rho = 1.0 + 0.2 * np.sin(2.1 * j1 + 1.3 * j2) + 0.01 * rng.standard_normal((n2, n1))
+    u = 0.5 + 0.1 * np.cos(1.7 * j2)
+    v = -0.2 + 0.1 * np.sin(2.3 * j1)
+    pr = 1.0 + 0.1 * np.cos(3.0 * j1 * j2)
+    e = np.stack([rho, rho * u, rho * v, pr / (gamma - 1) + 0.5 * rho * (u * u + v * v)])
+    eb = rng.standard_normal(e.shape)
+    g = flt.filter_state_patch_vjp(e, eb, 5, 27, 28, ALPHA, P, gamma)
+    for _ in range(3):
+        de = rng.standard_normal(e.shape)
+        h = 1e-6
+        fp = flt.filter_state_patch(e + h * de, 5, 27, 28, ALPHA, P, gamma)
+        fm = flt.filter_state_patch(e - h * de, 5, 27, 28, ALPHA, P, gamma)
+        fd = np.sum((fp - fm) * eb) / (2 * h)
+        an = np.sum(g * de)
+        assert abs(fd - an) <= 1e-6 * abs(an)
