@@ -72,6 +72,10 @@ def recorded_traffic(kernel, npts):
     return fetch + write
 
 
+# per-step filter: q1 pass reads and writes the 4 state fields, the q2 pass
+# again (FP32)
+FILTER_BYTES = 64
+
 PASS_KERNEL = {"A": "k_dev_diff<1>", "B1": "k_passB1", "B2": "k_passB2", "C": "k_passC"}
 
 
@@ -257,6 +261,24 @@ def main():
     stage_bytes = sum(pass_gb.values()) * 1e9 / npts
     traffic = recorded_traffic(PASS_KERNEL[dom], npts)
 
+    # ---------------- per-step spectral filter (paper Sec. 4.3.1, alpha 10,
+    # p 14), timed on its own: two line passes over the state in place
+    s.set_filter(10.0, 14)
+    uf = u.clone()
+    api.fcsd_filter(s, uf, uf, 1.4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    for _ in range(4):
+        api.fcsd_filter(s, uf, uf, 1.4)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms_filter = e0.elapsed_time(e1) / 4
+    filt = {"ms": ms_filter, "bytes_per_point": FILTER_BYTES,
+            "achieved_GBs": FILTER_BYTES * npts / (ms_filter / 1e3) / 1e9,
+            "finite": bool(torch.isfinite(uf).all().item())}
+    del uf
+
     # ---------------- reverse mode: checkpointed adjoint of K steps
     adjoint = None
     if args.adj_steps > 0:
@@ -318,6 +340,7 @@ def main():
                      "batched_over_per_patch": None if ms_pp is None else ms_pp / ms_batched},
         "pass_ms": passes,
         "adjoint": adjoint,
+        "filter": filt,
         "schedule": {k: v for k, v in tuning.items() if k != "table"},
         "stage_bytes_per_point": stage_bytes,
         "stage_effective_GBs": stage_bytes * npts / (ms_batched / 5 / 1e3) / 1e9,

@@ -128,7 +128,8 @@ enum {
 fcsd_status fcsd_set_tune(fcsd_set* set, const int lds_budget[3], const int threads[3], int order);
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
-enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3, FCSD_WS_STEP_ADJ = 4 };
+enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3, FCSD_WS_STEP_ADJ = 4,
+       FCSD_WS_FILTER_ADJ = 5 };
 fcsd_status fcsd_workspace_size(const fcsd_set* set, int op, size_t* bytes);
 
 /* ---- FC-Gram line operators (Sec. 2.2) --------------------------------- */
@@ -145,6 +146,34 @@ fcsd_status fc_continue(fcsd_ctx* ctx, const fcsd_set* set, int dir, int nf,
 /* Transpose of fc_continue: in_bar += E^T ext_bar. */
 fcsd_status fc_continue_adj(fcsd_ctx* ctx, const fcsd_set* set, int dir, int nf,
                             const float* ext_bar, int64_t ext_plane, float* in_bar, int64_t plane);
+
+/* Spectral filter of FC expansions (paper Sec. 4.3.1, eq. filtering).
+ * fcsd_set_filter fixes its parameters for the set: every line of length L =
+ * N + C has its extension's coefficient at signed wavenumber k multiplied
+ * by sigma(2k/L) = exp(-alpha (2k/L)^p) (the paper uses alpha = 10, p = 14).
+ * alpha >= 0 finite, p even in [2, 64], else FCSD_EINVAL.  Synchronises the
+ * context's stream, uploads the factor tables and drops captured step
+ * graphs; until it is called, fcsd_filter and steps with a->filter return
+ * FCSD_EINVAL. */
+fcsd_status fcsd_set_filter(fcsd_set* set, double alpha, int p);
+
+/* The per-step state filter: for every patch, the one-dimensional filter
+ * along q1 lines and then along q2 lines of rho, rho u, rho v and theta =
+ * p / rho (eqs. perfect_gas, p_T); E is not filtered but rebuilt as
+ * rho theta / (gamma - 1) + |rho u|^2 / (2 rho) (eq. perfect_gas_T).
+ * u, out: [4][plane] states; out may equal u (in place).  Points outside
+ * the patches are not touched.  Asynchronous on the context's stream. */
+fcsd_status fcsd_filter(fcsd_ctx* ctx, const fcsd_set* set, const float* u, float* out, int64_t plane,
+                        float gamma);
+
+/* Reverse mode of fcsd_filter at state u: given the cotangent out_bar of
+ * the filtered state, writes the cotangent of u to u_bar (may alias
+ * out_bar, not u).  Each line filter R S E (S the real symmetric circulant)
+ * is transposed as E^T S R^T; the temperature and the rebuilt energy by
+ * their vector-Jacobian products.  ws: fcsd_workspace_size(
+ * FCSD_WS_FILTER_ADJ) bytes (the filtered state is recomputed there). */
+fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* out_bar,
+                            float* u_bar, int64_t plane, float gamma, void* ws, size_t ws_bytes);
 
 /* FC derivative d/dq^dir of nf fields (eq. fc_der): continuation, FFT of
  * length L, multiplication by 2 pi i k / beta (beta = L h, h = 1/(N-1);
@@ -300,11 +329,14 @@ typedef struct {
   const fcsd_mlp* w;    /* NULL: mu given (unless fixed_tau) */
   int fixed_tau;        /* 1: classes given in tau (network not run), mu
                            computed from them: replays a recorded step */
+  int filter;           /* 1: apply the spectral filter configured by
+                           fcsd_set_filter after the viscosity (then glue
+                           again), before the step size */
 } fcsd_step_args;
 
 /* One full time step (Algorithm 1): glue, network classes and viscosity
- * (when w != NULL), step size, five fused stages with glue on every stage
- * input.  use_graph = 1 captures the step once into a hipGraph and replays
+ * (when w != NULL), spectral filter and glue (when a->filter), step size,
+ * five fused stages with glue on every stage input.  use_graph = 1 captures the step once into a hipGraph and replays
  * it on later calls with identical arguments. */
 fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* a,
                       int64_t plane, void* ws, size_t ws_bytes, int use_graph);
@@ -322,7 +354,8 @@ fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* 
  * fcsd_step (tau, mu, argmax buffers required then; mu is rewritten);
  * constant mu (a->w == NULL, fixed_tau == 0) is not differentiated.
  * ws: fcsd_workspace_size(FCSD_WS_STEP_ADJ) bytes (paper Sec. 4, Algorithm 1,
- * transposed stage by stage). */
+ * transposed stage by stage; with a->filter the spectral filter and the
+ * glue after it are transposed too). */
 fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* a,
                           const float* u_in, float* u_bar, const float dstate_dparam[4],
                           double* dparam_dev, int64_t plane, void* ws, size_t ws_bytes);

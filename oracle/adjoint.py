@@ -10,6 +10,8 @@ contributes nothing through tau).  Building blocks:
 
   * the right-hand side VJP (euler.full_rhs_vjp) at every glued stage input;
   * the viscosity VJP (av.viscosity_vjp) at the glued step input;
+  * the spectral filter's VJP (filter.filter_state_vjp) and the glue after
+    it, when the step filters;
   * the transpose of the glue: Dirichlet overwrite (cotangent zeroed, the
     free-stream's Mach derivative collected), then the shell and sector
     fringe copies in reverse order (receiver cotangent moved to its donor);
@@ -20,6 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 from oracle import av, euler, rk, solver
+from oracle import filter as spectral_filter
 
 
 def glue_vjp(eb, ps, mach, gamma=1.4):
@@ -94,15 +97,22 @@ def step_vjp(run, entry, ub_next):
         if i >= 1:
             dM += glue_vjp(ub[i], ps, mach, g)
             distribute(i, ub[i])
+    u_visc = st[0]
+    if entry.get("filt") is not None:
+        alpha, p = entry["filt"]
+        dM += glue_vjp(ub[0], ps, mach, g)
+        ub[0] = spectral_filter.filter_state_vjp(entry["pre"], ub[0], ps, alpha, p, g)
+        u_visc = entry["pre"]
     if visc:
-        ub[0] += av.viscosity_vjp(st[0], entry["tau"], entry["arg"], ps, g, mub)
+        ub[0] += av.viscosity_vjp(u_visc, entry["tau"], entry["arg"], ps, g, mub)
     dM += glue_vjp(ub[0], ps, mach, g)
     return ub[0], dM
 
 
-def forward(cfg, steps, u0=None, mach=None, replay=None, record=True):
+def forward(cfg, steps, u0=None, mach=None, replay=None, record=True, filt=None):
     """Run `steps` steps in FP64 from u0 (default cfg.u0); replay: list of
-    recorded entries whose dt, tau, arg are reused."""
+    recorded entries whose dt, tau, arg are reused; filt = (alpha, p): the
+    spectral filter in every step."""
     run = solver.Run(cfg)
     if u0 is not None:
         run.u = np.array(u0, np.float64)
@@ -111,9 +121,9 @@ def forward(cfg, steps, u0=None, mach=None, replay=None, record=True):
     for k in range(steps):
         if replay is not None:
             e = replay[k]
-            run.step(dt=e["dt"], tau=e["tau"], arg=e["arg"], record=record)
+            run.step(dt=e["dt"], tau=e["tau"], arg=e["arg"], record=record, filt=filt)
         else:
-            run.step(record=record)
+            run.step(record=record, filt=filt)
     return run
 
 
@@ -142,13 +152,13 @@ def initial_state(ps, mach, amp, pert, gamma=1.4):
     return e, de_dM, de_da
 
 
-def gradient(cfg, steps, replay=None):
+def gradient(cfg, steps, replay=None, filt=None):
     """Loss and its gradient with respect to (M, a_1..a_K) through `steps`
     steps, decisions frozen at the base run (or at `replay`, recorded dt /
     tau / arg per step).  Returns (L, g, base_run)."""
     ps = cfg.ps
     e0, de_dM, de_da = initial_state(ps, cfg.mach, cfg.pert.amp, cfg.pert)
-    run = forward(cfg, steps, u0=e0, mach=cfg.mach, replay=replay)
+    run = forward(cfg, steps, u0=e0, mach=cfg.mach, replay=replay, filt=filt)
     L, ub = outer_density_loss(ps, run.u)
     dM_bc = 0.0
     for k in range(steps - 1, -1, -1):
@@ -159,7 +169,7 @@ def gradient(cfg, steps, replay=None):
     return L, np.concatenate([[gM], ga]), run
 
 
-def loss_at(cfg, steps, mach, amp, replay):
+def loss_at(cfg, steps, mach, amp, replay, filt=None):
     e0, _, _ = initial_state(cfg.ps, mach, amp, cfg.pert)
-    run = forward(cfg, steps, u0=e0, mach=mach, replay=replay, record=False)
+    run = forward(cfg, steps, u0=e0, mach=mach, replay=replay, record=False, filt=filt)
     return outer_density_loss(cfg.ps, run.u)[0]

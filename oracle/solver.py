@@ -95,14 +95,16 @@ class Run:
             mu, tau_used, arg = av.viscosity(e, ps, self.cfg.mlp, g, tau=tau, arg=arg)
         else:
             mu, tau_used, arg = self.viscosity(e)
+        pre = None
         if filt is not None:
+            pre = np.array(e)
             e = spectral_filter.filter_state(e, ps, filt[0], filt[1], g)
             glue(e, ps, self.mach, g)
         if dt is None:
             dt = rk.cfl_dt(e, mu, ps, self.cfg.cfl, g)
         L = lambda u, s: euler.full_rhs(u, ps.metric, mu, ps, g)
         new, stages, rhs = rk.ssprk_step(e, dt, L, glue=lambda u, s: glue(u, ps, self.mach, g))
-        entry = dict(dt=dt, tau=tau_used, arg=arg, mu=mu)
+        entry = dict(dt=dt, tau=tau_used, arg=arg, mu=mu, filt=filt, pre=pre)
         if record:
             entry["stages"] = [np.array(x) for x in stages[:-1]]
         self.log.append(entry)

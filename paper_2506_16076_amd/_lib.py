@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcsdnn.so")
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EHIP", 5: "EUNSUPPORTED", 6: "ENONFINITE"}
-WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ = 0, 1, 2, 3, 4
+WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ, WS_FILTER_ADJ = 0, 1, 2, 3, 4, 5
 LAYOUT_ROWS, LAYOUT_B8X4 = 0, 1
 
 
@@ -66,7 +66,8 @@ class StepArgs(ctypes.Structure):
                 ("tau", ctypes.c_void_p), ("argmax", ctypes.c_void_p), ("dt_dev", ctypes.c_void_p),
                 ("dirichlet_mask", ctypes.c_void_p), ("dirichlet_state", ctypes.c_float * 4),
                 ("ref", ctypes.c_float * 4), ("gamma", ctypes.c_float), ("cfl", ctypes.c_float),
-                ("fixed_dt", ctypes.c_int), ("w", ctypes.c_void_p), ("fixed_tau", ctypes.c_int)]
+                ("fixed_dt", ctypes.c_int), ("w", ctypes.c_void_p), ("fixed_tau", ctypes.c_int),
+                ("filter", ctypes.c_int)]
 
 
 _lib = None
@@ -89,6 +90,9 @@ def lib():
             "fcsd_set_create": [vp, i32, P(PatchDesc), i32, i64, i32, i32, i32, P(vp)],
             "fcsd_set_destroy": [vp],
             "fcsd_set_tune": [vp, P(i32), P(i32), i32],
+            "fcsd_set_filter": [vp, ctypes.c_double, i32],
+            "fcsd_filter": [vp, vp, vp, vp, i64, f32],
+            "fcsd_filter_adj": [vp, vp, vp, vp, vp, i64, f32, vp, sz],
             "fcsd_workspace_size": [vp, i32, P(sz)],
             "fcsd_ext_size": [vp, i32, P(i64)],
             "fc_continue": [vp, vp, i32, i32, vp, i64, vp, i64],
@@ -132,6 +136,7 @@ def lib():
 # the names every header declaration exports (checked by the CPU tests)
 EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_last_error",
            "fcsd_ctx_stream", "fcsd_ctx_sync", "fcsd_set_create", "fcsd_set_destroy", "fcsd_set_tune",
+           "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj",
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
            "rk_stage_adj", "fcsd_cfl_dt", "sdnn_infer", "av_viscosity", "av_viscosity_adj",

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from ._lib import (LAYOUT_B8X4, LAYOUT_ROWS, FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP,
-                   WS_STEP_ADJ, blocked_layout, layout_index, lib, patch_descs)
+                   WS_STEP_ADJ, WS_FILTER_ADJ, blocked_layout, layout_index, lib, patch_descs)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -150,6 +150,12 @@ class PatchSet:
         t = (ctypes.c_int * 3)(*[int(x) for x in threads])
         self.ctx.check(lib().fcsd_set_tune(self.h, b, t, int(order)), "fcsd_set_tune")
         self.tuning = (tuple(int(x) for x in budgets), tuple(int(x) for x in threads), int(order))
+
+    def set_filter(self, alpha: float = 10.0, p: int = 14):
+        """Parameters of the spectral filter (paper Sec. 4.3.1): factors
+        exp(-alpha (2k/L)^p) on the coefficients of every line extension."""
+        self.ctx.check(lib().fcsd_set_filter(self.h, float(alpha), int(p)), "fcsd_set_filter")
+        self.filter_params = (float(alpha), int(p))
 
     def ext_size(self, direction: int) -> int:
         v = ctypes.c_int64()
@@ -303,6 +309,22 @@ def fcsd_glue_adj(s, u_bar, mask=None, dstate=(0, 0, 0, 0), dparam=None):
     _call(s, "fcsd_glue_adj", _p(u_bar), s.plane, _p(mask), _f4(dstate), _p(dparam))
 
 
+def fcsd_filter(s, u, out, gamma=1.4):
+    """Per-step state filter (rho, rho u, rho v, theta; E rebuilt); out may
+    be u."""
+    _chk(u, numel=4 * s.plane), _chk(out, numel=4 * s.plane)
+    _call(s, "fcsd_filter", _p(u), _p(out), s.plane, float(gamma))
+
+
+def fcsd_filter_adj(s, u, out_bar, u_bar, gamma=1.4):
+    """Reverse mode of fcsd_filter at u: u_bar = cotangent of u given the
+    filtered state's cotangent out_bar (u_bar may be out_bar)."""
+    for t in (u, out_bar, u_bar):
+        _chk(t, numel=4 * s.plane)
+    ws = s.workspace(WS_FILTER_ADJ)
+    _call(s, "fcsd_filter_adj", _p(u), _p(out_bar), _p(u_bar), s.plane, float(gamma), _p(ws), ws.numel() * 4)
+
+
 # ------------------------------------------------------------------ fused
 
 def fcsd_stage(s, stage, u0, ui, acc, uout, metric, mu, ref, gamma, dt_dev, per_patch=False):
@@ -325,7 +347,7 @@ class Stepper:
     """Holds the buffers of fcsd_step (state advanced in place)."""
 
     def __init__(self, s: PatchSet, u, metric, ref, gamma=1.4, cfl=0.5, W=None, mu=None,
-                 dirichlet_mask=None, dirichlet_state=(0, 0, 0, 0), fixed_dt=None):
+                 dirichlet_mask=None, dirichlet_state=(0, 0, 0, 0), fixed_dt=None, filt=False):
         dev = u.device
         self.s = s
         self.u, self.metric = u, metric
@@ -344,6 +366,7 @@ class Stepper:
         a.gamma, a.cfl = float(gamma), float(cfl)
         a.fixed_dt = 0
         a.fixed_tau = 0
+        a.filter = 1 if filt else 0   # spectral filter after the viscosity (PatchSet.set_filter first)
         if fixed_dt is not None:
             self.dt.fill_(float(fixed_dt))
             a.fixed_dt = 1

@@ -45,6 +45,7 @@ struct PlanDev {
   int km;        // offset of the multiplier table (float2) for this (N, L)
   int aq;        // offset of A_r Q^T (double) for this C, C*d entries
   int dq;        // offset of the differenced rows (double), (C+1)*2d entries
+  int kf;        // offset of the spectral filter factors (float2) for this L
   int nlines;    // lines along this direction
   int n1, n2;    // patch shape
   int patch;     // patch index
@@ -84,16 +85,19 @@ __device__ __forceinline__ size_t tile_lds_bytes(int L, int ld, int d) {
   return (size_t)L * ld * sizeof(float2) + (size_t)L * 2 * sizeof(float2) + (size_t)2 * d * ld * sizeof(float2);
 }
 
-// Copy the plan's twiddles and multipliers into LDS; the caller syncs.
+// Copy the plan's twiddles and multipliers (table kmg at offset kmo; the
+// derivative multipliers by default) into LDS; the caller syncs.
 __device__ __forceinline__ LineCtx line_setup(float2* lds, const TileDev& T, const PlanDev& P,
-                                              const float2* __restrict__ twg, const float2* __restrict__ kmg) {
+                                              const float2* __restrict__ twg, const float2* __restrict__ kmg,
+                                              int kmo = -1) {
   LineCtx X;
   X.z = lds;
   float2* tw = lds + (size_t)P.L * T.ld;
   float2* km = tw + P.L;
+  if (kmo < 0) kmo = P.km;
   for (int i = threadIdx.x; i < P.L; i += blockDim.x) {
     tw[i] = twg[P.tw + i];
-    km[i] = kmg[P.km + i];
+    km[i] = kmg[kmo + i];
   }
   X.tw = tw;
   X.km = km;
@@ -544,6 +548,13 @@ __device__ __forceinline__ void diff_tail(const LineCtx& X, const PlanDev& P, co
   }
 }
 
+// Zero positions N .. L-1 of every line of the tile (the padding R^T of a
+// transposed restriction).
+__device__ __forceinline__ void zero_tail(const LineCtx& X, const PlanDev& P) {
+  if (!X.active) return;
+  for (int r = X.b0; r < P.C; r += X.BS) X.z[(P.N + r) * X.ld + X.c] = make_float2(0.f, 0.f);
+}
+
 // Delta^T of the zero-padded cotangent in place (transposed operator):
 // (Delta^T x)[n] = x[n-1] - x[n], cyclic, with x = [y; 0].  Positions N.. are
 // written in phase 1 (y[N-1] at N, zeros after), the first N in phase 2 from
@@ -578,12 +589,14 @@ __device__ __forceinline__ void difference_adj(const LineCtx& X, const PlanDev& 
   __syncthreads();
 }
 
-// FFT part of the derivative: forward stages (the last one fused with the
-// multiplier and the first inverse stage), inverse stages.  The caller has
-// written the differenced extension (or, for ADJ, Delta^T of the padded
-// cotangent) and synchronised.
+// Circulant operator F^-1 diag(t) F of every line of the tile, t the table
+// copied to LDS (X.km; its conjugate for ADJ): forward stages (the last one
+// fused with the multiplier and the first inverse stage), inverse stages.
+// The caller has written the input -- the differenced extension for the
+// derivative (for ADJ, Delta^T of the padded cotangent), the extension for
+// the spectral filter -- and synchronised.
 template <bool ADJ>
-__device__ __forceinline__ void fft_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P) {
+__device__ __forceinline__ void fft_apply(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P) {
   // radices are read from the (uniform) plan in global memory: a private
   // array indexed by the stage counter would live in scratch
   const int* rad = Pg->rad;
@@ -617,7 +630,7 @@ __device__ __forceinline__ void line_derivative(const LineCtx& X, const PlanDev*
     difference_ext(X, P, dqp + P.dq, d);
   else
     difference_adj(X, P);
-  fft_derivative<ADJ>(X, Pg, P);
+  fft_apply<ADJ>(X, Pg, P);
   if (ADJ && !P.periodic) {
     fold_tail(X, P, aqp + P.aq, d);
     __syncthreads();

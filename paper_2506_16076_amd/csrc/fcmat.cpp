@@ -258,18 +258,25 @@ extern "C" int fcsd_host_factor(int L, int* rad) {
 // / L) - 1) with w_k = 2 pi k (N-1) / L^2 (the FFT normalisation 1/L and
 // the period beta = L/(N-1) folded in); k = 0 and the Nyquist of even L are
 // zero.
+namespace {
+int64_t position_wavenumber(int p, int L, int nst, const int* rad) {
+  int rem = p, M = L;
+  int64_t k = 0, place = 1;
+  for (int s = 0; s < nst; ++s) {
+    int m = M / rad[s];
+    int q = rem / m;
+    rem -= q * m;
+    k += (int64_t)q * place;
+    place *= rad[s];
+    M = m;
+  }
+  return k;
+}
+}  // namespace
+
 extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic) {
   for (int p = 0; p < L; ++p) {
-    int rem = p, M = L;
-    int64_t k = 0, place = 1;
-    for (int s = 0; s < nst; ++s) {
-      int m = M / rad[s];
-      int q = rem / m;
-      rem -= q * m;
-      k += (int64_t)q * place;
-      place *= rad[s];
-      M = m;
-    }
+    const int64_t k = position_wavenumber(p, L, nst, rad);
     int64_t ks = (k <= L / 2) ? k : k - L;
     if (L % 2 == 0 && k == L / 2) ks = 0;
     // derivative w.r.t. q in [0, 1]: beta = L h, h = 1/(N-1); periodic mode h = 1/N, beta = 1
@@ -288,5 +295,21 @@ extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out
     }
     out[2 * p] = (float)re;
     out[2 * p + 1] = (float)im;
+  }
+}
+
+// Filter factors by position of the same digit-reversed order (paper Sec.
+// 4.3.1, eq. filtering): sigma(2k/L) / L = exp(-alpha (2k/L)^p) / L for the
+// signed wavenumber k of the position (the FFT normalisation 1/L folded in),
+// as (re, 0) pairs.  p is even, so the sign of k (and the side the Nyquist of
+// an even L is counted on) does not matter.
+extern "C" void fcsd_host_fmul(int L, int nst, const int* rad, double alpha, int p, float* out) {
+  for (int pos = 0; pos < L; ++pos) {
+    const int64_t k = position_wavenumber(pos, L, nst, rad);
+    const int64_t ks = (k <= L / 2) ? k : k - L;
+    const qf x = 2 * (qf)ks / L;
+    const qf v = expq(-(qf)alpha * powq(x, p)) / L;
+    out[2 * pos] = (float)v;
+    out[2 * pos + 1] = 0.0f;
   }
 }

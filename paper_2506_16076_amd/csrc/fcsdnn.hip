@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <string>
@@ -22,6 +23,7 @@ extern "C" int fcsd_host_fc_dmatrix(int d, int C, double* out);
 extern "C" void fcsd_host_twiddles(int L, float* out);
 extern "C" int fcsd_host_factor(int L, int* rad);
 extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic);
+extern "C" void fcsd_host_fmul(int L, int nst, const int* rad, double alpha, int p, float* out);
 
 namespace {
 
@@ -78,6 +80,10 @@ struct fcsd_set {
   DirPlan dir[2];
   float2* d_tw = nullptr;
   float2* d_km = nullptr;
+  float2* d_kf = nullptr;                 // spectral filter factors (fcsd_set_filter)
+  int filter_on = 0;
+  double filter_alpha = 0.0;
+  int filter_p = 0;
   double* d_aq = nullptr;
   double* d_dq = nullptr;
   PatchDev* d_patches = nullptr;
@@ -133,6 +139,7 @@ PassArgs base_args(const fcsd_set* s, int dir) {
   a.tiles = s->dir[dir - 1].ts[0].d_tiles;
   a.tw = s->d_tw;
   a.km = s->d_km;
+  a.kf = s->d_kf;
   a.aq = s->d_aq;
   a.dq = s->d_dq;
   a.d = s->d;
@@ -198,6 +205,7 @@ size_t ws_planes(const fcsd_set* s, int op) {
     case FCSD_WS_STEP: return 16 + 12 + 11;
     case FCSD_WS_RHS_ADJ: return 24;
     case FCSD_WS_STEP_ADJ: return kStepAdjPlanes;
+    case FCSD_WS_FILTER_ADJ: return 8;
     default: return 0;
   }
 }
@@ -608,6 +616,7 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   }
   hipFree(s->d_tw);
   hipFree(s->d_km);
+  hipFree(s->d_kf);
   hipFree(s->d_aq);
   hipFree(s->d_dq);
   hipFree(s->d_patches);
@@ -656,8 +665,45 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const
   return FCSD_OK;
 }
 
+extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
+  if (!s) return FCSD_EINVAL;
+  fcsd_ctx* ctx = s->ctx;
+  if (!(alpha >= 0.0) || !std::isfinite(alpha) || p < 2 || p > 64 || p % 2)
+    return fail(ctx, FCSD_EINVAL, "fcsd_set_filter: need alpha >= 0 finite and an even p in [2, 64]");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& g : s->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
+  std::vector<float2> kf;
+  std::map<int, int> kf_of_L;
+  for (int dir = 0; dir < 2; ++dir)
+    for (PlanDev& P : s->dir[dir].plans) {
+      if (!kf_of_L.count(P.L)) {
+        kf_of_L[P.L] = (int)kf.size();
+        std::vector<float> t(2 * P.L);
+        fcsd_host_fmul(P.L, P.nst, P.rad, alpha, p, t.data());
+        for (int n = 0; n < P.L; ++n) kf.push_back(make_float2(t[2 * n], t[2 * n + 1]));
+      }
+      P.kf = kf_of_L[P.L];
+    }
+  (void)hipFree(s->d_kf);
+  s->d_kf = nullptr;
+  s->filter_on = 0;
+  fcsd_status r;
+  if ((r = upload(ctx, &s->d_kf, kf))) return r;
+  for (int dir = 0; dir < 2; ++dir) {
+    DirPlan& D = s->dir[dir];
+    (void)hipFree(D.d_plans);
+    if ((r = upload(ctx, &D.d_plans, D.plans))) return r;
+  }
+  s->filter_on = 1;
+  s->filter_alpha = alpha;
+  s->filter_p = p;
+  return FCSD_OK;
+}
+
 extern "C" fcsd_status fcsd_workspace_size(const fcsd_set* s, int op, size_t* bytes) {
-  if (!s || !bytes || op < 0 || op > FCSD_WS_STEP_ADJ) return FCSD_EINVAL;
+  if (!s || !bytes || op < 0 || op > FCSD_WS_FILTER_ADJ) return FCSD_EINVAL;
   *bytes = ws_bytes_of(s, op);
   return FCSD_OK;
 }
@@ -1119,6 +1165,42 @@ extern "C" fcsd_status fcsd_stage_pass(fcsd_ctx* ctx, const fcsd_set* s, int pas
 
 namespace {
 
+// Spectral filter of the state, q1 lines then q2 lines (in may equal out).
+fcsd_status filter_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* in, float* out, float gamma) {
+  PassArgs a = base_args(s, 1);
+  a.gamma = gamma;
+  a.in = in;
+  a.out = out;
+  fcsd_status st = launch_lines(s, 1, k_filter<1>, a, -1, 2);
+  if (st) return st;
+  PassArgs b = a;
+  b.plans = s->dir[1].d_plans;
+  b.in = out;
+  return launch_lines(s, 2, k_filter<2>, b, -1, 2);
+}
+
+// Reverse mode of filter_impl at state e: out_bar (cotangent of the
+// filtered state) -> u_bar (of e; may alias out_bar).  w: 8 planes (the
+// filtered state, recomputed, and the cotangent between the two passes).
+fcsd_status filter_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* e, const float* out_bar, float* u_bar,
+                            float gamma, float* w) {
+  const long long pl = s->plane;
+  fcsd_status st = filter_impl(ctx, s, e, w, gamma);
+  if (st) return st;
+  PassArgs a = base_args(s, 2);
+  a.gamma = gamma;
+  a.in = out_bar;
+  a.u = w;
+  a.out = w + 4 * pl;
+  if ((st = launch_lines(s, 2, k_filter_adj<2>, a, -1, 2))) return st;
+  PassArgs b = base_args(s, 1);
+  b.gamma = gamma;
+  b.in = w + 4 * pl;
+  b.u = e;
+  b.out = u_bar;
+  return launch_lines(s, 1, k_filter_adj<1>, b, -1, 2);
+}
+
 fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a, void* ws) {
   const long long pl = s->plane;
   float* w = (float*)ws;
@@ -1134,6 +1216,10 @@ fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a,
     if ((st = sdnn_impl(ctx, s, a->u, a->gamma, a->w, a->tau, nullptr, A.phi))) return st;
   if (a->w || a->fixed_tau)
     if ((st = viscosity_impl(ctx, s, a->u, a->tau, a->gamma, a->mu, a->argmax, A))) return st;
+  if (a->filter) {
+    if ((st = filter_impl(ctx, s, a->u, a->u, a->gamma))) return st;
+    if ((st = glue_impl(ctx, s, a->u, a->dirichlet_mask, a->dirichlet_state))) return st;
+  }
   if (!a->fixed_dt)
     if ((st = cfl_dt_impl(ctx, s, a->u, a->mu, a->cfl, a->gamma, a->dt_dev, A.red))) return st;
   const float* ins[5] = {a->u, Ua, Ub, Ua, Ub};
@@ -1157,6 +1243,7 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   if (!a || !a->u || !a->metric || !a->dt_dev || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_step: null argument");
   if ((a->w || a->fixed_tau) && (!a->tau || !a->mu))
     return fail(ctx, FCSD_EINVAL, "fcsd_step: network needs tau and mu buffers");
+  if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step: filter not configured (fcsd_set_filter)");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP)) return fail(ctx, FCSD_EINVAL, "fcsd_step: workspace too small");
   if (!use_graph) return step_body(ctx, s, a, ws);
   if (!ctx->stream) return fail(ctx, FCSD_EINVAL, "fcsd_step: graph capture needs a non-default stream");
@@ -1184,6 +1271,27 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   ms->graphs.push_back(g);
   HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
   return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_filter(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float* out, int64_t plane,
+                                   float gamma) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !out) return fail(ctx, FCSD_EINVAL, "fcsd_filter: null argument");
+  if (!s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_filter: filter not configured (fcsd_set_filter)");
+  return filter_impl(ctx, s, u, out, gamma);
+}
+
+extern "C" fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* out_bar,
+                                       float* u_bar, int64_t plane, float gamma, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !out_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_filter_adj: null argument");
+  if (u_bar == u) return fail(ctx, FCSD_EINVAL, "fcsd_filter_adj: u_bar may not alias u");
+  if (!s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_filter_adj: filter not configured (fcsd_set_filter)");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_FILTER_ADJ))
+    return fail(ctx, FCSD_EINVAL, "fcsd_filter_adj: workspace too small");
+  return filter_adj_impl(ctx, s, u, out_bar, u_bar, gamma, (float*)ws);
 }
 
 // ======================================================================== reverse mode of the RHS
@@ -1259,11 +1367,12 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   if (visc_net && (!a->tau || !a->mu || !a->argmax))
     return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: classes need tau, mu and argmax buffers");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: workspace too small");
+  if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: filter not configured (fcsd_set_filter)");
   const long long pl = s->plane, n4 = 4 * pl;
   float* w = (float*)ws;
   float* STG = w;           // glued stage inputs 0..4
   float* ACC = w + 20 * pl;
-  float* OUT = w + 24 * pl;
+  float* OUT = w + 24 * pl;  // step output; with the filter: the glued state before it (PRE)
   float* YB = w + 28 * pl;  // cotangent of the current stage output
   float* UIB = w + 32 * pl; // cotangent of the current stage input
   float* U0B = w + 36 * pl; // cotangent of the glued step input
@@ -1279,12 +1388,20 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   if ((st = glue_impl(ctx, s, stg(0), a->dirichlet_mask, a->dirichlet_state))) return st;
   if (visc_net)
     if ((st = viscosity_impl(ctx, s, stg(0), a->tau, a->gamma, a->mu, a->argmax, A))) return st;
+  float* PRE = OUT;
+  if (a->filter) {
+    HIPCHK(ctx, hipMemcpyAsync(PRE, stg(0), n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
+    if ((st = filter_impl(ctx, s, stg(0), stg(0), a->gamma))) return st;
+    if ((st = glue_impl(ctx, s, stg(0), a->dirichlet_mask, a->dirichlet_state))) return st;
+  }
   const float* mu = a->mu;
   const int flux = mu ? FLUX_FULL : FLUX_INVISCID;
   for (int k = 0; k < 5; ++k) {
     if (k > 0)
       if ((st = glue_impl(ctx, s, stg(k), a->dirichlet_mask, a->dirichlet_state))) return st;
-    float* out = k < 4 ? stg(k + 1) : OUT;
+    // the step output is not needed in reverse: with the filter it goes to
+    // planes of the right-hand-side workspace that the forward passes leave free
+    float* out = k < 4 ? stg(k + 1) : (a->filter ? RWS + 16 * pl : OUT);
     if ((st = rhs_passes(ctx, s, stg(k), a->metric, mu, a->ref, a->gamma, flux, MODE_RK, nullptr, k, stg(0), ACC, out,
                          a->dt_dev, RWS, -1)))
       return st;
@@ -1314,8 +1431,14 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
       uib = t;
     }
   }
+  const float* vin = stg(0);
+  if (a->filter) {
+    if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;
+    if ((st = filter_adj_impl(ctx, s, PRE, U0B, U0B, a->gamma, RWS))) return st;
+    vin = PRE;
+  }
   if (visc_net)
-    if ((st = av_viscosity_adj(ctx, s, stg(0), a->tau, a->argmax, a->gamma, MUB, U0B, plane, w + 73 * pl,
+    if ((st = av_viscosity_adj(ctx, s, vin, a->tau, a->argmax, a->gamma, MUB, U0B, plane, w + 73 * pl,
                                ws_bytes_of(s, FCSD_WS_AV))))
       return st;
   if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;

@@ -23,6 +23,7 @@ struct PassArgs {
   const TileDev* tiles;
   const float2* tw;
   const float2* km;
+  const float2* kf;           // spectral filter factors (null until configured)
   const double* aq;
   const double* dq;
   int d;
@@ -145,7 +146,7 @@ extern __shared__ float2 lds_z[];
   __syncthreads();                                                           \
   diff_tail(X, P, (a).dq + P.dq, (a).d);                                     \
   __syncthreads();                                                           \
-  fft_derivative<false>(X, Pg, P);
+  fft_apply<false>(X, Pg, P);
 
 // ---------------------------------------------------------------- generic line ops
 
@@ -356,6 +357,144 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
           at(H + (2 * k + 1) * pl, g) = vy - dG[k];
         }
       });
+}
+
+// Spectral filter of the state (paper Sec. 4.3.1, eq. filtering) along
+// DIR: two complex lines per grid line, (rho, rho u) at z[pos][c] and
+// (rho v, theta) at z[pos][nl + c], extended by the continuation (fc_tail),
+// transformed with the filter factors as multipliers.  DIR 1 reads the
+// conserved state and forms theta = p / rho (eqs. perfect_gas, p_T), and
+// writes theta in place of E; DIR 2 reads that and writes the state with E
+// rebuilt from the filtered fields (eq. perfect_gas_T).  A tile reads all of
+// its lines before it writes them, so in may equal out.
+template <int DIR>
+__global__ void FCSD_LINE_BOUNDS k_filter(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T2 = T;
+  T2.nl = 2 * T.nl;
+  const LineCtx X = line_setup(lds_z, T2, P, a.tw, a.kf, P.kf);
+  float2* __restrict__ z = X.z;
+  const int nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  const float g1 = a.gamma - 1.0f;
+  const float* in = a.in + M.base;
+  float* out = a.out + M.base;
+  float2* __restrict__ zb = z + nl;
+  __syncthreads();
+  walk_b<kEpiBatch>(
+      M.w, [&](unsigned g) { return make_float4(at(in, g), at(in + pl, g), at(in + 2 * pl, g), at(in + 3 * pl, g)); },
+      [&](unsigned, unsigned l, float4 v) {
+        float th = v.w;
+        if (DIR == 1) th = g1 * (v.w - 0.5f * (v.y * v.y + v.z * v.z) / v.x) / v.x;
+        at(z, l) = make_float2(v.x, v.y);
+        at(zb, l) = make_float2(v.z, th);
+      });
+  __syncthreads();
+  if (!P.periodic) {
+    fc_tail(X, P, a.aq + P.aq, a.d);
+    __syncthreads();
+  }
+  fft_apply<false>(X, Pg, P);
+  walk(M.w, [&](unsigned g, unsigned l) {
+    const float2 p = at(z, l), q = at(zb, l);
+    at(out, g) = p.x;
+    at(out + pl, g) = p.y;
+    at(out + 2 * pl, g) = q.x;
+    at(out + 3 * pl, g) = DIR == 1 ? q.y : p.x * q.y / g1 + 0.5f * (p.y * p.y + q.x * q.x) / p.x;
+  });
+}
+
+// Reverse mode of k_filter along DIR (transpose E^T S R^T of each line
+// filter, S symmetric: zero-pad, the same factors, fold the tail), two
+// complex lines per grid line as in the forward pass.  DIR 2 runs first:
+// a.in holds the cotangent of the filtered state, a.u the filtered state
+// (for the vector-Jacobian product of the rebuilt E), out the cotangent of
+// (rho, rho u, rho v, theta) after the transposed q2 filter.  DIR 1: a.in
+// holds that, a.u the filter's input state (for the product of theta), out
+// the cotangent of the input state.  in may equal out.
+template <int DIR>
+__global__ void FCSD_LINE_BOUNDS k_filter_adj(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T2 = T;
+  T2.nl = 2 * T.nl;
+  const LineCtx X = line_setup(lds_z, T2, P, a.tw, a.kf, P.kf);
+  float2* __restrict__ z = X.z;
+  const int nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  const float g1 = a.gamma - 1.0f;
+  const float* in = a.in + M.base;
+  const float* st = a.u + M.base;
+  float* out = a.out + M.base;
+  float2* __restrict__ zb = z + nl;
+  __syncthreads();
+  if (DIR == 2) {
+    struct In8 {
+      float b[4], e[4];
+    };
+    walk_b<kEpiBatchH>(
+        M.w,
+        [&](unsigned g) {
+          In8 q;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            q.b[k] = at(in + k * pl, g);
+            q.e[k] = at(st + k * pl, g);
+          }
+          return q;
+        },
+        [&](unsigned, unsigned l, const In8& q) {
+          // E' = rho' theta' / (gamma - 1) + (m'^2 + n'^2) / (2 rho')
+          const float r = q.e[0], m = q.e[1], n = q.e[2];
+          const float ir = 1.0f / r, ke = 0.5f * (m * m + n * n) * ir;
+          const float th = g1 * (q.e[3] - ke) * ir;
+          const float Eb = q.b[3];
+          at(z, l) = make_float2(q.b[0] + Eb * (th / g1 - ke * ir), q.b[1] + Eb * m * ir);
+          at(zb, l) = make_float2(q.b[2] + Eb * n * ir, Eb * r / g1);
+        });
+  } else {
+    walk_b<kEpiBatch>(
+        M.w, [&](unsigned g) { return make_float4(at(in, g), at(in + pl, g), at(in + 2 * pl, g), at(in + 3 * pl, g)); },
+        [&](unsigned, unsigned l, float4 v) {
+          at(z, l) = make_float2(v.x, v.y);
+          at(zb, l) = make_float2(v.z, v.w);
+        });
+  }
+  zero_tail(X, P);
+  __syncthreads();
+  fft_apply<true>(X, Pg, P);
+  if (!P.periodic) {
+    fold_tail(X, P, a.aq + P.aq, a.d);
+    __syncthreads();
+  }
+  if (DIR == 2) {
+    walk(M.w, [&](unsigned g, unsigned l) {
+      const float2 p = at(z, l), q = at(zb, l);
+      at(out, g) = p.x;
+      at(out + pl, g) = p.y;
+      at(out + 2 * pl, g) = q.x;
+      at(out + 3 * pl, g) = q.y;
+    });
+  } else {
+    // theta = (gamma - 1) (E / rho - (m^2 + n^2) / (2 rho^2))
+    walk_b<kEpiBatch>(
+        M.w, [&](unsigned g) { return make_float4(at(st, g), at(st + pl, g), at(st + 2 * pl, g), at(st + 3 * pl, g)); },
+        [&](unsigned g, unsigned l, float4 e) {
+          const float2 p = at(z, l), q = at(zb, l);
+          const float ir = 1.0f / e.x, ir2 = ir * ir, tb = q.y * g1;
+          at(out, g) = p.x + tb * (-e.w * ir2 + (e.y * e.y + e.z * e.z) * ir2 * ir);
+          at(out + pl, g) = p.y - tb * e.y * ir2;
+          at(out + 2 * pl, g) = q.x - tb * e.z * ir2;
+          at(out + 3 * pl, g) = tb * ir;
+        });
+  }
 }
 
 // Inviscid H = -f' (pointwise, no derivative needed).
