@@ -180,21 +180,53 @@ struct MlpPtr {
 // -- exactly the B operand the next product needs when its K step k = 0..3
 // is read as unit 16 t + 4 k + v: activations never leave the registers.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-constexpr int kW2S = 68;  // padded LDS row stride of W2 (floats)
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
+// The network's products run on the fp16 matrix cores with FP32 accuracy:
+// every operand v is split as v = hi + lo, hi = fp16(v) (round to nearest),
+// lo = v - hi (exact in FP32, |lo| <= 2^-11 |v|), and a product sum is
+//     sum hi_a hi_b  +  2^-11 sum (lo_a 2^11 hi_b + hi_a lo_b 2^11)
+// with the low parts scaled by 2^11 so that they stay normal fp16 numbers;
+// the dropped lo lo term is below 2^-22 of each product.  The main and the
+// correction sums accumulate in FP32 in two accumulators.
+constexpr float kLoScale = 2048.0f;
+constexpr float kLoUnscale = 1.0f / 2048.0f;
+
+// Weights in LDS in the operand layout of the 16x16x32 fp16 product: for
+// lane group g (lanes 16 g .. 16 g + 15) the contraction slots are 4 units
+// k = 16 c + 4 g + e (e = 0..3) of a 16-unit chunk c, and a half8 holds
+// {lo * 2^11 (e = 0..3), hi (e = 0..3)} of row n = lane % 16.  A layer's
+// output tile t (rows 16 t + 4 g + v in lane group g, D layout) then is, as
+// it stands in the registers, chunk t of the next layer's contraction.
 struct MlpLds {
-  float W1[16 * 64];
+  half8 W1[4][4][16];     // [output chunk t][g][n]: W1[4 e + g][16 t + n] (layer 1 slots: feature 4 e + g)
+  half8 W2[4][4][4][16];  // [output chunk mt][input chunk c][g][n]: W2[16 c + 4 g + e][16 mt + n]
+  half8 W3[4][4][16];     // [input chunk c][g][n]: W3[16 c + 4 g + e][n] (n < 4), zero rows n >= 4
   float b1[64];
-  float W2[64 * kW2S];
   float b2[64];
-  float W3[64 * 4];
   float b3[4];
 };
 
+__device__ __forceinline__ void split_store(_Float16* hl, int e, float w) {
+  const _Float16 h = (_Float16)w;
+  hl[e] = (_Float16)((w - (float)h) * kLoScale);
+  hl[4 + e] = h;
+}
+
 __device__ __forceinline__ void mlp_load(MlpLds& L, const MlpPtr& w) {
-  for (int k = threadIdx.x; k < 16 * 64; k += blockDim.x) L.W1[k] = w.W1[k];
-  for (int k = threadIdx.x; k < 64 * 64; k += blockDim.x) L.W2[(k >> 6) * kW2S + (k & 63)] = w.W2[k];
-  for (int k = threadIdx.x; k < 64 * 4; k += blockDim.x) L.W3[k] = w.W3[k];
+  for (int q = threadIdx.x; q < 4 * 4 * 16 * 4; q += blockDim.x) {
+    const int e = q & 3, n = (q >> 2) & 15, g = (q >> 6) & 3, t = q >> 8;
+    split_store((_Float16*)&L.W1[t][g][n], e, w.W1[(4 * e + g) * 64 + 16 * t + n]);
+  }
+  for (int q = threadIdx.x; q < 4 * 4 * 4 * 16 * 4; q += blockDim.x) {
+    const int e = q & 3, n = (q >> 2) & 15, g = (q >> 6) & 3, c = (q >> 8) & 3, mt = q >> 10;
+    split_store((_Float16*)&L.W2[mt][c][g][n], e, w.W2[(16 * c + 4 * g + e) * 64 + 16 * mt + n]);
+  }
+  for (int q = threadIdx.x; q < 4 * 4 * 16 * 4; q += blockDim.x) {
+    const int e = q & 3, n = (q >> 2) & 15, g = (q >> 6) & 3, c = q >> 8;
+    split_store((_Float16*)&L.W3[c][g][n], e, n < 4 ? w.W3[(16 * c + 4 * g + e) * 4 + n] : 0.f);
+  }
   for (int k = threadIdx.x; k < 64; k += blockDim.x) {
     L.b1[k] = w.b1[k];
     L.b2[k] = w.b2[k];
@@ -202,41 +234,71 @@ __device__ __forceinline__ void mlp_load(MlpLds& L, const MlpPtr& w) {
   if (threadIdx.x < 4) L.b3[threadIdx.x] = w.b3[threadIdx.x];
 }
 
+__device__ __forceinline__ half4 hi4(const half8 a) { return half4{a[4], a[5], a[6], a[7]}; }
+__device__ __forceinline__ half8 cat(const half4 a, const half4 b) {
+  return half8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+}
+// hi and scaled lo of four FP32 values
+__device__ __forceinline__ void split4(const floatx4 v, half4& h, half4& l) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = (_Float16)v[e];
+    l[e] = (_Float16)((v[e] - (float)h[e]) * kLoScale);
+  }
+}
+
 // Logits of 16 windows; lane 16 g + r supplies features 4 s + g (s = 0..3)
 // of window r in x[s]; lanes 0..15 receive the four logits of window r.
+// Each product is computed transposed (windows along the columns), so the
+// D layout of one layer's output is the B layout of the next.
 __device__ __forceinline__ floatx4 mlp16(const MlpLds& L, const float x[4], int g, int r) {
-  floatx4 h1[4], h2[4];
+  half4 xh, xl;
+  split4(floatx4{x[0], x[1], x[2], x[3]}, xh, xl);
+  const half8 xb = cat(xh, xl);
+  half4 ah[4], al[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    h1[t] = floatx4{L.b1[16 * t + 4 * g], L.b1[16 * t + 4 * g + 1], L.b1[16 * t + 4 * g + 2],
-                    L.b1[16 * t + 4 * g + 3]};
+    floatx4 m = floatx4{L.b1[16 * t + 4 * g], L.b1[16 * t + 4 * g + 1], L.b1[16 * t + 4 * g + 2],
+                        L.b1[16 * t + 4 * g + 3]};
+    floatx4 c = floatx4{0.f, 0.f, 0.f, 0.f};
+    const half8 a = L.W1[t][g][r];
+    m = __builtin_amdgcn_mfma_f32_16x16x16f16(hi4(a), xh, m, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, xb, c, 0, 0, 0);
+    floatx4 h;
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-      h1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.W1[(4 * s + g) * 64 + 16 * t + r], x[s], h1[t], 0, 0, 0);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) h1[t][v] = fmaxf(h1[t][v], 0.f);
+    for (int v = 0; v < 4; ++v) h[v] = fmaxf(m[v] + c[v] * kLoUnscale, 0.f);
+    split4(h, ah[t], al[t]);
   }
+  half4 bh[4], bl[4];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
-    h2[mt] = floatx4{L.b2[16 * mt + 4 * g], L.b2[16 * mt + 4 * g + 1], L.b2[16 * mt + 4 * g + 2],
-                     L.b2[16 * mt + 4 * g + 3]};
+    floatx4 m = floatx4{L.b2[16 * mt + 4 * g], L.b2[16 * mt + 4 * g + 1], L.b2[16 * mt + 4 * g + 2],
+                        L.b2[16 * mt + 4 * g + 3]};
+    floatx4 c = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int p = 0; p < 2; ++p)
+      m = __builtin_amdgcn_mfma_f32_16x16x32_f16(cat(hi4(L.W2[mt][2 * p][g][r]), hi4(L.W2[mt][2 * p + 1][g][r])),
+                                                 cat(ah[2 * p], ah[2 * p + 1]), m, 0, 0, 0);
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        h2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.W2[(16 * t + 4 * g + v) * kW2S + 16 * mt + r], h1[t][v],
-                                                      h2[mt], 0, 0, 0);
+    for (int k = 0; k < 4; ++k)
+      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2[mt][k][g][r], cat(ah[k], al[k]), c, 0, 0, 0);
+    floatx4 h;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) h2[mt][v] = fmaxf(h2[mt][v], 0.f);
+    for (int v = 0; v < 4; ++v) h[v] = fmaxf(m[v] + c[v] * kLoUnscale, 0.f);
+    split4(h, bh[mt], bl[mt]);
   }
-  floatx4 o = g == 0 ? floatx4{L.b3[0], L.b3[1], L.b3[2], L.b3[3]} : floatx4{0.f, 0.f, 0.f, 0.f};
+  floatx4 m = g == 0 ? floatx4{L.b3[0], L.b3[1], L.b3[2], L.b3[3]} : floatx4{0.f, 0.f, 0.f, 0.f};
+  floatx4 c = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int p = 0; p < 2; ++p)
+    m = __builtin_amdgcn_mfma_f32_16x16x32_f16(cat(hi4(L.W3[2 * p][g][r]), hi4(L.W3[2 * p + 1][g][r])),
+                                               cat(bh[2 * p], bh[2 * p + 1]), m, 0, 0, 0);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float a = r < 4 ? L.W3[(16 * mt + 4 * g + v) * 4 + r] : 0.f;
-      o = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h2[mt][v], o, 0, 0, 0);
-    }
+  for (int k = 0; k < 4; ++k)
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3[k][g][r], cat(bh[k], bl[k]), c, 0, 0, 0);
+  floatx4 o;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) o[v] = m[v] + c[v] * kLoUnscale;
   return o;
 }
 
