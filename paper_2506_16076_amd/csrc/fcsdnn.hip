@@ -158,6 +158,7 @@ void set_ref(PassArgs& a, const float ref[4], float gamma) {
 }
 
 unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+unsigned chunk_grid(int nchunks) { return (unsigned)std::max(1, std::min(nchunks, kChunkGrid)); }
 
 // launch a line-engine kernel over the batched tile list or one patch's tiles
 template <class K>
@@ -912,7 +913,7 @@ fcsd_status cfl_dt_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const 
   unsigned* mmax = red + np;
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(2 * np)), dim3(kBlock), 0, ctx->stream, (float*)red, 0.f,
                      (long long)(2 * np));
-  hipLaunchKernelGGL(k_dt_reduce, dim3(s->nchunks), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->d_patches, u, mu,
+  hipLaunchKernelGGL(k_dt_reduce, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->nchunks, s->d_patches, u, mu,
                      (long long)s->plane, gamma, smax, mmax);
   hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(kBlock), 0, ctx->stream, s->d_patches, np, smax, mmax, cfl, dt_dev);
   return launch_check(ctx, "cfl_dt");
@@ -960,7 +961,7 @@ AvWs carve_av(const fcsd_set* s, void* ws) {
 
 fcsd_status sdnn_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float gamma, const fcsd_mlp* w,
                       int8_t* tau, float* logits, float* phi) {
-  hipLaunchKernelGGL(k_proxy, dim3(s->nchunks), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->d_patches, u,
+  hipLaunchKernelGGL(k_proxy, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->nchunks, s->d_patches, u,
                      (long long)s->plane, gamma, phi, (float*)nullptr);
   MlpPtr m{w->W1, w->b1, w->W2, w->b2, w->W3, w->b3};
   // blocks stride over the chunks so each loads the weights into LDS once
@@ -973,14 +974,14 @@ fcsd_status sdnn_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float ga
 // forward Lambda denominators (den = conv of the D~ indicator) into A.t1
 fcsd_status lambda_forward(fcsd_ctx* ctx, const fcsd_set* s, const AvWs& A, const float* muh, float* mu) {
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_lat_gather, dim3(s->nlchunks), dim3(kBlock), 0, st, s->d_lchunks, s->d_lats, s->d_patches,
+  hipLaunchKernelGGL(k_lat_gather, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, st, s->d_lchunks, s->nlchunks, s->d_lats, s->d_patches,
                      s->an, muh, A.num, A.den, s->annulus, 0);
-  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, st, s->d_lchunks, s->d_lats,
+  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, st, s->d_lchunks, s->nlchunks, s->d_lats,
                      (const float*)A.num, (const float*)A.den, A.t0, A.t1, 0);
-  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, st, s->d_lchunks, s->d_lats,
+  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, st, s->d_lchunks, s->nlchunks, s->d_lats,
                      (const float*)A.t0, (const float*)A.t1, A.num, A.den, 1);
   if (mu)
-    hipLaunchKernelGGL(k_lat_scatter, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches, s->an,
+    hipLaunchKernelGGL(k_lat_scatter, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, st, s->d_chunks, s->nchunks, s->d_patches, s->an,
                        s->annulus, (const float*)A.num, (const float*)A.den, mu);
   return launch_check(ctx, "lambda");
 }
@@ -988,11 +989,11 @@ fcsd_status lambda_forward(fcsd_ctx* ctx, const fcsd_set* s, const AvWs& A, cons
 fcsd_status viscosity_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const int8_t* tau, float gamma,
                            float* mu, int32_t* argmax, const AvWs& A) {
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_proxy, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches, u,
+  hipLaunchKernelGGL(k_proxy, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, st, s->d_chunks, s->nchunks, s->d_patches, u,
                      (long long)s->plane, gamma, (float*)nullptr, A.S);
-  hipLaunchKernelGGL(k_rowmax, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches, (const float*)A.S,
+  hipLaunchKernelGGL(k_rowmax, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, st, s->d_chunks, s->nchunks, s->d_patches, (const float*)A.S,
                      A.rmax, A.rarg);
-  hipLaunchKernelGGL(k_muhat, dim3(s->nchunks), dim3(kBlock), 0, st, s->d_chunks, s->d_patches,
+  hipLaunchKernelGGL(k_muhat, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, st, s->d_chunks, s->nchunks, s->d_patches,
                      (const float*)A.rmax, (const int*)A.rarg, (const signed char*)tau, A.muh, (int*)argmax);
   fcsd_status r = launch_check(ctx, "mu hat");
   if (r) return r;
@@ -1033,17 +1034,17 @@ extern "C" fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* s, const 
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(s->plane)), dim3(kBlock), 0, sm, A.muh, 0.f, (long long)s->plane);
   if ((st = lambda_forward(ctx, s, A, A.muh, nullptr))) return st;
   // t = mu_bar / den at every point, gathered into the lattice, window sum
-  hipLaunchKernelGGL(k_lat_divide_pts, dim3(s->nchunks), dim3(kBlock), 0, sm, s->d_chunks, s->d_patches, s->an,
+  hipLaunchKernelGGL(k_lat_divide_pts, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, sm, s->d_chunks, s->nchunks, s->d_patches, s->an,
                      s->annulus, mu_bar, (const float*)A.den, A.tp);
-  hipLaunchKernelGGL(k_lat_gather, dim3(s->nlchunks), dim3(kBlock), 0, sm, s->d_lchunks, s->d_lats, s->d_patches,
+  hipLaunchKernelGGL(k_lat_gather, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats, s->d_patches,
                      s->an, (const float*)A.tp, A.t0, (float*)nullptr, s->annulus, 1);
-  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, sm, s->d_lchunks, s->d_lats,
+  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats,
                      (const float*)A.t0, (const float*)nullptr, A.t1, (float*)nullptr, 0);
-  hipLaunchKernelGGL(k_lat_conv, dim3(s->nlchunks), dim3(kBlock), 0, sm, s->d_lchunks, s->d_lats,
+  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats,
                      (const float*)A.t1, (const float*)nullptr, A.t0, (float*)nullptr, 1);
-  hipLaunchKernelGGL(k_route_S, dim3(s->nchunks), dim3(kBlock), 0, sm, s->d_chunks, s->d_patches, s->an, s->annulus,
+  hipLaunchKernelGGL(k_route_S, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, sm, s->d_chunks, s->nchunks, s->d_patches, s->an, s->annulus,
                      (const float*)A.t0, (const signed char*)tau, argmax, A.S);
-  hipLaunchKernelGGL(k_speed_vjp, dim3(s->nchunks), dim3(kBlock), 0, sm, s->d_chunks, s->d_patches, u,
+  hipLaunchKernelGGL(k_speed_vjp, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, sm, s->d_chunks, s->nchunks, s->d_patches, u,
                      (long long)s->plane, gamma, (const float*)A.S, u_bar);
   return launch_check(ctx, "av_viscosity_adj");
 }

@@ -50,6 +50,14 @@ struct ChunkDev {
   int start;  // first storage index within the patch (lattice: row-major)
 };
 
+// Chunk kernels run a grid of at most kChunkGrid blocks that stride over the
+// chunks (a block per 256-point chunk spends its time being scheduled).
+constexpr int kChunkGrid = 2048;
+template <class F>
+__device__ __forceinline__ void for_chunks(const ChunkDev* chunks, int nchunks, F&& f) {
+  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) f(chunks[cb]);
+}
+
 // lattice of the smoothing-blending operator: independent patches are their
 // own lattice; the index-aligned annulus is one periodic (G, J) lattice
 struct LatDev {
@@ -147,23 +155,24 @@ __device__ __forceinline__ void prim(const float* u, long long pl, long long g, 
 }
 
 // Phi = |u| sqrt(rho/(gamma p)) and S = |u| + |v| + a on every patch point
-__global__ void __launch_bounds__(kBlock) k_proxy(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_proxy(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                   const float* u, long long pl, float gam, float* phi,
                                                   float* S) {
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  int i, j;
-  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-  const long long g = P.off + k;
-  {
-#pragma clang fp contract(off)
-    float rho, vx, vy, p;
-    prim(u, pl, g, gam, rho, vx, vy, p);
-    const float a = sqrtf((gam * p) / rho);
-    if (phi) phi[g] = sqrtf(vx * vx + vy * vy) / a;
-    if (S) S[g] = (fabsf(vx) + fabsf(vy)) + a;
-  }
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long g = P.off + k;
+    {
+  #pragma clang fp contract(off)
+      float rho, vx, vy, p;
+      prim(u, pl, g, gam, rho, vx, vy, p);
+      const float a = sqrtf((gam * p) / rho);
+      if (phi) phi[g] = sqrtf(vx * vx + vy * vy) / a;
+      if (S) S[g] = (fabsf(vx) + fabsf(vy)) + a;
+    }
+  });
 }
 
 // ---------------------------------------------------------------- network
@@ -394,55 +403,57 @@ __global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* chunks, int nch
 // ---------------------------------------------------------------- 7x7 max
 
 // max over i-3..i+3 (clamped) with the first maximiser
-__global__ void __launch_bounds__(kBlock) k_rowmax(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_rowmax(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                    const float* S, float* rmax, int* rarg) {
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  int i, j;
-  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-  const int lo = i - 3 < 0 ? 0 : i - 3, hi = i + 3 > P.n1 - 1 ? P.n1 - 1 : i + 3;
-  float best = S[pidx(P, lo, j)];
-  int bi = lo;
-  for (int t = lo + 1; t <= hi; ++t) {
-    const float v = S[pidx(P, t, j)];
-    if (v > best) {
-      best = v;
-      bi = t;
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const int lo = i - 3 < 0 ? 0 : i - 3, hi = i + 3 > P.n1 - 1 ? P.n1 - 1 : i + 3;
+    float best = S[pidx(P, lo, j)];
+    int bi = lo;
+    for (int t = lo + 1; t <= hi; ++t) {
+      const float v = S[pidx(P, t, j)];
+      if (v > best) {
+        best = v;
+        bi = t;
+      }
     }
-  }
-  rmax[P.off + k] = best;
-  rarg[P.off + k] = bi;
+    rmax[P.off + k] = best;
+    rarg[P.off + k] = bi;
+  });
 }
 
 // column pass of the 7x7 max and mu^ = R(tau) max S h^ on D~ (0 elsewhere)
-__global__ void __launch_bounds__(kBlock) k_muhat(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_muhat(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                   const float* rmax, const int* rarg,
                                                   const signed char* tau, float* muh, int* argmax) {
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  int i, j;
-  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-  const int lo = j - 3 < 0 ? 0 : j - 3, hi = j + 3 > P.n2 - 1 ? P.n2 - 1 : j + 3;
-  float best = rmax[pidx(P, i, lo)];
-  int bj = lo;
-  for (int t = lo + 1; t <= hi; ++t) {
-    const float v = rmax[pidx(P, i, t)];
-    if (v > best) {
-      best = v;
-      bj = t;
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const int lo = j - 3 < 0 ? 0 : j - 3, hi = j + 3 > P.n2 - 1 ? P.n2 - 1 : j + 3;
+    float best = rmax[pidx(P, i, lo)];
+    int bj = lo;
+    for (int t = lo + 1; t <= hi; ++t) {
+      const float v = rmax[pidx(P, i, t)];
+      if (v > best) {
+        best = v;
+        bj = t;
+      }
     }
-  }
-  const long long g = P.off + k;
-  if (argmax) argmax[g] = bj * P.n1 + rarg[pidx(P, i, bj)];
-  float m = 0.f;
-  if (in_dtilde(P, i, j)) {
-    const int t = tau[g];
-    const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
-    m = R * best * P.hhat;
-  }
-  muh[g] = m;
+    const long long g = P.off + k;
+    if (argmax) argmax[g] = bj * P.n1 + rarg[pidx(P, i, bj)];
+    float m = 0.f;
+    if (in_dtilde(P, i, j)) {
+      const int t = tau[g];
+      const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
+      m = R * best * P.hhat;
+    }
+    muh[g] = m;
+  });
 }
 
 // ---------------------------------------------------------------- Lambda
@@ -465,77 +476,79 @@ __device__ __forceinline__ float win(int k) {
 // gather mu^ and the D~ indicator into the lattice.  Independent patches:
 // the lattice is the patch itself.  Annulus: cell (G, J) collects every
 // patch point with that global index (<= 2 sectors x 2 shells).
-__global__ void __launch_bounds__(kBlock) k_lat_gather(const ChunkDev* lchunks, const LatDev* lats,
+__global__ void __launch_bounds__(kBlock) k_lat_gather(const ChunkDev* lchunks, int nchunks, const LatDev* lats,
                                                        const PatchDev* patches, AnnulusDev an,
                                                        const float* muh, float* num, float* den,
                                                        int annulus, int transpose_src) {
-  const ChunkDev ck = lchunks[blockIdx.x];
-  const LatDev Lt = lats[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  if (k >= Lt.W * Lt.H) return;
-  const long long cell = Lt.base + k;
-  if (!annulus) {
-    const PatchDev P = patches[ck.patch];
-    const int j = k / P.n1, i = k - j * P.n1;
-    const bool in = transpose_src ? true : in_dtilde(P, i, j);
-    num[cell] = in ? muh[pidx(P, i, j)] : 0.f;
-    if (den) den[cell] = in ? 1.f : 0.f;
-    return;
-  }
-  const int J = k / Lt.W, G = k - J * Lt.W;
-  float sn = 0.f, sd = 0.f;
-  int k0 = J / an.st2;
-  if (k0 > an.nshell - 1) k0 = an.nshell - 1;
-  for (int kk = k0 - 1; kk <= k0; ++kk) {
-    if (kk < 0) continue;
-    const int jj = J - kk * an.st2;
-    if (jj < 0 || jj >= an.n2) continue;
-    const int s0 = G / an.st1;
-    for (int ss = s0 - 1; ss <= s0; ++ss) {
-      const int s = (ss + an.nsec) % an.nsec;
-      int ii = G - ss * an.st1;
-      if (ii < 0 || ii >= an.n1) continue;
-      const int p = kk * an.nsec + s;
-      const PatchDev P = patches[p];
-      if (!transpose_src && !in_dtilde(P, ii, jj)) continue;
-      sn += muh[pidx(P, ii, jj)];
-      sd += 1.f;
+  for_chunks(lchunks, nchunks, [&](const ChunkDev ck) {
+    const LatDev Lt = lats[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    if (k >= Lt.W * Lt.H) return;
+    const long long cell = Lt.base + k;
+    if (!annulus) {
+      const PatchDev P = patches[ck.patch];
+      const int j = k / P.n1, i = k - j * P.n1;
+      const bool in = transpose_src ? true : in_dtilde(P, i, j);
+      num[cell] = in ? muh[pidx(P, i, j)] : 0.f;
+      if (den) den[cell] = in ? 1.f : 0.f;
+      return;
     }
-  }
-  num[cell] = sn;
-  if (den) den[cell] = sd;
+    const int J = k / Lt.W, G = k - J * Lt.W;
+    float sn = 0.f, sd = 0.f;
+    int k0 = J / an.st2;
+    if (k0 > an.nshell - 1) k0 = an.nshell - 1;
+    for (int kk = k0 - 1; kk <= k0; ++kk) {
+      if (kk < 0) continue;
+      const int jj = J - kk * an.st2;
+      if (jj < 0 || jj >= an.n2) continue;
+      const int s0 = G / an.st1;
+      for (int ss = s0 - 1; ss <= s0; ++ss) {
+        const int s = (ss + an.nsec) % an.nsec;
+        int ii = G - ss * an.st1;
+        if (ii < 0 || ii >= an.n1) continue;
+        const int p = kk * an.nsec + s;
+        const PatchDev P = patches[p];
+        if (!transpose_src && !in_dtilde(P, ii, jj)) continue;
+        sn += muh[pidx(P, ii, jj)];
+        sd += 1.f;
+      }
+    }
+    num[cell] = sn;
+    if (den) den[cell] = sd;
+  });
 }
 
 // separable 17-tap window sum along G (dir 0, periodic or zero padded) or J
-__global__ void __launch_bounds__(kBlock) k_lat_conv(const ChunkDev* lchunks, const LatDev* lats,
+__global__ void __launch_bounds__(kBlock) k_lat_conv(const ChunkDev* lchunks, int nchunks, const LatDev* lats,
                                                      const float* in0, const float* in1, float* out0,
                                                      float* out1, int dir) {
-  const ChunkDev ck = lchunks[blockIdx.x];
-  const LatDev Lt = lats[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  if (k >= Lt.W * Lt.H) return;
-  const int J = k / Lt.W, G = k - J * Lt.W;
-  float s0 = 0.f, s1 = 0.f;
-  for (int l = -8; l <= 8; ++l) {
-    int gg = G, jj = J;
-    if (dir == 0) {
-      gg = G + l;
-      if (Lt.periodic) {
-        gg = (gg % Lt.W + Lt.W) % Lt.W;
-      } else if (gg < 0 || gg >= Lt.W) {
-        continue;
+  for_chunks(lchunks, nchunks, [&](const ChunkDev ck) {
+    const LatDev Lt = lats[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    if (k >= Lt.W * Lt.H) return;
+    const int J = k / Lt.W, G = k - J * Lt.W;
+    float s0 = 0.f, s1 = 0.f;
+    for (int l = -8; l <= 8; ++l) {
+      int gg = G, jj = J;
+      if (dir == 0) {
+        gg = G + l;
+        if (Lt.periodic) {
+          gg = (gg % Lt.W + Lt.W) % Lt.W;
+        } else if (gg < 0 || gg >= Lt.W) {
+          continue;
+        }
+      } else {
+        jj = J + l;
+        if (jj < 0 || jj >= Lt.H) continue;
       }
-    } else {
-      jj = J + l;
-      if (jj < 0 || jj >= Lt.H) continue;
+      const long long c = Lt.base + (long long)jj * Lt.W + gg;
+      const float w = win(l);
+      s0 = fmaf(w, in0[c], s0);
+      if (in1) s1 = fmaf(w, in1[c], s1);
     }
-    const long long c = Lt.base + (long long)jj * Lt.W + gg;
-    const float w = win(l);
-    s0 = fmaf(w, in0[c], s0);
-    if (in1) s1 = fmaf(w, in1[c], s1);
-  }
-  out0[Lt.base + k] = s0;
-  if (out1) out1[Lt.base + k] = s1;
+    out0[Lt.base + k] = s0;
+    if (out1) out1[Lt.base + k] = s1;
+  });
 }
 
 __device__ __forceinline__ long long lat_cell(const PatchDev& P, int p, int i, int j, int annulus,
@@ -549,86 +562,90 @@ __device__ __forceinline__ long long lat_cell(const PatchDev& P, int p, int i, i
 
 // mu = num / den at every patch point (mode 0), or the transpose
 // gather-scatter of Lambda^T: out = mu_bar / den at every point (mode 1)
-__global__ void __launch_bounds__(kBlock) k_lat_scatter(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_lat_scatter(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                         AnnulusDev an, int annulus, const float* num,
                                                         const float* den, float* mu) {
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  int i, j;
-  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-  const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
-  mu[P.off + k] = num[c] / den[c];
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
+    mu[P.off + k] = num[c] / den[c];
+  });
 }
 
 // Lambda^T first step: t = mu_bar / den (per patch point, into a plane)
-__global__ void __launch_bounds__(kBlock) k_lat_divide_pts(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_lat_divide_pts(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                            AnnulusDev an, int annulus, const float* mub,
                                                            const float* den, float* t) {
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  int i, j;
-  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-  const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
-  t[P.off + k] = mub[P.off + k] / den[c];
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
+    t[P.off + k] = mub[P.off + k] / den[c];
+  });
 }
 
 // Lambda^T last step + mu^ -> S routing: sbar(x) = sum over points y in
 // the 7x7 neighbourhood of x whose maximiser is x of R(tau_y) h^ mu^bar(y),
 // with mu^bar(y) = conv(acc)(cell of y) on D~.
-__global__ void __launch_bounds__(kBlock) k_route_S(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_route_S(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                     AnnulusDev an, int annulus, const float* accconv,
                                                     const signed char* tau, const int* argmax,
                                                     float* sbar) {
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  int i, j;
-  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-  const int kr = j * P.n1 + i;  // patch-local row-major index, as argmax stores it
-  float s = 0.f;
-  for (int dj = -3; dj <= 3; ++dj) {
-    const int yj = j + dj;
-    if (yj < 0 || yj >= P.n2) continue;
-    for (int di = -3; di <= 3; ++di) {
-      const int yi = i + di;
-      if (yi < 0 || yi >= P.n1) continue;
-      const long long gy = pidx(P, yi, yj);
-      if (argmax[gy] != kr || !in_dtilde(P, yi, yj)) continue;
-      const int t = tau[gy];
-      const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
-      s += R * P.hhat * accconv[lat_cell(P, ck.patch, yi, yj, annulus, an)];
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const int kr = j * P.n1 + i;  // patch-local row-major index, as argmax stores it
+    float s = 0.f;
+    for (int dj = -3; dj <= 3; ++dj) {
+      const int yj = j + dj;
+      if (yj < 0 || yj >= P.n2) continue;
+      for (int di = -3; di <= 3; ++di) {
+        const int yi = i + di;
+        if (yi < 0 || yi >= P.n1) continue;
+        const long long gy = pidx(P, yi, yj);
+        if (argmax[gy] != kr || !in_dtilde(P, yi, yj)) continue;
+        const int t = tau[gy];
+        const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
+        s += R * P.hhat * accconv[lat_cell(P, ck.patch, yi, yj, annulus, an)];
+      }
     }
-  }
-  sbar[P.off + k] = s;
+    sbar[P.off + k] = s;
+  });
 }
 
 // u_bar += (dS/du)^T sbar, S = |u| + |v| + sqrt(gamma p / rho)
-__global__ void __launch_bounds__(kBlock) k_speed_vjp(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_speed_vjp(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                       const float* u, long long pl, float gam,
                                                       const float* sbar, float* ub) {
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  int i, j;
-  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-  const long long g = P.off + k;
-  const float sb = sbar[g];
-  if (sb == 0.f) return;
-  float rho, vx, vy, p;
-  prim(u, pl, g, gam, rho, vx, vy, p);
-  const float ir = 1.0f / rho;
-  const float a = sqrtf(gam * p / rho);
-  const float su = vx > 0.f ? 1.f : (vx < 0.f ? -1.f : 0.f);
-  const float sv = vy > 0.f ? 1.f : (vy < 0.f ? -1.f : 0.f);
-  // da/dp = gamma/(2 a rho), da/drho|_p = -a/(2 rho)
-  const float ap = gam / (2.f * a * rho) * sb;
-  const float g1 = gam - 1.f;
-  ub[g] += sb * (-(su * vx + sv * vy) * ir - a * 0.5f * ir) + ap * g1 * 0.5f * (vx * vx + vy * vy);
-  ub[pl + g] += sb * su * ir - ap * g1 * vx;
-  ub[2 * pl + g] += sb * sv * ir - ap * g1 * vy;
-  ub[3 * pl + g] += ap * g1;
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long g = P.off + k;
+    const float sb = sbar[g];
+    if (sb == 0.f) return;
+    float rho, vx, vy, p;
+    prim(u, pl, g, gam, rho, vx, vy, p);
+    const float ir = 1.0f / rho;
+    const float a = sqrtf(gam * p / rho);
+    const float su = vx > 0.f ? 1.f : (vx < 0.f ? -1.f : 0.f);
+    const float sv = vy > 0.f ? 1.f : (vy < 0.f ? -1.f : 0.f);
+    // da/dp = gamma/(2 a rho), da/drho|_p = -a/(2 rho)
+    const float ap = gam / (2.f * a * rho) * sb;
+    const float g1 = gam - 1.f;
+    ub[g] += sb * (-(su * vx + sv * vy) * ir - a * 0.5f * ir) + ap * g1 * 0.5f * (vx * vx + vy * vy);
+    ub[pl + g] += sb * su * ir - ap * g1 * vx;
+    ub[2 * pl + g] += sb * sv * ir - ap * g1 * vy;
+    ub[3 * pl + g] += ap * g1;
+  });
 }
 
 // ---------------------------------------------------------------- step size
@@ -638,40 +655,42 @@ __global__ void __launch_bounds__(kBlock) k_fill(float* p, float v, long long n)
   if (g < n) p[g] = v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_dt_reduce(const ChunkDev* chunks, const PatchDev* patches,
+__global__ void __launch_bounds__(kBlock) k_dt_reduce(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                       const float* u, const float* mu, long long pl,
                                                       float gam, unsigned* smax, unsigned* mmax) {
   __shared__ float rs[kBlock / 64], rm[kBlock / 64];
-  const ChunkDev ck = chunks[blockIdx.x];
-  const PatchDev P = patches[ck.patch];
-  const int k = ck.start + threadIdx.x;
-  float s = 0.f, m = 0.f;
-  int i, j;
-  if (k < pstore(P) && pdecode(P, k, i, j)) {
-    const long long g = P.off + k;
-    float rho, vx, vy, p;
-    prim(u, pl, g, gam, rho, vx, vy, p);
-    s = fabsf(vx) + fabsf(vy) + sqrtf(gam * p / rho);
-    if (mu) m = mu[g];
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    s = fmaxf(s, __shfl_xor(s, o));
-    m = fmaxf(m, __shfl_xor(m, o));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    rs[threadIdx.x >> 6] = s;
-    rm[threadIdx.x >> 6] = m;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-      s = fmaxf(s, rs[w]);
-      m = fmaxf(m, rm[w]);
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    float s = 0.f, m = 0.f;
+    int i, j;
+    if (k < pstore(P) && pdecode(P, k, i, j)) {
+      const long long g = P.off + k;
+      float rho, vx, vy, p;
+      prim(u, pl, g, gam, rho, vx, vy, p);
+      s = fabsf(vx) + fabsf(vy) + sqrtf(gam * p / rho);
+      if (mu) m = mu[g];
     }
-    // non-negative floats order like their bit patterns
-    atomicMax(smax + ck.patch, __float_as_uint(fmaxf(s, 0.f)));
-    atomicMax(mmax + ck.patch, __float_as_uint(fmaxf(m, 0.f)));
-  }
+    for (int o = 32; o > 0; o >>= 1) {
+      s = fmaxf(s, __shfl_xor(s, o));
+      m = fmaxf(m, __shfl_xor(m, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      rs[threadIdx.x >> 6] = s;
+      rm[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+        s = fmaxf(s, rs[w]);
+        m = fmaxf(m, rm[w]);
+      }
+      // non-negative floats order like their bit patterns
+      atomicMax(smax + ck.patch, __float_as_uint(fmaxf(s, 0.f)));
+      atomicMax(mmax + ck.patch, __float_as_uint(fmaxf(m, 0.f)));
+    }
+    __syncthreads();  // rs, rm are reused by the next chunk
+  });
 }
 
 __global__ void __launch_bounds__(kBlock) k_dt_final(const PatchDev* patches, int np, const unsigned* smax,
