@@ -202,39 +202,56 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 constexpr float kLoScale = 2048.0f;
 constexpr float kLoUnscale = 1.0f / 2048.0f;
 
-// Weights in LDS in the operand layout of the 16x16x32 fp16 product: for
-// lane group g (lanes 16 g .. 16 g + 15) the contraction slots are 4 units
-// k = 16 c + 4 g + e (e = 0..3) of a 16-unit chunk c, and a half8 holds
-// {lo * 2^11 (e = 0..3), hi (e = 0..3)} of row n = lane % 16.  A layer's
-// output tile t (rows 16 t + 4 g + v in lane group g, D layout) then is, as
-// it stands in the registers, chunk t of the next layer's contraction.
+// Weights in LDS in the operand layout of the fp16 products.  For lane group
+// g (lanes 16 g .. 16 g + 15) and row n = lane % 16, a half8 holds the
+// contraction slots k = 16 (2 p) + 4 g + e (e = 0..3) followed by
+// k = 16 (2 p + 1) + 4 g + e: a 32-unit chunk pair p.  A layer's output tile
+// t (rows 16 t + 4 g + v in lane group g, D layout) is, as it stands in the
+// registers, half of chunk pair t / 2 of the next layer's contraction.
+// Separate arrays hold the high parts and the 2^11-scaled low parts, so the
+// main product and the two corrections each read one half8.
 struct MlpLds {
-  half8 W1[4][4][16];     // [output chunk t][g][n]: W1[4 e + g][16 t + n] (layer 1 slots: feature 4 e + g)
-  half8 W2[4][4][4][16];  // [output chunk mt][input chunk c][g][n]: W2[16 c + 4 g + e][16 mt + n]
-  half8 W3[4][4][16];     // [input chunk c][g][n]: W3[16 c + 4 g + e][n] (n < 4), zero rows n >= 4
+  half4 W1h[4][4][16];        // [output tile t][g][n]: hi of W1[4 e + g][16 t + n] (slots: feature 4 e + g)
+  half8 W1c[4][4][16];        // {lo * 2^11 (e = 0..3), hi (e = 0..3)} of the same
+  half8 W2h[4][2][4][16];     // [output tile mt][pair p][g][n]: hi of W2[k][16 mt + n]
+  half8 W2l[4][2][4][16];     // lo * 2^11 of the same
+  half8 W3h[2][4][16];        // [pair p][g][n]: hi of W3[k][n] (n < 4), zero rows n >= 4
+  half8 W3l[2][4][16];
   float b1[64];
   float b2[64];
   float b3[4];
 };
 
-__device__ __forceinline__ void split_store(_Float16* hl, int e, float w) {
-  const _Float16 h = (_Float16)w;
-  hl[e] = (_Float16)((w - (float)h) * kLoScale);
-  hl[4 + e] = h;
+__device__ __forceinline__ void split1(float w, _Float16& h, _Float16& l) {
+  h = (_Float16)w;
+  // (w - hi) 2^11 in one mixed-precision fma (exact: w - hi is exact in FP32)
+  l = (_Float16)__builtin_fmaf((float)h, -kLoScale, w * kLoScale);
 }
 
 __device__ __forceinline__ void mlp_load(MlpLds& L, const MlpPtr& w) {
   for (int q = threadIdx.x; q < 4 * 4 * 16 * 4; q += blockDim.x) {
     const int e = q & 3, n = (q >> 2) & 15, g = (q >> 6) & 3, t = q >> 8;
-    split_store((_Float16*)&L.W1[t][g][n], e, w.W1[(4 * e + g) * 64 + 16 * t + n]);
+    _Float16 h, l;
+    split1(w.W1[(4 * e + g) * 64 + 16 * t + n], h, l);
+    ((_Float16*)&L.W1h[t][g][n])[e] = h;
+    ((_Float16*)&L.W1c[t][g][n])[e] = l;
+    ((_Float16*)&L.W1c[t][g][n])[4 + e] = h;
   }
-  for (int q = threadIdx.x; q < 4 * 4 * 4 * 16 * 4; q += blockDim.x) {
-    const int e = q & 3, n = (q >> 2) & 15, g = (q >> 6) & 3, c = (q >> 8) & 3, mt = q >> 10;
-    split_store((_Float16*)&L.W2[mt][c][g][n], e, w.W2[(16 * c + 4 * g + e) * 64 + 16 * mt + n]);
+  for (int q = threadIdx.x; q < 4 * 2 * 4 * 16 * 8; q += blockDim.x) {
+    const int e = q & 7, n = (q >> 3) & 15, g = (q >> 7) & 3, pp = (q >> 9) & 1, mt = q >> 10;
+    const int k = 16 * (2 * pp + (e >> 2)) + 4 * g + (e & 3);
+    _Float16 h, l;
+    split1(w.W2[k * 64 + 16 * mt + n], h, l);
+    ((_Float16*)&L.W2h[mt][pp][g][n])[e] = h;
+    ((_Float16*)&L.W2l[mt][pp][g][n])[e] = l;
   }
-  for (int q = threadIdx.x; q < 4 * 4 * 16 * 4; q += blockDim.x) {
-    const int e = q & 3, n = (q >> 2) & 15, g = (q >> 6) & 3, c = q >> 8;
-    split_store((_Float16*)&L.W3[c][g][n], e, n < 4 ? w.W3[(16 * c + 4 * g + e) * 4 + n] : 0.f);
+  for (int q = threadIdx.x; q < 2 * 4 * 16 * 8; q += blockDim.x) {
+    const int e = q & 7, n = (q >> 3) & 15, g = (q >> 7) & 3, pp = q >> 9;
+    const int k = 16 * (2 * pp + (e >> 2)) + 4 * g + (e & 3);
+    _Float16 h, l;
+    split1(n < 4 ? w.W3[k * 4 + n] : 0.f, h, l);
+    ((_Float16*)&L.W3h[pp][g][n])[e] = h;
+    ((_Float16*)&L.W3l[pp][g][n])[e] = l;
   }
   for (int k = threadIdx.x; k < 64; k += blockDim.x) {
     L.b1[k] = w.b1[k];
@@ -243,16 +260,25 @@ __device__ __forceinline__ void mlp_load(MlpLds& L, const MlpPtr& w) {
   if (threadIdx.x < 4) L.b3[threadIdx.x] = w.b3[threadIdx.x];
 }
 
-__device__ __forceinline__ half4 hi4(const half8 a) { return half4{a[4], a[5], a[6], a[7]}; }
-__device__ __forceinline__ half8 cat(const half4 a, const half4 b) {
-  return half8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-}
-// hi and scaled lo of four FP32 values
-__device__ __forceinline__ void split4(const floatx4 v, half4& h, half4& l) {
+// relu(m + c 2^-11) of two output tiles, split into the hi and scaled-lo
+// half8 operands of a chunk pair (tile a in slots 0..3, tile b in 4..7)
+template <bool RELU>
+__device__ __forceinline__ void finish_pair(const floatx4 ma, const floatx4 ca, const floatx4 mb,
+                                            const floatx4 cb, half8& h, half8& l) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    h[e] = (_Float16)v[e];
-    l[e] = (_Float16)((v[e] - (float)h[e]) * kLoScale);
+  for (int v = 0; v < 4; ++v) {
+    float x = ma[v] + ca[v] * kLoUnscale, y = mb[v] + cb[v] * kLoUnscale;
+    if (RELU) {
+      x = fmaxf(x, 0.f);
+      y = fmaxf(y, 0.f);
+    }
+    _Float16 t0, t1, t2, t3;
+    split1(x, t0, t1);
+    split1(y, t2, t3);
+    h[v] = t0;
+    l[v] = t1;
+    h[4 + v] = t2;
+    l[4 + v] = t3;
   }
 }
 
@@ -262,49 +288,56 @@ __device__ __forceinline__ void split4(const floatx4 v, half4& h, half4& l) {
 // D layout of one layer's output is the B layout of the next.
 __device__ __forceinline__ floatx4 mlp16(const MlpLds& L, const float x[4], int g, int r) {
   half4 xh, xl;
-  split4(floatx4{x[0], x[1], x[2], x[3]}, xh, xl);
-  const half8 xb = cat(xh, xl);
-  half4 ah[4], al[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    floatx4 m = floatx4{L.b1[16 * t + 4 * g], L.b1[16 * t + 4 * g + 1], L.b1[16 * t + 4 * g + 2],
-                        L.b1[16 * t + 4 * g + 3]};
-    floatx4 c = floatx4{0.f, 0.f, 0.f, 0.f};
-    const half8 a = L.W1[t][g][r];
-    m = __builtin_amdgcn_mfma_f32_16x16x16f16(hi4(a), xh, m, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, xb, c, 0, 0, 0);
-    floatx4 h;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) h[v] = fmaxf(m[v] + c[v] * kLoUnscale, 0.f);
-    split4(h, ah[t], al[t]);
+  for (int e = 0; e < 4; ++e) {
+    _Float16 t0, t1;
+    split1(x[e], t0, t1);
+    xh[e] = t0;
+    xl[e] = t1;
   }
-  half4 bh[4], bl[4];
+  const half8 xb = half8{xh[0], xh[1], xh[2], xh[3], xl[0], xl[1], xl[2], xl[3]};
+  half8 ah[2], al[2];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    floatx4 m = floatx4{L.b2[16 * mt + 4 * g], L.b2[16 * mt + 4 * g + 1], L.b2[16 * mt + 4 * g + 2],
-                        L.b2[16 * mt + 4 * g + 3]};
-    floatx4 c = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int p = 0; p < 2; ++p) {
+    floatx4 m[2], c[2];
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
-      m = __builtin_amdgcn_mfma_f32_16x16x32_f16(cat(hi4(L.W2[mt][2 * p][g][r]), hi4(L.W2[mt][2 * p + 1][g][r])),
-                                                 cat(ah[2 * p], ah[2 * p + 1]), m, 0, 0, 0);
+    for (int u = 0; u < 2; ++u) {
+      const int t = 2 * p + u;
+      m[u] = floatx4{L.b1[16 * t + 4 * g], L.b1[16 * t + 4 * g + 1], L.b1[16 * t + 4 * g + 2],
+                     L.b1[16 * t + 4 * g + 3]};
+      c[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+      m[u] = __builtin_amdgcn_mfma_f32_16x16x16f16(L.W1h[t][g][r], xh, m[u], 0, 0, 0);
+      c[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W1c[t][g][r], xb, c[u], 0, 0, 0);
+    }
+    finish_pair<true>(m[0], c[0], m[1], c[1], ah[p], al[p]);
+  }
+  half8 bh[2], bl[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2[mt][k][g][r], cat(ah[k], al[k]), c, 0, 0, 0);
-    floatx4 h;
+  for (int q = 0; q < 2; ++q) {
+    floatx4 m[2], c[2];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) h[v] = fmaxf(m[v] + c[v] * kLoUnscale, 0.f);
-    split4(h, bh[mt], bl[mt]);
+    for (int u = 0; u < 2; ++u) {
+      const int mt = 2 * q + u;
+      m[u] = floatx4{L.b2[16 * mt + 4 * g], L.b2[16 * mt + 4 * g + 1], L.b2[16 * mt + 4 * g + 2],
+                     L.b2[16 * mt + 4 * g + 3]};
+      c[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        m[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2h[mt][p][g][r], ah[p], m[u], 0, 0, 0);
+        c[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2l[mt][p][g][r], ah[p], c[u], 0, 0, 0);
+        c[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2h[mt][p][g][r], al[p], c[u], 0, 0, 0);
+      }
+    }
+    finish_pair<true>(m[0], c[0], m[1], c[1], bh[q], bl[q]);
   }
   floatx4 m = g == 0 ? floatx4{L.b3[0], L.b3[1], L.b3[2], L.b3[3]} : floatx4{0.f, 0.f, 0.f, 0.f};
   floatx4 c = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
-    m = __builtin_amdgcn_mfma_f32_16x16x32_f16(cat(hi4(L.W3[2 * p][g][r]), hi4(L.W3[2 * p + 1][g][r])),
-                                               cat(bh[2 * p], bh[2 * p + 1]), m, 0, 0, 0);
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3[k][g][r], cat(bh[k], bl[k]), c, 0, 0, 0);
+  for (int p = 0; p < 2; ++p) {
+    m = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3h[p][g][r], bh[p], m, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3l[p][g][r], bh[p], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3h[p][g][r], bl[p], c, 0, 0, 0);
+  }
   floatx4 o;
 #pragma unroll
   for (int v = 0; v < 4; ++v) o[v] = m[v] + c[v] * kLoUnscale;
