@@ -171,16 +171,21 @@ __global__ void FCSD_LINE_BOUNDS k_fcdiff(PassArgs a) {
     }
     float* OA = a.out + (long long)f * a.plane + M.base;
     float* OB = two ? a.out + (long long)(f + 1) * a.plane + M.base : OA;
-    walk(M.w, [&](unsigned g, unsigned l) {
-      const float2 v = at(z, l);
-      if (ADJ) {
-        at(OA, g) += v.x;
-        if (two) at(OB, g) += v.y;
-      } else {
+    if (ADJ) {
+      walk_b<kLoadBatch>(
+          M.w, [&](unsigned g) { return make_float2(at(OA, g), two ? at(OB, g) : 0.f); },
+          [&](unsigned g, unsigned l, float2 o) {
+            const float2 v = at(z, l);
+            at(OA, g) = o.x + v.x;
+            if (two) at(OB, g) = o.y + v.y;
+          });
+    } else {
+      walk(M.w, [&](unsigned g, unsigned l) {
+        const float2 v = at(z, l);
         at(OA, g) = v.x;
         if (two) at(OB, g) = v.y;
-      }
-    });
+      });
+    }
     __syncthreads();
   }
 }

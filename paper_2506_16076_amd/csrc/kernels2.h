@@ -946,55 +946,104 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
   const int mx = DIR == 1 ? 0 : 2, my = DIR == 1 ? 1 : 3;
   const float* mdx = a.metric + mx * pl + bo;
   const float* mdy = a.metric + my * pl + bo;
+  const float* m1x = a.metric + bo;
+  const float* m1y = a.metric + pl + bo;
+  const float* m2x = a.metric + 2 * pl + bo;
+  const float* m2y = a.metric + 3 * pl + bo;
+  // loads of the element loops are batched (walk_b): one element's loads
+  // waited for before the next element's were issued made this kernel
+  // latency-bound
   for (int comp = 0; comp < 4; ++comp) {
     const float* rbc = rb + comp * pl + bo;
-    walk(M.w, [&](unsigned g, unsigned l) {
-      const float r = at(rbc, g);
-      at(z, l) = make_float2(at(mdx, g) * r, at(mdy, g) * r);
-    });
+    walk_b<kLoadBatch>(
+        M.w, [&](unsigned g) { return make_float4(at(rbc, g), at(mdx, g), at(mdy, g), 0.f); },
+        [&](unsigned, unsigned l, float4 v) { at(z, l) = make_float2(v.y * v.x, v.z * v.x); });
     __syncthreads();
     line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
     float* hbx = Hb + (2 * comp) * pl + bo;
     float* hby = Hb + (2 * comp + 1) * pl + bo;
     const long long fo = comp * pl + bo;
-    walk(M.w, [&](unsigned g, unsigned l) {
-      const float2 v = at(z, l);
-      if (DIR == 1) {
+    if (DIR == 1) {
+      walk(M.w, [&](unsigned g, unsigned l) {
+        const float2 v = at(z, l);
         at(hbx, g) = v.x;
         at(hby, g) = v.y;
-      } else {
-        const float hx = at(hbx, g) + v.x, hy = at(hby, g) + v.y;
-        at(hbx, g) = hx;
-        at(hby, g) = hy;
-        if (visc) {
-          const float m1x = at(a.metric + bo, g), m1y = at(a.metric + pl + bo, g),
-                      m2x = at(a.metric + 2 * pl + bo, g), m2y = at(a.metric + 3 * pl + bo, g);
-          const float mu = at(a.mu + bo, g);
-          at(G1 + fo, g) = mu * (m1x * hx + m1y * hy);
-          at(G2 + fo, g) = mu * (m2x * hx + m2y * hy);
-          if (mub) {
-            const float ex = m1x * at(d1e + fo, g) + m2x * at(d2e + fo, g);
-            const float ey = m1y * at(d1e + fo, g) + m2y * at(d2e + fo, g);
-            at(mub + bo, g) += hx * ex + hy * ey;
-          }
-        }
-      }
-    });
+      });
+    } else if (!visc) {
+      walk_b<kLoadBatch>(
+          M.w, [&](unsigned g) { return make_float2(at(hbx, g), at(hby, g)); },
+          [&](unsigned g, unsigned l, float2 h) {
+            const float2 v = at(z, l);
+            at(hbx, g) = h.x + v.x;
+            at(hby, g) = h.y + v.y;
+          });
+    } else {
+      struct VIn {
+        float hx, hy, m1x, m1y, m2x, m2y, mu, d1, d2, mb;
+      };
+      const float* d1c = d1e + fo;
+      const float* d2c = d2e + fo;
+      float* mubp = mub ? mub + bo : nullptr;
+      walk_b<kEpiBatchH>(
+          M.w,
+          [&](unsigned g) {
+            VIn q;
+            q.hx = at(hbx, g);
+            q.hy = at(hby, g);
+            q.m1x = at(m1x, g);
+            q.m1y = at(m1y, g);
+            q.m2x = at(m2x, g);
+            q.m2y = at(m2y, g);
+            q.mu = at(a.mu + bo, g);
+            q.d1 = mubp ? at(d1c, g) : 0.f;
+            q.d2 = mubp ? at(d2c, g) : 0.f;
+            q.mb = mubp ? at(mubp, g) : 0.f;
+            return q;
+          },
+          [&](unsigned g, unsigned l, const VIn& q) {
+            const float2 v = at(z, l);
+            const float hx = q.hx + v.x, hy = q.hy + v.y;
+            at(hbx, g) = hx;
+            at(hby, g) = hy;
+            at(G1 + fo, g) = q.mu * (q.m1x * hx + q.m1y * hy);
+            at(G2 + fo, g) = q.mu * (q.m2x * hx + q.m2y * hy);
+            if (mubp) {
+              const float ex = q.m1x * q.d1 + q.m2x * q.d2;
+              const float ey = q.m1y * q.d1 + q.m2y * q.d2;
+              at(mubp, g) = q.mb + hx * ex + hy * ey;
+            }
+          });
+    }
     __syncthreads();
   }
   if (DIR == 2 && a.mode != FLUX_VISC) {
-    walk(M.w, [&](unsigned g, unsigned) {
-      float e[4], fb[4], gb[4], o[4];
+    struct FIn {
+      float e[4], fb[4], gb[4], ub[4];
+    };
+    walk_b<2>(
+        M.w,
+        [&](unsigned g) {
+          FIn q;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        e[q] = at(a.u + q * pl + bo, g);
-        fb[q] = -at(Hb + (2 * q) * pl + bo, g);
-        gb[q] = -at(Hb + (2 * q + 1) * pl + bo, g);
-      }
-      flux_vjp(e, a.gamma, fb, gb, o);
+          for (int k = 0; k < 4; ++k) {
+            q.e[k] = at(a.u + k * pl + bo, g);
+            q.fb[k] = at(Hb + (2 * k) * pl + bo, g);
+            q.gb[k] = at(Hb + (2 * k + 1) * pl + bo, g);
+            q.ub[k] = at(ub + k * pl + bo, g);
+          }
+          return q;
+        },
+        [&](unsigned g, unsigned, const FIn& q) {
+          float fb[4], gb[4], o[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) at(ub + q * pl + bo, g) += o[q];
-    });
+          for (int k = 0; k < 4; ++k) {
+            fb[k] = -q.fb[k];
+            gb[k] = -q.gb[k];
+          }
+          flux_vjp(q.e, a.gamma, fb, gb, o);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) at(ub + k * pl + bo, g) = q.ub[k] + o[k];
+        });
   }
 }
 
