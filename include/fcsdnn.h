@@ -332,12 +332,25 @@ typedef struct {
   int filter;           /* 1: apply the spectral filter configured by
                            fcsd_set_filter after the viscosity (then glue
                            again), before the step size */
+  float* record;        /* nullable [FCSD_RECORD_PLANES][plane]: fcsd_step
+                           stores what its reverse mode needs (below) and
+                           fcsd_step_adj reads it instead of recomputing
+                           the forward step */
 } fcsd_step_args;
+
+/* Planes of a step record: 0..19 the five glued stage inputs [5][4][plane]
+ * (stage 0 = the state after glue, viscosity and filter), 20 mu, 21 the 7x7
+ * maximisers as int32 (with classes), 22..25 the glued state before the
+ * filter (with a->filter). */
+#define FCSD_RECORD_PLANES 26
 
 /* One full time step (Algorithm 1): glue, network classes and viscosity
  * (when w != NULL), spectral filter and glue (when a->filter), step size,
  * five fused stages with glue on every stage input.  use_graph = 1 captures the step once into a hipGraph and replays
- * it on later calls with identical arguments. */
+ * it on later calls with identical arguments.  With a->record the stage
+ * inputs, mu, the maximisers (argmax required then, with classes) and the
+ * pre-filter state are written to the record as well; the step's result is
+ * the same. */
 fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* a,
                       int64_t plane, void* ws, size_t ws_bytes, int use_graph);
 
@@ -346,7 +359,9 @@ fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* set, const fcsd_step_args* 
  * recorded ones): given the cotangent of the step output in u_bar, replaces
  * it by the cotangent of the step input u_in (the state before the first
  * glue; not modified).  The forward step is recomputed from u_in into the
- * workspace.  With a Dirichlet mask, dparam_dev[0] (device FP64) is
+ * workspace, unless a->record holds the record that fcsd_step wrote for this
+ * step with the same arguments (then u_in may be NULL, nothing is
+ * recomputed and mu and argmax are read from the record).  With a Dirichlet mask, dparam_dev[0] (device FP64) is
  * incremented by u_bar_glued . dstate_dparam summed over the flagged points
  * of every glue, i.e. the derivative through the boundary state with
  * respect to a scalar parameter whose state derivative (4 floats, host) is

@@ -67,7 +67,10 @@ class StepArgs(ctypes.Structure):
                 ("dirichlet_mask", ctypes.c_void_p), ("dirichlet_state", ctypes.c_float * 4),
                 ("ref", ctypes.c_float * 4), ("gamma", ctypes.c_float), ("cfl", ctypes.c_float),
                 ("fixed_dt", ctypes.c_int), ("w", ctypes.c_void_p), ("fixed_tau", ctypes.c_int),
-                ("filter", ctypes.c_int)]
+                ("filter", ctypes.c_int), ("record", ctypes.c_void_p)]
+
+
+RECORD_PLANES = 26  # planes of a step record (stage inputs, mu, maximisers, pre-filter state)
 
 
 _lib = None

@@ -13,7 +13,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import (LAYOUT_B8X4, LAYOUT_ROWS, FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP,
+from ._lib import (LAYOUT_B8X4, LAYOUT_ROWS, RECORD_PLANES, FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP,
                    WS_STEP_ADJ, WS_FILTER_ADJ, blocked_layout, layout_index, lib, patch_descs)
 
 
@@ -375,11 +375,23 @@ class Stepper:
         self.args = a
         self.ws = s.workspace(WS_STEP)
 
-    def step(self, use_graph=False):
-        _call(self.s, "fcsd_step", ctypes.byref(self.args), self.s.plane, _p(self.ws), self.ws.numel() * 4,
-              1 if use_graph else 0)
+    def new_record(self):
+        """A buffer for one step record (RECORD_PLANES float planes)."""
+        return torch.empty(RECORD_PLANES * self.s.plane, device=self.u.device)
 
-    def replay(self, tau, dt, use_graph=False):
+    def step(self, use_graph=False, record=None):
+        """One step; with `record` (from new_record) the step also stores
+        what step_adj needs to skip the forward recomputation."""
+        _chk(record, torch.float32, RECORD_PLANES * self.s.plane)
+        a = self.args
+        a.record = record.data_ptr() if record is not None else None
+        try:
+            _call(self.s, "fcsd_step", ctypes.byref(a), self.s.plane, _p(self.ws), self.ws.numel() * 4,
+                  1 if use_graph else 0)
+        finally:
+            a.record = None
+
+    def replay(self, tau, dt, use_graph=False, record=None):
         """One step with recorded decisions: classes `tau` (int8 plane) and
         step size `dt` (1-element tensor) instead of the network and CFL."""
         a = self.args
@@ -388,24 +400,31 @@ class Stepper:
         fd, ft = a.fixed_dt, a.fixed_tau
         a.fixed_dt, a.fixed_tau = 1, 1 if self.W is not None else 0
         try:
-            self.step(use_graph=use_graph)
+            self.step(use_graph=use_graph, record=record)
         finally:
             a.fixed_dt, a.fixed_tau = fd, ft
 
-    def step_adj(self, u_in, u_bar, tau, dt, dstate=(0, 0, 0, 0), dparam=None):
+    def step_adj(self, u_in, u_bar, tau, dt, dstate=(0, 0, 0, 0), dparam=None, record=None):
         """Reverse mode of a step from state u_in with recorded decisions:
         u_bar (cotangent of the step output) becomes the cotangent of u_in;
-        dparam (float64, 1 element) gathers the boundary-state derivative."""
-        _chk(u_in, numel=4 * self.s.plane), _chk(u_bar, numel=4 * self.s.plane)
+        dparam (float64, 1 element) gathers the boundary-state derivative.
+        With `record` (written by step/replay of this same step) the forward
+        step is not recomputed and u_in may be None."""
+        if record is None:
+            _chk(u_in, numel=4 * self.s.plane)
+        _chk(u_bar, numel=4 * self.s.plane)
         _chk(dparam, torch.float64, 1)
+        _chk(record, torch.float32, RECORD_PLANES * self.s.plane)
         a = self.args
         self.tau.copy_(tau)
         self.dt.copy_(dt)
         fd, ft = a.fixed_dt, a.fixed_tau
         a.fixed_dt, a.fixed_tau = 1, 1 if self.W is not None else 0
+        a.record = record.data_ptr() if record is not None else None
         ws = self.s.workspace(WS_STEP_ADJ)
         try:
             _call(self.s, "fcsd_step_adj", ctypes.byref(a), _p(u_in), _p(u_bar), _f4(dstate), _p(dparam),
                   self.s.plane, _p(ws), ws.numel() * 4)
         finally:
             a.fixed_dt, a.fixed_tau = fd, ft
+            a.record = None

@@ -1217,6 +1217,16 @@ fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a,
     if ((st = sdnn_impl(ctx, s, a->u, a->gamma, a->w, a->tau, nullptr, A.phi))) return st;
   if (a->w || a->fixed_tau)
     if ((st = viscosity_impl(ctx, s, a->u, a->tau, a->gamma, a->mu, a->argmax, A))) return st;
+  const long long n4 = 4 * pl;
+  float* rec = a->record;
+  hipStream_t sm = ctx->stream;
+  if (rec) {
+    if (a->mu) HIPCHK(ctx, hipMemcpyAsync(rec + 5 * n4, a->mu, pl * sizeof(float), hipMemcpyDeviceToDevice, sm));
+    if (a->w || a->fixed_tau)
+      HIPCHK(ctx, hipMemcpyAsync(rec + 5 * n4 + pl, a->argmax, pl * sizeof(int32_t), hipMemcpyDeviceToDevice, sm));
+    if (a->filter)
+      HIPCHK(ctx, hipMemcpyAsync(rec + 5 * n4 + 2 * pl, a->u, n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
+  }
   if (a->filter) {
     if ((st = filter_impl(ctx, s, a->u, a->u, a->gamma))) return st;
     if ((st = glue_impl(ctx, s, a->u, a->dirichlet_mask, a->dirichlet_state))) return st;
@@ -1225,6 +1235,13 @@ fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a,
     if ((st = cfl_dt_impl(ctx, s, a->u, a->mu, a->cfl, a->gamma, a->dt_dev, A.red))) return st;
   const float* ins[5] = {a->u, Ua, Ub, Ua, Ub};
   float* outs[5] = {Ua, Ub, Ua, Ub, a->u};
+  if (rec) {  // stage inputs 1..4 are computed straight into the record
+    HIPCHK(ctx, hipMemcpyAsync(rec, a->u, n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
+    for (int k = 1; k < 5; ++k) {
+      ins[k] = rec + k * n4;
+      outs[k - 1] = rec + k * n4;
+    }
+  }
   for (int k = 0; k < 5; ++k) {
     if (k > 0)
       if ((st = glue_impl(ctx, s, const_cast<float*>(ins[k]), a->dirichlet_mask, a->dirichlet_state))) return st;
@@ -1245,6 +1262,8 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   if ((a->w || a->fixed_tau) && (!a->tau || !a->mu))
     return fail(ctx, FCSD_EINVAL, "fcsd_step: network needs tau and mu buffers");
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step: filter not configured (fcsd_set_filter)");
+  if (a->record && (a->w || a->fixed_tau) && !a->argmax)
+    return fail(ctx, FCSD_EINVAL, "fcsd_step: a record with classes needs the argmax buffer");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP)) return fail(ctx, FCSD_EINVAL, "fcsd_step: workspace too small");
   if (!use_graph) return step_body(ctx, s, a, ws);
   if (!ctx->stream) return fail(ctx, FCSD_EINVAL, "fcsd_step: graph capture needs a non-default stream");
@@ -1360,7 +1379,7 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
                                      void* ws, size_t ws_bytes) {
   fcsd_status st = check_set(ctx, s, plane);
   if (st) return st;
-  if (!a || !a->metric || !a->dt_dev || !u_in || !u_bar || !ws)
+  if (!a || !a->metric || !a->dt_dev || (!u_in && !a->record) || !u_bar || !ws)
     return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: null argument");
   if (a->dirichlet_mask && (!dstate_dparam || !dparam_dev))
     return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: Dirichlet data needs dstate_dparam and dparam_dev");
@@ -1371,7 +1390,8 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: filter not configured (fcsd_set_filter)");
   const long long pl = s->plane, n4 = 4 * pl;
   float* w = (float*)ws;
-  float* STG = w;           // glued stage inputs 0..4
+  const bool have = a->record != nullptr;  // the forward step recorded what the reverse needs
+  float* STG = have ? a->record : w;        // glued stage inputs 0..4
   float* ACC = w + 20 * pl;
   float* OUT = w + 24 * pl;  // step output; with the filter: the glued state before it (PRE)
   float* YB = w + 28 * pl;  // cotangent of the current stage output
@@ -1384,20 +1404,24 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   AvWs A = carve_av(s, w + 73 * pl);
   hipStream_t sm = ctx->stream;
   auto stg = [&](int k) { return STG + (long long)k * n4; };
-  // forward recomputation with the recorded classes and step size
-  HIPCHK(ctx, hipMemcpyAsync(stg(0), u_in, n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
-  if ((st = glue_impl(ctx, s, stg(0), a->dirichlet_mask, a->dirichlet_state))) return st;
-  if (visc_net)
-    if ((st = viscosity_impl(ctx, s, stg(0), a->tau, a->gamma, a->mu, a->argmax, A))) return st;
-  float* PRE = OUT;
-  if (a->filter) {
-    HIPCHK(ctx, hipMemcpyAsync(PRE, stg(0), n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
-    if ((st = filter_impl(ctx, s, stg(0), stg(0), a->gamma))) return st;
-    if ((st = glue_impl(ctx, s, stg(0), a->dirichlet_mask, a->dirichlet_state))) return st;
-  }
-  const float* mu = a->mu;
+  float* PRE = have ? a->record + 5 * n4 + 2 * pl : OUT;
+  const float* mu = a->mu ? (have ? a->record + 5 * n4 : a->mu) : nullptr;
+  const int32_t* amax = have ? (const int32_t*)(a->record + 5 * n4 + pl) : a->argmax;
   const int flux = mu ? FLUX_FULL : FLUX_INVISCID;
-  for (int k = 0; k < 5; ++k) {
+  // forward recomputation with the recorded classes and step size (unless
+  // the forward step recorded its stage inputs)
+  if (!have) {
+    HIPCHK(ctx, hipMemcpyAsync(stg(0), u_in, n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
+    if ((st = glue_impl(ctx, s, stg(0), a->dirichlet_mask, a->dirichlet_state))) return st;
+    if (visc_net)
+      if ((st = viscosity_impl(ctx, s, stg(0), a->tau, a->gamma, a->mu, a->argmax, A))) return st;
+    if (a->filter) {
+      HIPCHK(ctx, hipMemcpyAsync(PRE, stg(0), n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
+      if ((st = filter_impl(ctx, s, stg(0), stg(0), a->gamma))) return st;
+      if ((st = glue_impl(ctx, s, stg(0), a->dirichlet_mask, a->dirichlet_state))) return st;
+    }
+  }
+  for (int k = 0; k < 5 && !have; ++k) {
     if (k > 0)
       if ((st = glue_impl(ctx, s, stg(k), a->dirichlet_mask, a->dirichlet_state))) return st;
     // the step output is not needed in reverse: with the filter it goes to
@@ -1439,7 +1463,7 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
     vin = PRE;
   }
   if (visc_net)
-    if ((st = av_viscosity_adj(ctx, s, vin, a->tau, a->argmax, a->gamma, MUB, U0B, plane, w + 73 * pl,
+    if ((st = av_viscosity_adj(ctx, s, vin, a->tau, amax, a->gamma, MUB, U0B, plane, w + 73 * pl,
                                ws_bytes_of(s, FCSD_WS_AV))))
       return st;
   if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;

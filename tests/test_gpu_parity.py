@@ -593,6 +593,52 @@ def test_rollout_gradient_with_filter(env):
     _rollout_gradient_check(env, 48, 6, 4, 1, filt=(10.0, 14))
 
 
+@pytest.mark.parametrize("filt", [None, (10.0, 14)])
+def test_step_record_equals_recompute(env, filt):
+    """A step that writes its record advances the state exactly as one that
+    does not, and the reverse mode read from the record equals, bit for bit,
+    the one that recomputes the step (network classes, Dirichlet glue, with
+    and without the filter); the boundary-parameter derivative to FP64
+    rounding."""
+    api, ctx, torch = env
+    cfg = synth.config(3, n=48)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, 1)
+    if filt is not None:
+        s.set_filter(*filt)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    ubuf = D(cfg.u0)
+    st = api.Stepper(s, ubuf, D(ps.metric), cfg.ref, W=W, dirichlet_mask=D(ps.dirichlet),
+                     dirichlet_state=synth.freestream(cfg.mach), filt=filt is not None)
+    st.step()                      # a state with shocks forming
+    u_in = ubuf.clone()
+    st.step()
+    plain = ubuf.clone()
+    tau, dt = st.tau.clone(), st.dt.clone()
+    ubuf.copy_(u_in)
+    rec = st.new_record()
+    st.replay(tau, dt, record=rec)
+    assert torch.equal(ubuf, plain)
+    g = torch.randn(4 * s.plane, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(11))
+    dstate = autodiff_dmach(cfg)
+    b1, b2 = g.clone(), g.clone()
+    p1 = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    p2 = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    st.step_adj(u_in, b1, tau, dt, dstate, p1)
+    st.step_adj(None, b2, tau, dt, dstate, p2, record=rec)
+    say("record vs recompute: max |diff|", float((b1 - b2).abs().max()), "dparam", float(p1), float(p2))
+    assert torch.equal(b1, b2)
+    # dparam is a sum of FP64 atomic adds: its rounding depends on their order
+    assert abs(float(p1) - float(p2)) <= 1e-12 * abs(float(p1))
+    assert float(b1.abs().max()) > 0 and float(p1.abs()) > 0
+    s.close()
+
+
+def autodiff_dmach(cfg):
+    from paper_2506_16076_amd import autodiff
+    return autodiff.freestream_dmach(cfg.mach)
+
+
 @pytest.mark.skipif(os.environ.get("FCSD_FULL") != "1", reason="full-size gradient check (minutes of FP64 "
                     "oracle work): set FCSD_FULL=1")
 def test_rollout_gradient_full_size(env):
