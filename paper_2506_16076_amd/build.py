@@ -12,8 +12,11 @@ LIB = os.path.join(HERE, "libfcsdnn.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
-             # packed FP32 instructions stay off (gfx950 notes)
+             # no packed FP32 instructions: plain FP32 code only
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # matrix-core products keep their accumulators in ordinary
+             # vector registers (no accumulator-register reads in the network)
+             "-mllvm", "-amdgpu-mfma-vgpr-form=1",
              "-I", os.path.join(ROOT, "include")]
 
 
