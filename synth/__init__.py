@@ -341,6 +341,21 @@ def config(idx: int, n: Optional[int] = None, npatch: Optional[int] = None,
     raise ValueError(idx)
 
 
+def paper_subpatches(nsec: int = 16, nshell: int = 1, seed: int = 5, mach: float = 3.0) -> Config:
+    """The paper's production discretisation on the annulus: subpatches of
+    101 x 101 points (n0 = 83 plus 2 n_v = 18 overlap points), d = 2
+    matching points and C = 27 continuation points, so every line extends
+    to L = 128; neighbouring subpatches overlap by 2 n_v + 1 = 19 lines.
+    Mach-3 freestream state with the +-1 % density perturbation, seeded
+    network weights."""
+    rng = np.random.default_rng(seed)
+    ps = annulus(nsec, nshell, 101, 101, d=2, c_min=27)
+    pert = draw_perturbation(rng)
+    e = mach_state(ps, mach, pert)
+    return Config(f"paper-d2-{nsec}x{nshell}-101", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]),
+                  mach=mach, pert=pert, mlp=mlp_weights(1000 + seed), steps=100)
+
+
 def random_lines(rng, nlines: int, n: int, smooth: bool = True):
     """Seeded test lines: smooth non-periodic functions (sum of a few random
     low-frequency sinusoids plus a random polynomial) or white noise."""

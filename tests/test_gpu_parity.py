@@ -208,6 +208,12 @@ def rhs_case(name):
             ps.view(u, p)[...] = ps.view(e, p)
         mu = (0.003 * (1.1 + np.cos(2 * ps.xy[0] + ps.xy[1]))).astype(np.float32)
         return ps, u, mu, np.array([1.4, 3.0, 0.0, 1.0])
+    if name == "paper_d2":
+        # the paper's subpatches: 101 x 101 points, d = 2, C = 27 (L = 128)
+        cfg = synth.paper_subpatches(8, 2)
+        ps = cfg.ps
+        mu = (0.003 * (1.3 + np.sin(2 * ps.xy[0] - ps.xy[1]))).astype(np.float32)
+        return ps, cfg.u0, mu, cfg.ref
     if name == "uneven":
         cfg = synth.config(2, npatch=5, nmax=200)
         ps = cfg.ps
@@ -217,7 +223,7 @@ def rhs_case(name):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("case", ["square64", "annulus", "shells", "uneven"])
+@pytest.mark.parametrize("case", ["square64", "annulus", "shells", "uneven", "paper_d2"])
 def test_full_rhs(env, case, layout):
     api, ctx, torch = env
     ps, u, mu, ref = rhs_case(case)
@@ -429,6 +435,32 @@ def test_steps_annulus_with_network(env, layout):
     err = relerr_phys(ps, got, run.u)
     chg = relerr_phys(ps, got - cfg.u0, run.u - cfg.u0)
     say("3 steps annulus: state rel L2", err, "change", chg)
+    assert np.all(err < STEP_TOL)
+    s.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_steps_paper_subpatches(env, layout):
+    """Three steps with the network on the paper's discretisation (16
+    subpatches of 101 x 101, d = 2, C = 27, fringe glue between them)."""
+    api, ctx, torch = env
+    cfg = synth.paper_subpatches(16, 1)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, layout)
+    u = D(cfg.u0)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W, dirichlet_mask=D(ps.dirichlet),
+                     dirichlet_state=synth.freestream(cfg.mach))
+    run = solver.Run(cfg)
+    for k in range(3):
+        st.step()
+        run.step()
+        same = np.mean(H(st.tau) == run.log[-1]["tau"])
+        say("paper subpatches step", k, "layout", layout, "tau agreement", same, "dt", float(host(st.dt)[0]),
+            run.log[-1]["dt"])
+        assert same > 0.999
+    err = relerr_phys(ps, H(u).reshape(4, -1), run.u)
+    say("3 steps paper subpatches: state rel L2", err)
     assert np.all(err < STEP_TOL)
     s.close()
 

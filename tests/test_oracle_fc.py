@@ -148,3 +148,53 @@ def test_c_rule():
     for n in range(48, 513):
         c = synth.cont_points(n)
         assert 27 <= c <= 45 and synth.smooth13(n + c)
+
+
+# ------------------------------------------------------------ d = 2 (the paper's runs)
+
+@pytest.mark.parametrize("N", [101, 128, 256, 512])
+def test_d2_differentiates_lines_exactly(N):
+    """With d = 2 matching points the continuation reproduces polynomials of
+    degree < 2: constants and straight lines are differentiated exactly."""
+    x = np.linspace(0, 1, N)
+    C = 27
+    assert np.abs(fcgram.diff_lines(np.ones((1, N)), 2, C)).max() <= 1e-12
+    assert np.abs(fcgram.diff_lines((3 * x - 1)[None], 2, C)[0] - 3).max() <= 1e-9
+
+
+def test_d2_convergence_is_first_order():
+    """d = 2 fixes only the end values and slopes to first order: the error
+    on smooth non-periodic lines halves with every doubling of N (observed
+    order 1), and is below 1e-2 relative from the paper's 101-point
+    subpatches on (the quadratic term is not reproduced: its error is the
+    same order)."""
+    f = lambda x: np.exp(np.sin(5.4 * np.pi * x - 2.7 * np.pi) - np.cos(2 * np.pi * x))
+    df = lambda x: f(x) * (5.4 * np.pi * np.cos(5.4 * np.pi * x - 2.7 * np.pi) + 2 * np.pi * np.sin(2 * np.pi * x))
+    errs = []
+    for N in (128, 256, 512, 1024):
+        x = np.linspace(0, 1, N)
+        errs.append(np.abs(fcgram.diff_lines(f(x)[None], 2, 27)[0] - df(x)).max() / np.abs(df(x)).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(orders - 1) < 0.15), orders
+    x = np.linspace(0, 1, 101)
+    assert np.abs(fcgram.diff_lines(f(x)[None], 2, 27)[0] - df(x)).max() / np.abs(df(x)).max() < 1e-2
+    # x^2 is outside the matched span: an O(1/N) error, not a rounding one
+    for N in (128, 256):
+        x = np.linspace(0, 1, N)
+        e = np.abs(fcgram.diff_lines((x * x)[None], 2, 27)[0] - 2 * x).max()
+        assert 0.1 / N < e < 2.0 / N
+
+
+def test_d2_blend_structure_mirror_and_transpose():
+    ArQ = fcgram.continuation_matrix(2, 27)
+    assert ArQ.shape == (27, 2)
+    ones = ArQ.sum(axis=1)
+    assert abs(ones[0] - 1) < 0.05 and abs(ones[-1]) < 1e-6
+    rng = np.random.default_rng(4)
+    N = 101
+    F = synth.random_lines(rng, 4, N)
+    D = fcgram.diff_lines(F, 2, 27)
+    assert np.abs(fcgram.diff_lines(F[:, ::-1], 2, 27) + D[:, ::-1]).max() <= 1e-10 * np.abs(D).max()
+    y = rng.standard_normal((4, N))
+    lhs, rhs = np.sum(D * y), np.sum(F * fcgram.diff_lines_adj(y, 2, 27))
+    assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(D) * np.abs(y))
