@@ -21,6 +21,7 @@ Modules
            smoothing-blending operator (Secs. 5.1, 5.2)
   filter   spectral filter of FC expansions and the per-step state filter
            (Sec. 4.3.1)
+  smear    localized discontinuity-smearing of the initial data (Sec. 4.3.2)
   solver   multi-patch time stepping with fringe exchange and boundary
            overwrite (Secs. 3.4, 4.2, Algorithm 1)
   adjoint  hand-written discrete adjoints (reverse mode) of all of the above
