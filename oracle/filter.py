@@ -40,12 +40,22 @@ def sigma(L: int, alpha: float, p: int) -> np.ndarray:
     return np.exp(-alpha * (2.0 * k / L) ** p)
 
 
-def filter_lines(F: np.ndarray, d: int, C: int, alpha: float, p: int) -> np.ndarray:
+def filter_lines(F: np.ndarray, d: int, C: int, alpha: float, p: int, fp32: bool = False) -> np.ndarray:
     """Filter every line (last axis) of F: extend, scale the coefficients by
-    sigma, evaluate at the first N points."""
+    sigma, evaluate at the first N points.
+
+    fp32=True rounds the extension and the factors to FP32 and runs the
+    transform pair in single precision: not the method, but the size of the
+    rounding error any FP32 implementation carries (a step within d points
+    of a line end gives tails up to sum |A_r Q^T| times the step)."""
     F = np.asarray(F, np.float64)
     N = F.shape[-1]
     ext = F if C == 0 else fcgram.extend(F, fcgram.continuation_matrix(d, C))
+    if fp32:
+        import scipy.fft
+        e32 = ext.astype(np.float32)
+        X = scipy.fft.fft(e32, axis=-1) * sigma(ext.shape[-1], alpha, p).astype(np.float32)
+        return np.real(scipy.fft.ifft(X.astype(np.complex64), axis=-1))[..., :N].astype(np.float64)
     X = np.fft.fft(ext, axis=-1) * sigma(ext.shape[-1], alpha, p)
     return np.real(np.fft.ifft(X, axis=-1))[..., :N]
 

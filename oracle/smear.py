@@ -80,29 +80,31 @@ def window(labels, c: float = C_WIN, r: float = R_WIN) -> np.ndarray:
 
 
 def smear_lines(F: np.ndarray, labels: np.ndarray, d: int, C: int, alpha: float = ALPHA, p: int = P_ORDER,
-                c: float = C_WIN, r: float = R_WIN) -> np.ndarray:
+                c: float = C_WIN, r: float = R_WIN, fp32: bool = False) -> np.ndarray:
     """Eq. q on every line (last axis) of F [..., nlines, N] with the region
-    labels of those lines [nlines, N]."""
+    labels of those lines [nlines, N] (fp32: the filter's FP32 emulation,
+    see oracle.filter.filter_lines)."""
     F = np.asarray(F, np.float64)
-    Ft = flt.filter_lines(F, d, C, alpha, p)
+    Ft = flt.filter_lines(F, d, C, alpha, p, fp32)
     w = np.stack([window(lab, c, r) for lab in np.asarray(labels)])
     return w * Ft + (1.0 - w) * F
 
 
 def smear_state_patch(e: np.ndarray, labels: np.ndarray, d: int, C1: int, C2: int, gamma: float,
-                      alpha: float = ALPHA, p: int = P_ORDER, c: float = C_WIN, r: float = R_WIN) -> np.ndarray:
+                      alpha: float = ALPHA, p: int = P_ORDER, c: float = C_WIN, r: float = R_WIN,
+                      fp32: bool = False) -> np.ndarray:
     """Smearing of one patch's state [4, n2, n1] with labels [n2, n1]: along
     q^1 (rows), then along q^2 (columns) of the result; E rebuilt."""
     e = np.asarray(e, np.float64)
     q = np.stack([e[0], e[1], e[2], flt.theta_of(e, gamma)])
-    q = smear_lines(q, labels, d, C1, alpha, p, c, r)
-    qt = smear_lines(np.swapaxes(q, -1, -2), np.asarray(labels).T, d, C2, alpha, p, c, r)
+    q = smear_lines(q, labels, d, C1, alpha, p, c, r, fp32)
+    qt = smear_lines(np.swapaxes(q, -1, -2), np.asarray(labels).T, d, C2, alpha, p, c, r, fp32)
     q = np.swapaxes(qt, -1, -2)
     return np.stack([q[0], q[1], q[2], flt.energy_of(q[0], q[1], q[2], q[3], gamma)])
 
 
 def smear_state(e: np.ndarray, labels: np.ndarray, ps, gamma: float, alpha: float = ALPHA, p: int = P_ORDER,
-                c: float = C_WIN, r: float = R_WIN) -> np.ndarray:
+                c: float = C_WIN, r: float = R_WIN, fp32: bool = False) -> np.ndarray:
     """Smearing of a multi-patch state [4, plane] with region labels [plane]
     (every patch on its own grid; padding between patches kept)."""
     out = np.array(e, np.float64, copy=True)
@@ -110,5 +112,5 @@ def smear_state(e: np.ndarray, labels: np.ndarray, ps, gamma: float, alpha: floa
         src = ps.view(np.asarray(e, np.float64), k)
         lab = ps.view(np.asarray(labels), k)
         ps.view(out, k)[...] = smear_state_patch(src, lab, ps.d, int(ps.C1[k]), int(ps.C2[k]), gamma,
-                                                 alpha, p, c, r)
+                                                 alpha, p, c, r, fp32)
     return out

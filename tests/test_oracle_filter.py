@@ -155,3 +155,22 @@ def test_state_filter_vjp_central_differences():
         fd = np.sum((fp - fm) * eb) / (2 * h)
         an = np.sum(g * de)
         assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_fp32_emulation_is_rounding_only():
+    """The FP32 emulation (used for parity bars, not a method) differs from
+    the FP64 filter by single-precision rounding on smooth lines, and by
+    ~eps32 times the continuation tail for a step that sits at a line end
+    (the tail is then thousands of times the step)."""
+    rng = np.random.default_rng(6)
+    from oracle import fcgram
+    import synth
+    F = synth.random_lines(rng, 4, 150)
+    a = flt.filter_lines(F, 5, 27, ALPHA, 2)
+    b = flt.filter_lines(F, 5, 27, ALPHA, 2, fp32=True)
+    assert 0 < np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
+    step = np.zeros(150)
+    step[-3:] = 1.0
+    big = np.abs(flt.filter_lines(step, 5, 27, ALPHA, 2) - flt.filter_lines(step, 5, 27, ALPHA, 2, fp32=True)).max()
+    amp = np.abs(fcgram.extend(step, fcgram.continuation_matrix(5, 27))).max()   # the tail, ~2.5e3
+    assert amp > 1e3 and 1e-8 * amp < big < 1e-6 * amp
