@@ -129,7 +129,7 @@ fcsd_status fcsd_set_tune(fcsd_set* set, const int lds_budget[3], const int thre
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
 enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3, FCSD_WS_STEP_ADJ = 4,
-       FCSD_WS_FILTER_ADJ = 5 };
+       FCSD_WS_FILTER_ADJ = 5, FCSD_WS_SMEAR = 6 };
 fcsd_status fcsd_workspace_size(const fcsd_set* set, int op, size_t* bytes);
 
 /* ---- FC-Gram line operators (Sec. 2.2) --------------------------------- */
@@ -174,6 +174,26 @@ fcsd_status fcsd_filter(fcsd_ctx* ctx, const fcsd_set* set, const float* u, floa
  * FCSD_WS_FILTER_ADJ) bytes (the filtered state is recomputed there). */
 fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* out_bar,
                             float* u_bar, int64_t plane, float gamma, void* ws, size_t ws_bytes);
+
+/* Localized discontinuity-smearing of initial data (paper Sec. 4.3.2, eqs.
+ * q and qf), applied once before time stepping.  region: [plane] labels,
+ * one per point; the initial data is taken as discontinuous between two
+ * line neighbours whose labels differ (at the midpoint between them).
+ * Along q1 lines, then along q2 lines of the result, each of rho, rho u,
+ * rho v and theta = p / rho becomes w F~ + (1 - w) F, with F~ the line
+ * filtered by eq. filtering with (alpha, p) (the paper: 10, 2) and w the
+ * window of eq. qf in grid units of the line (the paper: c = 18, r = 9):
+ * 1 within c/2 of a discontinuity, cos^2(pi (s - c/2) / (2 r)) up to
+ * c/2 + r, 0 beyond; discontinuities closer than c + 2 r share one window
+ * that is 1 between them.  E is rebuilt (eq. perfect_gas_T) everywhere, so
+ * away from discontinuities it changes by rounding only; the other fields
+ * of lines without a discontinuity keep their values.  u, out: [4][plane]
+ * (out may equal u);
+ * ws: fcsd_workspace_size(FCSD_WS_SMEAR) bytes (the two window planes).
+ * At most 65535 patches. */
+fcsd_status fcsd_smear(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const uint8_t* region, float* out,
+                       int64_t plane, float gamma, double alpha, int p, double c, double r, void* ws,
+                       size_t ws_bytes);
 
 /* FC derivative d/dq^dir of nf fields (eq. fc_der): continuation, FFT of
  * length L, multiplication by 2 pi i k / beta (beta = L h, h = 1/(N-1);

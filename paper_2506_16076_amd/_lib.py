@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcsdnn.so")
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EHIP", 5: "EUNSUPPORTED", 6: "ENONFINITE"}
-WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ, WS_FILTER_ADJ = 0, 1, 2, 3, 4, 5
+WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR = 0, 1, 2, 3, 4, 5, 6
 LAYOUT_ROWS, LAYOUT_B8X4 = 0, 1
 
 
@@ -95,6 +95,8 @@ def lib():
             "fcsd_set_tune": [vp, P(i32), P(i32), i32],
             "fcsd_set_filter": [vp, ctypes.c_double, i32],
             "fcsd_filter": [vp, vp, vp, vp, i64, f32],
+            "fcsd_smear": [vp, vp, vp, vp, vp, i64, f32, ctypes.c_double, i32, ctypes.c_double, ctypes.c_double,
+                           vp, sz],
             "fcsd_filter_adj": [vp, vp, vp, vp, vp, i64, f32, vp, sz],
             "fcsd_workspace_size": [vp, i32, P(sz)],
             "fcsd_ext_size": [vp, i32, P(i64)],
@@ -139,7 +141,7 @@ def lib():
 # the names every header declaration exports (checked by the CPU tests)
 EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_last_error",
            "fcsd_ctx_stream", "fcsd_ctx_sync", "fcsd_set_create", "fcsd_set_destroy", "fcsd_set_tune",
-           "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj",
+           "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj", "fcsd_smear",
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
            "rk_stage_adj", "fcsd_cfl_dt", "sdnn_infer", "av_viscosity", "av_viscosity_adj",

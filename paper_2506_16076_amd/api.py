@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from ._lib import (LAYOUT_B8X4, LAYOUT_ROWS, RECORD_PLANES, FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP,
-                   WS_STEP_ADJ, WS_FILTER_ADJ, blocked_layout, layout_index, lib, patch_descs)
+                   WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR, blocked_layout, layout_index, lib, patch_descs)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -314,6 +314,17 @@ def fcsd_filter(s, u, out, gamma=1.4):
     be u."""
     _chk(u, numel=4 * s.plane), _chk(out, numel=4 * s.plane)
     _call(s, "fcsd_filter", _p(u), _p(out), s.plane, float(gamma))
+
+
+def fcsd_smear(s, u, region, out, gamma=1.4, alpha=10.0, p=2, c=18.0, r=9.0):
+    """Localized smearing of discontinuous initial data (once, before the
+    first step): `region` is a uint8 label plane (discontinuities between
+    line neighbours with different labels); out may be u."""
+    _chk(u, numel=4 * s.plane), _chk(out, numel=4 * s.plane)
+    _chk(region, torch.uint8, s.plane, name="region")
+    ws = s.workspace(WS_SMEAR)
+    _call(s, "fcsd_smear", _p(u), _p(region), _p(out), s.plane, float(gamma), float(alpha), int(p), float(c),
+          float(r), _p(ws), ws.numel() * 4)
 
 
 def fcsd_filter_adj(s, u, out_bar, u_bar, gamma=1.4):

@@ -84,6 +84,10 @@ struct fcsd_set {
   int filter_on = 0;
   double filter_alpha = 0.0;
   int filter_p = 0;
+  float2* d_ks = nullptr;                 // initial-data smearing filter factors (fcsd_smear)
+  int* d_ksoff[2] = {nullptr, nullptr};   // per direction and plan: offset of the plan's factors
+  double ks_alpha = -1.0;
+  int ks_p = -1;
   double* d_aq = nullptr;
   double* d_dq = nullptr;
   PatchDev* d_patches = nullptr;
@@ -207,6 +211,7 @@ size_t ws_planes(const fcsd_set* s, int op) {
     case FCSD_WS_RHS_ADJ: return 24;
     case FCSD_WS_STEP_ADJ: return kStepAdjPlanes;
     case FCSD_WS_FILTER_ADJ: return 8;
+    case FCSD_WS_SMEAR: return 2;
     default: return 0;
   }
 }
@@ -618,6 +623,9 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_tw);
   hipFree(s->d_km);
   hipFree(s->d_kf);
+  hipFree(s->d_ks);
+  hipFree(s->d_ksoff[0]);
+  hipFree(s->d_ksoff[1]);
   hipFree(s->d_aq);
   hipFree(s->d_dq);
   hipFree(s->d_patches);
@@ -704,7 +712,7 @@ extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
 }
 
 extern "C" fcsd_status fcsd_workspace_size(const fcsd_set* s, int op, size_t* bytes) {
-  if (!s || !bytes || op < 0 || op > FCSD_WS_FILTER_ADJ) return FCSD_EINVAL;
+  if (!s || !bytes || op < 0 || op > FCSD_WS_SMEAR) return FCSD_EINVAL;
   *bytes = ws_bytes_of(s, op);
   return FCSD_OK;
 }
@@ -1291,6 +1299,77 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   ms->graphs.push_back(g);
   HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
   return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_smear(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const uint8_t* region,
+                                  float* out, int64_t plane, float gamma, double alpha, int p, double c, double r,
+                                  void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !region || !out || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_smear: null argument");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha) || p < 2 || p > 64 || p % 2)
+    return fail(ctx, FCSD_EINVAL, "fcsd_smear: need alpha >= 0 finite and an even p in [2, 64]");
+  if (!(c >= 0.0) || !(r > 0.0) || !(c / 2 + r <= 1e6))
+    return fail(ctx, FCSD_EINVAL, "fcsd_smear: need c >= 0, r > 0 and c/2 + r <= 1e6 grid spacings");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_SMEAR)) return fail(ctx, FCSD_EINVAL, "fcsd_smear: workspace too small");
+  if (s->npatch > 65535) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_smear: more than 65535 patches");
+  fcsd_set* ms = const_cast<fcsd_set*>(s);
+  if (!ms->d_ks || ms->ks_alpha != alpha || ms->ks_p != p) {
+    // factors of every distinct extended length, offsets per direction and plan
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<float2> ks;
+    std::map<int, int> at_L;
+    std::vector<int> off[2];
+    for (int dir = 0; dir < 2; ++dir)
+      for (const PlanDev& P : s->dir[dir].plans) {
+        if (!at_L.count(P.L)) {
+          at_L[P.L] = (int)ks.size();
+          std::vector<float> t(2 * P.L);
+          fcsd_host_fmul(P.L, P.nst, P.rad, alpha, p, t.data());
+          for (int n = 0; n < P.L; ++n) ks.push_back(make_float2(t[2 * n], t[2 * n + 1]));
+        }
+        off[dir].push_back(at_L[P.L]);
+      }
+    (void)hipFree(ms->d_ks);
+    (void)hipFree(ms->d_ksoff[0]);
+    (void)hipFree(ms->d_ksoff[1]);
+    ms->d_ks = nullptr;
+    ms->d_ksoff[0] = ms->d_ksoff[1] = nullptr;
+    ms->ks_alpha = -1.0;
+    fcsd_status r2;
+    if ((r2 = upload(ctx, &ms->d_ks, ks)) || (r2 = upload(ctx, &ms->d_ksoff[0], off[0])) ||
+        (r2 = upload(ctx, &ms->d_ksoff[1], off[1])))
+      return r2;
+    ms->ks_alpha = alpha;
+    ms->ks_p = p;
+  }
+  int max1 = 0, max2 = 0;
+  for (const fcsd_patch_desc& q : s->desc) {
+    max1 = std::max(max1, q.n1);
+    max2 = std::max(max2, q.n2);
+  }
+  float* w1 = (float*)ws;
+  float* w2 = w1 + s->plane;
+  const float c2 = (float)(c / 2), rf = (float)r;
+  hipLaunchKernelGGL(k_smear_window<1>, dim3((unsigned)((max2 + kBlock - 1) / kBlock), (unsigned)s->npatch),
+                     dim3(kBlock), 0, ctx->stream, s->d_patches, region, w1, c2, rf);
+  hipLaunchKernelGGL(k_smear_window<2>, dim3((unsigned)((max1 + kBlock - 1) / kBlock), (unsigned)s->npatch),
+                     dim3(kBlock), 0, ctx->stream, s->d_patches, region, w2, c2, rf);
+  if ((st = launch_check(ctx, "smear window"))) return st;
+  PassArgs a = base_args(s, 1);
+  a.gamma = gamma;
+  a.in = u;
+  a.out = out;
+  a.kf = ms->d_ks;
+  a.koff = ms->d_ksoff[0];
+  a.win = w1;
+  if ((st = launch_lines(s, 1, k_smear<1>, a, -1, 2))) return st;
+  PassArgs b = a;
+  b.plans = s->dir[1].d_plans;
+  b.in = out;
+  b.koff = ms->d_ksoff[1];
+  b.win = w2;
+  return launch_lines(s, 2, k_smear<2>, b, -1, 2);
 }
 
 extern "C" fcsd_status fcsd_filter(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float* out, int64_t plane,

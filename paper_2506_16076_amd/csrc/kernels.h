@@ -24,6 +24,8 @@ struct PassArgs {
   const float2* tw;
   const float2* km;
   const float2* kf;           // spectral filter factors (null until configured)
+  const int* koff;            // per plan: offset of its factors in kf (when not the plan's own)
+  const float* win;           // blending window plane (initial-data smearing)
   const double* aq;
   const double* dq;
   int d;
@@ -411,6 +413,68 @@ __global__ void FCSD_LINE_BOUNDS k_filter(PassArgs a) {
     at(out + 2 * pl, g) = q.x;
     at(out + 3 * pl, g) = DIR == 1 ? q.y : p.x * q.y / g1 + 0.5f * (p.y * p.y + q.x * q.x) / p.x;
   });
+}
+
+// Localized smearing of initial data (paper Sec. 4.3.2, eq. q) along DIR:
+// every line is filtered as in k_filter, with the smearing filter's factors
+// (table a.kf at offset a.koff[plan]), and blended with its unfiltered values
+// by the window plane a.win, F + w (F~ - F), for rho, rho u, rho v and theta.
+// DIR 1 reads the state and writes theta in place of E; DIR 2 reads that
+// and writes the state with E rebuilt (eq. perfect_gas_T).  in may equal out.
+template <int DIR>
+__global__ void FCSD_LINE_BOUNDS k_smear(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T2 = T;
+  T2.nl = 2 * T.nl;
+  const LineCtx X = line_setup(lds_z, T2, P, a.tw, a.kf, a.koff[T.plan]);
+  float2* __restrict__ z = X.z;
+  const int nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  const float g1 = a.gamma - 1.0f;
+  const float* in = a.in + M.base;
+  const float* win = a.win + M.base;
+  float* out = a.out + M.base;
+  float2* __restrict__ zb = z + nl;
+  auto theta = [&](float4 v) { return DIR == 1 ? g1 * (v.w - 0.5f * (v.y * v.y + v.z * v.z) / v.x) / v.x : v.w; };
+  __syncthreads();
+  walk_b<kEpiBatch>(
+      M.w, [&](unsigned g) { return make_float4(at(in, g), at(in + pl, g), at(in + 2 * pl, g), at(in + 3 * pl, g)); },
+      [&](unsigned, unsigned l, float4 v) {
+        at(z, l) = make_float2(v.x, v.y);
+        at(zb, l) = make_float2(v.z, theta(v));
+      });
+  __syncthreads();
+  if (!P.periodic) {
+    fc_tail(X, P, a.aq + P.aq, a.d);
+    __syncthreads();
+  }
+  fft_apply<false>(X, Pg, P);
+  struct In5 {
+    float4 v;
+    float w;
+  };
+  walk_b<kEpiBatch>(
+      M.w,
+      [&](unsigned g) {
+        In5 q;
+        q.v = make_float4(at(in, g), at(in + pl, g), at(in + 2 * pl, g), at(in + 3 * pl, g));
+        q.w = at(win, g);
+        return q;
+      },
+      [&](unsigned g, unsigned l, const In5& q) {
+        const float2 p = at(z, l), r = at(zb, l);
+        const float th = theta(q.v);
+        const float f0 = q.v.x + q.w * (p.x - q.v.x), f1 = q.v.y + q.w * (p.y - q.v.y);
+        const float f2 = q.v.z + q.w * (r.x - q.v.z), f3 = th + q.w * (r.y - th);
+        at(out, g) = f0;
+        at(out + pl, g) = f1;
+        at(out + 2 * pl, g) = f2;
+        at(out + 3 * pl, g) = DIR == 1 ? f3 : f0 * f3 / g1 + 0.5f * (f1 * f1 + f2 * f2) / f0;
+      });
 }
 
 // Reverse mode of k_filter along DIR (transpose E^T S R^T of each line

@@ -31,6 +31,53 @@ __device__ __forceinline__ int pstore(const PatchDev& P) {
   return P.nb1 == 0 ? P.n1 * P.n2 : (P.nb1 << 3) * ((P.n2 + 3) & ~3);
 }
 
+// Blending window of the initial-data smearing (paper Sec. 4.3.2, eq. qf)
+// along DIR, one thread per line of one patch (blockIdx.y): a discontinuity
+// sits between neighbours whose region labels differ.  A forward sweep
+// stores each point's distance to the nearest discontinuity on its left, a
+// backward sweep combines it with the one on the right: 1 between two
+// discontinuities closer than c + 2r (one window group), else the rise
+// 1 / cos^2(pi (s - c/2) / (2r)) / 0 of the nearer one (c2 = c/2).
+template <int DIR>
+__global__ void __launch_bounds__(kBlock) k_smear_window(const PatchDev* __restrict__ pd,
+                                                          const uint8_t* __restrict__ lab, float* __restrict__ win,
+                                                          float c2, float r) {
+  const PatchDev P = pd[blockIdx.y];
+  const int nlines = DIR == 1 ? P.n2 : P.n1;
+  const int N = DIR == 1 ? P.n1 : P.n2;
+  const int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= nlines) return;
+  auto idx = [&](int t) { return DIR == 1 ? pidx(P, t, line) : pidx(P, line, t); };
+  const float far = 1e30f;
+  float zl = -far;
+  unsigned prev = lab[idx(0)];
+  for (int t = 0; t < N; ++t) {
+    const long long k = idx(t);
+    const unsigned cur = lab[k];
+    if (cur != prev) zl = (float)t - 0.5f;
+    prev = cur;
+    win[k] = (float)t - zl;
+  }
+  float zr = far;
+  unsigned next = lab[idx(N - 1)];
+  for (int t = N - 1; t >= 0; --t) {
+    const long long k = idx(t);
+    const unsigned cur = lab[k];
+    if (cur != next) zr = (float)t + 0.5f;
+    next = cur;
+    const float dl = win[k], dr = zr - (float)t;
+    float w;
+    if (dl + dr < 2.0f * (c2 + r)) {
+      w = 1.0f;
+    } else {
+      const float s = fminf(dl, dr);
+      const float cs = cosf(3.14159265358979f * (s - c2) / (2.0f * r));
+      w = s < c2 ? 1.0f : (s > c2 + r ? 0.0f : cs * cs);
+    }
+    win[k] = w;
+  }
+}
+
 // point (i, j) stored at storage index k of the patch; false for padding
 __device__ __forceinline__ bool pdecode(const PatchDev& P, int k, int& i, int& j) {
   if (P.nb1 == 0) {
