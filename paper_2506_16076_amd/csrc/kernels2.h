@@ -613,7 +613,8 @@ __global__ void __launch_bounds__(kBlock) k_lat_conv(const ChunkDev* lchunks, in
       if (dir == 0) {
         gg = G + l;
         if (Lt.periodic) {
-          gg = (gg % Lt.W + Lt.W) % Lt.W;
+          // |l| <= 8 < W: one wrap at most (no integer division per tap)
+          gg = gg < 0 ? gg + Lt.W : (gg >= Lt.W ? gg - Lt.W : gg);
         } else if (gg < 0 || gg >= Lt.W) {
           continue;
         }
@@ -738,39 +739,45 @@ __global__ void __launch_bounds__(kBlock) k_fill(float* p, float v, long long n)
 __global__ void __launch_bounds__(kBlock) k_dt_reduce(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
                                                       const float* u, const float* mu, long long pl,
                                                       float gam, unsigned* smax, unsigned* mmax) {
-  __shared__ float rs[kBlock / 64], rm[kBlock / 64];
-  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
-    const PatchDev P = patches[ck.patch];
-    const int k = ck.start + threadIdx.x;
-    float s = 0.f, m = 0.f;
-    int i, j;
-    if (k < pstore(P) && pdecode(P, k, i, j)) {
-      const long long g = P.off + k;
-      float rho, vx, vy, p;
-      prim(u, pl, g, gam, rho, vx, vy, p);
-      s = fabsf(vx) + fabsf(vy) + sqrtf(gam * p / rho);
-      if (mu) m = mu[g];
-    }
+  // a block takes a contiguous run of chunks (chunks are ordered by patch)
+  // and keeps per-thread maxima until the patch changes: a wave posts its
+  // maxima with two atomics only then and at the end, and the chunk loop
+  // has no barrier
+  const int per = (nchunks + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int c0 = (int)blockIdx.x * per, c1 = min(c0 + per, nchunks);
+  auto post = [&](int patch, float s, float m) {
     for (int o = 32; o > 0; o >>= 1) {
       s = fmaxf(s, __shfl_xor(s, o));
       m = fmaxf(m, __shfl_xor(m, o));
     }
     if ((threadIdx.x & 63) == 0) {
-      rs[threadIdx.x >> 6] = s;
-      rm[threadIdx.x >> 6] = m;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-        s = fmaxf(s, rs[w]);
-        m = fmaxf(m, rm[w]);
-      }
       // non-negative floats order like their bit patterns
-      atomicMax(smax + ck.patch, __float_as_uint(fmaxf(s, 0.f)));
-      atomicMax(mmax + ck.patch, __float_as_uint(fmaxf(m, 0.f)));
+      atomicMax(smax + patch, __float_as_uint(fmaxf(s, 0.f)));
+      atomicMax(mmax + patch, __float_as_uint(fmaxf(m, 0.f)));
     }
-    __syncthreads();  // rs, rm are reused by the next chunk
-  });
+  };
+  if (c0 >= c1) return;
+  int cur = chunks[c0].patch;
+  float s = 0.f, m = 0.f;
+  for (int c = c0; c < c1; ++c) {
+    const ChunkDev ck = chunks[c];
+    if (ck.patch != cur) {  // the same for every thread of the block
+      post(cur, s, m);
+      s = m = 0.f;
+      cur = ck.patch;
+    }
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k < pstore(P) && pdecode(P, k, i, j)) {
+      const long long g = P.off + k;
+      float rho, vx, vy, p;
+      prim(u, pl, g, gam, rho, vx, vy, p);
+      s = fmaxf(s, fabsf(vx) + fabsf(vy) + sqrtf(gam * p / rho));
+      if (mu) m = fmaxf(m, mu[g]);
+    }
+  }
+  post(cur, s, m);
 }
 
 __global__ void __launch_bounds__(kBlock) k_dt_final(const PatchDev* patches, int np, const unsigned* smax,
