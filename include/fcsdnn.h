@@ -361,8 +361,9 @@ typedef struct {
 /* Planes of a step record: 0..19 the five glued stage inputs [5][4][plane]
  * (stage 0 = the state after glue, viscosity and filter), 20 mu, 21 the 7x7
  * maximisers as int32 (with classes), 22..25 the glued state before the
- * filter (with a->filter). */
-#define FCSD_RECORD_PLANES 26
+ * filter (with a->filter), 26..45 and 46..65 the q1 and q2 FC derivatives
+ * of e - e_ref of every stage input [5][4][plane] (with a viscosity). */
+#define FCSD_RECORD_PLANES 66
 
 /* One full time step (Algorithm 1): glue, network classes and viscosity
  * (when w != NULL), spectral filter and glue (when a->filter), step size,

@@ -70,7 +70,7 @@ class StepArgs(ctypes.Structure):
                 ("filter", ctypes.c_int), ("record", ctypes.c_void_p)]
 
 
-RECORD_PLANES = 26  # planes of a step record (stage inputs, mu, maximisers, pre-filter state)
+RECORD_PLANES = 66  # planes of a step record (stage inputs, mu, maximisers, pre-filter state, derivatives)
 
 
 _lib = None

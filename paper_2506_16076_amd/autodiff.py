@@ -11,12 +11,13 @@ branch that was taken, like the reverse mode of any piecewise map):
   * backward: segments are processed last to first; a segment is re-run
     from its checkpoint with the recorded decisions (fcsd_step replay,
     bit-identical to the forward run) writing a step record per step (its
-    glued stage inputs, viscosity, maximisers and pre-filter state), then
+    glued stage inputs, viscosity, maximisers, pre-filter state and the FC
+    derivatives of the stage inputs that the reverse mode uses), then
     reversed step by step from the records, so no step is run forward a
     third time.  With ``record=False`` the replay keeps only each step's
     input and fcsd_step_adj recomputes the step from it.
 
-Memory: nsteps/every checkpoints + ``every`` step records (26 planes each;
+Memory: nsteps/every checkpoints + ``every`` step records (66 planes each;
 4 with record=False) + one int8 plane and one float per step, instead of
 all nsteps states.
 

@@ -801,8 +801,9 @@ RhsWs carve_rhs(const fcsd_set* s, void* ws) {
 fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric, const float* mu,
                        const float ref[4], float gamma, int flux, int outmode, float* rhs, int stage,
                        const float* u0, float* acc, float* uout, const float* dtp, void* ws, int patch,
-                       unsigned passes = 15u) {
+                       unsigned passes = 15u, float* d1e_rec = nullptr, float* d2e_rec = nullptr) {
   RhsWs W = carve_rhs(s, ws);
+  if (d1e_rec) W.d1e = d1e_rec;  // q1 derivatives of e - e_ref kept for the reverse mode
   PassArgs a = base_args(s, 1);
   set_ref(a, ref, gamma);
   a.u = u;
@@ -832,6 +833,7 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
     PassArgs b = a;
     b.plans = s->dir[1].d_plans;
     b.mode = flux;
+    b.d2out = d2e_rec;
     if (passes & 2u)
       if ((st = launch_lines(s, 2, k_passB1, b, patch, 2))) return st;
   }
@@ -1210,6 +1212,11 @@ fcsd_status filter_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* e, co
   return launch_lines(s, 1, k_filter_adj<1>, b, -1, 2);
 }
 
+// planes of a step record after the stage inputs, mu, the maximisers and the
+// pre-filter state: the q1 and q2 derivatives of e - e_ref of each stage input
+constexpr long long kRecD1 = 26, kRecD2 = 46;
+static_assert(kRecD2 + 20 == FCSD_RECORD_PLANES, "record layout");
+
 fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a, void* ws) {
   const long long pl = s->plane;
   float* w = (float*)ws;
@@ -1253,8 +1260,10 @@ fcsd_status step_body(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_step_args* a,
   for (int k = 0; k < 5; ++k) {
     if (k > 0)
       if ((st = glue_impl(ctx, s, const_cast<float*>(ins[k]), a->dirichlet_mask, a->dirichlet_state))) return st;
+    float* d1r = rec && a->mu ? rec + kRecD1 * pl + k * n4 : nullptr;
+    float* d2r = rec && a->mu ? rec + kRecD2 * pl + k * n4 : nullptr;
     st = rhs_passes(ctx, s, ins[k], a->metric, a->mu, a->ref, a->gamma, a->mu ? FLUX_FULL : FLUX_INVISCID, MODE_RK,
-                    nullptr, k, a->u, ACC, outs[k], a->dt_dev, rhs_ws, -1);
+                    nullptr, k, a->u, ACC, outs[k], a->dt_dev, rhs_ws, -1, 15u, d1r, d2r);
     if (st) return st;
   }
   return FCSD_OK;
@@ -1395,17 +1404,19 @@ extern "C" fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* s, const f
 
 // ======================================================================== reverse mode of the RHS
 
-extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
-                                    const float* mu, const float ref[4], float gamma, const float* rhs_bar,
-                                    float* u_bar, float* mu_bar, int64_t plane, void* ws, size_t ws_bytes) {
-  fcsd_status st = check_set(ctx, s, plane);
-  if (st) return st;
-  if (!u || !metric || !ref || !rhs_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: null argument");
-  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: workspace too small");
+namespace {
+
+// Reverse mode of the right-hand side; given1 / given2 (nullable): the q1
+// and q2 derivatives of e - e_ref at u, recorded by the forward step, which
+// are then not recomputed.
+fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric, const float* mu,
+                         const float ref[4], float gamma, const float* rhs_bar, float* u_bar, float* mu_bar,
+                         void* ws, const float* given1, const float* given2) {
+  fcsd_status st;
   const long long pl = s->plane;
   float* w = (float*)ws;
-  float* d1e = w;
-  float* d2e = w + 4 * pl;
+  const float* d1e = given1 ? given1 : w;
+  const float* d2e = given2 ? given2 : w + 4 * pl;
   float* Hb = w + 8 * pl;
   float* G1 = w + 16 * pl;
   float* G2 = w + 20 * pl;
@@ -1418,12 +1429,16 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
   a.mode = FLUX_FULL;
   if (visc) {
     PassArgs b = a;
-    b.out = d1e;
-    b.plans = s->dir[0].d_plans;
-    if ((st = launch_lines(s, 1, k_dev_diff<1>, b))) return st;
-    b.out = d2e;
-    b.plans = s->dir[1].d_plans;
-    if ((st = launch_lines(s, 2, k_dev_diff<2>, b))) return st;
+    if (!given1) {
+      b.out = w;
+      b.plans = s->dir[0].d_plans;
+      if ((st = launch_lines(s, 1, k_dev_diff<1>, b))) return st;
+    }
+    if (!given2) {
+      b.out = w + 4 * pl;
+      b.plans = s->dir[1].d_plans;
+      if ((st = launch_lines(s, 2, k_dev_diff<2>, b))) return st;
+    }
   }
   {
     const DirPlan& D = s->dir[0];
@@ -1445,10 +1460,22 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
   }
   if (visc) {
     // u_bar += D2^T G2 + D1^T G1 (deviation form: the constant reference has no adjoint)
-    if ((st = fc_diff_adj(ctx, s, 2, 4, G2, u_bar, plane))) return st;
-    if ((st = fc_diff_adj(ctx, s, 1, 4, G1, u_bar, plane))) return st;
+    if ((st = fc_diff_adj(ctx, s, 2, 4, G2, u_bar, pl))) return st;
+    if ((st = fc_diff_adj(ctx, s, 1, 4, G1, u_bar, pl))) return st;
   }
   return FCSD_OK;
+}
+
+}  // namespace
+
+extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
+                                    const float* mu, const float ref[4], float gamma, const float* rhs_bar,
+                                    float* u_bar, float* mu_bar, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !metric || !ref || !rhs_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: workspace too small");
+  return rhs_adj_impl(ctx, s, u, metric, mu, ref, gamma, rhs_bar, u_bar, mu_bar, ws, nullptr, nullptr);
 }
 
 // ======================================================================== reverse mode of a step
@@ -1525,8 +1552,9 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
     hipLaunchKernelGGL(k_rk_adj, dim3(b4), dim3(kBlock), 0, sm, k, a->dt_dev, (const float*)yb, U0B, uib, ACCB, RB,
                        n4);
     if ((st = launch_check(ctx, "step_adj rk"))) return st;
-    if ((st = fcsd_rhs_adj(ctx, s, stg(k), a->metric, mu, a->ref, a->gamma, RB, tgt, mu ? MUB : nullptr, plane, RWS,
-                           24 * (size_t)pl * sizeof(float))))
+    const float* g1 = have && mu ? a->record + kRecD1 * pl + k * n4 : nullptr;
+    const float* g2 = have && mu ? a->record + kRecD2 * pl + k * n4 : nullptr;
+    if ((st = rhs_adj_impl(ctx, s, stg(k), a->metric, mu, a->ref, a->gamma, RB, tgt, mu ? MUB : nullptr, RWS, g1, g2)))
       return st;
     if (k > 0) {
       if ((st = glue_adj_impl(ctx, s, uib, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;

@@ -26,6 +26,7 @@ struct PassArgs {
   const float2* kf;           // spectral filter factors (null until configured)
   const int* koff;            // per plan: offset of its factors in kf (when not the plan's own)
   const float* win;           // blending window plane (initial-data smearing)
+  float* d2out;               // pass B1: also store d2 (e - e_ref) here when not null
   const double* aq;
   const double* dq;
   int d;
@@ -345,12 +346,17 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
   const int flux = a.mode;
   const HSrc hs = h_sources(a, M.base, flux);
   float* H = a.H + M.base;
+  float* d2o = a.d2out ? a.d2out + M.base : nullptr;
   const float2* zb = z + nl;
   walk_b<kEpiBatchH>(
       M.w, [&](unsigned g) { return load_H4_inputs(hs, g); },
       [&](unsigned g, unsigned l, const HIn4& q) {
         const float2 za = at(z, l), zq = at(zb, l);
         const float d2[4] = {za.x, za.y, zq.x, zq.y};
+        if (d2o) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) at(d2o + k * pl, g) = d2[k];
+        }
         float dF[4] = {0.f, 0.f, 0.f, 0.f}, dG[4] = {0.f, 0.f, 0.f, 0.f};
         if (flux != FLUX_VISC) dev_flux(q.e, a.eref, a.pref, a.gamma, dF, dG);
 #pragma unroll
