@@ -19,20 +19,29 @@ Readings for the index-aligned annulus used by the synthetic workloads:
     free (no wall model on this path);
   * the state is glued once at the start of each step (before mu and dt) and
     on every later stage input.
+
+Patch sets that carry patch maps (``geom``) and are not index-aligned take
+their communication from the inter-patch interpolation of Sec. 3.4.1
+(oracle.interp) instead.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from oracle import av, euler, filter as spectral_filter, rk
+from oracle import av, euler, filter as spectral_filter, interp, rk
 
 NF = 5
 OVL = 19
 
 
 def glue(e, ps, mach, gamma=1.4):
-    """In-place fringe copy and Dirichlet overwrite on a [4, plane] state."""
+    """In-place fringe copy (or interpolation) and Dirichlet overwrite on a
+    [4, plane] state."""
     if ps.nsec == 0:
+        if ps.geom is not None:
+            if getattr(ps, "_interp_table", None) is None:
+                ps._interp_table = interp.build(ps)
+            interp.interpolate(e, ps, ps._interp_table)
         return e
     S, K = ps.nsec, ps.nshell
     for k in range(K):

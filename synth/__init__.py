@@ -70,6 +70,10 @@ class PatchSet:
     nsec: int = 0
     nshell: int = 0
     dirichlet: Optional[np.ndarray] = None   # uint8 [plane]: freestream-overwrite points
+    # patch maps for inter-patch interpolation (None: not described)
+    # float64 [P, 5]: kind (0 Cartesian x = a0 + i da, y = b0 + j db;
+    # 1 polar theta = a0 + i da, r = b0 + j db), a0, da, b0, db
+    geom: Optional[np.ndarray] = None
 
     @property
     def npatch(self) -> int:
@@ -175,6 +179,37 @@ def uneven_sectors(npatch: int, nmin: int, nmax: int, seed: int, d: int = 5,
     span = (2 * np.pi / 16) * 255 / 237
     specs = [(t0[p], span / (n1[p] - 1), 0.5, 1.5 / (n2[p] - 1)) for p in range(npatch)]
     return _polar_patches(specs, n1, n2, d, c_min)
+
+
+def overlap_pair(n: int = 48, d: int = 5, c_min: int = 27) -> PatchSet:
+    """Two overlapping patches of different kinds that are not index-aligned:
+    a Cartesian patch on [-1, 0.6] x [-0.5, 0.5] whose q1+ side (x = 0.6)
+    is an inter-patch side, and a polar sector theta in [-1, 1], r in
+    [0.3, 1.5] whose q2- side (r = 0.3) is one; each side's fringe lies
+    inside the other patch.  n x n points each."""
+    n1 = np.array([n, n], np.int32)
+    n2 = n1.copy()
+    ps = _polar_patches([(0.0, 1.0, 0.3, 1.2 / (n - 1))] * 2, n1, n2, d, c_min)
+    # patch 1: the sector
+    ht, hr = 2.0 / (n - 1), 1.2 / (n - 1)
+    sec = _polar_patches([(-1.0, ht, 0.3, hr)], n1[:1], n2[:1], d, c_min)
+    o = int(ps.off[1])
+    ps.xy[:, o:o + n * n] = sec.xy[:, :n * n]
+    ps.metric[:, o:o + n * n] = sec.metric[:, :n * n]
+    ps.htilde[1], ps.hhat[1] = sec.htilde[0], sec.hhat[0]
+    # patch 0: Cartesian
+    hx, hy = 1.6 / (n - 1), 1.0 / (n - 1)
+    X, Y = np.meshgrid(-1.0 + hx * np.arange(n), -0.5 + hy * np.arange(n))
+    ps.xy[0, :n * n] = X.ravel()
+    ps.xy[1, :n * n] = Y.ravel()
+    ps.metric[:, :n * n] = 0
+    ps.metric[0, :n * n] = 1 / 1.6
+    ps.metric[3, :n * n] = 1 / 1.0
+    ps.htilde[0], ps.hhat[0] = min(hx, hy), max(hx, hy)
+    ps.internal[0] = (0, 1, 0, 0)
+    ps.internal[1] = (0, 0, 1, 0)
+    ps.geom = np.array([[0, -1.0, hx, -0.5, hy], [1, -1.0, ht, 0.3, hr]], np.float64)
+    return ps
 
 
 def unit_square(n: int, d: int = 5, C: int = 27) -> PatchSet:
@@ -354,6 +389,19 @@ def paper_subpatches(nsec: int = 16, nshell: int = 1, seed: int = 5, mach: float
     e = mach_state(ps, mach, pert)
     return Config(f"paper-d2-{nsec}x{nshell}-101", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]),
                   mach=mach, pert=pert, mlp=mlp_weights(1000 + seed), steps=100)
+
+
+def overlap_config(n: int = 48, seed: int = 6, mach: float = 3.0) -> Config:
+    """The Cartesian / polar patch pair of overlap_pair with the Mach-3
+    freestream state and its +-1 % density perturbation and a constant
+    viscosity (the network's smoothing operator needs index-aligned
+    neighbours across inter-patch sides); no Dirichlet points."""
+    rng = np.random.default_rng(seed)
+    ps = overlap_pair(n)
+    pert = draw_perturbation(rng)
+    e = mach_state(ps, mach, pert)
+    return Config(f"overlap-pair-{n}", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]), mach=mach, pert=pert,
+                  mu_const=2e-3, steps=10)
 
 
 def random_lines(rng, nlines: int, n: int, smooth: bool = True):

@@ -1,0 +1,106 @@
+"""Pins of the oracle's inter-patch interpolation (paper Sec. 3.4.1, Remark
+overlap_cond) against facts that do not restate its code:
+
+* Neville's three-point recurrence reproduces every quadratic exactly
+  (a + b s + c s^2 at the nodes -1, 0, 1) and is the Lagrange interpolant;
+* the iterated interpolation reproduces, at every fringe point, a field that
+  is a product of quadratics in the donor's own parameters (x, y on the
+  Cartesian patch; theta, r on the sector) to rounding;
+* for a smooth field the fringe error falls like h^3 (third order of
+  quadratic interpolation): about 8x per halving of h;
+* the table: every fringe point of both patches gets a donor of the other
+  patch whose 3 x 3 stencil holds the point's preimage, no stencil point is
+  a fringe point, and a decomposition whose overlap is too thin for that is
+  refused.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import interp
+
+
+def test_neville_is_exact_on_quadratics():
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        a, b, c = rng.standard_normal(3)
+        f = lambda s: a + b * s + c * s * s
+        s = rng.uniform(-1.5, 1.5, 7)
+        got = interp.neville3(f(-1.0), f(0.0), f(1.0), s)
+        assert np.abs(got - f(s)).max() <= 1e-14 * (abs(a) + abs(b) + abs(c)) * 3
+    # Lagrange weights at s = 1/2: (-1/8, 3/4, 3/8)
+    assert abs(interp.neville3(1.0, 0.0, 0.0, 0.5) + 0.125) < 1e-16
+    assert abs(interp.neville3(0.0, 1.0, 0.0, 0.5) - 0.75) < 1e-16
+    assert abs(interp.neville3(0.0, 0.0, 1.0, 0.5) - 0.375) < 1e-16
+
+
+def _fill(ps, f_cart, f_polar):
+    e = np.zeros((1, ps.plane))
+    for p in range(ps.npatch):
+        x, y = ps.view(ps.xy, p)
+        ps.view(e, p)[0] = f_cart(x, y) if int(ps.geom[p, 0]) == 0 else f_polar(np.arctan2(y, x), np.hypot(x, y))
+    return e
+
+
+def test_quadratics_in_donor_parameters_are_reproduced():
+    ps = synth.overlap_pair(48)
+    table = interp.build(ps)
+    fc = lambda x, y: (1 + 0.3 * x - 0.7 * x * x) * (0.5 - y + 0.2 * y * y)
+    fp = lambda th, r: (0.2 + th - 0.4 * th * th) * (1.1 + 0.5 * r - 0.3 * r * r)
+    # each patch holds the field its receivers' donors interpolate: a
+    # receiver of the Cartesian patch reads the sector (fp), and back
+    e = _fill(ps, fc, fp)
+    want = e.copy()
+    for (p, i, j, q, ic, jc, s, t) in table:
+        x, y = ps.view(ps.xy, p)[:, j, i]
+        want_val = fc(x, y) if int(ps.geom[q, 0]) == 0 else fp(np.arctan2(y, x), np.hypot(x, y))
+        ps.view(want, p)[0, j, i] = want_val
+    got = interp.interpolate(e.copy(), ps, table)
+    assert np.abs(got - want).max() <= 1e-13
+
+
+def test_smooth_field_third_order():
+    f = lambda x, y: np.sin(2.1 * x + 0.7) * np.cos(1.3 * y - 0.2)
+    errs = []
+    for n in (48, 95, 189):
+        ps = synth.overlap_pair(n)
+        table = interp.build(ps)
+        e = np.zeros((1, ps.plane))
+        for p in range(ps.npatch):
+            x, y = ps.view(ps.xy, p)
+            ps.view(e, p)[0] = f(x, y)
+        exact = e.copy()
+        # perturb the fringe so only interpolated values can restore it
+        for (p, i, j, *_r) in table:
+            ps.view(e, p)[0, j, i] = 0.0
+        got = interp.interpolate(e, ps, table)
+        errs.append(np.abs(got - exact).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 2.6), (errs, rates)
+
+
+def test_table_is_a_valid_decomposition():
+    ps = synth.overlap_pair(48)
+    table = interp.build(ps)
+    masks = [interp.receivers(ps, p) for p in range(ps.npatch)]
+    assert len(table) == sum(int(m.sum()) for m in masks)
+    for (p, i, j, q, ic, jc, s, t) in table:
+        assert q != p and masks[p][j, i]
+        assert not masks[q][jc - 1:jc + 2, ic - 1:ic + 2].any()
+        assert abs(s) <= 1.0 and abs(t) <= 1.0
+        x, y = ps.view(ps.xy, p)[:, j, i]
+        xi, eta = interp.preimage(ps.geom[q], x, y)
+        assert abs(ic + s - xi) < 1e-12 and abs(jc + t - eta) < 1e-12
+
+
+def test_thin_overlap_is_refused():
+    ps = synth.overlap_pair(48)
+    # shrink the Cartesian patch's reach: its fringe now lies where the
+    # sector's stencils would touch the sector's own fringe
+    ps.geom = ps.geom.copy()
+    ps.internal[0] = (0, 1, 0, 0)
+    ps.internal[1] = (0, 0, 1, 0)
+    x0 = ps.view(ps.xy, 0)[0]
+    ps.xy[0, :x0.size] -= 0.3          # fringe of patch 0 near x = 0.3, close to r = 0.3
+    with pytest.raises(ValueError):
+        interp.build(ps)
