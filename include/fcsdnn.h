@@ -175,6 +175,34 @@ fcsd_status fcsd_filter(fcsd_ctx* ctx, const fcsd_set* set, const float* u, floa
 fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* out_bar,
                             float* u_bar, int64_t plane, float gamma, void* ws, size_t ws_bytes);
 
+/* Map of a patch's grid to the plane: kind 0 Cartesian, (x, y) = (a0 + i da,
+ * b0 + j db); kind 1 polar, (theta, r) = (a0 + i da, b0 + j db) and
+ * (x, y) = r (cos theta, sin theta). */
+typedef struct {
+  int32_t kind;
+  double a0, da, b0, db;
+} fcsd_patch_map;
+
+/* Inter-patch communication by interpolation (paper Sec. 3.4.1, Remark
+ * overlap_cond) for patches that overlap without sharing grid lines: every
+ * point within nf grid lines of an internal side (fcsd_patch_desc.internal)
+ * receives, at every glue (fcsd_glue, every stage of fcsd_step), the value
+ * interpolated from a donor patch: of the other patches whose grid holds a
+ * 3 x 3 stencil around the point's preimage (fractional indices xi, eta,
+ * min(xi, n1-1-xi, eta, n2-1-eta) >= 1), the one where that distance is
+ * largest (lower index on ties); the stencil is centred on
+ * floor(xi + 1/2), floor(eta + 1/2) moved inwards to stay on the grid; the
+ * value is iterated quadratic interpolation with Neville's recurrence in the
+ * donor's parameters, along q1 on the three rows, then along q2.  Fails
+ * with FCSD_EINVAL (and a message naming the point) when a fringe point has
+ * no donor or a donor stencil holds fringe points (the decomposition check
+ * of the Remark).  maps: npatch entries; *nrecv (nullable) receives the
+ * number of fringe points.  Not for index-aligned annulus sets (they glue
+ * by copy); sets with a table take no network viscosity (the multi-patch
+ * smoothing operator across non-aligned patches is not built) and have no
+ * reverse mode.  Host-side set-up, synchronises the context's stream. */
+fcsd_status fcsd_set_interp(fcsd_set* set, const fcsd_patch_map* maps, int nf, int64_t* nrecv);
+
 /* Localized discontinuity-smearing of initial data (paper Sec. 4.3.2, eqs.
  * q and qf), applied once before time stepping.  region: [plane] labels,
  * one per point; the initial data is taken as discontinuous between two

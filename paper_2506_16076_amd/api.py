@@ -157,6 +157,17 @@ class PatchSet:
         self.ctx.check(lib().fcsd_set_filter(self.h, float(alpha), int(p)), "fcsd_set_filter")
         self.filter_params = (float(alpha), int(p))
 
+    def set_interp(self, maps, nf: int = 5) -> int:
+        """Inter-patch interpolation of the fringe (paper Sec. 3.4.1) from
+        patch maps: rows (kind, a0, da, b0, db), kind 0 Cartesian, 1 polar.
+        Returns the number of fringe points."""
+        from ._lib import PatchMap
+        rows = np.asarray(maps, np.float64).reshape(-1, 5)
+        arr = (PatchMap * len(rows))(*[PatchMap(int(r[0]), r[1], r[2], r[3], r[4]) for r in rows])
+        n = ctypes.c_int64()
+        self.ctx.check(lib().fcsd_set_interp(self.h, arr, int(nf), ctypes.byref(n)), "fcsd_set_interp")
+        return n.value
+
     def ext_size(self, direction: int) -> int:
         v = ctypes.c_int64()
         self.ctx.check(lib().fcsd_ext_size(self.h, direction, ctypes.byref(v)), "ext_size")

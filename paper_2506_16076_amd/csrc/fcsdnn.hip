@@ -84,6 +84,8 @@ struct fcsd_set {
   int filter_on = 0;
   double filter_alpha = 0.0;
   int filter_p = 0;
+  InterpDev* d_interp = nullptr;          // inter-patch interpolation table (fcsd_set_interp)
+  int ninterp = 0;
   float2* d_ks = nullptr;                 // initial-data smearing filter factors (fcsd_smear)
   int* d_ksoff[2] = {nullptr, nullptr};   // per direction and plan: offset of the plan's factors
   double ks_alpha = -1.0;
@@ -623,6 +625,7 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_tw);
   hipFree(s->d_km);
   hipFree(s->d_kf);
+  hipFree(s->d_interp);
   hipFree(s->d_ks);
   hipFree(s->d_ksoff[0]);
   hipFree(s->d_ksoff[1]);
@@ -1077,6 +1080,9 @@ fcsd_status glue_impl(fcsd_ctx* ctx, const fcsd_set* s, float* u, const uint8_t*
                          (long long)s->plane);
     }
   }
+  if (s->ninterp > 0)
+    hipLaunchKernelGGL(k_interp, dim3(blocks_for(4LL * s->ninterp)), dim3(kBlock), 0, ctx->stream, s->d_interp,
+                       s->ninterp, s->d_patches, u, (long long)s->plane);
   if (mask)
     hipLaunchKernelGGL(k_dirichlet, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, mask, u,
                        (long long)s->plane, st4[0], st4[1], st4[2], st4[3]);
@@ -1114,6 +1120,7 @@ extern "C" fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* s, float* u_
   if (st) return st;
   if (!u_bar || (dirichlet_mask && (!dstate_dparam || !dparam_dev)))
     return fail(ctx, FCSD_EINVAL, "fcsd_glue_adj: null argument");
+  if (s->ninterp > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_glue_adj: no reverse mode of the interpolation");
   return glue_adj_impl(ctx, s, u_bar, dirichlet_mask, dstate_dparam, dparam_dev);
 }
 
@@ -1279,6 +1286,9 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   if ((a->w || a->fixed_tau) && (!a->tau || !a->mu))
     return fail(ctx, FCSD_EINVAL, "fcsd_step: network needs tau and mu buffers");
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step: filter not configured (fcsd_set_filter)");
+  if (s->ninterp > 0 && (a->w || a->fixed_tau))
+    return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_step: the network's viscosity on interpolated (non-aligned) patch sets "
+                                        "needs the multi-patch smoothing operator, which is not built");
   if (a->record && (a->w || a->fixed_tau) && !a->argmax)
     return fail(ctx, FCSD_EINVAL, "fcsd_step: a record with classes needs the argmax buffer");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP)) return fail(ctx, FCSD_EINVAL, "fcsd_step: workspace too small");
@@ -1307,6 +1317,94 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   if (e != hipSuccess) return fail(ctx, FCSD_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
   ms->graphs.push_back(g);
   HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, int nf, int64_t* nrecv) {
+  if (!s) return FCSD_EINVAL;
+  fcsd_ctx* ctx = s->ctx;
+  if (!maps) return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: null patch maps");
+  if (s->annulus) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_set_interp: index-aligned sets glue by copy");
+  const int np = s->npatch;
+  for (int p = 0; p < np; ++p)
+    if ((maps[p].kind != 0 && maps[p].kind != 1) || !(maps[p].da > 0) || !(maps[p].db > 0))
+      return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: bad patch map (kind 0 or 1, positive steps)");
+  int minside = 1 << 30;
+  for (const fcsd_patch_desc& q : s->desc) minside = std::min(minside, std::min(q.n1, q.n2));
+  if (nf < 1 || 2 * nf + 3 > minside) return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: fringe width out of range");
+  // fringe points: the nf grid lines nearest to every internal side
+  auto recv = [&](int p, int i, int j) {
+    const fcsd_patch_desc& q = s->desc[p];
+    return (q.internal[0] && i < nf) || (q.internal[1] && i >= q.n1 - nf) || (q.internal[2] && j < nf) ||
+           (q.internal[3] && j >= q.n2 - nf);
+  };
+  std::vector<InterpDev> tab;
+  for (int p = 0; p < np; ++p) {
+    const fcsd_patch_desc& q = s->desc[p];
+    const fcsd_patch_map& m = maps[p];
+    for (int j = 0; j < q.n2; ++j)
+      for (int i = 0; i < q.n1; ++i) {
+        if (!recv(p, i, j)) continue;
+        double x, y;
+        if (m.kind == 0) {
+          x = m.a0 + i * m.da;
+          y = m.b0 + j * m.db;
+        } else {
+          const double th = m.a0 + i * m.da, r = m.b0 + j * m.db;
+          x = r * std::cos(th);
+          y = r * std::sin(th);
+        }
+        // donor: the other patch holding a full stencil around the point's
+        // preimage in which the point lies farthest from the boundary (the
+        // lower index on ties)
+        int best = -1;
+        double bd = 0.0, bxi = 0.0, beta = 0.0;
+        for (int d = 0; d < np; ++d) {
+          if (d == p) continue;
+          const fcsd_patch_map& dm = maps[d];
+          double xi, eta;
+          if (dm.kind == 0) {
+            xi = (x - dm.a0) / dm.da;
+            eta = (y - dm.b0) / dm.db;
+          } else {
+            xi = (std::atan2(y, x) - dm.a0) / dm.da;
+            eta = (std::hypot(x, y) - dm.b0) / dm.db;
+          }
+          const fcsd_patch_desc& dq = s->desc[d];
+          const double dist = std::min(std::min(xi, dq.n1 - 1 - xi), std::min(eta, dq.n2 - 1 - eta));
+          if (dist >= 1.0 && (best < 0 || dist > bd)) {
+            best = d;
+            bd = dist;
+            bxi = xi;
+            beta = eta;
+          }
+        }
+        if (best < 0)
+          return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: fringe point (" + std::to_string(p) + ", " +
+                                            std::to_string(i) + ", " + std::to_string(j) + ") has no donor");
+        const fcsd_patch_desc& dq = s->desc[best];
+        const int ic = std::min(std::max((int)std::floor(bxi + 0.5), 1), dq.n1 - 2);
+        const int jc = std::min(std::max((int)std::floor(beta + 0.5), 1), dq.n2 - 2);
+        for (int b = -1; b <= 1; ++b)
+          for (int a = -1; a <= 1; ++a)
+            if (recv(best, ic + a, jc + b))
+              return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: donor stencil of fringe point (" + std::to_string(p) +
+                                                ", " + std::to_string(i) + ", " + std::to_string(j) +
+                                                ") holds fringe points of patch " + std::to_string(best));
+        tab.push_back(InterpDev{p, i, j, best, ic, jc, (float)(bxi - ic), (float)(beta - jc)});
+      }
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& g : s->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
+  (void)hipFree(s->d_interp);
+  s->d_interp = nullptr;
+  s->ninterp = 0;
+  fcsd_status r;
+  if ((r = upload(ctx, &s->d_interp, tab))) return r;
+  s->ninterp = (int)tab.size();
+  if (nrecv) *nrecv = (int64_t)tab.size();
   return FCSD_OK;
 }
 
@@ -1493,6 +1591,7 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   if (visc_net && (!a->tau || !a->mu || !a->argmax))
     return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: classes need tau, mu and argmax buffers");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: workspace too small");
+  if (s->ninterp > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_step_adj: no reverse mode of the interpolation");
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: filter not configured (fcsd_set_filter)");
   const long long pl = s->plane, n4 = 4 * pl;
   float* w = (float*)ws;

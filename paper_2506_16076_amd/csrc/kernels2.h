@@ -31,6 +31,48 @@ __device__ __forceinline__ int pstore(const PatchDev& P) {
   return P.nb1 == 0 ? P.n1 * P.n2 : (P.nb1 << 3) * ((P.n2 + 3) & ~3);
 }
 
+// ---------------------------------------------------------------- inter-patch interpolation
+
+// A fringe point and its donor stencil: receiver patch and indices, donor
+// patch, stencil centre and the point's local donor coordinates.
+struct InterpDev {
+  int rp, ri, rj;
+  int dp, di, dj;
+  float s, t;
+};
+
+// Quadratic through (-1, ym), (0, y0), (1, yp) at s by Neville's recurrence
+// (the two linear interpolants, then their combination).
+__device__ __forceinline__ float neville3(float ym, float y0, float yp, float s) {
+  const float p01 = (s + 1.0f) * y0 - s * ym;
+  const float p12 = (1.0f - s) * y0 + s * yp;
+  return 0.5f * ((s + 1.0f) * p12 - (s - 1.0f) * p01);
+}
+
+// Fringe values from the donor patches (paper Sec. 3.4.1): iterated
+// quadratic interpolation on the 3 x 3 donor stencil, along q1 on its three
+// rows, then along q2; one thread per (fringe point, field).  Donor points
+// are never receivers, so every thread reads values no thread writes.
+__global__ void __launch_bounds__(kBlock) k_interp(const InterpDev* __restrict__ tab, int n,
+                                                   const PatchDev* __restrict__ patches, float* u, long long pl) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 4 * n) return;
+  const int f = k / n;
+  const InterpDev e = tab[k - f * n];
+  const PatchDev D = patches[e.dp];
+  const PatchDev R = patches[e.rp];
+  const float* v = u + f * pl;
+  float x[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[3 * r + c] = v[pidx(D, e.di - 1 + c, e.dj - 1 + r)];
+  float row[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) row[r] = neville3(x[3 * r], x[3 * r + 1], x[3 * r + 2], e.s);
+  u[f * pl + pidx(R, e.ri, e.rj)] = neville3(row[0], row[1], row[2], e.t);
+}
+
 // Blending window of the initial-data smearing (paper Sec. 4.3.2, eq. qf)
 // along DIR, one thread per line of one patch (blockIdx.y): a discontinuity
 // sits between neighbours whose region labels differ.  A forward sweep

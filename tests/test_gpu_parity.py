@@ -465,6 +465,80 @@ def test_steps_paper_subpatches(env, layout):
     s.close()
 
 
+# ------------------------------------------------------------------ inter-patch interpolation
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_interpolated_fringe(env, layout):
+    """fcsd_set_interp + fcsd_glue against the oracle's interpolation on the
+    Cartesian / polar pair (Sec. 3.4.1): the same receivers, and fringe
+    values within FP32 rounding of the weights (relative 1e-6 of the field
+    scale); every other point untouched."""
+    from oracle import interp
+    api, ctx, torch = env
+    cfg = synth.overlap_config(48)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, layout)
+    n = s.set_interp(ps.geom)
+    table = interp.build(ps)
+    say("interpolated fringe layout", layout, "receivers", n, "oracle", len(table))
+    assert n == len(table)
+    x = cfg.u0.astype(np.float32)
+    xd = D(x)
+    api.fcsd_glue(s, xd)
+    got = H(xd).reshape(4, -1)
+    want = interp.interpolate(x.astype(np.float64).copy(), ps, table)
+    # per component; rho v is zero in this flow, so its scale is the momentum's
+    scale = np.abs(want).max(axis=1)
+    scale[2] = max(scale[1], scale[2])
+    err = np.abs(got - want).max(axis=1) / scale
+    say("  fringe max rel error", err)
+    assert np.all(err <= 1e-6)
+    mask = np.zeros(ps.plane, bool)
+    for (p, i, j, *_r) in table:
+        ps.view(mask, p)[j, i] = True
+    for p in range(ps.npatch):
+        a, b, m = ps.view(got, p), ps.view(x, p), ps.view(mask, p)
+        assert np.array_equal(a[:, ~m], b[:, ~m])
+    s.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_steps_interpolated_patches(env, layout):
+    """Five steps on the non-aligned pair with the fringe interpolated at
+    every stage, constant viscosity, against the oracle (state <= 1e-4)."""
+    api, ctx, torch = env
+    cfg = synth.overlap_config(48)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, layout)
+    s.set_interp(ps.geom)
+    u = D(cfg.u0)
+    mu = D(np.full(ps.plane, cfg.mu_const, np.float32))
+    st = api.Stepper(s, u, D(ps.metric), cfg.ref, mu=mu)
+    run = solver.Run(cfg)
+    for k in range(5):
+        st.step(use_graph=(k > 0))
+        run.step()
+    got = H(u).reshape(4, -1)
+    err = relerr_phys(ps, got, run.u)
+    chg = relerr_phys(ps, got - cfg.u0, run.u - cfg.u0)
+    say("5 steps interpolated pair layout", layout, "state rel L2", err, "change", chg)
+    assert np.all(err < STEP_TOL) and np.all(chg[[0, 1, 3]] < 1e-2)
+    s.close()
+
+
+def test_interpolation_refuses_bad_decompositions(env):
+    api, ctx, torch = env
+    ps = synth.overlap_pair(48)
+    s = api.PatchSet.from_layout(ctx, ps)
+    geom = ps.geom.copy()
+    geom[0, 1] -= 0.3                 # the Cartesian patch moved left: its fringe now meets the sector's
+    with pytest.raises(api.FcsdError):
+        s.set_interp(geom)
+    with pytest.raises(api.FcsdError):
+        s.set_interp(ps.geom, nf=40)   # fringe wider than the patches allow
+    s.close()
+
+
 # ------------------------------------------------------------------ adjoints
 
 @pytest.mark.parametrize("case", ["square64", "shells"])
