@@ -26,13 +26,18 @@ Test infrastructure only (see oracle/__init__.py).
     cos^2(pi k / 18) for |k| <= 8.  Normalisation sums over all patches; on
     the index-aligned annulus the nearest-point map zeta is an index shift, so
     Lambda is a separable window sum over a global index lattice followed by
-    division by the window sum of the D~ indicator.
+    division by the window sum of the D~ indicator.  On patches that overlap
+    without shared grid lines (sets with patch maps), zeta_R(x) is the grid
+    point of R nearest to x's preimage (eq. zeta, rnd(n + 1/2) = n + 1), x
+    in R's domain meaning its preimage lies in R's closed parameter
+    rectangle; the numerator and denominator at x sum R's window sums at
+    zeta_R(x) over every patch R holding x.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from oracle import euler
+from oracle import euler, interp
 
 NV = 9
 R_TABLE = np.array([1.5, 1.0, 0.5, 0.0])
@@ -210,10 +215,32 @@ def smooth_blend(muh, ps):
     w = window_weights()
     mu = np.zeros(ps.plane)
     if ps.nsec == 0:
+        nums, dens = [], []
         for p in range(ps.npatch):
             m = dtilde_mask(ps, p).astype(np.float64)
-            num = _sep_conv(ps.view(muh, p) * m, w)
-            den = _sep_conv(m, w)
+            nums.append(_sep_conv(ps.view(muh, p) * m, w))
+            dens.append(_sep_conv(m, w))
+        if ps.geom is None:
+            for p in range(ps.npatch):
+                ps.view(mu, p)[...] = nums[p] / dens[p]
+            return mu
+        # patches that overlap without shared grid lines (eqs. multipatch_W,
+        # zeta): a point x of patch p also collects, from every other patch
+        # R whose domain holds it, R's window sums at zeta_R(x), the grid
+        # point of R nearest to x's preimage (rnd(n + 1/2) = n + 1)
+        for p in range(ps.npatch):
+            num, den = nums[p].copy(), dens[p].copy()
+            x, y = ps.view(ps.xy, p)
+            for q in range(ps.npatch):
+                if q == p:
+                    continue
+                xi, eta = interp.preimage(ps.geom[q], x, y)
+                n1, n2 = int(ps.n1[q]), int(ps.n2[q])
+                inside = (xi >= 0) & (xi <= n1 - 1) & (eta >= 0) & (eta <= n2 - 1)
+                I = np.floor(np.where(inside, xi, 0) + 0.5).astype(int)
+                J = np.floor(np.where(inside, eta, 0) + 0.5).astype(int)
+                num += np.where(inside, nums[q][J, I], 0.0)
+                den += np.where(inside, dens[q][J, I], 0.0)
             ps.view(mu, p)[...] = num / den
         return mu
     g0, j0, ring, nJ = _global_index(ps, 0)
@@ -274,6 +301,8 @@ def viscosity(e, ps, W, gamma, tau=None, fp32=True, arg=None):
 
 def smooth_blend_adj(mub, ps):
     """Transpose of smooth_blend (a linear map of mu^)."""
+    if ps.nsec == 0 and ps.geom is not None:
+        raise NotImplementedError("transpose of the smoothing across non-aligned patches")
     w = window_weights()
     out = np.zeros(ps.plane)
     if ps.nsec == 0:

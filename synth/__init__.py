@@ -391,17 +391,20 @@ def paper_subpatches(nsec: int = 16, nshell: int = 1, seed: int = 5, mach: float
                   mach=mach, pert=pert, mlp=mlp_weights(1000 + seed), steps=100)
 
 
-def overlap_config(n: int = 48, seed: int = 6, mach: float = 3.0) -> Config:
+def overlap_config(n: int = 48, seed: int = 6, mach: float = 3.0, network: bool = False) -> Config:
     """The Cartesian / polar patch pair of overlap_pair with the Mach-3
-    freestream state and its +-1 % density perturbation and a constant
-    viscosity (the network's smoothing operator needs index-aligned
-    neighbours across inter-patch sides); no Dirichlet points."""
+    freestream state and its +-1 % density perturbation, seeded network
+    weights (network=False: a constant viscosity instead); no Dirichlet
+    points."""
     rng = np.random.default_rng(seed)
     ps = overlap_pair(n)
     pert = draw_perturbation(rng)
     e = mach_state(ps, mach, pert)
+    if not network:
+        return Config(f"overlap-pair-{n}", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]), mach=mach, pert=pert,
+                      mu_const=2e-3, steps=10)
     return Config(f"overlap-pair-{n}", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]), mach=mach, pert=pert,
-                  mu_const=2e-3, steps=10)
+                  mlp=mlp_weights(1000 + seed), steps=10)
 
 
 def random_lines(rng, nlines: int, n: int, smooth: bool = True):

@@ -104,3 +104,60 @@ def test_thin_overlap_is_refused():
     ps.xy[0, :x0.size] -= 0.3          # fringe of patch 0 near x = 0.3, close to r = 0.3
     with pytest.raises(ValueError):
         interp.build(ps)
+
+
+# ------------------------------------------------------------ smoothing across non-aligned patches
+
+def test_multipatch_smoothing_partition_of_unity_and_locality():
+    from oracle import av
+    ps = synth.overlap_pair(48)
+    muh = np.zeros(ps.plane)
+    for p in range(ps.npatch):
+        ps.view(muh, p)[...] = 0.013
+    mu = av.smooth_blend(muh, ps)
+    for p in range(ps.npatch):
+        assert np.abs(ps.view(mu, p) - 0.013).max() <= 1e-15
+    # far from the overlap the result is the patch's own smoothing
+    rng = np.random.default_rng(3)
+    for p in range(ps.npatch):
+        ps.view(muh, p)[...] = rng.uniform(0, 1, ps.view(muh, p).shape)
+    mu = av.smooth_blend(muh, ps)
+    single = synth.overlap_pair(48)
+    single.geom = None
+    with np.errstate(invalid="ignore"):     # strips without D~ points nearby: 0 / 0
+        mu1 = av.smooth_blend(muh, single)
+    far = ps.view(ps.xy, 0)[0] < -0.2          # Cartesian points left of the sector
+    assert np.array_equal(ps.view(mu, 0)[far], ps.view(mu1, 0)[far])
+    assert not np.allclose(ps.view(mu, 0)[~far], ps.view(mu1, 0)[~far])
+
+
+def test_multipatch_smoothing_brute_force_at_overlap_points():
+    """eqs. W, multipatch_W, zeta, multipatch_W_norm written out as explicit
+    sums over every D~ point of both patches, at a few overlap points."""
+    from oracle import av
+    ps = synth.overlap_pair(48)
+    rng = np.random.default_rng(4)
+    muh = rng.uniform(0, 1, ps.plane)
+    mu = av.smooth_blend(muh, ps)
+    wk = lambda k: np.cos(np.pi * k / 18) ** 2 if abs(k) <= 8 else 0.0
+
+    def rnd(t):
+        return int(np.floor(t + 0.5))
+
+    for (p, i, j) in [(0, 45, 20), (0, 40, 30), (1, 10, 2), (1, 30, 7)]:
+        x, y = ps.view(ps.xy, p)[:, j, i]
+        num = den = 0.0
+        for R in range(ps.npatch):
+            xi, eta = interp.preimage(ps.geom[R], x, y)
+            if not (0 <= xi <= ps.n1[R] - 1 and 0 <= eta <= ps.n2[R] - 1):
+                continue
+            I, J = rnd(xi), rnd(eta)
+            m = av.dtilde_mask(ps, R)
+            vals = ps.view(muh, R)
+            for jj in range(ps.n2[R]):
+                for ii in range(ps.n1[R]):
+                    if m[jj, ii]:
+                        wgt = wk(I - ii) * wk(J - jj)
+                        num += wgt * vals[jj, ii]
+                        den += wgt
+        assert abs(ps.view(mu, p)[j, i] - num / den) <= 1e-14
