@@ -196,11 +196,16 @@ typedef struct {
  * donor's parameters, along q1 on the three rows, then along q2.  Fails
  * with FCSD_EINVAL (and a message naming the point) when a fringe point has
  * no donor or a donor stencil holds fringe points (the decomposition check
- * of the Remark).  maps: npatch entries; *nrecv (nullable) receives the
- * number of fringe points.  Not for index-aligned annulus sets (they glue
- * by copy); sets with a table take no network viscosity (the multi-patch
- * smoothing operator across non-aligned patches is not built) and have no
- * reverse mode.  Host-side set-up, synchronises the context's stream. */
+ * of the Remark).  The same maps extend the smoothing-blending operator of
+ * the viscosity across the patches (eqs. multipatch_W, zeta,
+ * multipatch_W_norm): a point that lies in another patch's closed
+ * parameter rectangle adds that patch's window sums at the grid point
+ * nearest to its preimage (rnd(n + 1/2) = n + 1) to its numerator and
+ * denominator.  maps: npatch entries; *nrecv (nullable) receives the number
+ * of fringe points.  Not for index-aligned annulus sets (they glue by copy
+ * and smooth on one global lattice); sets with a table have no reverse mode
+ * of the glue or the viscosity (FCSD_EUNSUPPORTED).  Host-side set-up,
+ * synchronises the context's stream. */
 fcsd_status fcsd_set_interp(fcsd_set* set, const fcsd_patch_map* maps, int nf, int64_t* nrecv);
 
 /* Localized discontinuity-smearing of initial data (paper Sec. 4.3.2, eqs.

@@ -86,6 +86,9 @@ struct fcsd_set {
   int filter_p = 0;
   InterpDev* d_interp = nullptr;          // inter-patch interpolation table (fcsd_set_interp)
   int ninterp = 0;
+  OvlTarget* d_ovl = nullptr;             // smoothing operator across those patches
+  long long* d_ovl_src = nullptr;
+  int novl = 0;
   float2* d_ks = nullptr;                 // initial-data smearing filter factors (fcsd_smear)
   int* d_ksoff[2] = {nullptr, nullptr};   // per direction and plan: offset of the plan's factors
   double ks_alpha = -1.0;
@@ -626,6 +629,8 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_km);
   hipFree(s->d_kf);
   hipFree(s->d_interp);
+  hipFree(s->d_ovl);
+  hipFree(s->d_ovl_src);
   hipFree(s->d_ks);
   hipFree(s->d_ksoff[0]);
   hipFree(s->d_ksoff[1]);
@@ -993,9 +998,13 @@ fcsd_status lambda_forward(fcsd_ctx* ctx, const fcsd_set* s, const AvWs& A, cons
                      (const float*)A.num, (const float*)A.den, A.t0, A.t1, 0);
   hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, st, s->d_lchunks, s->nlchunks, s->d_lats,
                      (const float*)A.t0, (const float*)A.t1, A.num, A.den, 1);
-  if (mu)
+  if (mu) {
     hipLaunchKernelGGL(k_lat_scatter, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, st, s->d_chunks, s->nchunks, s->d_patches, s->an,
                        s->annulus, (const float*)A.num, (const float*)A.den, mu);
+    if (s->novl > 0)
+      hipLaunchKernelGGL(k_lat_overlap, dim3(blocks_for(s->novl)), dim3(kBlock), 0, st, s->d_ovl, s->novl,
+                         s->d_ovl_src, (const float*)A.num, (const float*)A.den, mu);
+  }
   return launch_check(ctx, "lambda");
 }
 
@@ -1041,6 +1050,8 @@ extern "C" fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* s, const 
   if (st) return st;
   if (!u || !tau || !argmax || !mu_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "av_viscosity_adj: null argument");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_AV)) return fail(ctx, FCSD_EINVAL, "av_viscosity_adj: workspace too small");
+  if (s->novl > 0)
+    return fail(ctx, FCSD_EUNSUPPORTED, "av_viscosity_adj: no transpose of the smoothing across interpolated patches");
   AvWs A = carve_av(s, ws);
   hipStream_t sm = ctx->stream;
   // denominators of the forward operator (indicator only; num unused)
@@ -1286,9 +1297,6 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   if ((a->w || a->fixed_tau) && (!a->tau || !a->mu))
     return fail(ctx, FCSD_EINVAL, "fcsd_step: network needs tau and mu buffers");
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step: filter not configured (fcsd_set_filter)");
-  if (s->ninterp > 0 && (a->w || a->fixed_tau))
-    return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_step: the network's viscosity on interpolated (non-aligned) patch sets "
-                                        "needs the multi-patch smoothing operator, which is not built");
   if (a->record && (a->w || a->fixed_tau) && !a->argmax)
     return fail(ctx, FCSD_EINVAL, "fcsd_step: a record with classes needs the argmax buffer");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP)) return fail(ctx, FCSD_EINVAL, "fcsd_step: workspace too small");
@@ -1394,16 +1402,67 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
         tab.push_back(InterpDev{p, i, j, best, ic, jc, (float)(bxi - ic), (float)(beta - jc)});
       }
   }
+  // smoothing operator: every point of a patch that lies in another patch's
+  // closed parameter rectangle also takes that patch's window sums at the
+  // grid point nearest to its preimage (rnd(n + 1/2) = n + 1)
+  std::vector<OvlTarget> ovl;
+  std::vector<long long> osrc;
+  for (int p = 0; p < np; ++p) {
+    const fcsd_patch_desc& q = s->desc[p];
+    const fcsd_patch_map& m = maps[p];
+    PatchDev P{};
+    P.n1 = q.n1;
+    P.n2 = q.n2;
+    P.off = q.off;
+    P.nb1 = s->layout == FCSD_LAYOUT_B8X4 ? (q.n1 + 7) >> 3 : 0;
+    for (int j = 0; j < q.n2; ++j)
+      for (int i = 0; i < q.n1; ++i) {
+        double x, y;
+        if (m.kind == 0) {
+          x = m.a0 + i * m.da;
+          y = m.b0 + j * m.db;
+        } else {
+          const double th = m.a0 + i * m.da, r = m.b0 + j * m.db;
+          x = r * std::cos(th);
+          y = r * std::sin(th);
+        }
+        const int begin = (int)osrc.size();
+        for (int d = 0; d < np; ++d) {
+          if (d == p) continue;
+          const fcsd_patch_map& dm = maps[d];
+          double xi, eta;
+          if (dm.kind == 0) {
+            xi = (x - dm.a0) / dm.da;
+            eta = (y - dm.b0) / dm.db;
+          } else {
+            xi = (std::atan2(y, x) - dm.a0) / dm.da;
+            eta = (std::hypot(x, y) - dm.b0) / dm.db;
+          }
+          const fcsd_patch_desc& dq = s->desc[d];
+          if (!(xi >= 0.0 && xi <= dq.n1 - 1 && eta >= 0.0 && eta <= dq.n2 - 1)) continue;
+          const long long I = (long long)std::floor(xi + 0.5), J = (long long)std::floor(eta + 0.5);
+          osrc.push_back(dq.off + J * dq.n1 + I);
+        }
+        if ((int)osrc.size() > begin)
+          ovl.push_back(OvlTarget{pidx(P, i, j), q.off + (long long)j * q.n1 + i, begin, (int)osrc.size()});
+      }
+  }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& g : s->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   s->graphs.clear();
   (void)hipFree(s->d_interp);
+  (void)hipFree(s->d_ovl);
+  (void)hipFree(s->d_ovl_src);
   s->d_interp = nullptr;
-  s->ninterp = 0;
+  s->d_ovl = nullptr;
+  s->d_ovl_src = nullptr;
+  s->ninterp = s->novl = 0;
   fcsd_status r;
-  if ((r = upload(ctx, &s->d_interp, tab))) return r;
+  if ((r = upload(ctx, &s->d_interp, tab)) || (r = upload(ctx, &s->d_ovl, ovl)) || (r = upload(ctx, &s->d_ovl_src, osrc)))
+    return r;
   s->ninterp = (int)tab.size();
+  s->novl = (int)ovl.size();
   if (nrecv) *nrecv = (int64_t)tab.size();
   return FCSD_OK;
 }

@@ -21,7 +21,7 @@ struct PatchDev {
 // cache line), block (i/8, j/4) at off + 32 (j/4 nb1 + i/8), row-major
 // inside the block.  A column tile of 8 q2 lines and a row tile of 4 q1
 // lines then both read whole cache lines.
-__device__ __forceinline__ long long pidx(const PatchDev& P, int i, int j) {
+__host__ __device__ __forceinline__ long long pidx(const PatchDev& P, int i, int j) {
   if (P.nb1 == 0) return P.off + (long long)j * P.n1 + i;
   return P.off + ((((long long)(j >> 2)) * P.nb1 + (i >> 3)) << 5) + ((j & 3) << 3) + (i & 7);
 }
@@ -696,6 +696,30 @@ __global__ void __launch_bounds__(kBlock) k_lat_scatter(const ChunkDev* chunks, 
     const long long c = lat_cell(P, ck.patch, i, j, annulus, an);
     mu[P.off + k] = num[c] / den[c];
   });
+}
+
+// Points of patches that overlap other patches without shared grid lines
+// (paper eqs. multipatch_W, zeta, multipatch_W_norm): mu = (num + sum of
+// the other patches' num at the nearest grid point of the preimage) / (den +
+// the same sum of den).  Targets hold the point's plane index and its own
+// lattice cell; src[begin..end) the other patches' cells.
+struct OvlTarget {
+  long long pt, cell;
+  int begin, end;
+};
+
+__global__ void __launch_bounds__(kBlock) k_lat_overlap(const OvlTarget* __restrict__ tg, int n,
+                                                        const long long* __restrict__ src, const float* num,
+                                                        const float* den, float* mu) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const OvlTarget t = tg[k];
+  float a = num[t.cell], b = den[t.cell];
+  for (int q = t.begin; q < t.end; ++q) {
+    a += num[src[q]];
+    b += den[src[q]];
+  }
+  mu[t.pt] = a / b;
 }
 
 // Lambda^T first step: t = mu_bar / den (per patch point, into a plane)

@@ -214,6 +214,11 @@ def rhs_case(name):
         ps = cfg.ps
         mu = (0.003 * (1.3 + np.sin(2 * ps.xy[0] - ps.xy[1]))).astype(np.float32)
         return ps, cfg.u0, mu, cfg.ref
+    if name == "overlap":
+        cfg = synth.overlap_config(48)
+        ps = cfg.ps
+        mu = (0.002 * (1.2 + np.sin(2 * ps.xy[0] + ps.xy[1]))).astype(np.float32)
+        return ps, cfg.u0, mu, cfg.ref
     if name == "uneven":
         cfg = synth.config(2, npatch=5, nmax=200)
         ps = cfg.ps
@@ -324,11 +329,13 @@ def test_network_classes(env):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("case", ["annulus", "shells", "uneven"])
+@pytest.mark.parametrize("case", ["annulus", "shells", "uneven", "overlap"])
 def test_viscosity_operator(env, case, layout):
     api, ctx, torch = env
     ps, u, _, ref = rhs_case(case)
     s, D, H = mkset(api, ctx, ps, layout)
+    if ps.geom is not None:
+        s.set_interp(ps.geom)        # smoothing across the non-aligned pair
     rng = np.random.default_rng(15)
     tau = np.zeros(ps.plane, np.int8)
     for p in range(ps.npatch):
@@ -502,22 +509,38 @@ def test_interpolated_fringe(env, layout):
     s.close()
 
 
+@pytest.mark.parametrize("network", [False, True])
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_steps_interpolated_patches(env, layout):
+def test_steps_interpolated_patches(env, layout, network):
     """Five steps on the non-aligned pair with the fringe interpolated at
-    every stage, constant viscosity, against the oracle (state <= 1e-4)."""
+    every stage, constant viscosity or the network's (smoothed across the
+    pair), against the oracle (state <= 1e-4).  With the network the
+    oracle replays the GPU's decisions (classes, maximisers, step sizes),
+    whose first step must agree with the oracle's own classes (>= 99.9 %)."""
     api, ctx, torch = env
-    cfg = synth.overlap_config(48)
+    cfg = synth.overlap_config(48, network=network)
     ps = cfg.ps
     s, D, H = mkset(api, ctx, ps, layout)
     s.set_interp(ps.geom)
     u = D(cfg.u0)
-    mu = D(np.full(ps.plane, cfg.mu_const, np.float32))
-    st = api.Stepper(s, u, D(ps.metric), cfg.ref, mu=mu)
+    if network:
+        W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+        st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W)
+    else:
+        st = api.Stepper(s, u, D(ps.metric), cfg.ref, mu=D(np.full(ps.plane, cfg.mu_const, np.float32)))
     run = solver.Run(cfg)
     for k in range(5):
         st.step(use_graph=(k > 0))
-        run.step()
+        if not network:
+            run.step()
+            continue
+        if k == 0:
+            free = solver.Run(cfg)
+            free.step()
+            same = np.mean(H(st.tau) == free.log[-1]["tau"])
+            say("  interpolated pair, first step tau agreement", same)
+            assert same > 0.999
+        run.step(dt=float(host(st.dt)[0]), tau=H(st.tau), arg=H(st.argmax))
     got = H(u).reshape(4, -1)
     err = relerr_phys(ps, got, run.u)
     chg = relerr_phys(ps, got - cfg.u0, run.u - cfg.u0)
