@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle import av, euler, rk, solver
+from oracle import av, euler, interp, rk, solver
 from oracle import filter as spectral_filter
 
 
@@ -30,6 +30,10 @@ def glue_vjp(eb, ps, mach, gamma=1.4):
     the derivative with respect to the free-stream Mach number."""
     dM = 0.0
     if ps.nsec == 0:
+        if ps.geom is not None:
+            if getattr(ps, "_interp_table", None) is None:
+                ps._interp_table = interp.build(ps)
+            interp.interpolate_adj(eb, ps, ps._interp_table)
         return dM
     if ps.dirichlet is not None:
         m = ps.dirichlet.astype(bool)

@@ -301,10 +301,41 @@ def viscosity(e, ps, W, gamma, tau=None, fp32=True, arg=None):
 
 def smooth_blend_adj(mub, ps):
     """Transpose of smooth_blend (a linear map of mu^)."""
-    if ps.nsec == 0 and ps.geom is not None:
-        raise NotImplementedError("transpose of the smoothing across non-aligned patches")
     w = window_weights()
     out = np.zeros(ps.plane)
+    if ps.nsec == 0 and ps.geom is not None:
+        # mu(x) = sum_R num_R(zeta_R(x)) / D(x): t = mu_bar / D goes back to
+        # every cell it was read from, then through the (symmetric) window
+        # sums and the D~ indicator
+        ms = [dtilde_mask(ps, p).astype(np.float64) for p in range(ps.npatch)]
+        dens = [_sep_conv(m, w) for m in ms]
+        cells = []          # per patch: list of (other patch, inside, I, J)
+        D = []
+        for p in range(ps.npatch):
+            x, y = ps.view(ps.xy, p)
+            d = dens[p].copy()
+            lst = []
+            for q in range(ps.npatch):
+                if q == p:
+                    continue
+                xi, eta = interp.preimage(ps.geom[q], x, y)
+                n1, n2 = int(ps.n1[q]), int(ps.n2[q])
+                inside = (xi >= 0) & (xi <= n1 - 1) & (eta >= 0) & (eta <= n2 - 1)
+                I = np.floor(np.where(inside, xi, 0) + 0.5).astype(int)
+                J = np.floor(np.where(inside, eta, 0) + 0.5).astype(int)
+                d += np.where(inside, dens[q][J, I], 0.0)
+                lst.append((q, inside, I, J))
+            cells.append(lst)
+            D.append(d)
+        acc = [np.zeros_like(d) for d in dens]
+        for p in range(ps.npatch):
+            t = ps.view(mub, p) / D[p]
+            acc[p] += t
+            for (q, inside, I, J) in cells[p]:
+                np.add.at(acc[q], (J[inside], I[inside]), t[inside])
+        for p in range(ps.npatch):
+            ps.view(out, p)[...] = ms[p] * _sep_conv(acc[p], w)
+        return out
     if ps.nsec == 0:
         for p in range(ps.npatch):
             m = dtilde_mask(ps, p).astype(np.float64)

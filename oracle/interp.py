@@ -107,3 +107,25 @@ def interpolate(e, ps, table):
         rows = [neville3(d[:, jc + k, ic - 1], d[:, jc + k, ic], d[:, jc + k, ic + 1], s) for k in (-1, 0, 1)]
         ps.view(e, p)[:, j, i] = neville3(rows[0], rows[1], rows[2], t)
     return e
+
+
+def lagrange3(s):
+    """Weights of the nodes -1, 0, 1 in the quadratic through them at s (the
+    polynomial Neville's recurrence evaluates)."""
+    return np.array([0.5 * s * (s - 1), 1 - s * s, 0.5 * s * (s + 1)])
+
+
+def interpolate_adj(eb, ps, table):
+    """In-place transpose of interpolate on a cotangent [nf, plane]: each
+    fringe point's cotangent goes to its nine donor points with the
+    interpolation weights and is then zeroed (its old value is overwritten
+    by the forward map; donors are never fringe points)."""
+    for (p, i, j, q, ic, jc, s, t) in table:
+        g = ps.view(eb, p)[:, j, i].copy()
+        ps.view(eb, p)[:, j, i] = 0.0
+        ws, wt = lagrange3(s), lagrange3(t)
+        d = ps.view(eb, q)
+        for b in range(3):
+            for a in range(3):
+                d[:, jc - 1 + b, ic - 1 + a] += wt[b] * ws[a] * g
+    return eb
