@@ -203,8 +203,10 @@ typedef struct {
  * nearest to its preimage (rnd(n + 1/2) = n + 1) to its numerator and
  * denominator.  maps: npatch entries; *nrecv (nullable) receives the number
  * of fringe points.  Not for index-aligned annulus sets (they glue by copy
- * and smooth on one global lattice); sets with a table have no reverse mode
- * of the glue or the viscosity (FCSD_EUNSUPPORTED).  Host-side set-up,
+ * and smooth on one global lattice).  fcsd_glue_adj, av_viscosity_adj and
+ * fcsd_step_adj transpose both (the interpolation with the Lagrange weights
+ * of the quadratic Neville's recurrence evaluates; accumulated with atomic
+ * adds, so their rounding depends on the order).  Host-side set-up,
  * synchronises the context's stream. */
 fcsd_status fcsd_set_interp(fcsd_set* set, const fcsd_patch_map* maps, int nf, int64_t* nrecv);
 

@@ -1050,8 +1050,6 @@ extern "C" fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* s, const 
   if (st) return st;
   if (!u || !tau || !argmax || !mu_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "av_viscosity_adj: null argument");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_AV)) return fail(ctx, FCSD_EINVAL, "av_viscosity_adj: workspace too small");
-  if (s->novl > 0)
-    return fail(ctx, FCSD_EUNSUPPORTED, "av_viscosity_adj: no transpose of the smoothing across interpolated patches");
   AvWs A = carve_av(s, ws);
   hipStream_t sm = ctx->stream;
   // denominators of the forward operator (indicator only; num unused)
@@ -1060,8 +1058,14 @@ extern "C" fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* s, const 
   // t = mu_bar / den at every point, gathered into the lattice, window sum
   hipLaunchKernelGGL(k_lat_divide_pts, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, sm, s->d_chunks, s->nchunks, s->d_patches, s->an,
                      s->annulus, mu_bar, (const float*)A.den, A.tp);
+  if (s->novl > 0)
+    hipLaunchKernelGGL(k_lat_overlap_div, dim3(blocks_for(s->novl)), dim3(kBlock), 0, sm, s->d_ovl, s->novl,
+                       s->d_ovl_src, mu_bar, (const float*)A.den, A.tp);
   hipLaunchKernelGGL(k_lat_gather, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats, s->d_patches,
                      s->an, (const float*)A.tp, A.t0, (float*)nullptr, s->annulus, 1);
+  if (s->novl > 0)
+    hipLaunchKernelGGL(k_lat_overlap_scatter, dim3(blocks_for(s->novl)), dim3(kBlock), 0, sm, s->d_ovl, s->novl,
+                       s->d_ovl_src, (const float*)A.tp, A.t0);
   hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats,
                      (const float*)A.t0, (const float*)nullptr, A.t1, (float*)nullptr, 0);
   hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats,
@@ -1106,6 +1110,9 @@ fcsd_status glue_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, float* ub, const uin
   if (mask)
     hipLaunchKernelGGL(k_dirichlet_adj, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, mask, ub,
                        (long long)s->plane, ds4[0], ds4[1], ds4[2], ds4[3], dparam);
+  if (s->ninterp > 0)
+    hipLaunchKernelGGL(k_interp_adj, dim3(blocks_for(4LL * s->ninterp)), dim3(kBlock), 0, ctx->stream, s->d_interp,
+                       s->ninterp, s->d_patches, ub, (long long)s->plane);
   if (s->annulus) {
     const AnnulusDev& A = s->an;
     if (A.nshell > 1) {
@@ -1131,7 +1138,6 @@ extern "C" fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* s, float* u_
   if (st) return st;
   if (!u_bar || (dirichlet_mask && (!dstate_dparam || !dparam_dev)))
     return fail(ctx, FCSD_EINVAL, "fcsd_glue_adj: null argument");
-  if (s->ninterp > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_glue_adj: no reverse mode of the interpolation");
   return glue_adj_impl(ctx, s, u_bar, dirichlet_mask, dstate_dparam, dparam_dev);
 }
 
@@ -1650,7 +1656,6 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   if (visc_net && (!a->tau || !a->mu || !a->argmax))
     return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: classes need tau, mu and argmax buffers");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: workspace too small");
-  if (s->ninterp > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_step_adj: no reverse mode of the interpolation");
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: filter not configured (fcsd_set_filter)");
   const long long pl = s->plane, n4 = 4 * pl;
   float* w = (float*)ws;

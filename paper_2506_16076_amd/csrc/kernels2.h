@@ -73,6 +73,30 @@ __global__ void __launch_bounds__(kBlock) k_interp(const InterpDev* __restrict__
   u[f * pl + pidx(R, e.ri, e.rj)] = neville3(row[0], row[1], row[2], e.t);
 }
 
+// Transpose of k_interp: every fringe point's cotangent goes to its nine
+// donor points with the weights of the quadratic Neville's recurrence
+// evaluates (Lagrange weights of the nodes -1, 0, 1) and is then zeroed;
+// one thread per (fringe point, field).
+__global__ void __launch_bounds__(kBlock) k_interp_adj(const InterpDev* __restrict__ tab, int n,
+                                                       const PatchDev* __restrict__ patches, float* ub, long long pl) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 4 * n) return;
+  const int f = k / n;
+  const InterpDev e = tab[k - f * n];
+  const PatchDev D = patches[e.dp];
+  const PatchDev R = patches[e.rp];
+  float* v = ub + f * pl;
+  const long long r = pidx(R, e.ri, e.rj);
+  const float g = v[r];
+  v[r] = 0.0f;
+  const float ws[3] = {0.5f * e.s * (e.s - 1.0f), 1.0f - e.s * e.s, 0.5f * e.s * (e.s + 1.0f)};
+  const float wt[3] = {0.5f * e.t * (e.t - 1.0f), 1.0f - e.t * e.t, 0.5f * e.t * (e.t + 1.0f)};
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) atomicAdd(v + pidx(D, e.di - 1 + a, e.dj - 1 + b), wt[b] * ws[a] * g);
+}
+
 // Blending window of the initial-data smearing (paper Sec. 4.3.2, eq. qf)
 // along DIR, one thread per line of one patch (blockIdx.y): a discontinuity
 // sits between neighbours whose region labels differ.  A forward sweep
@@ -720,6 +744,31 @@ __global__ void __launch_bounds__(kBlock) k_lat_overlap(const OvlTarget* __restr
     b += den[src[q]];
   }
   mu[t.pt] = a / b;
+}
+
+// Transpose of k_lat_overlap, two steps.  First, at each target point,
+// t = mu_bar / (its full denominator) replaces mu_bar / den[own cell];
+// after t has been gathered into the lattice, every target's t is also
+// added at the other patches' cells it read from.
+__global__ void __launch_bounds__(kBlock) k_lat_overlap_div(const OvlTarget* __restrict__ tg, int n,
+                                                            const long long* __restrict__ src, const float* mub,
+                                                            const float* den, float* t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const OvlTarget q = tg[k];
+  float b = den[q.cell];
+  for (int i = q.begin; i < q.end; ++i) b += den[src[i]];
+  t[q.pt] = mub[q.pt] / b;
+}
+
+__global__ void __launch_bounds__(kBlock) k_lat_overlap_scatter(const OvlTarget* __restrict__ tg, int n,
+                                                                const long long* __restrict__ src, const float* t,
+                                                                float* acc) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const OvlTarget q = tg[k];
+  const float v = t[q.pt];
+  for (int i = q.begin; i < q.end; ++i) atomicAdd(acc + src[i], v);
 }
 
 // Lambda^T first step: t = mu_bar / den (per patch point, into a plane)

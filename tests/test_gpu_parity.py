@@ -562,6 +562,46 @@ def test_interpolation_refuses_bad_decompositions(env):
     s.close()
 
 
+def test_interpolated_glue_and_step_reverse_mode(env):
+    """Transposes on the interpolated pair: fcsd_glue_adj against the
+    oracle's (dot-product exact up to FP32 accumulation), and one network
+    step's reverse mode against the oracle's step VJP at the GPU's
+    decisions (relative L2 per component <= 1e-4)."""
+    from oracle import adjoint, interp
+    api, ctx, torch = env
+    cfg = synth.overlap_config(48, network=True)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, 1)
+    s.set_interp(ps.geom)
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal((4, ps.plane)).astype(np.float32)
+    yd = D(y)
+    api.fcsd_glue_adj(s, yd)
+    want = y.astype(np.float64).copy()
+    adjoint.glue_vjp(want, ps, cfg.mach)
+    gerr = relerr_phys(ps, H(yd).reshape(4, -1), want)
+    say("interpolated glue transpose rel L2", gerr)
+    assert np.all(gerr < 1e-6)
+    # one step and its reverse mode
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    u = D(cfg.u0)
+    st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W)
+    u_in = u.clone()
+    st.step()
+    tau, dt, arg = st.tau.clone(), st.dt.clone(), H(st.argmax)
+    w = rng.standard_normal((4, ps.plane)).astype(np.float32)
+    ub = D(w)
+    st.step_adj(u_in, ub, tau, dt)
+    run = solver.Run(cfg)
+    run.u = H(u_in).reshape(4, -1).astype(np.float64)
+    run.step(dt=float(host(dt)[0]), tau=H(tau), arg=arg, record=True)
+    want, _ = adjoint.step_vjp(run, run.log[-1], w.astype(np.float64))
+    err = relerr_phys(ps, H(ub).reshape(4, -1), want)
+    say("interpolated pair step reverse mode rel L2", err)
+    assert np.all(err < 1e-4)
+    s.close()
+
+
 # ------------------------------------------------------------------ adjoints
 
 @pytest.mark.parametrize("case", ["square64", "shells"])
@@ -583,15 +623,18 @@ def test_rhs_reverse_mode(env, case):
     s.close()
 
 
-def test_viscosity_reverse_mode(env):
+@pytest.mark.parametrize("case", ["annulus", "overlap"])
+def test_viscosity_reverse_mode(env, case):
     api, ctx, torch = env
-    cfg = synth.config(1, n=40)
+    cfg = synth.config(1, n=40) if case == "annulus" else synth.overlap_config(48, network=True)
     ps = cfg.ps
     e = cfg.u0.astype(np.float64)
     mu, tau, arg = av.viscosity(e, ps, cfg.mlp, G)
     rng = np.random.default_rng(19)
     mb = rng.standard_normal(ps.plane).astype(np.float32)
     s = api.PatchSet.from_layout(ctx, ps)
+    if ps.geom is not None:
+        s.set_interp(ps.geom)
     ub = torch.zeros(4 * ps.plane, device="cuda:0")
     api.av_viscosity_adj(s, dev(torch, cfg.u0), dev(torch, tau.astype(np.int8)), dev(torch, arg.astype(np.int32)),
                          G, dev(torch, mb), ub)
