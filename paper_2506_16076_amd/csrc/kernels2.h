@@ -665,37 +665,64 @@ __global__ void __launch_bounds__(kBlock) k_lat_gather(const ChunkDev* lchunks, 
 }
 
 // separable 17-tap window sum along G (dir 0, periodic or zero padded) or J
+// (dir 1, zero padded).  Along G a chunk's cells and their 8 neighbours on
+// either side are contiguous, so they are staged in LDS once and the taps
+// read from there (a periodic wrap at a row end reads global memory); the
+// taps are summed in the same order either way.
 __global__ void __launch_bounds__(kBlock) k_lat_conv(const ChunkDev* lchunks, int nchunks, const LatDev* lats,
                                                      const float* in0, const float* in1, float* out0,
                                                      float* out1, int dir) {
-  for_chunks(lchunks, nchunks, [&](const ChunkDev ck) {
+  __shared__ float st0[kChunk + 16], st1[kChunk + 16];
+  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {
+    const ChunkDev ck = lchunks[cb];
     const LatDev Lt = lats[ck.patch];
+    const long long ncell = (long long)Lt.W * Lt.H;
     const int k = ck.start + threadIdx.x;
-    if (k >= Lt.W * Lt.H) return;
-    const int J = k / Lt.W, G = k - J * Lt.W;
-    float s0 = 0.f, s1 = 0.f;
-    for (int l = -8; l <= 8; ++l) {
-      int gg = G, jj = J;
-      if (dir == 0) {
-        gg = G + l;
-        if (Lt.periodic) {
-          // |l| <= 8 < W: one wrap at most (no integer division per tap)
-          gg = gg < 0 ? gg + Lt.W : (gg >= Lt.W ? gg - Lt.W : gg);
-        } else if (gg < 0 || gg >= Lt.W) {
-          continue;
-        }
-      } else {
-        jj = J + l;
-        if (jj < 0 || jj >= Lt.H) continue;
+    if (dir == 0) {
+      for (int q = threadIdx.x; q < kChunk + 16; q += blockDim.x) {
+        const long long c = (long long)ck.start - 8 + q;
+        const bool ok = c >= 0 && c < ncell;
+        st0[q] = ok ? in0[Lt.base + c] : 0.f;
+        if (in1) st1[q] = ok ? in1[Lt.base + c] : 0.f;
       }
-      const long long c = Lt.base + (long long)jj * Lt.W + gg;
-      const float w = win(l);
-      s0 = fmaf(w, in0[c], s0);
-      if (in1) s1 = fmaf(w, in1[c], s1);
+      __syncthreads();
     }
-    out0[Lt.base + k] = s0;
-    if (out1) out1[Lt.base + k] = s1;
-  });
+    if (k < ncell) {
+      const int J = k / Lt.W, G = k - J * Lt.W;
+      float s0 = 0.f, s1 = 0.f;
+      // unrolled: the window weights become literals
+#pragma unroll
+      for (int l = -8; l <= 8; ++l) {
+        float a, b = 0.f;
+        const float w = win(l);
+        if (dir == 0) {
+          const int gg = G + l;
+          if (gg >= 0 && gg < Lt.W) {
+            a = st0[threadIdx.x + 8 + l];
+            if (in1) b = st1[threadIdx.x + 8 + l];
+          } else if (Lt.periodic) {
+            // |l| <= 8 < W: one wrap at most (no integer division per tap)
+            const long long c = Lt.base + (long long)J * Lt.W + (gg < 0 ? gg + Lt.W : gg - Lt.W);
+            a = in0[c];
+            if (in1) b = in1[c];
+          } else {
+            continue;
+          }
+        } else {
+          const int jj = J + l;
+          if (jj < 0 || jj >= Lt.H) continue;
+          const long long c = Lt.base + (long long)jj * Lt.W + G;
+          a = in0[c];
+          if (in1) b = in1[c];
+        }
+        s0 = fmaf(w, a, s0);
+        if (in1) s1 = fmaf(w, b, s1);
+      }
+      out0[Lt.base + k] = s0;
+      if (out1) out1[Lt.base + k] = s1;
+    }
+    if (dir == 0) __syncthreads();  // the staging buffers are reused by the next chunk
+  }
 }
 
 __device__ __forceinline__ long long lat_cell(const PatchDev& P, int p, int i, int j, int annulus,
