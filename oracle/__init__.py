@@ -23,6 +23,7 @@ Modules
            (Sec. 4.3.1)
   smear    localized discontinuity-smearing of the initial data (Sec. 4.3.2)
   interp   inter-patch interpolation of fringe values (Sec. 3.4.1)
+  wall     no-slip adiabatic walls through a Neumann FC boundary value
   solver   multi-patch time stepping with fringe exchange and boundary
            overwrite (Secs. 3.4, 4.2, Algorithm 1)
   adjoint  hand-written discrete adjoints (reverse mode) of all of the above

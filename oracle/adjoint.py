@@ -29,6 +29,8 @@ def glue_vjp(eb, ps, mach, gamma=1.4):
     """In-place transpose of solver.glue on a cotangent [4, plane]; returns
     the derivative with respect to the free-stream Mach number."""
     dM = 0.0
+    if getattr(ps, "wall", None) is not None and ps.wall.any():
+        raise NotImplementedError("reverse mode of the wall condition")
     if ps.nsec == 0:
         if ps.geom is not None:
             if getattr(ps, "_interp_table", None) is None:

@@ -22,13 +22,14 @@ Readings for the index-aligned annulus used by the synthetic workloads:
 
 Patch sets that carry patch maps (``geom``) and are not index-aligned take
 their communication from the inter-patch interpolation of Sec. 3.4.1
-(oracle.interp) instead.
+(oracle.interp) instead.  Sides flagged as walls get the no-slip adiabatic
+condition of oracle.wall after the rest of the glue.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from oracle import av, euler, filter as spectral_filter, interp, rk
+from oracle import av, euler, filter as spectral_filter, interp, rk, wall
 
 NF = 5
 OVL = 19
@@ -42,7 +43,7 @@ def glue(e, ps, mach, gamma=1.4):
             if getattr(ps, "_interp_table", None) is None:
                 ps._interp_table = interp.build(ps)
             interp.interpolate(e, ps, ps._interp_table)
-        return e
+        return wall.apply(e, ps, gamma)
     S, K = ps.nsec, ps.nshell
     for k in range(K):
         for s in range(S):
@@ -69,6 +70,7 @@ def glue(e, ps, mach, gamma=1.4):
         fs = np.array([1.4, 1.4 * mach, 0.0, 1.0 / (gamma - 1) + 0.5 * 1.4 * mach * mach])
         m = ps.dirichlet.astype(bool)
         e[:, m] = fs[:, None]
+    wall.apply(e, ps, gamma)        # no-slip adiabatic walls (oracle.wall), last
     return e
 
 

@@ -74,6 +74,8 @@ class PatchSet:
     # float64 [P, 5]: kind (0 Cartesian x = a0 + i da, y = b0 + j db;
     # 1 polar theta = a0 + i da, r = b0 + j db), a0, da, b0, db
     geom: Optional[np.ndarray] = None
+    # no-slip adiabatic wall sides (None: none), uint8 [P, 4]: q1-, q1+, q2-, q2+
+    wall: Optional[np.ndarray] = None
 
     @property
     def npatch(self) -> int:
@@ -405,6 +407,16 @@ def overlap_config(n: int = 48, seed: int = 6, mach: float = 3.0, network: bool 
                       mu_const=2e-3, steps=10)
     return Config(f"overlap-pair-{n}", ps, _f32(e, ps), np.array([1.4, mach, 0, 1.0]), mach=mach, pert=pert,
                   mlp=mlp_weights(1000 + seed), steps=10)
+
+
+def with_cylinder_wall(cfg: Config) -> Config:
+    """An annulus workload whose inner circle (r = 0.5, the q2- side of the
+    innermost shell) is a no-slip adiabatic wall."""
+    ps = cfg.ps
+    ps.wall = np.zeros((ps.npatch, 4), np.uint8)
+    for s in range(ps.nsec):
+        ps.wall[ps.patch_of_shell(s, 0), 2] = 1
+    return cfg
 
 
 def random_lines(rng, nlines: int, n: int, smooth: bool = True):
