@@ -311,13 +311,15 @@ def main():
 
     # ---------------- the paper's discretisation at the same point count:
     # 48 x 32 annulus subpatches of 101 x 101 (d = 2, C = 27, L = 128) with
-    # fringe glue and the Dirichlet inflow, network every step
+    # fringe glue, the Dirichlet inflow and the cylinder wall, network every
+    # step
     paper = None
     if not args.no_paper:
-        pc = synth.paper_subpatches(48, 32)
+        pc = synth.with_cylinder_wall(synth.paper_subpatches(48, 32))
         pps = pc.ps
         s2 = api.PatchSet.from_layout(ctx, pps, layout)
         s2.tune(tuning["budgets"], tuning["threads"], {"lpt": 0, "xcd": 1}[tuning["order"]])
+        s2.set_walls(pps.wall, 1.4)
         u2 = s2.to_device(pc.u0)
         st2 = api.Stepper(s2, u2, s2.to_device(pps.metric), pc.ref, W={k: t(v) for k, v in pc.mlp.items()},
                           dirichlet_mask=s2.to_device(pps.dirichlet), dirichlet_state=synth.freestream(pc.mach))
@@ -332,7 +334,8 @@ def main():
         torch.cuda.synchronize()
         ms2 = e0.elapsed_time(e1) / args.steps
         paper = {"workload": f"annulus, {pps.npatch} subpatches of 101 x 101 (48 sectors x 32 shells), d 2, "
-                             f"C 27 (L 128), fringe glue, Dirichlet inflow, network every step",
+                             f"C 27 (L 128), fringe glue, Dirichlet inflow, no-slip adiabatic cylinder wall, "
+                             f"network every step",
                  "points": int(pps.npoints), "value": pps.npoints * 5 / (ms2 / 1e3), "unit": "grid-pt RK-stages/s",
                  "ms_per_step": ms2, "finite": bool(torch.isfinite(u2).all().item())}
         s2.close()

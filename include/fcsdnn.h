@@ -175,6 +175,23 @@ fcsd_status fcsd_filter(fcsd_ctx* ctx, const fcsd_set* set, const float* u, floa
 fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* out_bar,
                             float* u_bar, int64_t plane, float gamma, void* ws, size_t ws_bytes);
 
+/* No-slip adiabatic walls (paper Remarks adiabatic_th, adiabatic; Neumann
+ * data in the FC continuation, Sec. 2.2).  sides: [npatch][4] flags
+ * (q1-, q1+, q2-, q2+; NULL clears every wall).  At every glue (fcsd_glue,
+ * every stage of fcsd_step), after the fringe exchange and the Dirichlet
+ * overwrite, each point of a wall line gets rho u = rho v = 0 and
+ * E = rho theta_w / (gamma - 1), theta_w the value at the wall of the
+ * polynomial of degree < d through theta = p / rho at the d - 1 points next
+ * to the wall along the grid line that meets it, with zero derivative at
+ * the wall (the Neumann continuation's boundary value); rho is left to
+ * evolve.  The derivatives of E inside the right-hand side are those of its
+ * FC expansion (the paper differentiates theta's Neumann expansion and
+ * rebuilds E's derivatives by the product rule).  No reverse mode
+ * (fcsd_glue_adj, fcsd_step_adj return FCSD_EUNSUPPORTED on such sets);
+ * walls on two sides of one patch that meet at a corner are refused the
+ * same way.  Host-side set-up, synchronises the context's stream. */
+fcsd_status fcsd_set_walls(fcsd_set* set, const uint8_t* sides, float gamma);
+
 /* Map of a patch's grid to the plane: kind 0 Cartesian, (x, y) = (a0 + i da,
  * b0 + j db); kind 1 polar, (theta, r) = (a0 + i da, b0 + j db) and
  * (x, y) = r (cos theta, sin theta). */

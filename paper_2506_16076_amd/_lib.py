@@ -101,6 +101,7 @@ def lib():
             "fcsd_set_filter": [vp, ctypes.c_double, i32],
             "fcsd_filter": [vp, vp, vp, vp, i64, f32],
             "fcsd_set_interp": [vp, vp, i32, P(i64)],
+            "fcsd_set_walls": [vp, vp, f32],
             "fcsd_smear": [vp, vp, vp, vp, vp, i64, f32, ctypes.c_double, i32, ctypes.c_double, ctypes.c_double,
                            vp, sz],
             "fcsd_filter_adj": [vp, vp, vp, vp, vp, i64, f32, vp, sz],
@@ -147,7 +148,7 @@ def lib():
 # the names every header declaration exports (checked by the CPU tests)
 EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_last_error",
            "fcsd_ctx_stream", "fcsd_ctx_sync", "fcsd_set_create", "fcsd_set_destroy", "fcsd_set_tune",
-           "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj", "fcsd_smear", "fcsd_set_interp",
+           "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj", "fcsd_smear", "fcsd_set_interp", "fcsd_set_walls",
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
            "rk_stage_adj", "fcsd_cfl_dt", "sdnn_infer", "av_viscosity", "av_viscosity_adj",

@@ -157,6 +157,17 @@ class PatchSet:
         self.ctx.check(lib().fcsd_set_filter(self.h, float(alpha), int(p)), "fcsd_set_filter")
         self.filter_params = (float(alpha), int(p))
 
+    def set_walls(self, sides, gamma: float = 1.4):
+        """No-slip adiabatic wall sides: [npatch, 4] flags (q1-, q1+, q2-,
+        q2+), or None to clear."""
+        if sides is None:
+            self.ctx.check(lib().fcsd_set_walls(self.h, None, float(gamma)), "fcsd_set_walls")
+            return
+        arr = np.ascontiguousarray(np.asarray(sides, np.uint8).reshape(-1, 4))
+        self._walls = arr
+        self.ctx.check(lib().fcsd_set_walls(self.h, arr.ctypes.data_as(ctypes.c_void_p), float(gamma)),
+                       "fcsd_set_walls")
+
     def set_interp(self, maps, nf: int = 5) -> int:
         """Inter-patch interpolation of the fringe (paper Sec. 3.4.1) from
         patch maps: rows (kind, a0, da, b0, db), kind 0 Cartesian, 1 polar.

@@ -84,6 +84,10 @@ struct fcsd_set {
   int filter_on = 0;
   double filter_alpha = 0.0;
   int filter_p = 0;
+  WallDev* d_walls = nullptr;             // no-slip adiabatic wall sides (fcsd_set_walls)
+  int nwalls = 0, wall_len = 0;
+  float* d_wall_c = nullptr;              // Neumann boundary-value weights c[0..d-1]
+  float wall_g1 = 0.4f;
   InterpDev* d_interp = nullptr;          // inter-patch interpolation table (fcsd_set_interp)
   int ninterp = 0;
   OvlTarget* d_ovl = nullptr;             // smoothing operator across those patches
@@ -628,6 +632,8 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_tw);
   hipFree(s->d_km);
   hipFree(s->d_kf);
+  hipFree(s->d_walls);
+  hipFree(s->d_wall_c);
   hipFree(s->d_interp);
   hipFree(s->d_ovl);
   hipFree(s->d_ovl_src);
@@ -1101,6 +1107,10 @@ fcsd_status glue_impl(fcsd_ctx* ctx, const fcsd_set* s, float* u, const uint8_t*
   if (mask)
     hipLaunchKernelGGL(k_dirichlet, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, mask, u,
                        (long long)s->plane, st4[0], st4[1], st4[2], st4[3]);
+  if (s->nwalls > 0)
+    hipLaunchKernelGGL(k_wall, dim3(blocks_for((long long)s->nwalls * s->wall_len)), dim3(kBlock), 0, ctx->stream,
+                       s->d_walls, s->nwalls, s->wall_len, s->d_patches, u, (long long)s->plane, s->wall_g1, s->d,
+                       (const float*)s->d_wall_c);
   return launch_check(ctx, "glue");
 }
 
@@ -1138,6 +1148,7 @@ extern "C" fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* s, float* u_
   if (st) return st;
   if (!u_bar || (dirichlet_mask && (!dstate_dparam || !dparam_dev)))
     return fail(ctx, FCSD_EINVAL, "fcsd_glue_adj: null argument");
+  if (s->nwalls > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_glue_adj: no reverse mode of the wall condition");
   return glue_adj_impl(ctx, s, u_bar, dirichlet_mask, dstate_dparam, dparam_dev);
 }
 
@@ -1331,6 +1342,68 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   if (e != hipSuccess) return fail(ctx, FCSD_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
   ms->graphs.push_back(g);
   HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_set_walls(fcsd_set* s, const uint8_t* sides, float gamma) {
+  if (!s) return FCSD_EINVAL;
+  fcsd_ctx* ctx = s->ctx;
+  if (!(gamma > 1.0f)) return fail(ctx, FCSD_EINVAL, "fcsd_set_walls: need gamma > 1");
+  std::vector<WallDev> walls;
+  int len = 0;
+  if (sides)
+    for (int p = 0; p < s->npatch; ++p) {
+      const uint8_t* f = sides + 4 * p;
+      if ((f[0] || f[1]) && (f[2] || f[3]))
+        return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_set_walls: walls that meet at a corner of patch " + std::to_string(p));
+      for (int side = 0; side < 4; ++side)
+        if (sides[4 * p + side]) {
+          const fcsd_patch_desc& q = s->desc[p];
+          if ((side < 2 ? q.n1 : q.n2) < s->d + 1)
+            return fail(ctx, FCSD_EINVAL, "fcsd_set_walls: patch too short across its wall");
+          walls.push_back(WallDev{p, side});
+          len = std::max(len, side < 2 ? q.n2 : q.n1);
+        }
+    }
+  // Neumann boundary value: p(0) = c[0] g + sum_{k=1}^{d-1} c[k] F_k for the
+  // polynomial of degree < d with p(k) = F_k and p'(0) = g (grid units);
+  // a_0 of the solution of the d x d system, by Gaussian elimination with
+  // partial pivoting in long double
+  const int d = s->d;
+  std::vector<float> c(d, 0.f);
+  for (int col = 0; col < d; ++col) {  // c[col]: a_0 for the data unit vector e_col
+    long double A[8][9];
+    for (int r = 0; r < d; ++r)
+      for (int m = 0; m < d; ++m) A[r][m] = r < d - 1 ? std::pow((long double)(r + 1), m) : (m == 1 ? 1.0L : 0.0L);
+    for (int r = 0; r < d; ++r)  // right-hand side: rows 0..d-2 the values F_1..F_{d-1}, row d-1 g
+      A[r][d] = (col == 0 ? r == d - 1 : r == col - 1) ? 1.0L : 0.0L;
+    for (int k = 0; k < d; ++k) {
+      int piv = k;
+      for (int r = k + 1; r < d; ++r)
+        if (std::fabs(A[r][k]) > std::fabs(A[piv][k])) piv = r;
+      for (int m = 0; m <= d; ++m) std::swap(A[k][m], A[piv][m]);
+      for (int r = 0; r < d; ++r)
+        if (r != k) {
+          const long double f = A[r][k] / A[k][k];
+          for (int m = k; m <= d; ++m) A[r][m] -= f * A[k][m];
+        }
+    }
+    c[col] = (float)(A[0][d] / A[0][0]);
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& g : s->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
+  (void)hipFree(s->d_walls);
+  (void)hipFree(s->d_wall_c);
+  s->d_walls = nullptr;
+  s->d_wall_c = nullptr;
+  s->nwalls = 0;
+  fcsd_status r;
+  if ((r = upload(ctx, &s->d_walls, walls)) || (r = upload(ctx, &s->d_wall_c, c))) return r;
+  s->nwalls = (int)walls.size();
+  s->wall_len = len;
+  s->wall_g1 = gamma - 1.0f;
   return FCSD_OK;
 }
 
@@ -1656,6 +1729,7 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   if (visc_net && (!a->tau || !a->mu || !a->argmax))
     return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: classes need tau, mu and argmax buffers");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: workspace too small");
+  if (s->nwalls > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_step_adj: no reverse mode of the wall condition");
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: filter not configured (fcsd_set_filter)");
   const long long pl = s->plane, n4 = 4 * pl;
   float* w = (float*)ws;

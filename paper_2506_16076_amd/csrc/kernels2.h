@@ -97,6 +97,51 @@ __global__ void __launch_bounds__(kBlock) k_interp_adj(const InterpDev* __restri
     for (int a = 0; a < 3; ++a) atomicAdd(v + pidx(D, e.di - 1 + a, e.dj - 1 + b), wt[b] * ws[a] * g);
 }
 
+// ---------------------------------------------------------------- walls
+
+// A wall side of a patch: patch index and side (q1-, q1+, q2-, q2+).
+struct WallDev {
+  int patch, side;
+};
+
+// No-slip adiabatic wall (paper Remarks adiabatic_th, adiabatic): on every
+// point of a wall line, rho u = rho v = 0 and E = rho theta_w / (gamma - 1)
+// with theta_w the Neumann FC boundary value of theta = p / rho for a zero
+// normal derivative: sum_k c[k] theta_k over the d - 1 points next to the
+// wall along the grid line that meets it.  One thread per (wall, position
+// along the wall).  A patch has walls on opposite sides at most (the host
+// refuses two walls that meet at a corner), so no thread reads a point
+// another thread writes.
+__global__ void __launch_bounds__(kBlock) k_wall(const WallDev* __restrict__ walls, int nwall, int maxlen,
+                                                 const PatchDev* __restrict__ patches, float* u, long long pl,
+                                                 float g1, int d, const float* __restrict__ c) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)nwall * maxlen) return;
+  const int wi = (int)(k / maxlen), t = (int)(k - (long long)wi * maxlen);
+  const WallDev w = walls[wi];
+  const PatchDev P = patches[w.patch];
+  const int len = w.side < 2 ? P.n2 : P.n1;
+  if (t >= len) return;
+  auto at_k = [&](int kk) {
+    switch (w.side) {
+      case 0: return pidx(P, kk, t);
+      case 1: return pidx(P, P.n1 - 1 - kk, t);
+      case 2: return pidx(P, t, kk);
+      default: return pidx(P, t, P.n2 - 1 - kk);
+    }
+  };
+  float th = 0.f;
+  for (int kk = 1; kk < d; ++kk) {
+    const long long g = at_k(kk);
+    const float rho = u[g], m = u[pl + g], n = u[2 * pl + g], E = u[3 * pl + g];
+    th = fmaf(c[kk], g1 * (E - 0.5f * (m * m + n * n) / rho) / rho, th);
+  }
+  const long long g0 = at_k(0);
+  u[pl + g0] = 0.f;
+  u[2 * pl + g0] = 0.f;
+  u[3 * pl + g0] = u[g0] * th / g1;
+}
+
 // Blending window of the initial-data smearing (paper Sec. 4.3.2, eq. qf)
 // along DIR, one thread per line of one patch (blockIdx.y): a discontinuity
 // sits between neighbours whose region labels differ.  A forward sweep

@@ -602,6 +602,60 @@ def test_interpolated_glue_and_step_reverse_mode(env):
     s.close()
 
 
+# ------------------------------------------------------------------ walls
+
+def test_wall_condition(env):
+    """fcsd_set_walls + fcsd_glue (with the fringe copies and the Dirichlet
+    inflow) against the oracle's glue on the annulus with its inner circle
+    a wall: momenta zero there, E from the Neumann temperature (relative
+    1e-6)."""
+    from oracle import wall
+    api, ctx, torch = env
+    cfg = synth.with_cylinder_wall(synth.config(1, n=48))
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, 1)
+    s.set_walls(ps.wall, G)
+    x = noisy_state(ps, cfg.u0, 8, amp=1e-2)
+    xd = D(x)
+    api.fcsd_glue(s, xd, D(ps.dirichlet), synth.freestream(cfg.mach))
+    got = H(xd).reshape(4, -1)
+    want = x.astype(np.float64).copy()
+    solver.glue(want, ps, cfg.mach, G)
+    err = np.abs(got - want).max(axis=1) / np.abs(want).max(axis=1)
+    say("wall glue max rel error", err)
+    assert np.all(err[[0, 1, 3]] <= 1e-6) and np.abs(got[2] - want[2]).max() <= 1e-6 * np.abs(want[1]).max()
+    for p in range(ps.npatch):
+        if ps.wall[p, 2]:
+            assert np.all(ps.view(got, p)[1:3, 0] == 0)
+    s.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_steps_with_cylinder_wall(env, layout):
+    """Three network steps on the annulus with the no-slip adiabatic
+    cylinder wall, fringe copies and the Dirichlet inflow, against the
+    oracle replaying the GPU's decisions (state <= 1e-4)."""
+    api, ctx, torch = env
+    cfg = synth.with_cylinder_wall(synth.config(1, n=48))
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, layout)
+    s.set_walls(ps.wall, G)
+    u = D(cfg.u0)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W, dirichlet_mask=D(ps.dirichlet),
+                     dirichlet_state=synth.freestream(cfg.mach))
+    run = solver.Run(cfg)
+    for k in range(3):
+        st.step(use_graph=(k > 0))
+        run.step(dt=float(host(st.dt)[0]), tau=H(st.tau), arg=H(st.argmax))
+    err = relerr_phys(ps, H(u).reshape(4, -1), run.u)
+    say("3 steps with the cylinder wall layout", layout, "state rel L2", err)
+    assert np.all(err < STEP_TOL)
+    with pytest.raises(api.FcsdError):
+        st.step_adj(u.clone(), torch.zeros_like(u), st.tau, st.dt)
+    s.close()
+
+
 # ------------------------------------------------------------------ adjoints
 
 @pytest.mark.parametrize("case", ["square64", "shells"])
