@@ -21,16 +21,19 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle import av, euler, interp, rk, solver
+from oracle import av, euler, interp, rk, solver, wall
 from oracle import filter as spectral_filter
 
 
-def glue_vjp(eb, ps, mach, gamma=1.4):
+def glue_vjp(eb, ps, mach, gamma=1.4, e_glued=None):
     """In-place transpose of solver.glue on a cotangent [4, plane]; returns
-    the derivative with respect to the free-stream Mach number."""
+    the derivative with respect to the free-stream Mach number.  e_glued:
+    the glued state (needed with walls, whose condition is not linear)."""
     dM = 0.0
     if getattr(ps, "wall", None) is not None and ps.wall.any():
-        raise NotImplementedError("reverse mode of the wall condition")
+        if e_glued is None:
+            raise ValueError("the wall condition's reverse mode needs the glued state")
+        wall.apply_vjp(eb, e_glued, ps, gamma)
     if ps.nsec == 0:
         if ps.geom is not None:
             if getattr(ps, "_interp_table", None) is None:
@@ -101,17 +104,17 @@ def step_vjp(run, entry, ub_next):
         ub[i] += eb
         mub += mb
         if i >= 1:
-            dM += glue_vjp(ub[i], ps, mach, g)
+            dM += glue_vjp(ub[i], ps, mach, g, st[i])
             distribute(i, ub[i])
     u_visc = st[0]
     if entry.get("filt") is not None:
         alpha, p = entry["filt"]
-        dM += glue_vjp(ub[0], ps, mach, g)
+        dM += glue_vjp(ub[0], ps, mach, g, st[0])
         ub[0] = spectral_filter.filter_state_vjp(entry["pre"], ub[0], ps, alpha, p, g)
         u_visc = entry["pre"]
     if visc:
         ub[0] += av.viscosity_vjp(u_visc, entry["tau"], entry["arg"], ps, g, mub)
-    dM += glue_vjp(ub[0], ps, mach, g)
+    dM += glue_vjp(ub[0], ps, mach, g, u_visc)
     return ub[0], dM
 
 

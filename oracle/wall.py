@@ -27,7 +27,7 @@ Readings:
     condition), not rebuilt by the product rule from a Neumann expansion of
     theta as Remark adiabatic describes -- a simplification of this build;
   * wall points are set after the fringe exchange and the Dirichlet
-    overwrite.
+    overwrite (so the reverse mode transposes them first).
 """
 from __future__ import annotations
 
@@ -84,3 +84,43 @@ def apply(e, ps, gamma=1.4):
             line(v[2], 0)[...] = 0.0
             line(v[3], 0)[...] = rho_w * th / g1
     return e
+
+
+def apply_vjp(eb, e_glued, ps, gamma=1.4):
+    """In-place transpose of apply at the state it produced (e_glued: the
+    wall leaves rho and every point off the wall line as it found them, so
+    its inputs are read there).  The momenta and E of a wall point are
+    overwritten: their cotangents are dropped; rho_w gets theta_w / (gamma
+    - 1) times E_w's cotangent, and each interior point k the Neumann weight
+    c_k times rho_w / (gamma - 1) times E_w's cotangent times d theta_k / d e_k."""
+    if getattr(ps, "wall", None) is None:
+        return eb
+    c = neumann_weights(ps.d)
+    g1 = gamma - 1.0
+    for p in range(ps.npatch):
+        for side in range(4):
+            if not ps.wall[p, side]:
+                continue
+            v = ps.view(e_glued, p)
+            b = ps.view(eb, p)
+            line = wall_lines(ps, p, side)
+            rho_w = line(v[0], 0)
+            Eb = line(b[3], 0).copy()
+            th = np.zeros_like(rho_w)
+            for k in range(1, ps.d):
+                rho, m, n, E = (line(v[f], k) for f in range(4))
+                th += c[k] * g1 * (E - 0.5 * (m * m + n * n) / rho) / rho
+            line(b[0], 0)[...] += Eb * th / g1
+            line(b[1], 0)[...] = 0.0
+            line(b[2], 0)[...] = 0.0
+            line(b[3], 0)[...] = 0.0
+            tb = Eb * rho_w / g1               # cotangent of theta_w
+            for k in range(1, ps.d):
+                rho, m, n, E = (line(v[f], k) for f in range(4))
+                tk = c[k] * tb
+                # theta = g1 (E / rho - (m^2 + n^2) / (2 rho^2))
+                line(b[0], k)[...] += tk * g1 * (-E / rho ** 2 + (m * m + n * n) / rho ** 3)
+                line(b[1], k)[...] += -tk * g1 * m / rho ** 2
+                line(b[2], k)[...] += -tk * g1 * n / rho ** 2
+                line(b[3], k)[...] += tk * g1 / rho
+    return eb

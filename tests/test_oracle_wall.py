@@ -59,3 +59,47 @@ def test_wall_condition_on_the_inner_circle():
         assert np.all(a[1, 0] == 0) and np.all(a[2, 0] == 0)  # no slip
         th_w = a[3, 0] * (gamma - 1) / a[0, 0]
         assert np.abs(th_w - 0.9).max() <= 1e-12          # the exact zero-slope value
+
+
+def test_wall_transpose_and_step_reverse_mode():
+    """The wall condition's VJP against central differences of the glue,
+    and one network step with the cylinder wall against central differences
+    of the step map (decisions frozen)."""
+    from oracle import adjoint, solver
+    gamma = 1.4
+    cfg = synth.with_cylinder_wall(synth.config(1, n=40))
+    ps = cfg.ps
+    rng = np.random.default_rng(1)
+    e = cfg.u0.astype(np.float64) * (1 + 0.01 * rng.standard_normal((4, ps.plane)))
+    w = rng.standard_normal((4, ps.plane))
+
+    def glued(x):
+        y = x.copy()
+        solver.glue(y, ps, cfg.mach, gamma)
+        return y
+
+    g = glued(e)
+    wb = w.copy()
+    adjoint.glue_vjp(wb, ps, cfg.mach, gamma, g)
+    h = 1e-6
+    for _ in range(2):
+        v = rng.standard_normal(e.shape) * np.abs(e).max(axis=1, keepdims=True)
+        fd = np.sum((glued(e + h * v) - glued(e - h * v)) * w) / (2 * h)
+        assert abs(fd - np.sum(wb * v)) <= 1e-6 * abs(fd)
+    run = solver.Run(cfg)
+    u0 = run.u.copy()
+    run.step(record=True)
+    entry = run.log[-1]
+
+    def F(u):
+        r = solver.Run(cfg)
+        r.u = u.copy()
+        r.step(dt=entry["dt"], tau=entry["tau"], arg=entry["arg"])
+        return r.u
+
+    ub, _ = adjoint.step_vjp(run, entry, w)
+    for _ in range(2):
+        v = rng.standard_normal(u0.shape) * np.abs(u0).max(axis=1, keepdims=True)
+        fd = np.sum((F(u0 + h * v) - F(u0 - h * v)) * w) / (2 * h)
+        an = np.sum(ub * v)
+        assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
