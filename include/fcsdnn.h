@@ -186,10 +186,11 @@ fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, 
  * the wall (the Neumann continuation's boundary value); rho is left to
  * evolve.  The derivatives of E inside the right-hand side are those of its
  * FC expansion (the paper differentiates theta's Neumann expansion and
- * rebuilds E's derivatives by the product rule).  No reverse mode
- * (fcsd_glue_adj, fcsd_step_adj return FCSD_EUNSUPPORTED on such sets);
- * walls on two sides of one patch that meet at a corner are refused the
- * same way.  Host-side set-up, synchronises the context's stream. */
+ * rebuilds E's derivatives by the product rule).  The wall condition is not
+ * linear: fcsd_step_adj transposes it at the glued states it keeps, while
+ * fcsd_glue_adj, which has no state, returns FCSD_EUNSUPPORTED on such
+ * sets; walls on two sides of one patch that meet at a corner are refused
+ * the same way.  Host-side set-up, synchronises the context's stream. */
 fcsd_status fcsd_set_walls(fcsd_set* set, const uint8_t* sides, float gamma);
 
 /* Map of a patch's grid to the plane: kind 0 Cartesian, (x, y) = (a0 + i da,

@@ -1116,7 +1116,13 @@ fcsd_status glue_impl(fcsd_ctx* ctx, const fcsd_set* s, float* u, const uint8_t*
 
 // transpose of glue_impl: Dirichlet, shells, sectors
 fcsd_status glue_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, float* ub, const uint8_t* mask, const float* ds4,
-                          double* dparam) {
+                          double* dparam, const float* glued = nullptr) {
+  if (s->nwalls > 0) {
+    if (!glued) return fail(ctx, FCSD_EUNSUPPORTED, "glue reverse mode: the wall condition needs the glued state");
+    hipLaunchKernelGGL(k_wall_adj, dim3(blocks_for((long long)s->nwalls * s->wall_len)), dim3(kBlock), 0,
+                       ctx->stream, s->d_walls, s->nwalls, s->wall_len, s->d_patches, glued, ub, (long long)s->plane,
+                       s->wall_g1, s->d, (const float*)s->d_wall_c);
+  }
   if (mask)
     hipLaunchKernelGGL(k_dirichlet_adj, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, mask, ub,
                        (long long)s->plane, ds4[0], ds4[1], ds4[2], ds4[3], dparam);
@@ -1148,7 +1154,9 @@ extern "C" fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* s, float* u_
   if (st) return st;
   if (!u_bar || (dirichlet_mask && (!dstate_dparam || !dparam_dev)))
     return fail(ctx, FCSD_EINVAL, "fcsd_glue_adj: null argument");
-  if (s->nwalls > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_glue_adj: no reverse mode of the wall condition");
+  if (s->nwalls > 0)
+    return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_glue_adj: the wall condition's reverse mode needs the glued state "
+                                        "(fcsd_step_adj has it)");
   return glue_adj_impl(ctx, s, u_bar, dirichlet_mask, dstate_dparam, dparam_dev);
 }
 
@@ -1729,7 +1737,6 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   if (visc_net && (!a->tau || !a->mu || !a->argmax))
     return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: classes need tau, mu and argmax buffers");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_STEP_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: workspace too small");
-  if (s->nwalls > 0) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_step_adj: no reverse mode of the wall condition");
   if (a->filter && !s->filter_on) return fail(ctx, FCSD_EINVAL, "fcsd_step_adj: filter not configured (fcsd_set_filter)");
   const long long pl = s->plane, n4 = 4 * pl;
   float* w = (float*)ws;
@@ -1794,7 +1801,7 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
     if ((st = rhs_adj_impl(ctx, s, stg(k), a->metric, mu, a->ref, a->gamma, RB, tgt, mu ? MUB : nullptr, RWS, g1, g2)))
       return st;
     if (k > 0) {
-      if ((st = glue_adj_impl(ctx, s, uib, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;
+      if ((st = glue_adj_impl(ctx, s, uib, a->dirichlet_mask, dstate_dparam, dparam_dev, stg(k)))) return st;
       float* t = yb;
       yb = uib;
       uib = t;
@@ -1802,7 +1809,7 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   }
   const float* vin = stg(0);
   if (a->filter) {
-    if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;
+    if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev, stg(0)))) return st;
     if ((st = filter_adj_impl(ctx, s, PRE, U0B, U0B, a->gamma, RWS))) return st;
     vin = PRE;
   }
@@ -1810,7 +1817,7 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
     if ((st = av_viscosity_adj(ctx, s, vin, a->tau, amax, a->gamma, MUB, U0B, plane, w + 73 * pl,
                                ws_bytes_of(s, FCSD_WS_AV))))
       return st;
-  if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev))) return st;
+  if ((st = glue_adj_impl(ctx, s, U0B, a->dirichlet_mask, dstate_dparam, dparam_dev, vin))) return st;
   HIPCHK(ctx, hipMemcpyAsync(u_bar, U0B, n4 * sizeof(float), hipMemcpyDeviceToDevice, sm));
   return launch_check(ctx, "fcsd_step_adj");
 }

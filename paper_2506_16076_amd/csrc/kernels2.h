@@ -142,6 +142,54 @@ __global__ void __launch_bounds__(kBlock) k_wall(const WallDev* __restrict__ wal
   u[3 * pl + g0] = u[g0] * th / g1;
 }
 
+// Transpose of k_wall at the state it produced (eg: the glued state, whose
+// wall-point rho and interior points the wall left as it found them): the
+// overwritten momenta and energy drop their cotangents, rho_w gets
+// theta_w / (gamma - 1) times E_w's cotangent, and every interior point the
+// Neumann weight times rho_w / (gamma - 1) times E_w's cotangent through
+// d theta / d e.  Same threads and exclusivity as k_wall.
+__global__ void __launch_bounds__(kBlock) k_wall_adj(const WallDev* __restrict__ walls, int nwall, int maxlen,
+                                                     const PatchDev* __restrict__ patches, const float* eg, float* ub,
+                                                     long long pl, float g1, int d, const float* __restrict__ c) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)nwall * maxlen) return;
+  const int wi = (int)(k / maxlen), t = (int)(k - (long long)wi * maxlen);
+  const WallDev w = walls[wi];
+  const PatchDev P = patches[w.patch];
+  const int len = w.side < 2 ? P.n2 : P.n1;
+  if (t >= len) return;
+  auto at_k = [&](int kk) {
+    switch (w.side) {
+      case 0: return pidx(P, kk, t);
+      case 1: return pidx(P, P.n1 - 1 - kk, t);
+      case 2: return pidx(P, t, kk);
+      default: return pidx(P, t, P.n2 - 1 - kk);
+    }
+  };
+  float th = 0.f;
+  for (int kk = 1; kk < d; ++kk) {
+    const long long g = at_k(kk);
+    const float rho = eg[g], m = eg[pl + g], n = eg[2 * pl + g], E = eg[3 * pl + g];
+    th = fmaf(c[kk], g1 * (E - 0.5f * (m * m + n * n) / rho) / rho, th);
+  }
+  const long long g0 = at_k(0);
+  const float Eb = ub[3 * pl + g0];
+  const float tb = Eb * eg[g0] / g1;
+  ub[g0] += Eb * th / g1;
+  ub[pl + g0] = 0.f;
+  ub[2 * pl + g0] = 0.f;
+  ub[3 * pl + g0] = 0.f;
+  for (int kk = 1; kk < d; ++kk) {
+    const long long g = at_k(kk);
+    const float rho = eg[g], m = eg[pl + g], n = eg[2 * pl + g], E = eg[3 * pl + g];
+    const float tk = c[kk] * tb * g1, ir = 1.0f / rho, ir2 = ir * ir;
+    ub[g] += tk * (-E * ir2 + (m * m + n * n) * ir2 * ir);
+    ub[pl + g] -= tk * m * ir2;
+    ub[2 * pl + g] -= tk * n * ir2;
+    ub[3 * pl + g] += tk * ir;
+  }
+}
+
 // Blending window of the initial-data smearing (paper Sec. 4.3.2, eq. qf)
 // along DIR, one thread per line of one patch (blockIdx.y): a discontinuity
 // sits between neighbours whose region labels differ.  A forward sweep

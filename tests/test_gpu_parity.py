@@ -652,7 +652,40 @@ def test_steps_with_cylinder_wall(env, layout):
     say("3 steps with the cylinder wall layout", layout, "state rel L2", err)
     assert np.all(err < STEP_TOL)
     with pytest.raises(api.FcsdError):
-        st.step_adj(u.clone(), torch.zeros_like(u), st.tau, st.dt)
+        api.fcsd_glue_adj(s, torch.zeros_like(u))      # no state: refused with walls
+    s.close()
+
+
+def test_step_reverse_mode_with_cylinder_wall(env):
+    """One network step's reverse mode with the cylinder wall against the
+    oracle's step VJP at the GPU's decisions (relative L2 <= 1e-4)."""
+    from oracle import adjoint
+    api, ctx, torch = env
+    cfg = synth.with_cylinder_wall(synth.config(1, n=48))
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, 1)
+    s.set_walls(ps.wall, G)
+    u = D(cfg.u0)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W, dirichlet_mask=D(ps.dirichlet),
+                     dirichlet_state=synth.freestream(cfg.mach))
+    st.step()                       # a state that has met the wall once
+    u_in = u.clone()
+    st.step()
+    tau, dt, arg = st.tau.clone(), st.dt.clone(), H(st.argmax)
+    rng = np.random.default_rng(23)
+    w = rng.standard_normal((4, ps.plane)).astype(np.float32)
+    ub = D(w)
+    dpar = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    st.step_adj(u_in, ub, tau, dt, (0.0, 1.4, 0.0, 1.4 * cfg.mach), dpar)
+    run = solver.Run(cfg)
+    run.u = H(u_in).reshape(4, -1).astype(np.float64)
+    run.step(dt=float(host(dt)[0]), tau=H(tau), arg=arg, record=True)
+    want, dM = adjoint.step_vjp(run, run.log[-1], w.astype(np.float64))
+    err = relerr_phys(ps, H(ub).reshape(4, -1), want)
+    say("step reverse mode with the cylinder wall rel L2", err, "dM gpu", float(dpar), "oracle", dM)
+    assert np.all(err < 1e-4)
+    assert abs(float(dpar) - dM) <= 1e-4 * abs(dM)
     s.close()
 
 
