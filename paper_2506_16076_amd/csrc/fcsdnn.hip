@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
@@ -1427,6 +1428,53 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
   int minside = 1 << 30;
   for (const fcsd_patch_desc& q : s->desc) minside = std::min(minside, std::min(q.n1, q.n2));
   if (nf < 1 || 2 * nf + 3 > minside) return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: fringe width out of range");
+  // physical bounding box of every patch (its boundary sampled at the grid
+  // points, a polar side's arc also at the axis crossings it spans), to skip
+  // the preimage of patches that cannot hold a point
+  std::vector<std::array<double, 4>> box(np);
+  for (int p = 0; p < np; ++p) {
+    const fcsd_patch_desc& q = s->desc[p];
+    const fcsd_patch_map& m = maps[p];
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    auto add = [&](double x, double y) {
+      x0 = std::min(x0, x);
+      x1 = std::max(x1, x);
+      y0 = std::min(y0, y);
+      y1 = std::max(y1, y);
+    };
+    auto pt = [&](double i, double j) {
+      if (m.kind == 0) {
+        add(m.a0 + i * m.da, m.b0 + j * m.db);
+      } else {
+        const double th = m.a0 + i * m.da, r = m.b0 + j * m.db;
+        add(r * std::cos(th), r * std::sin(th));
+      }
+    };
+    for (int i = 0; i < q.n1; ++i) {
+      pt(i, 0);
+      pt(i, q.n2 - 1);
+    }
+    for (int j = 0; j < q.n2; ++j) {
+      pt(0, j);
+      pt(q.n1 - 1, j);
+    }
+    if (m.kind == 1) {  // axis crossings inside the angular range
+      const double t0 = m.a0, t1 = m.a0 + (q.n1 - 1) * m.da, rmax = m.b0 + (q.n2 - 1) * m.db;
+      for (int k = -8; k <= 8; ++k) {
+        const double a = k * 0.5 * 3.14159265358979323846;
+        if (a > t0 && a < t1) add(rmax * std::cos(a), rmax * std::sin(a));
+      }
+    }
+    // generous margin: two grid spacings (covers the bulge of an arc between
+    // its sampled points); the box only spares work
+    const double hmax = m.kind == 0 ? std::max(m.da, m.db)
+                                    : std::max((m.b0 + (q.n2 - 1) * m.db) * m.da, m.db);
+    const double pad = 2.0 * hmax + 1e-9 * (1.0 + std::max(x1 - x0, y1 - y0));
+    box[p] = {x0 - pad, x1 + pad, y0 - pad, y1 + pad};
+  }
+  auto in_box = [&](int d, double x, double y) {
+    return x >= box[d][0] && x <= box[d][1] && y >= box[d][2] && y <= box[d][3];
+  };
   // fringe points: the nf grid lines nearest to every internal side
   auto recv = [&](int p, int i, int j) {
     const fcsd_patch_desc& q = s->desc[p];
@@ -1455,7 +1503,7 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
         int best = -1;
         double bd = 0.0, bxi = 0.0, beta = 0.0;
         for (int d = 0; d < np; ++d) {
-          if (d == p) continue;
+          if (d == p || !in_box(d, x, y)) continue;
           const fcsd_patch_map& dm = maps[d];
           double xi, eta;
           if (dm.kind == 0) {
@@ -1515,7 +1563,7 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
         }
         const int begin = (int)osrc.size();
         for (int d = 0; d < np; ++d) {
-          if (d == p) continue;
+          if (d == p || !in_box(d, x, y)) continue;
           const fcsd_patch_map& dm = maps[d];
           double xi, eta;
           if (dm.kind == 0) {
