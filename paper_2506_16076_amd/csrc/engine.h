@@ -255,6 +255,25 @@ __device__ __forceinline__ const T& at(const T* base, unsigned byte_off) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
+// Loads and stores of an LDS element at a byte offset from a pointer into
+// LDS, addressed in the LDS address space: 32-bit offset arithmetic and
+// ds_read / ds_write (a generic pointer's low 32 bits are its LDS offset;
+// through the generic pointer the compiler forms 64-bit addresses, with a
+// 64-bit multiply-add per twiddle).
+__device__ __forceinline__ float2 ld_lds(const float2* base, unsigned byte_off) {
+  typedef __attribute__((address_space(3))) const unsigned long long lU;
+  const unsigned long long v = *(lU*)(size_t)((unsigned)(size_t)base + byte_off);
+  float2 r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+__device__ __forceinline__ void st_lds(float2* base, unsigned byte_off, float2 x) {
+  typedef __attribute__((address_space(3))) unsigned long long lU;
+  unsigned long long v;
+  __builtin_memcpy(&v, &x, sizeof(v));
+  *(lU*)(size_t)((unsigned)(size_t)base + byte_off) = v;
+}
+
 // Visit the valid elements of a walk: f(g, l).
 template <class F>
 __device__ __forceinline__ void walk(Walk w, F&& f) {
@@ -320,28 +339,28 @@ __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
   for (; b < nb; b += X.BS) {
     float2 x[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) x[t] = at(X.z, a + t * leg);
+    for (int t = 0; t < R; ++t) x[t] = ld_lds(X.z, a + t * leg);
     // j = 0 reads twiddle 1 + 0i: the product is exact, so no branch
     if (!INV) {
       Dft<R, false>::run(x);
       if (MUL) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          const float2 k = at(X.km, kq + 8u * q);
+          const float2 k = ld_lds(X.km, kq + 8u * q);
           x[q] = CONJ ? cmulc(x[q], k) : cmul(x[q], k);
         }
         Dft<R, true>::run(x);
       } else {
 #pragma unroll
-        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], at(X.tw, q * tq));
+        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], ld_lds(X.tw, q * tq));
       }
     } else {
 #pragma unroll
-      for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], at(X.tw, q * tq));
+      for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], ld_lds(X.tw, q * tq));
       Dft<R, true>::run(x);
     }
 #pragma unroll
-    for (int t = 0; t < R; ++t) at(X.z, a + t * leg) = x[t];
+    for (int t = 0; t < R; ++t) st_lds(X.z, a + t * leg, x[t]);
     a += da;
     tq += dtw;
     kq += dk;
