@@ -1745,9 +1745,10 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
     const DirPlan& D = s->dir[1];
     PassArgs b = a;
     b.plans = D.d_plans;
-    b.tiles = D.ts[0].d_tiles;
-    hipLaunchKernelGGL(k_adjHb<2>, dim3((unsigned)D.ts[0].tiles.size()), dim3(D.ts[0].threads), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
-                       (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
+    b.tiles = D.ts[1].d_tiles;
+    hipLaunchKernelGGL(k_adjHb2p, dim3((unsigned)D.ts[1].tiles.size()), dim3(D.ts[1].threads), D.ts[1].lds,
+                       ctx->stream, b, rhs_bar, Hb, (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar,
+                       visc);
     if ((st = launch_check(ctx, "adj B2"))) return st;
   }
   if (visc) {

@@ -1336,4 +1336,129 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
   }
 }
 
+// k_adjHb<2> with two state components per transform (H_bar x,y of
+// component c at z[pos][l], of c + 1 at z[pos][nl + l]; tiles of the set
+// with two complex lines per grid line): the metric rows, mu and mu_bar are
+// read and written once per component pair instead of once per component,
+// which is what bounds this reverse pass (HBM traffic).
+__global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* Hb, const float* d1e,
+                                            const float* d2e, float* G1, float* G2, float* mub, float* ub,
+                                            int visc) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T2 = T;
+  T2.nl = 2 * T.nl;
+  const LineCtx X = line_setup(lds_z, T2, P, a.tw, a.km);
+  float2* __restrict__ z = X.z;
+  const int nl = T.nl, ld = T.ld;
+  __syncthreads();
+  const TileMem M = tile_mem<2>(P, T, nl, ld);
+  const long long pl = a.plane, bo = M.base;
+  const float* m1x = a.metric + bo;
+  const float* m1y = a.metric + pl + bo;
+  const float* m2x = a.metric + 2 * pl + bo;
+  const float* m2y = a.metric + 3 * pl + bo;
+  float2* __restrict__ zb = z + nl;
+  for (int comp = 0; comp < 4; comp += 2) {
+    const float* rb0 = rb + comp * pl + bo;
+    const float* rb1 = rb0 + pl;
+    struct RIn {
+      float r0, r1, mx, my;
+    };
+    walk_b<kEpiBatch>(
+        M.w, [&](unsigned g) { return RIn{at(rb0, g), at(rb1, g), at(m2x, g), at(m2y, g)}; },
+        [&](unsigned, unsigned l, const RIn& q) {
+          at(z, l) = make_float2(q.mx * q.r0, q.my * q.r0);
+          at(zb, l) = make_float2(q.mx * q.r1, q.my * q.r1);
+        });
+    __syncthreads();
+    line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
+    float* hb0 = Hb + (2 * comp) * pl + bo;   // x, y of comp; then of comp + 1
+    const long long fo = comp * pl + bo;
+    if (!visc) {
+      walk_b<kLoadBatch>(
+          M.w, [&](unsigned g) { return make_float4(at(hb0, g), at(hb0 + pl, g), at(hb0 + 2 * pl, g), at(hb0 + 3 * pl, g)); },
+          [&](unsigned g, unsigned l, float4 h) {
+            const float2 v = at(z, l), w = at(zb, l);
+            at(hb0, g) = h.x + v.x;
+            at(hb0 + pl, g) = h.y + v.y;
+            at(hb0 + 2 * pl, g) = h.z + w.x;
+            at(hb0 + 3 * pl, g) = h.w + w.y;
+          });
+    } else {
+      struct VIn2 {
+        float h[4], m1x, m1y, m2x, m2y, mu, d1[2], d2[2], mb;
+      };
+      float* mubp = mub ? mub + bo : nullptr;
+      walk_b<2>(
+          M.w,
+          [&](unsigned g) {
+            VIn2 q;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q.h[k] = at(hb0 + k * pl, g);
+            q.m1x = at(m1x, g);
+            q.m1y = at(m1y, g);
+            q.m2x = at(m2x, g);
+            q.m2y = at(m2y, g);
+            q.mu = at(a.mu + bo, g);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              q.d1[k] = mubp ? at(d1e + fo + k * pl, g) : 0.f;
+              q.d2[k] = mubp ? at(d2e + fo + k * pl, g) : 0.f;
+            }
+            q.mb = mubp ? at(mubp, g) : 0.f;
+            return q;
+          },
+          [&](unsigned g, unsigned l, const VIn2& q) {
+            const float2 v0 = at(z, l), v1 = at(zb, l);
+            const float hx[2] = {q.h[0] + v0.x, q.h[2] + v1.x}, hy[2] = {q.h[1] + v0.y, q.h[3] + v1.y};
+            float mb = q.mb;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              at(hb0 + (2 * k) * pl, g) = hx[k];
+              at(hb0 + (2 * k + 1) * pl, g) = hy[k];
+              at(G1 + fo + k * pl, g) = q.mu * (q.m1x * hx[k] + q.m1y * hy[k]);
+              at(G2 + fo + k * pl, g) = q.mu * (q.m2x * hx[k] + q.m2y * hy[k]);
+              const float ex = q.m1x * q.d1[k] + q.m2x * q.d2[k];
+              const float ey = q.m1y * q.d1[k] + q.m2y * q.d2[k];
+              mb = mb + hx[k] * ex + hy[k] * ey;
+            }
+            if (mubp) at(mubp, g) = mb;
+          });
+    }
+    __syncthreads();
+  }
+  if (a.mode != FLUX_VISC) {
+    struct FIn {
+      float e[4], fb[4], gb[4], ub[4];
+    };
+    walk_b<2>(
+        M.w,
+        [&](unsigned g) {
+          FIn q;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            q.e[k] = at(a.u + k * pl + bo, g);
+            q.fb[k] = at(Hb + (2 * k) * pl + bo, g);
+            q.gb[k] = at(Hb + (2 * k + 1) * pl + bo, g);
+            q.ub[k] = at(ub + k * pl + bo, g);
+          }
+          return q;
+        },
+        [&](unsigned g, unsigned, const FIn& q) {
+          float fb[4], gb[4], o[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            fb[k] = -q.fb[k];
+            gb[k] = -q.gb[k];
+          }
+          flux_vjp(q.e, a.gamma, fb, gb, o);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) at(ub + k * pl + bo, g) = q.ub[k] + o[k];
+        });
+  }
+}
+
 }  // namespace fcsd
