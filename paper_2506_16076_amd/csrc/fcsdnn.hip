@@ -1737,8 +1737,8 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
     PassArgs b = a;
     b.plans = D.d_plans;
     b.tiles = D.ts[0].d_tiles;
-    hipLaunchKernelGGL(k_adjHb<1>, dim3((unsigned)D.ts[0].tiles.size()), dim3(D.ts[0].threads), D.ts[0].lds, ctx->stream, b, rhs_bar, Hb,
-                       (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar, visc);
+    hipLaunchKernelGGL(k_adjHb1, dim3((unsigned)D.ts[0].tiles.size()), dim3(D.ts[0].threads), D.ts[0].lds,
+                       ctx->stream, b, rhs_bar, Hb);
     if ((st = launch_check(ctx, "adj C"))) return st;
   }
   {

@@ -1221,24 +1221,15 @@ __device__ __forceinline__ void flux_vjp(const float e[4], float gam, const floa
   out[3] = Eb + Pb * g1;
 }
 
-// Reverse of pass C / B2: Hb (+)= D_dir^T (m_dir,x rb, m_dir,y rb).
-// DIR = 2 additionally finishes H_bar and applies the pointwise reverse of
-// H = mu grad e - f': G1/G2 = mu-weighted metric products (for D^T later),
-// mu_bar += H_bar . grad e, u_bar += flux VJP of -H_bar.
-template <int DIR>
-__global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
-                                                  const float* d1e, const float* d2e, float* G1,
-                                                  float* G2, float* mub, float* ub, int visc) {
+// Reverse of pass C: Hb = D_1^T (m_1x rb, m_1y rb) for every state
+// component (q1 lines).  The reverse of pass B2, which also finishes H_bar
+// and applies the pointwise reverse of H = mu grad e - f', is k_adjHb2p.
+__global__ void FCSD_LINE_BOUNDS k_adjHb1(PassArgs a, const float* rb, float* Hb) {
   FCSD_TILE_BEGIN(a)
-  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  const TileMem M = tile_mem<1>(P, T, nl, ld);
   const long long pl = a.plane, bo = M.base;
-  const int mx = DIR == 1 ? 0 : 2, my = DIR == 1 ? 1 : 3;
-  const float* mdx = a.metric + mx * pl + bo;
-  const float* mdy = a.metric + my * pl + bo;
-  const float* m1x = a.metric + bo;
-  const float* m1y = a.metric + pl + bo;
-  const float* m2x = a.metric + 2 * pl + bo;
-  const float* m2y = a.metric + 3 * pl + bo;
+  const float* mdx = a.metric + bo;
+  const float* mdy = a.metric + pl + bo;
   // loads of the element loops are batched (walk_b): one element's loads
   // waited for before the next element's were issued made this kernel
   // latency-bound
@@ -1251,96 +1242,22 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb(PassArgs a, const float* rb, float* Hb,
     line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
     float* hbx = Hb + (2 * comp) * pl + bo;
     float* hby = Hb + (2 * comp + 1) * pl + bo;
-    const long long fo = comp * pl + bo;
-    if (DIR == 1) {
-      walk(M.w, [&](unsigned g, unsigned l) {
-        const float2 v = at(z, l);
-        at(hbx, g) = v.x;
-        at(hby, g) = v.y;
-      });
-    } else if (!visc) {
-      walk_b<kLoadBatch>(
-          M.w, [&](unsigned g) { return make_float2(at(hbx, g), at(hby, g)); },
-          [&](unsigned g, unsigned l, float2 h) {
-            const float2 v = at(z, l);
-            at(hbx, g) = h.x + v.x;
-            at(hby, g) = h.y + v.y;
-          });
-    } else {
-      struct VIn {
-        float hx, hy, m1x, m1y, m2x, m2y, mu, d1, d2, mb;
-      };
-      const float* d1c = d1e + fo;
-      const float* d2c = d2e + fo;
-      float* mubp = mub ? mub + bo : nullptr;
-      walk_b<kEpiBatchH>(
-          M.w,
-          [&](unsigned g) {
-            VIn q;
-            q.hx = at(hbx, g);
-            q.hy = at(hby, g);
-            q.m1x = at(m1x, g);
-            q.m1y = at(m1y, g);
-            q.m2x = at(m2x, g);
-            q.m2y = at(m2y, g);
-            q.mu = at(a.mu + bo, g);
-            q.d1 = mubp ? at(d1c, g) : 0.f;
-            q.d2 = mubp ? at(d2c, g) : 0.f;
-            q.mb = mubp ? at(mubp, g) : 0.f;
-            return q;
-          },
-          [&](unsigned g, unsigned l, const VIn& q) {
-            const float2 v = at(z, l);
-            const float hx = q.hx + v.x, hy = q.hy + v.y;
-            at(hbx, g) = hx;
-            at(hby, g) = hy;
-            at(G1 + fo, g) = q.mu * (q.m1x * hx + q.m1y * hy);
-            at(G2 + fo, g) = q.mu * (q.m2x * hx + q.m2y * hy);
-            if (mubp) {
-              const float ex = q.m1x * q.d1 + q.m2x * q.d2;
-              const float ey = q.m1y * q.d1 + q.m2y * q.d2;
-              at(mubp, g) = q.mb + hx * ex + hy * ey;
-            }
-          });
-    }
+    walk(M.w, [&](unsigned g, unsigned l) {
+      const float2 v = at(z, l);
+      at(hbx, g) = v.x;
+      at(hby, g) = v.y;
+    });
     __syncthreads();
-  }
-  if (DIR == 2 && a.mode != FLUX_VISC) {
-    struct FIn {
-      float e[4], fb[4], gb[4], ub[4];
-    };
-    walk_b<2>(
-        M.w,
-        [&](unsigned g) {
-          FIn q;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            q.e[k] = at(a.u + k * pl + bo, g);
-            q.fb[k] = at(Hb + (2 * k) * pl + bo, g);
-            q.gb[k] = at(Hb + (2 * k + 1) * pl + bo, g);
-            q.ub[k] = at(ub + k * pl + bo, g);
-          }
-          return q;
-        },
-        [&](unsigned g, unsigned, const FIn& q) {
-          float fb[4], gb[4], o[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            fb[k] = -q.fb[k];
-            gb[k] = -q.gb[k];
-          }
-          flux_vjp(q.e, a.gamma, fb, gb, o);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) at(ub + k * pl + bo, g) = q.ub[k] + o[k];
-        });
   }
 }
 
-// k_adjHb<2> with two state components per transform (H_bar x,y of
+// Reverse of pass B2 with two state components per transform (H_bar x,y of
 // component c at z[pos][l], of c + 1 at z[pos][nl + l]; tiles of the set
 // with two complex lines per grid line): the metric rows, mu and mu_bar are
 // read and written once per component pair instead of once per component,
-// which is what bounds this reverse pass (HBM traffic).
+// which is what bounds this reverse pass (HBM traffic).  Hb (+)= D_2^T
+// (m_2x rb, m_2y rb), then G1/G2 = mu-weighted metric products (for D^T
+// later), mu_bar += H_bar . grad e, u_bar += flux VJP of -H_bar.
 __global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* Hb, const float* d1e,
                                             const float* d2e, float* G1, float* G2, float* mub, float* ub,
                                             int visc) {
