@@ -371,6 +371,68 @@ def main():
         s3.close()
         del st3, u3
 
+    # ---------------- the 64-patch annulus (16 sectors x 4 shells of 512 x 512,
+    # Mach 5, glue and inflow every stage, network every step): forward step
+    # rate, a 20-step checkpointed reverse sweep (checkpoints every 5) and the
+    # device memory both need
+    shells = None
+    if not args.no_paper:
+        from paper_2506_16076_amd import autodiff
+        c4 = synth.config(4)
+        ps4 = c4.ps
+        torch.cuda.synchronize()
+        mem0 = torch.cuda.memory_allocated()      # buffers of the other workloads still held
+        s4 = api.PatchSet.from_layout(ctx, ps4, layout)
+        s4.tune(tuning["budgets"], tuning["threads"], {"lpt": 0, "xcd": 1}[tuning["order"]])
+        u4 = s4.to_device(c4.u0)
+        st4 = api.Stepper(s4, u4, s4.to_device(ps4.metric), c4.ref, W={k: t(v) for k, v in c4.mlp.items()},
+                          dirichlet_mask=s4.to_device(ps4.dirichlet), dirichlet_state=synth.freestream(c4.mach))
+        for _ in range(args.warmup):
+            st4.step(use_graph=True)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base4 = torch.cuda.memory_allocated()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(args.steps):
+            st4.step(use_graph=True)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms4 = e0.elapsed_time(e1) / args.steps
+        fwd_peak = torch.cuda.max_memory_allocated()
+        K4, every4 = 20, 5
+        ustart = u4.clone()
+        for warm in (True, False):
+            u4.copy_(ustart)
+            v0 = ustart.clone().requires_grad_(True)
+            par4 = torch.zeros((), device=dev, requires_grad=True)
+            uT4 = autodiff.rollout(st4, v0, par4, K4, every4, autodiff.freestream_dmach(c4.mach))
+            seed = torch.ones_like(uT4)
+            if warm:
+                uT4.backward(seed)
+                torch.cuda.synchronize()
+                torch.cuda.reset_peak_memory_stats()
+        e0.record(ctx.stream)
+        uT4.backward(seed)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms4a = e0.elapsed_time(e1)
+        adj_peak = torch.cuda.max_memory_allocated()
+        shells = {"workload": "annulus of 16 sectors x 4 shells of 512 x 512, Mach 5 +-1% density, fringe glue "
+                              "and Dirichlet inflow every stage, network every step",
+                  "points": int(ps4.npoints), "value": ps4.npoints * 5 / (ms4 / 1e3), "unit": "grid-pt RK-stages/s",
+                  "ms_per_step": ms4,
+                  "adjoint": {"value": ps4.npoints * 5 * K4 / (ms4a / 1e3), "steps": K4, "checkpoint_every": every4,
+                              "ms_per_step": ms4a / K4, "finite": bool(torch.isfinite(v0.grad).all().item())},
+                  "footprint_GB": {"note": "torch-allocated device memory of this workload (state, metric, "
+                                           "workspaces, checkpoints, step records); the library's tables are "
+                                           "not included",
+                                   "buffers": (base4 - mem0) / 1e9, "forward_peak": (fwd_peak - mem0) / 1e9,
+                                   "reverse_peak": (adj_peak - mem0) / 1e9}}
+        s4.close()
+        del st4, u4, v0, uT4, seed, ustart
+        torch.cuda.empty_cache()
+
     if args.copy_calib:
         # plain copy of known size for the counter scale factors: reads and
         # writes COPY_MIB MiB once per launch, after a fill of another buffer
@@ -413,6 +475,7 @@ def main():
         "filter": filt,
         "paper_subpatches": paper,
         "interpolated_pair": interp_rec,
+        "annulus_shells": shells,
         "schedule": {k: v for k, v in tuning.items() if k != "table"},
         "stage_bytes_per_point": stage_bytes,
         "stage_effective_GBs": stage_bytes * npts / (ms_batched / 5 / 1e3) / 1e9,
