@@ -1746,9 +1746,12 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
     PassArgs b = a;
     b.plans = D.d_plans;
     b.tiles = D.ts[1].d_tiles;
-    hipLaunchKernelGGL(k_adjHb2p, dim3((unsigned)D.ts[1].tiles.size()), dim3(D.ts[1].threads), D.ts[1].lds,
-                       ctx->stream, b, rhs_bar, Hb, (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar,
-                       visc);
+    if (visc)
+      hipLaunchKernelGGL(k_adjHb2p<true>, dim3((unsigned)D.ts[1].tiles.size()), dim3(D.ts[1].threads), D.ts[1].lds,
+                         ctx->stream, b, rhs_bar, Hb, (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar);
+    else
+      hipLaunchKernelGGL(k_adjHb2p<false>, dim3((unsigned)D.ts[1].tiles.size()), dim3(D.ts[1].threads), D.ts[1].lds,
+                         ctx->stream, b, rhs_bar, Hb, (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar);
     if ((st = launch_check(ctx, "adj B2"))) return st;
   }
   if (visc) {

@@ -1258,9 +1258,9 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb1(PassArgs a, const float* rb, float* Hb
 // which is what bounds this reverse pass (HBM traffic).  Hb (+)= D_2^T
 // (m_2x rb, m_2y rb), then G1/G2 = mu-weighted metric products (for D^T
 // later), mu_bar += H_bar . grad e, u_bar += flux VJP of -H_bar.
+template <bool VISC>
 __global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* Hb, const float* d1e,
-                                            const float* d2e, float* G1, float* G2, float* mub, float* ub,
-                                            int visc) {
+                                            const float* d2e, float* G1, float* G2, float* mub, float* ub) {
   const TileDev T = a.tiles[blockIdx.x];
   if (T.nl == 0) return;
   const PlanDev P = a.plans[T.plan];
@@ -1294,8 +1294,8 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* H
     line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
     float* hb0 = Hb + (2 * comp) * pl + bo;   // x, y of comp; then of comp + 1
     const long long fo = comp * pl + bo;
-    if (!visc) {
-      walk_b<kLoadBatch>(
+    if (!VISC) {
+      walk_b<4>(
           M.w, [&](unsigned g) { return make_float4(at(hb0, g), at(hb0 + pl, g), at(hb0 + 2 * pl, g), at(hb0 + 3 * pl, g)); },
           [&](unsigned g, unsigned l, float4 h) {
             const float2 v = at(z, l), w = at(zb, l);
@@ -1309,7 +1309,7 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* H
         float h[4], m1x, m1y, m2x, m2y, mu, d1[2], d2[2], mb;
       };
       float* mubp = mub ? mub + bo : nullptr;
-      walk_b<2>(
+      walk_b<kEpiBatchH>(
           M.w,
           [&](unsigned g) {
             VIn2 q;
