@@ -107,6 +107,8 @@ struct fcsd_set {
   LatDev* d_lats = nullptr;
   ChunkDev* d_lchunks = nullptr;
   int nlchunks = 0;
+  LatTile* d_ltiles = nullptr;            // column tiles of the lattices (J-direction window sums)
+  int nltiles = 0;
   long long lat_size = 0;
   int annulus = 0;
   AnnulusDev an{};
@@ -596,11 +598,17 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
     s->lat_size = plane;
   }
   s->nlchunks = (int)lch.size();
+  std::vector<LatTile> ltiles;
+  for (int li = 0; li < (int)lat.size(); ++li)
+    for (int j0 = 0; j0 < lat[li].H; j0 += kLatRows)
+      for (int g0 = 0; g0 < lat[li].W; g0 += kBlock) ltiles.push_back(LatTile{li, g0, j0, 0});
+  s->nltiles = (int)ltiles.size();
   fcsd_status r;
   if ((r = upload(ctx, &s->d_tw, tw)) || (r = upload(ctx, &s->d_km, km)) || (r = upload(ctx, &s->d_aq, aq)) ||
       (r = upload(ctx, &s->d_dq, dq)) ||
       (r = upload(ctx, &s->d_patches, pd)) || (r = upload(ctx, &s->d_chunks, ch)) ||
-      (r = upload(ctx, &s->d_lats, lat)) || (r = upload(ctx, &s->d_lchunks, lch)))
+      (r = upload(ctx, &s->d_lats, lat)) || (r = upload(ctx, &s->d_lchunks, lch)) ||
+      (r = upload(ctx, &s->d_ltiles, ltiles)))
     return r;
   if (aq.empty()) {  // keep a valid pointer for kernels
     std::vector<double> one(1, 0.0);
@@ -647,6 +655,7 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_chunks);
   hipFree(s->d_lats);
   hipFree(s->d_lchunks);
+  hipFree(s->d_ltiles);
   delete s;
   return FCSD_OK;
 }
@@ -1001,10 +1010,10 @@ fcsd_status lambda_forward(fcsd_ctx* ctx, const fcsd_set* s, const AvWs& A, cons
   hipStream_t st = ctx->stream;
   hipLaunchKernelGGL(k_lat_gather, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, st, s->d_lchunks, s->nlchunks, s->d_lats, s->d_patches,
                      s->an, muh, A.num, A.den, s->annulus, 0);
-  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, st, s->d_lchunks, s->nlchunks, s->d_lats,
-                     (const float*)A.num, (const float*)A.den, A.t0, A.t1, 0);
-  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, st, s->d_lchunks, s->nlchunks, s->d_lats,
-                     (const float*)A.t0, (const float*)A.t1, A.num, A.den, 1);
+  hipLaunchKernelGGL(k_lat_conv_g, dim3(chunk_grid(s->nltiles)), dim3(kBlock), 0, st, s->d_ltiles, s->nltiles, s->d_lats,
+                     (const float*)A.num, (const float*)A.den, A.t0, A.t1);
+  hipLaunchKernelGGL(k_lat_conv_j, dim3(chunk_grid(s->nltiles)), dim3(kBlock), 0, st, s->d_ltiles, s->nltiles, s->d_lats,
+                     (const float*)A.t0, (const float*)A.t1, A.num, A.den);
   if (mu) {
     hipLaunchKernelGGL(k_lat_scatter, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, st, s->d_chunks, s->nchunks, s->d_patches, s->an,
                        s->annulus, (const float*)A.num, (const float*)A.den, mu);
@@ -1073,10 +1082,10 @@ extern "C" fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* s, const 
   if (s->novl > 0)
     hipLaunchKernelGGL(k_lat_overlap_scatter, dim3(blocks_for(s->novl)), dim3(kBlock), 0, sm, s->d_ovl, s->novl,
                        s->d_ovl_src, (const float*)A.tp, A.t0);
-  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats,
-                     (const float*)A.t0, (const float*)nullptr, A.t1, (float*)nullptr, 0);
-  hipLaunchKernelGGL(k_lat_conv, dim3(chunk_grid(s->nlchunks)), dim3(kBlock), 0, sm, s->d_lchunks, s->nlchunks, s->d_lats,
-                     (const float*)A.t1, (const float*)nullptr, A.t0, (float*)nullptr, 1);
+  hipLaunchKernelGGL(k_lat_conv_g, dim3(chunk_grid(s->nltiles)), dim3(kBlock), 0, sm, s->d_ltiles, s->nltiles, s->d_lats,
+                     (const float*)A.t0, (const float*)nullptr, A.t1, (float*)nullptr);
+  hipLaunchKernelGGL(k_lat_conv_j, dim3(chunk_grid(s->nltiles)), dim3(kBlock), 0, sm, s->d_ltiles, s->nltiles, s->d_lats,
+                     (const float*)A.t1, (const float*)nullptr, A.t0, (float*)nullptr);
   hipLaunchKernelGGL(k_route_S, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, sm, s->d_chunks, s->nchunks, s->d_patches, s->an, s->annulus,
                      (const float*)A.t0, (const signed char*)tau, argmax, A.S);
   hipLaunchKernelGGL(k_speed_vjp, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, sm, s->d_chunks, s->nchunks, s->d_patches, u,

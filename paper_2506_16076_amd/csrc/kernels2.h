@@ -757,64 +757,111 @@ __global__ void __launch_bounds__(kBlock) k_lat_gather(const ChunkDev* lchunks, 
   });
 }
 
-// separable 17-tap window sum along G (dir 0, periodic or zero padded) or J
-// (dir 1, zero padded).  Along G a chunk's cells and their 8 neighbours on
-// either side are contiguous, so they are staged in LDS once and the taps
-// read from there (a periodic wrap at a row end reads global memory); the
-// taps are summed in the same order either way.
-__global__ void __launch_bounds__(kBlock) k_lat_conv(const ChunkDev* lchunks, int nchunks, const LatDev* lats,
-                                                     const float* in0, const float* in1, float* out0,
-                                                     float* out1, int dir) {
-  __shared__ float st0[kChunk + 16], st1[kChunk + 16];
-  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {
-    const ChunkDev ck = lchunks[cb];
-    const LatDev Lt = lats[ck.patch];
-    const long long ncell = (long long)Lt.W * Lt.H;
-    const int k = ck.start + threadIdx.x;
-    if (dir == 0) {
-      for (int q = threadIdx.x; q < kChunk + 16; q += blockDim.x) {
-        const long long c = (long long)ck.start - 8 + q;
-        const bool ok = c >= 0 && c < ncell;
-        st0[q] = ok ? in0[Lt.base + c] : 0.f;
-        if (in1) st1[q] = ok ? in1[Lt.base + c] : 0.f;
-      }
-      __syncthreads();
+// Separable 17-tap window sums of a lattice (the smoothing operator's
+// numerator and denominator, or the transposed sums), in two passes over
+// tiles of 256 columns by kLatRows rows.  Along J (zero padded): a thread
+// keeps its column's
+// kLatRows + 16 values in registers and forms the kLatRows sums from them
+// (two loads per output instead of seventeen), the taps summed in the same
+// order, a row outside the lattice read as zero.
+constexpr int kLatRows = 16;
+struct LatTile {
+  int lat, g0, j0, pad;
+};
+
+__global__ void __launch_bounds__(kBlock) k_lat_conv_j(const LatTile* __restrict__ tiles, int ntiles,
+                                                       const LatDev* __restrict__ lats, const float* in0,
+                                                       const float* in1, float* out0, float* out1) {
+  for (int tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+    const LatTile tt = tiles[tb];
+    const LatDev Lt = lats[tt.lat];
+    const int G = tt.g0 + (int)threadIdx.x;
+    if (G >= Lt.W) continue;
+    const long long col = Lt.base + G;
+    float v0[kLatRows + 16], v1[kLatRows + 16];
+#pragma unroll
+    for (int q = 0; q < kLatRows + 16; ++q) {
+      const int j = tt.j0 - 8 + q;
+      const bool ok = j >= 0 && j < Lt.H;
+      v0[q] = ok ? in0[col + (long long)j * Lt.W] : 0.f;
+      v1[q] = (ok && in1) ? in1[col + (long long)j * Lt.W] : 0.f;
     }
-    if (k < ncell) {
-      const int J = k / Lt.W, G = k - J * Lt.W;
+#pragma unroll
+    for (int r = 0; r < kLatRows; ++r) {
+      const int J = tt.j0 + r;
+      if (J >= Lt.H) break;
       float s0 = 0.f, s1 = 0.f;
-      // unrolled: the window weights become literals
 #pragma unroll
       for (int l = -8; l <= 8; ++l) {
-        float a, b = 0.f;
-        const float w = win(l);
-        if (dir == 0) {
-          const int gg = G + l;
-          if (gg >= 0 && gg < Lt.W) {
-            a = st0[threadIdx.x + 8 + l];
-            if (in1) b = st1[threadIdx.x + 8 + l];
-          } else if (Lt.periodic) {
-            // |l| <= 8 < W: one wrap at most (no integer division per tap)
-            const long long c = Lt.base + (long long)J * Lt.W + (gg < 0 ? gg + Lt.W : gg - Lt.W);
-            a = in0[c];
-            if (in1) b = in1[c];
-          } else {
-            continue;
-          }
-        } else {
-          const int jj = J + l;
-          if (jj < 0 || jj >= Lt.H) continue;
-          const long long c = Lt.base + (long long)jj * Lt.W + G;
-          a = in0[c];
-          if (in1) b = in1[c];
-        }
-        s0 = fmaf(w, a, s0);
-        if (in1) s1 = fmaf(w, b, s1);
+        const int jj = J + l;
+        if (jj < 0 || jj >= Lt.H) continue;
+        s0 = fmaf(win(l), v0[r + 8 + l], s0);
+        if (in1) s1 = fmaf(win(l), v1[r + 8 + l], s1);
       }
-      out0[Lt.base + k] = s0;
-      if (out1) out1[Lt.base + k] = s1;
+      out0[col + (long long)J * Lt.W] = s0;
+      if (out1) out1[col + (long long)J * Lt.W] = s1;
     }
-    if (dir == 0) __syncthreads();  // the staging buffers are reused by the next chunk
+  }
+}
+
+// Along G (periodic or zero padded), the same tiles: the tile's kLatRows
+// row segments and their 8-cell halos (wrapped on a periodic
+// lattice, zero outside a plain one) are staged in LDS, then each thread
+// forms the sums of its column, taps in the same order.
+__global__ void __launch_bounds__(kBlock) k_lat_conv_g(const LatTile* __restrict__ tiles, int ntiles,
+                                                       const LatDev* __restrict__ lats, const float* in0,
+                                                       const float* in1, float* out0, float* out1) {
+  constexpr int kW = kBlock + 16;
+  __shared__ float s0[kLatRows][kW], s1[kLatRows][kW];
+  for (int tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+    const LatTile tt = tiles[tb];
+    const LatDev Lt = lats[tt.lat];
+    // every thread's share of the staging loads is issued before any of them
+    // is written to LDS (kLatRows * kW is kStage workgroups' worth exactly)
+    constexpr int kStage = kLatRows * kW / kBlock;
+    static_assert(kStage * kBlock == kLatRows * kW, "staging covers the tile exactly");
+    float a[kStage], b[kStage];
+#pragma unroll
+    for (int it = 0; it < kStage; ++it) {
+      const int q = it * kBlock + (int)threadIdx.x;
+      const int r = q / kW, c = q - r * kW;
+      const int J = tt.j0 + r;
+      int g = tt.g0 - 8 + c;
+      bool ok = J < Lt.H;
+      if (Lt.periodic) {
+        g = g < 0 ? g + Lt.W : (g >= Lt.W ? g - Lt.W : g);   // |offset| <= 8 < W
+      } else {
+        ok = ok && g >= 0 && g < Lt.W;
+      }
+      const long long cell = Lt.base + (long long)J * Lt.W + g;
+      a[it] = ok ? in0[cell] : 0.f;
+      b[it] = (ok && in1) ? in1[cell] : 0.f;
+    }
+#pragma unroll
+    for (int it = 0; it < kStage; ++it) {
+      const int q = it * kBlock + (int)threadIdx.x;
+      const int r = q / kW, c = q - r * kW;
+      s0[r][c] = a[it];
+      if (in1) s1[r][c] = b[it];
+    }
+    __syncthreads();
+    const int G = tt.g0 + (int)threadIdx.x;
+    if (G < Lt.W) {
+      for (int r = 0; r < kLatRows; ++r) {
+        const int J = tt.j0 + r;
+        if (J >= Lt.H) break;
+        float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+        for (int l = -8; l <= 8; ++l) {
+          a0 = fmaf(win(l), s0[r][threadIdx.x + 8 + l], a0);
+          if (in1) a1 = fmaf(win(l), s1[r][threadIdx.x + 8 + l], a1);
+        }
+        const long long cell = Lt.base + (long long)J * Lt.W + G;
+        out0[cell] = a0;
+        if (out1) out1[cell] = a1;
+      }
+    }
+    __syncthreads();   // the staging rows are reused by the next tile
   }
 }
 
