@@ -649,16 +649,21 @@ __global__ void __launch_bounds__(kBlock) k_rowmax(const ChunkDev* chunks, int n
     const int k = ck.start + threadIdx.x;
     int i, j;
     if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-    const int lo = i - 3 < 0 ? 0 : i - 3, hi = i + 3 > P.n1 - 1 ? P.n1 - 1 : i + 3;
-    float best = S[pidx(P, lo, j)];
-    int bi = lo;
-    for (int t = lo + 1; t <= hi; ++t) {
-      const float v = S[pidx(P, t, j)];
-      if (v > best) {
-        best = v;
-        bi = t;
+    // the seven samples are loaded together at clamped indices; scanning
+    // them in order with a strict comparison keeps the first maximiser of
+    // the clamped range i-3..i+3 (a clamped duplicate repeats an end value
+    // at the same index)
+    float v[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v[q] = S[pidx(P, min(max(i + q - 3, 0), P.n1 - 1), j)];
+    float best = v[0];
+    int bi = max(i - 3, 0);
+#pragma unroll
+    for (int q = 1; q < 7; ++q)
+      if (v[q] > best) {
+        best = v[q];
+        bi = min(i + q - 3, P.n1 - 1);
       }
-    }
     rmax[P.off + k] = best;
     rarg[P.off + k] = bi;
   });
@@ -673,16 +678,17 @@ __global__ void __launch_bounds__(kBlock) k_muhat(const ChunkDev* chunks, int nc
     const int k = ck.start + threadIdx.x;
     int i, j;
     if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-    const int lo = j - 3 < 0 ? 0 : j - 3, hi = j + 3 > P.n2 - 1 ? P.n2 - 1 : j + 3;
-    float best = rmax[pidx(P, i, lo)];
-    int bj = lo;
-    for (int t = lo + 1; t <= hi; ++t) {
-      const float v = rmax[pidx(P, i, t)];
-      if (v > best) {
-        best = v;
-        bj = t;
+    float v[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v[q] = rmax[pidx(P, i, min(max(j + q - 3, 0), P.n2 - 1))];
+    float best = v[0];
+    int bj = max(j - 3, 0);
+#pragma unroll
+    for (int q = 1; q < 7; ++q)
+      if (v[q] > best) {
+        best = v[q];
+        bj = min(j + q - 3, P.n2 - 1);
       }
-    }
     const long long g = P.off + k;
     if (argmax) argmax[g] = bj * P.n1 + rarg[pidx(P, i, bj)];
     float m = 0.f;
