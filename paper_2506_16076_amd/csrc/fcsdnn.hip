@@ -418,21 +418,39 @@ void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget,
     });
     return;
   }
-  // XCD-grouped: whole patches are dealt to the dies by longest-first
-  // greedy balancing of their work, so that the tiles of one patch, which
-  // share cache lines at their column edges (q2 lines) and metric rows, run
-  // on one L2.  Slot b of the launch belongs to die b % kXcd; dies with
-  // fewer tiles get empty tiles (nl = 0, the kernels return at once).
-  const int np = (int)plans.size();
-  std::vector<int> porder(np);
-  for (int p = 0; p < np; ++p) porder[p] = p;
-  std::stable_sort(porder.begin(), porder.end(), [&](int a, int b) { return pcost[a] > pcost[b]; });
+  // XCD-grouped: patches are dealt to the dies by longest-first greedy
+  // balancing of their work, so that the tiles of one patch, which share
+  // cache lines at their column edges (q2 lines) and metric rows, run on one
+  // L2.  A patch with more work than a die's fair share (few large patches)
+  // is first cut into runs of consecutive tiles of about that share, so
+  // that every die gets work.  Slot b of the launch belongs to die b % kXcd;
+  // dies with fewer tiles get empty tiles (nl = 0, the kernels return at
+  // once).
+  struct Run {
+    int begin, end;
+    long long cost;
+  };
+  long long total = 0;
+  for (long long c : pcost) total += c;
+  const long long share = std::max(1LL, (total + kXcd - 1) / kXcd);
+  std::vector<Run> runs;
+  for (int p = 0; p < (int)plans.size(); ++p) {
+    const int b = D.patch_begin[p], e = D.patch_begin[p + 1], nt = e - b;
+    if (nt == 0) continue;
+    const int k = (int)std::min<long long>(nt, (pcost[p] + share - 1) / share);
+    for (int i = 0; i < k; ++i) {
+      Run r{b + (int)((long long)nt * i / k), b + (int)((long long)nt * (i + 1) / k), 0};
+      for (int t = r.begin; t < r.end; ++t) r.cost += (long long)plans[p].L * D.tiles_by_patch[t].nl;
+      runs.push_back(r);
+    }
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.cost > b.cost; });
   std::vector<long long> load(kXcd, 0);
   std::vector<std::vector<TileDev>> lst(kXcd);
-  for (int p : porder) {
+  for (const Run& r : runs) {
     const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    load[x] += pcost[p];
-    for (int t = D.patch_begin[p]; t < D.patch_begin[p + 1]; ++t) lst[x].push_back(D.tiles_by_patch[t]);
+    load[x] += r.cost;
+    for (int t = r.begin; t < r.end; ++t) lst[x].push_back(D.tiles_by_patch[t]);
   }
   size_t mx = 0;
   for (auto& l : lst) mx = std::max(mx, l.size());

@@ -617,6 +617,22 @@ __global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* chunks, int nch
       // in the matrix products) and write nothing
       i = i < P.n1 ? i : P.n1 - 1;
       j = j < P.n2 ? j : P.n2 - 1;
+      // 16 points that all lie outside D~ (the strips next to internal
+      // sides) have class 0 and zero logits: the products are skipped
+      if (!__any(valid && in_dtilde(P, i, j))) {
+        if (g == 0 && valid) {
+          const long long gi = P.off + kk;
+          tau[gi] = (signed char)0;
+          if (logits) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              logits[4 * gi + v] = 0.f;
+              logits[4 * (pl + gi) + v] = 0.f;
+            }
+          }
+        }
+        continue;
+      }
       float x[4];
       window4<1>(phi, P, i, j, g, x);
       const floatx4 o1 = mlp16(L, x, g, r);
@@ -1028,9 +1044,13 @@ __global__ void __launch_bounds__(kBlock) k_dt_reduce(const ChunkDev* chunks, in
                                                       const float* u, const float* mu, long long pl,
                                                       float gam, unsigned* smax, unsigned* mmax) {
   // a block takes a contiguous run of chunks (chunks are ordered by patch)
-  // and keeps per-thread maxima until the patch changes: a wave posts its
-  // maxima with two atomics only then and at the end, and the chunk loop
-  // has no barrier
+  // and keeps per-thread maxima until the patch changes (the same chunk for
+  // every thread of the block): the block's maxima are posted only then and
+  // at the end, one thread per block, and only where they exceed the value
+  // already there (posted maxima only grow, so a stale read costs an atomic
+  // at most and never loses one).  Few large patches thus do not serialise
+  // thousands of atomics on one address; the chunk loop has no barrier.
+  __shared__ float red_s[kBlock / 64], red_m[kBlock / 64];
   const int per = (nchunks + (int)gridDim.x - 1) / (int)gridDim.x;
   const int c0 = (int)blockIdx.x * per, c1 = min(c0 + per, nchunks);
   auto post = [&](int patch, float s, float m) {
@@ -1039,10 +1059,21 @@ __global__ void __launch_bounds__(kBlock) k_dt_reduce(const ChunkDev* chunks, in
       m = fmaxf(m, __shfl_xor(m, o));
     }
     if ((threadIdx.x & 63) == 0) {
-      // non-negative floats order like their bit patterns
-      atomicMax(smax + patch, __float_as_uint(fmaxf(s, 0.f)));
-      atomicMax(mmax + patch, __float_as_uint(fmaxf(m, 0.f)));
+      red_s[threadIdx.x >> 6] = s;
+      red_m[threadIdx.x >> 6] = m;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kBlock / 64; ++w) {
+        s = fmaxf(s, red_s[w]);
+        m = fmaxf(m, red_m[w]);
+      }
+      // non-negative floats order like their bit patterns
+      const unsigned sb = __float_as_uint(fmaxf(s, 0.f)), mb = __float_as_uint(fmaxf(m, 0.f));
+      if (sb > smax[patch]) atomicMax(smax + patch, sb);
+      if (mb > mmax[patch]) atomicMax(mmax + patch, mb);
+    }
+    __syncthreads();
   };
   if (c0 >= c1) return;
   int cur = chunks[c0].patch;

@@ -323,6 +323,7 @@ def test_network_classes(env):
         o, n1_, n2_ = int(ps.off[p]), int(ps.n1[p]), int(ps.n2[p])
         g1 = gl[0][o:o + n1_ * n2_].reshape(n2_, n1_, 4)
         assert np.abs(g1[m] - l1[m]).max() < 2e-5
+        assert np.all(g1[~m] == 0)
     say("network classes decided", decided)
     assert decided > 0.99 * sum(av.dtilde_mask(ps, p).sum() for p in range(ps.npatch))
     s.close()
