@@ -735,12 +735,14 @@ def test_viscosity_reverse_mode(env, case):
 
 # ------------------------------------------------------------------ schedules
 
-def test_tiling_and_order_do_not_change_results(env):
+@pytest.mark.parametrize("case", ["uneven", "overlap", "square64"])
+def test_tiling_and_order_do_not_change_results(env, case):
     """Every line is transformed by the same arithmetic whatever its tile and
     launch slot: the right-hand side is bit-identical across LDS budgets and
-    launch orders."""
+    launch orders (with one or two patches the XCD order cuts each patch
+    into runs of tiles on several dies)."""
     api, ctx, torch = env
-    ps, u, mu, ref = rhs_case("uneven")
+    ps, u, mu, ref = rhs_case(case)
     s = api.PatchSet.from_layout(ctx, ps)
     metric = dev(torch, ps.metric)
     ud, mud = dev(torch, u), dev(torch, mu)
