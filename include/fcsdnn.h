@@ -310,6 +310,17 @@ fcsd_status fcsd_cfl_dt(fcsd_ctx* ctx, const fcsd_set* set, const float* u, cons
                         float cfl, float gamma, float* dt_dev, int64_t plane,
                         void* ws, size_t ws_bytes);
 
+/* State monitor (the admissibility the paper reports its runs keep without
+ * limiters, Remark adiabatic_th: positive density and pressure): over the
+ * grid points of every patch of a state u [4][plane] (padding is not looked
+ * at), *flags_dev (one int32 in device memory, overwritten, stream-ordered)
+ * becomes the OR of 1 (a non-finite component), 2 (rho <= 0) and 4
+ * (p = (gamma - 1)(E - |m|^2 / (2 rho)) <= 0, or not a number); 0 when the
+ * state is admissible.  No host synchronisation.  FCSD_EINVAL for a null
+ * pointer or gamma <= 1. */
+fcsd_status fcsd_check(fcsd_ctx* ctx, const fcsd_set* set, const float* u, float gamma,
+                       int32_t* flags_dev, int64_t plane);
+
 /* ---- network-driven viscosity (Sec. 5) ---------------------------------- */
 
 /* Network weights (device FP32, row-vector convention y = x W + b):

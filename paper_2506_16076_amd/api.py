@@ -286,6 +286,13 @@ def fcsd_cfl_dt(s, u, mu, cfl, gamma, dt_dev):
           ws.numel() * 4)
 
 
+def fcsd_check(s, u, gamma, flags_dev):
+    """State monitor: flags_dev (one int32 on the device) becomes the OR of
+    1 (non-finite value), 2 (rho <= 0), 4 (p <= 0) over the grid points."""
+    _chk(u, numel=4 * s.plane), _chk(flags_dev, dtype=torch.int32, numel=1)
+    _call(s, "fcsd_check", _p(u), float(gamma), _p(flags_dev), s.plane)
+
+
 # ------------------------------------------------------------------ viscosity
 
 def mlp_struct(W: dict):

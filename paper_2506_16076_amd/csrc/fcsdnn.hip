@@ -983,6 +983,17 @@ extern "C" fcsd_status fcsd_cfl_dt(fcsd_ctx* ctx, const fcsd_set* s, const float
   return cfl_dt_impl(ctx, s, u, mu, cfl, gamma, dt_dev, (unsigned*)ws);
 }
 
+extern "C" fcsd_status fcsd_check(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float gamma, int32_t* flags_dev,
+                                  int64_t plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !flags_dev || !(gamma > 1.0f)) return fail(ctx, FCSD_EINVAL, "fcsd_check: bad arguments");
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, ctx->stream, (float*)flags_dev, 0.f, 1LL);
+  hipLaunchKernelGGL(k_check, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->nchunks,
+                     s->d_patches, u, (long long)s->plane, gamma, (int*)flags_dev);
+  return launch_check(ctx, "fcsd_check");
+}
+
 // ======================================================================== viscosity
 
 namespace {

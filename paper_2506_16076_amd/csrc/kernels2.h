@@ -1033,6 +1033,37 @@ __global__ void __launch_bounds__(kBlock) k_speed_vjp(const ChunkDev* chunks, in
   });
 }
 
+// ---------------------------------------------------------------- state monitor
+
+// flags |= 1 for a non-finite component, 2 for rho <= 0, 4 for p <= 0 at a
+// grid point of a patch (padding is not looked at); one OR per block.
+__global__ void __launch_bounds__(kBlock) k_check(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
+                                                  const float* u, long long pl, float gam, int* flags) {
+  __shared__ int red[kBlock / 64];
+  int f = 0;
+  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {
+    const ChunkDev ck = chunks[cb];
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k < pstore(P) && pdecode(P, k, i, j)) {
+      const long long g = P.off + k;
+      const float e0 = u[g], e1 = u[pl + g], e2 = u[2 * pl + g], e3 = u[3 * pl + g];
+      if (!(isfinite(e0) && isfinite(e1) && isfinite(e2) && isfinite(e3))) f |= 1;
+      if (!(e0 > 0.f)) f |= 2;
+      const float p = (gam - 1.0f) * (e3 - 0.5f * (e1 * e1 + e2 * e2) / e0);
+      if (!(p > 0.f)) f |= 4;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) f |= red[w];
+    if (f) atomicOr(flags, f);
+  }
+}
+
 // ---------------------------------------------------------------- step size
 
 __global__ void __launch_bounds__(kBlock) k_fill(float* p, float v, long long n) {

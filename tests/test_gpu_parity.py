@@ -291,6 +291,42 @@ def test_cfl_step_size(env):
     s.close()
 
 
+def test_state_monitor(env):
+    """fcsd_check: 0 on an admissible state; each planted defect at a grid
+    point sets its bit (1 non-finite, 2 rho <= 0, 4 p <= 0); a defect in
+    the padding between patches is not looked at."""
+    api, ctx, torch = env
+    ps, u, mu, ref = rhs_case("uneven")
+    s = api.PatchSet.from_layout(ctx, ps)
+    flags = torch.full((1,), -1, dtype=torch.int32, device="cuda:0")
+
+    def run(v):
+        api.fcsd_check(s, dev(torch, v), G, flags)
+        return int(host(flags)[0])
+
+    assert run(u) == 0
+    p = ps.npatch // 2
+    n1, n2 = int(ps.n1[p]), int(ps.n2[p])
+    for field, val, want in [(2, np.nan, 1 | 4), (0, -1.0, 2), (3, 0.0, 4), (1, np.inf, 1 | 4)]:
+        v = u.copy()
+        ps.view(v, p)[field, n2 - 1, n1 - 1] = val
+        got = run(v)
+        say("planted", field, val, got)
+        assert got == want
+    two = u.copy()
+    ps.view(two, 0)[0, 0, 0] = -1.0
+    ps.view(two, ps.npatch - 1)[2, 3, 5] = np.nan
+    assert run(two) == (1 | 2 | 4)
+    used = np.zeros(ps.plane, bool)
+    for q in range(ps.npatch):
+        used[int(ps.off[q]):int(ps.off[q]) + int(ps.n1[q]) * int(ps.n2[q])] = True
+    if not used.all():
+        v = u.copy()
+        v[:, np.nonzero(~used)[0][0]] = np.nan
+        assert run(v) == 0
+    s.close()
+
+
 # ------------------------------------------------------------------ viscosity
 
 def test_network_classes(env):
