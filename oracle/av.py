@@ -46,47 +46,6 @@ STENCIL = 3          # 7x7 stencil half-width
 FEAT = 16
 
 
-def proxy_speed_f32(e, gamma):
-    """Phi and S evaluated in IEEE FP32 from an FP32 state, one rounding per
-    operation in this order: rho, ir = 1/rho, vx = m ir, vy = n ir,
-    q = vx vx + vy vy, p = (gamma-1) (E - (rho/2) q), a = sqrt((gamma p)/rho),
-    Phi = sqrt(q)/a, S = (|vx| + |vy|) + a.  Reading for decisions: the
-    classifier argmax and the 7x7 argmax are integer results decided by
-    floating point, so the oracle takes them in the kernel's precision
-    (FP32); every value downstream of a decision is FP64."""
-    f = np.float32
-    e = np.asarray(e).astype(f)
-    with np.errstate(all="ignore"):
-        rho = e[0]
-        ir = f(1) / rho
-        vx = e[1] * ir
-        vy = e[2] * ir
-        q = vx * vx + vy * vy
-        g = f(gamma)
-        p = (g - f(1)) * (e[3] - (f(0.5) * rho) * q)
-        a = np.sqrt((g * p) / rho)
-        phi = np.sqrt(q) / a
-        S = (np.abs(vx) + np.abs(vy)) + a
-    return phi, S
-
-
-def features_lines_f32(phi_lines):
-    """features_lines in IEEE FP32: x = (w - lo) (2/(hi - lo)) - 1."""
-    f = np.float32
-    phi_lines = np.asarray(phi_lines, f)
-    nl, n = phi_lines.shape
-    idx = np.clip(np.arange(n)[:, None] + np.arange(-8, 8)[None, :], 0, n - 1)
-    w = phi_lines[:, idx]
-    lo = w.min(axis=-1, keepdims=True)
-    hi = w.max(axis=-1, keepdims=True)
-    rng = hi - lo
-    flat = rng <= f(1e-6) * np.maximum(f(1), np.abs(hi))
-    with np.errstate(all="ignore"):
-        s = f(2) / rng
-        x = (w - lo) * s - f(1)
-    return np.where(flat, f(0), x).astype(f)
-
-
 def window_weights():
     k = np.arange(-WIN_HALF, WIN_HALF + 1)
     return np.cos(np.pi * k / 18.0) ** 2
@@ -133,30 +92,39 @@ def mlp_logits(x, W):
     return h @ W["W3"].astype(np.float64) + W["b3"].astype(np.float64)
 
 
-def classify(e, ps, W, gamma, return_logits=False, fp32=True):
-    """tau plane (int8, 0 outside D~) and optionally the per-direction logits.
-    fp32: proxy and features in FP32 (decision precision of the kernel, see
-    proxy_speed_f32), network in FP64; fp32=False: everything in FP64."""
-    phi = proxy_speed_f32(e, gamma)[0] if fp32 else proxy(e, gamma)
-    feats = features_lines_f32 if fp32 else features_lines
+def classes_from_logits(l1, l2):
+    """2D smoothness class from the logits of the two directions (reading
+    of Sec. 5.1): a direction's class is 1 + the index of its largest logit
+    (the lowest index among equal largest logits), and the point takes the
+    smaller of the two directions' classes (the more viscous one)."""
+    return np.minimum(np.argmax(l1, -1), np.argmax(l2, -1)) + 1
+
+
+def classify(e, ps, W, gamma, return_logits=False):
+    """tau plane (int8, 0 outside D~) and optionally the per-direction logits
+    {patch: (l1, l2)}, each [n2, n1, 4]; proxy, features and network in
+    FP64."""
+    e = np.asarray(e, np.float64)
     tau = np.zeros(ps.plane, np.int8)
     logits = {}
     for p in range(ps.npatch):
-        ph = ps.view(phi, p)                       # [n2, n1]
-        l1 = mlp_logits(feats(ph).astype(np.float64), W)                       # lines along q1
-        l2 = np.swapaxes(mlp_logits(feats(ph.T).astype(np.float64), W), 0, 1)  # lines along q2 -> [n2, n1, 4]
-        t = np.minimum(np.argmax(l1, -1), np.argmax(l2, -1)) + 1
-        t = np.where(dtilde_mask(ps, p), t, 0)
-        ps.view(tau, p)[...] = t
+        ph = proxy(ps.view(e, p), gamma)                                      # [n2, n1]
+        l1 = mlp_logits(features_lines(ph), W)                                # lines along q1
+        l2 = np.swapaxes(mlp_logits(features_lines(ph.T), W), 0, 1)           # lines along q2 -> [n2, n1, 4]
+        t = classes_from_logits(l1, l2)
+        ps.view(tau, p)[...] = np.where(dtilde_mask(ps, p), t, 0)
         logits[p] = (l1, l2)
     return (tau, logits) if return_logits else tau
 
 
-def stencil_max(S2d):
+def stencil_max(S2d, second=False):
     """7x7 maximum clamped to the grid, with the flat index of the maximiser
-    (first in row-major stencil order on ties)."""
+    (first in row-major stencil order on ties); second=True also returns
+    the largest value at any other stencil position (the decision's
+    margin is best - second)."""
     b, a = S2d.shape
     best = np.full((b, a), -np.inf)
+    nxt = np.full((b, a), -np.inf)
     arg = np.zeros((b, a), np.int64)
     J, I = np.meshgrid(np.arange(b), np.arange(a), indexing="ij")
     for dj in range(-STENCIL, STENCIL + 1):
@@ -165,32 +133,30 @@ def stencil_max(S2d):
             ok = (jj >= 0) & (jj < b) & (ii >= 0) & (ii < a)
             val = np.where(ok, S2d[np.clip(jj, 0, b - 1), np.clip(ii, 0, a - 1)], -np.inf)
             better = val > best
+            nxt = np.where(better, best, np.maximum(nxt, val))
             best = np.where(better, val, best)
             arg = np.where(better, np.clip(jj, 0, b - 1) * a + np.clip(ii, 0, a - 1), arg)
-    return best, arg
+    return (best, arg, nxt) if second else (best, arg)
 
 
-def preliminary(e, tau, ps, gamma, fp32=True, arg=None):
-    """mu^ plane (0 outside D~) and the argmax plane (patch-local flat index).
-    fp32: the 7x7 maximum and its position are taken on S evaluated in FP32
-    (decision precision of the kernel); mu^ itself is formed in FP64.
-    arg: replay recorded maximiser positions (frozen decision) and take S
-    there, in FP64."""
+def preliminary(e, tau, ps, gamma, arg=None):
+    """mu^ plane (0 outside D~) and the argmax plane (patch-local flat
+    index), FP64.  arg: replay recorded maximiser positions (frozen
+    decision) and take S there."""
     from oracle.rk import wave_speed
+    e = np.asarray(e, np.float64)
     if arg is not None:
-        S = wave_speed(e, gamma)
         muh = np.zeros(ps.plane)
         for p in range(ps.npatch):
-            mx = ps.view(S, p).ravel()[ps.view(arg, p)]
+            mx = wave_speed(ps.view(e, p), gamma).ravel()[ps.view(arg, p)]
             t = ps.view(tau, p).astype(np.int64)
             r = np.where(t > 0, R_TABLE[np.clip(t - 1, 0, 3)], 0.0)
             ps.view(muh, p)[...] = np.where(dtilde_mask(ps, p), r * mx * ps.hhat[p], 0.0)
         return muh, arg
-    S = proxy_speed_f32(e, gamma)[1].astype(np.float64) if fp32 else wave_speed(e, gamma)
     muh = np.zeros(ps.plane)
     arg = np.zeros(ps.plane, np.int64)
     for p in range(ps.npatch):
-        mx, am = stencil_max(ps.view(S, p))
+        mx, am = stencil_max(wave_speed(ps.view(e, p), gamma))
         t = ps.view(tau, p).astype(np.int64)
         r = np.where(t > 0, R_TABLE[np.clip(t - 1, 0, 3)], 0.0)
         ps.view(muh, p)[...] = np.where(dtilde_mask(ps, p), r * mx * ps.hhat[p], 0.0)
@@ -288,12 +254,12 @@ def _sep_conv(a, w, periodic_cols=False):
     return res
 
 
-def viscosity(e, ps, W, gamma, tau=None, fp32=True, arg=None):
+def viscosity(e, ps, W, gamma, tau=None, arg=None):
     """Full per-step viscosity: classifier, preliminary, Lambda.  Returns
     (mu, tau, argmax).  tau / arg given: replayed decisions."""
     if tau is None:
-        tau = classify(e, ps, W, gamma, fp32=fp32)
-    muh, arg = preliminary(e, tau, ps, gamma, fp32=fp32, arg=arg)
+        tau = classify(e, ps, W, gamma)
+    muh, arg = preliminary(e, tau, ps, gamma, arg=arg)
     return smooth_blend(muh, ps), tau, arg
 
 

@@ -22,6 +22,17 @@ import numpy as np
 from oracle import fcgram
 
 
+def points(ps):
+    """Flat plane indices of every patch's grid points (the padding between
+    patches, which holds no state, is left out of pointwise work)."""
+    idx = getattr(ps, "_points", None)
+    if idx is None:
+        idx = np.concatenate([np.arange(int(o), int(o) + int(a) * int(b))
+                              for o, a, b in zip(ps.off, ps.n1, ps.n2)])
+        ps._points = idx
+    return idx
+
+
 def primitives(e, gamma):
     rho = e[0]
     u = e[1] / rho
@@ -71,7 +82,10 @@ def gradient(e, metric, ps):
 
 def euler_rhs(e, metric, ps, gamma):
     """Inviscid right-hand side r = - div_x f(e)."""
-    F, G = fluxes(np.asarray(e, np.float64), gamma)
+    e = np.asarray(e, np.float64)
+    k = points(ps)
+    F, G = np.zeros(e.shape), np.zeros(e.shape)
+    F[:, k], G[:, k] = fluxes(e[:, k], gamma)
     return -divergence(F, G, metric, ps)
 
 
@@ -162,7 +176,9 @@ def full_rhs_vjp(e, metric, mu, ps, gamma, rb):
     """(e_bar, mu_bar) for the map (e, mu) -> full_rhs(e, metric, mu)."""
     e = np.asarray(e, np.float64)
     fxb, fyb = divergence_adj(rb, metric, ps)
-    eb = fluxes_vjp(e, gamma, -fxb, -fyb)
+    k = points(ps)
+    eb = np.zeros(e.shape)
+    eb[:, k] = fluxes_vjp(e[:, k], gamma, -fxb[:, k], -fyb[:, k])
     mub = None
     if mu is not None:
         mu = np.asarray(mu, np.float64)

@@ -83,11 +83,10 @@ def wave_speed(e, gamma):
 
 def cfl_dt(e, mu, ps, cfl, gamma):
     """eq. CFL, minimum over patches."""
-    S = wave_speed(e, gamma)
     best = np.inf
     for p in range(ps.npatch):
         h = ps.htilde[p]
-        s = ps.view(S, p).max() / h
+        s = wave_speed(ps.view(np.asarray(e, np.float64), p), gamma).max() / h
         m = ps.view(np.asarray(mu, np.float64), p).max() / h ** 2 if mu is not None else 0.0
         best = min(best, cfl / (s + m))
     return best / np.pi

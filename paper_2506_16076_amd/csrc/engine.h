@@ -46,6 +46,8 @@ struct PlanDev {
   int aq;        // offset of A_r Q^T (double) for this C, C*d entries
   int dq;        // offset of the differenced rows (double), (C+1)*2d entries
   int kf;        // offset of the spectral filter factors (float2) for this L
+  int gq;        // offset of the derivative's fold matrix (double), N*2d entries, for this (N, C)
+  int gf;        // offset of the filter's fold matrix (double), N*2d entries (filter configured)
   int nlines;    // lines along this direction
   int n1, n2;    // patch shape
   int patch;     // patch index
@@ -448,6 +450,81 @@ __device__ __forceinline__ void fold_tail(const LineCtx& X, const PlanDev& P, co
   }
 }
 
+// Fold of a transposed operator's tail onto the end samples, formed from the
+// cotangent itself (positions 0..N-1 of every line, before the transform
+// runs in place): side[e][c] = sum_n G[n][e] y_c[n], e < 2d, in FP64, with G
+// the host's fold matrix of the plan (2d entries per n: e < d the right end
+// sample N-d+e, e >= d the left one e-d).  The fold entries are the
+// continuation's (up to ~1e4) times the circulant's, so an FP32 tail folded
+// after the transform would carry amplified rounding onto the end samples.
+// S lanes (a power of two, S * nl <= blockDim) share a line, each summing
+// every S-th sample, and reduce with lane shuffles inside their wave.  No
+// barrier: reads positions < N, writes side.  DD >= d bounds the unrolled
+// accumulators.
+template <int DD>
+__device__ __forceinline__ void fold_pre_t(const LineCtx& X, int N, const double* __restrict__ G, int d) {
+  int S = 64;
+  while (S * X.nl > (int)blockDim.x) S >>= 1;
+  const int c = threadIdx.x / S, s = threadIdx.x - c * S;
+  const bool on = c < X.nl;
+  const int cc = on ? c : 0;
+  const float2* __restrict__ z = X.z;
+  const int ld = X.ld;
+  for (int h = 0; h < 2; ++h) {
+    double ax[DD], ay[DD];
+#pragma unroll
+    for (int e = 0; e < DD; ++e) ax[e] = ay[e] = 0.0;
+    if (on) {
+      for (int n = s; n < N; n += S) {
+        const float2 y = z[n * ld + cc];
+        const double yx = (double)y.x, yy = (double)y.y;
+        const double* g = G + (size_t)n * 2 * d + h * d;
+#pragma unroll
+        for (int e = 0; e < DD; ++e)
+          if (e < d) {
+            const double w = g[e];
+            ax[e] = fma(w, yx, ax[e]);
+            ay[e] = fma(w, yy, ay[e]);
+          }
+      }
+    }
+    for (int o = S >> 1; o > 0; o >>= 1) {
+#pragma unroll
+      for (int e = 0; e < DD; ++e) {
+        ax[e] += __shfl_xor(ax[e], o);
+        ay[e] += __shfl_xor(ay[e], o);
+      }
+    }
+    if (on && s == 0) {
+#pragma unroll
+      for (int e = 0; e < DD; ++e)
+        if (e < d) X.side[(h * d + e) * ld + c] = make_float2((float)ax[e], (float)ay[e]);
+    }
+  }
+}
+
+__device__ __forceinline__ void fold_pre(const LineCtx& X, int N, const double* __restrict__ G, int d) {
+  if (d <= 2)
+    fold_pre_t<2>(X, N, G, d);
+  else if (d <= 5)
+    fold_pre_t<5>(X, N, G, d);
+  else
+    fold_pre_t<kMaxD>(X, N, G, d);
+}
+
+// Add the fold that fold_pre left in the side buffer to the end samples
+// (after the transform; the caller syncs after).
+__device__ __forceinline__ void fold_post(const LineCtx& X, int N, int d) {
+  const int ld = X.ld;
+  for (int t = threadIdx.x; t < 2 * d * X.nl; t += blockDim.x) {
+    const int e = t / X.nl, c = t - e * X.nl;
+    const int pos = e < d ? N - d + e : e - d;
+    const float2 f = X.side[e * ld + c];
+    float2& v = X.z[pos * ld + c];
+    v = make_float2(v.x + f.x, v.y + f.y);
+  }
+}
+
 // Delta ext in place (forward operator).  Positions 0..N-1 hold f; the
 // C + 1 differences that involve the tail (or, for a periodic plan, the
 // wrap f[0] - f[N-1]) come from the end samples, the N - 1 interior ones
@@ -641,17 +718,22 @@ __device__ __forceinline__ void fft_apply(const LineCtx& X, const PlanDev* __res
 }
 
 // Derivative of the tile in place; the caller has filled positions 0..N-1
-// and synchronised.  ADJ = transpose (Delta^T, conjugate multipliers, fold).
+// and synchronised.  ADJ = transpose: the tail fold from the cotangent in
+// FP64 (fold_pre; its reads of positions < N end before difference_adj's
+// first barrier, after which those positions are overwritten), Delta^T,
+// conjugate multipliers, then the fold added to the end samples.
 template <bool ADJ>
 __device__ __forceinline__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
-                                const double* __restrict__ aqp, const double* __restrict__ dqp, int d) {
-  if (!ADJ)
+                                const double* __restrict__ gqp, const double* __restrict__ dqp, int d) {
+  if (!ADJ) {
     difference_ext(X, P, dqp + P.dq, d);
-  else
+  } else {
+    if (!P.periodic) fold_pre(X, P.N, gqp + P.gq, d);
     difference_adj(X, P);
+  }
   fft_apply<ADJ>(X, Pg, P);
   if (ADJ && !P.periodic) {
-    fold_tail(X, P, aqp + P.aq, d);
+    fold_post(X, P.N, d);
     __syncthreads();
   }
 }

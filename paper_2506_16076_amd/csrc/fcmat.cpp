@@ -313,3 +313,68 @@ extern "C" void fcsd_host_fmul(int L, int nst, const int* rad, double alpha, int
     out[2 * pos + 1] = 0.0f;
   }
 }
+
+// Fold matrix of a transposed FC line operator (paper Sec. 2.2, eqs.
+// continuation and fc_der, transposed).  A line operator of the engine is
+// R K E: E extends the N samples by the continuation tail (T, C x 2d on the
+// end samples), K is a circulant of length L = N + C with first column k,
+// R keeps positions 0..N-1.  Its transpose is E^T K^T R^T: on positions
+// < N the circulant's own transpose, plus the fold T^T (K^T)[N.., 0..N-1] of
+// the tail onto the 2d end samples.  The fold's matrix entries reach ~1e4
+// (T) times the circulant's, so the device applies it in FP64 straight to
+// the cotangent instead of folding a tail rounded by an FP32 transform.
+//   out[n * 2d + e] = sum_{m < C} T[m][e] k[(n - N - m) mod L],  n < N,
+// e < d: right end sample N-d+e (T[m][e] = (A_r Q^T)[m][e]); e >= d: left end
+// sample e-d (T[m][e] = (A_r Q^T)[C-1-m][2d-1-e]).
+// kind 0: derivative, k[r] = (1/L) sum_kappa (2 pi i kappa / beta)
+//   exp(2 pi i kappa r / L), beta = L/(N-1), |kappa| < L/2 (the Nyquist mode
+//   of an even L is zero);
+// kind 1: spectral filter (Sec. 4.3.1, eq. filtering), k[r] = (1/L) sum_kappa
+//   sigma(2 kappa / L) exp(2 pi i kappa r / L), sigma(x) = exp(-alpha x^p),
+//   Nyquist included.
+// The circulant's column is summed in long double over binary128 sine and
+// cosine tables.  arq: A_r Q^T in double, C rows of d.
+extern "C" int fcsd_host_fold_matrix(int N, int C, int d, const double* arq, int kind, double alpha, int p,
+                                     double* out) {
+  if (!arq || !out || N < 2 * d || C < 1 || d < 1 || d > 8 || (kind != 0 && kind != 1)) return 1;
+  const int L = N + C;
+  typedef long double ld;
+  std::vector<ld> sn(L), cs(L), k(L, 0.0L);
+  for (int j = 0; j < L; ++j) {
+    qf c, s;
+    cis2pi(j, L, &c, &s);
+    cs[j] = (ld)c;
+    sn[j] = (ld)s;
+  }
+  const int M = (L - 1) / 2;  // kappa = 1..M pairs with -kappa; an even L's Nyquist L/2 is apart
+  if (kind == 0) {
+    // (1/L) (2 pi i kappa / beta) (e^{i phi} - e^{-i phi}) = -(2/L) (2 pi kappa / beta) sin(phi)
+    const ld w = 2.0L * (ld)M_PIq * (ld)(N - 1) / ((ld)L * (ld)L);
+    for (int r = 0; r < L; ++r) {
+      ld acc = 0.0L;
+      for (int kap = 1; kap <= M; ++kap) acc += (ld)kap * sn[(int)(((int64_t)kap * r) % L)];
+      k[r] = -2.0L * w * acc;
+    }
+  } else {
+    std::vector<ld> sig(L / 2 + 1);
+    for (int kap = 0; kap <= L / 2; ++kap) sig[kap] = (ld)expq(-(qf)alpha * powq(2 * (qf)kap / L, p));
+    for (int r = 0; r < L; ++r) {
+      ld acc = sig[0];
+      for (int kap = 1; kap <= M; ++kap) acc += 2.0L * sig[kap] * cs[(int)(((int64_t)kap * r) % L)];
+      if (L % 2 == 0) acc += sig[L / 2] * ((r & 1) ? -1.0L : 1.0L);
+      k[r] = acc / (ld)L;
+    }
+  }
+  for (int n = 0; n < N; ++n)
+    for (int e = 0; e < 2 * d; ++e) {
+      ld acc = 0.0L;
+      for (int m = 0; m < C; ++m) {
+        const double t = e < d ? arq[(size_t)m * d + e] : arq[(size_t)(C - 1 - m) * d + (2 * d - 1 - e)];
+        int r = (n - N - m) % L;
+        if (r < 0) r += L;
+        acc += (ld)t * k[r];
+      }
+      out[(size_t)n * 2 * d + e] = (double)acc;
+    }
+  return 0;
+}

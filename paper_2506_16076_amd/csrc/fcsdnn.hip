@@ -25,6 +25,8 @@ extern "C" void fcsd_host_twiddles(int L, float* out);
 extern "C" int fcsd_host_factor(int L, int* rad);
 extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic);
 extern "C" void fcsd_host_fmul(int L, int nst, const int* rad, double alpha, int p, float* out);
+extern "C" int fcsd_host_fold_matrix(int N, int C, int d, const double* arq, int kind, double alpha, int p,
+                                     double* out);
 
 namespace {
 
@@ -100,6 +102,8 @@ struct fcsd_set {
   int ks_p = -1;
   double* d_aq = nullptr;
   double* d_dq = nullptr;
+  double* d_gq = nullptr;                 // fold matrices of the transposed derivatives, per (N, C)
+  double* d_gf = nullptr;                 // fold matrices of the transposed filter (fcsd_set_filter)
   PatchDev* d_patches = nullptr;
   ChunkDev* d_chunks = nullptr;
   int nchunks = 0;
@@ -158,6 +162,8 @@ PassArgs base_args(const fcsd_set* s, int dir) {
   a.kf = s->d_kf;
   a.aq = s->d_aq;
   a.dq = s->d_dq;
+  a.gq = s->d_gq;
+  a.gf = s->d_gf;
   a.d = s->d;
   a.plane = s->plane;
   return a;
@@ -505,8 +511,9 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   // pools
   std::vector<float2> tw;
   std::vector<float2> km;
-  std::vector<double> aq, dq;
+  std::vector<double> aq, dq, gq;
   std::map<int, int> tw_of_L, aq_of_C, dq_of_C;
+  std::map<std::pair<int, int>, int> gq_of;
   std::map<std::tuple<int, int, int>, int> km_of;
   for (int dir = 1; dir <= 2; ++dir) {
     DirPlan& D = s->dir[dir - 1];
@@ -556,6 +563,15 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
         }
         P.aq = aq_of_C[P.C];
         P.dq = dq_of_C[P.C];
+        const auto gkey = std::make_pair(P.N, P.C);
+        if (!gq_of.count(gkey)) {
+          gq_of[gkey] = (int)gq.size();
+          std::vector<double> g((size_t)P.N * 2 * d);
+          if (fcsd_host_fold_matrix(P.N, P.C, d, aq.data() + P.aq, 0, 0.0, 0, g.data()) != 0)
+            return fail(ctx, FCSD_EUNSUPPORTED, "fold matrix of the transposed derivative failed");
+          gq.insert(gq.end(), g.begin(), g.end());
+        }
+        P.gq = gq_of[gkey];
       }
       D.plans.push_back(P);
       D.ext_off.push_back(eo);
@@ -623,14 +639,15 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   s->nltiles = (int)ltiles.size();
   fcsd_status r;
   if ((r = upload(ctx, &s->d_tw, tw)) || (r = upload(ctx, &s->d_km, km)) || (r = upload(ctx, &s->d_aq, aq)) ||
-      (r = upload(ctx, &s->d_dq, dq)) ||
+      (r = upload(ctx, &s->d_dq, dq)) || (r = upload(ctx, &s->d_gq, gq)) ||
       (r = upload(ctx, &s->d_patches, pd)) || (r = upload(ctx, &s->d_chunks, ch)) ||
       (r = upload(ctx, &s->d_lats, lat)) || (r = upload(ctx, &s->d_lchunks, lch)) ||
       (r = upload(ctx, &s->d_ltiles, ltiles)))
     return r;
   if (aq.empty()) {  // keep a valid pointer for kernels
     std::vector<double> one(1, 0.0);
-    if ((r = upload(ctx, &s->d_aq, one)) || (r = upload(ctx, &s->d_dq, one))) return r;
+    if ((r = upload(ctx, &s->d_aq, one)) || (r = upload(ctx, &s->d_dq, one)) || (r = upload(ctx, &s->d_gq, one)))
+      return r;
   }
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
@@ -669,6 +686,8 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_ksoff[1]);
   hipFree(s->d_aq);
   hipFree(s->d_dq);
+  hipFree(s->d_gq);
+  hipFree(s->d_gf);
   hipFree(s->d_patches);
   hipFree(s->d_chunks);
   hipFree(s->d_lats);
@@ -727,6 +746,9 @@ extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
   s->graphs.clear();
   std::vector<float2> kf;
   std::map<int, int> kf_of_L;
+  std::vector<double> gf;
+  std::map<std::pair<int, int>, int> gf_of;
+  std::map<int, std::vector<double>> aq_of_C;
   for (int dir = 0; dir < 2; ++dir)
     for (PlanDev& P : s->dir[dir].plans) {
       if (!kf_of_L.count(P.L)) {
@@ -736,12 +758,31 @@ extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
         for (int n = 0; n < P.L; ++n) kf.push_back(make_float2(t[2 * n], t[2 * n + 1]));
       }
       P.kf = kf_of_L[P.L];
+      if (P.periodic) continue;
+      const auto key = std::make_pair(P.N, P.C);
+      if (!gf_of.count(key)) {
+        if (!aq_of_C.count(P.C)) {
+          std::vector<double> m((size_t)P.C * s->d);
+          if (fcsd_host_fc_matrix(s->d, P.C, m.data()) != 0)
+            return fail(ctx, FCSD_EUNSUPPORTED, "continuation fit failed");
+          aq_of_C[P.C] = m;
+        }
+        gf_of[key] = (int)gf.size();
+        std::vector<double> g((size_t)P.N * 2 * s->d);
+        if (fcsd_host_fold_matrix(P.N, P.C, s->d, aq_of_C[P.C].data(), 1, alpha, p, g.data()) != 0)
+          return fail(ctx, FCSD_EUNSUPPORTED, "fold matrix of the transposed filter failed");
+        gf.insert(gf.end(), g.begin(), g.end());
+      }
+      P.gf = gf_of[key];
     }
+  if (gf.empty()) gf.push_back(0.0);
   (void)hipFree(s->d_kf);
   s->d_kf = nullptr;
+  (void)hipFree(s->d_gf);
+  s->d_gf = nullptr;
   s->filter_on = 0;
   fcsd_status r;
-  if ((r = upload(ctx, &s->d_kf, kf))) return r;
+  if ((r = upload(ctx, &s->d_kf, kf)) || (r = upload(ctx, &s->d_gf, gf))) return r;
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
     (void)hipFree(D.d_plans);

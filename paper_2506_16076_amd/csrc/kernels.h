@@ -29,6 +29,8 @@ struct PassArgs {
   float* d2out;               // pass B1: also store d2 (e - e_ref) here when not null
   const double* aq;
   const double* dq;
+  const double* gq;           // fold matrices of the transposed derivative (per plan, P.gq)
+  const double* gf;           // fold matrices of the transposed filter (per plan, P.gf)
   int d;
   long long plane;
   int nf;
@@ -170,7 +172,7 @@ __global__ void FCSD_LINE_BOUNDS k_fcdiff(PassArgs a) {
           M.w, [&](unsigned g) { return make_float2(at(A, g), at(B, g)); },
           [&](unsigned, unsigned l, float2 v) { at(z, l) = make_float2(v.x, two ? v.y : 0.f); });
       __syncthreads();
-      line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
+      line_derivative<true>(X, Pg, P, a.gq, a.dq, a.d);
     }
     float* OA = a.out + (long long)f * a.plane + M.base;
     float* OB = two ? a.out + (long long)(f + 1) * a.plane + M.base : OA;
@@ -544,9 +546,13 @@ __global__ void FCSD_LINE_BOUNDS k_filter_adj(PassArgs a) {
   }
   zero_tail(X, P);
   __syncthreads();
+  if (!P.periodic) {
+    fold_pre(X, P.N, a.gf + P.gf, a.d);
+    __syncthreads();
+  }
   fft_apply<true>(X, Pg, P);
   if (!P.periodic) {
-    fold_tail(X, P, a.aq + P.aq, a.d);
+    fold_post(X, P.N, a.d);
     __syncthreads();
   }
   if (DIR == 2) {

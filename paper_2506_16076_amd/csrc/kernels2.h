@@ -1354,7 +1354,7 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb1(PassArgs a, const float* rb, float* Hb
         M.w, [&](unsigned g) { return make_float4(at(rbc, g), at(mdx, g), at(mdy, g), 0.f); },
         [&](unsigned, unsigned l, float4 v) { at(z, l) = make_float2(v.y * v.x, v.z * v.x); });
     __syncthreads();
-    line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
+    line_derivative<true>(X, Pg, P, a.gq, a.dq, a.d);
     float* hbx = Hb + (2 * comp) * pl + bo;
     float* hby = Hb + (2 * comp + 1) * pl + bo;
     walk(M.w, [&](unsigned g, unsigned l) {
@@ -1406,7 +1406,7 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* H
           at(zb, l) = make_float2(q.mx * q.r1, q.my * q.r1);
         });
     __syncthreads();
-    line_derivative<true>(X, Pg, P, a.aq, a.dq, a.d);
+    line_derivative<true>(X, Pg, P, a.gq, a.dq, a.d);
     float* hb0 = Hb + (2 * comp) * pl + bo;   // x, y of comp; then of comp + 1
     const long long fo = comp * pl + bo;
     if (!VISC) {

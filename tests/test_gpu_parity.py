@@ -18,10 +18,15 @@ pytestmark = pytest.mark.gpu
 G = 1.4
 RHS_TOL = 1e-5
 STEP_TOL = 1e-4
-# transposed FC operators fold the tail back onto the end samples through
-# A_r Q^T (entries up to ~1e4): FP32 rounding of the inverse-FFT tail is
-# amplified there, which sets this bar for single reverse-mode evaluations
-ADJ_TOL = 5e-4
+# single reverse-mode evaluations: the transposed FC operators fold their
+# tail onto the end samples in FP64 from the cotangent itself (the fold's
+# entries reach ~1e4), so they keep the forward's accuracy up to the
+# longer chains of FP32 products in the reverse passes
+ADJ_TOL = 2e-5
+# pointwise bar: the largest error of a component, relative to the
+# component's largest value, within 10x the component's relative-L2 bar
+# (errors gathered at line ends or patch edges cannot hide in the norm)
+PT = 10.0
 
 
 def say(*a):
@@ -97,6 +102,187 @@ def relerr_phys(ps, got, want):
     return np.array([np.linalg.norm(flat(got, f) - flat(want, f)) / den[f] for f in range(4)])
 
 
+def maxrel_phys(ps, got, want):
+    """max |got - want| per conserved component over valid patch points,
+    relative to the component's largest |want| (the momentum components to
+    their common scale, as in relerr_phys); any number of fields when not 4
+    (then each to its own scale)"""
+    got = np.asarray(got, np.float64).reshape(-1, ps.plane)
+    want = np.asarray(want, np.float64).reshape(-1, ps.plane)
+    nf = want.shape[0]
+    def flat(a, f):
+        return np.concatenate([ps.view(a[f], p).ravel() for p in range(ps.npatch)])
+    sc = [np.abs(flat(want, f)).max() for f in range(nf)]
+    if nf == 4:
+        sc[1] = sc[2] = max(sc[1], sc[2])
+    return np.array([np.abs(flat(got, f) - flat(want, f)).max() / max(sc[f], 1e-300) for f in range(nf)])
+
+
+# ------------------------------------------------------------------ decisions
+# The network classes and the 7 x 7 maximisers are integers decided by
+# floating point.  The oracle decides in FP64 (the definition); the kernels
+# decide on FP32 values.  Bounds on the FP32 values' errors:
+#   * Phi and S from an FP32 state: relative error <= (4 kappa + 8) u,
+#     u = 2^-24, kappa = E / (E - |m|^2/(2 rho)) the cancellation factor of
+#     the pressure (a chain of about eight roundings, the subtraction's
+#     operands' errors amplified by kappa);
+#   * features x = 2 (w - lo)/(hi - lo) - 1 of a window whose samples carry
+#     absolute errors <= eps: |dx| <= 8 eps / (rng - 2 eps) + 8 u
+#     (rng = hi - lo; unbounded when 2 eps >= rng or when rng is within
+#     2 eps of the flatness threshold; a window of identical samples is flat
+#     on both sides);
+#   * logits, to first order: |dl_k| <= sum_i |J_ik| max |dx|, J the
+#     network's Jacobian at the window (W1 D1 W2 D2 W3, D the ReLU masks),
+#     plus the network's own rounding (fp16 splits with FP32 sums: <= 100 u
+#     times the magnitude of every layer's products, carried on by the
+#     later layers' largest column sums of |W|).
+# A decision whose FP64 margin (top-two logit gap, or best minus second
+# 7 x 7 value) exceeds twice the bound is compared exactly; at every other
+# point the GPU's choice must be one of the FP64 candidates within twice
+# the bound of the best.  The features are ill-conditioned (the window's
+# range of Phi is ~1e-3 of Phi on a +-1 % flow, less on small subpatches),
+# so on these workloads 10-50 % of the classes, and as many of the
+# maximisers (S varies along plane waves, so stencils hold near-equal
+# values), are such near ties; their count is printed.
+U32 = 2.0 ** -24
+
+
+def fp32_value_bound(e):
+    """Relative FP32 error bound of Phi and S at every point of e [4, ...]."""
+    rho, m, n, E = np.asarray(e, np.float64)
+    ke = 0.5 * (m * m + n * n) / rho
+    return (4.0 * np.abs(E) / np.abs(E - ke) + 8.0) * U32
+
+
+def _window_dx_bound(phi, eps):
+    """[nl, n] lines of Phi and of its absolute error bound -> [nl, n] bound
+    on max |dx| over each point's window (inf where undecidable)."""
+    nl, n = phi.shape
+    idx = np.clip(np.arange(n)[:, None] + np.arange(-8, 8)[None, :], 0, n - 1)
+    w, ew = phi[:, idx], eps[:, idx]
+    lo, hi = w.min(-1), w.max(-1)
+    rng = hi - lo
+    em = ew.max(-1)
+    thr = 1e-6 * np.maximum(1.0, np.abs(hi))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dx = np.where(2 * em < rng, 8 * em / (rng - 2 * em) + 8 * U32, np.inf)
+    dx = np.where(np.abs(rng - thr) <= 2 * em, np.inf, dx)          # flatness undecidable
+    dx = np.where(rng + 2 * em < thr, 8 * U32, dx)                   # flat on both sides
+    dx = np.where(rng == 0, 0.0, dx)                                 # identical samples
+    return dx
+
+
+def _logit_bound(x, dx, W):
+    """First-order bound of |FP32 logits - FP64 logits| for feature rows x
+    [..., 16] with feature errors <= dx [...]."""
+    W = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    A = {k: np.abs(v) for k, v in W.items()}
+    z1 = x @ W["W1"] + W["b1"]
+    z2 = np.maximum(z1, 0) @ W["W2"] + W["b2"]
+    Tm = np.matmul(W["W2"], (z2 > 0)[..., :, None] * W["W3"])            # [..., 64, 4]
+    J = np.matmul(W["W1"], (z1 > 0)[..., :, None] * Tm)                  # [..., 16, 4]
+    first = np.abs(J).sum(-2) * dx[..., None]
+    n = [A[k].sum(0).max() for k in ("W1", "W2", "W3")]
+    m1 = np.abs(x) @ A["W1"] + A["b1"]
+    m2 = m1 @ A["W2"] + A["b2"]
+    m3 = m2 @ A["W3"] + A["b3"]
+    own = 100 * U32 * (m3 + n[2] * m2.max(-1, keepdims=True) + n[2] * n[1] * m1.max(-1, keepdims=True))
+    with np.errstate(invalid="ignore"):
+        return first + own
+
+
+def decision_check(ps, e, mlp, tau_gpu, arg_gpu=None, logits_gpu=None, label=""):
+    """Compare the GPU's classes (and maximisers, logits) at the FP32 state
+    e with the oracle's FP64 decisions: exactly where the FP64 margin is
+    above twice the FP32 bound, and as a choice among the near-tied FP64
+    candidates everywhere else; logits within the bound."""
+    from oracle import rk
+    e = np.asarray(e, np.float64).reshape(4, ps.plane)
+    want, lg = av.classify(e, ps, mlp, G, return_logits=True)
+    comp = excl = acomp = aexcl = 0
+    for p in range(ps.npatch):
+        ep = ps.view(e, p)
+        rel = fp32_value_bound(ep)
+        phi = av.proxy(ep, G)
+        eps = rel * np.abs(phi)
+        m = av.dtilde_mask(ps, p)
+        l1, l2 = lg[p]
+        x1 = av.features_lines(phi)
+        x2 = np.swapaxes(av.features_lines(phi.T), 0, 1)
+        b1 = _logit_bound(x1, _window_dx_bound(phi, eps), mlp)
+        b2 = _logit_bound(x2, np.swapaxes(_window_dx_bound(phi.T, eps.T), 0, 1), mlp)
+        B1, B2 = b1.max(-1), b2.max(-1)
+
+        def gap(l):
+            srt = np.sort(l, axis=-1)
+            return srt[..., -1] - srt[..., -2]
+        sure = (gap(l1) > 2 * B1) & (gap(l2) > 2 * B2) & m
+        g = ps.view(tau_gpu, p)
+        assert np.array_equal(g[sure], ps.view(want, p)[sure]), (label, p)
+        assert np.all(g[~m] == 0) and np.all((g[m] >= 1) & (g[m] <= 4))
+        # near ties: the GPU's class is 1 + min(i, j) over candidates i of
+        # direction 1 and j of direction 2 within 2B of their best logit
+        c1 = l1 >= l1.max(-1, keepdims=True) - 2 * B1[..., None]
+        c2 = l2 >= l2.max(-1, keepdims=True) - 2 * B2[..., None]
+        ok = np.zeros(g.shape, bool)
+        for i in range(4):
+            for j in range(4):
+                ok |= c1[..., i] & c2[..., j] & (g == 1 + min(i, j))
+        assert np.all(ok[m & ~sure]), (label, p)
+        comp += int(sure.sum())
+        excl += int((m & ~sure).sum())
+        if logits_gpu is not None:
+            o, a_, b_ = int(ps.off[p]), int(ps.n1[p]), int(ps.n2[p])
+            gls = []
+            for k, (lw, bd) in enumerate(((l1, b1), (l2, b2))):
+                gl = logits_gpu[k][o:o + a_ * b_].reshape(b_, a_, 4)
+                fin = m[..., None] & np.isfinite(bd)
+                assert np.all(np.abs(gl - lw)[fin] <= bd[fin]), (label, p, k)
+                assert np.all(gl[~m] == 0)
+                gls.append(gl)
+            # the GPU's classes are its own logits' classes (same rule)
+            assert np.array_equal(g[m], av.classes_from_logits(gls[0], gls[1])[m]), (label, p)
+        if arg_gpu is not None:
+            a, x = maximiser_check(ep, ps.view(arg_gpu, p), (label, p))
+            acomp += a
+            aexcl += x
+    say("  decisions", label, "classes compared", comp, "near ties", excl,
+        "| maximisers compared", acomp, "near ties", aexcl)
+    assert comp > 0 and (arg_gpu is None or acomp > 0)
+    return comp, excl
+
+
+def maximiser_check(ep, ga, label=""):
+    """The GPU's 7 x 7 maximisers ga [n2, n1] (patch-local flat indices) at
+    the FP32 patch state ep [4, n2, n1]: the FP64 maximiser wherever the
+    margin best - second exceeds twice the FP32 bound of S, elsewhere a
+    position of the clamped stencil whose FP64 value is within that bound
+    of the best.  Returns (compared, near ties)."""
+    from oracle import rk
+    S = rk.wave_speed(ep, G)
+    best, arg, second = av.stencil_max(S, second=True)
+    dS, _ = av.stencil_max(fp32_value_bound(ep) * S)
+    sure = best - second > 2 * dS
+    assert np.array_equal(ga[sure], arg[sure]), label
+    b_, a_ = S.shape
+    J_, I_ = np.meshgrid(np.arange(b_), np.arange(a_), indexing="ij")
+    inside = (ga >= 0) & (ga < a_ * b_) & (np.abs(ga // a_ - J_) <= 3) & (np.abs(ga % a_ - I_) <= 3)
+    assert np.all(inside), label
+    assert np.all(S.ravel()[np.clip(ga, 0, a_ * b_ - 1)] >= best - 2 * dS), label
+    return int(sure.sum()), int((~sure).sum())
+
+
+def first_step_input(api, s, D, ps, u, cfg):
+    """The glued FP32 state a step's network sees: a copy of the device
+    state through fcsd_glue (fringe copies, Dirichlet inflow, walls)."""
+    x = u.clone()
+    if ps.dirichlet is not None:
+        api.fcsd_glue(s, x, D(ps.dirichlet), synth.freestream(cfg.mach))
+    else:
+        api.fcsd_glue(s, x)
+    return s.to_host(x).reshape(4, -1)
+
+
 def smooth_fields(ps, nf, seed):
     rng = np.random.default_rng(seed)
     x, y = ps.xy
@@ -130,8 +316,9 @@ def test_fc_diff_uneven_patches(env, direction, layout):
     api.fc_diff(s, direction, D(F), out, nf=3)
     want = fcgram.diff_plane(F.astype(np.float64), ps, direction)
     err = relerr(ps, H(out), want)
-    say("  rel L2", err)
-    assert np.all(err < RHS_TOL)
+    mx = maxrel_phys(ps, H(out), want)
+    say("  rel L2", err, "max", mx)
+    assert np.all(err < RHS_TOL) and np.all(mx < PT * RHS_TOL)
     s.close()
 
 
@@ -146,8 +333,11 @@ def test_fc_diff_adjoint(env, direction):
     api.fc_diff_adj(s, direction, dev(torch, Y), acc, nf=2)
     want = base.reshape(2, -1) + fcgram.diff_plane_adj(Y.astype(np.float64), ps, direction)
     err = relerr(ps, host(acc), want)
-    say("fc_diff_adj", direction, err)
-    assert np.all(err < ADJ_TOL)
+    # the transposed part alone (the accumulator's base is exact)
+    d_err = relerr(ps, host(acc) - base, want - base.reshape(2, -1))
+    mx = maxrel_phys(ps, host(acc) - base, want - base.reshape(2, -1))
+    say("fc_diff_adj", direction, err, "transposed part", d_err, "max", mx)
+    assert np.all(d_err < ADJ_TOL) and np.all(mx < PT * ADJ_TOL)
     s.close()
 
 
@@ -247,8 +437,9 @@ def test_full_rhs(env, case, layout):
     e1 = relerr_phys(ps, H(r1), w1)
     api.av_apply(s, ud, metric, mud, ref, r1)
     e2 = relerr_phys(ps, H(r1), want)
-    say("  full rhs rel L2", err, "euler_rhs", e1, "euler_rhs + av_apply", e2)
-    assert np.all(err < RHS_TOL)
+    mx = maxrel_phys(ps, H(rhs), want)
+    say("  full rhs rel L2", err, "max", mx, "euler_rhs", e1, "euler_rhs + av_apply", e2)
+    assert np.all(err < RHS_TOL) and np.all(mx < PT * RHS_TOL)
     assert np.all(e1 < RHS_TOL) and np.all(e2 < RHS_TOL)
     s.close()
 
@@ -330,6 +521,9 @@ def test_state_monitor(env):
 # ------------------------------------------------------------------ viscosity
 
 def test_network_classes(env):
+    """sdnn_infer against the oracle's FP64 classifier: logits of both
+    directions within the FP32 bound of every window, classes equal wherever
+    the FP64 top-two gap exceeds twice it (near ties counted)."""
     api, ctx, torch = env
     cfg = synth.config(1, n=48)
     ps = cfg.ps
@@ -338,30 +532,8 @@ def test_network_classes(env):
     tau = torch.zeros(ps.plane, dtype=torch.int8, device="cuda:0")
     logits = torch.zeros(8 * ps.plane, device="cuda:0")
     api.sdnn_infer(s, dev(torch, cfg.u0), G, W, tau, logits)
-    want, lg = av.classify(cfg.u0.astype(np.float64), ps, cfg.mlp, G, return_logits=True)
-    got = host(tau)
     gl = host(logits).reshape(2, ps.plane, 4)
-    decided = 0
-    for p in range(ps.npatch):
-        m = av.dtilde_mask(ps, p)
-        l1, l2 = lg[p]
-        # decision is unique where both directions' top-two gaps exceed the bound
-        def gap(l):
-            srt = np.sort(l, axis=-1)
-            return srt[..., -1] - srt[..., -2]
-        sure = (gap(l1) > 1e-5) & (gap(l2) > 1e-5) & m
-        g = ps.view(got, p)
-        w = ps.view(want, p)
-        assert np.array_equal(g[sure], w[sure])
-        assert np.all(g[~m] == 0)
-        assert np.all((g[m] >= 1) & (g[m] <= 4))
-        decided += sure.sum()
-        o, n1_, n2_ = int(ps.off[p]), int(ps.n1[p]), int(ps.n2[p])
-        g1 = gl[0][o:o + n1_ * n2_].reshape(n2_, n1_, 4)
-        assert np.abs(g1[m] - l1[m]).max() < 2e-5
-        assert np.all(g1[~m] == 0)
-    say("network classes decided", decided)
-    assert decided > 0.99 * sum(av.dtilde_mask(ps, p).sum() for p in range(ps.npatch))
+    decision_check(ps, cfg.u0, cfg.mlp, host(tau), logits_gpu=gl, label="network")
     s.close()
 
 
@@ -384,11 +556,17 @@ def test_viscosity_operator(env, case, layout):
     muh, arg = av.preliminary(u.astype(np.float64), tau, ps, G)
     want = av.smooth_blend(muh, ps)
     err = relerr(ps, H(mu), want)
+    mx = maxrel_phys(ps, H(mu), want)
+    # maximisers: the FP64 one where the margin exceeds the FP32 bound of S,
+    # elsewhere a near-tied stencil position
     ga = H(amax)
+    comp = excl = 0
     for p in range(ps.npatch):
-        assert np.array_equal(ps.view(ga, p), ps.view(arg, p))
-    say("av_viscosity", case, err)
-    assert err[0] < 2e-6
+        a, x = maximiser_check(ps.view(np.asarray(u, np.float64), p), ps.view(ga, p), (case, p))
+        comp += a
+        excl += x
+    say("av_viscosity", case, err, "max", mx, "maximisers compared", comp, "near ties", excl)
+    assert err[0] < 2e-6 and mx[0] < 2e-5 and comp > 0
     s.close()
 
 
@@ -470,11 +648,12 @@ def test_steps_annulus_with_network(env, layout):
                      dirichlet_state=synth.freestream(cfg.mach))
     run = solver.Run(cfg)
     for k in range(3):
+        u_in = first_step_input(api, s, D, ps, u, cfg) if k == 0 else None
         st.step()
-        run.step()
-        same = np.mean(H(st.tau) == run.log[-1]["tau"])
-        say("step", k, "layout", layout, "tau agreement", same, "dt", float(host(st.dt)[0]), run.log[-1]["dt"])
-        assert same > 0.999
+        if k == 0:
+            decision_check(ps, u_in, cfg.mlp, H(st.tau), H(st.argmax), label="annulus first step")
+        run.step(tau=H(st.tau), arg=H(st.argmax))
+        say("step", k, "layout", layout, "dt", float(host(st.dt)[0]), run.log[-1]["dt"])
     got = H(u).reshape(4, -1)
     err = relerr_phys(ps, got, run.u)
     chg = relerr_phys(ps, got - cfg.u0, run.u - cfg.u0)
@@ -497,12 +676,12 @@ def test_steps_paper_subpatches(env, layout):
                      dirichlet_state=synth.freestream(cfg.mach))
     run = solver.Run(cfg)
     for k in range(3):
+        u_in = first_step_input(api, s, D, ps, u, cfg) if k == 0 else None
         st.step()
-        run.step()
-        same = np.mean(H(st.tau) == run.log[-1]["tau"])
-        say("paper subpatches step", k, "layout", layout, "tau agreement", same, "dt", float(host(st.dt)[0]),
-            run.log[-1]["dt"])
-        assert same > 0.999
+        if k == 0:
+            decision_check(ps, u_in, cfg.mlp, H(st.tau), H(st.argmax), label="paper subpatches first step")
+        run.step(tau=H(st.tau), arg=H(st.argmax))
+        say("paper subpatches step", k, "layout", layout, "dt", float(host(st.dt)[0]), run.log[-1]["dt"])
     err = relerr_phys(ps, H(u).reshape(4, -1), run.u)
     say("3 steps paper subpatches: state rel L2", err)
     assert np.all(err < STEP_TOL)
@@ -553,7 +732,8 @@ def test_steps_interpolated_patches(env, layout, network):
     every stage, constant viscosity or the network's (smoothed across the
     pair), against the oracle (state <= 1e-4).  With the network the
     oracle replays the GPU's decisions (classes, maximisers, step sizes),
-    whose first step must agree with the oracle's own classes (>= 99.9 %)."""
+    whose first step must agree with the oracle's FP64 decisions wherever
+    their margin exceeds the FP32 bound."""
     api, ctx, torch = env
     cfg = synth.overlap_config(48, network=network)
     ps = cfg.ps
@@ -567,16 +747,13 @@ def test_steps_interpolated_patches(env, layout, network):
         st = api.Stepper(s, u, D(ps.metric), cfg.ref, mu=D(np.full(ps.plane, cfg.mu_const, np.float32)))
     run = solver.Run(cfg)
     for k in range(5):
+        u_in = first_step_input(api, s, D, ps, u, cfg) if (network and k == 0) else None
         st.step(use_graph=(k > 0))
         if not network:
             run.step()
             continue
         if k == 0:
-            free = solver.Run(cfg)
-            free.step()
-            same = np.mean(H(st.tau) == free.log[-1]["tau"])
-            say("  interpolated pair, first step tau agreement", same)
-            assert same > 0.999
+            decision_check(ps, u_in, cfg.mlp, H(st.tau), H(st.argmax), label="interpolated pair first step")
         run.step(dt=float(host(st.dt)[0]), tau=H(st.tau), arg=H(st.argmax))
     got = H(u).reshape(4, -1)
     err = relerr_phys(ps, got, run.u)
@@ -742,8 +919,11 @@ def test_rhs_reverse_mode(env, case):
                                 rb.astype(np.float64))
     e1 = relerr_phys(ps, host(ub), we)
     e2 = relerr(ps, host(mb), wm)
-    say("rhs adjoint", case, e1, e2)
+    m1 = maxrel_phys(ps, host(ub), we)
+    m2 = maxrel_phys(ps, host(mb), wm)
+    say("rhs adjoint", case, e1, e2, "max", m1, m2)
     assert np.all(e1 < ADJ_TOL) and e2[0] < ADJ_TOL
+    assert np.all(m1 < PT * ADJ_TOL) and m2[0] < PT * ADJ_TOL
     s.close()
 
 
@@ -985,8 +1165,9 @@ def test_full_size_rhs_sampled_patches(env, idx):
     sub = _subset(ps, plist)
     want = euler.full_rhs(cfg.u0.astype(np.float64), ps.metric, mu.astype(np.float64), sub, G)
     err = relerr_phys(sub, got, want)
-    say("  patches", plist, "rel L2", err)
-    assert np.all(err < RHS_TOL)
+    mx = maxrel_phys(sub, got, want)
+    say("  patches", plist, "rel L2", err, "max", mx)
+    assert np.all(err < RHS_TOL) and np.all(mx < PT * RHS_TOL)
     s.close()
 
 
@@ -1160,12 +1341,12 @@ def test_steps_with_filter(env, layout):
     ref_run = solver.Run(cfg)
     ref_run.u = u0.astype(np.float64)
     for k in range(3):
+        u_in = first_step_input(api, s, D, ps, u, cfg) if k == 0 else None
         st.step()
-        run.step(filt=(ALPHA_F, P_F))
+        if k == 0:
+            decision_check(ps, u_in, cfg.mlp, H(st.tau), H(st.argmax), label="filtered first step")
+        run.step(tau=H(st.tau), arg=H(st.argmax), filt=(ALPHA_F, P_F))
         ref_run.step(dt=run.log[-1]["dt"], tau=run.log[-1]["tau"], arg=run.log[-1]["arg"])
-        same = np.mean(H(st.tau) == run.log[-1]["tau"])
-        say("filtered step", k, "layout", layout, "tau agreement", same)
-        assert same > 0.999
     got = H(u).reshape(4, -1)
     err = relerr_phys(ps, got, run.u)
     eff = relerr_phys(ps, run.u, ref_run.u)     # what the filter changed over three steps
@@ -1178,14 +1359,11 @@ def test_steps_with_filter(env, layout):
 @pytest.mark.parametrize("case", ["square64", "annulus", "uneven"])
 def test_filter_reverse_mode(env, case):
     """fcsd_filter_adj against the oracle's vector-Jacobian product of the
-    state filter at the same state.  Bars: the transposed line filter folds
-    the tail of an FP32 transform back onto the d end samples of each line
-    through A_r Q^T, whose column sums of magnitudes reach 4e4 (C = 27) to
-    2e5 (C = 38): the transform's absolute rounding (~2e-7 of the line's
-    size) becomes ~1e-3 there, and the rho component, where the energy and
-    temperature terms cancel, carries it relative to a smaller value.  So:
-    away from the patch edges (more than 2d samples in) <= 1e-5, over the
-    whole field <= 5e-3 (random cotangents: 1.4e-3 observed on 64^2)."""
+    state filter at the same state.  The transposed line filter folds its
+    tail onto the d end samples of each line in FP64 from the cotangent
+    (the fold's entries reach ~1e4), so the bar holds over the whole field:
+    relative L2 <= 1e-5 and pointwise <= 1e-4 per component, and <= 1e-5
+    away from the patch edges."""
     from oracle import filter as flt
     api, ctx, torch = env
     ps, u, _, _ = rhs_case(case)
@@ -1203,8 +1381,9 @@ def test_filter_reverse_mode(env, case):
         ps.view(inner[0], p)[10:-10, 10:-10] = 1
     inner[1:] = inner[0]
     err_in = relerr(ps, got * inner, want * inner)
-    say("filter reverse mode", case, "rel L2", err, "interior", err_in)
-    assert np.all(err < 5e-3) and np.all(err_in < 1e-5)
+    mx = maxrel_phys(ps, got, want)
+    say("filter reverse mode", case, "rel L2", err, "interior", err_in, "max", mx)
+    assert np.all(err < 1e-5) and np.all(err_in < 1e-5) and np.all(mx < PT * 1e-5)
     # in place (u_bar = out_bar)
     yd = D(yb)
     api.fcsd_filter_adj(s, D(x), yd, yd, G)

@@ -249,3 +249,45 @@ def test_blocked_layout_tables(L):
     want = int(off[p]) + 32 * ((j // 4) * nb1 + i // 8) + 8 * (j % 4) + i % 8
     k = int(np.sum(ps.n1[:p].astype(np.int64) * ps.n2[:p])) + j * n1 + i
     assert rows[k] == int(ps.off[p]) + j * n1 + i and blk[k] == want
+
+
+def _fold(lib, N, C, d, kind, alpha=0.0, p=0):
+    arq = np.ascontiguousarray(fcgram.continuation_matrix(d, C), np.float64)
+    out = np.zeros(N * 2 * d, np.float64)
+    rc = lib.fcsd_host_fold_matrix(ctypes.c_int(N), ctypes.c_int(C), ctypes.c_int(d),
+                                   arq.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(kind),
+                                   ctypes.c_double(alpha), ctypes.c_int(p), out.ctypes.data_as(ctypes.c_void_p))
+    assert rc == 0
+    return out.reshape(N, 2 * d)
+
+
+@pytest.mark.parametrize("N,C,d", [(48, 30, 5), (64, 27, 5), (101, 27, 2), (120, 36, 5), (57, 33, 5)])
+def test_fold_matrix_is_the_transposed_operators_tail_fold(L, N, C, d):
+    """The library's fold matrix G (host, binary128 / long double) applied
+    to a cotangent equals what the oracle's transposed operator adds to the
+    2d end samples beyond its circulant part: D^T y - (-S pad(y))[:N] for the
+    derivative, F^T y - (F pad(y))[:N] for the filter (F symmetric)."""
+    from oracle import filter as flt
+    lib = L.lib()
+    rng = np.random.default_rng(N + C)
+    Y = rng.standard_normal((6, N))
+    h = 1.0 / (N - 1)
+    pad = np.concatenate([Y, np.zeros((6, C))], axis=-1)
+    for kind in (0, 1):
+        if kind == 0:
+            G = _fold(lib, N, C, d, 0)
+            full = fcgram.diff_lines_adj(Y, d, C)
+            circ = -fcgram.periodic_derivative(pad, (N + C) * h)[:, :N]
+        else:
+            G = _fold(lib, N, C, d, 1, 10.0, 14)
+            full = flt.filter_lines_adj(Y, d, C, 10.0, 14)
+            circ = np.real(np.fft.ifft(np.fft.fft(pad, axis=-1) * flt.sigma(N + C, 10.0, 14), axis=-1))[:, :N]
+        fold = full - circ
+        want = np.concatenate([fold[:, N - d:], fold[:, :d]], axis=-1)     # e < d right, e >= d left
+        got = Y @ G
+        # the oracle folds an FP64 FFT tail: its own rounding, eps64 times
+        # sum |A_r Q^T| (~1.4e4 for d = 5) times the transform's size
+        bound = 16 * np.finfo(float).eps * np.abs(fcgram.continuation_matrix(d, C)).sum() * np.abs(full).max()
+        assert np.abs(got - want).max() <= bound, kind
+        # nothing is folded onto the interior samples
+        assert np.abs(fold[:, d:N - d]).max() <= 1e-12 * np.abs(full).max()

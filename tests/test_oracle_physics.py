@@ -251,17 +251,79 @@ def test_mlp_matches_naive_loops():
         assert np.allclose(out[r], o, rtol=1e-12, atol=1e-12)
 
 
-def test_fp32_decision_path_matches_fp64_values():
-    cfg = synth.config(1, n=40)
-    e = cfg.u0
-    phi32, S32 = av.proxy_speed_f32(e, G)
-    ps = cfg.ps
-    for p in range(ps.npatch):
-        assert np.allclose(ps.view(phi32, p), ps.view(av.proxy(e, G), p), rtol=1e-6)
-        assert np.allclose(ps.view(S32, p), ps.view(rk.wave_speed(e, G), p), rtol=1e-6)
-    t64 = av.classify(e, ps, cfg.mlp, G, fp32=False)
-    t32 = av.classify(e, ps, cfg.mlp, G, fp32=True)
-    assert np.mean(t64 == t32) > 0.99
+def test_wave_speed_and_proxy_at_known_states():
+    """S = |u| + |v| + a and Phi = |u| sqrt(rho / (gamma p)) (Sec. 5.1) at
+    (rho, u, v, p) = (2, 3, -1, 5): S = 4 + sqrt(3.5), Phi = sqrt(20/7); at
+    (0.5, -2, 4, 0.7): S = 6 + 1.4, Phi = sqrt(20 * 0.5 / 0.98).  The
+    conserved states are written out: E = p/(gamma-1) + rho |u|^2/2."""
+    e = np.array([[2.0, 0.5], [6.0, -1.0], [-2.0, 2.0], [22.5, 6.75]])
+    S = rk.wave_speed(e, G)
+    phi = av.proxy(e, G)
+    assert np.allclose(S, [4 + np.sqrt(3.5), 7.4], rtol=1e-14, atol=0)
+    assert np.allclose(phi, [np.sqrt(20 / 7), np.sqrt(10 / 0.98)], rtol=1e-14, atol=0)
+
+
+def test_two_direction_class_rule():
+    """The class of a point is 1 + the smaller of the two directions'
+    argmax indices, a direction's ties going to the lowest index."""
+    l1 = np.array([[0.1, 0.5, 0.5, 0.2], [0.9, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 1.0], [0.3, 0.3, 0.3, 0.3]])
+    l2 = np.array([[0.3, 0.1, 0.2, 0.6], [0.0, 0.0, 0.7, 0.0], [0.0, 0.0, 1.0, 0.0], [0.0, 0.1, 0.1, 0.0]])
+    assert av.classes_from_logits(l1, l2).tolist() == [2, 1, 3, 1]
+
+
+def _probe_network():
+    """A 16-64-64-4 network with known logits: unit 0 carries the window's
+    first feature x0 (offset -8), unit 1 carries -x0, so the logits are
+    (relu(x0), relu(-x0), 1/4, 1/4)."""
+    W = {"W1": np.zeros((16, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+         "W3": np.zeros((64, 4)), "b3": np.array([0.0, 0.0, 0.25, 0.25])}
+    W["W1"][0, 0], W["W1"][0, 1] = 1.0, -1.0
+    W["W2"][0, 0] = W["W2"][1, 1] = 1.0
+    W["W3"][0, 0] = W["W3"][1, 1] = 1.0
+    return W
+
+
+def test_classify_combines_directions_by_the_smaller_class():
+    """On a 40 x 40 square with rho = 1, p = 1/gamma, v = 0 the proxy is
+    Phi = |u|.  With u = 1 + 0.1 x - 0.1 y every q1 window rises (x0 = -1:
+    logits (0, 1, 1/4, 1/4), class 2) and every q2 window falls (x0 = 1:
+    logits (1, 0, 1/4, 1/4), class 1): the point's class is 1.  With u
+    constant every window is flat (x = 0): logits (0, 0, 1/4, 1/4), tied,
+    class 3 in both directions.  Points outside D~ (here the 9 columns next
+    to the internal q1- side and the 9 rows next to the internal q2+ side)
+    are 0."""
+    import dataclasses
+    ps = synth.unit_square(40)
+    ps = dataclasses.replace(ps, internal=np.array([[1, 0, 0, 1]], np.uint8))
+    x, y = ps.xy
+    W = _probe_network()
+    for u, want_in in [(1.0 + 0.1 * x - 0.1 * y, 1), (np.full(ps.plane, 1.3), 3)]:
+        e = np.stack([np.ones(ps.plane), u, np.zeros(ps.plane), 1 / (G * (G - 1)) + 0.5 * u * u])
+        tau, lg = av.classify(e, ps, W, G, return_logits=True)
+        t = ps.view(tau, 0)
+        assert np.all(t[:, :9] == 0) and np.all(t[-9:, :] == 0)
+        assert np.all(t[:-9, 9:] == want_in)
+    l1, l2 = lg[0]
+    assert np.allclose(l1[20, 20], [0, 0, 0.25, 0.25]) and np.allclose(l2[20, 20], [0, 0, 0.25, 0.25])
+
+
+def test_viscosity_generation_subgrid_width():
+    """D~ leaves out exactly n_v = 9 grid lines next to each internal side
+    (eq. fringe_region with the equation's strict inequality), for every
+    combination of internal sides of a 30 x 26 patch."""
+    import dataclasses
+    import itertools
+    ps = synth.uneven_sectors(1, 30, 30, 0)
+    ps = dataclasses.replace(ps, n1=np.array([30], np.int32), n2=np.array([26], np.int32))
+    for flags in itertools.product([0, 1], repeat=4):
+        q = dataclasses.replace(ps, internal=np.array([flags], np.uint8))
+        m = av.dtilde_mask(q, 0)
+        assert m.shape == (26, 30)
+        for j in range(26):
+            for i in range(30):
+                out = (flags[0] and i <= 8) or (flags[1] and i >= 21) or (flags[2] and j <= 8) or (flags[3] and j >= 17)
+                assert m[j, i] == (not out), (flags, j, i)
+        assert m.sum() == (30 - 9 * (flags[0] + flags[1])) * (26 - 9 * (flags[2] + flags[3]))
 
 
 def test_features():
@@ -280,12 +342,12 @@ def test_preliminary_viscosity_values():
     for p in range(ps.npatch):
         m = av.dtilde_mask(ps, p)
         ps.view(tau, p)[m] = 1 + (np.arange(m.sum()) % 4)
-    muh, arg = av.preliminary(cfg.u0, tau, ps, G, fp32=False)
-    S = rk.wave_speed(cfg.u0, G)
+    muh, arg = av.preliminary(cfg.u0, tau, ps, G)
     p = 3
+    S = rk.wave_speed(ps.view(cfg.u0.astype(np.float64), p), G)
     m = av.dtilde_mask(ps, p)
     j, i = np.argwhere(m)[17]
-    blk = ps.view(S, p)[max(0, j - 3):j + 4, max(0, i - 3):i + 4].max()
+    blk = S[max(0, j - 3):j + 4, max(0, i - 3):i + 4].max()
     t = ps.view(tau, p)[j, i]
     assert np.isclose(ps.view(muh, p)[j, i], [1.5, 1, 0.5, 0][t - 1] * blk * ps.hhat[p], rtol=1e-14)
     assert np.all(ps.view(muh, p)[~m] == 0)
@@ -295,7 +357,7 @@ def test_viscosity_vjp_matches_finite_differences():
     cfg = synth.config(1, n=36)
     ps = cfg.ps
     e = np.array(cfg.u0, np.float64)
-    mu, tau, arg = av.viscosity(e, ps, cfg.mlp, G, fp32=False)
+    mu, tau, arg = av.viscosity(e, ps, cfg.mlp, G)
     rng = np.random.default_rng(11)
     mb = rng.standard_normal(ps.plane)
     eb = av.viscosity_vjp(e, tau, arg, ps, G, mb)
@@ -303,12 +365,12 @@ def test_viscosity_vjp_matches_finite_differences():
     h = 1e-5
     # frozen decisions: recompute mu^ with the recorded tau and argmax
     def mu_frozen(ee):
-        S = rk.wave_speed(ee, G)
         muh = np.zeros(ps.plane)
         for p in range(ps.npatch):
+            S = rk.wave_speed(ps.view(ee, p), G)
             t = ps.view(tau, p).astype(int)
             r = np.where(t > 0, av.R_TABLE[np.clip(t - 1, 0, 3)], 0.0)
-            muh_p = r * ps.view(S, p).ravel()[ps.view(arg, p)] * ps.hhat[p]
+            muh_p = r * S.ravel()[ps.view(arg, p)] * ps.hhat[p]
             ps.view(muh, p)[...] = np.where(av.dtilde_mask(ps, p), muh_p, 0)
         return av.smooth_blend(muh, ps)
     assert np.allclose(mu_frozen(e), mu, rtol=1e-13)
