@@ -310,6 +310,18 @@ fcsd_status fcsd_cfl_dt(fcsd_ctx* ctx, const fcsd_set* set, const float* u, cons
                         float cfl, float gamma, float* dt_dev, int64_t plane,
                         void* ws, size_t ws_bytes);
 
+/* fcsd_cfl_dt for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, with the per-patch maxima kept in a static device array
+ * of the library (two words per patch) instead of a workspace.  Allocates
+ * nothing and calls no allocating routine.  At most 16384 patches
+ * (FCSD_EINVAL beyond, before any launch).  The array is one per device and
+ * shared by every call on it; each call clears it (fill kernel, no memset)
+ * before use, and calls that overlap on one device (different streams,
+ * threads or contexts of the same device) race on it. */
+fcsd_status fcsd_cfl_dt_noalloc(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* mu,
+                                float cfl, float gamma, float* dt_dev, int64_t plane);
+
 /* State monitor (the admissibility the paper reports its runs keep without
  * limiters, Remark adiabatic_th: positive density and pressure): over the
  * grid points of every patch of a state u [4][plane] (padding is not looked

@@ -118,6 +118,7 @@ def lib():
             "rk_stage": [vp, vp, i32, vp, vp, vp, vp, vp, vp, i64],
             "rk_stage_adj": [vp, vp, i32, vp, vp, vp, vp, vp, vp, i64],
             "fcsd_cfl_dt": [vp, vp, vp, vp, f32, f32, vp, i64, vp, sz],
+            "fcsd_cfl_dt_noalloc": [vp, vp, vp, vp, f32, f32, vp, i64],
             "fcsd_check": [vp, vp, vp, f32, vp, i64],
             "sdnn_infer": [vp, vp, vp, f32, P(Mlp), vp, vp, i64, vp, sz],
             "av_viscosity": [vp, vp, vp, vp, f32, vp, vp, i64, vp, sz],
@@ -152,7 +153,7 @@ EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_l
            "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj", "fcsd_smear", "fcsd_set_interp", "fcsd_set_walls",
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
-           "rk_stage_adj", "fcsd_cfl_dt", "fcsd_check", "sdnn_infer", "av_viscosity", "av_viscosity_adj",
+           "rk_stage_adj", "fcsd_cfl_dt", "fcsd_cfl_dt_noalloc", "fcsd_check", "sdnn_infer", "av_viscosity", "av_viscosity_adj",
            "fcsd_glue", "fcsd_glue_adj", "fcsd_step_adj", "fcsd_stage", "fcsd_stage_per_patch", "fcsd_stage_pass", "fcsd_step", "fcsd_fc_matrix",
            "fcsd_validate_patches", "fcsd_fft_plan", "fcsd_version"]
 

@@ -286,6 +286,13 @@ def fcsd_cfl_dt(s, u, mu, cfl, gamma, dt_dev):
           ws.numel() * 4)
 
 
+def fcsd_cfl_dt_noalloc(s, u, mu, cfl, gamma, dt_dev):
+    """fcsd_cfl_dt without a workspace: the library's static per-device
+    scratch (at most 16384 patches; overlapping calls on one device race)."""
+    _chk(u, numel=4 * s.plane), _chk(mu, numel=s.plane), _chk(dt_dev, numel=1)
+    _call(s, "fcsd_cfl_dt_noalloc", _p(u), _p(mu), float(cfl), float(gamma), _p(dt_dev), s.plane)
+
+
 def fcsd_check(s, u, gamma, flags_dev):
     """State monitor: flags_dev (one int32 on the device) becomes the OR of
     1 (non-finite value), 2 (rho <= 0), 4 (p <= 0) over the grid points."""

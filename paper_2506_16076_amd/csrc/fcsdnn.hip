@@ -11,6 +11,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -44,7 +45,39 @@ struct fcsd_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
+  unsigned* scratch = nullptr;  // this device's address of the static scratch array
 };
+
+// Scratch of the allocation-free entry point fcsd_cfl_dt_noalloc: the
+// per-patch maxima of the step-size reduction, two words per patch, for at
+// most kNoAllocPatches patches (128 KiB).  Every device the library runs on
+// holds its own copy until the process ends.  Host code never uses the
+// name as an address: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current, at context creation) and
+// kept in scratch_of_device.
+constexpr int kNoAllocPatches = 16384;
+static __device__ __align__(256) unsigned scratch[2 * kNoAllocPatches];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+unsigned* scratch_of_device[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device`.
+hipError_t scratch_address(int device, unsigned** out) {
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_of_device[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_of_device[device] = static_cast<unsigned*>(p);
+  }
+  *out = scratch_of_device[device];
+  return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -253,7 +286,9 @@ extern "C" fcsd_status fcsd_ctx_create(int device, void* stream, fcsd_ctx** out)
   if (device < 0 || device >= n) return FCSD_EINVAL;
   std::unique_ptr<fcsd_ctx> c(new fcsd_ctx);
   c->device = device;
+  if (device >= kMaxDevices) return FCSD_EUNSUPPORTED;
   if (hipSetDevice(device) != hipSuccess) return FCSD_EDEVICE;
+  if (scratch_address(device, &c->scratch) != hipSuccess) return FCSD_EHIP;
   if (stream) {
     c->stream = (hipStream_t)stream;
   } else {
@@ -1022,6 +1057,18 @@ extern "C" fcsd_status fcsd_cfl_dt(fcsd_ctx* ctx, const fcsd_set* s, const float
   if (ws_bytes < 2 * sizeof(unsigned) * (size_t)s->npatch)
     return fail(ctx, FCSD_EINVAL, "fcsd_cfl_dt: workspace too small");
   return cfl_dt_impl(ctx, s, u, mu, cfl, gamma, dt_dev, (unsigned*)ws);
+}
+
+extern "C" fcsd_status fcsd_cfl_dt_noalloc(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* mu,
+                                           float cfl, float gamma, float* dt_dev, int64_t plane) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !dt_dev || !(cfl > 0)) return fail(ctx, FCSD_EINVAL, "fcsd_cfl_dt_noalloc: bad arguments");
+  if (s->npatch > kNoAllocPatches)
+    return fail(ctx, FCSD_EINVAL, "fcsd_cfl_dt_noalloc: more than " + std::to_string(kNoAllocPatches) +
+                                      " patches (the static scratch holds two words per patch)");
+  if (!ctx->scratch) return fail(ctx, FCSD_EHIP, "fcsd_cfl_dt_noalloc: no scratch address for this device");
+  return cfl_dt_impl(ctx, s, u, mu, cfl, gamma, dt_dev, ctx->scratch);
 }
 
 extern "C" fcsd_status fcsd_check(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float gamma, int32_t* flags_dev,
