@@ -129,7 +129,7 @@ fcsd_status fcsd_set_tune(fcsd_set* set, const int lds_budget[3], const int thre
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
 enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3, FCSD_WS_STEP_ADJ = 4,
-       FCSD_WS_FILTER_ADJ = 5, FCSD_WS_SMEAR = 6 };
+       FCSD_WS_FILTER_ADJ = 5, FCSD_WS_SMEAR = 6, FCSD_WS_STAGE_ADJ = 7 };
 fcsd_status fcsd_workspace_size(const fcsd_set* set, int op, size_t* bytes);
 
 /* ---- FC-Gram line operators (Sec. 2.2) --------------------------------- */
@@ -284,6 +284,25 @@ fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, con
                          const float* mu, const float ref[4], float gamma, const float* rhs_bar,
                          float* u_bar, float* mu_bar, int64_t plane, void* ws, size_t ws_bytes);
 
+/* Transpose of euler_rhs at u (Secs. 2.1, 3.3, eq. general_curvilinear):
+ * u_bar += (d rhs / du)^T rhs_bar, with the flux Jacobians' transposes at
+ * every point and the transposed FC derivatives (the deviation reference is
+ * a constant and has no cotangent).  rhs_bar [4][plane] is read, u_bar
+ * [4][plane] accumulated; ws: fcsd_workspace_size(FCSD_WS_RHS_ADJ) bytes.
+ * FCSD_EINVAL for a null pointer or a small workspace. */
+fcsd_status euler_rhs_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* metric,
+                          const float ref[4], float gamma, const float* rhs_bar, float* u_bar,
+                          int64_t plane, void* ws, size_t ws_bytes);
+/* Transpose of av_apply at (u, mu) (Sec. 2.3, eqs. f_visc, convection
+ * diffusion eqn, in the chain-rule form of Sec. 3.3): the term
+ * div_x (mu grad_x u) is linear in u for fixed mu and in mu for fixed u;
+ * u_bar += its u-transpose applied to rhs_bar, mu_bar (nullable, one plane)
+ * += grad_x u . (grad_x-divergence transpose of rhs_bar).  Accumulates;
+ * ws: FCSD_WS_RHS_ADJ bytes; mu is required. */
+fcsd_status av_apply_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, const float* metric,
+                         const float* mu, const float ref[4], const float* rhs_bar, float* u_bar,
+                         float* mu_bar, int64_t plane, void* ws, size_t ws_bytes);
+
 /* ---- time stepping (Sec. 4.1) ------------------------------------------ */
 
 /* One stage s = 0..4 of the five-stage fourth-order SSP Runge-Kutta scheme
@@ -382,6 +401,19 @@ fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* set, float* u_bar, int6
                           const uint8_t* dirichlet_mask, const float dstate_dparam[4],
                           double* dparam_dev);
 
+/* Transpose of the classifier network (Sec. 5.1) at the features of the
+ * state u: for every point of the viscosity-generation subgrid and each
+ * direction d = 0, 1 (q1, q2 lines), feat_bar[d][p][0..15] = the cotangent
+ * of the 16 window features given logits_bar[d][p][0..3], through the ReLU
+ * masks of the forward pass at those features (the solver's reverse mode
+ * freezes the classes and does not use this).  Layouts [2][plane][4] and
+ * [2][plane][16] at each point's storage index; feat_bar is overwritten at
+ * grid points (zero outside the subgrid), padding untouched.  ws:
+ * FCSD_WS_AV bytes.  FCSD_EINVAL for a null pointer or weight. */
+fcsd_status sdnn_infer_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, float gamma,
+                           const fcsd_mlp* w, const float* logits_bar, float* feat_bar, int64_t plane,
+                           void* ws, size_t ws_bytes);
+
 /* ---- fused stage and step ------------------------------------------------ */
 
 /* One fused SSPRK stage: right-hand side of ui (with viscosity mu, NULL =
@@ -391,6 +423,18 @@ fcsd_status fcsd_stage(fcsd_ctx* ctx, const fcsd_set* set, int stage, const floa
                        const float* ui, float* acc, float* uout, const float* metric,
                        const float* mu, const float ref[4], float gamma, const float* dt_dev,
                        int64_t plane, void* ws, size_t ws_bytes);
+/* Reverse mode of fcsd_stage (Sec. 4.1) at its input ui, mu fixed: the
+ * register update transposed (as rk_stage_adj: u0_bar and ui_bar
+ * accumulated, acc_bar read and updated for stages >= 2, the dt-scaled
+ * right-hand-side cotangent formed in the workspace), then the right-hand
+ * side's transpose at ui added to ui_bar and, when mu and mu_bar are given,
+ * to mu_bar.  At stage 0 the right-hand side is evaluated at u0: pass the
+ * same buffer as u0_bar and ui_bar to collect both parts.  ws:
+ * fcsd_workspace_size(FCSD_WS_STAGE_ADJ) bytes. */
+fcsd_status fcsd_stage_adj(fcsd_ctx* ctx, const fcsd_set* set, int stage, const float* ui,
+                           const float* metric, const float* mu, const float ref[4], float gamma,
+                           const float* dt_dev, const float* uout_bar, float* u0_bar, float* ui_bar,
+                           float* acc_bar, float* mu_bar, int64_t plane, void* ws, size_t ws_bytes);
 
 /* One of the four passes of fcsd_stage (0: q1 derivatives of the state,
  * 1: q2 derivatives and the combined fluxes H, 2: q2 derivatives of H,

@@ -92,6 +92,18 @@ def mlp_logits(x, W):
     return h @ W["W3"].astype(np.float64) + W["b3"].astype(np.float64)
 
 
+def mlp_vjp(x, W, lb):
+    """Cotangent of the features x [..., 16] given that of the logits lb
+    [..., 4]: the reverse of mlp_logits, through the ReLU masks at x
+    (derivative 0 at a unit whose input is exactly 0)."""
+    Wd = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    z1 = x @ Wd["W1"] + Wd["b1"]
+    z2 = np.maximum(z1, 0.0) @ Wd["W2"] + Wd["b2"]
+    g2 = (lb @ Wd["W3"].T) * (z2 > 0)
+    g1 = (g2 @ Wd["W2"].T) * (z1 > 0)
+    return g1 @ Wd["W1"].T
+
+
 def classes_from_logits(l1, l2):
     """2D smoothness class from the logits of the two directions (reading
     of Sec. 5.1): a direction's class is 1 + the index of its largest logit

@@ -172,6 +172,19 @@ def gradient_adj(exb, eyb, metric, ps):
             + fcgram.diff_plane_adj(m2x * exb + m2y * eyb, ps, 2))
 
 
+def av_term_vjp(e, metric, mu, ps, rb):
+    """(e_bar, mu_bar) for the map (e, mu) -> av_term(e, metric, mu): the
+    term is the divergence of V = mu grad_x e, so with (V_x_bar, V_y_bar) the
+    divergence transpose of rb, mu_bar = V_bar . grad_x e and e_bar is the
+    gradient transpose of mu V_bar."""
+    e = np.asarray(e, np.float64)
+    mu = np.asarray(mu, np.float64)
+    fxb, fyb = divergence_adj(rb, metric, ps)
+    ex, ey = gradient(e, metric, ps)
+    mub = np.sum(fxb * ex + fyb * ey, axis=0)
+    return gradient_adj(mu * fxb, mu * fyb, metric, ps), mub
+
+
 def full_rhs_vjp(e, metric, mu, ps, gamma, rb):
     """(e_bar, mu_bar) for the map (e, mu) -> full_rhs(e, metric, mu)."""
     e = np.asarray(e, np.float64)

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcsdnn.so")
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EHIP", 5: "EUNSUPPORTED", 6: "ENONFINITE"}
-WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR = 0, 1, 2, 3, 4, 5, 6
+WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR, WS_STAGE_ADJ = 0, 1, 2, 3, 4, 5, 6, 7
 LAYOUT_ROWS, LAYOUT_B8X4 = 0, 1
 
 
@@ -115,6 +115,10 @@ def lib():
             "av_apply": [vp, vp, vp, vp, vp, P(f32), vp, i64, vp, sz],
             "fcsd_rhs": [vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
             "fcsd_rhs_adj": [vp, vp, vp, vp, vp, P(f32), f32, vp, vp, vp, i64, vp, sz],
+            "euler_rhs_adj": [vp, vp, vp, vp, P(f32), f32, vp, vp, i64, vp, sz],
+            "av_apply_adj": [vp, vp, vp, vp, vp, P(f32), vp, vp, vp, i64, vp, sz],
+            "sdnn_infer_adj": [vp, vp, vp, f32, P(Mlp), vp, vp, i64, vp, sz],
+            "fcsd_stage_adj": [vp, vp, i32, vp, vp, vp, P(f32), f32, vp, vp, vp, vp, vp, vp, i64, vp, sz],
             "rk_stage": [vp, vp, i32, vp, vp, vp, vp, vp, vp, i64],
             "rk_stage_adj": [vp, vp, i32, vp, vp, vp, vp, vp, vp, i64],
             "fcsd_cfl_dt": [vp, vp, vp, vp, f32, f32, vp, i64, vp, sz],
@@ -152,7 +156,8 @@ EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_l
            "fcsd_ctx_stream", "fcsd_ctx_sync", "fcsd_set_create", "fcsd_set_destroy", "fcsd_set_tune",
            "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj", "fcsd_smear", "fcsd_set_interp", "fcsd_set_walls",
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
-           "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "rk_stage",
+           "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "euler_rhs_adj", "av_apply_adj",
+           "sdnn_infer_adj", "fcsd_stage_adj", "rk_stage",
            "rk_stage_adj", "fcsd_cfl_dt", "fcsd_cfl_dt_noalloc", "fcsd_check", "sdnn_infer", "av_viscosity", "av_viscosity_adj",
            "fcsd_glue", "fcsd_glue_adj", "fcsd_step_adj", "fcsd_stage", "fcsd_stage_per_patch", "fcsd_stage_pass", "fcsd_step", "fcsd_fc_matrix",
            "fcsd_validate_patches", "fcsd_fft_plan", "fcsd_version"]

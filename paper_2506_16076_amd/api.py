@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 from ._lib import (LAYOUT_B8X4, LAYOUT_ROWS, RECORD_PLANES, FcsdError, Mlp, StepArgs, WS_AV, WS_RHS, WS_RHS_ADJ, WS_STEP,
-                   WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR, blocked_layout, layout_index, lib, patch_descs)
+                   WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR, WS_STAGE_ADJ, blocked_layout, layout_index, lib,
+                   patch_descs)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -265,6 +266,23 @@ def fcsd_rhs_adj(s, u, metric, mu, ref, gamma, rhs_bar, u_bar, mu_bar=None):
           _p(mu_bar), s.plane, _p(ws), ws.numel() * 4)
 
 
+def euler_rhs_adj(s, u, metric, ref, gamma, rhs_bar, u_bar):
+    """u_bar += transpose of euler_rhs at u applied to rhs_bar."""
+    _chk(u, numel=4 * s.plane), _chk(rhs_bar, numel=4 * s.plane), _chk(u_bar, numel=4 * s.plane)
+    ws = s.workspace(WS_RHS_ADJ)
+    _call(s, "euler_rhs_adj", _p(u), _p(metric), _f4(ref), float(gamma), _p(rhs_bar), _p(u_bar), s.plane, _p(ws),
+          ws.numel() * 4)
+
+
+def av_apply_adj(s, u, metric, mu, ref, rhs_bar, u_bar, mu_bar=None):
+    """u_bar (and mu_bar) += transpose of av_apply at (u, mu) applied to rhs_bar."""
+    _chk(u, numel=4 * s.plane), _chk(rhs_bar, numel=4 * s.plane), _chk(u_bar, numel=4 * s.plane)
+    _chk(mu, numel=s.plane), _chk(mu_bar, numel=s.plane)
+    ws = s.workspace(WS_RHS_ADJ)
+    _call(s, "av_apply_adj", _p(u), _p(metric), _p(mu), _f4(ref), _p(rhs_bar), _p(u_bar), _p(mu_bar), s.plane,
+          _p(ws), ws.numel() * 4)
+
+
 # ------------------------------------------------------------------ stepping
 
 def rk_stage(s, stage, dt_dev, rhs, u0, ui, acc, uout):
@@ -284,6 +302,16 @@ def fcsd_cfl_dt(s, u, mu, cfl, gamma, dt_dev):
     ws = s.workspace(WS_AV)
     _call(s, "fcsd_cfl_dt", _p(u), _p(mu), float(cfl), float(gamma), _p(dt_dev), s.plane, _p(ws),
           ws.numel() * 4)
+
+
+def sdnn_infer_adj(s, u, gamma, W, logits_bar, feat_bar):
+    """feat_bar [2][plane][16] = transpose of the network at the state's
+    window features applied to logits_bar [2][plane][4] (subgrid points)."""
+    _chk(u, numel=4 * s.plane), _chk(logits_bar, numel=8 * s.plane), _chk(feat_bar, numel=32 * s.plane)
+    ws = s.workspace(WS_AV)
+    m = mlp_struct(W)
+    _call(s, "sdnn_infer_adj", _p(u), float(gamma), ctypes.byref(m), _p(logits_bar), _p(feat_bar), s.plane,
+          _p(ws), ws.numel() * 4)
 
 
 def fcsd_cfl_dt_noalloc(s, u, mu, cfl, gamma, dt_dev):
@@ -382,6 +410,18 @@ def fcsd_stage(s, stage, u0, ui, acc, uout, metric, mu, ref, gamma, dt_dev, per_
     name = "fcsd_stage_per_patch" if per_patch else "fcsd_stage"
     _call(s, name, int(stage), _p(u0), _p(ui), _p(acc), _p(uout), _p(metric), _p(mu), _f4(ref),
           float(gamma), _p(dt_dev), s.plane, _p(ws), ws.numel() * 4)
+
+
+def fcsd_stage_adj(s, stage, ui, metric, mu, ref, gamma, dt_dev, uout_bar, u0_bar, ui_bar, acc_bar=None,
+                   mu_bar=None):
+    """Reverse mode of fcsd_stage at ui (see the header): u0_bar, ui_bar,
+    acc_bar, mu_bar accumulated / updated in place."""
+    for t in (ui, uout_bar, u0_bar, ui_bar):
+        _chk(t, numel=4 * s.plane)
+    _chk(acc_bar, numel=4 * s.plane), _chk(mu, numel=s.plane), _chk(mu_bar, numel=s.plane), _chk(dt_dev, numel=1)
+    ws = s.workspace(WS_STAGE_ADJ)
+    _call(s, "fcsd_stage_adj", int(stage), _p(ui), _p(metric), _p(mu), _f4(ref), float(gamma), _p(dt_dev),
+          _p(uout_bar), _p(u0_bar), _p(ui_bar), _p(acc_bar), _p(mu_bar), s.plane, _p(ws), ws.numel() * 4)
 
 
 def fcsd_stage_pass(s, pass_id, stage, u0, ui, acc, uout, metric, mu, ref, gamma, dt_dev):

@@ -263,6 +263,7 @@ size_t ws_planes(const fcsd_set* s, int op) {
     case FCSD_WS_STEP_ADJ: return kStepAdjPlanes;
     case FCSD_WS_FILTER_ADJ: return 8;
     case FCSD_WS_SMEAR: return 2;
+    case FCSD_WS_STAGE_ADJ: return 24 + 4;   // right-hand-side reverse workspace, rhs_bar
     default: return 0;
   }
 }
@@ -830,7 +831,7 @@ extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
 }
 
 extern "C" fcsd_status fcsd_workspace_size(const fcsd_set* s, int op, size_t* bytes) {
-  if (!s || !bytes || op < 0 || op > FCSD_WS_SMEAR) return FCSD_EINVAL;
+  if (!s || !bytes || op < 0 || op > FCSD_WS_STAGE_ADJ) return FCSD_EINVAL;
   *bytes = ws_bytes_of(s, op);
   return FCSD_OK;
 }
@@ -1829,7 +1830,7 @@ namespace {
 // are then not recomputed.
 fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric, const float* mu,
                          const float ref[4], float gamma, const float* rhs_bar, float* u_bar, float* mu_bar,
-                         void* ws, const float* given1, const float* given2) {
+                         void* ws, const float* given1, const float* given2, int flux = FLUX_FULL) {
   fcsd_status st;
   const long long pl = s->plane;
   float* w = (float*)ws;
@@ -1844,7 +1845,7 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
   a.u = u;
   a.metric = metric;
   a.mu = mu;
-  a.mode = FLUX_FULL;
+  a.mode = flux;   // FLUX_VISC: the viscous term alone (no flux cotangent)
   if (visc) {
     PassArgs b = a;
     if (!given1) {
@@ -1898,6 +1899,65 @@ extern "C" fcsd_status fcsd_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const floa
   if (!u || !metric || !ref || !rhs_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: null argument");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_rhs_adj: workspace too small");
   return rhs_adj_impl(ctx, s, u, metric, mu, ref, gamma, rhs_bar, u_bar, mu_bar, ws, nullptr, nullptr);
+}
+
+extern "C" fcsd_status euler_rhs_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
+                                     const float ref[4], float gamma, const float* rhs_bar, float* u_bar,
+                                     int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !metric || !ref || !rhs_bar || !u_bar || !ws) return fail(ctx, FCSD_EINVAL, "euler_rhs_adj: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS_ADJ)) return fail(ctx, FCSD_EINVAL, "euler_rhs_adj: workspace too small");
+  return rhs_adj_impl(ctx, s, u, metric, nullptr, ref, gamma, rhs_bar, u_bar, nullptr, ws, nullptr, nullptr);
+}
+
+extern "C" fcsd_status av_apply_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric,
+                                    const float* mu, const float ref[4], const float* rhs_bar, float* u_bar,
+                                    float* mu_bar, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !metric || !mu || !ref || !rhs_bar || !u_bar || !ws)
+    return fail(ctx, FCSD_EINVAL, "av_apply_adj: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS_ADJ)) return fail(ctx, FCSD_EINVAL, "av_apply_adj: workspace too small");
+  return rhs_adj_impl(ctx, s, u, metric, mu, ref, 1.4f, rhs_bar, u_bar, mu_bar, ws, nullptr, nullptr, FLUX_VISC);
+}
+
+extern "C" fcsd_status fcsd_stage_adj(fcsd_ctx* ctx, const fcsd_set* s, int stage, const float* ui,
+                                      const float* metric, const float* mu, const float ref[4], float gamma,
+                                      const float* dt_dev, const float* uout_bar, float* u0_bar, float* ui_bar,
+                                      float* acc_bar, float* mu_bar, int64_t plane, void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (stage < 0 || stage > 4 || !ui || !metric || !ref || !dt_dev || !uout_bar || !u0_bar || !ui_bar || !ws ||
+      (stage >= 2 && !acc_bar))
+    return fail(ctx, FCSD_EINVAL, "fcsd_stage_adj: bad arguments");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_STAGE_ADJ)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_adj: workspace too small");
+  const long long n4 = 4 * (long long)s->plane;
+  float* rb = (float*)ws + 24 * s->plane;
+  // register update transposed (rhs_bar written), then the right-hand side's
+  hipLaunchKernelGGL(k_rk_adj, dim3(blocks_for(n4)), dim3(kBlock), 0, ctx->stream, stage, dt_dev, uout_bar, u0_bar,
+                     ui_bar, acc_bar, rb, n4);
+  if ((st = launch_check(ctx, "fcsd_stage_adj rk"))) return st;
+  return rhs_adj_impl(ctx, s, ui, metric, mu, ref, gamma, rb, ui_bar, mu ? mu_bar : nullptr, ws, nullptr, nullptr);
+}
+
+extern "C" fcsd_status sdnn_infer_adj(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float gamma,
+                                      const fcsd_mlp* w, const float* logits_bar, float* feat_bar, int64_t plane,
+                                      void* ws, size_t ws_bytes) {
+  fcsd_status st = check_set(ctx, s, plane);
+  if (st) return st;
+  if (!u || !w || !logits_bar || !feat_bar || !ws || !w->W1 || !w->b1 || !w->W2 || !w->b2 || !w->W3 || !w->b3)
+    return fail(ctx, FCSD_EINVAL, "sdnn_infer_adj: null argument");
+  if (ws_bytes < ws_bytes_of(s, FCSD_WS_AV)) return fail(ctx, FCSD_EINVAL, "sdnn_infer_adj: workspace too small");
+  float* phi = carve_av(s, ws).phi;
+  hipLaunchKernelGGL(k_proxy, dim3(chunk_grid(s->nchunks)), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->nchunks,
+                     s->d_patches, u, (long long)s->plane, gamma, phi, (float*)nullptr);
+  MlpPtr m{w->W1, w->b1, w->W2, w->b2, w->W3, w->b3};
+  // the padding between patches is not a point: its feature cotangents are left as they are
+  hipLaunchKernelGGL(k_sdnn_adj, dim3(chunk_grid(s->nchunks)), dim3(kBlock), sdnn_adj_lds_bytes(), ctx->stream,
+                     s->d_chunks, s->nchunks, s->d_patches, (const float*)phi, m, logits_bar, feat_bar,
+                     (long long)s->plane);
+  return launch_check(ctx, "sdnn_infer_adj");
 }
 
 // ======================================================================== reverse mode of a step

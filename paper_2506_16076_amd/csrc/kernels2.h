@@ -387,8 +387,9 @@ struct MlpPtr {
   const float *W1, *b1, *W2, *b2, *W3, *b3;
 };
 
-// The 16-64-64-4 classifier on MFMA (v_mfma_f32_16x16x4f32, FP32 in, FP32
-// accumulate).  A wavefront evaluates 16 windows at once, as the transposed
+// The 16-64-64-4 classifier on the fp16 matrix cores with FP32 accuracy
+// (operands split into fp16 high and 2^11-scaled low parts, products summed
+// in FP32; see mlp16).  A wavefront evaluates 16 windows at once, as the transposed
 // products H1^T = W1^T X^T, H2^T = W2^T relu(H1^T), O^T = W3^T relu(H2^T)
 // with windows along the columns.  Lane l = 16 g + r holds column r (window
 // r) and, after each product, rows 4 g + v (v = 0..3) of every 16-row tile
@@ -1490,6 +1491,113 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* H
 #pragma unroll
           for (int k = 0; k < 4; ++k) at(ub + k * pl + bo, g) = q.ub[k] + o[k];
         });
+  }
+}
+
+// ---------------------------------------------------------------- network reverse mode
+
+// Reverse mode of the classifier network (Sec. 5.1) at the features of the
+// state: for every point of D~ and each direction, the cotangent of the 16
+// window features given that of the four logits,
+//   feat_bar = W1 (m1 .* W2 (m2 .* W3 logit_bar)),
+// m1, m2 the ReLU masks of the forward pass at the window (row-vector
+// convention y = x W + b, so the transposes act from the left here); zero
+// outside D~.  One thread per (point, direction), FP32; the weights and, per
+// thread, the 64 hidden activations and their cotangents live in LDS
+// (column tid of a [64][kBlock] array: conflict-free), so that no loop
+// keeps 64-entry arrays or the weights in registers.  The features are
+// formed as in the forward kernel (window4): offsets -8..7, clamped,
+// rescaled to [-1, 1], zero for a flat window.  logit_bar / feat_bar:
+// [2][plane][4] / [2][plane][16] at the point's storage index.  Dynamic LDS:
+// sdnn_adj_lds_bytes().
+struct MlpAdjLds {
+  float W1[16 * 64], b1[64], W2[64 * 64], b2[64], W3[64 * 4];
+};
+
+__host__ __device__ constexpr size_t sdnn_adj_lds_bytes() {
+  return sizeof(MlpAdjLds) + 2 * 64 * kBlock * sizeof(float);
+}
+
+__global__ void __launch_bounds__(kBlock) k_sdnn_adj(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
+                                                     const float* phi, MlpPtr w, const float* lbar, float* fbar,
+                                                     long long pl) {
+  MlpAdjLds& L = *reinterpret_cast<MlpAdjLds*>(lds_z);
+  float* H = reinterpret_cast<float*>(&L + 1);   // [64][kBlock] hidden activations of layer 1
+  float* Gb = H + 64 * kBlock;                    // [64][kBlock] their cotangents
+  for (int q = threadIdx.x; q < 16 * 64; q += blockDim.x) L.W1[q] = w.W1[q];
+  for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) L.W2[q] = w.W2[q];
+  for (int q = threadIdx.x; q < 64 * 4; q += blockDim.x) L.W3[q] = w.W3[q];
+  for (int q = threadIdx.x; q < 64; q += blockDim.x) {
+    L.b1[q] = w.b1[q];
+    L.b2[q] = w.b2[q];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {
+    const ChunkDev ck = chunks[cb];
+    const PatchDev P = patches[ck.patch];
+    const int kk = ck.start + t;
+    int i = 0, j = 0;
+    if (kk >= pstore(P) || !pdecode(P, kk, i, j)) continue;
+    const long long gi = P.off + kk;
+    const bool in = in_dtilde(P, i, j);
+#pragma unroll 1
+    for (int dir = 0; dir < 2; ++dir) {
+      float* fo = fbar + 16 * (dir * pl + gi);
+      if (!in) {
+        for (int f = 0; f < 16; ++f) fo[f] = 0.f;
+        continue;
+      }
+      float x[16];
+      {
+#pragma clang fp contract(off)
+        const int pos = dir == 0 ? i : j, n = dir == 0 ? P.n1 : P.n2;
+        float lo = 3.4e38f, hi = -3.4e38f;
+#pragma unroll
+        for (int f = 0; f < 16; ++f) {
+          int k = pos - 8 + f;
+          k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+          x[f] = phi[dir == 0 ? pidx(P, k, j) : pidx(P, i, k)];
+          lo = fminf(lo, x[f]);
+          hi = fmaxf(hi, x[f]);
+        }
+        const float rng = hi - lo;
+        const bool flat = rng <= 1e-6f * fmaxf(1.0f, fabsf(hi));
+        const float sc = flat ? 0.f : 2.0f / rng;
+#pragma unroll
+        for (int f = 0; f < 16; ++f) x[f] = flat ? 0.f : (x[f] - lo) * sc - 1.0f;
+      }
+#pragma unroll 1
+      for (int u = 0; u < 64; ++u) {
+        float z = L.b1[u];
+#pragma unroll
+        for (int f = 0; f < 16; ++f) z = fmaf(x[f], L.W1[f * 64 + u], z);
+        H[u * kBlock + t] = fmaxf(z, 0.f);
+        Gb[u * kBlock + t] = 0.f;
+      }
+      const float* lb = lbar + 4 * (dir * pl + gi);
+      const float l0 = lb[0], l1 = lb[1], l2 = lb[2], l3 = lb[3];
+#pragma unroll 1
+      for (int k = 0; k < 64; ++k) {
+        float z = L.b2[k];
+#pragma unroll 8
+        for (int u = 0; u < 64; ++u) z = fmaf(H[u * kBlock + t], L.W2[u * 64 + k], z);
+        if (z > 0.f) {
+          const float* w3 = L.W3 + 4 * k;
+          const float g2 = w3[0] * l0 + w3[1] * l1 + w3[2] * l2 + w3[3] * l3;
+#pragma unroll 8
+          for (int u = 0; u < 64; ++u) Gb[u * kBlock + t] = fmaf(L.W2[u * 64 + k], g2, Gb[u * kBlock + t]);
+        }
+      }
+#pragma unroll 1
+      for (int f = 0; f < 16; ++f) {
+        float acc = 0.f;
+#pragma unroll 8
+        for (int u = 0; u < 64; ++u)
+          acc = H[u * kBlock + t] > 0.f ? fmaf(L.W1[f * 64 + u], Gb[u * kBlock + t], acc) : acc;
+        fo[f] = acc;
+      }
+    }
   }
 }
 

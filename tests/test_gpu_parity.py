@@ -927,6 +927,135 @@ def test_rhs_reverse_mode(env, case):
     s.close()
 
 
+@pytest.mark.parametrize("case", ["square64", "shells"])
+def test_euler_rhs_and_av_apply_reverse_modes(env, case):
+    """euler_rhs_adj (inviscid right-hand side transposed) and av_apply_adj
+    (the viscous term alone, with its viscosity cotangent) against the
+    oracle's vector-Jacobian products, accumulating into nonzero buffers."""
+    api, ctx, torch = env
+    ps, u, mu, ref = rhs_case(case)
+    s = api.PatchSet.from_layout(ctx, ps)
+    rb = smooth_fields(ps, 4, 31)
+    base = smooth_fields(ps, 4, 32)
+    ub = dev(torch, base)
+    api.euler_rhs_adj(s, dev(torch, u), dev(torch, ps.metric), ref, G, dev(torch, rb), ub)
+    we, _ = euler.full_rhs_vjp(u.astype(np.float64), ps.metric, None, ps, G, rb.astype(np.float64))
+    got = host(ub).reshape(4, -1) - base
+    e1, m1 = relerr_phys(ps, got, we), maxrel_phys(ps, got, we)
+    ub = dev(torch, base)
+    mb0 = smooth_fields(ps, 1, 33)[0]
+    mb = dev(torch, mb0)
+    api.av_apply_adj(s, dev(torch, u), dev(torch, ps.metric), dev(torch, mu), ref, dev(torch, rb), ub, mb)
+    wa, wm = euler.av_term_vjp(u.astype(np.float64), ps.metric, mu.astype(np.float64), ps, rb.astype(np.float64))
+    ga = host(ub).reshape(4, -1) - base
+    gm = host(mb) - mb0
+    e2, m2 = relerr(ps, ga, wa), maxrel_phys(ps, ga, wa)
+    e3, m3 = relerr(ps, gm, wm), maxrel_phys(ps, gm, wm)
+    say("euler_rhs_adj", case, e1, "max", m1, "| av_apply_adj", e2, "max", m2, "mu_bar", e3, m3)
+    assert np.all(e1 < ADJ_TOL) and np.all(m1 < PT * ADJ_TOL)
+    assert np.all(e2 < ADJ_TOL) and np.all(m2 < PT * ADJ_TOL)
+    assert e3[0] < ADJ_TOL and m3[0] < PT * ADJ_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("stage", [1, 4])
+def test_stage_reverse_mode(env, stage):
+    """fcsd_stage_adj against the oracle: stage 1 maps (u0, u1) to
+    u2 = a10 u0 + a11 u1 + b11 dt L(u1), stage 4 maps (acc, u4) to
+    acc + a44 u4 + b44 dt L(u4) (Shu-Osher coefficients of the oracle's
+    scheme; acc holds the earlier terms of the last stage), so the
+    cotangents are u0_bar += a10 y, acc_bar += y, ui_bar += a y +
+    L'(ui)^T (b dt y), mu_bar += the viscosity part."""
+    api, ctx, torch = env
+    ps, u, mu, ref = rhs_case("uneven")
+    s = api.PatchSet.from_layout(ctx, ps)
+    ui = (u * (1 + 1e-3 * smooth_fields(ps, 4, 34))).astype(np.float32)     # a smooth stage input
+    y = smooth_fields(ps, 4, 35)
+    dt = 2e-3
+    dtd = dev(torch, np.array([dt], np.float32))
+    b0 = smooth_fields(ps, 4, 36)
+    u0b, uib, accb = dev(torch, b0), dev(torch, b0 * 0.5), dev(torch, b0 * 0.25)
+    mb = torch.zeros(ps.plane, device="cuda:0")
+    api.fcsd_stage_adj(s, stage, dev(torch, ui), dev(torch, ps.metric), dev(torch, mu), ref, G, dtd, dev(torch, y),
+                       u0b, uib, accb, mb)
+    a, b = rk.ALPHA[stage][stage], rk.BETA[stage][stage]
+    re, rm = euler.full_rhs_vjp(ui.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G,
+                                b * float(np.float32(dt)) * y.astype(np.float64))
+    want_ui = 0.5 * b0 + a * y + re
+    err_ui = relerr_phys(ps, host(uib).reshape(4, -1), want_ui)
+    mx_ui = maxrel_phys(ps, host(uib).reshape(4, -1), want_ui)
+    err_mu = relerr(ps, host(mb), rm)
+    if stage == 1:
+        want_0 = b0 + rk.ALPHA[1][0] * y
+        other = relerr_phys(ps, host(u0b).reshape(4, -1), want_0)
+        assert np.array_equal(host(accb), (b0 * 0.25).reshape(-1))
+    else:
+        want_acc = 0.25 * b0 + y
+        other = relerr_phys(ps, host(accb).reshape(4, -1), want_acc)
+        assert np.array_equal(host(u0b), b0.reshape(-1))
+    say("stage", stage, "reverse: ui_bar", err_ui, "max", mx_ui, "mu_bar", err_mu, "u0/acc", other)
+    assert np.all(err_ui < ADJ_TOL) and np.all(mx_ui < PT * ADJ_TOL) and err_mu[0] < ADJ_TOL
+    assert np.all(other < 1e-6)
+    s.close()
+
+
+def test_network_reverse_mode(env):
+    """sdnn_infer_adj (the network's transpose at the state's window
+    features) against the oracle's mlp_vjp on the 64 x 64 square, whose
+    features are well conditioned.  Compared at the windows whose ReLU masks
+    are the same in FP32 and FP64 for certain (every unit's input beyond
+    twice its FP32 error bound); the count of the others is printed."""
+    api, ctx, torch = env
+    cfg = synth.config(0)
+    ps = cfg.ps
+    W = synth.mlp_weights(5)
+    s = api.PatchSet.from_layout(ctx, ps)
+    Wd = {k: dev(torch, v) for k, v in W.items()}
+    rng = np.random.default_rng(37)
+    lb = rng.standard_normal((2, ps.plane, 4)).astype(np.float32)
+    fb = torch.full((32 * ps.plane,), 7.0, device="cuda:0")
+    api.sdnn_infer_adj(s, dev(torch, cfg.u0), G, Wd, dev(torch, lb), fb)
+    got = host(fb).reshape(2, ps.plane, 16)
+    A = {k: np.abs(np.asarray(v, np.float64)) for k, v in W.items()}
+    Wf = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    e = np.asarray(cfg.u0, np.float64)
+    comp = excl = 0
+    errs, wants, scale = [], [], 0.0
+    for p in range(ps.npatch):
+        ep = ps.view(e, p)
+        phi = av.proxy(ep, G)
+        eps = fp32_value_bound(ep) * np.abs(phi)
+        o, a_, b_ = int(ps.off[p]), int(ps.n1[p]), int(ps.n2[p])
+        for d in range(2):
+            if d == 0:
+                x = av.features_lines(phi)
+                dx = _window_dx_bound(phi, eps)
+            else:
+                x = np.swapaxes(av.features_lines(phi.T), 0, 1)
+                dx = np.swapaxes(_window_dx_bound(phi.T, eps.T), 0, 1)
+            want = av.mlp_vjp(x, W, lb[d, o:o + a_ * b_].reshape(b_, a_, 4).astype(np.float64))
+            z1 = x @ Wf["W1"] + Wf["b1"]
+            d1 = dx[..., None] * A["W1"].sum(0) + 32 * U32 * (np.abs(x) @ A["W1"] + A["b1"])
+            h1 = np.maximum(z1, 0)
+            z2 = h1 @ Wf["W2"] + Wf["b2"]
+            d2 = np.where(z1 > -d1, d1, 0) @ A["W2"] + 128 * U32 * (h1 @ A["W2"] + A["b2"])
+            sure = np.all(np.abs(z1) > 2 * d1, -1) & np.all(np.abs(z2) > 2 * d2, -1)
+            sure &= np.isfinite(dx)
+            g = got[d, o:o + a_ * b_].reshape(b_, a_, 16)
+            errs.append((g - want)[sure])
+            wants.append(want[sure])
+            scale = max(scale, np.abs(want).max())
+            comp += int(sure.sum())
+            excl += int((~sure).sum())
+    err = np.concatenate(errs)
+    rel = np.linalg.norm(err) / np.linalg.norm(np.concatenate(wants))
+    say("network reverse mode: compared", comp, "uncertain masks", excl, "rel L2", rel,
+        "max", np.abs(err).max() / scale)
+    assert comp > 0.9 * (comp + excl)
+    assert rel < 1e-5 and np.abs(err).max() <= 1e-4 * scale
+    s.close()
+
+
 @pytest.mark.parametrize("case", ["annulus", "overlap"])
 def test_viscosity_reverse_mode(env, case):
     api, ctx, torch = env

@@ -404,3 +404,51 @@ def test_glue_copies_same_physical_point():
     d = ps.dirichlet.astype(bool)
     assert np.allclose(e[0, ~d], ref[0, ~d], atol=1e-12)
     assert np.allclose(e[:, d], synth.freestream(3.0)[:, None])
+
+
+def test_mlp_vjp_matches_central_differences_and_loops():
+    """The network's reverse mode (Sec. 5.1 network, transposed): <x_bar, dx>
+    equals the central difference of <logits, l_bar> along dx (FP64, away
+    from ReLU kinks), and a naive loop over units gives the same x_bar."""
+    W = synth.mlp_weights(4)
+    rng = np.random.default_rng(12)
+    x = rng.uniform(-1, 1, (7, 16))
+    lb = rng.standard_normal((7, 4))
+    xb = av.mlp_vjp(x, W, lb)
+    for r in range(7):
+        dx = rng.standard_normal(16)
+        h = 1e-6
+        fd = np.sum((av.mlp_logits(x[r] + h * dx, W) - av.mlp_logits(x[r] - h * dx, W)) * lb[r]) / (2 * h)
+        assert abs(fd - xb[r] @ dx) <= 1e-7 * max(1.0, abs(fd))
+    Wd = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    for r in range(2):
+        z1 = [sum(x[r, i] * Wd["W1"][i, j] for i in range(16)) + Wd["b1"][j] for j in range(64)]
+        h1 = [max(0.0, v) for v in z1]
+        z2 = [sum(h1[i] * Wd["W2"][i, k] for i in range(64)) + Wd["b2"][k] for k in range(64)]
+        g2 = [sum(Wd["W3"][k, l] * lb[r, l] for l in range(4)) if z2[k] > 0 else 0.0 for k in range(64)]
+        g1 = [sum(Wd["W2"][j, k] * g2[k] for k in range(64)) if z1[j] > 0 else 0.0 for j in range(64)]
+        want = [sum(Wd["W1"][i, j] * g1[j] for j in range(64)) for i in range(16)]
+        assert np.allclose(xb[r], want, rtol=1e-12, atol=1e-12)
+
+
+def test_viscous_term_vjp_matches_central_differences():
+    """av_term_vjp: e_bar and mu_bar against central differences of the
+    viscous term div_x (mu grad_x e) on the 3 x 2 annulus (linear in each of
+    e and mu, so the difference is exact up to rounding)."""
+    ps = synth.annulus(3, 2, 40, 36)
+    rng = np.random.default_rng(13)
+    e = rng.standard_normal((4, ps.plane))
+    mu = 1e-3 * (1 + rng.random(ps.plane))
+    rb = rng.standard_normal((4, ps.plane))
+    eb, mub = euler.av_term_vjp(e, ps.metric, mu, ps, rb)
+    de = rng.standard_normal((4, ps.plane))
+    dm = 1e-3 * rng.standard_normal(ps.plane)
+    keep = np.zeros(ps.plane, bool)
+    keep[euler.points(ps)] = True
+    de[:, ~keep] = 0
+    dm[~keep] = 0
+    h = 1e-3
+    fe = np.sum((euler.av_term(e + h * de, ps.metric, mu, ps) - euler.av_term(e - h * de, ps.metric, mu, ps)) * rb) / (2 * h)
+    fm = np.sum((euler.av_term(e, ps.metric, mu + h * dm, ps) - euler.av_term(e, ps.metric, mu - h * dm, ps)) * rb) / (2 * h)
+    assert abs(fe - np.sum(eb * de)) <= 1e-9 * abs(fe)
+    assert abs(fm - np.sum(mub * dm)) <= 1e-9 * abs(fm)
