@@ -156,11 +156,13 @@ def wavenumbers(L: int) -> np.ndarray:
 def periodic_derivative(ext: np.ndarray, period: float) -> np.ndarray:
     """Derivative of the trigonometric interpolant of a periodic sample
     vector: FFT, multiply by 2 pi i k / period, inverse FFT, real part
-    (eq. fc_der)."""
+    (eq. fc_der).  The library FFT transforms the batch of lines on every
+    host thread."""
+    import scipy.fft
     L = ext.shape[-1]
-    X = np.fft.fft(ext, axis=-1)
+    X = scipy.fft.fft(ext, axis=-1, workers=-1)
     X = X * (2j * np.pi * wavenumbers(L) / period)
-    return np.real(np.fft.ifft(X, axis=-1))
+    return np.real(scipy.fft.ifft(X, axis=-1, workers=-1))
 
 
 def diff_lines(F: np.ndarray, d: int, C: int) -> np.ndarray:
