@@ -89,45 +89,128 @@ def pass_bytes(stage):
     return {"A": 32, "B1": 84, "B2": 56, "C": 32 + 16 + 8 + rk_read + rk_write}
 
 
-def cpu_baseline(cfg, budget_s=20.0):
-    """The oracle (FP64 numpy) on a bounded sample: the first patches of the
-    workload until ~budget_s of work, one full step (network, viscosity, dt,
-    five stages).  Single thread."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_patch_step(args):
+    """One full oracle step (network, viscosity, dt, five stages) of one
+    patch of the workload, in a single-threaded pool worker; returns
+    (points, seconds)."""
+    p, n1, n2, d, mach, pert, ref, mlp = args
+    import synth
+    from oracle import fcgram, solver
+    fcgram.FFT_WORKERS = 1
+    sub = synth._polar_patches([(0.3 * p, ((2 * np.pi / 16) * 255 / 237) / (n1 - 1), 0.5, 1.5 / (n2 - 1))],
+                               [n1], [n2], d, 27)
+    e = synth.mach_state(sub, mach, pert)
+    c = synth.Config("sample", sub, synth._f32(e, sub), ref, mach=mach, pert=pert, mlp=mlp)
+    run = solver.Run(c)
+    t0 = time.perf_counter()
+    run.step()
+    return n1 * n2, time.perf_counter() - t0
+
+
+_THREAD_VARS = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+
+
+def _single_thread_env():
+    """Pool worker initializer: one BLAS thread (the environment the worker
+    was spawned with already says so; threadpoolctl covers a BLAS that was
+    loaded before)."""
     try:
         from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
     except ImportError:  # pragma: no cover
-        threadpool_limits = None
-    import synth
-    from oracle import solver
+        pass
+
+
+def cpu_baseline(cfg, budget_s=20.0, workers=None):
+    """The oracle (FP64 numpy) over the host's cores: a process pool of
+    single-threaded workers, one patch of the workload each (the bench
+    workload's patches are independent), one full step per patch; patches
+    are handed out in the workload's order as workers free up until ~budget_s
+    of wall time has passed.  Throughput = the points stepped x 5 / the wall
+    time until the last of them finished."""
+    import multiprocessing as mp
 
     ps = cfg.ps
-    # sample: a subset of patches (timed per patch to stay in budget)
-    order = list(range(ps.npatch))
-    pts, secs, used = 0, 0.0, 0
-    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
+    workers = workers or min(os.cpu_count() or 1, 16)
+    ctx = mp.get_context("spawn")
+    pts, wall, used = 0, 0.0, 0
+    saved = {k: os.environ.get(k) for k in _THREAD_VARS}
+    for k in _THREAD_VARS:
+        os.environ[k] = "1"            # inherited by the spawned workers
     try:
-        for p in order:
-            # rebuild a one-patch layout with patch p's geometry
-            n1, n2 = int(ps.n1[p]), int(ps.n2[p])
-            sub = synth._polar_patches([(0.3 * p, ((2 * np.pi / 16) * 255 / 237) / (n1 - 1), 0.5, 1.5 / (n2 - 1))],
-                                       [n1], [n2], ps.d, 27)
-            e = synth.mach_state(sub, cfg.mach, cfg.pert)
-            c = synth.Config("sample", sub, synth._f32(e, sub), cfg.ref, mach=cfg.mach, pert=cfg.pert,
-                             mlp=cfg.mlp)
-            run = solver.Run(c)
-            t0 = time.perf_counter()
-            run.step()
-            secs += time.perf_counter() - t0
-            pts += n1 * n2
-            used += 1
-            if secs > budget_s:
-                break
+        pool = ctx.Pool(workers, initializer=_single_thread_env)
     finally:
-        if ctxm is not None:
-            ctxm.__exit__(None, None, None)
-    return {"value": pts * 5 / secs, "unit": "grid-pt RK-stages/s", "cores": 1, "kind": "oracle",
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    with pool:
+        # warm the workers (imports) outside the timed region
+        pool.map(_single_thread_env_probe, range(workers))
+        todo = [(q, int(ps.n1[q]), int(ps.n2[q]), ps.d, cfg.mach, cfg.pert, cfg.ref, cfg.mlp)
+                for q in range(ps.npatch)]
+        t0 = time.perf_counter()
+        flight = [pool.apply_async(_oracle_patch_step, (todo[q],)) for q in range(min(workers, len(todo)))]
+        nxt = len(flight)
+        while flight:
+            done = [f for f in flight if f.ready()]
+            if not done:
+                time.sleep(0.005)
+                continue
+            for f in done:
+                flight.remove(f)
+                n, _ = f.get()
+                pts += n
+                used += 1
+                if nxt < len(todo) and time.perf_counter() - t0 < budget_s:
+                    flight.append(pool.apply_async(_oracle_patch_step, (todo[nxt],)))
+                    nxt += 1
+        wall = time.perf_counter() - t0
+    return {"value": pts * 5 / wall, "unit": "grid-pt RK-stages/s", "cores": workers, "kind": "oracle",
+            "cpu": _cpu_model(),
             "sample": f"{used} of {ps.npatch} patches ({pts} points), one full step each, FP64 numpy, "
-                      f"{secs:.1f} s"}
+                      f"pool of {workers} single-threaded processes, {wall:.1f} s wall"}
+
+
+def _single_thread_env_probe(_):
+    import synth  # noqa: F401
+    from oracle import solver  # noqa: F401
+    return 0
+
+
+def oracle_configs():
+    """The FP64 oracle (one process, library FFT and BLAS threads on the
+    host) on the 64 x 64 square for its 10 steps and on the 64-patch annulus
+    of 512 x 512 patches for one step (network, viscosity, glue and inflow
+    at every stage), in grid-pt RK-stages/s."""
+    import synth
+    from oracle import solver
+    out = {"cpu": _cpu_model(), "threads": os.cpu_count()}
+    for name, idx, steps in (("square_64x64_10_steps", 0, 10), ("annulus_64x512x512_1_step", 4, 1)):
+        cfg = synth.config(idx)
+        run = solver.Run(cfg)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            run.step(progress=lambda st, k=k: print(f"  {name}: step {k} stage {st} done, "
+                                                     f"{time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                                                     flush=True))
+        secs = time.perf_counter() - t0
+        out[name] = {"points": cfg.ps.npoints, "steps": steps, "seconds": secs,
+                     "value": cfg.ps.npoints * 5 * steps / secs, "finite": bool(np.isfinite(run.u).all())}
+        print(name, out[name], file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -147,7 +230,13 @@ def main():
     ap.add_argument("--schedule", default="auto",
                     help="auto (autotuner) or B_q1,B_q2,B_q2wide,T_q1,T_q2,T_q2wide,lpt|xcd (LDS budgets in "
                          "bytes, workgroup sizes)")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="only time the FP64 oracle on the host: the 64 x 64 square for its 10 steps and the "
+                         "64-patch annulus (16.8 M points) for one step, one process; prints one JSON line")
     args = ap.parse_args()
+    if args.oracle_configs:
+        print(json.dumps(oracle_configs()), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding by whole patches is a design note, not built)", file=sys.stderr)
@@ -393,12 +482,13 @@ def main():
         torch.cuda.reset_peak_memory_stats()
         base4 = torch.cuda.memory_allocated()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        C4_STEPS = 100          # the configuration's forward run
         e0.record(ctx.stream)
-        for _ in range(args.steps):
+        for _ in range(C4_STEPS):
             st4.step(use_graph=True)
         e1.record(ctx.stream)
         torch.cuda.synchronize()
-        ms4 = e0.elapsed_time(e1) / args.steps
+        ms4 = e0.elapsed_time(e1) / C4_STEPS
         fwd_peak = torch.cuda.max_memory_allocated()
         K4, every4 = 20, 5
         ustart = u4.clone()
@@ -421,7 +511,7 @@ def main():
         shells = {"workload": "annulus of 16 sectors x 4 shells of 512 x 512, Mach 5 +-1% density, fringe glue "
                               "and Dirichlet inflow every stage, network every step",
                   "points": int(ps4.npoints), "value": ps4.npoints * 5 / (ms4 / 1e3), "unit": "grid-pt RK-stages/s",
-                  "ms_per_step": ms4,
+                  "ms_per_step": ms4, "steps": C4_STEPS,
                   "adjoint": {"value": ps4.npoints * 5 * K4 / (ms4a / 1e3), "steps": K4, "checkpoint_every": every4,
                               "ms_per_step": ms4a / K4, "finite": bool(torch.isfinite(v0.grad).all().item())},
                   "footprint_GB": {"note": "torch-allocated device memory of this workload (state, metric, "

@@ -487,8 +487,11 @@ typedef struct {
 
 /* One full time step (Algorithm 1): glue, network classes and viscosity
  * (when w != NULL), spectral filter and glue (when a->filter), step size,
- * five fused stages with glue on every stage input.  use_graph = 1 captures the step once into a hipGraph and replays
- * it on later calls with identical arguments.  With a->record the stage
+ * five fused stages with glue on every stage input.  use_graph = 1 captures
+ * the step once into a hipGraph and replays it on later calls with identical
+ * arguments; the set keeps the graphs of its 8 most recent argument sets
+ * (capturing a ninth synchronises the stream and drops the oldest), and a
+ * capture whose body fails is discarded.  With a->record the stage
  * inputs, mu, the maximisers (argmax required then, with classes) and the
  * pre-filter state are written to the record as well; the step's result is
  * the same. */

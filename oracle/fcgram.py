@@ -42,6 +42,7 @@ import numpy as np
 FC_K = 18       # trigonometric modes in the blend-to-zero fit
 FC_NOS = 20     # samples per grid interval in the fit
 FC_DPS = 40     # working decimal digits of the fit
+FFT_WORKERS = -1  # host threads of the library FFT (-1: all; a process pool sets 1 per worker)
 
 _TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                       "tests", "golden", "fc_tables.npz")
@@ -160,9 +161,9 @@ def periodic_derivative(ext: np.ndarray, period: float) -> np.ndarray:
     host thread."""
     import scipy.fft
     L = ext.shape[-1]
-    X = scipy.fft.fft(ext, axis=-1, workers=-1)
+    X = scipy.fft.fft(ext, axis=-1, workers=FFT_WORKERS)
     X = X * (2j * np.pi * wavenumbers(L) / period)
-    return np.real(scipy.fft.ifft(X, axis=-1, workers=-1))
+    return np.real(scipy.fft.ifft(X, axis=-1, workers=FFT_WORKERS))
 
 
 def diff_lines(F: np.ndarray, d: int, C: int) -> np.ndarray:

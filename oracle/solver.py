@@ -95,10 +95,11 @@ class Run:
             return mu, None, None
         return av.viscosity(e, ps, self.cfg.mlp, self.gamma)
 
-    def step(self, dt=None, tau=None, arg=None, record=False, filt=None):
+    def step(self, dt=None, tau=None, arg=None, record=False, filt=None, progress=None):
         """One step; dt, tau, arg replay recorded decisions.  record keeps
         the glued stage inputs for the discrete adjoint.  filt = (alpha, p)
-        applies the spectral filter after the viscosity."""
+        applies the spectral filter after the viscosity.  progress(stage),
+        if given, is called as each stage's right-hand side is done."""
         ps, g = self.ps, self.gamma
         e = self.u
         glue(e, ps, self.mach, g)
@@ -113,7 +114,11 @@ class Run:
             glue(e, ps, self.mach, g)
         if dt is None:
             dt = rk.cfl_dt(e, mu, ps, self.cfg.cfl, g)
-        L = lambda u, s: euler.full_rhs(u, ps.metric, mu, ps, g)
+        def L(u, s):
+            r = euler.full_rhs(u, ps.metric, mu, ps, g)
+            if progress is not None:
+                progress(s)
+            return r
         new, stages, rhs = rk.ssprk_step(e, dt, L, glue=lambda u, s: glue(u, ps, self.mach, g))
         entry = dict(dt=dt, tau=tau_used, arg=arg, mu=mu, filt=filt, pre=pre)
         if record:

@@ -46,8 +46,8 @@ struct PlanDev {
   int aq;        // offset of A_r Q^T (double) for this C, C*d entries
   int dq;        // offset of the differenced rows (double), (C+1)*2d entries
   int kf;        // offset of the spectral filter factors (float2) for this L
-  int gq;        // offset of the derivative's fold matrix (double), N*2d entries, for this (N, C)
-  int gf;        // offset of the filter's fold matrix (double), N*2d entries (filter configured)
+  int gq;        // offset of the derivative's fold matrix (float), N*2d entries, for this (N, C)
+  int gf;        // offset of the filter's fold matrix (float), N*2d entries (filter configured)
   int nlines;    // lines along this direction
   int n1, n2;    // patch shape
   int patch;     // patch index
@@ -452,39 +452,52 @@ __device__ __forceinline__ void fold_tail(const LineCtx& X, const PlanDev& P, co
 
 // Fold of a transposed operator's tail onto the end samples, formed from the
 // cotangent itself (positions 0..N-1 of every line, before the transform
-// runs in place): side[e][c] = sum_n G[n][e] y_c[n], e < 2d, in FP64, with G
-// the host's fold matrix of the plan (2d entries per n: e < d the right end
-// sample N-d+e, e >= d the left one e-d).  The fold entries are the
-// continuation's (up to ~1e4) times the circulant's, so an FP32 tail folded
-// after the transform would carry amplified rounding onto the end samples.
-// S lanes (a power of two, S * nl <= blockDim) share a line, each summing
-// every S-th sample, and reduce with lane shuffles inside their wave.  No
-// barrier: reads positions < N, writes side.  DD >= d bounds the unrolled
-// accumulators.
+// runs in place): side[e][c] = sum_n G[n][e] y_c[n], e < 2d, with G the
+// host's fold matrix of the plan (2d entries per n: e < d the right end
+// sample N-d+e, e >= d the left one e-d; FP32, formed in long double).  The
+// fold's entries are the continuation's (up to ~1e4) times the circulant's,
+// so an FP32 tail folded after the transform would carry amplified rounding
+// onto the end samples; this direct product carries only its own rounding
+// (~1e-7 of the line's largest cotangent).  S lanes (a power of two,
+// S * nl <= blockDim) share a line, each summing every S-th sample with the
+// loads of eight samples (four for d > 5) in flight together, and reduce with lane shuffles
+// inside their wave.  No barrier: reads positions < N, writes side.  DD >= d
+// bounds the unrolled accumulators.
 template <int DD>
-__device__ __forceinline__ void fold_pre_t(const LineCtx& X, int N, const double* __restrict__ G, int d) {
+__device__ __forceinline__ void fold_pre_t(const LineCtx& X, int N, const float* __restrict__ G, int d) {
+  constexpr int U = DD <= 5 ? 8 : 4;  // samples whose loads are in flight together
   int S = 64;
   while (S * X.nl > (int)blockDim.x) S >>= 1;
   const int c = threadIdx.x / S, s = threadIdx.x - c * S;
   const bool on = c < X.nl;
   const int cc = on ? c : 0;
   const float2* __restrict__ z = X.z;
-  const int ld = X.ld;
+  const int ld = X.ld, w = 2 * d;
   for (int h = 0; h < 2; ++h) {
-    double ax[DD], ay[DD];
+    float ax[DD], ay[DD];
 #pragma unroll
-    for (int e = 0; e < DD; ++e) ax[e] = ay[e] = 0.0;
+    for (int e = 0; e < DD; ++e) ax[e] = ay[e] = 0.f;
     if (on) {
-      for (int n = s; n < N; n += S) {
-        const float2 y = z[n * ld + cc];
-        const double yx = (double)y.x, yy = (double)y.y;
-        const double* g = G + (size_t)n * 2 * d + h * d;
+      for (int n0 = s; n0 < N; n0 += U * S) {
+        float2 y[U];
+        float g[U][DD];
 #pragma unroll
-        for (int e = 0; e < DD; ++e)
-          if (e < d) {
-            const double w = g[e];
-            ax[e] = fma(w, yx, ax[e]);
-            ay[e] = fma(w, yy, ay[e]);
+        for (int u = 0; u < U; ++u) {
+          const int n = n0 + u * S;
+          const bool ok = n < N;
+          const int nn = ok ? n : s;
+          y[u] = z[nn * ld + cc];
+          if (!ok) y[u] = make_float2(0.f, 0.f);
+          const float* gr = G + (size_t)nn * w + h * d;
+#pragma unroll
+          for (int e = 0; e < DD; ++e) g[u][e] = e < d ? gr[e] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int e = 0; e < DD; ++e) {
+            ax[e] = fmaf(g[u][e], y[u].x, ax[e]);
+            ay[e] = fmaf(g[u][e], y[u].y, ay[e]);
           }
       }
     }
@@ -498,12 +511,12 @@ __device__ __forceinline__ void fold_pre_t(const LineCtx& X, int N, const double
     if (on && s == 0) {
 #pragma unroll
       for (int e = 0; e < DD; ++e)
-        if (e < d) X.side[(h * d + e) * ld + c] = make_float2((float)ax[e], (float)ay[e]);
+        if (e < d) X.side[(h * d + e) * ld + c] = make_float2(ax[e], ay[e]);
     }
   }
 }
 
-__device__ __forceinline__ void fold_pre(const LineCtx& X, int N, const double* __restrict__ G, int d) {
+__device__ __forceinline__ void fold_pre(const LineCtx& X, int N, const float* __restrict__ G, int d) {
   if (d <= 2)
     fold_pre_t<2>(X, N, G, d);
   else if (d <= 5)
@@ -724,7 +737,7 @@ __device__ __forceinline__ void fft_apply(const LineCtx& X, const PlanDev* __res
 // conjugate multipliers, then the fold added to the end samples.
 template <bool ADJ>
 __device__ __forceinline__ void line_derivative(const LineCtx& X, const PlanDev* __restrict__ Pg, const PlanDev& P,
-                                const double* __restrict__ gqp, const double* __restrict__ dqp, int d) {
+                                const float* __restrict__ gqp, const double* __restrict__ dqp, int d) {
   if (!ADJ) {
     difference_ext(X, P, dqp + P.dq, d);
   } else {

@@ -37,6 +37,7 @@ struct GraphEntry {
   std::vector<unsigned char> key;
   hipGraphExec_t exec = nullptr;
 };
+constexpr size_t kMaxGraphs = 8;   // captured steps kept per patch set (distinct argument sets)
 
 }  // namespace
 
@@ -135,8 +136,8 @@ struct fcsd_set {
   int ks_p = -1;
   double* d_aq = nullptr;
   double* d_dq = nullptr;
-  double* d_gq = nullptr;                 // fold matrices of the transposed derivatives, per (N, C)
-  double* d_gf = nullptr;                 // fold matrices of the transposed filter (fcsd_set_filter)
+  float* d_gq = nullptr;                  // fold matrices of the transposed derivatives, per (N, C)
+  float* d_gf = nullptr;                  // fold matrices of the transposed filter (fcsd_set_filter)
   PatchDev* d_patches = nullptr;
   ChunkDev* d_chunks = nullptr;
   int nchunks = 0;
@@ -547,7 +548,8 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   // pools
   std::vector<float2> tw;
   std::vector<float2> km;
-  std::vector<double> aq, dq, gq;
+  std::vector<double> aq, dq;
+  std::vector<float> gq;
   std::map<int, int> tw_of_L, aq_of_C, dq_of_C;
   std::map<std::pair<int, int>, int> gq_of;
   std::map<std::tuple<int, int, int>, int> km_of;
@@ -605,7 +607,7 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
           std::vector<double> g((size_t)P.N * 2 * d);
           if (fcsd_host_fold_matrix(P.N, P.C, d, aq.data() + P.aq, 0, 0.0, 0, g.data()) != 0)
             return fail(ctx, FCSD_EUNSUPPORTED, "fold matrix of the transposed derivative failed");
-          gq.insert(gq.end(), g.begin(), g.end());
+          for (double v : g) gq.push_back((float)v);
         }
         P.gq = gq_of[gkey];
       }
@@ -682,7 +684,8 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
     return r;
   if (aq.empty()) {  // keep a valid pointer for kernels
     std::vector<double> one(1, 0.0);
-    if ((r = upload(ctx, &s->d_aq, one)) || (r = upload(ctx, &s->d_dq, one)) || (r = upload(ctx, &s->d_gq, one)))
+    std::vector<float> onef(1, 0.f);
+    if ((r = upload(ctx, &s->d_aq, one)) || (r = upload(ctx, &s->d_dq, one)) || (r = upload(ctx, &s->d_gq, onef)))
       return r;
   }
   for (int dir = 0; dir < 2; ++dir) {
@@ -782,7 +785,7 @@ extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
   s->graphs.clear();
   std::vector<float2> kf;
   std::map<int, int> kf_of_L;
-  std::vector<double> gf;
+  std::vector<float> gf;
   std::map<std::pair<int, int>, int> gf_of;
   std::map<int, std::vector<double>> aq_of_C;
   for (int dir = 0; dir < 2; ++dir)
@@ -807,11 +810,11 @@ extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
         std::vector<double> g((size_t)P.N * 2 * s->d);
         if (fcsd_host_fold_matrix(P.N, P.C, s->d, aq_of_C[P.C].data(), 1, alpha, p, g.data()) != 0)
           return fail(ctx, FCSD_EUNSUPPORTED, "fold matrix of the transposed filter failed");
-        gf.insert(gf.end(), g.begin(), g.end());
+        for (double v : g) gf.push_back((float)v);
       }
       P.gf = gf_of[key];
     }
-  if (gf.empty()) gf.push_back(0.0);
+  if (gf.empty()) gf.push_back(0.f);
   (void)hipFree(s->d_kf);
   s->d_kf = nullptr;
   (void)hipFree(s->d_gf);
@@ -1465,17 +1468,28 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
       HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
       return FCSD_OK;
     }
-  hipGraph_t graph;
+  hipGraph_t graph = nullptr;
   HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
   st = step_body(ctx, s, a, ws);
   hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
-  if (st) return st;
-  if (e != hipSuccess) return fail(ctx, FCSD_EHIP, std::string("capture: ") + hipGetErrorString(e));
+  if (st || e != hipSuccess) {
+    // a body that failed part-way leaves a partial graph: never kept
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st) return st;
+    return fail(ctx, FCSD_EHIP, std::string("capture: ") + hipGetErrorString(e));
+  }
   GraphEntry g;
   g.key = key;
   e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(ctx, FCSD_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+  // bounded cache: the oldest graph goes once kMaxGraphs argument sets are
+  // held (after the stream has drained, so it is not running)
+  if (ms->graphs.size() >= kMaxGraphs) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipGraphExecDestroy(ms->graphs.front().exec);
+    ms->graphs.erase(ms->graphs.begin());
+  }
   ms->graphs.push_back(g);
   HIPCHK(ctx, hipGraphLaunch(g.exec, ctx->stream));
   return FCSD_OK;

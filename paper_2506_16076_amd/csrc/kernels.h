@@ -29,8 +29,8 @@ struct PassArgs {
   float* d2out;               // pass B1: also store d2 (e - e_ref) here when not null
   const double* aq;
   const double* dq;
-  const double* gq;           // fold matrices of the transposed derivative (per plan, P.gq)
-  const double* gf;           // fold matrices of the transposed filter (per plan, P.gf)
+  const float* gq;            // fold matrices of the transposed derivative (per plan, P.gq)
+  const float* gf;            // fold matrices of the transposed filter (per plan, P.gf)
   int d;
   long long plane;
   int nf;
