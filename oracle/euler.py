@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle import fcgram
+from oracle import fcgram, wall
 
 
 def points(ps):
@@ -72,11 +72,95 @@ def divergence(fx, fy, metric, ps):
     return m1x * d1x + m2x * d2x + m1y * d1y + m2y * d2y
 
 
-def gradient(e, metric, ps):
+def _wall_patches(ps):
+    w = getattr(ps, "wall", None)
+    return [] if w is None else [p for p in range(ps.npatch) if np.asarray(w[p]).any()]
+
+
+def _patch_diff(x, ps, p, direction):
+    """FC derivative of one patch array [n2, n1] along q^direction."""
+    C = int(ps.C1[p] if direction == 1 else ps.C2[p])
+    if direction == 1:
+        return fcgram.diff_lines(x, ps.d, C)
+    return fcgram.diff_lines(x.T, ps.d, C).T
+
+
+def _patch_diff_adj(y, ps, p, direction):
+    C = int(ps.C1[p] if direction == 1 else ps.C2[p])
+    if direction == 1:
+        return fcgram.diff_lines_adj(y, ps.d, C)
+    return fcgram.diff_lines_adj(y.T, ps.d, C).T
+
+
+def _energy_rule(v, gamma):
+    """Coefficients of the energy derivative by the sum and product rules
+    (Remark adiabatic, eqs. p_T, perfect_gas_T): with E = rho theta /
+    (gamma - 1) + |m|^2 / (2 rho), dE = A d rho + B d theta + Cx d m_x +
+    Cy d m_y, A = E / rho - |m|^2 / rho^2, B = rho / (gamma - 1),
+    C = m / rho; and their partial derivatives in (rho, m_x, m_y, E)."""
+    rho, m, n, E = v
+    g1 = gamma - 1.0
+    q = m * m + n * n
+    A, B, Cx, Cy = E / rho - q / rho ** 2, rho / g1, m / rho, n / rho
+    z = np.zeros_like(rho)
+    dA = (-E / rho ** 2 + 2 * q / rho ** 3, -2 * m / rho ** 2, -2 * n / rho ** 2, 1 / rho)
+    dB = (np.full_like(rho, 1 / g1), z, z, z)
+    dCx = (-m / rho ** 2, 1 / rho, z, z)
+    dCy = (-n / rho ** 2, z, 1 / rho, z)
+    return (A, B, Cx, Cy), (dA, dB, dCx, dCy)
+
+
+def derivatives(e, ps, gamma=1.4):
+    """(d e/dq^1, d e/dq^2) of the four state components by FC (Sec. 2.2).
+    On patches with a wall side the energy's derivatives are formed by the
+    sum and product rules from those of rho, rho u, rho v and theta = p /
+    rho (Remark adiabatic; eqs. p_T, perfect_gas_T), theta's expansion
+    being the one through the wall values the glue sets (Neumann-consistent,
+    oracle.wall)."""
+    e = np.asarray(e, np.float64)
+    d = [fcgram.diff_plane(e, ps, 1), fcgram.diff_plane(e, ps, 2)]
+    for p in _wall_patches(ps):
+        v = ps.view(e, p)
+        th = wall.theta_of(v, gamma)
+        (A, B, Cx, Cy), _ = _energy_rule(v, gamma)
+        for k, direction in ((0, 1), (1, 2)):
+            dv = ps.view(d[k], p)
+            dth = _patch_diff(th, ps, p, direction)
+            dv[3] = A * dv[0] + B * dth + Cx * dv[1] + Cy * dv[2]
+    return d[0], d[1]
+
+
+def derivatives_vjp(e, ps, gamma, g1, g2):
+    """Cotangent of e given those of derivatives(e) (g1, g2: [4, plane])."""
+    e = np.asarray(e, np.float64)
+    g = [np.array(g1, np.float64, copy=True), np.array(g2, np.float64, copy=True)]
+    eb = np.zeros(e.shape)
+    for p in _wall_patches(ps):
+        v = ps.view(e, p)
+        th = wall.theta_of(v, gamma)
+        (A, B, Cx, Cy), (dA, dB, dCx, dCy) = _energy_rule(v, gamma)
+        ebp = ps.view(eb, p)
+        for k, direction in ((0, 1), (1, 2)):
+            gv = ps.view(g[k], p)
+            gE = gv[3].copy()
+            dv = ps.view(fcgram.diff_plane(e, ps, direction), p)
+            dth = _patch_diff(th, ps, p, direction)
+            # the rule's coefficients depend on the state at the point
+            for f in range(4):
+                ebp[f] += gE * (dA[f] * dv[0] + dB[f] * dth + dCx[f] * dv[1] + dCy[f] * dv[2])
+            # the derivatives it combines: rho, m_x, m_y lanes and theta's
+            gv[0] += A * gE
+            gv[1] += Cx * gE
+            gv[2] += Cy * gE
+            gv[3] = 0.0
+            ebp += wall.theta_vjp(v, _patch_diff_adj(B * gE, ps, p, direction), gamma)
+    return eb + fcgram.diff_plane_adj(g[0], ps, 1) + fcgram.diff_plane_adj(g[1], ps, 2)
+
+
+def gradient(e, metric, ps, gamma=1.4):
     """(d e/dx, d e/dy) by the chain rule: d/dx_a = sum_m m[m,a] d/dq^m."""
     m1x, m1y, m2x, m2y = _metric(metric)
-    d1 = fcgram.diff_plane(e, ps, 1)
-    d2 = fcgram.diff_plane(e, ps, 2)
+    d1, d2 = derivatives(e, ps, gamma)
     return m1x * d1 + m2x * d2, m1y * d1 + m2y * d2
 
 
@@ -89,9 +173,9 @@ def euler_rhs(e, metric, ps, gamma):
     return -divergence(F, G, metric, ps)
 
 
-def av_term(e, metric, mu, ps):
+def av_term(e, metric, mu, ps, gamma=1.4):
     """Viscous term div_x (mu grad_x e)."""
-    ex, ey = gradient(np.asarray(e, np.float64), metric, ps)
+    ex, ey = gradient(np.asarray(e, np.float64), metric, ps, gamma)
     mu = np.asarray(mu, np.float64)
     return divergence(mu * ex, mu * ey, metric, ps)
 
@@ -100,7 +184,7 @@ def full_rhs(e, metric, mu, ps, gamma):
     """L[e] = - div_x f(e) + div_x (mu grad_x e)  (eq. semi-discrete)."""
     r = euler_rhs(e, metric, ps, gamma)
     if mu is not None:
-        r = r + av_term(e, metric, mu, ps)
+        r = r + av_term(e, metric, mu, ps, gamma)
     return r
 
 
@@ -166,13 +250,17 @@ def divergence_adj(rb, metric, ps):
     return fxb, fyb
 
 
-def gradient_adj(exb, eyb, metric, ps):
+def gradient_adj(exb, eyb, metric, ps, e=None, gamma=1.4):
+    """Transpose of gradient at e (e is needed only on patches with walls,
+    where the energy's derivatives depend on the state)."""
     m1x, m1y, m2x, m2y = _metric(metric)
-    return (fcgram.diff_plane_adj(m1x * exb + m1y * eyb, ps, 1)
-            + fcgram.diff_plane_adj(m2x * exb + m2y * eyb, ps, 2))
+    g1, g2 = m1x * exb + m1y * eyb, m2x * exb + m2y * eyb
+    if _wall_patches(ps):
+        return derivatives_vjp(e, ps, gamma, g1, g2)
+    return fcgram.diff_plane_adj(g1, ps, 1) + fcgram.diff_plane_adj(g2, ps, 2)
 
 
-def av_term_vjp(e, metric, mu, ps, rb):
+def av_term_vjp(e, metric, mu, ps, rb, gamma=1.4):
     """(e_bar, mu_bar) for the map (e, mu) -> av_term(e, metric, mu): the
     term is the divergence of V = mu grad_x e, so with (V_x_bar, V_y_bar) the
     divergence transpose of rb, mu_bar = V_bar . grad_x e and e_bar is the
@@ -180,9 +268,9 @@ def av_term_vjp(e, metric, mu, ps, rb):
     e = np.asarray(e, np.float64)
     mu = np.asarray(mu, np.float64)
     fxb, fyb = divergence_adj(rb, metric, ps)
-    ex, ey = gradient(e, metric, ps)
+    ex, ey = gradient(e, metric, ps, gamma)
     mub = np.sum(fxb * ex + fyb * ey, axis=0)
-    return gradient_adj(mu * fxb, mu * fyb, metric, ps), mub
+    return gradient_adj(mu * fxb, mu * fyb, metric, ps, e, gamma), mub
 
 
 def full_rhs_vjp(e, metric, mu, ps, gamma, rb):
@@ -195,7 +283,7 @@ def full_rhs_vjp(e, metric, mu, ps, gamma, rb):
     mub = None
     if mu is not None:
         mu = np.asarray(mu, np.float64)
-        ex, ey = gradient(e, metric, ps)
+        ex, ey = gradient(e, metric, ps, gamma)
         mub = np.sum(fxb * ex + fyb * ey, axis=0)
-        eb = eb + gradient_adj(mu * fxb, mu * fyb, metric, ps)
+        eb = eb + gradient_adj(mu * fxb, mu * fyb, metric, ps, e, gamma)
     return eb, mub

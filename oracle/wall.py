@@ -22,10 +22,18 @@ evolved like an interior value.
 Readings:
   * the normal derivative is taken along the grid line that meets the wall
     (on the annulus the radial q^2 lines, normal to the cylinder);
-  * the derivatives of E and p inside the right-hand side are those of the
-    FC expansions of the glued state (the wall value carries the adiabatic
-    condition), not rebuilt by the product rule from a Neumann expansion of
-    theta as Remark adiabatic describes -- a simplification of this build;
+  * where two walls meet at a patch corner, the corner point takes the zero
+    normal slope in both directions: theta_c = sum_k sum_l c_k c_l
+    theta(k, l) over the interior points k, l = 1..d-1 away from the two
+    walls (the tensor product of the one-sided Neumann values); every other
+    wall point takes its own normal line, which then holds interior points
+    only, so the result does not depend on the order of the sides;
+  * inside the right-hand side, on patches with a wall side, the
+    derivatives of E are formed by the sum and product rules from those of
+    rho, rho u, rho v and theta (Remark adiabatic; euler.derivatives), the
+    theta lines through the wall values above being the Neumann-consistent
+    expansion; in the flux form used here E's derivatives enter the viscous
+    flux mu grad_x E, and p's do not appear apart from the flux values;
   * wall points are set after the fringe exchange and the Dirichlet
     overwrite (so the reverse mode transposes them first).
 """
@@ -62,65 +70,139 @@ def wall_lines(ps, p, side):
     return lambda v, k: v[..., n2 - 1 - k, :]
 
 
+def theta_of(v, gamma):
+    """theta = p / rho (eqs. perfect_gas, p_T) of a state [4, ...]."""
+    rho, m, n, E = v
+    return (gamma - 1.0) * (E - 0.5 * (m * m + n * n) / rho) / rho
+
+
+def _corner_index(ps, p, side, end):
+    """(i, j) index function of the interior points (k, l) of the corner
+    where wall `side` of patch p meets the wall at its tangential `end`
+    (0: t = 0, 1: t = last): k along the side's normal, l along the wall."""
+    n1, n2 = int(ps.n1[p]), int(ps.n2[p])
+    if side < 2:                      # wall along j: t = j, normal along i
+        ii = (lambda k: k) if side == 0 else (lambda k: n1 - 1 - k)
+        jj = (lambda l: l) if end == 0 else (lambda l: n2 - 1 - l)
+        return lambda k, l: (jj(l), ii(k))
+    jj = (lambda k: k) if side == 2 else (lambda k: n2 - 1 - k)
+    ii = (lambda l: l) if end == 0 else (lambda l: n1 - 1 - l)
+    return lambda k, l: (jj(k), ii(l))
+
+
+def corners(ps, p):
+    """Corner points of patch p shared by two wall sides: list of
+    (side owning the point, end, index function) -- the q1 side (0 or 1)
+    owns a corner it shares with a q2 side."""
+    out = []
+    w = ps.wall[p]
+    for side in (0, 1):
+        if not w[side]:
+            continue
+        for end, other in ((0, 2), (1, 3)):
+            if w[other]:
+                out.append((side, end, _corner_index(ps, p, side, end)))
+    return out
+
+
+def _wall_points(ps, p, side):
+    """Tangential index range of the non-corner points of a wall side."""
+    n1, n2 = int(ps.n1[p]), int(ps.n2[p])
+    length = n2 if side < 2 else n1
+    w = ps.wall[p]
+    lo = 1 if (side < 2 and w[2]) or (side >= 2 and w[0]) else 0
+    hi = length - 1 if (side < 2 and w[3]) or (side >= 2 and w[1]) else length
+    return lo, hi
+
+
+def rules(ps, p):
+    """The wall points of patch p with the interior points their theta is
+    formed from: a list of (jj, ii, terms), jj / ii index arrays of wall
+    points in the patch's [n2, n1] view and terms a list of (weight, js,
+    is) with index arrays aligned with them: theta_w = sum weight
+    theta(js, is)."""
+    c = neumann_weights(ps.d)
+    n1, n2 = int(ps.n1[p]), int(ps.n2[p])
+    out = []
+    for side in range(4):
+        if not ps.wall[p, side]:
+            continue
+        lo, hi = _wall_points(ps, p, side)
+        t = np.arange(lo, hi)
+        if side == 0:
+            jj, ii, nrm = t, np.zeros_like(t), (lambda k: (t, np.full_like(t, k)))
+        elif side == 1:
+            jj, ii, nrm = t, np.full_like(t, n1 - 1), (lambda k: (t, np.full_like(t, n1 - 1 - k)))
+        elif side == 2:
+            jj, ii, nrm = np.zeros_like(t), t, (lambda k: (np.full_like(t, k), t))
+        else:
+            jj, ii, nrm = np.full_like(t, n2 - 1), t, (lambda k: (np.full_like(t, n2 - 1 - k), t))
+        out.append((jj, ii, [(c[k],) + nrm(k) for k in range(1, ps.d)]))
+    for side, end, idx in corners(ps, p):
+        j0, i0 = idx(0, 0)
+        terms = []
+        for k in range(1, ps.d):
+            for l in range(1, ps.d):
+                j, i = idx(k, l)
+                terms.append((c[k] * c[l], np.array([j]), np.array([i])))
+        out.append((np.array([j0]), np.array([i0]), terms))
+    return out
+
+
 def apply(e, ps, gamma=1.4):
     """In-place wall condition on a [4, plane] state for every side flagged
-    in ps.wall ([P, 4]: q1-, q1+, q2-, q2+)."""
+    in ps.wall ([P, 4]: q1-, q1+, q2-, q2+), corners shared by two walls
+    included.  Every theta used is an interior point's, read before any
+    wall point is written."""
     if getattr(ps, "wall", None) is None:
         return e
-    c = neumann_weights(ps.d)
     g1 = gamma - 1.0
     for p in range(ps.npatch):
-        for side in range(4):
-            if not ps.wall[p, side]:
-                continue
-            v = ps.view(e, p)
-            line = wall_lines(ps, p, side)
-            th = np.zeros_like(line(v[0], 0))
-            for k in range(1, ps.d):
-                rho, m, n, E = (line(v[f], k) for f in range(4))
-                th += c[k] * g1 * (E - 0.5 * (m * m + n * n) / rho) / rho
-            rho_w = line(v[0], 0)
-            line(v[1], 0)[...] = 0.0
-            line(v[2], 0)[...] = 0.0
-            line(v[3], 0)[...] = rho_w * th / g1
+        if not ps.wall[p].any():
+            continue
+        v = ps.view(e, p)
+        th_all = theta_of(v, gamma)
+        writes = [(jj, ii, sum(w * th_all[js, is_] for w, js, is_ in terms)) for jj, ii, terms in rules(ps, p)]
+        for jj, ii, th in writes:
+            v[1, jj, ii] = 0.0
+            v[2, jj, ii] = 0.0
+            v[3, jj, ii] = v[0, jj, ii] * th / g1
     return e
+
+
+def theta_vjp(v, tb, gamma):
+    """Cotangent of a state [4, ...] given that of theta = theta_of(v)."""
+    rho, m, n, E = v
+    g1 = gamma - 1.0
+    return np.stack([tb * g1 * (-E / rho ** 2 + (m * m + n * n) / rho ** 3), -tb * g1 * m / rho ** 2,
+                     -tb * g1 * n / rho ** 2, tb * g1 / rho])
 
 
 def apply_vjp(eb, e_glued, ps, gamma=1.4):
     """In-place transpose of apply at the state it produced (e_glued: the
-    wall leaves rho and every point off the wall line as it found them, so
+    wall leaves rho and every point off the wall points as it found them, so
     its inputs are read there).  The momenta and E of a wall point are
     overwritten: their cotangents are dropped; rho_w gets theta_w / (gamma
-    - 1) times E_w's cotangent, and each interior point k the Neumann weight
-    c_k times rho_w / (gamma - 1) times E_w's cotangent times d theta_k / d e_k."""
+    - 1) times E_w's cotangent, and each interior source point its weight
+    times rho_w / (gamma - 1) times E_w's cotangent through d theta / d e."""
     if getattr(ps, "wall", None) is None:
         return eb
-    c = neumann_weights(ps.d)
     g1 = gamma - 1.0
     for p in range(ps.npatch):
-        for side in range(4):
-            if not ps.wall[p, side]:
-                continue
-            v = ps.view(e_glued, p)
-            b = ps.view(eb, p)
-            line = wall_lines(ps, p, side)
-            rho_w = line(v[0], 0)
-            Eb = line(b[3], 0).copy()
-            th = np.zeros_like(rho_w)
-            for k in range(1, ps.d):
-                rho, m, n, E = (line(v[f], k) for f in range(4))
-                th += c[k] * g1 * (E - 0.5 * (m * m + n * n) / rho) / rho
-            line(b[0], 0)[...] += Eb * th / g1
-            line(b[1], 0)[...] = 0.0
-            line(b[2], 0)[...] = 0.0
-            line(b[3], 0)[...] = 0.0
-            tb = Eb * rho_w / g1               # cotangent of theta_w
-            for k in range(1, ps.d):
-                rho, m, n, E = (line(v[f], k) for f in range(4))
-                tk = c[k] * tb
-                # theta = g1 (E / rho - (m^2 + n^2) / (2 rho^2))
-                line(b[0], k)[...] += tk * g1 * (-E / rho ** 2 + (m * m + n * n) / rho ** 3)
-                line(b[1], k)[...] += -tk * g1 * m / rho ** 2
-                line(b[2], k)[...] += -tk * g1 * n / rho ** 2
-                line(b[3], k)[...] += tk * g1 / rho
+        if not ps.wall[p].any():
+            continue
+        v = ps.view(e_glued, p)
+        b = ps.view(eb, p)
+        th_all = theta_of(v, gamma)
+        rl = rules(ps, p)
+        # every cotangent read before any is written (wall points are never sources)
+        reads = [(b[3, jj, ii].copy(), sum(w * th_all[js, is_] for w, js, is_ in terms)) for jj, ii, terms in rl]
+        for (jj, ii, terms), (Eb, th) in zip(rl, reads):
+            b[0, jj, ii] += Eb * th / g1
+            b[1, jj, ii] = 0.0
+            b[2, jj, ii] = 0.0
+            b[3, jj, ii] = 0.0
+            tb = Eb * v[0, jj, ii] / g1          # cotangent of theta_w
+            for w, js, is_ in terms:
+                np.add.at(b, (slice(None), js, is_), theta_vjp(v[:, js, is_], w * tb, gamma))
     return eb
