@@ -184,13 +184,16 @@ fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, 
  * polynomial of degree < d through theta = p / rho at the d - 1 points next
  * to the wall along the grid line that meets it, with zero derivative at
  * the wall (the Neumann continuation's boundary value); rho is left to
- * evolve.  The derivatives of E inside the right-hand side are those of its
- * FC expansion (the paper differentiates theta's Neumann expansion and
- * rebuilds E's derivatives by the product rule).  The wall condition is not
- * linear: fcsd_step_adj transposes it at the glued states it keeps, while
- * fcsd_glue_adj, which has no state, returns FCSD_EUNSUPPORTED on such
- * sets; walls on two sides of one patch that meet at a corner are refused
- * the same way.  Host-side set-up, synchronises the context's stream. */
+ * evolve.  Where two walls meet at a corner, the corner's theta is the
+ * tensor product of the two one-sided values over the (d-1)^2 interior
+ * points next to it.  On patches with a wall side the right-hand side's
+ * energy derivatives (in the viscous flux) are formed by the sum and
+ * product rules from those of rho, rho u, rho v and theta (Remark
+ * adiabatic).  The set then holds six planes of device memory of its own
+ * (theta, its derivatives and reverse-mode scratch) until the walls are
+ * cleared or the set is destroyed.  A side shorter than d + 1 points, across
+ * or along, returns FCSD_EINVAL.  Host-side set-up, synchronises the
+ * context's stream. */
 fcsd_status fcsd_set_walls(fcsd_set* set, const uint8_t* sides, float gamma);
 
 /* Map of a patch's grid to the plane: kind 0 Cartesian, (x, y) = (a0 + i da,
@@ -392,14 +395,17 @@ fcsd_status av_viscosity_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u,
  * plane `dirichlet_mask` (nullable).  No-op for independent patches. */
 fcsd_status fcsd_glue(fcsd_ctx* ctx, const fcsd_set* set, float* u, int64_t plane,
                       const uint8_t* dirichlet_mask, const float dirichlet_state[4]);
-/* Transpose of fcsd_glue on a cotangent u_bar (in place): the Dirichlet
- * points' cotangent is dotted with dstate_dparam (4 floats, host) into
+/* Transpose of fcsd_glue on a cotangent u_bar (in place): the wall
+ * condition's transpose at the glued state `glued` ([4][plane], the output
+ * of the fcsd_glue being reversed; required on sets with walls, else
+ * FCSD_EINVAL, and may be NULL without walls), then the Dirichlet points'
+ * cotangent is dotted with dstate_dparam (4 floats, host) into
  * dparam_dev[0] (device FP64, incremented) and zeroed; then every fringe
  * receiver's cotangent moves onto its donor (shells, then sectors).
  * dstate_dparam / dparam_dev may be NULL without a mask. */
 fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* set, float* u_bar, int64_t plane,
                           const uint8_t* dirichlet_mask, const float dstate_dparam[4],
-                          double* dparam_dev);
+                          double* dparam_dev, const float* glued);
 
 /* Transpose of the classifier network (Sec. 5.1) at the features of the
  * state u: for every point of the viscosity-generation subgrid and each

@@ -128,7 +128,7 @@ def lib():
             "av_viscosity": [vp, vp, vp, vp, f32, vp, vp, i64, vp, sz],
             "av_viscosity_adj": [vp, vp, vp, vp, vp, f32, vp, vp, i64, vp, sz],
             "fcsd_glue": [vp, vp, vp, i64, vp, P(f32)],
-            "fcsd_glue_adj": [vp, vp, vp, i64, vp, P(f32), vp],
+            "fcsd_glue_adj": [vp, vp, vp, i64, vp, P(f32), vp, vp],
             "fcsd_step_adj": [vp, vp, P(StepArgs), vp, vp, P(f32), vp, i64, vp, sz],
             "fcsd_stage": [vp, vp, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],
             "fcsd_stage_per_patch": [vp, vp, i32, vp, vp, vp, vp, vp, vp, P(f32), f32, vp, i64, vp, sz],

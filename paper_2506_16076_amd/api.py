@@ -366,11 +366,13 @@ def fcsd_glue(s, u, mask=None, state=(0, 0, 0, 0)):
     _call(s, "fcsd_glue", _p(u), s.plane, _p(mask), _f4(state))
 
 
-def fcsd_glue_adj(s, u_bar, mask=None, dstate=(0, 0, 0, 0), dparam=None):
+def fcsd_glue_adj(s, u_bar, mask=None, dstate=(0, 0, 0, 0), dparam=None, glued=None):
     """Transpose of fcsd_glue in place; dparam (float64 device, 1 element)
-    is incremented by the Dirichlet points' cotangent dotted with dstate."""
+    is incremented by the Dirichlet points' cotangent dotted with dstate;
+    glued: the glue's output state (needed on sets with walls)."""
     _chk(u_bar, numel=4 * s.plane), _chk(mask, torch.uint8, s.plane), _chk(dparam, torch.float64, 1)
-    _call(s, "fcsd_glue_adj", _p(u_bar), s.plane, _p(mask), _f4(dstate), _p(dparam))
+    _chk(glued, numel=4 * s.plane)
+    _call(s, "fcsd_glue_adj", _p(u_bar), s.plane, _p(mask), _f4(dstate), _p(dparam), _p(glued))
 
 
 def fcsd_filter(s, u, out, gamma=1.4):

@@ -48,6 +48,7 @@ struct PlanDev {
   int kf;        // offset of the spectral filter factors (float2) for this L
   int gq;        // offset of the derivative's fold matrix (float), N*2d entries, for this (N, C)
   int gf;        // offset of the filter's fold matrix (float), N*2d entries (filter configured)
+  int wallp;     // the patch has a wall side (energy derivatives by the product rule)
   int nlines;    // lines along this direction
   int n1, n2;    // patch shape
   int patch;     // patch index

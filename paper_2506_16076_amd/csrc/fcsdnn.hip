@@ -121,8 +121,14 @@ struct fcsd_set {
   int filter_on = 0;
   double filter_alpha = 0.0;
   int filter_p = 0;
-  WallDev* d_walls = nullptr;             // no-slip adiabatic wall sides (fcsd_set_walls)
+  WallDev* d_walls = nullptr;             // no-slip adiabatic wall entries (fcsd_set_walls)
   int nwalls = 0, wall_len = 0;
+  std::vector<uint8_t> wall_patch;        // per patch: has a wall side
+  ChunkDev* d_wchunks = nullptr;          // point chunks of the wall patches
+  int nwchunks = 0;
+  TileDev* d_wtiles[2] = {nullptr, nullptr};  // per direction: line tiles (single-field set) of the wall patches
+  int nwtiles[2] = {0, 0};
+  float* d_wplanes = nullptr;             // 6 planes: theta, d1 theta, d2 theta, and reverse-mode scratch
   float* d_wall_c = nullptr;              // Neumann boundary-value weights c[0..d-1]
   float wall_g1 = 0.4f;
   InterpDev* d_interp = nullptr;          // inter-patch interpolation table (fcsd_set_interp)
@@ -158,6 +164,8 @@ struct fcsd_set {
 };
 
 namespace {
+
+fcsd_status rebuild_wall_tiles(fcsd_set* s);
 
 fcsd_status fail(fcsd_ctx* c, fcsd_status s, const std::string& m) {
   if (c) c->err = m;
@@ -717,6 +725,10 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_kf);
   hipFree(s->d_walls);
   hipFree(s->d_wall_c);
+  hipFree(s->d_wchunks);
+  hipFree(s->d_wtiles[0]);
+  hipFree(s->d_wtiles[1]);
+  hipFree(s->d_wplanes);
   hipFree(s->d_interp);
   hipFree(s->d_ovl);
   hipFree(s->d_ovl_src);
@@ -765,13 +777,13 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const
   s->dir[1].ts[0].threads = threads[1];
   s->dir[1].ts[1].budget = (size_t)lds_budget[2];
   s->dir[1].ts[1].threads = threads[2];
+  fcsd_status r;
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
     build_tiles(D, order, tile_align(s->layout, dir), s->d);
-    fcsd_status r;
     if ((r = upload_tiles(ctx, D))) return r;
   }
-  return FCSD_OK;
+  return rebuild_wall_tiles(s);
 }
 
 extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
@@ -920,6 +932,54 @@ RhsWs carve_rhs(const fcsd_set* s, void* ws) {
 }
 
 // flux: FLUX_FULL, FLUX_VISC, FLUX_INVISCID ; out: MODE_SET / MODE_ADD / MODE_RK
+// Launch a line kernel over an explicit list of n tiles of the
+// single-field tile set of direction dir.
+template <class K>
+fcsd_status launch_tiles(const fcsd_set* s, int dir, K kern, PassArgs a, const TileDev* tiles, int n) {
+  if (n == 0) return FCSD_OK;
+  const TileSet& D = s->dir[dir - 1].ts[0];
+  a.tiles = tiles;
+  hipLaunchKernelGGL(kern, dim3((unsigned)n), dim3(D.threads), D.lds, s->ctx->stream, a);
+  return launch_check(s->ctx, "line kernel");
+}
+
+// The chunks of the wall patches (patch < 0) or of wall patch `patch`.
+void wall_chunks(const fcsd_set* s, int patch, const ChunkDev** ch, int* n) {
+  if (patch < 0) {
+    *ch = s->d_wchunks;
+    *n = s->nwchunks;
+  } else {
+    *ch = s->d_chunks + s->patch_chunk_begin[patch];
+    *n = s->patch_chunk_begin[patch + 1] - s->patch_chunk_begin[patch];
+  }
+}
+
+// theta - theta_ref on the wall patches (or wall patch `patch`) and its FC
+// derivatives along q1 and q2, into the set's planes 0, 1, 2 (the energy's
+// product rule, Remark adiabatic; ref = (rho, u, v, p) of the reference).
+fcsd_status wall_theta_derivs(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float ref[4], float gamma,
+                              int patch) {
+  const long long pl = s->plane;
+  float* TH = s->d_wplanes;
+  const ChunkDev* ch;
+  int n;
+  wall_chunks(s, patch, &ch, &n);
+  hipLaunchKernelGGL(k_theta, dim3(chunk_grid(n)), dim3(kBlock), 0, ctx->stream, ch, n, s->d_patches, u, pl,
+                     (double)gamma - 1.0, (double)ref[3] / (double)ref[0], TH);
+  fcsd_status st;
+  for (int dir = 1; dir <= 2; ++dir) {
+    PassArgs a = base_args(s, dir);
+    a.in = TH;
+    a.out = TH + dir * pl;
+    a.nf = 1;
+    auto kern = dir == 1 ? k_fcdiff<1, false> : k_fcdiff<2, false>;
+    st = patch < 0 ? launch_tiles(s, dir, kern, a, s->d_wtiles[dir - 1], s->nwtiles[dir - 1])
+                   : launch_lines(s, dir, kern, a, patch);
+    if (st) return st;
+  }
+  return launch_check(ctx, "wall theta derivatives");
+}
+
 fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const float* metric, const float* mu,
                        const float ref[4], float gamma, int flux, int outmode, float* rhs, int stage,
                        const float* u0, float* acc, float* uout, const float* dtp, void* ws, int patch,
@@ -948,14 +1008,29 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
     }
     if ((st = launch_check(ctx, "pass H"))) return st;
   } else if (flux != FLUX_INVISCID) {
+    // patches with a wall side: the energy's derivatives by the product rule
+    // from those of rho, m and theta (after pass A for q1, inside B1 for q2)
+    const bool walls = s->nwchunks > 0 && (patch < 0 || s->wall_patch[patch]);
+    if (walls && (passes & 3u))
+      if ((st = wall_theta_derivs(ctx, s, u, ref, gamma, patch))) return st;
     a.plans = s->dir[0].d_plans;
     a.out = W.d1e;
-    if (passes & 1u)
+    if (passes & 1u) {
       if ((st = launch_lines(s, 1, k_dev_diff<1>, a, patch))) return st;
+      if (walls) {
+        const ChunkDev* ch;
+        int n;
+        wall_chunks(s, patch, &ch, &n);
+        hipLaunchKernelGGL(k_energy_rule, dim3(chunk_grid(n)), dim3(kBlock), 0, ctx->stream, ch, n, s->d_patches, u,
+                           (long long)s->plane, gamma - 1.0f, (const float*)(s->d_wplanes + s->plane), W.d1e);
+        if ((st = launch_check(ctx, "energy rule q1"))) return st;
+      }
+    }
     PassArgs b = a;
     b.plans = s->dir[1].d_plans;
     b.mode = flux;
     b.d2out = d2e_rec;
+    b.d2th = walls ? s->d_wplanes + 2 * s->plane : nullptr;
     if (passes & 2u)
       if ((st = launch_lines(s, 2, k_passB1, b, patch, 2))) return st;
   }
@@ -1249,10 +1324,13 @@ fcsd_status glue_impl(fcsd_ctx* ctx, const fcsd_set* s, float* u, const uint8_t*
 fcsd_status glue_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, float* ub, const uint8_t* mask, const float* ds4,
                           double* dparam, const float* glued = nullptr) {
   if (s->nwalls > 0) {
-    if (!glued) return fail(ctx, FCSD_EUNSUPPORTED, "glue reverse mode: the wall condition needs the glued state");
-    hipLaunchKernelGGL(k_wall_adj, dim3(blocks_for((long long)s->nwalls * s->wall_len)), dim3(kBlock), 0,
-                       ctx->stream, s->d_walls, s->nwalls, s->wall_len, s->d_patches, glued, ub, (long long)s->plane,
-                       s->wall_g1, s->d, (const float*)s->d_wall_c);
+    if (!glued) return fail(ctx, FCSD_EINVAL, "glue reverse mode: the wall condition needs the glued state");
+    // one launch per side, then the corners: entries in one launch never
+    // share a source point
+    for (int only = 0; only < 5; ++only)
+      hipLaunchKernelGGL(k_wall_adj, dim3(blocks_for((long long)s->nwalls * s->wall_len)), dim3(kBlock), 0,
+                         ctx->stream, s->d_walls, s->nwalls, s->wall_len, s->d_patches, glued, ub,
+                         (long long)s->plane, s->wall_g1, s->d, (const float*)s->d_wall_c, only);
   }
   if (mask)
     hipLaunchKernelGGL(k_dirichlet_adj, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, mask, ub,
@@ -1280,15 +1358,14 @@ fcsd_status glue_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, float* ub, const uin
 
 extern "C" fcsd_status fcsd_glue_adj(fcsd_ctx* ctx, const fcsd_set* s, float* u_bar, int64_t plane,
                                      const uint8_t* dirichlet_mask, const float dstate_dparam[4],
-                                     double* dparam_dev) {
+                                     double* dparam_dev, const float* glued) {
   fcsd_status st = check_set(ctx, s, plane);
   if (st) return st;
   if (!u_bar || (dirichlet_mask && (!dstate_dparam || !dparam_dev)))
     return fail(ctx, FCSD_EINVAL, "fcsd_glue_adj: null argument");
-  if (s->nwalls > 0)
-    return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_glue_adj: the wall condition's reverse mode needs the glued state "
-                                        "(fcsd_step_adj has it)");
-  return glue_adj_impl(ctx, s, u_bar, dirichlet_mask, dstate_dparam, dparam_dev);
+  if (s->nwalls > 0 && !glued)
+    return fail(ctx, FCSD_EINVAL, "fcsd_glue_adj: the wall condition's reverse mode needs the glued state");
+  return glue_adj_impl(ctx, s, u_bar, dirichlet_mask, dstate_dparam, dparam_dev, glued);
 }
 
 extern "C" fcsd_status fcsd_glue(fcsd_ctx* ctx, const fcsd_set* s, float* u, int64_t plane,
@@ -1495,25 +1572,58 @@ extern "C" fcsd_status fcsd_step(fcsd_ctx* ctx, const fcsd_set* s, const fcsd_st
   return FCSD_OK;
 }
 
+namespace {
+
+// Line tiles of the wall patches, per direction (from the single-field tile
+// sets, in their launch order), for the FC derivatives of theta.
+fcsd_status rebuild_wall_tiles(fcsd_set* s) {
+  fcsd_ctx* ctx = s->ctx;
+  fcsd_status r;
+  for (int dir = 0; dir < 2; ++dir) {
+    (void)hipFree(s->d_wtiles[dir]);
+    s->d_wtiles[dir] = nullptr;
+    s->nwtiles[dir] = 0;
+    if (s->wall_patch.empty()) continue;
+    const DirPlan& D = s->dir[dir];
+    std::vector<TileDev> t;
+    for (const TileDev& T : D.ts[0].tiles)
+      if (T.nl > 0 && s->wall_patch[D.plans[T.plan].patch]) t.push_back(T);
+    if ((r = upload(ctx, &s->d_wtiles[dir], t))) return r;
+    s->nwtiles[dir] = (int)t.size();
+  }
+  return FCSD_OK;
+}
+
+}  // namespace
+
 extern "C" fcsd_status fcsd_set_walls(fcsd_set* s, const uint8_t* sides, float gamma) {
   if (!s) return FCSD_EINVAL;
   fcsd_ctx* ctx = s->ctx;
   if (!(gamma > 1.0f)) return fail(ctx, FCSD_EINVAL, "fcsd_set_walls: need gamma > 1");
   std::vector<WallDev> walls;
+  std::vector<uint8_t> wp(s->npatch, 0);
   int len = 0;
   if (sides)
     for (int p = 0; p < s->npatch; ++p) {
       const uint8_t* f = sides + 4 * p;
-      if ((f[0] || f[1]) && (f[2] || f[3]))
-        return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_set_walls: walls that meet at a corner of patch " + std::to_string(p));
-      for (int side = 0; side < 4; ++side)
-        if (sides[4 * p + side]) {
-          const fcsd_patch_desc& q = s->desc[p];
-          if ((side < 2 ? q.n1 : q.n2) < s->d + 1)
-            return fail(ctx, FCSD_EINVAL, "fcsd_set_walls: patch too short across its wall");
-          walls.push_back(WallDev{p, side});
-          len = std::max(len, side < 2 ? q.n2 : q.n1);
+      const fcsd_patch_desc& q = s->desc[p];
+      for (int side = 0; side < 4; ++side) {
+        if (!f[side]) continue;
+        if ((side < 2 ? q.n1 : q.n2) < s->d + 1)
+          return fail(ctx, FCSD_EINVAL, "fcsd_set_walls: patch too short across its wall");
+        if ((side < 2 ? q.n2 : q.n1) < s->d + 1)
+          return fail(ctx, FCSD_EINVAL, "fcsd_set_walls: patch too short along its wall");
+        const int length = side < 2 ? q.n2 : q.n1;
+        // points shared with a perpendicular wall are corners, owned by the q1 side
+        const bool lo_c = side < 2 ? f[2] : f[0], hi_c = side < 2 ? f[3] : f[1];
+        walls.push_back(WallDev{p, side, lo_c ? 1 : 0, hi_c ? length - 1 : length, -1});
+        if (side < 2) {
+          if (lo_c) walls.push_back(WallDev{p, side, 0, 1, 0});
+          if (hi_c) walls.push_back(WallDev{p, side, 0, 1, 1});
         }
+        len = std::max(len, length);
+        wp[p] = 1;
+      }
     }
   // Neumann boundary value: p(0) = c[0] g + sum_{k=1}^{d-1} c[k] F_k for the
   // polynomial of degree < d with p(k) = F_k and p'(0) = g (grid units);
@@ -1546,11 +1656,40 @@ extern "C" fcsd_status fcsd_set_walls(fcsd_set* s, const uint8_t* sides, float g
   s->graphs.clear();
   (void)hipFree(s->d_walls);
   (void)hipFree(s->d_wall_c);
+  (void)hipFree(s->d_wchunks);
+  (void)hipFree(s->d_wplanes);
   s->d_walls = nullptr;
   s->d_wall_c = nullptr;
+  s->d_wchunks = nullptr;
+  s->d_wplanes = nullptr;
   s->nwalls = 0;
+  s->nwchunks = 0;
+  s->wall_patch.clear();
   fcsd_status r;
   if ((r = upload(ctx, &s->d_walls, walls)) || (r = upload(ctx, &s->d_wall_c, c))) return r;
+  // wall patches: their plans' flag, point chunks, line tiles and the set's
+  // scratch planes for theta and its derivatives
+  const bool any = !walls.empty();
+  for (int dir = 0; dir < 2; ++dir) {
+    DirPlan& D = s->dir[dir];
+    for (PlanDev& P : D.plans) P.wallp = any ? wp[P.patch] : 0;
+    (void)hipFree(D.d_plans);
+    D.d_plans = nullptr;
+    if ((r = upload(ctx, &D.d_plans, D.plans))) return r;
+  }
+  if (any) {
+    s->wall_patch = wp;
+    std::vector<ChunkDev> wc;
+    for (int p = 0; p < s->npatch; ++p)
+      if (wp[p])
+        for (long long k = 0; k < patch_storage(s->desc[p].n1, s->desc[p].n2, s->layout); k += kChunk)
+          wc.push_back(ChunkDev{p, (int)k});
+    if ((r = upload(ctx, &s->d_wchunks, wc))) return r;
+    s->nwchunks = (int)wc.size();
+    HIPCHK(ctx, hipMalloc((void**)&s->d_wplanes, 6 * (size_t)s->plane * sizeof(float)));
+    HIPCHK(ctx, hipMemset(s->d_wplanes, 0, 6 * (size_t)s->plane * sizeof(float)));
+  }
+  if ((r = rebuild_wall_tiles(s))) return r;
   s->nwalls = (int)walls.size();
   s->wall_len = len;
   s->wall_g1 = gamma - 1.0f;
@@ -1860,17 +1999,30 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
   a.metric = metric;
   a.mu = mu;
   a.mode = flux;   // FLUX_VISC: the viscous term alone (no flux cotangent)
+  // wall patches: theta's derivatives for the energy's product rule (the
+  // recorded derivatives already hold the rule's energy lane)
+  const bool walls = visc && s->nwchunks > 0;
+  const float* D1TH = walls ? s->d_wplanes + pl : nullptr;
+  const float* D2TH = walls ? s->d_wplanes + 2 * pl : nullptr;
+  if (walls)
+    if ((st = wall_theta_derivs(ctx, s, u, ref, gamma, -1))) return st;
   if (visc) {
     PassArgs b = a;
     if (!given1) {
       b.out = w;
       b.plans = s->dir[0].d_plans;
       if ((st = launch_lines(s, 1, k_dev_diff<1>, b))) return st;
+      if (walls)
+        hipLaunchKernelGGL(k_energy_rule, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream, s->d_wchunks,
+                           s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, D1TH, w);
     }
     if (!given2) {
       b.out = w + 4 * pl;
       b.plans = s->dir[1].d_plans;
       if ((st = launch_lines(s, 2, k_dev_diff<2>, b))) return st;
+      if (walls)
+        hipLaunchKernelGGL(k_energy_rule, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream, s->d_wchunks,
+                           s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, D2TH, w + 4 * pl);
     }
   }
   {
@@ -1896,6 +2048,31 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
     if ((st = launch_check(ctx, "adj B2"))) return st;
   }
   if (visc) {
+    if (walls) {
+      // the energy rule transposed: G1, G2 move the energy lane's cotangent
+      // onto rho, m and theta's lanes (TB1, TB2), the rule's coefficients
+      // add to u_bar; theta's cotangent D1^T TB1 + D2^T TB2 then goes
+      // through d theta / d e
+      float* TB1 = s->d_wplanes + 3 * pl;
+      float* TB2 = s->d_wplanes + 4 * pl;
+      float* THB = s->d_wplanes + 5 * pl;
+      hipLaunchKernelGGL(k_energy_rule_adj, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream,
+                         s->d_wchunks, s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, d1e, D1TH, G1, TB1, u_bar);
+      hipLaunchKernelGGL(k_energy_rule_adj, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream,
+                         s->d_wchunks, s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, d2e, D2TH, G2, TB2, u_bar);
+      hipLaunchKernelGGL(k_fill, dim3(blocks_for(pl)), dim3(kBlock), 0, ctx->stream, THB, 0.f, pl);
+      for (int dir = 1; dir <= 2; ++dir) {
+        PassArgs c = base_args(s, dir);
+        c.in = dir == 1 ? TB1 : TB2;
+        c.out = THB;
+        c.nf = 1;
+        auto kern = dir == 1 ? k_fcdiff<1, true> : k_fcdiff<2, true>;
+        if ((st = launch_tiles(s, dir, kern, c, s->d_wtiles[dir - 1], s->nwtiles[dir - 1]))) return st;
+      }
+      hipLaunchKernelGGL(k_theta_adj, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream, s->d_wchunks,
+                         s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, (const float*)THB, u_bar);
+      if ((st = launch_check(ctx, "energy rule reverse"))) return st;
+    }
     // u_bar += D2^T G2 + D1^T G1 (deviation form: the constant reference has no adjoint)
     if ((st = fc_diff_adj(ctx, s, 2, 4, G2, u_bar, pl))) return st;
     if ((st = fc_diff_adj(ctx, s, 1, 4, G1, u_bar, pl))) return st;

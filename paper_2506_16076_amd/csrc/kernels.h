@@ -27,6 +27,7 @@ struct PassArgs {
   const int* koff;            // per plan: offset of its factors in kf (when not the plan's own)
   const float* win;           // blending window plane (initial-data smearing)
   float* d2out;               // pass B1: also store d2 (e - e_ref) here when not null
+  const float* d2th;          // pass B1 on wall patches: d2 theta, for the energy's product rule
   const double* aq;
   const double* dq;
   const float* gq;            // fold matrices of the transposed derivative (per plan, P.gq)
@@ -286,8 +287,10 @@ __device__ __forceinline__ HSrc h_sources(const PassArgs& a, long long base, int
   const float* mt = a.metric + base;
   const float* d1 = (visc ? a.d1e : a.metric) + base;
   const long long ds = visc ? pl : 0;
-  const float* e = (inv ? a.u : a.metric) + base;
-  const long long es = inv ? pl : 0;
+  // the state: for the fluxes, and on wall patches for the energy's product rule
+  const bool need_e = inv || a.d2th != nullptr;
+  const float* e = (need_e ? a.u : a.metric) + base;
+  const long long es = need_e ? pl : 0;
   HSrc h;
   h.m1x = mt;
   h.m1y = mt + pl;
@@ -354,7 +357,14 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
       M.w, [&](unsigned g) { return load_H4_inputs(hs, g); },
       [&](unsigned g, unsigned l, const HIn4& q) {
         const float2 za = at(z, l), zq = at(zb, l);
-        const float d2[4] = {za.x, za.y, zq.x, zq.y};
+        float d2[4] = {za.x, za.y, zq.x, zq.y};
+        if (a.d2th && P.wallp) {
+          // the energy's derivative by the product rule from rho, m and theta's
+          // (Remark adiabatic): dE = A d rho + B d theta + (m . dm) / rho
+          const float ir = 1.0f / q.e[0], mq = q.e[1] * q.e[1] + q.e[2] * q.e[2];
+          const float A = q.e[3] * ir - mq * ir * ir, B = q.e[0] / (a.gamma - 1.0f);
+          d2[3] = A * d2[0] + B * at(a.d2th + M.base, g) + (q.e[1] * d2[1] + q.e[2] * d2[2]) * ir;
+        }
         if (d2o) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) at(d2o + k * pl, g) = d2[k];

@@ -100,18 +100,59 @@ __global__ void __launch_bounds__(kBlock) k_interp_adj(const InterpDev* __restri
 // ---------------------------------------------------------------- walls
 
 // A wall side of a patch: patch index and side (q1-, q1+, q2-, q2+).
+// One entry of a patch's wall condition: the non-corner points t in
+// [lo, hi) of a wall side (end < 0), or the corner point where the side
+// meets the wall at its tangential end `end` (0: t = 0, 1: t = last; the
+// q1 side owns a corner it shares with a q2 side).
 struct WallDev {
-  int patch, side;
+  int patch, side, lo, hi, end;
 };
 
+// Grid offset of the point kk steps from wall `side` along its normal and
+// tt along the wall (from its t = 0 end).
+__device__ __forceinline__ long long wall_at(const PatchDev& P, int side, int kk, int tt) {
+  switch (side) {
+    case 0: return pidx(P, kk, tt);
+    case 1: return pidx(P, P.n1 - 1 - kk, tt);
+    case 2: return pidx(P, tt, kk);
+    default: return pidx(P, tt, P.n2 - 1 - kk);
+  }
+}
+
+__device__ __forceinline__ float theta_at(const float* u, long long pl, long long g, float g1) {
+  const float rho = u[g], m = u[pl + g], n = u[2 * pl + g], E = u[3 * pl + g];
+  return g1 * (E - 0.5f * (m * m + n * n) / rho) / rho;
+}
+
+// theta_w of a wall entry's point t: along its normal line (c[k] theta(k)),
+// or at a corner the tensor product of the two one-sided Neumann values
+// (c[k] c[l] theta(k, l) over the interior points k, l = 1..d-1).
+__device__ __forceinline__ float wall_theta(const WallDev& w, const PatchDev& P, int t, const float* u, long long pl,
+                                            float g1, int d, const float* __restrict__ c) {
+  float th = 0.f;
+  if (w.end < 0) {
+    for (int kk = 1; kk < d; ++kk) th = fmaf(c[kk], theta_at(u, pl, wall_at(P, w.side, kk, t), g1), th);
+  } else {
+    const int len = w.side < 2 ? P.n2 : P.n1;
+    for (int kk = 1; kk < d; ++kk)
+      for (int ll = 1; ll < d; ++ll)
+        th = fmaf(c[kk] * c[ll], theta_at(u, pl, wall_at(P, w.side, kk, w.end == 0 ? ll : len - 1 - ll), g1), th);
+  }
+  return th;
+}
+
+// Tangential position of thread t of wall entry w (corner entries: one).
+__device__ __forceinline__ int wall_point(const WallDev& w, const PatchDev& P, int t) {
+  if (w.end >= 0) return t == 0 ? (w.end == 0 ? 0 : (w.side < 2 ? P.n2 : P.n1) - 1) : -1;
+  const int tt = w.lo + t;
+  return tt < w.hi ? tt : -1;
+}
+
 // No-slip adiabatic wall (paper Remarks adiabatic_th, adiabatic): on every
-// point of a wall line, rho u = rho v = 0 and E = rho theta_w / (gamma - 1)
-// with theta_w the Neumann FC boundary value of theta = p / rho for a zero
-// normal derivative: sum_k c[k] theta_k over the d - 1 points next to the
-// wall along the grid line that meets it.  One thread per (wall, position
-// along the wall).  A patch has walls on opposite sides at most (the host
-// refuses two walls that meet at a corner), so no thread reads a point
-// another thread writes.
+// wall point, rho u = rho v = 0 and E = rho theta_w / (gamma - 1) with
+// theta_w the Neumann FC boundary value of theta = p / rho for a zero
+// normal slope (weights c, host-computed).  Every theta read is an interior
+// point's, which no thread writes.
 __global__ void __launch_bounds__(kBlock) k_wall(const WallDev* __restrict__ walls, int nwall, int maxlen,
                                                  const PatchDev* __restrict__ patches, float* u, long long pl,
                                                  float g1, int d, const float* __restrict__ c) {
@@ -120,23 +161,10 @@ __global__ void __launch_bounds__(kBlock) k_wall(const WallDev* __restrict__ wal
   const int wi = (int)(k / maxlen), t = (int)(k - (long long)wi * maxlen);
   const WallDev w = walls[wi];
   const PatchDev P = patches[w.patch];
-  const int len = w.side < 2 ? P.n2 : P.n1;
-  if (t >= len) return;
-  auto at_k = [&](int kk) {
-    switch (w.side) {
-      case 0: return pidx(P, kk, t);
-      case 1: return pidx(P, P.n1 - 1 - kk, t);
-      case 2: return pidx(P, t, kk);
-      default: return pidx(P, t, P.n2 - 1 - kk);
-    }
-  };
-  float th = 0.f;
-  for (int kk = 1; kk < d; ++kk) {
-    const long long g = at_k(kk);
-    const float rho = u[g], m = u[pl + g], n = u[2 * pl + g], E = u[3 * pl + g];
-    th = fmaf(c[kk], g1 * (E - 0.5f * (m * m + n * n) / rho) / rho, th);
-  }
-  const long long g0 = at_k(0);
+  const int tt = wall_point(w, P, t);
+  if (tt < 0) return;
+  const float th = wall_theta(w, P, tt, u, pl, g1, d, c);
+  const long long g0 = wall_at(P, w.side, 0, tt);
   u[pl + g0] = 0.f;
   u[2 * pl + g0] = 0.f;
   u[3 * pl + g0] = u[g0] * th / g1;
@@ -145,48 +173,45 @@ __global__ void __launch_bounds__(kBlock) k_wall(const WallDev* __restrict__ wal
 // Transpose of k_wall at the state it produced (eg: the glued state, whose
 // wall-point rho and interior points the wall left as it found them): the
 // overwritten momenta and energy drop their cotangents, rho_w gets
-// theta_w / (gamma - 1) times E_w's cotangent, and every interior point the
-// Neumann weight times rho_w / (gamma - 1) times E_w's cotangent through
-// d theta / d e.  Same threads and exclusivity as k_wall.
+// theta_w / (gamma - 1) times E_w's cotangent, and every interior source its
+// weight times rho_w / (gamma - 1) times E_w's cotangent through
+// d theta / d e.  Entries whose sources may coincide (two sides of one
+// patch, a side and a corner) run in separate launches: `only` selects the
+// side (0..3) or the corners (4).
 __global__ void __launch_bounds__(kBlock) k_wall_adj(const WallDev* __restrict__ walls, int nwall, int maxlen,
                                                      const PatchDev* __restrict__ patches, const float* eg, float* ub,
-                                                     long long pl, float g1, int d, const float* __restrict__ c) {
+                                                     long long pl, float g1, int d, const float* __restrict__ c,
+                                                     int only) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (long long)nwall * maxlen) return;
   const int wi = (int)(k / maxlen), t = (int)(k - (long long)wi * maxlen);
   const WallDev w = walls[wi];
+  if (only < 4 ? (w.end >= 0 || w.side != only) : w.end < 0) return;
   const PatchDev P = patches[w.patch];
-  const int len = w.side < 2 ? P.n2 : P.n1;
-  if (t >= len) return;
-  auto at_k = [&](int kk) {
-    switch (w.side) {
-      case 0: return pidx(P, kk, t);
-      case 1: return pidx(P, P.n1 - 1 - kk, t);
-      case 2: return pidx(P, t, kk);
-      default: return pidx(P, t, P.n2 - 1 - kk);
-    }
-  };
-  float th = 0.f;
-  for (int kk = 1; kk < d; ++kk) {
-    const long long g = at_k(kk);
-    const float rho = eg[g], m = eg[pl + g], n = eg[2 * pl + g], E = eg[3 * pl + g];
-    th = fmaf(c[kk], g1 * (E - 0.5f * (m * m + n * n) / rho) / rho, th);
-  }
-  const long long g0 = at_k(0);
+  const int tt = wall_point(w, P, t);
+  if (tt < 0) return;
+  const float th = wall_theta(w, P, tt, eg, pl, g1, d, c);
+  const long long g0 = wall_at(P, w.side, 0, tt);
   const float Eb = ub[3 * pl + g0];
   const float tb = Eb * eg[g0] / g1;
   ub[g0] += Eb * th / g1;
   ub[pl + g0] = 0.f;
   ub[2 * pl + g0] = 0.f;
   ub[3 * pl + g0] = 0.f;
-  for (int kk = 1; kk < d; ++kk) {
-    const long long g = at_k(kk);
+  auto add = [&](long long g, float wgt) {
     const float rho = eg[g], m = eg[pl + g], n = eg[2 * pl + g], E = eg[3 * pl + g];
-    const float tk = c[kk] * tb * g1, ir = 1.0f / rho, ir2 = ir * ir;
+    const float tk = wgt * tb * g1, ir = 1.0f / rho, ir2 = ir * ir;
     ub[g] += tk * (-E * ir2 + (m * m + n * n) * ir2 * ir);
     ub[pl + g] -= tk * m * ir2;
     ub[2 * pl + g] -= tk * n * ir2;
     ub[3 * pl + g] += tk * ir;
+  };
+  if (w.end < 0) {
+    for (int kk = 1; kk < d; ++kk) add(wall_at(P, w.side, kk, tt), c[kk]);
+  } else {
+    const int len = w.side < 2 ? P.n2 : P.n1;
+    for (int kk = 1; kk < d; ++kk)
+      for (int ll = 1; ll < d; ++ll) add(wall_at(P, w.side, kk, w.end == 0 ? ll : len - 1 - ll), c[kk] * c[ll]);
   }
 }
 
@@ -262,6 +287,97 @@ constexpr int kChunkGrid = 2048;
 template <class F>
 __device__ __forceinline__ void for_chunks(const ChunkDev* chunks, int nchunks, F&& f) {
   for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) f(chunks[cb]);
+}
+
+// ---- energy derivatives by the product rule on wall patches (Remark
+// adiabatic; eqs. p_T, perfect_gas_T): with E = rho theta / (gamma - 1) +
+// |m|^2 / (2 rho), dE = A d rho + B d theta + Cx d m_x + Cy d m_y,
+// A = E / rho - |m|^2 / rho^2, B = rho / (gamma - 1), C = m / rho.
+
+// theta - theta_ref at every point of the chunks (the wall patches' ones),
+// formed in FP64 and rounded once: its rounding is then relative to the
+// difference, as that of e - e_ref is on the other lanes, rather than to
+// theta itself (two FC derivatives amplify pointwise noise by about n^2).
+__global__ void __launch_bounds__(kBlock) k_theta(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
+                                                  const float* u, long long pl, double g1, double th_ref, float* th) {
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long g = P.off + k;
+    const double rho = u[g], m = u[pl + g], n = u[2 * pl + g], E = u[3 * pl + g];
+    th[g] = (float)(g1 * (E - 0.5 * (m * m + n * n) / rho) / rho - th_ref);
+  });
+}
+
+// d[3] = A d[0] + B dth + Cx d[1] + Cy d[2] at the chunks' points (d: the
+// four derivative planes of one direction).
+__global__ void __launch_bounds__(kBlock) k_energy_rule(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
+                                                        const float* u, long long pl, float g1, const float* dth,
+                                                        float* d) {
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long g = P.off + k;
+    const float rho = u[g], m = u[pl + g], n = u[2 * pl + g], E = u[3 * pl + g];
+    const float ir = 1.0f / rho;
+    const float A = E * ir - (m * m + n * n) * ir * ir, B = rho / g1;
+    d[3 * pl + g] = A * d[g] + B * dth[g] + m * ir * d[pl + g] + n * ir * d[2 * pl + g];
+  });
+}
+
+// Transpose of k_energy_rule at u with the forward derivatives d (lanes
+// 0..2) and dth: G (the four cotangent planes of d) gets A, Cx, Cy times
+// G[3] on lanes 0..2 and G[3] = 0, tb = B G[3] (theta's lane), and ub the
+// rule's coefficients' derivatives in (rho, m_x, m_y, E) times G[3].
+__global__ void __launch_bounds__(kBlock) k_energy_rule_adj(const ChunkDev* chunks, int nchunks,
+                                                            const PatchDev* patches, const float* u, long long pl,
+                                                            float g1, const float* d, const float* dth, float* G,
+                                                            float* tb, float* ub) {
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long g = P.off + k;
+    const float rho = u[g], m = u[pl + g], n = u[2 * pl + g], E = u[3 * pl + g];
+    const float ir = 1.0f / rho, ir2 = ir * ir, q = m * m + n * n;
+    const float gE = G[3 * pl + g];
+    const float dr = d[g], dm = d[pl + g], dn = d[2 * pl + g], dt = dth[g];
+    const float A = E * ir - q * ir2, B = rho / g1;
+    G[g] += A * gE;
+    G[pl + g] += m * ir * gE;
+    G[2 * pl + g] += n * ir * gE;
+    G[3 * pl + g] = 0.f;
+    tb[g] = B * gE;
+    // d/d(rho, m, n, E) of A dr + B dt + (m dm + n dn) / rho
+    ub[g] += gE * ((-E * ir2 + 2.f * q * ir2 * ir) * dr + dt / g1 - (m * dm + n * dn) * ir2);
+    ub[pl + g] += gE * (-2.f * m * ir2 * dr + dm * ir);
+    ub[2 * pl + g] += gE * (-2.f * n * ir2 * dr + dn * ir);
+    ub[3 * pl + g] += gE * ir * dr;
+  });
+}
+
+// ub += (d theta / d e)^T thb at the chunks' points.
+__global__ void __launch_bounds__(kBlock) k_theta_adj(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
+                                                      const float* u, long long pl, float g1, const float* thb,
+                                                      float* ub) {
+  for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
+    const PatchDev P = patches[ck.patch];
+    const int k = ck.start + threadIdx.x;
+    int i, j;
+    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+    const long long g = P.off + k;
+    const float rho = u[g], m = u[pl + g], n = u[2 * pl + g], E = u[3 * pl + g];
+    const float tk = thb[g] * g1, ir = 1.0f / rho, ir2 = ir * ir;
+    ub[g] += tk * (-E * ir2 + (m * m + n * n) * ir2 * ir);
+    ub[pl + g] -= tk * m * ir2;
+    ub[2 * pl + g] -= tk * n * ir2;
+    ub[3 * pl + g] += tk * ir;
+  });
 }
 
 // lattice of the smoothing-blending operator: independent patches are their

@@ -908,6 +908,122 @@ def test_steps_with_cylinder_wall(env, layout):
     s.close()
 
 
+@pytest.mark.parametrize("flags", [(1, 1, 1, 1), (1, 0, 1, 0), (0, 1, 1, 1)])
+def test_corner_walls_glue_and_transpose(env, flags):
+    """Walls that meet at patch corners (the corner's theta from the tensor
+    product of the two one-sided Neumann values): fcsd_glue against the
+    oracle's wall condition, and fcsd_glue_adj at the glued state against
+    the oracle's transpose."""
+    import dataclasses
+    from oracle import adjoint
+    api, ctx, torch = env
+    ps = dataclasses.replace(synth.unit_square(37), wall=np.array([flags], np.uint8))   # L = 64
+    s, D, H = mkset(api, ctx, ps, 1)
+    s.set_walls(ps.wall, G)
+    rng = np.random.default_rng(41)
+    x = noisy_state(ps, smooth_state(ps), 42, amp=1e-2)
+    xd = D(x)
+    api.fcsd_glue(s, xd)
+    got = H(xd).reshape(4, -1)
+    want = x.astype(np.float64).copy()
+    solver.glue(want, ps, 3.0, G)
+    err = np.abs(got - want).max(axis=1) / np.abs(want).max(axis=1)
+    y = rng.standard_normal((4, ps.plane)).astype(np.float32)
+    yd = D(y)
+    api.fcsd_glue_adj(s, yd, glued=xd)
+    wb = y.astype(np.float64).copy()
+    adjoint.glue_vjp(wb, ps, 3.0, G, e_glued=got.astype(np.float64))
+    eb = relerr_phys(ps, H(yd).reshape(4, -1), wb)
+    say("corner walls", flags, "glue max rel", err, "transpose rel L2", eb)
+    # a corner's theta sums (d-1)^2 FP32 temperatures with weights of total
+    # size sum |c_k c_l| = 17 (d = 5): a few 1e-6 of the field there
+    assert np.all(err <= 1e-5) and np.all(eb <= 1e-6)
+    with pytest.raises(api.FcsdError):
+        api.fcsd_glue_adj(s, yd)                        # walls need the glued state
+    s.close()
+
+
+def smooth_state(ps):
+    """A smooth admissible state on any patch set (rho ~ 1, p ~ 1, |u| ~ 0.3)."""
+    x, y = ps.xy
+    rho = 1.0 + 0.1 * np.sin(2 * x + 1) * np.cos(3 * y)
+    u = 0.3 + 0.1 * np.cos(x - 2 * y)
+    v = -0.2 + 0.1 * np.sin(3 * x + y)
+    p = 1.0 + 0.1 * np.cos(2 * x) * np.sin(y + 0.5)
+    e = np.stack([rho, rho * u, rho * v, p / (G - 1) + 0.5 * rho * (u * u + v * v)])
+    out = np.zeros((4, ps.plane), np.float32)
+    for q in range(ps.npatch):
+        ps.view(out, q)[...] = ps.view(e, q)
+    return out
+
+
+def wall_layer_state(ps, r0, dr):
+    """smooth_state with a velocity layer two cells thick at the circle r = r0
+    (the velocity falls to zero there): under-resolved enough that the
+    energy's product rule differs from the plain FC derivative far beyond
+    FP32 rounding, at a low Mach number where the energy lane is well
+    conditioned."""
+    x, y = ps.xy
+    layer = 1.0 - np.exp(-(np.hypot(x, y) - r0) / (2.0 * dr))
+    rho = 1.0 + 0.1 * np.sin(2 * x + 1) * np.cos(3 * y)
+    u = (0.3 + 0.1 * np.cos(x - 2 * y)) * layer
+    v = (-0.2 + 0.1 * np.sin(3 * x + y)) * layer
+    p = 1.0 + 0.1 * np.cos(2 * x) * np.sin(y + 0.5)
+    e = np.stack([rho, rho * u, rho * v, p / (G - 1) + 0.5 * rho * (u * u + v * v)])
+    out = np.zeros((4, ps.plane), np.float32)
+    for q in range(ps.npatch):
+        ps.view(out, q)[...] = ps.view(e, q)
+    return out
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rhs_with_wall_patches(env, layout):
+    """The full right-hand side and its reverse mode on the annulus whose
+    inner circle is a wall: on the wall patches the energy's derivatives
+    come from the product rule over theta's FC derivatives (Remark
+    adiabatic).  Against the oracle at the RHS / reverse bars, on a state
+    with a thin velocity layer at the wall, where the rule changes the
+    result by far more than the error."""
+    api, ctx, torch = env
+    cfg = synth.with_cylinder_wall(synth.config(1, n=48))
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, layout)
+    s.set_walls(ps.wall, G)
+    wall_r = min(np.hypot(*[ps.view(c, q) for c in ps.xy]).min() for q in range(ps.npatch) if ps.wall[q].any())
+    x32 = wall_layer_state(ps, wall_r, 1.5 / 47)          # the annulus' radial spacing: 1.5 over 47 cells
+    ref = (1.0, 0.3, -0.2, 1.0)
+    mu = (0.004 * (1.2 + np.sin(3 * ps.xy[0]) * np.cos(2 * ps.xy[1]))).astype(np.float32)
+    rhs = torch.zeros(4 * s.plane, device="cuda:0")
+    api.fcsd_rhs(s, D(x32), D(ps.metric), D(mu), ref, G, rhs)
+    want = euler.full_rhs(x32.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G)
+    err = relerr_phys(ps, H(rhs), want)
+    mx = maxrel_phys(ps, H(rhs), want)
+    import dataclasses
+    plain = euler.full_rhs(x32.astype(np.float64), ps.metric, mu.astype(np.float64),
+                           dataclasses.replace(ps, wall=None), G)
+    effect = relerr_phys(ps, plain, want)
+    # the layer makes the lanes ill conditioned: the bar per lane is the
+    # larger of the RHS bar and the exact result's response to FP32 rounding
+    # of the input (a relative 2^-24 perturbation, seeded)
+    rng = np.random.default_rng(45)
+    xp = x32.astype(np.float64) * (1 + 2.0 ** -24 * rng.choice((-1.0, 1.0), x32.shape))
+    sens = relerr_phys(ps, euler.full_rhs(xp, ps.metric, mu.astype(np.float64), ps, G), want)
+    bar = np.maximum(RHS_TOL, sens)
+    rb = smooth_fields(ps, 4, 44)
+    ub = torch.zeros(4 * s.plane, device="cuda:0")
+    mb = torch.zeros(s.plane, device="cuda:0")
+    api.fcsd_rhs_adj(s, D(x32), D(ps.metric), D(mu), ref, G, D(rb), ub, mb)
+    we, wm = euler.full_rhs_vjp(x32.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G,
+                                rb.astype(np.float64))
+    e1, e2 = relerr_phys(ps, H(ub), we), relerr(ps, H(mb), wm)
+    say("rhs with wall patches layout", layout, "rel L2", err, "max", mx, "bar", bar, "rule's effect", effect,
+        "| reverse", e1, e2)
+    assert np.all(err < bar) and np.all(mx < PT * bar)
+    assert effect[3] > 20 * err[3]
+    assert np.all(e1 < ADJ_TOL) and e2[0] < ADJ_TOL
+    s.close()
+
+
 def test_step_reverse_mode_with_cylinder_wall(env):
     """One network step's reverse mode with the cylinder wall against the
     oracle's step VJP at the GPU's decisions (relative L2 <= 1e-4)."""
