@@ -76,7 +76,11 @@ def recorded_traffic(kernel, npts):
 # again (FP32)
 FILTER_BYTES = 64
 
-PASS_KERNEL = {"A": "k_dev_diff<1>", "B1": "k_passB1", "B2": "k_passB2", "C": "k_passC"}
+PASS_KERNEL = {"A": "k_dev_diff<1>", "B1": "k_passB1", "B2": "k_passB2", "C": "k_passC", "Bf": "k_passB",
+               "stage": "k_stage"}
+# passes of a stage under each schedule (Bf: passes B1 and B2 in one launch)
+SCHED_PASSES = {"split": ["A", "B1", "B2", "C"], "fused": ["A", "Bf", "C"], "persistent": ["A", "Bf", "C"]}
+SCHED_ID = {"split": 0, "fused": 1, "persistent": 2}
 
 
 def pass_bytes(stage):
@@ -86,7 +90,8 @@ def pass_bytes(stage):
     r2 (16), metric q1 row (8), register reads/writes of the stage."""
     rk_read = {0: 16, 1: 32, 2: 32, 3: 48, 4: 32}[stage]
     rk_write = {0: 16, 1: 16, 2: 32, 3: 32, 4: 16}[stage]
-    return {"A": 32, "B1": 84, "B2": 56, "C": 32 + 16 + 8 + rk_read + rk_write}
+    # Bf: read e, d1e, metric, mu (52), write H (32) and r2 (16)
+    return {"A": 32, "B1": 84, "B2": 56, "C": 32 + 16 + 8 + rk_read + rk_write, "Bf": 100}
 
 
 def _cpu_model():
@@ -228,8 +233,8 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=8, help="steps of the timed reverse sweep (0: skip)")
     ap.add_argument("--adj-every", type=int, default=4, help="checkpoint spacing of the reverse sweep")
     ap.add_argument("--schedule", default="auto",
-                    help="auto (autotuner) or B_q1,B_q2,B_q2wide,T_q1,T_q2,T_q2wide,lpt|xcd (LDS budgets in "
-                         "bytes, workgroup sizes)")
+                    help="auto (autotuner) or B_q1,B_q2,B_q2wide,T_q1,T_q2,T_q2wide,lpt|xcd[,split|fused|"
+                         "persistent] (LDS budgets in bytes, workgroup sizes, launch order, stage schedule)")
     ap.add_argument("--oracle-configs", action="store_true",
                     help="only time the FP64 oracle on the host: the 64 x 64 square for its 10 steps and the "
                          "64-patch annulus (16.8 M points) for one step, one process; prints one JSON line")
@@ -272,8 +277,14 @@ def main():
         # B0,B1,B2,T0,T1,T2,ORDER: LDS budgets and workgroup sizes of the three tile sets
         f = args.schedule.split(",")
         bud, thr, order = [int(x) for x in f[0:3]], [int(x) for x in f[3:6]], f[6]
+        sched = f[7] if len(f) > 7 else "fused"
         s.tune(bud, thr, {"lpt": 0, "xcd": 1}[order])
-        tuning = {"budgets": bud, "threads": thr, "order": order, "given": True}
+        s.set_schedule(SCHED_ID[sched])
+        tuning = {"budgets": bud, "threads": thr, "order": order, "schedule": sched, "given": True}
+
+    def apply_tuning(ss):
+        ss.tune(tuning["budgets"], tuning["threads"], {"lpt": 0, "xcd": 1}[tuning["order"]])
+        ss.set_schedule(SCHED_ID[tuning["schedule"]])
     st = api.Stepper(s, u, metric, cfg.ref, W=W)
 
     # ---------------- full step, graph replay
@@ -322,17 +333,28 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     ms_batched = time_stages(False, 3)
+    # the same stages under each schedule at the chosen tiling
+    sched_ms = {}
+    for name, sid in SCHED_ID.items():
+        try:
+            s.set_schedule(sid)
+        except api.FcsdError:
+            sched_ms[name] = None
+            continue
+        sched_ms[name] = time_stages(False, 3) / 5
+    s.set_schedule(SCHED_ID[tuning["schedule"]])
+    stage_errors = s.stage_errors()
     ms_pp = None if args.no_per_patch else time_stages(True, 2)
 
     # ---------------- per-pass timing (dominant kernel), every pass at each
     # of the five stages (pass C's register traffic depends on the stage)
-    names = ["A", "B1", "B2", "C"]
+    names = ["A", "B1", "B2", "C", "Bf"]
     passes, pass_gb = {}, {}
     for pid, name in enumerate(names):
         tot_ms, tot_bytes = 0.0, 0.0
         for stage in range(5):
             # prerequisites so every pass reads defined data
-            for q in range(pid + 1):
+            for q in range(min(pid + 1, 4)):
                 api.fcsd_stage_pass(s, q, stage, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -346,9 +368,16 @@ def main():
             tot_bytes += pass_bytes(stage)[name] * npts
         passes[name] = tot_ms / 5
         pass_gb[name] = tot_bytes / 5 / 1e9
-    dom = max(passes, key=passes.get)
+    used = SCHED_PASSES[tuning["schedule"]]
+    if tuning["schedule"] == "persistent":
+        # one kernel per stage: its bytes are those of its passes, its time the stage's
+        passes["stage"] = ms_batched / 5
+        pass_gb["stage"] = sum(pass_gb[n] for n in used)
+        dom = "stage"
+    else:
+        dom = max(used, key=passes.get)
     achieved = pass_gb[dom] / (passes[dom] / 1e3)
-    stage_bytes = sum(pass_gb.values()) * 1e9 / npts
+    stage_bytes = sum(pass_gb[n] for n in used) * 1e9 / npts
     traffic = recorded_traffic(PASS_KERNEL[dom], npts)
 
     # ---------------- per-step spectral filter (paper Sec. 4.3.1, alpha 10,
@@ -407,7 +436,7 @@ def main():
         pc = synth.with_cylinder_wall(synth.paper_subpatches(48, 32))
         pps = pc.ps
         s2 = api.PatchSet.from_layout(ctx, pps, layout)
-        s2.tune(tuning["budgets"], tuning["threads"], {"lpt": 0, "xcd": 1}[tuning["order"]])
+        apply_tuning(s2)
         s2.set_walls(pps.wall, 1.4)
         u2 = s2.to_device(pc.u0)
         st2 = api.Stepper(s2, u2, s2.to_device(pps.metric), pc.ref, W={k: t(v) for k, v in pc.mlp.items()},
@@ -438,7 +467,7 @@ def main():
         oc = synth.overlap_config(1024, network=True)
         ops = oc.ps
         s3 = api.PatchSet.from_layout(ctx, ops, layout)
-        s3.tune(tuning["budgets"], tuning["threads"], {"lpt": 0, "xcd": 1}[tuning["order"]])
+        apply_tuning(s3)
         nrecv = s3.set_interp(ops.geom)
         u3 = s3.to_device(oc.u0)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -472,7 +501,7 @@ def main():
         torch.cuda.synchronize()
         mem0 = torch.cuda.memory_allocated()      # buffers of the other workloads still held
         s4 = api.PatchSet.from_layout(ctx, ps4, layout)
-        s4.tune(tuning["budgets"], tuning["threads"], {"lpt": 0, "xcd": 1}[tuning["order"]])
+        apply_tuning(s4)
         u4 = s4.to_device(c4.u0)
         st4 = api.Stepper(s4, u4, s4.to_device(ps4.metric), c4.ref, W={k: t(v) for k, v in c4.mlp.items()},
                           dirichlet_mask=s4.to_device(ps4.dirichlet), dirichlet_state=synth.freestream(c4.mach))
@@ -559,7 +588,8 @@ def main():
                      "note": "achieved = algorithmic bytes of the kernel averaged over the five stages / "
                              "its mean launch time (HIP events on the library stream)"},
         "stage_ms": {"batched": ms_batched / 5, "per_patch": None if ms_pp is None else ms_pp / 5,
-                     "batched_over_per_patch": None if ms_pp is None else ms_pp / ms_batched},
+                     "batched_over_per_patch": None if ms_pp is None else ms_pp / ms_batched,
+                     "by_schedule": sched_ms, "persistent_wait_errors": stage_errors},
         "pass_ms": passes,
         "adjoint": adjoint,
         "filter": filt,

@@ -127,6 +127,32 @@ enum {
  * an out-of-range argument.  Used by the autotuner. */
 fcsd_status fcsd_set_tune(fcsd_set* set, const int lds_budget[3], const int threads[3], int order);
 
+/* How the line passes of one right-hand side or stage are launched (the
+ * schedule of the four passes A, B1, B2, C of the chain-rule right-hand
+ * side, Sec. 3.3, eq. general_curvilinear; every schedule gives the same
+ * results bit for bit). */
+enum {
+  FCSD_SCHED_SPLIT = 0,      /* four launches: A, B1, B2, C */
+  FCSD_SCHED_FUSED = 1,      /* three launches: A, B1 + B2 on one q2 tile, C (the default) */
+  FCSD_SCHED_PERSISTENT = 2  /* one launch per stage: resident workgroups take A, B and C
+                                tiles from a queue; a B tile starts once its patch's A
+                                tiles are done, a C tile once its patch's B tiles are */
+};
+/* Select the schedule of `set` for fcsd_rhs, fcsd_stage and fcsd_step (the
+ * per-patch and per-pass entry points always launch the passes one by one).
+ * The persistent schedule uses the q1 tile set's workgroup size for every
+ * task and the larger of the two tile sets' LDS plus 16 bytes (the queue
+ * slot); it needs that to fit the device's LDS per workgroup (budgets of at
+ * most 160 KB - 16), else FCSD_EINVAL.  It is used for every stage of sets
+ * without wall sides; stages of sets with walls (whose energy rule runs
+ * between passes A and B) fall back to the fused schedule.  A dependency
+ * wait that gives up (never expected: it would take about a second) sets
+ * bit 0 of the word fcsd_stage_errors reads.  Synchronises the context's
+ * stream and drops captured step graphs. */
+fcsd_status fcsd_set_schedule(fcsd_set* set, int schedule);
+/* Read and clear the persistent schedule's error word (blocking read). */
+fcsd_status fcsd_stage_errors(fcsd_set* set, int32_t* flags);
+
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
 enum { FCSD_WS_RHS = 0, FCSD_WS_AV = 1, FCSD_WS_STEP = 2, FCSD_WS_RHS_ADJ = 3, FCSD_WS_STEP_ADJ = 4,
        FCSD_WS_FILTER_ADJ = 5, FCSD_WS_SMEAR = 6, FCSD_WS_STAGE_ADJ = 7 };
@@ -444,9 +470,10 @@ fcsd_status fcsd_stage_adj(fcsd_ctx* ctx, const fcsd_set* set, int stage, const 
 
 /* One of the four passes of fcsd_stage (0: q1 derivatives of the state,
  * 1: q2 derivatives and the combined fluxes H, 2: q2 derivatives of H,
- * 3: q1 derivatives of H and the register update), for timing and
- * profiling.  Running passes 0..3 in order equals one fcsd_stage call; with
- * mu == NULL passes 0 and 1 together are the pointwise inviscid H. */
+ * 3: q1 derivatives of H and the register update), or 4: passes 1 and 2 in
+ * one launch (the fused schedule's q2 pass), for timing and profiling.
+ * Running passes 0..3 (or 0, 4, 3) in order equals one fcsd_stage call;
+ * with mu == NULL passes 0 and 1 together are the pointwise inviscid H. */
 fcsd_status fcsd_stage_pass(fcsd_ctx* ctx, const fcsd_set* set, int pass, int stage, const float* u0,
                             const float* ui, float* acc, float* uout, const float* metric,
                             const float* mu, const float ref[4], float gamma, const float* dt_dev,

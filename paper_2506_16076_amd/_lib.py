@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfcsdnn.so")
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EHIP", 5: "EUNSUPPORTED", 6: "ENONFINITE"}
 WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR, WS_STAGE_ADJ = 0, 1, 2, 3, 4, 5, 6, 7
 LAYOUT_ROWS, LAYOUT_B8X4 = 0, 1
+SCHED_SPLIT, SCHED_FUSED, SCHED_PERSISTENT = 0, 1, 2
 
 
 def blocked_layout(n1, n2, base_off=None):
@@ -98,6 +99,8 @@ def lib():
             "fcsd_set_create": [vp, i32, P(PatchDesc), i32, i64, i32, i32, i32, P(vp)],
             "fcsd_set_destroy": [vp],
             "fcsd_set_tune": [vp, P(i32), P(i32), i32],
+            "fcsd_set_schedule": [vp, i32],
+            "fcsd_stage_errors": [vp, P(ctypes.c_int32)],
             "fcsd_set_filter": [vp, ctypes.c_double, i32],
             "fcsd_filter": [vp, vp, vp, vp, i64, f32],
             "fcsd_set_interp": [vp, vp, i32, P(i64)],
@@ -154,6 +157,7 @@ def lib():
 # the names every header declaration exports (checked by the CPU tests)
 EXPORTS = ["fcsd_ctx_create", "fcsd_ctx_destroy", "fcsd_ctx_set_stream", "fcsd_last_error",
            "fcsd_ctx_stream", "fcsd_ctx_sync", "fcsd_set_create", "fcsd_set_destroy", "fcsd_set_tune",
+           "fcsd_set_schedule", "fcsd_stage_errors",
            "fcsd_set_filter", "fcsd_filter", "fcsd_filter_adj", "fcsd_smear", "fcsd_set_interp", "fcsd_set_walls",
            "fcsd_workspace_size", "fcsd_ext_size", "fc_continue", "fc_continue_adj", "fc_diff",
            "fc_diff_adj", "euler_rhs", "av_apply", "fcsd_rhs", "fcsd_rhs_adj", "euler_rhs_adj", "av_apply_adj",

@@ -76,6 +76,7 @@ class PatchSet:
         self.h = h
         self._ws = {}
         self._map = None
+        self.schedule = 1    # the library's default: SCHED_FUSED
 
     @classmethod
     def from_layout(cls, ctx, ps, layout: int = LAYOUT_ROWS):
@@ -151,6 +152,22 @@ class PatchSet:
         t = (ctypes.c_int * 3)(*[int(x) for x in threads])
         self.ctx.check(lib().fcsd_set_tune(self.h, b, t, int(order)), "fcsd_set_tune")
         self.tuning = (tuple(int(x) for x in budgets), tuple(int(x) for x in threads), int(order))
+
+    SCHED_SPLIT, SCHED_FUSED, SCHED_PERSISTENT = 0, 1, 2
+
+    def set_schedule(self, schedule: int):
+        """Launch schedule of a stage's line passes: SCHED_SPLIT (four
+        launches), SCHED_FUSED (three: passes B1 and B2 on one q2 tile) or
+        SCHED_PERSISTENT (one launch per stage taking tiles from a queue)."""
+        self.ctx.check(lib().fcsd_set_schedule(self.h, int(schedule)), "fcsd_set_schedule")
+        self.schedule = int(schedule)
+
+    def stage_errors(self) -> int:
+        """Read and clear the persistent schedule's error word (bit 0: a
+        dependency wait gave up)."""
+        v = ctypes.c_int32(0)
+        self.ctx.check(lib().fcsd_stage_errors(self.h, ctypes.byref(v)), "fcsd_stage_errors")
+        return int(v.value)
 
     def set_filter(self, alpha: float = 10.0, p: int = 14):
         """Parameters of the spectral filter (paper Sec. 4.3.1): factors

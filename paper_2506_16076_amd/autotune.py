@@ -1,15 +1,20 @@
 """Autotuner of the batched line-tile schedule.
 
 The tile split of a patch set decides how many lines share a workgroup,
-the workgroup size how many threads work on each line, and the launch order
-which die (L2) runs which tiles.  Results do not depend on any of them:
-every line is transformed by the same arithmetic whatever its tile.  There
-are three tile sets -- q1 lines (passes A, C), q2 lines (pass B2), q2 lines
-with two complex lines per grid line (pass B1) -- each with its own LDS
-budget and workgroup size.  The tuner times the four passes of one stage
-through fcsd_stage_pass with HIP events on the library's stream for every
-(budget, workgroup size) candidate under each launch order, picks the best
-candidate per tile set and keeps the order with the smallest stage time.
+the workgroup size how many threads work on each line, the launch order
+which die (L2) runs which tiles, and the stage schedule how the passes are
+launched (four launches, three with passes B1 and B2 fused on one q2 tile,
+or one persistent launch per stage).  Results do not depend on any of them:
+every line is transformed by the same arithmetic whatever its tile and
+launch.  There are three tile sets -- q1 lines (passes A, C), q2 lines
+(pass B2), q2 lines with two complex lines per grid line (passes B1 and the
+fused B) -- each with its own LDS budget and workgroup size.  The tuner
+times the passes of one stage through fcsd_stage_pass with HIP events on
+the library's stream for every (budget, workgroup size) candidate under each
+launch order, picks the best candidate per tile set for the split and the
+fused schedules, times whole stages of both and of persistent candidates
+(one workgroup size and budgets that leave room for the queue slot), and
+keeps the fastest.
 """
 from __future__ import annotations
 
@@ -18,6 +23,8 @@ import torch
 from . import api
 
 SET_PASSES = ((0, 3), (2,), (1,))   # tile set -> passes timed (A+C, B2, B1)
+FUSED_PASSES = ((0, 3), (2,), (4,))  # the same with the fused B pass on the third set
+PERSISTENT_BUDGET = 163840 - 256    # leaves room for the persistent kernel's queue slot
 DEFAULT_BUDGETS = (24576, 32768, 49152, 65536, 81920, 98304, 131072, 163840)
 DEFAULT_THREADS = (256, 512, 1024)
 
@@ -43,8 +50,24 @@ def time_passes(s, bufs, passes, reps=3):
     return out
 
 
+def time_stage(s, bufs, reps=3):
+    """Mean milliseconds of one whole stage (stage 1) under the set's
+    current schedule."""
+    u0, ui, acc, uout, metric, mu, ref, gamma, dt = bufs
+    ctx = s.ctx
+    api.fcsd_stage(s, 1, u0, ui, acc, uout, metric, mu, ref, gamma, dt)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    for _ in range(reps):
+        api.fcsd_stage(s, 1, u0, ui, acc, uout, metric, mu, ref, gamma, dt)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS, threads=DEFAULT_THREADS,
-             orders=(api.PatchSet.ORDER_LPT, api.PatchSet.ORDER_XCD), reps=3):
+             orders=(api.PatchSet.ORDER_LPT, api.PatchSet.ORDER_XCD), reps=3, schedules=(0, 1, 2)):
     """Choose the schedule of patch set `s` on state `u`; applies the choice
     and returns it with the timing table."""
     dev = u.device
@@ -66,20 +89,43 @@ def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS,
     for order in orders:
         for (b, t) in cands:
             s.tune(b, t, order)
-            table[(order, b, t)] = time_passes(s, bufs, (0, 1, 2, 3), reps)
-    best = None
+            table[(order, b, t)] = time_passes(s, bufs, (0, 1, 2, 3, 4), reps)
+    # per-set picks of the split and fused schedules under each order, then
+    # whole stages of each pick and of the persistent candidates
+    stage = []   # (ms, schedule, budgets, threads, order)
     for order in orders:
-        pick, ms = [], 0.0
-        for passes in SET_PASSES:
-            c = min(cands, key=lambda bt: sum(table[(order,) + bt][p] for p in passes))
-            pick.append(c)
-            ms += sum(table[(order,) + c][p] for p in passes)
-        if best is None or ms < best[2]:
-            best = (pick, order, ms)
-    pick, order, ms = best
-    s.tune([c[0] for c in pick], [c[1] for c in pick], order)
-    return {"budgets": [c[0] for c in pick], "threads": [c[1] for c in pick],
-            "order": "xcd" if order else "lpt", "stage_passes_ms": ms,
-            "table": {f"{'xcd' if o else 'lpt'}-{b // 1024}K-{t}": {["A", "B1", "B2", "C"][p]: round(v, 4)
+        for sched, set_passes in ((0, SET_PASSES), (1, FUSED_PASSES)):
+            if sched not in schedules:
+                continue
+            pick = [min(cands, key=lambda bt: sum(table[(order,) + bt][p] for p in passes))
+                    for passes in set_passes]
+            bud, thr = [c[0] for c in pick], [c[1] for c in pick]
+            s.tune(bud, thr, order)
+            s.set_schedule(sched)
+            stage.append((time_stage(s, bufs, reps), sched, bud, thr, order))
+        if 2 in schedules:
+            # one workgroup size for every task of the launch; budgets of the
+            # fused pick, capped for the queue slot, and uniform ones
+            fb = stage[-1][2] if 1 in schedules else [max(budgets)] * 3
+            pers = {tuple(min(b, PERSISTENT_BUDGET) for b in fb)} | \
+                {(b, b, b) for b in budgets if 65536 <= b <= PERSISTENT_BUDGET}
+            pthreads = [t for t in threads if t >= 512] or [max(threads)]
+            for bud in sorted(pers):
+                for t in pthreads:
+                    try:
+                        s.tune(list(bud), [t] * 3, order)
+                        s.set_schedule(2)
+                    except api.FcsdError:
+                        continue
+                    stage.append((time_stage(s, bufs, reps), 2, list(bud), [t] * 3, order))
+    ms, sched, bud, thr, order = min(stage, key=lambda r: r[0])
+    s.tune(bud, thr, order)
+    s.set_schedule(sched)
+    names = ["split", "fused", "persistent"]
+    return {"budgets": bud, "threads": thr, "order": "xcd" if order else "lpt", "schedule": names[sched],
+            "stage_ms": ms,
+            "stages": [{"ms": round(r[0], 4), "schedule": names[r[1]], "budgets": r[2], "threads": r[3],
+                        "order": "xcd" if r[4] else "lpt"} for r in stage],
+            "table": {f"{'xcd' if o else 'lpt'}-{b // 1024}K-{t}": {["A", "B1", "B2", "C", "Bf"][p]: round(v, 4)
                                                                    for p, v in tm.items()}
                       for (o, b, t), tm in table.items()}}

@@ -161,6 +161,17 @@ struct fcsd_set {
   int layout = FCSD_LAYOUT_ROWS;
 
   int tile_order = FCSD_ORDER_XCD;
+
+  // schedule of a stage's line passes (FCSD_SCHED_*) and the persistent
+  // stage kernel's task queue
+  int schedule = FCSD_SCHED_FUSED;
+  int2* d_tasks = nullptr;
+  int ntasks = 0;
+  unsigned* d_ctr = nullptr;              // queue head, 2 npatch counters, then the error word
+  unsigned* d_need = nullptr;             // 2 npatch: A tiles, B tiles per patch
+  unsigned stage_grid = 0;                // resident workgroups of the persistent launch
+  size_t stage_lds = 0;
+  int stage_threads = 0;
 };
 
 namespace {
@@ -533,6 +544,73 @@ fcsd_status upload_tiles(fcsd_ctx* ctx, DirPlan& D) {
   return FCSD_OK;
 }
 
+// Task queue of the persistent stage kernel from the current tile sets:
+// every A task (q1 tiles in launch order), then the B tasks (q2 tiles with
+// two complex lines per grid line) patch by patch in the order in which the
+// patches' last A tasks stand in the queue, then the C tasks (q1 tiles)
+// patch by patch in the order of the patches' last B tasks, so that the
+// tasks taken first are the ones whose inputs are done first.  Also the
+// per-patch tile counts, the counters and the launch shape.
+fcsd_status build_stage_tasks(fcsd_set* s) {
+  fcsd_ctx* ctx = s->ctx;
+  const int np = s->npatch;
+  const TileSet& TA = s->dir[0].ts[0];
+  const TileSet& TB = s->dir[1].ts[1];
+  std::vector<int2> tasks;
+  std::vector<unsigned> need(2 * (size_t)np, 0u);
+  std::vector<long long> lastA(np, -1), lastB(np, -1);
+  for (size_t i = 0; i < TA.tiles.size(); ++i) {
+    const TileDev& T = TA.tiles[i];
+    if (T.nl == 0) continue;
+    lastA[T.plan] = (long long)tasks.size();
+    ++need[T.plan];
+    tasks.push_back(make_int2(TASK_A, (int)i));
+  }
+  auto by_last = [&](const std::vector<long long>& last) {
+    std::vector<int> ord(np);
+    for (int p = 0; p < np; ++p) ord[p] = p;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return last[a] < last[b]; });
+    return ord;
+  };
+  std::vector<std::vector<int>> tb(np), ta(np);
+  for (size_t i = 0; i < TB.tiles.size(); ++i)
+    if (TB.tiles[i].nl > 0) tb[TB.tiles[i].plan].push_back((int)i);
+  for (size_t i = 0; i < TA.tiles.size(); ++i)
+    if (TA.tiles[i].nl > 0) ta[TA.tiles[i].plan].push_back((int)i);
+  for (int p : by_last(lastA))
+    for (int i : tb[p]) {
+      lastB[p] = (long long)tasks.size();
+      ++need[np + p];
+      tasks.push_back(make_int2(TASK_B, i));
+    }
+  for (int p : by_last(lastB))
+    for (int i : ta[p]) tasks.push_back(make_int2(TASK_C, i));
+  (void)hipFree(s->d_tasks);
+  (void)hipFree(s->d_need);
+  s->d_tasks = nullptr;
+  s->d_need = nullptr;
+  fcsd_status r;
+  if ((r = upload(ctx, &s->d_tasks, tasks)) || (r = upload(ctx, &s->d_need, need))) return r;
+  s->ntasks = (int)tasks.size();
+  if (!s->d_ctr) {
+    const size_t words = 2 + 2 * (size_t)np;
+    HIPCHK(ctx, hipMalloc(&s->d_ctr, words * sizeof(unsigned)));
+    HIPCHK(ctx, hipMemset(s->d_ctr, 0, words * sizeof(unsigned)));
+  }
+  // launch shape: the q1 set's workgroup size, the larger LDS of the two
+  // sets plus the queue slot, as many workgroups as can be resident
+  s->stage_threads = TA.threads;
+  s->stage_lds = std::max(TA.lds, TB.lds) + 16;
+  s->stage_grid = 0;
+  int maxlds = 0, ncu = 0, per_cu = 0;
+  HIPCHK(ctx, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+  if (s->stage_lds > (size_t)maxlds) return FCSD_OK;  // the persistent schedule cannot run with these tiles
+  HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage, s->stage_threads, s->stage_lds));
+  s->stage_grid = (unsigned)std::max(0, std::min(s->ntasks, per_cu * ncu));
+  return FCSD_OK;
+}
+
 }  // namespace
 
 // ======================================================================== patch set
@@ -702,6 +780,7 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
         (r = upload(ctx, &D.d_ext_off, D.ext_off)))
       return r;
   }
+  if ((r = build_stage_tasks(s.get()))) return r;
   HIPCHK(ctx, hipDeviceSynchronize());
   *out = s.release();
   return FCSD_OK;
@@ -744,6 +823,9 @@ extern "C" fcsd_status fcsd_set_destroy(fcsd_set* s) {
   hipFree(s->d_lats);
   hipFree(s->d_lchunks);
   hipFree(s->d_ltiles);
+  hipFree(s->d_tasks);
+  hipFree(s->d_need);
+  hipFree(s->d_ctr);
   delete s;
   return FCSD_OK;
 }
@@ -783,7 +865,38 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const
     build_tiles(D, order, tile_align(s->layout, dir), s->d);
     if ((r = upload_tiles(ctx, D))) return r;
   }
+  if ((r = build_stage_tasks(s))) return r;
+  if (s->schedule == FCSD_SCHED_PERSISTENT && s->stage_grid == 0) s->schedule = FCSD_SCHED_FUSED;
   return rebuild_wall_tiles(s);
+}
+
+extern "C" fcsd_status fcsd_set_schedule(fcsd_set* s, int schedule) {
+  if (!s) return FCSD_EINVAL;
+  fcsd_ctx* ctx = s->ctx;
+  if (schedule != FCSD_SCHED_SPLIT && schedule != FCSD_SCHED_FUSED && schedule != FCSD_SCHED_PERSISTENT)
+    return fail(ctx, FCSD_EINVAL, "fcsd_set_schedule: unknown schedule");
+  if (schedule == FCSD_SCHED_PERSISTENT && s->stage_grid == 0)
+    return fail(ctx, FCSD_EINVAL,
+                "fcsd_set_schedule: the tile sets leave no room for the persistent kernel's queue slot "
+                "(tune LDS budgets to at most 160 KB - 16)");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& g : s->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
+  s->schedule = schedule;
+  return FCSD_OK;
+}
+
+extern "C" fcsd_status fcsd_stage_errors(fcsd_set* s, int32_t* flags) {
+  if (!s || !flags) return FCSD_EINVAL;
+  fcsd_ctx* ctx = s->ctx;
+  unsigned* e = s->d_ctr + 1 + 2 * (size_t)s->npatch;
+  unsigned v = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&v, e, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipMemsetAsync(e, 0, sizeof(v), ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  *flags = (int32_t)v;
+  return FCSD_OK;
 }
 
 extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
@@ -995,26 +1108,71 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
   a.H = W.H;
   a.r2 = W.r2;
   fcsd_status st;
-  if (flux == FLUX_INVISCID && (passes & 3u)) {
-    if (patch < 0) {
-      hipLaunchKernelGGL(k_passH, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, a, (long long)s->plane);
-    } else {
-      const fcsd_patch_desc& q = s->desc[patch];
-      PassArgs b = a;
-      b.u = u + q.off;
-      b.H = W.H + q.off;
-      const long long n = (long long)q.n1 * q.n2;
-      hipLaunchKernelGGL(k_passH, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, b, n);
+  // patches with a wall side: the energy's derivatives by the product rule
+  // from those of rho, m and theta (after pass A for q1, inside B1 for q2)
+  const bool walls = flux != FLUX_INVISCID && s->nwchunks > 0 && (patch < 0 || s->wall_patch[patch]);
+  // passes B1 and B2 in one launch (a whole-set call of the fused or
+  // persistent schedule)
+  // (bit 4 of passes asks for it whatever the schedule)
+  const bool fuse = patch < 0 && (s->schedule != FCSD_SCHED_SPLIT || (passes & 16u)) && (passes & 6u) == 6u;
+  const bool persistent = fuse && passes == 15u && !walls && s->schedule == FCSD_SCHED_PERSISTENT;
+  a.out = W.d1e;
+  PassArgs b = a;
+  b.plans = s->dir[1].d_plans;
+  b.mode = flux;
+  b.d2out = d2e_rec;
+  b.d2th = walls ? s->d_wplanes + 2 * s->plane : nullptr;
+  PassArgs e = a;
+  e.plans = s->dir[0].d_plans;
+  e.mode = outmode;
+  e.rhs = rhs;
+  e.stage = stage;
+  e.u0 = u0;
+  e.ui = u;
+  e.acc = acc;
+  e.uout = uout;
+  e.dt = dtp;
+  if (persistent) {
+    const int np = s->npatch;
+    StageArgs g;
+    g.A = a;
+    g.A.tiles = s->dir[0].ts[0].d_tiles;
+    g.B = b;
+    g.B.tiles = s->dir[1].ts[1].d_tiles;
+    g.C = e;
+    g.C.tiles = s->dir[0].ts[0].d_tiles;
+    g.tasks = s->d_tasks;
+    g.ntasks = s->ntasks;
+    g.npatch = np;
+    g.skipA = flux == FLUX_INVISCID;
+    g.ctr = s->d_ctr;
+    g.need = s->d_need;
+    g.err = s->d_ctr + 1 + 2 * (size_t)np;
+    // counters to zero with a fill kernel (no memset node in a captured step)
+    const long long nw = 1 + 2 * (long long)np;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(nw)), dim3(kBlock), 0, ctx->stream, (float*)s->d_ctr, 0.0f, nw);
+    if ((st = launch_check(ctx, "stage counters"))) return st;
+    hipLaunchKernelGGL(k_stage, dim3(s->stage_grid), dim3(s->stage_threads), s->stage_lds, ctx->stream, g);
+    return launch_check(ctx, "persistent stage");
+  }
+  if (flux == FLUX_INVISCID) {
+    if (!fuse && (passes & 3u)) {
+      if (patch < 0) {
+        hipLaunchKernelGGL(k_passH, dim3(blocks_for(s->plane)), dim3(kBlock), 0, ctx->stream, a,
+                           (long long)s->plane);
+      } else {
+        const fcsd_patch_desc& q = s->desc[patch];
+        PassArgs h = a;
+        h.u = u + q.off;
+        h.H = W.H + q.off;
+        const long long n = (long long)q.n1 * q.n2;
+        hipLaunchKernelGGL(k_passH, dim3(blocks_for(n)), dim3(kBlock), 0, ctx->stream, h, n);
+      }
+      if ((st = launch_check(ctx, "pass H"))) return st;
     }
-    if ((st = launch_check(ctx, "pass H"))) return st;
-  } else if (flux != FLUX_INVISCID) {
-    // patches with a wall side: the energy's derivatives by the product rule
-    // from those of rho, m and theta (after pass A for q1, inside B1 for q2)
-    const bool walls = s->nwchunks > 0 && (patch < 0 || s->wall_patch[patch]);
+  } else {
     if (walls && (passes & 3u))
       if ((st = wall_theta_derivs(ctx, s, u, ref, gamma, patch))) return st;
-    a.plans = s->dir[0].d_plans;
-    a.out = W.d1e;
     if (passes & 1u) {
       if ((st = launch_lines(s, 1, k_dev_diff<1>, a, patch))) return st;
       if (walls) {
@@ -1026,29 +1184,17 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
         if ((st = launch_check(ctx, "energy rule q1"))) return st;
       }
     }
-    PassArgs b = a;
-    b.plans = s->dir[1].d_plans;
-    b.mode = flux;
-    b.d2out = d2e_rec;
-    b.d2th = walls ? s->d_wplanes + 2 * s->plane : nullptr;
-    if (passes & 2u)
+    if ((passes & 2u) && !fuse)
       if ((st = launch_lines(s, 2, k_passB1, b, patch, 2))) return st;
   }
-  PassArgs c = a;
-  c.plans = s->dir[1].d_plans;
-  if (passes & 4u)
+  if (fuse) {
+    if ((st = launch_lines(s, 2, k_passB, b, patch, 2))) return st;
+  } else if (passes & 4u) {
+    PassArgs c = a;
+    c.plans = s->dir[1].d_plans;
     if ((st = launch_lines(s, 2, k_passB2, c, patch))) return st;
+  }
   if (!(passes & 8u)) return FCSD_OK;
-  PassArgs e = a;
-  e.plans = s->dir[0].d_plans;
-  e.mode = outmode;
-  e.rhs = rhs;
-  e.stage = stage;
-  e.u0 = u0;
-  e.ui = u;
-  e.acc = acc;
-  e.uout = uout;
-  e.dt = dtp;
   return launch_lines(s, 1, k_passC, e, patch);
 }
 
@@ -1416,13 +1562,13 @@ extern "C" fcsd_status fcsd_stage_pass(fcsd_ctx* ctx, const fcsd_set* s, int pas
                                        size_t ws_bytes) {
   fcsd_status st = check_set(ctx, s, plane);
   if (st) return st;
-  if (pass < 0 || pass > 3 || stage < 0 || stage > 4 || !u0 || !ui || !uout || !metric || !ref || !dt_dev || !ws ||
+  if (pass < 0 || pass > 4 || stage < 0 || stage > 4 || !u0 || !ui || !uout || !metric || !ref || !dt_dev || !ws ||
       (stage >= 2 && !acc))
     return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: bad arguments");
   if (uout == ui || (uout == u0 && stage != 4)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: output aliases an input");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: workspace too small");
   return rhs_passes(ctx, s, ui, metric, mu, ref, gamma, mu ? FLUX_FULL : FLUX_INVISCID, MODE_RK, nullptr, stage, u0,
-                    acc, uout, dt_dev, ws, -1, 1u << pass);
+                    acc, uout, dt_dev, ws, -1, pass == 4 ? 6u | 16u : 1u << pass);
 }
 
 namespace {

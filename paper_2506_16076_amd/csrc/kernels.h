@@ -132,19 +132,25 @@ __device__ __forceinline__ TileMem tile_mem(const PlanDev& P, const TileDev& T, 
 
 extern __shared__ float2 lds_z[];
 
-// tile prologue common to every line kernel: tile, plan, LDS tables
-#define FCSD_TILE_BEGIN(a)                                                   \
-  const TileDev T = (a).tiles[blockIdx.x];                                   \
-  if (T.nl == 0) return; /* padding slot of the launch order */              \
+// tile prologue common to every line body: tile Tin (nl > 0), plan, LDS
+// tables at lds
+#define FCSD_TILE_AT(a, Tin, lds)                                            \
+  const TileDev T = (Tin);                                                   \
   const PlanDev P = (a).plans[T.plan];                                       \
   const PlanDev* Pg = (a).plans + T.plan;                                    \
-  const LineCtx X = line_setup(lds_z, T, P, (a).tw, (a).km);                 \
+  const LineCtx X = line_setup((lds), T, P, (a).tw, (a).km);                 \
   float2* __restrict__ z = X.z;                                              \
   const int N = P.N, nl = T.nl, ld = T.ld;                                   \
   (void)Pg;                                                                  \
   (void)nl;                                                                  \
   (void)N;                                                                   \
   __syncthreads();
+
+// the same for the tile of this workgroup in a one-tile-per-workgroup launch
+#define FCSD_TILE_BEGIN(a)                                                   \
+  const TileDev T_wg = (a).tiles[blockIdx.x];                                \
+  if (T_wg.nl == 0) return; /* padding slot of the launch order */           \
+  FCSD_TILE_AT(a, T_wg, lds_z)
 
 // Forward derivative of pairs already loaded by load_differenced: tail
 // differences, then the FFT part.
@@ -242,10 +248,11 @@ __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
 
 // ---------------------------------------------------------------- RHS passes
 
-// d_DIR (e - e_ref) of the four state fields into out (pass A for DIR 1).
+// d_DIR (e - e_ref) of the four state fields into out (pass A for DIR 1),
+// on tile Tin with its LDS at lds.
 template <int DIR>
-__global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
-  FCSD_TILE_BEGIN(a)
+__device__ __forceinline__ void dev_diff_tile(const PassArgs& a, const TileDev& Tin, float2* lds) {
+  FCSD_TILE_AT(a, Tin, lds)
   const TileMem M = tile_mem<DIR>(P, T, nl, ld);
   const long long pl = a.plane;
   for (int f = 0; f < 4; f += 2) {
@@ -264,6 +271,13 @@ __global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
     });
     __syncthreads();
   }
+}
+
+template <int DIR>
+__global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  dev_diff_tile<DIR>(a, T, lds_z);
 }
 
 // Point inputs of all eight H fields (loaded once per point; inputs a flux
@@ -330,29 +344,38 @@ __device__ __forceinline__ HIn4 load_H4_inputs(const HSrc& h, unsigned g) {
 // lines per grid line: components 0,1 at z[pos][c], 2,3 at z[pos][nl + c]),
 // then H = mu grad_x e - f' (mode FLUX_FULL / FLUX_VISC).  H layout: field
 // 2c = H_x component c, 2c+1 = H_y component c.
-__global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
-  const TileDev T = a.tiles[blockIdx.x];
-  if (T.nl == 0) return;
+// FUSED: passes B1 and B2 on one tile.  The H epilogue also leaves
+// (H_x, H_y) of components 0 and 1 in LDS as the two complex lines of every
+// grid line, which are differenced and transformed in place; components 2
+// and 3 are then read back from the H this workgroup has just stored (the
+// barrier orders the stores before the loads), and r2_c = m2x d2 H_x,c +
+// m2y d2 H_y,c is stored for all four.  The result equals passes B1 and B2
+// bit for bit (the same FP32 operations on every line).  With FLUX_INVISCID
+// the first transform is skipped and H = -f'.
+template <bool FUSED>
+__device__ __forceinline__ void passB_tile(const PassArgs& a, const TileDev& T, float2* lds) {
   const PlanDev P = a.plans[T.plan];
   const PlanDev* Pg = a.plans + T.plan;
   TileDev T2 = T;
   T2.nl = 2 * T.nl;
-  const LineCtx X = line_setup(lds_z, T2, P, a.tw, a.km);
+  const LineCtx X = line_setup(lds, T2, P, a.tw, a.km);
   float2* __restrict__ z = X.z;
   const int N = P.N, nl = T.nl, ld = T.ld;
   const long long pl = a.plane;
   const TileMem M = tile_mem<2>(P, T, nl, ld);
   __syncthreads();
-  const float* u = a.u + M.base;
-  load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, u, u + pl, a.eref[0], a.eref[1], a.d);
-  load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, nl, P.nb1, P.n1, u + 2 * pl, u + 3 * pl, a.eref[2],
-                                  a.eref[3], a.d);
-  FCSD_DIFF_AND_TRANSFORM(a)
   const int flux = a.mode;
+  if (!FUSED || flux != FLUX_INVISCID) {
+    const float* u = a.u + M.base;
+    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, u, u + pl, a.eref[0], a.eref[1], a.d);
+    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, nl, P.nb1, P.n1, u + 2 * pl, u + 3 * pl, a.eref[2],
+                                    a.eref[3], a.d);
+    FCSD_DIFF_AND_TRANSFORM(a)
+  }
   const HSrc hs = h_sources(a, M.base, flux);
   float* H = a.H + M.base;
   float* d2o = a.d2out ? a.d2out + M.base : nullptr;
-  const float2* zb = z + nl;
+  float2* zb = z + nl;
   walk_b<kEpiBatchH>(
       M.w, [&](unsigned g) { return load_H4_inputs(hs, g); },
       [&](unsigned g, unsigned l, const HIn4& q) {
@@ -371,6 +394,7 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
         }
         float dF[4] = {0.f, 0.f, 0.f, 0.f}, dG[4] = {0.f, 0.f, 0.f, 0.f};
         if (flux != FLUX_VISC) dev_flux(q.e, a.eref, a.pref, a.gamma, dF, dG);
+        float h[8];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           float vx = 0.f, vy = 0.f;
@@ -378,10 +402,55 @@ __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
             vx = q.mu * (q.m1x * q.d1[k] + q.m2x * d2[k]);
             vy = q.mu * (q.m1y * q.d1[k] + q.m2y * d2[k]);
           }
-          at(H + (2 * k) * pl, g) = vx - dF[k];
-          at(H + (2 * k + 1) * pl, g) = vy - dG[k];
+          h[2 * k] = vx - dF[k];
+          h[2 * k + 1] = vy - dG[k];
+          at(H + (2 * k) * pl, g) = h[2 * k];
+          at(H + (2 * k + 1) * pl, g) = h[2 * k + 1];
+        }
+        if (FUSED) {
+          at(z, l) = make_float2(h[0], h[1]);
+          at(zb, l) = make_float2(h[2], h[3]);
         }
       });
+  if (!FUSED) return;
+  const float* m2x = a.metric + 2 * pl + M.base;
+  const float* m2y = a.metric + 3 * pl + M.base;
+  float* r2 = a.r2 + M.base;
+  __syncthreads();
+  // components 0 and 1: differences of the LDS lines, transform
+  difference_ext(X, P, a.dq + P.dq, a.d);
+  fft_apply<false>(X, Pg, P);
+  for (int half = 0; half < 2; ++half) {
+    float* ra = r2 + (2 * half) * pl;
+    float* rb = r2 + (2 * half + 1) * pl;
+    walk_b<kLoadBatch>(
+        M.w, [&](unsigned g) { return make_float2(at(m2x, g), at(m2y, g)); },
+        [&](unsigned g, unsigned l, float2 m) {
+          const float2 v = at(z, l), w = at(zb, l);
+          at(ra, g) = m.x * v.x + m.y * v.y;
+          at(rb, g) = m.x * w.x + m.y * w.y;
+        });
+    __syncthreads();
+    if (half == 1) break;
+    // components 2 and 3 from the stored H
+    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, H + 4 * pl, H + 5 * pl, 0.f, 0.f, a.d);
+    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, nl, P.nb1, P.n1, H + 6 * pl, H + 7 * pl, 0.f, 0.f,
+                                    a.d);
+    FCSD_DIFF_AND_TRANSFORM(a)
+  }
+}
+
+__global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  passB_tile<false>(a, T, lds_z);
+}
+
+// Passes B1 and B2 in one launch (see passB_tile).
+__global__ void FCSD_LINE_BOUNDS k_passB(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  passB_tile<true>(a, T, lds_z);
 }
 
 // Spectral filter of the state (paper Sec. 4.3.1, eq. filtering) along
@@ -632,9 +701,9 @@ __global__ void FCSD_LINE_BOUNDS k_passB2(PassArgs a) {
 }
 
 // Pass C (q1 lines): r = m1x d1 H_x + m1y d1 H_y + r2, then store (SET/ADD)
-// or the SSPRK register update (RK).
-__global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
-  FCSD_TILE_BEGIN(a)
+// or the SSPRK register update (RK), on tile Tin with its LDS at lds.
+__device__ __forceinline__ void passC_tile(const PassArgs& a, const TileDev& Tin, float2* lds) {
+  FCSD_TILE_AT(a, Tin, lds)
   const TileMem M = tile_mem<1>(P, T, nl, ld);
   const long long pl = a.plane;
   float dt = 0.f;
@@ -697,6 +766,92 @@ __global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
           }
         });
     __syncthreads();
+  }
+}
+
+__global__ void FCSD_LINE_BOUNDS k_passC(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  passC_tile(a, T, lds_z);
+}
+
+// ---------------------------------------------------------------- one launch per stage
+
+// Task kinds of the persistent stage kernel: pass A on a q1 tile, passes
+// B1 + B2 on a q2 tile (two complex lines per grid line), pass C on a q1
+// tile.
+enum { TASK_A = 0, TASK_B = 1, TASK_C = 2 };
+
+struct StageArgs {
+  PassArgs A, B, C;         // the passes' arguments (A.tiles, B.tiles: the q1 and q2 tile arrays)
+  const int2* tasks;        // (kind, tile index), in queue order
+  int ntasks;
+  int npatch;
+  int skipA;                // inviscid stage: A tasks do nothing
+  unsigned* ctr;            // [0] queue head; [1 + p] A tiles done of patch p; [1 + np + p] B tiles done
+  const unsigned* need;     // [p] A tiles of patch p; [np + p] B tiles of patch p
+  unsigned* err;            // bit 0 set when a wait gave up (results of the launch are then invalid)
+};
+
+// Upper bound on the polls of one dependency wait (each poll sleeps ~128
+// cycles: about a second in all), after which the workgroup records the
+// failure in err and goes on, so that every workgroup ends.
+constexpr int kSpinLimit = 1 << 24;
+
+// One RK stage in one launch: every workgroup takes tasks from a global
+// queue until it is empty.  The queue holds all A tasks, then every B task,
+// then every C task, so a task only depends on tasks taken before it (B on
+// its patch's A tiles, C on its patch's B tiles), which are held by running
+// workgroups: the earliest unfinished task can always proceed, whatever the
+// number of resident workgroups.  A task's completion is published by a
+// release increment of its patch's counter after a workgroup barrier (every
+// thread's stores are then complete); a dependent task starts after an
+// acquire poll of that counter.  Phases of different patches overlap, and no
+// workgroup idles at the end of a pass.  The counters start at zero (the
+// host clears them before the launch).
+__global__ void FCSD_LINE_BOUNDS k_stage(StageArgs s) {
+  // the first 16 bytes of the dynamic LDS hold the task index; tiles start after
+  int* slot = reinterpret_cast<int*>(lds_z);
+  float2* lds = lds_z + 2;
+  const int np = s.npatch;
+  for (;;) {
+    __syncthreads();  // the previous task's LDS reads are done; the slot is free
+    if (threadIdx.x == 0) slot[0] = (int)atomicAdd(s.ctr, 1u);
+    __syncthreads();
+    const int t = slot[0];
+    if (t >= s.ntasks) return;
+    const int2 k = s.tasks[t];
+    const TileDev T = (k.x == TASK_B ? s.B.tiles : s.A.tiles)[k.y];
+    const int p = T.plan;  // one plan per patch and direction
+    if (k.x != TASK_A) {
+      if (threadIdx.x == 0) {
+        const int dep = (k.x == TASK_B ? 0 : np) + p;
+        const unsigned need = s.need[dep];
+        unsigned* c = s.ctr + 1 + dep;
+        int polls = 0;
+        while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (++polls > kSpinLimit) {
+            atomicOr(s.err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __syncthreads();
+    }
+    if (k.x == TASK_A) {
+      if (!s.skipA) dev_diff_tile<1>(s.A, T, lds);
+    } else if (k.x == TASK_B) {
+      passB_tile<true>(s.B, T, lds);
+    } else {
+      passC_tile(s.C, T, lds);
+    }
+    if (k.x != TASK_C) {
+      __syncthreads();  // every thread's stores of the task are complete
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(s.ctr + 1 + (k.x == TASK_A ? 0 : np) + p, 1u, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 

@@ -654,6 +654,71 @@ def test_fused_stage_and_per_patch_equal(env, layout):
     s.close()
 
 
+SCHEDULES = (0, 1, 2)   # split (four launches), fused (three), persistent (one per stage)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("case", ["uneven", "annulus", "square64", "overlap", "uneven_inviscid"])
+def test_schedules_give_identical_stages(env, case, layout):
+    """The three launch schedules of a stage's line passes run the same FP32
+    operations on every line: all five stages, viscous and inviscid, are
+    bit-identical across them (and the persistent queue's waits never give
+    up).  Small tiles make the persistent queue long (many tasks per patch
+    and per workgroup)."""
+    api, ctx, torch = env
+    name = case.replace("_inviscid", "")
+    ps, u, mu, ref = rhs_case(name)
+    s, D, H = mkset(api, ctx, ps, layout)
+    metric = D(ps.metric)
+    mud = None if case.endswith("_inviscid") else D(mu)
+    dtd = dev(torch, np.array([1e-3], np.float32))
+    u0 = D(u)
+    for tiles in [((65536,) * 3, (512,) * 3), ((16384, 16384, 24576), (256,) * 3)]:
+        s.tune(*tiles, 1)
+        outs = {}
+        for sched in SCHEDULES:
+            s.set_schedule(sched)
+            acc = torch.zeros(4 * s.plane, device="cuda:0")
+            ua = torch.zeros(4 * s.plane, device="cuda:0")
+            ub = torch.zeros(4 * s.plane, device="cuda:0")
+            uc = torch.zeros(4 * s.plane, device="cuda:0")
+            ins, outs_ = [u0, ua, ub, ua, ub], [ua, ub, ua, ub, uc]
+            for k in range(5):
+                api.fcsd_stage(s, k, u0, ins[k], acc, outs_[k], metric, mud, ref, G, dtd)
+            outs[sched] = (H(uc), H(acc))
+        assert s.stage_errors() == 0
+        say(case, layout, tiles, "max |split - fused|", float(np.abs(outs[0][0] - outs[1][0]).max()),
+            "max |split - persistent|", float(np.abs(outs[0][0] - outs[2][0]).max()))
+        for sched in SCHEDULES[1:]:
+            assert np.array_equal(outs[sched][0], outs[0][0])
+            assert np.array_equal(outs[sched][1], outs[0][1])
+    assert np.all(np.isfinite(outs[0][0]))
+    s.close()
+
+
+def test_persistent_schedule_steps_with_network(env):
+    """Five full steps of the 16-sector annulus (network, viscosity, step
+    size, glue and inflow every stage, graph replay) give bit-identical
+    states with the persistent and the split schedules."""
+    api, ctx, torch = env
+    cfg = synth.config(1, n=48)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, 1)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    res = []
+    for sched in (0, 2):
+        s.set_schedule(sched)
+        u = D(cfg.u0)
+        st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W, dirichlet_mask=D(ps.dirichlet),
+                         dirichlet_state=synth.freestream(cfg.mach))
+        for k in range(5):
+            st.step(use_graph=(k > 0))
+        res.append(H(u))
+    assert s.stage_errors() == 0
+    assert np.all(np.isfinite(res[0])) and np.array_equal(res[0], res[1])
+    s.close()
+
+
 def test_ten_steps_square(env):
     api, ctx, torch = env
     cfg = synth.config(0)
