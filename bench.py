@@ -459,6 +459,35 @@ def main():
         s2.close()
         del st2, u2
 
+    # ---------------- the strict continuation length: the bench workload with
+    # C = 27 on every line; most extension lengths N + 27 have a prime factor
+    # above 13 and their circulants run embedded in a 13-smooth transform of
+    # length >= N + L (about twice the transform work)
+    strict = None
+    if not args.no_paper:
+        sps = synth.with_continuation(ps, 27)
+        nemb = sum(1 for n in list(sps.n1) + list(sps.n2) if not synth.smooth13(int(n) + 27))
+        s5 = api.PatchSet.from_layout(ctx, sps, layout)
+        apply_tuning(s5)
+        u5 = s5.to_device(cfg.u0)
+        st5 = api.Stepper(s5, u5, s5.to_device(sps.metric), cfg.ref, W=W)
+        for _ in range(args.warmup):
+            st5.step(use_graph=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(args.steps):
+            st5.step(use_graph=True)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms5 = e0.elapsed_time(e1) / args.steps
+        strict = {"workload": "the bench workload with C = 27 on every line (no 13-smooth rule)",
+                  "embedded_line_families": nemb, "line_families": 2 * sps.npatch,
+                  "value": npts * 5 / (ms5 / 1e3), "unit": "grid-pt RK-stages/s", "ms_per_step": ms5,
+                  "finite": bool(torch.isfinite(u5).all().item())}
+        s5.close()
+        del st5, u5
+
     # ---------------- inter-patch interpolation (Sec. 3.4.1) on a Cartesian /
     # polar pair of 1024 x 1024 patches that overlap without shared grid
     # lines: step rate with the network viscosity
@@ -594,6 +623,7 @@ def main():
         "adjoint": adjoint,
         "filter": filt,
         "paper_subpatches": paper,
+        "strict_continuation": strict,
         "interpolated_pair": interp_rec,
         "annulus_shells": shells,
         "schedule": {k: v for k, v in tuning.items() if k != "table"},

@@ -94,8 +94,14 @@ enum {
 };
 /* Build a patch set: validates the descriptors (n >= 2d+1, n <= 4096,
  * 0 <= C <= 256, 1 <= d <= 8, patches inside [0, plane) and disjoint),
- * factors every extension length L = n + C into radices {2,3,4,5,7,8,11,13}
- * (FCSD_EUNSUPPORTED otherwise), computes the FC-Gram continuation matrices
+ * factors every extension length L = n + C into radices 2..16 (primes up to
+ * 13); a line whose L has a larger prime factor has its circulant operators
+ * (derivative, filter; Sec. 2.2 eq. fc_der, Sec. 4.3.1 eq. filtering) applied
+ * as a cyclic convolution of the smallest 13-smooth length M >= n + L, the
+ * line zero-padded to M and the operator's first column wrapped onto it, the
+ * same operator exactly in exact arithmetic at about twice the transform
+ * work (FCSD_EUNSUPPORTED when M exceeds 8192 or the smallest tile of such
+ * lines does not fit a workgroup's LDS), computes the FC-Gram continuation matrices
  * (Sec. 2.2, eq. continuation) in binary128 arithmetic, the FP32 twiddle
  * and derivative-multiplier tables and the tile schedules, and uploads them.
  * `ring_sectors` / `ring_shells` > 0 declare the index-aligned annulus

@@ -39,7 +39,8 @@ constexpr int kMaxTile = 64;     // complex lines per tile
 constexpr int kBlock = 256;      // threads per workgroup
 
 struct PlanDev {
-  int N, L, C, nst;
+  int N, L, C, nst;  // L: transform length (N + C, or the embedding length of a circulant of N + C)
+  int Lx;            // extension length N + C
   int rad[kMaxStages];
   int tw;        // offset of the twiddle table (float2) for this L
   int km;        // offset of the multiplier table (float2) for this (N, L)
@@ -398,6 +399,14 @@ __device__ __forceinline__ void fft_dispatch(int R, const LineCtx& X, int L, int
   }
 }
 
+// Zero positions Lx .. L-1 of every line of the tile: the padding of an
+// extension whose circulant runs embedded in a longer transform (none when
+// the transform length is the extension length).
+__device__ __forceinline__ void zero_pad(const LineCtx& X, const PlanDev& P) {
+  if (!X.active) return;
+  for (int r = P.Lx + X.b0; r < P.L; r += X.BS) X.z[r * X.ld + X.c] = make_float2(0.f, 0.f);
+}
+
 // Tail of every line (continuation); periodic plans have no tail.
 __device__ __forceinline__ void fc_tail(const LineCtx& X, const PlanDev& P, const double* __restrict__ aq, int d) {
   if (!X.active) return;
@@ -418,6 +427,7 @@ __device__ __forceinline__ void fc_tail(const LineCtx& X, const PlanDev& P, cons
     }
     z[(N + m) * ld + c] = make_float2((float)sx, (float)sy);
   }
+  zero_pad(X, P);
 }
 
 // E^T of the continuation: add sum_m (A Q^T)[m][j] tail[m] to the 2d end
@@ -593,6 +603,7 @@ __device__ __forceinline__ void difference_ext(const LineCtx& X, const PlanDev& 
     }
     if (X.b0 == 0) z[(N - 1) * ld + c] = keep;
   }
+  zero_pad(X, P);
   __syncthreads();
 }
 
@@ -636,6 +647,7 @@ __device__ __forceinline__ void diff_tail(const LineCtx& X, const PlanDev& P, co
   const int N = P.N, C = P.C, ld = X.ld, c = X.c;
   float2* __restrict__ z = X.z;
   const float2* __restrict__ side = X.side;
+  zero_pad(X, P);
   if (P.periodic) {
     if (X.b0 == 0) {
       const float2 a = side[c], b = side[(2 * d - 1) * ld + c];
@@ -662,7 +674,7 @@ __device__ __forceinline__ void diff_tail(const LineCtx& X, const PlanDev& P, co
 // transposed restriction).
 __device__ __forceinline__ void zero_tail(const LineCtx& X, const PlanDev& P) {
   if (!X.active) return;
-  for (int r = X.b0; r < P.C; r += X.BS) X.z[(P.N + r) * X.ld + X.c] = make_float2(0.f, 0.f);
+  for (int r = P.N + X.b0; r < P.L; r += X.BS) X.z[r * X.ld + X.c] = make_float2(0.f, 0.f);
 }
 
 // Delta^T of the zero-padded cotangent in place (transposed operator):
@@ -683,10 +695,9 @@ __device__ __forceinline__ void difference_adj(const LineCtx& X, const PlanDev& 
       else if (P.periodic)
         prv = z[(N - 1) * ld + c];
     }
-    if (!P.periodic) {
-      for (int n = N + X.b0; n < L; n += X.BS)
-        z[n * ld + c] = (n == N) ? z[(N - 1) * ld + c] : make_float2(0.f, 0.f);
-    }
+    // positions N.. (an embedded periodic line: the padding only)
+    for (int n = N + X.b0; n < L; n += X.BS)
+      z[n * ld + c] = (n == N && !P.periodic) ? z[(N - 1) * ld + c] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   if (X.active && s0 < e0) {

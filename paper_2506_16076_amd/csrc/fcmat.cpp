@@ -314,6 +314,132 @@ extern "C" void fcsd_host_fmul(int L, int nst, const int* rad, double alpha, int
   }
 }
 
+// ------------------------------------------------------------------ embedded circulants
+// A line operator of the engine is a circulant of the extension length
+// L = N + C (the FC derivative, eq. fc_der, on the differenced extension;
+// the spectral filter, eq. filtering).  When L has a prime factor above 13
+// there is no mixed-radix plan of length L; the circulant is then applied as
+// a cyclic convolution of a 13-smooth length M >= N + L: the line is padded
+// with zeros to M and the kernel's first column h (period L) is wrapped as
+// k[t mod M] = h[t mod L] for t in [-(L-1), N], zero elsewhere.  For the
+// outputs n < N of inputs m < L (the forward operators) n - m lies in
+// [-(L-1), N-1], for the transposes (inputs m <= N, outputs n < N) m - n in
+// [-(N-1), N]; on both ranges k equals h's periodic continuation and the
+// ranges do not wrap onto each other in M >= N + L, so the cyclic convolution
+// of length M returns the circulant of length L exactly (in exact
+// arithmetic) on the positions used.
+
+// Smallest length M >= n whose prime factors are at most 13 and that has a
+// radix plan of at most 8 stages; 0 if none up to 65536.
+extern "C" int fcsd_host_embed_length(int n) {
+  int rad[8];
+  for (int M = std::max(n, 2); M <= 65536; ++M) {
+    int m = M;
+    for (int q : {2, 3, 5, 7, 11, 13})
+      while (m % q == 0) m /= q;
+    if (m == 1 && fcsd_host_factor(M, rad) > 0) return M;
+  }
+  return 0;
+}
+
+namespace {
+typedef long double ldt;
+
+// First column h[0..L-1] of a line circulant of length L.
+// kind 0: derivative of the differenced extension, the multipliers
+//   i w_k / (exp(2 pi i k / L) - 1), w_k = 2 pi k / beta (beta = L / (N-1),
+//   or 1 for a periodic line), k = 0 and the Nyquist of an even L zero:
+//   h[r] = (1/L) sum_{k=1}^{(L-1)/2} w_k cos(2 pi k (2r - 1) / (2L)) / sin(pi k / L);
+// kind 1: spectral filter, sigma(2k/L) = exp(-alpha (2k/L)^p) on every k:
+//   h[r] = (1/L) (sigma_0 + 2 sum_k sigma_k cos(2 pi k r / L) + [L even] sigma_{L/2} (-1)^r).
+std::vector<ldt> circulant_column(int kind, int N, int L, int periodic, double alpha, int p) {
+  std::vector<ldt> h(L, 0.0L);
+  const int K = (L - 1) / 2;
+  if (kind == 0) {
+    const qf wscale = periodic ? 2 * M_PIq : 2 * M_PIq * (N - 1) / (qf)L;
+    const int64_t L2 = 2 * (int64_t)L;
+    std::vector<ldt> cs2(L2);  // cos(2 pi j / (2L))
+    std::vector<ldt> inv_s(K + 1);
+    for (int j = 0; j < L2; ++j) {
+      qf c, sn;
+      cis2pi(j, L2, &c, &sn);
+      cs2[j] = (ldt)c;
+      if (j >= 1 && j <= K) inv_s[j] = (ldt)(wscale * (qf)j / sn);  // w_j / sin(pi j / L)
+    }
+    for (int r = 0; r < L; ++r) {
+      ldt acc = 0.0L;
+      for (int k = 1; k <= K; ++k) {
+        int64_t num = ((int64_t)k * (2 * (int64_t)r - 1)) % L2;
+        if (num < 0) num += L2;
+        acc += inv_s[k] * cs2[num];
+      }
+      h[r] = acc / (ldt)L;
+    }
+  } else {
+    std::vector<ldt> sig(L / 2 + 1), cs(L);
+    for (int k = 0; k <= L / 2; ++k) sig[k] = (ldt)expq(-(qf)alpha * powq(2 * (qf)k / L, p));
+    for (int j = 0; j < L; ++j) {
+      qf c, sn;
+      cis2pi(j, L, &c, &sn);
+      cs[j] = (ldt)c;
+    }
+    for (int r = 0; r < L; ++r) {
+      ldt acc = sig[0];
+      for (int k = 1; k <= K; ++k) acc += 2.0L * sig[k] * cs[(int)(((int64_t)k * r) % L)];
+      if (L % 2 == 0) acc += sig[L / 2] * ((r & 1) ? -1.0L : 1.0L);
+      h[r] = acc / (ldt)L;
+    }
+  }
+  return h;
+}
+
+// Multiplier table of the wrapped kernel for the engine's transform of
+// length M (plan rad): position pos holds DFT_M(k)[kappa] / M for the
+// wavenumber kappa of the position (the inverse transform's 1/M folded in),
+// as interleaved (re, im) FP32 pairs.
+void embedded_table(const std::vector<ldt>& h, int N, int L, int M, int nst, const int* rad, float* out) {
+  std::vector<ldt> k(M, 0.0L);
+  for (int t = -(L - 1); t <= N; ++t) {
+    int tm = t % M, tl = t % L;
+    if (tm < 0) tm += M;
+    if (tl < 0) tl += L;
+    k[tm] = h[tl];
+  }
+  std::vector<ldt> cs(M), sn(M);
+  for (int j = 0; j < M; ++j) {
+    qf c, s;
+    cis2pi(j, M, &c, &s);
+    cs[j] = (ldt)c;
+    sn[j] = (ldt)s;
+  }
+  for (int pos = 0; pos < M; ++pos) {
+    const int64_t kap = position_wavenumber(pos, M, nst, rad);
+    ldt re = 0.0L, im = 0.0L;
+    for (int t = 0; t < M; ++t) {
+      if (k[t] == 0.0L) continue;
+      const int j = (int)((kap * t) % M);
+      re += k[t] * cs[j];
+      im -= k[t] * sn[j];
+    }
+    out[2 * pos] = (float)(re / (ldt)M);
+    out[2 * pos + 1] = (float)(im / (ldt)M);
+  }
+}
+}  // namespace
+
+// Derivative multipliers of a line of N points with extension length L
+// embedded in a transform of length M (see above).
+extern "C" void fcsd_host_kmul_embedded(int N, int L, int M, int nst, const int* rad, float* out, int periodic) {
+  embedded_table(circulant_column(0, N, L, periodic, 0.0, 0), N, L, M, nst, rad, out);
+}
+
+// Spectral filter factors (alpha, p) of an extension of length L embedded
+// in a transform of length M.
+extern "C" void fcsd_host_fmul_embedded(int N, int L, int M, int nst, const int* rad, double alpha, int p,
+                                        float* out) {
+  embedded_table(circulant_column(1, N, L, 0, alpha, p), N, L, M, nst, rad, out);
+}
+
 // Fold matrix of a transposed FC line operator (paper Sec. 2.2, eqs.
 // continuation and fc_der, transposed).  A line operator of the engine is
 // R K E: E extends the N samples by the continuation tail (T, C x 2d on the

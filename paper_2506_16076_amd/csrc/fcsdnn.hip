@@ -24,6 +24,10 @@ extern "C" int fcsd_host_fc_matrix(int d, int C, double* out);
 extern "C" int fcsd_host_fc_dmatrix(int d, int C, double* out);
 extern "C" void fcsd_host_twiddles(int L, float* out);
 extern "C" int fcsd_host_factor(int L, int* rad);
+extern "C" int fcsd_host_embed_length(int n);
+extern "C" void fcsd_host_kmul_embedded(int N, int L, int M, int nst, const int* rad, float* out, int periodic);
+extern "C" void fcsd_host_fmul_embedded(int N, int L, int M, int nst, const int* rad, double alpha, int p,
+                                        float* out);
 extern "C" void fcsd_host_kmul(int N, int L, int nst, const int* rad, float* out, int periodic);
 extern "C" void fcsd_host_fmul(int L, int nst, const int* rad, double alpha, int p, float* out);
 extern "C" int fcsd_host_fold_matrix(int N, int C, int d, const double* arq, int kind, double alpha, int p,
@@ -363,6 +367,24 @@ extern "C" fcsd_status fcsd_fft_plan(int L, int* nst, int rad[8]) {
 }
 
 // Validate a patch table without a device (also used by fcsd_set_create).
+namespace {
+// Longest transform of a line (an extension of up to 4096 + 256 points, or
+// the embedding of a circulant whose extension length has a prime factor
+// above 13).
+constexpr int kMaxTransform = 8192;
+
+// Transform length of a line of N points with C continuation points: the
+// extension length N + C when it has a radix plan, else the embedding length
+// of its circulant (the smallest 13-smooth length >= N + (N + C) with a plan,
+// see fcmat.cpp); 0 if none.
+int transform_length(int N, int C) {
+  int rad[8];
+  const int Lx = N + C;
+  if (Lx <= kMaxTransform && fcsd_host_factor(Lx, rad) > 0) return Lx;
+  return fcsd_host_embed_length(N + Lx);
+}
+}  // namespace
+
 extern "C" fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* p, int d, int64_t plane,
                                              int ring_sectors, int ring_shells, int layout, char* msg,
                                              int msglen) {
@@ -398,10 +420,12 @@ extern "C" fcsd_status fcsd_validate_patches(int npatch, const fcsd_patch_desc* 
       return say(b), FCSD_EINVAL;
     }
     for (int dir = 0; dir < 2; ++dir) {
-      const int N = dir ? q.n2 : q.n1, C = dir ? q.C2 : q.C1, L = N + C;
-      int rad[8];
-      if (L > 4096 || fcsd_host_factor(L, rad) == 0) {
-        snprintf(b, sizeof b, "patch %d: extension length %d has a prime factor above 13", i, L);
+      const int N = dir ? q.n2 : q.n1, C = dir ? q.C2 : q.C1;
+      const int L = transform_length(N, C);
+      if (L == 0 || L > kMaxTransform) {
+        snprintf(b, sizeof b,
+                 "patch %d: extension length %d has a prime factor above 13 and no embedding of length <= %d",
+                 i, N + C, kMaxTransform);
         return say(b), FCSD_EUNSUPPORTED;
       }
     }
@@ -544,6 +568,20 @@ fcsd_status upload_tiles(fcsd_ctx* ctx, DirPlan& D) {
   return FCSD_OK;
 }
 
+// Spectral filter factors (alpha, p) of plan P (Sec. 4.3.1, eq. filtering):
+// of its extension length, or of its circulant embedded in the longer
+// transform (then they also depend on N).
+std::tuple<int, int, int> filter_key(const PlanDev& P) {
+  return std::make_tuple(P.Lx, P.L, P.L == P.Lx ? 0 : P.N);
+}
+void filter_table(const PlanDev& P, double alpha, int p, std::vector<float>& t) {
+  t.assign(2 * (size_t)P.L, 0.0f);
+  if (P.L == P.Lx)
+    fcsd_host_fmul(P.L, P.nst, P.rad, alpha, p, t.data());
+  else
+    fcsd_host_fmul_embedded(P.N, P.Lx, P.L, P.nst, P.rad, alpha, p, t.data());
+}
+
 // Task queue of the persistent stage kernel from the current tile sets:
 // every A task (q1 tiles in launch order), then the B tasks (q2 tiles with
 // two complex lines per grid line) patch by patch in the order in which the
@@ -638,7 +676,7 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
   std::vector<float> gq;
   std::map<int, int> tw_of_L, aq_of_C, dq_of_C;
   std::map<std::pair<int, int>, int> gq_of;
-  std::map<std::tuple<int, int, int>, int> km_of;
+  std::map<std::tuple<int, int, int, int>, int> km_of;
   for (int dir = 1; dir <= 2; ++dir) {
     DirPlan& D = s->dir[dir - 1];
     long long eo = 0;
@@ -648,7 +686,8 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
       memset(&P, 0, sizeof(P));
       P.N = dir == 1 ? q.n1 : q.n2;
       P.C = dir == 1 ? q.C1 : q.C2;
-      P.L = P.N + P.C;
+      P.Lx = P.N + P.C;
+      P.L = transform_length(P.N, P.C);
       P.periodic = P.C == 0;
       P.nst = fcsd_host_factor(P.L, P.rad);
       P.nlines = dir == 1 ? q.n2 : q.n1;
@@ -664,11 +703,14 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
         for (int n = 0; n < P.L; ++n) tw.push_back(make_float2(t[2 * n], t[2 * n + 1]));
       }
       P.tw = tw_of_L[P.L];
-      auto key = std::make_tuple(P.N, P.L, P.periodic);
+      auto key = std::make_tuple(P.N, P.L, P.periodic, P.Lx);
       if (!km_of.count(key)) {
         km_of[key] = (int)km.size();
         std::vector<float> t(2 * P.L);
-        fcsd_host_kmul(P.N, P.L, P.nst, P.rad, t.data(), P.periodic);
+        if (P.L == P.Lx)
+          fcsd_host_kmul(P.N, P.L, P.nst, P.rad, t.data(), P.periodic);
+        else  // the circulant of the extension, embedded in the longer transform
+          fcsd_host_kmul_embedded(P.N, P.Lx, P.L, P.nst, P.rad, t.data(), P.periodic);
         for (int n = 0; n < P.L; ++n) km.push_back(make_float2(t[2 * n], t[2 * n + 1]));
       }
       P.km = km_of[key];
@@ -699,13 +741,24 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
       }
       D.plans.push_back(P);
       D.ext_off.push_back(eo);
-      eo += (long long)P.nlines * P.L;
+      eo += (long long)P.nlines * P.Lx;
     }
     D.ext_plane = eo;
   }
   for (int dir = 0; dir < 2; ++dir) {
     for (auto& t : s->dir[dir].ts) t.budget = default_lds_budget();
     build_tiles(s->dir[dir], s->tile_order, tile_align(layout, dir), d);
+  }
+  {
+    // the smallest tiles (one storage-aligned group of lines) must fit the LDS
+    int maxlds = 0;
+    HIPCHK(ctx, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    for (int dir = 0; dir < 2; ++dir)
+      for (const TileSet& t : s->dir[dir].ts)
+        if (t.lds > (size_t)maxlds)
+          return fail(ctx, FCSD_EUNSUPPORTED,
+                      "a line tile needs more LDS than a workgroup has (transform length too long for the "
+                      "storage's smallest tile)");
   }
   // per-patch descriptors and point chunks
   std::vector<PatchDev> pd;
@@ -909,19 +962,20 @@ extern "C" fcsd_status fcsd_set_filter(fcsd_set* s, double alpha, int p) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   s->graphs.clear();
   std::vector<float2> kf;
-  std::map<int, int> kf_of_L;
+  std::map<std::tuple<int, int, int>, int> kf_of_L;
   std::vector<float> gf;
   std::map<std::pair<int, int>, int> gf_of;
   std::map<int, std::vector<double>> aq_of_C;
   for (int dir = 0; dir < 2; ++dir)
     for (PlanDev& P : s->dir[dir].plans) {
-      if (!kf_of_L.count(P.L)) {
-        kf_of_L[P.L] = (int)kf.size();
-        std::vector<float> t(2 * P.L);
-        fcsd_host_fmul(P.L, P.nst, P.rad, alpha, p, t.data());
+      const auto fkey = filter_key(P);
+      if (!kf_of_L.count(fkey)) {
+        kf_of_L[fkey] = (int)kf.size();
+        std::vector<float> t;
+        filter_table(P, alpha, p, t);
         for (int n = 0; n < P.L; ++n) kf.push_back(make_float2(t[2 * n], t[2 * n + 1]));
       }
-      P.kf = kf_of_L[P.L];
+      P.kf = kf_of_L[fkey];
       if (P.periodic) continue;
       const auto key = std::make_pair(P.N, P.C);
       if (!gf_of.count(key)) {
@@ -2045,17 +2099,18 @@ extern "C" fcsd_status fcsd_smear(fcsd_ctx* ctx, const fcsd_set* s, const float*
     // factors of every distinct extended length, offsets per direction and plan
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     std::vector<float2> ks;
-    std::map<int, int> at_L;
+    std::map<std::tuple<int, int, int>, int> at_L;
     std::vector<int> off[2];
     for (int dir = 0; dir < 2; ++dir)
       for (const PlanDev& P : s->dir[dir].plans) {
-        if (!at_L.count(P.L)) {
-          at_L[P.L] = (int)ks.size();
-          std::vector<float> t(2 * P.L);
-          fcsd_host_fmul(P.L, P.nst, P.rad, alpha, p, t.data());
+        const auto fkey = filter_key(P);
+        if (!at_L.count(fkey)) {
+          at_L[fkey] = (int)ks.size();
+          std::vector<float> t;
+          filter_table(P, alpha, p, t);
           for (int n = 0; n < P.L; ++n) ks.push_back(make_float2(t[2 * n], t[2 * n + 1]));
         }
-        off[dir].push_back(at_L[P.L]);
+        off[dir].push_back(at_L[fkey]);
       }
     (void)hipFree(ms->d_ks);
     (void)hipFree(ms->d_ksoff[0]);

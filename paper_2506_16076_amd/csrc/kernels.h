@@ -207,7 +207,7 @@ __global__ void FCSD_LINE_BOUNDS k_fcdiff(PassArgs a) {
 template <int DIR, bool ADJ>
 __global__ void FCSD_LINE_BOUNDS k_fccont(PassArgs a) {
   FCSD_TILE_BEGIN(a)
-  const int L = P.L;
+  const int L = P.Lx;  // ext lines: the extension, without the padding of an embedded transform
   const TileMem M = tile_mem<DIR>(P, T, nl, ld);
   const Walk we = make_walk<1>(L, nl, ld, 0, L);
   const long long e0 = a.ext_off[T.plan] + (long long)T.line0 * L;
@@ -488,10 +488,11 @@ __global__ void FCSD_LINE_BOUNDS k_filter(PassArgs a) {
         at(zb, l) = make_float2(v.z, th);
       });
   __syncthreads();
-  if (!P.periodic) {
+  if (!P.periodic)
     fc_tail(X, P, a.aq + P.aq, a.d);
-    __syncthreads();
-  }
+  else
+    zero_pad(X, P);
+  __syncthreads();
   fft_apply<false>(X, Pg, P);
   walk(M.w, [&](unsigned g, unsigned l) {
     const float2 p = at(z, l), q = at(zb, l);
@@ -535,10 +536,11 @@ __global__ void FCSD_LINE_BOUNDS k_smear(PassArgs a) {
         at(zb, l) = make_float2(v.z, theta(v));
       });
   __syncthreads();
-  if (!P.periodic) {
+  if (!P.periodic)
     fc_tail(X, P, a.aq + P.aq, a.d);
-    __syncthreads();
-  }
+  else
+    zero_pad(X, P);
+  __syncthreads();
   fft_apply<false>(X, Pg, P);
   struct In5 {
     float4 v;

@@ -214,6 +214,15 @@ def overlap_pair(n: int = 48, d: int = 5, c_min: int = 27) -> PatchSet:
     return ps
 
 
+def with_continuation(ps: PatchSet, C: int = 27) -> PatchSet:
+    """The same patches with C continuation points on every line (the
+    strict reading of the continuation length, C = 27 whatever N + C
+    factors into)."""
+    import dataclasses
+    n = len(ps.n1)
+    return dataclasses.replace(ps, C1=np.full(n, C, np.int32), C2=np.full(n, C, np.int32))
+
+
 def unit_square(n: int, d: int = 5, C: int = 27) -> PatchSet:
     """One Cartesian patch on [0,1]^2 (identity metric)."""
     n1 = np.array([n], np.int32)

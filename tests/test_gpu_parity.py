@@ -415,6 +415,100 @@ def test_fc_continue_and_transpose(env, direction):
     s.close()
 
 
+# ------------------------------------------------------------------ strict continuation length
+# C = 27 on every line: most extension lengths N + 27 then have a prime
+# factor above 13 and their circulants run embedded in a 13-smooth transform
+# of length M >= N + L (zero padding, wrapped first column).
+
+def strict_uneven(seed=21, npatch=6, nmax=400):
+    ps = synth.with_continuation(synth.uneven_sectors(npatch, 48, nmax, seed), 27)
+    emb = [(n, n + 27) for n in list(ps.n1) + list(ps.n2) if not synth.smooth13(int(n) + 27)]
+    say("strict C = 27:", len(emb), "of", 2 * ps.npatch, "line families embedded", emb)
+    assert len(emb) >= ps.npatch
+    return ps
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("direction", [1, 2])
+def test_strict_continuation_fc_diff(env, direction, layout):
+    """fc_diff and fc_diff_adj on lines whose N + 27 has a prime factor
+    above 13, against the oracle (which transforms length N + 27 directly)."""
+    api, ctx, torch = env
+    ps = strict_uneven()
+    s, D, H = mkset(api, ctx, ps, layout)
+    F = smooth_fields(ps, 3, 1)
+    out = torch.zeros(3 * s.plane, device="cuda:0")
+    api.fc_diff(s, direction, D(F), out, nf=3)
+    want = fcgram.diff_plane(F.astype(np.float64), ps, direction)
+    err, mx = relerr(ps, H(out), want), maxrel_phys(ps, H(out), want)
+    Y = smooth_fields(ps, 2, 2)
+    acc = torch.zeros(2 * s.plane, device="cuda:0")
+    api.fc_diff_adj(s, direction, D(Y), acc, nf=2)
+    wa = fcgram.diff_plane_adj(Y.astype(np.float64), ps, direction)
+    ea, ma = relerr(ps, H(acc), wa), maxrel_phys(ps, H(acc), wa)
+    say("strict fc_diff", direction, layout, "rel L2", err, "max", mx, "transpose", ea, "max", ma)
+    assert np.all(err < RHS_TOL) and np.all(mx < PT * RHS_TOL)
+    assert np.all(ea < ADJ_TOL) and np.all(ma < PT * ADJ_TOL)
+    s.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_strict_continuation_rhs_and_filter(env, layout):
+    """The full right-hand side and the spectral filter of the strict set
+    against the oracle."""
+    from oracle import filter as flt
+    api, ctx, torch = env
+    ps = strict_uneven(seed=22, npatch=5, nmax=300)
+    cfg = synth.config(2, npatch=5, nmax=300)
+    u = np.zeros((4, ps.plane), np.float32)
+    e = synth.mach_state(ps, 3.0, cfg.pert)
+    for p in range(ps.npatch):
+        ps.view(u, p)[...] = ps.view(e, p)
+    mu = (0.002 * (1.5 + np.sin(4 * ps.xy[1]))).astype(np.float32)
+    s, D, H = mkset(api, ctx, ps, layout)
+    rhs = torch.zeros(4 * s.plane, device="cuda:0")
+    api.fcsd_rhs(s, D(u), D(ps.metric), D(mu), cfg.ref, G, rhs)
+    want = euler.full_rhs(u.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G)
+    err, mx = relerr_phys(ps, H(rhs), want), maxrel_phys(ps, H(rhs), want)
+    un = noisy_state(ps, u, 3)
+    s.set_filter(ALPHA_F, P_F)
+    out = torch.zeros(4 * s.plane, device="cuda:0")
+    api.fcsd_filter(s, D(un), out, G)
+    wf = flt.filter_state(un.astype(np.float64), ps, ALPHA_F, P_F, G)
+    got = H(out).reshape(4, -1)
+    ef = relerr_phys(ps, got, wf)
+    ec = relerr_phys(ps, got - un, wf - un)
+    say("strict rhs", layout, "rel L2", err, "max", mx, "filter", ef, "filter change", ec)
+    assert np.all(err < RHS_TOL) and np.all(mx < PT * RHS_TOL)
+    assert np.all(ef < FILTER_TOL) and np.all(ec < 2e-2)
+    s.close()
+
+
+def test_strict_continuation_steps_with_network(env):
+    """Three network steps of the 16-sector annulus at 52 x 52 with C = 27
+    (L = 79, prime: every line runs embedded), the oracle replaying the
+    GPU's decisions."""
+    api, ctx, torch = env
+    cfg = synth.config(1, n=52)
+    import dataclasses
+    cfg = dataclasses.replace(cfg, ps=synth.with_continuation(cfg.ps, 27))
+    ps = cfg.ps
+    assert not synth.smooth13(52 + 27)
+    s, D, H = mkset(api, ctx, ps, 1)
+    u = D(cfg.u0)
+    st = api.Stepper(s, u, D(ps.metric), cfg.ref, W={k: dev(torch, v) for k, v in cfg.mlp.items()},
+                     dirichlet_mask=D(ps.dirichlet), dirichlet_state=synth.freestream(cfg.mach))
+    run = solver.Run(cfg)
+    for k in range(3):
+        st.step(use_graph=(k > 0))
+        run.step(dt=float(host(st.dt)[0]), tau=H(st.tau), arg=H(st.argmax))
+    got = H(u).reshape(4, -1)
+    err, mx = relerr_phys(ps, got, run.u), maxrel_phys(ps, got, run.u)
+    say("strict annulus 3 steps", err, "max", mx)
+    assert np.all(err < STEP_TOL) and np.all(mx < PT * STEP_TOL)
+    s.close()
+
+
 # ------------------------------------------------------------------ right-hand side
 
 def rhs_case(name):

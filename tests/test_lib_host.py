@@ -212,9 +212,13 @@ def test_patch_validation(L):
     end = int(ps.off[-1] + ps.n1[-1] * ps.n2[-1])
     assert L.validate_patches(descs, 5, end)[0] == 0
     assert L.validate_patches(descs, 5, end - 1)[0] == 1                  # outside the plane
-    bad = L.patch_descs(ps.n1, ps.n2, np.full(5, 17 * 7 - 48), ps.C2, ps.off, ps.hhat, ps.htilde, ps.internal)
-    rc, msg = L.validate_patches(bad, 5, ps.plane)
-    assert rc in (1, 5)
+    # extension lengths with a prime factor above 13 run embedded in a longer
+    # 13-smooth transform: accepted, unless that transform exceeds 8192
+    emb = L.patch_descs(ps.n1, ps.n2, 17 * 7 - ps.n1, ps.C2, ps.off, ps.hhat, ps.htilde, ps.internal)
+    assert L.validate_patches(emb, 5, ps.plane)[0] == 0
+    big = L.patch_descs([4096], [50], [27], [27], [0], [0.1], [0.1], [[0, 0, 0, 0]])
+    rc, msg = L.validate_patches(big, 5, 4096 * 50)
+    assert rc == 5 and "prime factor above 13" in msg
     over = L.patch_descs(ps.n1, ps.n2, ps.C1, ps.C2, np.zeros(5, np.int64), ps.hhat, ps.htilde, ps.internal)
     assert L.validate_patches(over, 5, ps.plane)[0] == 1                  # overlapping patches
     tiny = L.patch_descs([9], [40], [27], [27], [0], [0.1], [0.1], [[0, 0, 0, 0]])
@@ -291,3 +295,102 @@ def test_fold_matrix_is_the_transposed_operators_tail_fold(L, N, C, d):
         assert np.abs(got - want).max() <= bound, kind
         # nothing is folded onto the interior samples
         assert np.abs(fold[:, d:N - d]).max() <= 1e-12 * np.abs(full).max()
+
+
+def _position_wavenumbers(M, rad):
+    """Wavenumber held by every position of the engine's digit-reversed
+    order (the forward transform of a unit impulse at n = 1 puts
+    exp(-2 pi i k / M) at the position of k)."""
+    e = np.zeros(M, complex)
+    e[1] = 1.0
+    Y = emulate_engine(e, rad, np.exp(-2j * np.pi * np.arange(M) / M), False)
+    return np.rint(-np.angle(Y) * M / (2 * np.pi)).astype(int) % M
+
+
+@pytest.mark.parametrize("N,C", [(128, 27), (256, 27), (100, 27), (61, 28), (97, 0)])
+def test_embedded_circulant_tables(L, N, C):
+    """Lines whose extension length L = N + C has a prime factor above 13:
+    the library wraps the circulant's first column onto a 13-smooth length
+    M >= N + L.  Through the emulated engine (differenced extension padded
+    to M, forward stages, the table, inverse stages) the first N outputs are
+    the oracle's FC derivative (periodic derivative for C = 0); the filter's
+    table gives the oracle's filtered line; and with the wrapped kernel in
+    double precision the transposed sequence (Delta^T of the padded
+    cotangent, conjugate table, positions < N, tail fold) is the oracle's
+    transpose, which needs the wrap to cover m - n up to N."""
+    lib = L.lib()
+    Lx = N + C
+    assert not synth.smooth13(Lx)
+    M = lib.fcsd_host_embed_length(ctypes.c_int(N + Lx))
+    assert M >= N + Lx and synth.smooth13(M)
+    rad = L.fft_plan(M)
+    tw = np.exp(-2j * np.pi * np.arange(M) / M)
+    rng = np.random.default_rng(N + C)
+    F = synth.random_lines(rng, 2, N)
+    f = F[0] + 1j * F[1]
+    if C:
+        ArQ = L.fc_matrix(5, C)
+        ext = fcgram.extend(F, ArQ)
+        want = fcgram.diff_lines(F, 5, C)
+    else:
+        ext = F
+        want = fcgram.periodic_derivative(F, 1.0)
+    e = ext[0] + 1j * ext[1]
+    dz = np.concatenate([np.roll(e, -1) - e, np.zeros(M - Lx)])
+    out = np.zeros(2 * M, np.float32)
+    r = (ctypes.c_int * 8)(*rad)
+    lib.fcsd_host_kmul_embedded(ctypes.c_int(N), ctypes.c_int(Lx), ctypes.c_int(M), ctypes.c_int(len(rad)), r,
+                                out.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(1 if C == 0 else 0))
+    km = out[0::2].astype(np.float64) + 1j * out[1::2]
+    d = emulate_engine(km * emulate_engine(dz, rad, tw, False), rad, tw, True)[:N]
+    assert np.abs(d.real - want[0]).max() <= 1e-5 * np.abs(want[0]).max()
+    assert np.abs(d.imag - want[1]).max() <= 1e-5 * np.abs(want[1]).max()
+    # the table is DFT_M of the wrapped first column of the length-L circulant
+    kw = _position_wavenumbers(M, rad)
+    ks = np.fft.fftfreq(Lx) * Lx
+    period = 1.0 if C == 0 else Lx / (N - 1)
+    with np.errstate(all="ignore"):
+        mult = np.where(ks == 0, 0, 2j * np.pi * ks / period / (np.exp(2j * np.pi * ks / Lx) - 1))
+    if Lx % 2 == 0:
+        mult[Lx // 2] = 0
+    h = np.fft.ifft(mult)
+    kM = np.zeros(M, complex)
+    for t in range(-(Lx - 1), N + 1):
+        kM[t % M] = h[t % Lx]
+    K = np.fft.fft(kM) / M
+    assert np.abs(km - K[kw]).max() <= 2e-7 * np.abs(K).max()
+    # filter factors: the filtered line through the same engine
+    out = np.zeros(2 * M, np.float32)
+    lib.fcsd_host_fmul_embedded(ctypes.c_int(N), ctypes.c_int(Lx), ctypes.c_int(M), ctypes.c_int(len(rad)), r,
+                                ctypes.c_double(10.0), ctypes.c_int(14), out.ctypes.data_as(ctypes.c_void_p))
+    kf = out[0::2].astype(np.float64) + 1j * out[1::2]
+    fl = emulate_engine(kf * emulate_engine(np.concatenate([e, np.zeros(M - Lx)]), rad, tw, False), rad, tw,
+                        True)[:N]
+    from oracle import filter as flt
+    wf = flt.filter_lines(F, 5, C, 10.0, 14)
+    assert np.abs(fl.real - wf[0]).max() <= 1e-6 * np.abs(wf[0]).max()
+    assert np.abs(fl.imag - wf[1]).max() <= 1e-6 * np.abs(wf[1]).max()
+    # transposed sequence with the wrapped kernel in double precision
+    y = synth.random_lines(rng, 2, N)
+    yz = y[0] + 1j * y[1]
+    v = np.zeros(M, complex)
+    v[:N] = yz
+    if C:
+        v[N] = yz[N - 1]
+        v[1:N] = yz[:N - 1] - yz[1:]
+        v[0] = -yz[0]
+    else:
+        v[:N] = np.roll(yz, 1) - yz
+    t = emulate_engine(np.conj(K[kw]) * emulate_engine(v, rad, tw, False), rad, tw, True)
+    if C:
+        # the tail positions N..Lx-1 of the length-L transpose, then the fold
+        got = t[:N].copy()
+        tail = t[N:Lx]
+        got[N - 5:] += ArQ.T @ tail
+        got[:5] += fcgram.left_matrix(ArQ).T @ tail
+        want_adj = fcgram.diff_lines_adj(y, 5, C)
+    else:
+        got = t[:N]
+        want_adj = -fcgram.periodic_derivative(y, 1.0)
+    assert np.abs(got.real - want_adj[0]).max() <= 1e-9 * np.abs(want_adj[0]).max()
+    assert np.abs(got.imag - want_adj[1]).max() <= 1e-9 * np.abs(want_adj[1]).max()
