@@ -228,12 +228,29 @@ fcsd_status fcsd_filter_adj(fcsd_ctx* ctx, const fcsd_set* set, const float* u, 
  * context's stream. */
 fcsd_status fcsd_set_walls(fcsd_set* set, const uint8_t* sides, float gamma);
 
-/* Map of a patch's grid to the plane: kind 0 Cartesian, (x, y) = (a0 + i da,
- * b0 + j db); kind 1 polar, (theta, r) = (a0 + i da, b0 + j db) and
- * (x, y) = r (cos theta, sin theta). */
+/* Map of a patch's grid (fractional indices i, j) to the plane (Sec. 3.1,
+ * eqs. mappings, param_S):
+ *   FCSD_MAP_CARTESIAN (x, y) = (a0 + i da, b0 + j db);
+ *   FCSD_MAP_POLAR     (theta, r) = (a0 + i da, b0 + j db),
+ *                      (x, y) = r (cos theta, sin theta);
+ *   FCSD_MAP_AFFINE    (x, y) = (x0, y0) + i (ux, uy) + j (vx, vy): the C- and
+ *                      I-type patches;
+ *   FCSD_MAP_STYPE     the S-type patch of eq. param_S, l(t) + s nu(t) with
+ *                      t = a0 + i da, s = b0 + j db, the arc
+ *                      l(t) = sum_{k < nmodes} (cx[k] cos kt + sx[k] sin kt,
+ *                                               cy[k] cos kt + sy[k] sin kt)
+ *                      and nu(t) the unit normal, the tangent l'(t) turned by
+ *                      -90 degrees (side = +1) or +90 degrees (side = -1);
+ *                      preimages by Newton's method on (t, s).
+ * Unused fields are ignored. */
+enum { FCSD_MAP_CARTESIAN = 0, FCSD_MAP_POLAR = 1, FCSD_MAP_AFFINE = 2, FCSD_MAP_STYPE = 3 };
 typedef struct {
   int32_t kind;
   double a0, da, b0, db;
+  double x0, y0, ux, uy, vx, vy;
+  double side;
+  int32_t nmodes; /* 1 .. 8 */
+  double cx[8], sx[8], cy[8], sy[8];
 } fcsd_patch_map;
 
 /* Inter-patch communication by interpolation (paper Sec. 3.4.1, Remark

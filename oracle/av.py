@@ -212,8 +212,8 @@ def smooth_blend(muh, ps):
             for q in range(ps.npatch):
                 if q == p:
                     continue
-                xi, eta = interp.preimage(ps.geom[q], x, y)
                 n1, n2 = int(ps.n1[q]), int(ps.n2[q])
+                xi, eta = interp.preimage(ps.geom[q], x, y, n1, n2)
                 inside = (xi >= 0) & (xi <= n1 - 1) & (eta >= 0) & (eta <= n2 - 1)
                 I = np.floor(np.where(inside, xi, 0) + 0.5).astype(int)
                 J = np.floor(np.where(inside, eta, 0) + 0.5).astype(int)
@@ -296,8 +296,8 @@ def smooth_blend_adj(mub, ps):
             for q in range(ps.npatch):
                 if q == p:
                     continue
-                xi, eta = interp.preimage(ps.geom[q], x, y)
                 n1, n2 = int(ps.n1[q]), int(ps.n2[q])
+                xi, eta = interp.preimage(ps.geom[q], x, y, n1, n2)
                 inside = (xi >= 0) & (xi <= n1 - 1) & (eta >= 0) & (eta <= n2 - 1)
                 I = np.floor(np.where(inside, xi, 0) + 0.5).astype(int)
                 J = np.floor(np.where(inside, eta, 0) + 0.5).astype(int)

@@ -15,10 +15,16 @@ The decomposition is checked first: no donor point may itself be a fringe
 (receiving) point.
 
 Readings:
-  * patch maps are given per patch (synth.PatchSet.geom): Cartesian
-    (x, y) = (a0 + i da, b0 + j db) or polar (theta, r) = (a0 + i da,
-    b0 + j db); a point's donor coordinates (xi, eta) are the fractional
-    grid indices of its preimage;
+  * patch maps are given per patch (synth.PatchSet.geom, one row of GEOM
+    numbers each): Cartesian (x, y) = (a0 + i da, b0 + j db); polar
+    (theta, r) = (a0 + i da, b0 + j db); affine (x, y) = (x0, y0) +
+    i (ux, uy) + j (vx, vy) (the C- and I-type patches of Sec. 3.1); and
+    S-type (eq. param_S) M = l(t) + s nu(t) with t = a0 + i da,
+    s = b0 + j db, the arc l(t) = sum_k (cx_k cos kt + sx_k sin kt,
+    cy_k cos kt + sy_k sin kt) and nu the unit normal, the tangent turned
+    by -90 degrees (side = +1) or +90 degrees (side = -1); a point's donor
+    coordinates (xi, eta) are the fractional grid indices of its preimage
+    (for S-type patches found by Newton's method on (t, s));
   * the stencil is centred on the nearest grid point, floor(xi + 1/2),
     moved inwards to stay on the grid; the local coordinates s = xi - ic,
     t = eta - jc lie in [-1/2, 1/2] (up to the inward move);
@@ -34,14 +40,131 @@ import numpy as np
 NF = 5
 
 
-def preimage(geom_row, x, y):
-    """Fractional grid indices (xi, eta) of physical points in one patch."""
-    kind, a0, da, b0, db = geom_row
-    if int(kind) == 0:
-        return (x - a0) / da, (y - b0) / db
-    th = np.arctan2(y, x)
-    r = np.hypot(x, y)
-    return (th - a0) / da, (r - b0) / db
+# layout of a patch-map row (synth.PatchSet.geom)
+KIND, A0, DA, B0, DB = 0, 1, 2, 3, 4
+X0, Y0, UX, UY, VX, VY = 5, 6, 7, 8, 9, 10
+SIDE, NMODES = 11, 12
+KMAX = 8
+CX, SX, CY, SY = 13, 13 + KMAX, 13 + 2 * KMAX, 13 + 3 * KMAX
+GEOM = 13 + 4 * KMAX
+CARTESIAN, POLAR, AFFINE, STYPE = 0, 1, 2, 3
+
+
+def arc(g, t, order=0):
+    """The S-type arc l(t) (order 0), l'(t) (1) or l''(t) (2), shape [2, ...]."""
+    t = np.asarray(t, np.float64)
+    x = np.zeros_like(t)
+    y = np.zeros_like(t)
+    for k in range(int(g[NMODES])):
+        c, s = np.cos(k * t), np.sin(k * t)
+        # d^order/dt^order of (a cos kt + b sin kt)
+        if order == 0:
+            fc, fs = c, s
+        elif order == 1:
+            fc, fs = -k * s, k * c
+        else:
+            fc, fs = -k * k * c, -k * k * s
+        x = x + g[CX + k] * fc + g[SX + k] * fs
+        y = y + g[CY + k] * fc + g[SY + k] * fs
+    return np.array([x, y])
+
+
+def normal(g, t):
+    """Unit normal nu(t) of the S-type arc and its derivative d nu / dt."""
+    d1, d2 = arc(g, t, 1), arc(g, t, 2)
+    sd = float(g[SIDE])
+    n = np.hypot(d1[0], d1[1])
+    rot = lambda v: sd * np.array([v[1], -v[0]])       # the tangent turned by -90 degrees (side +1)
+    nu = rot(d1) / n
+    dn = rot(d2) / n - rot(d1) * (d1[0] * d2[0] + d1[1] * d2[1]) / n ** 3
+    return nu, dn
+
+
+def image(g, i, j):
+    """Physical point (x, y) of fractional grid indices (i, j) of a patch."""
+    kind = int(g[KIND])
+    i = np.asarray(i, np.float64)
+    j = np.asarray(j, np.float64)
+    if kind == CARTESIAN:
+        return g[A0] + i * g[DA], g[B0] + j * g[DB]
+    if kind == POLAR:
+        th, r = g[A0] + i * g[DA], g[B0] + j * g[DB]
+        return r * np.cos(th), r * np.sin(th)
+    if kind == AFFINE:
+        return g[X0] + i * g[UX] + j * g[VX], g[Y0] + i * g[UY] + j * g[VY]
+    t, s = g[A0] + i * g[DA], g[B0] + j * g[DB]
+    l = arc(g, t)
+    nu, _ = normal(g, t)
+    return l[0] + s * nu[0], l[1] + s * nu[1]
+
+
+def _grid_image(g, n1, n2):
+    """Grid indices and images of the n1 x n2 grid and one ring beyond it."""
+    I, J = np.meshgrid(np.arange(-1, n1 + 1), np.arange(-1, n2 + 1))
+    I, J = I.ravel(), J.ravel()
+    gx, gy = image(g, I, J)
+    return I, J, gx, gy
+
+
+def _stype_preimage(g, x, y, grid):
+    """(t, s) with l(t) + s nu(t) = (x, y) by Newton's method on the 2 x 2
+    system, started from the grid point (of the patch grid and one ring of
+    points beyond it) nearest to (x, y); NaN where the iteration does not
+    settle."""
+    I, J, gx, gy = grid
+    k = int(np.argmin((gx - x) ** 2 + (gy - y) ** 2))
+    t = g[A0] + I[k] * g[DA]
+    s = g[B0] + J[k] * g[DB]
+    scale = 1.0 + abs(x) + abs(y)
+    for _ in range(50):
+        l = arc(g, t)
+        d1 = arc(g, t, 1)
+        nu, dn = normal(g, t)
+        f = np.array([l[0] + s * nu[0] - x, l[1] + s * nu[1] - y])
+        Jm = np.array([[d1[0] + s * dn[0], nu[0]], [d1[1] + s * dn[1], nu[1]]])
+        step = np.linalg.solve(Jm, f)
+        t -= step[0]
+        s -= step[1]
+        if np.hypot(f[0], f[1]) <= 1e-14 * scale and abs(step[0]) <= 1e-13 * (1 + abs(t)):
+            return t, s
+    l = arc(g, t)
+    nu, _ = normal(g, t)
+    if np.hypot(l[0] + s * nu[0] - x, l[1] + s * nu[1] - y) <= 1e-12 * scale:
+        return t, s
+    return np.nan, np.nan
+
+
+def preimage(geom_row, x, y, n1=None, n2=None):
+    """Fractional grid indices (xi, eta) of physical points in one patch
+    (n1, n2: the patch grid, needed for S-type patches)."""
+    g = geom_row
+    kind = int(g[KIND])
+    if kind == CARTESIAN:
+        return (x - g[A0]) / g[DA], (y - g[B0]) / g[DB]
+    if kind == POLAR:
+        th = np.arctan2(y, x)
+        r = np.hypot(x, y)
+        return (th - g[A0]) / g[DA], (r - g[B0]) / g[DB]
+    if kind == AFFINE:
+        det = g[UX] * g[VY] - g[VX] * g[UY]
+        dx, dy = x - g[X0], y - g[Y0]
+        return (dx * g[VY] - dy * g[VX]) / det, (g[UX] * dy - g[UY] * dx) / det
+    key = (np.asarray(g, np.float64).tobytes(), int(n1), int(n2), np.asarray(x, np.float64).tobytes(),
+           np.asarray(y, np.float64).tobytes())
+    if key not in _STYPE_CACHE:
+        grid = _grid_image(g, int(n1), int(n2))
+        out = [_stype_preimage(g, float(a), float(b), grid) for a, b in zip(np.ravel(x), np.ravel(y))]
+        t = np.array([o[0] for o in out]).reshape(np.shape(x))
+        s = np.array([o[1] for o in out]).reshape(np.shape(x))
+        if len(_STYPE_CACHE) > 256:
+            _STYPE_CACHE.clear()
+        _STYPE_CACHE[key] = ((t - g[A0]) / g[DA], (s - g[B0]) / g[DB])
+    xi, eta = _STYPE_CACHE[key]
+    return (float(xi), float(eta)) if np.ndim(x) == 0 else (xi.copy(), eta.copy())
+
+
+# S-type preimages of repeated queries (the same points every step)
+_STYPE_CACHE = {}
 
 
 def receivers(ps, p, nf=NF):
@@ -74,8 +197,8 @@ def build(ps, nf=NF):
             for q in range(ps.npatch):
                 if q == p:
                     continue
-                xi, eta = preimage(ps.geom[q], x, y)
                 n1, n2 = int(ps.n1[q]), int(ps.n2[q])
+                xi, eta = preimage(ps.geom[q], x, y, n1, n2)
                 dist = min(xi, n1 - 1 - xi, eta, n2 - 1 - eta)
                 if dist >= 1 and (best is None or dist > best[0]):
                     best = (dist, q, xi, eta)

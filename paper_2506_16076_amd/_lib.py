@@ -64,7 +64,29 @@ class Mlp(ctypes.Structure):
 
 class PatchMap(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("a0", ctypes.c_double), ("da", ctypes.c_double),
-                ("b0", ctypes.c_double), ("db", ctypes.c_double)]
+                ("b0", ctypes.c_double), ("db", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("ux", ctypes.c_double), ("uy", ctypes.c_double),
+                ("vx", ctypes.c_double), ("vy", ctypes.c_double), ("side", ctypes.c_double),
+                ("nmodes", ctypes.c_int32), ("cx", ctypes.c_double * 8), ("sx", ctypes.c_double * 8),
+                ("cy", ctypes.c_double * 8), ("sy", ctypes.c_double * 8)]
+
+    @classmethod
+    def from_row(cls, r):
+        """A patch-map row (kind, a0, da, b0, db, x0, y0, ux, uy, vx, vy, side,
+        nmodes, cx[8], sx[8], cy[8], sy[8]); rows of 5 numbers are the
+        Cartesian and polar maps."""
+        r = np.zeros(45) if r is None else np.concatenate([np.asarray(r, np.float64), np.zeros(45)])[:45]
+        m = cls()
+        m.kind = int(r[0])
+        m.a0, m.da, m.b0, m.db = (float(v) for v in r[1:5])
+        m.x0, m.y0, m.ux, m.uy, m.vx, m.vy = (float(v) for v in r[5:11])
+        m.side = float(r[11])
+        m.nmodes = int(r[12])
+        for name, o in (("cx", 13), ("sx", 21), ("cy", 29), ("sy", 37)):
+            arr = getattr(m, name)
+            for k in range(8):
+                arr[k] = float(r[o + k])
+        return m
 
 
 class StepArgs(ctypes.Structure):

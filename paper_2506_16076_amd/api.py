@@ -188,11 +188,13 @@ class PatchSet:
 
     def set_interp(self, maps, nf: int = 5) -> int:
         """Inter-patch interpolation of the fringe (paper Sec. 3.4.1) from
-        patch maps: rows (kind, a0, da, b0, db), kind 0 Cartesian, 1 polar.
-        Returns the number of fringe points."""
+        patch maps, one row per patch: (kind, a0, da, b0, db, x0, y0, ux, uy,
+        vx, vy, side, nmodes, cx[8], sx[8], cy[8], sy[8]) (fcsd_patch_map;
+        kind 0 Cartesian, 1 polar, 2 affine, 3 S-type; rows of 5 numbers
+        for the first two).  Returns the number of fringe points."""
         from ._lib import PatchMap
-        rows = np.asarray(maps, np.float64).reshape(-1, 5)
-        arr = (PatchMap * len(rows))(*[PatchMap(int(r[0]), r[1], r[2], r[3], r[4]) for r in rows])
+        rows = [np.asarray(r, np.float64) for r in maps]
+        arr = (PatchMap * len(rows))(*[PatchMap.from_row(r) for r in rows])
         n = ctypes.c_int64()
         self.ctx.check(lib().fcsd_set_interp(self.h, arr, int(nf), ctypes.byref(n)), "fcsd_set_interp")
         return n.value

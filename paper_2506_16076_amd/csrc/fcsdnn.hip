@@ -1896,6 +1896,149 @@ extern "C" fcsd_status fcsd_set_walls(fcsd_set* s, const uint8_t* sides, float g
   return FCSD_OK;
 }
 
+namespace {
+
+// Evaluation of a patch map (fcsd_patch_map) and of its inverse.
+struct MapEval {
+  const fcsd_patch_map& m;
+  int n1, n2;
+
+  // the S-type arc l (order 0), l' (1) or l'' (2) at t
+  void arc(double t, int order, double& x, double& y) const {
+    x = y = 0.0;
+    for (int k = 0; k < m.nmodes; ++k) {
+      const double c = std::cos(k * t), sn = std::sin(k * t);
+      double fc = c, fs = sn;
+      if (order == 1) {
+        fc = -k * sn;
+        fs = k * c;
+      } else if (order == 2) {
+        fc = -(double)k * k * c;
+        fs = -(double)k * k * sn;
+      }
+      x += m.cx[k] * fc + m.sx[k] * fs;
+      y += m.cy[k] * fc + m.sy[k] * fs;
+    }
+  }
+  // unit normal nu(t) = side * (l'_y, -l'_x) / |l'| and its derivative
+  void normal(double t, double nu[2], double dnu[2]) const {
+    double ax, ay, bx, by;
+    arc(t, 1, ax, ay);
+    arc(t, 2, bx, by);
+    const double n = std::hypot(ax, ay), dot = ax * bx + ay * by, sd = m.side;
+    nu[0] = sd * ay / n;
+    nu[1] = -sd * ax / n;
+    dnu[0] = sd * (by / n - ay * dot / (n * n * n));
+    dnu[1] = -sd * (bx / n - ax * dot / (n * n * n));
+  }
+  void image(double i, double j, double& x, double& y) const {
+    switch (m.kind) {
+      case FCSD_MAP_CARTESIAN:
+        x = m.a0 + i * m.da;
+        y = m.b0 + j * m.db;
+        return;
+      case FCSD_MAP_POLAR: {
+        const double th = m.a0 + i * m.da, r = m.b0 + j * m.db;
+        x = r * std::cos(th);
+        y = r * std::sin(th);
+        return;
+      }
+      case FCSD_MAP_AFFINE:
+        x = m.x0 + i * m.ux + j * m.vx;
+        y = m.y0 + i * m.uy + j * m.vy;
+        return;
+      default: {
+        const double t = m.a0 + i * m.da, sv = m.b0 + j * m.db;
+        double lx, ly, nu[2], dn[2];
+        arc(t, 0, lx, ly);
+        normal(t, nu, dn);
+        x = lx + sv * nu[0];
+        y = ly + sv * nu[1];
+      }
+    }
+  }
+  // fractional grid indices of (x, y); false where an S-type inverse does
+  // not settle
+  bool preimage(double x, double y, double& xi, double& eta) const {
+    switch (m.kind) {
+      case FCSD_MAP_CARTESIAN:
+        xi = (x - m.a0) / m.da;
+        eta = (y - m.b0) / m.db;
+        return true;
+      case FCSD_MAP_POLAR:
+        xi = (std::atan2(y, x) - m.a0) / m.da;
+        eta = (std::hypot(x, y) - m.b0) / m.db;
+        return true;
+      case FCSD_MAP_AFFINE: {
+        const double det = m.ux * m.vy - m.vx * m.uy, dx = x - m.x0, dy = y - m.y0;
+        xi = (dx * m.vy - dy * m.vx) / det;
+        eta = (m.ux * dy - m.uy * dx) / det;
+        return true;
+      }
+      default:
+        break;
+    }
+    // S-type: start at the foot point on the arc -- of the arc parameters of
+    // the grid columns (and one beyond each end), the one where (x, y) - l(t)
+    // is most nearly normal to the arc -- then Newton's method on
+    // l(t) + s nu(t) = (x, y)
+    double t = m.a0, sv = 0.0, best = 1e300;
+    for (int i = -1; i <= n1; ++i) {
+      const double tc = m.a0 + i * m.da;
+      double lx, ly, tx, ty, nu[2], dn[2];
+      arc(tc, 0, lx, ly);
+      arc(tc, 1, tx, ty);
+      normal(tc, nu, dn);
+      const double dx = x - lx, dy = y - ly, tn = std::hypot(tx, ty);
+      const double along = std::fabs(dx * tx + dy * ty) / tn, across = dx * nu[0] + dy * nu[1];
+      const double score = along + 1e-3 * std::fabs(across);
+      if (score < best) {
+        best = score;
+        t = tc;
+        sv = across;
+      }
+    }
+    const double scale = 1.0 + std::fabs(x) + std::fabs(y);
+    for (int it = 0; it < 60; ++it) {
+      double lx, ly, ax, ay, nu[2], dn[2];
+      arc(t, 0, lx, ly);
+      arc(t, 1, ax, ay);
+      normal(t, nu, dn);
+      const double fx = lx + sv * nu[0] - x, fy = ly + sv * nu[1] - y;
+      const double j11 = ax + sv * dn[0], j21 = ay + sv * dn[1], j12 = nu[0], j22 = nu[1];
+      const double det = j11 * j22 - j12 * j21;
+      if (!(std::fabs(det) > 0.0)) return false;
+      const double dt = (fx * j22 - fy * j12) / det, ds = (j11 * fy - j21 * fx) / det;
+      t -= dt;
+      sv -= ds;
+      if (std::hypot(fx, fy) <= 1e-14 * scale && std::fabs(dt) <= 1e-13 * (1.0 + std::fabs(t))) break;
+    }
+    double lx, ly, nu[2], dn[2];
+    arc(t, 0, lx, ly);
+    normal(t, nu, dn);
+    if (!(std::hypot(lx + sv * nu[0] - x, ly + sv * nu[1] - y) <= 1e-12 * scale)) return false;
+    xi = (t - m.a0) / m.da;
+    eta = (sv - m.b0) / m.db;
+    return true;
+  }
+};
+
+bool map_valid(const fcsd_patch_map& m) {
+  switch (m.kind) {
+    case FCSD_MAP_CARTESIAN:
+    case FCSD_MAP_POLAR:
+      return m.da > 0 && m.db > 0;
+    case FCSD_MAP_AFFINE:
+      return std::isfinite(m.ux * m.vy - m.vx * m.uy) && std::fabs(m.ux * m.vy - m.vx * m.uy) > 0;
+    case FCSD_MAP_STYPE:
+      return m.da > 0 && m.db > 0 && m.nmodes >= 1 && m.nmodes <= 8 && (m.side == 1.0 || m.side == -1.0);
+    default:
+      return false;
+  }
+}
+
+}  // namespace
+
 extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, int nf, int64_t* nrecv) {
   if (!s) return FCSD_EINVAL;
   fcsd_ctx* ctx = s->ctx;
@@ -1903,11 +2046,15 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
   if (s->annulus) return fail(ctx, FCSD_EUNSUPPORTED, "fcsd_set_interp: index-aligned sets glue by copy");
   const int np = s->npatch;
   for (int p = 0; p < np; ++p)
-    if ((maps[p].kind != 0 && maps[p].kind != 1) || !(maps[p].da > 0) || !(maps[p].db > 0))
-      return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: bad patch map (kind 0 or 1, positive steps)");
+    if (!map_valid(maps[p]))
+      return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: bad patch map " + std::to_string(p) +
+                                        " (unknown kind, non-positive steps, singular affine map, or an S-type "
+                                        "arc without 1..8 modes or side +-1)");
   int minside = 1 << 30;
   for (const fcsd_patch_desc& q : s->desc) minside = std::min(minside, std::min(q.n1, q.n2));
   if (nf < 1 || 2 * nf + 3 > minside) return fail(ctx, FCSD_EINVAL, "fcsd_set_interp: fringe width out of range");
+  std::vector<MapEval> ev;
+  for (int p = 0; p < np; ++p) ev.push_back(MapEval{maps[p], s->desc[p].n1, s->desc[p].n2});
   // physical bounding box of every patch (its boundary sampled at the grid
   // points, a polar side's arc also at the axis crossings it spans), to skip
   // the preimage of patches that cannot hold a point
@@ -1915,40 +2062,38 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
   for (int p = 0; p < np; ++p) {
     const fcsd_patch_desc& q = s->desc[p];
     const fcsd_patch_map& m = maps[p];
-    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300, hmax = 0.0, px = 0.0, py = 0.0;
+    bool first = true;
     auto add = [&](double x, double y) {
       x0 = std::min(x0, x);
       x1 = std::max(x1, x);
       y0 = std::min(y0, y);
       y1 = std::max(y1, y);
     };
+    // the boundary walked in order (consecutive samples give the largest
+    // boundary spacing)
     auto pt = [&](double i, double j) {
-      if (m.kind == 0) {
-        add(m.a0 + i * m.da, m.b0 + j * m.db);
-      } else {
-        const double th = m.a0 + i * m.da, r = m.b0 + j * m.db;
-        add(r * std::cos(th), r * std::sin(th));
-      }
+      double x, y;
+      ev[p].image(i, j, x, y);
+      add(x, y);
+      if (!first) hmax = std::max(hmax, std::hypot(x - px, y - py));
+      first = false;
+      px = x;
+      py = y;
     };
-    for (int i = 0; i < q.n1; ++i) {
-      pt(i, 0);
-      pt(i, q.n2 - 1);
-    }
-    for (int j = 0; j < q.n2; ++j) {
-      pt(0, j);
-      pt(q.n1 - 1, j);
-    }
-    if (m.kind == 1) {  // axis crossings inside the angular range
+    for (int i = 0; i < q.n1; ++i) pt(i, 0);
+    for (int j = 0; j < q.n2; ++j) pt(q.n1 - 1, j);
+    for (int i = q.n1 - 1; i >= 0; --i) pt(i, q.n2 - 1);
+    for (int j = q.n2 - 1; j >= 0; --j) pt(0, j);
+    if (m.kind == FCSD_MAP_POLAR) {  // axis crossings inside the angular range
       const double t0 = m.a0, t1 = m.a0 + (q.n1 - 1) * m.da, rmax = m.b0 + (q.n2 - 1) * m.db;
       for (int k = -8; k <= 8; ++k) {
         const double a = k * 0.5 * 3.14159265358979323846;
         if (a > t0 && a < t1) add(rmax * std::cos(a), rmax * std::sin(a));
       }
     }
-    // generous margin: two grid spacings (covers the bulge of an arc between
-    // its sampled points); the box only spares work
-    const double hmax = m.kind == 0 ? std::max(m.da, m.db)
-                                    : std::max((m.b0 + (q.n2 - 1) * m.db) * m.da, m.db);
+    // generous margin: two of the largest boundary spacings (covers the
+    // bulge of a curved side between its samples); the box only spares work
     const double pad = 2.0 * hmax + 1e-9 * (1.0 + std::max(x1 - x0, y1 - y0));
     box[p] = {x0 - pad, x1 + pad, y0 - pad, y1 + pad};
   }
@@ -1964,19 +2109,11 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
   std::vector<InterpDev> tab;
   for (int p = 0; p < np; ++p) {
     const fcsd_patch_desc& q = s->desc[p];
-    const fcsd_patch_map& m = maps[p];
     for (int j = 0; j < q.n2; ++j)
       for (int i = 0; i < q.n1; ++i) {
         if (!recv(p, i, j)) continue;
         double x, y;
-        if (m.kind == 0) {
-          x = m.a0 + i * m.da;
-          y = m.b0 + j * m.db;
-        } else {
-          const double th = m.a0 + i * m.da, r = m.b0 + j * m.db;
-          x = r * std::cos(th);
-          y = r * std::sin(th);
-        }
+        ev[p].image(i, j, x, y);
         // donor: the other patch holding a full stencil around the point's
         // preimage in which the point lies farthest from the boundary (the
         // lower index on ties)
@@ -1984,15 +2121,8 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
         double bd = 0.0, bxi = 0.0, beta = 0.0;
         for (int d = 0; d < np; ++d) {
           if (d == p || !in_box(d, x, y)) continue;
-          const fcsd_patch_map& dm = maps[d];
           double xi, eta;
-          if (dm.kind == 0) {
-            xi = (x - dm.a0) / dm.da;
-            eta = (y - dm.b0) / dm.db;
-          } else {
-            xi = (std::atan2(y, x) - dm.a0) / dm.da;
-            eta = (std::hypot(x, y) - dm.b0) / dm.db;
-          }
+          if (!ev[d].preimage(x, y, xi, eta)) continue;
           const fcsd_patch_desc& dq = s->desc[d];
           const double dist = std::min(std::min(xi, dq.n1 - 1 - xi), std::min(eta, dq.n2 - 1 - eta));
           if (dist >= 1.0 && (best < 0 || dist > bd)) {
@@ -2024,7 +2154,6 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
   std::vector<long long> osrc;
   for (int p = 0; p < np; ++p) {
     const fcsd_patch_desc& q = s->desc[p];
-    const fcsd_patch_map& m = maps[p];
     PatchDev P{};
     P.n1 = q.n1;
     P.n2 = q.n2;
@@ -2033,26 +2162,12 @@ extern "C" fcsd_status fcsd_set_interp(fcsd_set* s, const fcsd_patch_map* maps, 
     for (int j = 0; j < q.n2; ++j)
       for (int i = 0; i < q.n1; ++i) {
         double x, y;
-        if (m.kind == 0) {
-          x = m.a0 + i * m.da;
-          y = m.b0 + j * m.db;
-        } else {
-          const double th = m.a0 + i * m.da, r = m.b0 + j * m.db;
-          x = r * std::cos(th);
-          y = r * std::sin(th);
-        }
+        ev[p].image(i, j, x, y);
         const int begin = (int)osrc.size();
         for (int d = 0; d < np; ++d) {
           if (d == p || !in_box(d, x, y)) continue;
-          const fcsd_patch_map& dm = maps[d];
           double xi, eta;
-          if (dm.kind == 0) {
-            xi = (x - dm.a0) / dm.da;
-            eta = (y - dm.b0) / dm.db;
-          } else {
-            xi = (std::atan2(y, x) - dm.a0) / dm.da;
-            eta = (std::hypot(x, y) - dm.b0) / dm.db;
-          }
+          if (!ev[d].preimage(x, y, xi, eta)) continue;
           const fcsd_patch_desc& dq = s->desc[d];
           if (!(xi >= 0.0 && xi <= dq.n1 - 1 && eta >= 0.0 && eta <= dq.n2 - 1)) continue;
           const long long I = (long long)std::floor(xi + 0.5), J = (long long)std::floor(eta + 0.5);

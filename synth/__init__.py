@@ -210,7 +210,120 @@ def overlap_pair(n: int = 48, d: int = 5, c_min: int = 27) -> PatchSet:
     ps.htilde[0], ps.hhat[0] = min(hx, hy), max(hx, hy)
     ps.internal[0] = (0, 1, 0, 0)
     ps.internal[1] = (0, 0, 1, 0)
-    ps.geom = np.array([[0, -1.0, hx, -0.5, hy], [1, -1.0, ht, 0.3, hr]], np.float64)
+    ps.geom = np.array([geom_row(0, -1.0, hx, -0.5, hy), geom_row(1, -1.0, ht, 0.3, hr)])
+    return ps
+
+
+# patch-map rows (PatchSet.geom): kind, a0, da, b0, db, affine x0, y0, ux, uy,
+# vx, vy, S-type side, mode count, then the arc's cos / sin coefficients of x
+# and of y (GEOM_KMAX each)
+GEOM_KMAX = 8
+GEOM_LEN = 13 + 4 * GEOM_KMAX
+
+
+def geom_row(kind, a0=0.0, da=1.0, b0=0.0, db=1.0, affine=(0, 0, 1, 0, 0, 1), side=1.0, cx=(), sx=(), cy=(),
+             sy=()):
+    """One patch map: 0 Cartesian (x, y) = (a0 + i da, b0 + j db); 1 polar
+    (theta, r) = (a0 + i da, b0 + j db); 2 affine (x, y) = (x0, y0) +
+    i (ux, uy) + j (vx, vy); 3 S-type (eq. param_S) l(t) + s nu(t),
+    t = a0 + i da, s = b0 + j db, l(t) = sum_k (cx_k cos kt + sx_k sin kt,
+    cy_k cos kt + sy_k sin kt), nu the unit normal (tangent turned by
+    -90 degrees for side = +1)."""
+    g = np.zeros(GEOM_LEN)
+    g[:5] = kind, a0, da, b0, db
+    g[5:11] = affine
+    g[11] = side
+    K = max(len(cx), len(sx), len(cy), len(sy))
+    g[12] = K
+    for o, c in ((13, cx), (13 + GEOM_KMAX, sx), (13 + 2 * GEOM_KMAX, cy), (13 + 3 * GEOM_KMAX, sy)):
+        g[o:o + len(c)] = c
+    return g
+
+
+def _arc_derivs(g, t):
+    """l, l', l'' of an S-type row's arc at t (arrays [2, ...])."""
+    K = int(g[12])
+    out = [np.zeros((2,) + np.shape(t)) for _ in range(3)]
+    for k in range(K):
+        c, s_ = np.cos(k * t), np.sin(k * t)
+        for comp, (oc, os_) in enumerate(((13, 13 + GEOM_KMAX), (13 + 2 * GEOM_KMAX, 13 + 3 * GEOM_KMAX))):
+            a, b = g[oc + k], g[os_ + k]
+            out[0][comp] += a * c + b * s_
+            out[1][comp] += k * (-a * s_ + b * c)
+            out[2][comp] += -k * k * (a * c + b * s_)
+    return out
+
+
+def _mapped_patch(g, n1, n2):
+    """Physical points [2, n2, n1] and inverse-Jacobian metric terms
+    [4, n2, n1] (dq1/dx, dq1/dy, dq2/dx, dq2/dy, with q = index / (n - 1))
+    of an affine or S-type patch map, in closed form."""
+    I, J = np.meshgrid(np.arange(n1, dtype=np.float64), np.arange(n2, dtype=np.float64))
+    if int(g[0]) == 2:
+        x0, y0, ux, uy, vx, vy = g[5:11]
+        X, Y = x0 + I * ux + J * vx, y0 + I * uy + J * vy
+        xq1, yq1 = np.full_like(I, ux * (n1 - 1)), np.full_like(I, uy * (n1 - 1))
+        xq2, yq2 = np.full_like(I, vx * (n2 - 1)), np.full_like(I, vy * (n2 - 1))
+    else:
+        t, sv = g[1] + I * g[2], g[3] + J * g[4]
+        l, d1, d2 = _arc_derivs(g, t)
+        sd = g[11]
+        nrm = np.hypot(d1[0], d1[1])
+        nu = sd * np.array([d1[1], -d1[0]]) / nrm
+        dot = d1[0] * d2[0] + d1[1] * d2[1]
+        dnu = sd * (np.array([d2[1], -d2[0]]) / nrm - np.array([d1[1], -d1[0]]) * dot / nrm ** 3)
+        X, Y = l[0] + sv * nu[0], l[1] + sv * nu[1]
+        xq1, yq1 = (d1[0] + sv * dnu[0]) * g[2] * (n1 - 1), (d1[1] + sv * dnu[1]) * g[2] * (n1 - 1)
+        xq2, yq2 = nu[0] * g[4] * (n2 - 1), nu[1] * g[4] * (n2 - 1)
+    det = xq1 * yq2 - xq2 * yq1
+    metric = np.array([yq2 / det, -xq2 / det, -yq1 / det, xq1 / det])
+    return np.array([X, Y]), metric
+
+
+def stype_trio(n: int = 48, d: int = 5, c_min: int = 27) -> PatchSet:
+    """Three patches of the paper's kinds that overlap without shared grid
+    lines: patch 0 an S-type band (eq. param_S) of width 0.5 along the arc
+    t in [pi/2 - 0.6, pi/2 + 0.6] of the smooth closed curve
+    l(t) = (0.6 cos t + 0.04 cos 3t, 0.4 sin t + 0.03 sin 2t), normal
+    pointing away from the curve's inside; patch 1 an affine (I-type)
+    parallelogram over it (rotated 8 degrees); patch 2 a small affine square
+    (rotated -12 degrees) inside the band.  Internal sides: the band's outer
+    side (fringe inside patch 1) and every side of patch 2 (fringe inside the
+    band); the other sides are free.  n x n points each."""
+    n1 = np.array([n] * 3, np.int32)
+    n2 = n1.copy()
+    off, plane = _offsets(n1, n2)
+    span, H = 1.2, 0.5
+    g0 = geom_row(3, np.pi / 2 - 0.6, span / (n - 1), 0.0, H / (n - 1), side=1.0,
+                  cx=(0.0, 0.6, 0.0, 0.04), sy=(0.0, 0.4, 0.03))
+    a1, a2 = np.deg2rad(8.0), np.deg2rad(-12.0)
+    w1, h1 = 1.9, 0.9
+    u1 = np.array([np.cos(a1), np.sin(a1)]) * w1 / (n - 1)
+    v1 = np.array([-np.sin(a1), np.cos(a1)]) * h1 / (n - 1)
+    c1 = np.array([0.0, 1.05]) - 0.5 * (n - 1) * (u1 + v1)
+    g1 = geom_row(2, affine=(c1[0], c1[1], u1[0], u1[1], v1[0], v1[1]))
+    w2 = 0.3
+    u2 = np.array([np.cos(a2), np.sin(a2)]) * w2 / (n - 1)
+    v2 = np.array([-np.sin(a2), np.cos(a2)]) * w2 / (n - 1)
+    c2 = np.array([0.0, 0.65]) - 0.5 * (n - 1) * (u2 + v2)
+    g2 = geom_row(2, affine=(c2[0], c2[1], u2[0], u2[1], v2[0], v2[1]))
+    xy = np.zeros((2, plane))
+    metric = np.zeros((4, plane), np.float32)
+    htl = np.zeros(3)
+    hht = np.zeros(3)
+    for p, g in enumerate((g0, g1, g2)):
+        P, M = _mapped_patch(g, n, n)
+        o = int(off[p])
+        xy[:, o:o + n * n] = P.reshape(2, -1)
+        metric[:, o:o + n * n] = M.reshape(4, -1).astype(np.float32)
+        hs = np.concatenate([np.hypot(*np.diff(P, axis=2)).ravel(), np.hypot(*np.diff(P, axis=1)).ravel()])
+        htl[p], hht[p] = hs.min(), hs.max()
+    C1 = np.array([cont_points(n, c_min)] * 3, np.int32)
+    ps = PatchSet(n1=n1, n2=n2, C1=C1, C2=C1.copy(), d=d, off=off, plane=plane, metric=metric, htilde=htl,
+                  hhat=hht, internal=np.zeros((3, 4), np.uint8), xy=xy)
+    ps.internal[0] = (0, 0, 0, 1)
+    ps.internal[2] = (1, 1, 1, 1)
+    ps.geom = np.array([g0, g1, g2])
     return ps
 
 
@@ -402,13 +515,14 @@ def paper_subpatches(nsec: int = 16, nshell: int = 1, seed: int = 5, mach: float
                   mach=mach, pert=pert, mlp=mlp_weights(1000 + seed), steps=100)
 
 
-def overlap_config(n: int = 48, seed: int = 6, mach: float = 3.0, network: bool = False) -> Config:
-    """The Cartesian / polar patch pair of overlap_pair with the Mach-3
-    freestream state and its +-1 % density perturbation, seeded network
-    weights (network=False: a constant viscosity instead); no Dirichlet
-    points."""
+def overlap_config(n: int = 48, seed: int = 6, mach: float = 3.0, network: bool = False,
+                   stype: bool = False) -> Config:
+    """The Cartesian / polar patch pair of overlap_pair (stype=True: the
+    S-type / affine trio of stype_trio) with the Mach-3 freestream state and
+    its +-1 % density perturbation, seeded network weights (network=False: a
+    constant viscosity instead); no Dirichlet points."""
     rng = np.random.default_rng(seed)
-    ps = overlap_pair(n)
+    ps = overlap_pair(n) if not stype else stype_trio(n)
     pert = draw_perturbation(rng)
     e = mach_state(ps, mach, pert)
     if not network:

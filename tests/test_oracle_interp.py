@@ -93,6 +93,102 @@ def test_table_is_a_valid_decomposition():
         assert abs(ic + s - xi) < 1e-12 and abs(jc + t - eta) < 1e-12
 
 
+# ------------------------------------------------------------ the paper's patch kinds (Sec. 3.1)
+
+def test_stype_map_of_a_circle_is_the_polar_map():
+    """An S-type band (eq. param_S) along the circle l(t) = R (cos t, sin t)
+    with the normal pointing outwards is the polar patch (theta, r) =
+    (t, R + s): the same points, and the Newton preimage equals the closed
+    form (the textbook inverse of polar coordinates)."""
+    R, a0, da, b0, db = 0.7, 0.3, 0.02, 0.05, 0.01
+    gS = synth.geom_row(3, a0, da, b0, db, side=1.0, cx=(0.0, R), sy=(0.0, R))
+    gP = synth.geom_row(1, a0, da, R + b0, db)
+    rng = np.random.default_rng(1)
+    i, j = rng.uniform(-0.5, 40.5, 40), rng.uniform(-0.5, 30.5, 40)
+    xP, yP = interp.image(gP, i, j)
+    xS, yS = interp.image(gS, i, j)
+    assert np.abs(xS - xP).max() < 1e-14 and np.abs(yS - yP).max() < 1e-14
+    xi, eta = interp.preimage(gS, xP, yP, 41, 31)
+    assert np.abs(xi - i).max() < 1e-10 and np.abs(eta - j).max() < 1e-10
+    xq, eq = interp.preimage(gP, xP, yP)
+    assert np.abs(xi - xq).max() < 1e-10 and np.abs(eta - eq).max() < 1e-10
+    # side = -1 turns the normal inwards: the band of radius R - s
+    gI = synth.geom_row(3, a0, da, b0, db, side=-1.0, cx=(0.0, R), sy=(0.0, R))
+    xI, yI = interp.image(gI, i, j)
+    r = R - (b0 + j * db)
+    assert np.abs(xI - r * np.cos(a0 + i * da)).max() < 1e-14
+
+
+def test_affine_map_preimage():
+    """An affine map with axis-aligned steps is the Cartesian map; a
+    rotated, sheared one inverts exactly."""
+    gA = synth.geom_row(2, affine=(-0.3, 0.2, 0.01, 0.0, 0.0, 0.02))
+    gC = synth.geom_row(0, -0.3, 0.01, 0.2, 0.02)
+    rng = np.random.default_rng(2)
+    x, y = rng.uniform(-1, 1, 50), rng.uniform(-1, 1, 50)
+    a, b = interp.preimage(gA, x, y)
+    c, d = interp.preimage(gC, x, y)
+    assert np.abs(a - c).max() < 1e-12 and np.abs(b - d).max() < 1e-12
+    gR = synth.geom_row(2, affine=(0.1, -0.4, 0.013, 0.004, -0.003, 0.017))
+    i, j = rng.uniform(0, 60, 50), rng.uniform(0, 60, 50)
+    a, b = interp.preimage(gR, *interp.image(gR, i, j))
+    assert np.abs(a - i).max() < 1e-10 and np.abs(b - j).max() < 1e-10
+
+
+def test_stype_trio_geometry():
+    """The S-type / affine trio: the Newton preimage inverts the band's map
+    on and around its grid (fractional indices), and the recipe's metric
+    terms are the inverse Jacobians of the maps (central differences of the
+    images, second order)."""
+    ps = synth.stype_trio(48)
+    rng = np.random.default_rng(3)
+    g = ps.geom[0]
+    i, j = rng.uniform(-0.5, 47.5, 60), rng.uniform(-0.5, 47.5, 60)
+    xi, eta = interp.preimage(g, *interp.image(g, i, j), 48, 48)
+    assert np.abs(xi - i).max() < 1e-9 and np.abs(eta - j).max() < 1e-9
+    for p in range(3):
+        gp = ps.geom[p]
+        I, J = np.meshgrid(np.arange(48.0), np.arange(48.0))
+        e = 1e-4
+        xq1 = (np.array(interp.image(gp, I + e, J)) - np.array(interp.image(gp, I - e, J))) / (2 * e) * 47
+        xq2 = (np.array(interp.image(gp, I, J + e)) - np.array(interp.image(gp, I, J - e))) / (2 * e) * 47
+        det = xq1[0] * xq2[1] - xq2[0] * xq1[1]
+        inv = np.array([xq2[1] / det, -xq2[0] / det, -xq1[1] / det, xq1[0] / det])
+        got = ps.view(ps.metric, p)
+        assert np.abs(got - inv).max() <= 1e-5 * np.abs(inv).max()
+        x, y = ps.view(ps.xy, p)
+        X, Y = interp.image(gp, I, J)
+        assert np.abs(x - X).max() < 1e-13 and np.abs(y - Y).max() < 1e-13
+
+
+def test_stype_trio_table_and_quadratics():
+    """On the trio every fringe point gets a donor (S-type donors through
+    the Newton preimage) whose stencil holds no fringe point, and the
+    iterated interpolation reproduces, at every fringe point, a field that
+    is a product of quadratics in its donor's own grid indices."""
+    ps = synth.stype_trio(48)
+    table = interp.build(ps)
+    masks = [interp.receivers(ps, p) for p in range(ps.npatch)]
+    assert len(table) == sum(int(m.sum()) for m in masks)
+    kinds = set()
+    for (p, i, j, q, ic, jc, s, t) in table:
+        assert q != p and masks[p][j, i] and not masks[q][jc - 1:jc + 2, ic - 1:ic + 2].any()
+        kinds.add(int(ps.geom[q, 0]))
+    assert kinds == {2, 3}
+    Q = [lambda i, j: (1 + 0.03 * i - 0.001 * i * i) * (0.5 - 0.02 * j + 0.0007 * j * j),
+         lambda i, j: (0.2 + 0.05 * i - 0.0008 * i * i) * (1.1 + 0.01 * j - 0.0004 * j * j),
+         lambda i, j: (0.7 - 0.04 * i + 0.0006 * i * i) * (0.3 + 0.03 * j + 0.0005 * j * j)]
+    e = np.zeros((1, ps.plane))
+    for p in range(3):
+        J, I = np.mgrid[0:48, 0:48]
+        ps.view(e, p)[0] = Q[p](I.astype(float), J.astype(float))
+    want = e.copy()
+    for (p, i, j, q, ic, jc, s, t) in table:
+        ps.view(want, p)[0, j, i] = Q[q](ic + s, jc + t)
+    got = interp.interpolate(e.copy(), ps, table)
+    assert np.abs(got - want).max() <= 1e-12
+
+
 def test_thin_overlap_is_refused():
     ps = synth.overlap_pair(48)
     # shrink the Cartesian patch's reach: its fringe now lies where the
