@@ -1039,9 +1039,12 @@ def test_wall_condition(env):
     got = H(xd).reshape(4, -1)
     want = x.astype(np.float64).copy()
     solver.glue(want, ps, cfg.mach, G)
-    err = np.abs(got - want).max(axis=1) / np.abs(want).max(axis=1)
+    # rho v is zero in this flow: its error is taken against the momentum's scale
+    scale = np.abs(want).max(axis=1)
+    scale[2] = scale[1]
+    err = np.abs(got - want).max(axis=1) / scale
     say("wall glue max rel error", err)
-    assert np.all(err[[0, 1, 3]] <= 1e-6) and np.abs(got[2] - want[2]).max() <= 1e-6 * np.abs(want[1]).max()
+    assert np.all(err <= 1e-6)
     for p in range(ps.npatch):
         if ps.wall[p, 2]:
             assert np.all(ps.view(got, p)[1:3, 0] == 0)
