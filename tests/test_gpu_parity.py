@@ -1588,17 +1588,23 @@ def _subset(ps, plist):
                                nsec=0, nshell=0, dirichlet=None)
 
 
-@pytest.mark.parametrize("idx", [1, 2, 4])
+@pytest.mark.parametrize("idx", [1, 2, 4, "2-strict"])
 def test_full_size_rhs_sampled_patches(env, idx):
     """The full right-hand side (convective + viscous) of the workloads at
     their stated sizes (c1 16 x 256^2, c2 200 uneven patches 48..512, c4
-    64 x 512^2), computed on the GPU for every patch in the configuration
-    the bench uses (blocked storage, autotuned tiles), against the oracle on
-    five sampled patches (first, last, largest, two seeded); bar 1e-5 per
-    component."""
+    64 x 512^2, and c2 with C = 27 on every line as the bench's strict-C
+    field runs it), computed on the GPU for every patch in the configuration
+    the bench uses (blocked storage, autotuned tiles and schedule), against
+    the oracle on five sampled patches (first, last, largest, two seeded);
+    bar 1e-5 per component."""
     from paper_2506_16076_amd import autotune
     api, ctx, torch = env
+    strict = idx == "2-strict"
+    idx = 2 if strict else idx
     cfg = synth.config(idx)
+    if strict:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, ps=synth.with_continuation(cfg.ps, 27))
     ps = cfg.ps
     say("full-size rhs", cfg.name, ps.npatch, "patches", ps.npoints, "points")
     s, D, H = mkset(api, ctx, ps, 1)
@@ -1619,6 +1625,40 @@ def test_full_size_rhs_sampled_patches(env, idx):
     err = relerr_phys(sub, got, want)
     mx = maxrel_phys(sub, got, want)
     say("  patches", plist, "rel L2", err, "max", mx)
+    assert np.all(err < RHS_TOL) and np.all(mx < PT * RHS_TOL)
+    s.close()
+
+
+def test_interpolated_pair_at_bench_size(env):
+    """The bench's interpolated pair (a Cartesian and a polar patch of
+    1024 x 1024, blocked storage): the fringe table and interpolated values
+    against the oracle's, and the full right-hand side of the glued state
+    (viscous term with a smooth viscosity) against the oracle's (1e-5 per
+    component)."""
+    from oracle import interp
+    api, ctx, torch = env
+    cfg = synth.overlap_config(1024, network=True)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, 1)
+    n = s.set_interp(ps.geom)
+    table = interp.build(ps)
+    say("interpolated pair 1024^2: receivers", n, "oracle", len(table))
+    assert n == len(table)
+    x = cfg.u0.astype(np.float32)
+    xd = D(x)
+    api.fcsd_glue(s, xd)
+    got = H(xd).reshape(4, -1)
+    want = interp.interpolate(x.astype(np.float64).copy(), ps, table)
+    scale = np.abs(want).max(axis=1)
+    scale[2] = max(scale[1], scale[2])
+    ferr = np.abs(got - want).max(axis=1) / scale
+    mu = (0.002 * (1.5 + np.sin(3 * ps.xy[0]) * np.cos(2 * ps.xy[1]))).astype(np.float32)
+    rhs = torch.zeros(4 * s.plane, device="cuda:0")
+    api.fcsd_rhs(s, xd, D(ps.metric), D(mu), cfg.ref, G, rhs)
+    wr = euler.full_rhs(got.astype(np.float64), ps.metric, mu.astype(np.float64), ps, G)
+    err, mx = relerr_phys(ps, H(rhs), wr), maxrel_phys(ps, H(rhs), wr)
+    say("  fringe max rel", ferr, "rhs rel L2", err, "max", mx)
+    assert np.all(ferr <= 1e-6)
     assert np.all(err < RHS_TOL) and np.all(mx < PT * RHS_TOL)
     s.close()
 
