@@ -566,12 +566,34 @@ def main():
         torch.cuda.synchronize()
         ms4a = e0.elapsed_time(e1)
         adj_peak = torch.cuda.max_memory_allocated()
+        fin4 = bool(torch.isfinite(v0.grad).all().item())
+        del uT4, seed, v0
+        # the same sweep without step records: each step is recomputed from
+        # its input inside the reverse mode (less memory, one more forward)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        u4.copy_(ustart)
+        v0 = ustart.clone().requires_grad_(True)
+        par4 = torch.zeros((), device=dev, requires_grad=True)
+        uT4 = autodiff.rollout(st4, v0, par4, K4, every4, autodiff.freestream_dmach(c4.mach), record=False)
+        seed = torch.ones_like(uT4)
+        e0.record(ctx.stream)
+        uT4.backward(seed)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms4n = e0.elapsed_time(e1)
+        nrec_peak = torch.cuda.max_memory_allocated()
         shells = {"workload": "annulus of 16 sectors x 4 shells of 512 x 512, Mach 5 +-1% density, fringe glue "
                               "and Dirichlet inflow every stage, network every step",
                   "points": int(ps4.npoints), "value": ps4.npoints * 5 / (ms4 / 1e3), "unit": "grid-pt RK-stages/s",
                   "ms_per_step": ms4, "steps": C4_STEPS,
                   "adjoint": {"value": ps4.npoints * 5 * K4 / (ms4a / 1e3), "steps": K4, "checkpoint_every": every4,
-                              "ms_per_step": ms4a / K4, "finite": bool(torch.isfinite(v0.grad).all().item())},
+                              "ms_per_step": ms4a / K4, "finite": fin4},
+                  "adjoint_without_records": {"value": ps4.npoints * 5 * K4 / (ms4n / 1e3), "steps": K4,
+                                              "checkpoint_every": every4, "ms_per_step": ms4n / K4,
+                                              "reverse_peak_GB": (nrec_peak - mem0) / 1e9,
+                                              "finite": bool(torch.isfinite(v0.grad).all().item())},
                   "footprint_GB": {"note": "torch-allocated device memory of this workload (state, metric, "
                                            "workspaces, checkpoints, step records); the library's tables are "
                                            "not included",
