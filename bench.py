@@ -77,10 +77,11 @@ def recorded_traffic(kernel, npts):
 FILTER_BYTES = 64
 
 PASS_KERNEL = {"A": "k_dev_diff<1>", "B1": "k_passB1", "B2": "k_passB2", "C": "k_passC", "Bf": "k_passB",
-               "stage": "k_stage"}
+               "Bw": "k_passB4", "stage": "k_stage"}
 # passes of a stage under each schedule (Bf: passes B1 and B2 in one launch)
-SCHED_PASSES = {"split": ["A", "B1", "B2", "C"], "fused": ["A", "Bf", "C"], "persistent": ["A", "Bf", "C"]}
-SCHED_ID = {"split": 0, "fused": 1, "persistent": 2}
+SCHED_PASSES = {"split": ["A", "B1", "B2", "C"], "fused": ["A", "Bf", "C"], "persistent": ["A", "Bf", "C"],
+                "fused_wide": ["A", "Bw", "C"]}
+SCHED_ID = {"split": 0, "fused": 1, "persistent": 2, "fused_wide": 3}
 
 
 def pass_bytes(stage):
@@ -91,7 +92,7 @@ def pass_bytes(stage):
     rk_read = {0: 16, 1: 32, 2: 32, 3: 48, 4: 32}[stage]
     rk_write = {0: 16, 1: 16, 2: 32, 3: 32, 4: 16}[stage]
     # Bf: read e, d1e, metric, mu (52), write H (32) and r2 (16)
-    return {"A": 32, "B1": 84, "B2": 56, "C": 32 + 16 + 8 + rk_read + rk_write, "Bf": 100}
+    return {"A": 32, "B1": 84, "B2": 56, "C": 32 + 16 + 8 + rk_read + rk_write, "Bf": 100, "Bw": 100}
 
 
 def _cpu_model():
@@ -348,10 +349,16 @@ def main():
 
     # ---------------- per-pass timing (dominant kernel), every pass at each
     # of the five stages (pass C's register traffic depends on the stage)
-    names = ["A", "B1", "B2", "C", "Bf"]
+    names = ["A", "B1", "B2", "C", "Bf", "Bw"]
     passes, pass_gb = {}, {}
     for pid, name in enumerate(names):
         tot_ms, tot_bytes = 0.0, 0.0
+        if name == "Bw":
+            try:   # the wide q2 tiles may not fit the LDS at the tuned budget
+                api.fcsd_stage_pass(s, pid, 0, u, ua, acc, ub, metric, mu, cfg.ref, 1.4, dtd)
+            except api.FcsdError:
+                passes[name] = pass_gb[name] = None
+                continue
         for stage in range(5):
             # prerequisites so every pass reads defined data
             for q in range(min(pid + 1, 4)):

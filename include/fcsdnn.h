@@ -140,9 +140,13 @@ fcsd_status fcsd_set_tune(fcsd_set* set, const int lds_budget[3], const int thre
 enum {
   FCSD_SCHED_SPLIT = 0,      /* four launches: A, B1, B2, C */
   FCSD_SCHED_FUSED = 1,      /* three launches: A, B1 + B2 on one q2 tile, C (the default) */
-  FCSD_SCHED_PERSISTENT = 2  /* one launch per stage: resident workgroups take A, B and C
+  FCSD_SCHED_PERSISTENT = 2, /* one launch per stage: resident workgroups take A, B and C
                                 tiles from a queue; a B tile starts once its patch's A
                                 tiles are done, a C tile once its patch's B tiles are */
+  FCSD_SCHED_FUSED_WIDE = 3   /* three launches like FCSD_SCHED_FUSED, the q2 pass on tiles
+                                that hold all eight H fields in LDS (four complex lines per
+                                grid line, half as many lines per tile); FCSD_EINVAL when
+                                such tiles do not fit a workgroup's LDS */
 };
 /* Select the schedule of `set` for fcsd_rhs, fcsd_stage and fcsd_step (the
  * per-patch and per-pass entry points always launch the passes one by one).
@@ -494,7 +498,8 @@ fcsd_status fcsd_stage_adj(fcsd_ctx* ctx, const fcsd_set* set, int stage, const 
 /* One of the four passes of fcsd_stage (0: q1 derivatives of the state,
  * 1: q2 derivatives and the combined fluxes H, 2: q2 derivatives of H,
  * 3: q1 derivatives of H and the register update), or 4: passes 1 and 2 in
- * one launch (the fused schedule's q2 pass), for timing and profiling.
+ * one launch (the fused schedule's q2 pass), 5: the same on tiles holding
+ * all eight H fields (the wide fused schedule's), for timing and profiling.
  * Running passes 0..3 (or 0, 4, 3) in order equals one fcsd_stage call;
  * with mu == NULL passes 0 and 1 together are the pointwise inviscid H. */
 fcsd_status fcsd_stage_pass(fcsd_ctx* ctx, const fcsd_set* set, int pass, int stage, const float* u0,

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfcsdnn.so")
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EHIP", 5: "EUNSUPPORTED", 6: "ENONFINITE"}
 WS_RHS, WS_AV, WS_STEP, WS_RHS_ADJ, WS_STEP_ADJ, WS_FILTER_ADJ, WS_SMEAR, WS_STAGE_ADJ = 0, 1, 2, 3, 4, 5, 6, 7
 LAYOUT_ROWS, LAYOUT_B8X4 = 0, 1
-SCHED_SPLIT, SCHED_FUSED, SCHED_PERSISTENT = 0, 1, 2
+SCHED_SPLIT, SCHED_FUSED, SCHED_PERSISTENT, SCHED_FUSED_WIDE = 0, 1, 2, 3
 
 
 def blocked_layout(n1, n2, base_off=None):

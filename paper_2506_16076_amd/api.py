@@ -153,12 +153,13 @@ class PatchSet:
         self.ctx.check(lib().fcsd_set_tune(self.h, b, t, int(order)), "fcsd_set_tune")
         self.tuning = (tuple(int(x) for x in budgets), tuple(int(x) for x in threads), int(order))
 
-    SCHED_SPLIT, SCHED_FUSED, SCHED_PERSISTENT = 0, 1, 2
+    SCHED_SPLIT, SCHED_FUSED, SCHED_PERSISTENT, SCHED_FUSED_WIDE = 0, 1, 2, 3
 
     def set_schedule(self, schedule: int):
         """Launch schedule of a stage's line passes: SCHED_SPLIT (four
-        launches), SCHED_FUSED (three: passes B1 and B2 on one q2 tile) or
-        SCHED_PERSISTENT (one launch per stage taking tiles from a queue)."""
+        launches), SCHED_FUSED (three: passes B1 and B2 on one q2 tile),
+        SCHED_PERSISTENT (one launch per stage taking tiles from a queue) or
+        SCHED_FUSED_WIDE (three, the q2 tile holding all eight H fields)."""
         self.ctx.check(lib().fcsd_set_schedule(self.h, int(schedule)), "fcsd_set_schedule")
         self.schedule = int(schedule)
 

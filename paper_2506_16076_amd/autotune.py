@@ -24,6 +24,7 @@ from . import api
 
 SET_PASSES = ((0, 3), (2,), (1,))   # tile set -> passes timed (A+C, B2, B1)
 FUSED_PASSES = ((0, 3), (2,), (4,))  # the same with the fused B pass on the third set
+WIDE_PASSES = ((0, 3), (2,), (5,))   # the fused B pass with all H fields in LDS
 PERSISTENT_BUDGET = 163840 - 256    # leaves room for the persistent kernel's queue slot
 DEFAULT_BUDGETS = (24576, 32768, 49152, 65536, 81920, 98304, 131072, 163840)
 DEFAULT_THREADS = (256, 512, 1024)
@@ -67,7 +68,7 @@ def time_stage(s, bufs, reps=3):
 
 
 def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS, threads=DEFAULT_THREADS,
-             orders=(api.PatchSet.ORDER_LPT, api.PatchSet.ORDER_XCD), reps=3, schedules=(0, 1, 2)):
+             orders=(api.PatchSet.ORDER_LPT, api.PatchSet.ORDER_XCD), reps=3, schedules=(0, 1, 2, 3)):
     """Choose the schedule of patch set `s` on state `u`; applies the choice
     and returns it with the timing table."""
     dev = u.device
@@ -89,24 +90,33 @@ def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS,
     for order in orders:
         for (b, t) in cands:
             s.tune(b, t, order)
-            table[(order, b, t)] = time_passes(s, bufs, (0, 1, 2, 3, 4), reps)
+            tm = time_passes(s, bufs, (0, 1, 2, 3, 4), reps)
+            try:
+                tm.update(time_passes(s, bufs, (5,), reps))
+            except api.FcsdError:     # wide q2 tiles do not fit the LDS at this budget
+                tm[5] = float("inf")
+            table[(order, b, t)] = tm
     # per-set picks of the split and fused schedules under each order, then
     # whole stages of each pick and of the persistent candidates
     stage = []   # (ms, schedule, budgets, threads, order)
     for order in orders:
-        for sched, set_passes in ((0, SET_PASSES), (1, FUSED_PASSES)):
+        for sched, set_passes in ((0, SET_PASSES), (1, FUSED_PASSES), (3, WIDE_PASSES)):
             if sched not in schedules:
                 continue
             pick = [min(cands, key=lambda bt: sum(table[(order,) + bt][p] for p in passes))
                     for passes in set_passes]
             bud, thr = [c[0] for c in pick], [c[1] for c in pick]
             s.tune(bud, thr, order)
-            s.set_schedule(sched)
+            try:
+                s.set_schedule(sched)
+            except api.FcsdError:
+                continue
             stage.append((time_stage(s, bufs, reps), sched, bud, thr, order))
         if 2 in schedules:
             # one workgroup size for every task of the launch; budgets of the
             # fused pick, capped for the queue slot, and uniform ones
-            fb = stage[-1][2] if 1 in schedules else [max(budgets)] * 3
+            fused = [r for r in stage if r[1] == 1 and r[4] == order]
+            fb = fused[-1][2] if fused else [max(budgets)] * 3
             pers = {tuple(min(b, PERSISTENT_BUDGET) for b in fb)} | \
                 {(b, b, b) for b in budgets if 65536 <= b <= PERSISTENT_BUDGET}
             pthreads = [t for t in threads if t >= 512] or [max(threads)]
@@ -121,11 +131,11 @@ def autotune(s, u, metric, mu, ref, gamma=1.4, dt=None, budgets=DEFAULT_BUDGETS,
     ms, sched, bud, thr, order = min(stage, key=lambda r: r[0])
     s.tune(bud, thr, order)
     s.set_schedule(sched)
-    names = ["split", "fused", "persistent"]
+    names = ["split", "fused", "persistent", "fused_wide"]
     return {"budgets": bud, "threads": thr, "order": "xcd" if order else "lpt", "schedule": names[sched],
             "stage_ms": ms,
             "stages": [{"ms": round(r[0], 4), "schedule": names[r[1]], "budgets": r[2], "threads": r[3],
                         "order": "xcd" if r[4] else "lpt"} for r in stage],
-            "table": {f"{'xcd' if o else 'lpt'}-{b // 1024}K-{t}": {["A", "B1", "B2", "C", "Bf"][p]: round(v, 4)
+            "table": {f"{'xcd' if o else 'lpt'}-{b // 1024}K-{t}": {["A", "B1", "B2", "C", "Bf", "Bw"][p]: round(v, 4)
                                                                    for p, v in tm.items()}
                       for (o, b, t), tm in table.items()}}

@@ -115,6 +115,19 @@ __device__ __forceinline__ LineCtx line_setup(float2* lds, const TileDev& T, con
   return X;
 }
 
+// The same tile viewed as nlc complex lines (a multiple of the lines the
+// context was set up for, within its row stride): thread mapping only, the
+// tables stay where line_setup put them.
+__device__ __forceinline__ LineCtx line_view(const LineCtx& X0, int nlc) {
+  LineCtx X = X0;
+  X.nl = nlc;
+  X.BS = blockDim.x / nlc;
+  X.c = threadIdx.x % nlc;
+  X.b0 = threadIdx.x / nlc;
+  X.active = X.b0 < X.BS;
+  return X;
+}
+
 // Walk over the elements (pos, c) of a tile in global-memory storage order.
 // Thread t visits elements t, t + blockDim, ... of the tile's storage and
 // carries, per element, two byte offsets updated by uniform increments:

@@ -103,7 +103,7 @@ struct TileSet {
 
 struct DirPlan {
   std::vector<PlanDev> plans;             // one per patch
-  TileSet ts[2];                          // one / two complex lines per grid line
+  TileSet ts[3];                          // one / two / four complex lines per grid line
   std::vector<long long> ext_off;         // per plan
   long long ext_plane = 0;
   PlanDev* d_plans = nullptr;
@@ -176,6 +176,7 @@ struct fcsd_set {
   unsigned stage_grid = 0;                // resident workgroups of the persistent launch
   size_t stage_lds = 0;
   int stage_threads = 0;
+  bool wide_ok = false;                   // the q2 tiles of four complex lines per grid line fit the LDS
 };
 
 namespace {
@@ -242,7 +243,7 @@ unsigned chunk_grid(int nchunks) { return (unsigned)std::max(1, std::min(nchunks
 // launch a line-engine kernel over the batched tile list or one patch's tiles
 template <class K>
 fcsd_status launch_lines(const fcsd_set* s, int dir, K kern, PassArgs a, int patch = -1, int fields = 1) {
-  const TileSet& D = s->dir[dir - 1].ts[fields - 1];
+  const TileSet& D = s->dir[dir - 1].ts[fields == 4 ? 2 : fields - 1];
   unsigned grid;
   size_t lds;
   if (patch < 0) {
@@ -552,7 +553,7 @@ void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget,
 
 // align: lines per tile a multiple of it (blocked storage: 4 q1 lines, 8 q2 lines)
 void build_tiles(DirPlan& D, int order, int align, int d) {
-  for (int f = 0; f < 2; ++f) build_tileset(D.plans, D.ts[f], D.ts[f].budget, order, f + 1, align, d);
+  for (int f = 0; f < 3; ++f) build_tileset(D.plans, D.ts[f], D.ts[f].budget, order, 1 << f, align, d);
 }
 
 int tile_align(int layout, int dir) { return layout == FCSD_LAYOUT_B8X4 ? (dir == 0 ? 4 : 8) : 1; }
@@ -754,11 +755,13 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
     int maxlds = 0;
     HIPCHK(ctx, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
     for (int dir = 0; dir < 2; ++dir)
-      for (const TileSet& t : s->dir[dir].ts)
-        if (t.lds > (size_t)maxlds)
+      for (int f = 0; f < 2; ++f)
+        if (s->dir[dir].ts[f].lds > (size_t)maxlds)
           return fail(ctx, FCSD_EUNSUPPORTED,
                       "a line tile needs more LDS than a workgroup has (transform length too long for the "
                       "storage's smallest tile)");
+    // the wide fused q2 pass (four complex lines per grid line) is optional
+    s->wide_ok = s->dir[1].ts[2].lds <= (size_t)maxlds;
   }
   // per-patch descriptors and point chunks
   std::vector<PatchDev> pd;
@@ -912,6 +915,10 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const
   s->dir[1].ts[0].threads = threads[1];
   s->dir[1].ts[1].budget = (size_t)lds_budget[2];
   s->dir[1].ts[1].threads = threads[2];
+  s->dir[0].ts[2].budget = (size_t)lds_budget[0];
+  s->dir[0].ts[2].threads = threads[0];
+  s->dir[1].ts[2].budget = (size_t)lds_budget[2];
+  s->dir[1].ts[2].threads = threads[2];
   fcsd_status r;
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
@@ -919,19 +926,25 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const
     if ((r = upload_tiles(ctx, D))) return r;
   }
   if ((r = build_stage_tasks(s))) return r;
-  if (s->schedule == FCSD_SCHED_PERSISTENT && s->stage_grid == 0) s->schedule = FCSD_SCHED_FUSED;
+  s->wide_ok = s->dir[1].ts[2].lds <= (size_t)maxlds;
+  if ((s->schedule == FCSD_SCHED_PERSISTENT && s->stage_grid == 0) ||
+      (s->schedule == FCSD_SCHED_FUSED_WIDE && !s->wide_ok))
+    s->schedule = FCSD_SCHED_FUSED;
   return rebuild_wall_tiles(s);
 }
 
 extern "C" fcsd_status fcsd_set_schedule(fcsd_set* s, int schedule) {
   if (!s) return FCSD_EINVAL;
   fcsd_ctx* ctx = s->ctx;
-  if (schedule != FCSD_SCHED_SPLIT && schedule != FCSD_SCHED_FUSED && schedule != FCSD_SCHED_PERSISTENT)
+  if (schedule != FCSD_SCHED_SPLIT && schedule != FCSD_SCHED_FUSED && schedule != FCSD_SCHED_PERSISTENT &&
+      schedule != FCSD_SCHED_FUSED_WIDE)
     return fail(ctx, FCSD_EINVAL, "fcsd_set_schedule: unknown schedule");
   if (schedule == FCSD_SCHED_PERSISTENT && s->stage_grid == 0)
     return fail(ctx, FCSD_EINVAL,
                 "fcsd_set_schedule: the tile sets leave no room for the persistent kernel's queue slot "
                 "(tune LDS budgets to at most 160 KB - 16)");
+  if (schedule == FCSD_SCHED_FUSED_WIDE && !s->wide_ok)
+    return fail(ctx, FCSD_EINVAL, "fcsd_set_schedule: q2 tiles of four complex lines per grid line do not fit the LDS");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& g : s->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -1168,7 +1181,10 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
   // passes B1 and B2 in one launch (a whole-set call of the fused or
   // persistent schedule)
   // (bit 4 of passes asks for it whatever the schedule)
-  const bool fuse = patch < 0 && (s->schedule != FCSD_SCHED_SPLIT || (passes & 16u)) && (passes & 6u) == 6u;
+  const bool fuse = patch < 0 && (s->schedule != FCSD_SCHED_SPLIT || (passes & 48u)) && (passes & 6u) == 6u;
+  // the fused pass with all eight H fields in LDS (bit 5 of passes asks for it)
+  const bool wide = fuse && !(passes & 16u) && s->wide_ok &&
+                    (s->schedule == FCSD_SCHED_FUSED_WIDE || (passes & 32u));
   const bool persistent = fuse && passes == 15u && !walls && s->schedule == FCSD_SCHED_PERSISTENT;
   a.out = W.d1e;
   PassArgs b = a;
@@ -1242,7 +1258,8 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
       if ((st = launch_lines(s, 2, k_passB1, b, patch, 2))) return st;
   }
   if (fuse) {
-    if ((st = launch_lines(s, 2, k_passB, b, patch, 2))) return st;
+    if ((st = wide ? launch_lines(s, 2, k_passB4, b, patch, 4) : launch_lines(s, 2, k_passB, b, patch, 2)))
+      return st;
   } else if (passes & 4u) {
     PassArgs c = a;
     c.plans = s->dir[1].d_plans;
@@ -1616,13 +1633,15 @@ extern "C" fcsd_status fcsd_stage_pass(fcsd_ctx* ctx, const fcsd_set* s, int pas
                                        size_t ws_bytes) {
   fcsd_status st = check_set(ctx, s, plane);
   if (st) return st;
-  if (pass < 0 || pass > 4 || stage < 0 || stage > 4 || !u0 || !ui || !uout || !metric || !ref || !dt_dev || !ws ||
+  if (pass < 0 || pass > 5 || stage < 0 || stage > 4 || !u0 || !ui || !uout || !metric || !ref || !dt_dev || !ws ||
       (stage >= 2 && !acc))
     return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: bad arguments");
   if (uout == ui || (uout == u0 && stage != 4)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: output aliases an input");
+  if (pass == 5 && !s->wide_ok)
+    return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: q2 tiles of four complex lines per grid line do not fit the LDS");
   if (ws_bytes < ws_bytes_of(s, FCSD_WS_RHS)) return fail(ctx, FCSD_EINVAL, "fcsd_stage_pass: workspace too small");
   return rhs_passes(ctx, s, ui, metric, mu, ref, gamma, mu ? FLUX_FULL : FLUX_INVISCID, MODE_RK, nullptr, stage, u0,
-                    acc, uout, dt_dev, ws, -1, pass == 4 ? 6u | 16u : 1u << pass);
+                    acc, uout, dt_dev, ws, -1, pass == 4 ? 6u | 16u : (pass == 5 ? 6u | 32u : 1u << pass));
 }
 
 namespace {

@@ -440,6 +440,91 @@ __device__ __forceinline__ void passB_tile(const PassArgs& a, const TileDev& T, 
   }
 }
 
+// Passes B1 and B2 on a q2 tile that holds all eight H fields in LDS (tile
+// set of four complex lines per grid line, row stride >= 4 nl): d2 e of the
+// four components in slots 0, 1 (two complex lines per grid line), the H
+// epilogue stores H (for pass C) and writes (H_x, H_y) of component c into
+// slot c, then one transform of the four slots and r2 of all components from
+// one read of the q2 metric rows.  The same FP32 operations on every line as
+// passes B1 and B2 (bit-identical results).
+__device__ __forceinline__ void passB4_tile(const PassArgs& a, const TileDev& T, float2* lds) {
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T2 = T;
+  T2.nl = 2 * T.nl;
+  const LineCtx X = line_setup(lds, T2, P, a.tw, a.km);
+  const LineCtx X4 = line_view(X, 4 * T.nl);
+  float2* __restrict__ z = X.z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  const TileMem M = tile_mem<2>(P, T, nl, ld);
+  __syncthreads();
+  const int flux = a.mode;
+  if (flux != FLUX_INVISCID) {
+    const float* u = a.u + M.base;
+    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, u, u + pl, a.eref[0], a.eref[1], a.d);
+    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, nl, P.nb1, P.n1, u + 2 * pl, u + 3 * pl, a.eref[2],
+                                    a.eref[3], a.d);
+    FCSD_DIFF_AND_TRANSFORM(a)
+  }
+  const HSrc hs = h_sources(a, M.base, flux);
+  float* H = a.H + M.base;
+  float* d2o = a.d2out ? a.d2out + M.base : nullptr;
+  float2* zb = z + nl;
+  float2* zc = z + 2 * nl;
+  float2* zd = z + 3 * nl;
+  walk_b<kEpiBatchH>(
+      M.w, [&](unsigned g) { return load_H4_inputs(hs, g); },
+      [&](unsigned g, unsigned l, const HIn4& q) {
+        const float2 za = at(z, l), zq = at(zb, l);
+        float d2[4] = {za.x, za.y, zq.x, zq.y};
+        if (a.d2th && P.wallp) {
+          // the energy's derivative by the product rule (Remark adiabatic)
+          const float ir = 1.0f / q.e[0], mq = q.e[1] * q.e[1] + q.e[2] * q.e[2];
+          const float A = q.e[3] * ir - mq * ir * ir, B = q.e[0] / (a.gamma - 1.0f);
+          d2[3] = A * d2[0] + B * at(a.d2th + M.base, g) + (q.e[1] * d2[1] + q.e[2] * d2[2]) * ir;
+        }
+        if (d2o) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) at(d2o + k * pl, g) = d2[k];
+        }
+        float dF[4] = {0.f, 0.f, 0.f, 0.f}, dG[4] = {0.f, 0.f, 0.f, 0.f};
+        if (flux != FLUX_VISC) dev_flux(q.e, a.eref, a.pref, a.gamma, dF, dG);
+        float h[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float vx = 0.f, vy = 0.f;
+          if (flux != FLUX_INVISCID) {
+            vx = q.mu * (q.m1x * q.d1[k] + q.m2x * d2[k]);
+            vy = q.mu * (q.m1y * q.d1[k] + q.m2y * d2[k]);
+          }
+          h[2 * k] = vx - dF[k];
+          h[2 * k + 1] = vy - dG[k];
+          at(H + (2 * k) * pl, g) = h[2 * k];
+          at(H + (2 * k + 1) * pl, g) = h[2 * k + 1];
+        }
+        at(z, l) = make_float2(h[0], h[1]);
+        at(zb, l) = make_float2(h[2], h[3]);
+        at(zc, l) = make_float2(h[4], h[5]);
+        at(zd, l) = make_float2(h[6], h[7]);
+      });
+  __syncthreads();
+  difference_ext(X4, P, a.dq + P.dq, a.d);
+  fft_apply<false>(X4, Pg, P);
+  const float* m2x = a.metric + 2 * pl + M.base;
+  const float* m2y = a.metric + 3 * pl + M.base;
+  float* r2 = a.r2 + M.base;
+  walk_b<kLoadBatch>(
+      M.w, [&](unsigned g) { return make_float2(at(m2x, g), at(m2y, g)); },
+      [&](unsigned g, unsigned l, float2 m) {
+        const float2 v0 = at(z, l), v1 = at(zb, l), v2 = at(zc, l), v3 = at(zd, l);
+        at(r2, g) = m.x * v0.x + m.y * v0.y;
+        at(r2 + pl, g) = m.x * v1.x + m.y * v1.y;
+        at(r2 + 2 * pl, g) = m.x * v2.x + m.y * v2.y;
+        at(r2 + 3 * pl, g) = m.x * v3.x + m.y * v3.y;
+      });
+}
+
 __global__ void FCSD_LINE_BOUNDS k_passB1(PassArgs a) {
   const TileDev T = a.tiles[blockIdx.x];
   if (T.nl == 0) return;
@@ -451,6 +536,13 @@ __global__ void FCSD_LINE_BOUNDS k_passB(PassArgs a) {
   const TileDev T = a.tiles[blockIdx.x];
   if (T.nl == 0) return;
   passB_tile<true>(a, T, lds_z);
+}
+
+// The same with all eight H fields in LDS (see passB4_tile).
+__global__ void FCSD_LINE_BOUNDS k_passB4(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  passB4_tile(a, T, lds_z);
 }
 
 // Spectral filter of the state (paper Sec. 4.3.1, eq. filtering) along

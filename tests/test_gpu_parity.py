@@ -748,7 +748,7 @@ def test_fused_stage_and_per_patch_equal(env, layout):
     s.close()
 
 
-SCHEDULES = (0, 1, 2)   # split (four launches), fused (three), persistent (one per stage)
+SCHEDULES = (0, 1, 2, 3)   # split (four launches), fused (three), persistent (one per stage), fused wide
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -793,14 +793,14 @@ def test_schedules_give_identical_stages(env, case, layout):
 def test_persistent_schedule_steps_with_network(env):
     """Five full steps of the 16-sector annulus (network, viscosity, step
     size, glue and inflow every stage, graph replay) give bit-identical
-    states with the persistent and the split schedules."""
+    states with the split, persistent and wide fused schedules."""
     api, ctx, torch = env
     cfg = synth.config(1, n=48)
     ps = cfg.ps
     s, D, H = mkset(api, ctx, ps, 1)
     W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
     res = []
-    for sched in (0, 2):
+    for sched in (0, 2, 3):
         s.set_schedule(sched)
         u = D(cfg.u0)
         st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W, dirichlet_mask=D(ps.dirichlet),
@@ -809,7 +809,7 @@ def test_persistent_schedule_steps_with_network(env):
             st.step(use_graph=(k > 0))
         res.append(H(u))
     assert s.stage_errors() == 0
-    assert np.all(np.isfinite(res[0])) and np.array_equal(res[0], res[1])
+    assert np.all(np.isfinite(res[0])) and all(np.array_equal(res[0], r) for r in res[1:])
     s.close()
 
 
