@@ -150,6 +150,11 @@ enum {
 };
 /* Select the schedule of `set` for fcsd_rhs, fcsd_stage and fcsd_step (the
  * per-patch and per-pass entry points always launch the passes one by one).
+ * The reverse modes of the right-hand side (fcsd_rhs_adj, av_apply_adj,
+ * fcsd_stage_adj, fcsd_step_adj) run their viscous q2 pass on tiles of all
+ * four components, fused with the q2 transpose of its output, except with
+ * FCSD_SCHED_SPLIT (and on sets with walls); the results agree to FP32
+ * rounding (the transposes' tail folds sum in a tile-dependent order).
  * The persistent schedule uses the q1 tile set's workgroup size for every
  * task and the larger of the two tile sets' LDS plus 16 bytes (the queue
  * slot); it needs that to fit the device's LDS per workgroup (budgets of at

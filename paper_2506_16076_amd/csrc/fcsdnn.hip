@@ -2369,12 +2369,21 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
                        ctx->stream, b, rhs_bar, Hb);
     if ((st = launch_check(ctx, "adj C"))) return st;
   }
+  // the viscous q2 reverse on tiles of all four components, with the q2
+  // transpose of G2 in the same tile (not with the split schedule, and not
+  // on wall sets, whose energy rule acts on G1 and G2 first)
+  const bool wide = visc && !walls && s->wide_ok && s->schedule != FCSD_SCHED_SPLIT;
   {
     const DirPlan& D = s->dir[1];
     PassArgs b = a;
     b.plans = D.d_plans;
     b.tiles = D.ts[1].d_tiles;
-    if (visc)
+    if (wide) {
+      b.tiles = D.ts[2].d_tiles;
+      hipLaunchKernelGGL(k_adjHb2w, dim3((unsigned)D.ts[2].tiles.size()), dim3(D.ts[2].threads), D.ts[2].lds,
+                         ctx->stream, b, rhs_bar, (const float*)Hb, (const float*)d1e, (const float*)d2e, G1, mu_bar,
+                         u_bar);
+    } else if (visc)
       hipLaunchKernelGGL(k_adjHb2p<true>, dim3((unsigned)D.ts[1].tiles.size()), dim3(D.ts[1].threads), D.ts[1].lds,
                          ctx->stream, b, rhs_bar, Hb, (const float*)d1e, (const float*)d2e, G1, G2, mu_bar, u_bar);
     else
@@ -2408,8 +2417,10 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
                          s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, (const float*)THB, u_bar);
       if ((st = launch_check(ctx, "energy rule reverse"))) return st;
     }
-    // u_bar += D2^T G2 + D1^T G1 (deviation form: the constant reference has no adjoint)
-    if ((st = fc_diff_adj(ctx, s, 2, 4, G2, u_bar, pl))) return st;
+    // u_bar += D2^T G2 + D1^T G1 (deviation form: the constant reference has
+    // no adjoint; the wide q2 kernel has already added D2^T G2)
+    if (!wide)
+      if ((st = fc_diff_adj(ctx, s, 2, 4, G2, u_bar, pl))) return st;
     if ((st = fc_diff_adj(ctx, s, 1, 4, G1, u_bar, pl))) return st;
   }
   return FCSD_OK;

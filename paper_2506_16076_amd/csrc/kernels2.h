@@ -1610,6 +1610,131 @@ __global__ void FCSD_LINE_BOUNDS k_adjHb2p(PassArgs a, const float* rb, float* H
   }
 }
 
+// The viscous reverse of pass B2 on q2 tiles that hold all four state
+// components (tile set of four complex lines per grid line), fused with the
+// transposed q2 derivative of G2: one transform gives Hb = Hb1 + D_2^T
+// (m_2x rb, m_2y rb) of the four components; at every point the epilogue
+// forms G1 (stored for the q1 transpose), G2 (kept in LDS as two complex
+// lines per grid line), mu_bar and, unless mode is FLUX_VISC, the flux VJP
+// of -Hb into u_bar, so that Hb itself is never stored; then u_bar +=
+// D_2^T G2.  The same FP32 operations as k_adjHb2p followed by fc_diff_adj
+// of G2 along q2, up to the order of the tail folds' sums (fold_pre splits
+// a line over a number of lanes that depends on the tile's line count).
+__global__ void FCSD_LINE_BOUNDS k_adjHb2w(PassArgs a, const float* rb, const float* Hb, const float* d1e,
+                                          const float* d2e, float* G1, float* mub, float* ub) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T4 = T;
+  T4.nl = 4 * T.nl;
+  const LineCtx X4 = line_setup(lds_z, T4, P, a.tw, a.km);
+  const LineCtx X2 = line_view(X4, 2 * T.nl);
+  float2* __restrict__ z = X4.z;
+  const int nl = T.nl, ld = T.ld;
+  __syncthreads();
+  const TileMem M = tile_mem<2>(P, T, nl, ld);
+  const long long pl = a.plane, bo = M.base;
+  const float* m1x = a.metric + bo;
+  const float* m1y = a.metric + pl + bo;
+  const float* m2x = a.metric + 2 * pl + bo;
+  const float* m2y = a.metric + 3 * pl + bo;
+  float2* __restrict__ z1 = z + nl;
+  float2* __restrict__ z2 = z + 2 * nl;
+  float2* __restrict__ z3 = z + 3 * nl;
+  struct RIn4 {
+    float r[4], mx, my;
+  };
+  walk_b<kEpiBatch>(
+      M.w,
+      [&](unsigned g) {
+        RIn4 q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q.r[k] = at(rb + k * pl + bo, g);
+        q.mx = at(m2x, g);
+        q.my = at(m2y, g);
+        return q;
+      },
+      [&](unsigned, unsigned l, const RIn4& q) {
+        at(z, l) = make_float2(q.mx * q.r[0], q.my * q.r[0]);
+        at(z1, l) = make_float2(q.mx * q.r[1], q.my * q.r[1]);
+        at(z2, l) = make_float2(q.mx * q.r[2], q.my * q.r[2]);
+        at(z3, l) = make_float2(q.mx * q.r[3], q.my * q.r[3]);
+      });
+  __syncthreads();
+  line_derivative<true>(X4, Pg, P, a.gq, a.dq, a.d);
+  const bool flux = a.mode != FLUX_VISC;
+  float* mubp = mub ? mub + bo : nullptr;
+  struct VIn4 {
+    float h[8], m1x, m1y, m2x, m2y, mu, d1[4], d2[4], mb, e[4], u[4];
+  };
+  walk_b<2>(
+      M.w,
+      [&](unsigned g) {
+        VIn4 q;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q.h[k] = at(Hb + k * pl + bo, g);
+        q.m1x = at(m1x, g);
+        q.m1y = at(m1y, g);
+        q.m2x = at(m2x, g);
+        q.m2y = at(m2y, g);
+        q.mu = at(a.mu + bo, g);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          q.d1[k] = mubp ? at(d1e + k * pl + bo, g) : 0.f;
+          q.d2[k] = mubp ? at(d2e + k * pl + bo, g) : 0.f;
+          q.e[k] = flux ? at(a.u + k * pl + bo, g) : 0.f;
+          q.u[k] = flux ? at(ub + k * pl + bo, g) : 0.f;
+        }
+        q.mb = mubp ? at(mubp, g) : 0.f;
+        return q;
+      },
+      [&](unsigned g, unsigned l, const VIn4& q) {
+        const float2 v[4] = {at(z, l), at(z1, l), at(z2, l), at(z3, l)};
+        float hx[4], hy[4], g2[4];
+        float mb = q.mb;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          hx[k] = q.h[2 * k] + v[k].x;
+          hy[k] = q.h[2 * k + 1] + v[k].y;
+          at(G1 + k * pl + bo, g) = q.mu * (q.m1x * hx[k] + q.m1y * hy[k]);
+          g2[k] = q.mu * (q.m2x * hx[k] + q.m2y * hy[k]);
+          const float ex = q.m1x * q.d1[k] + q.m2x * q.d2[k];
+          const float ey = q.m1y * q.d1[k] + q.m2y * q.d2[k];
+          mb = mb + hx[k] * ex + hy[k] * ey;
+        }
+        if (mubp) at(mubp, g) = mb;
+        at(z, l) = make_float2(g2[0], g2[1]);
+        at(z1, l) = make_float2(g2[2], g2[3]);
+        if (flux) {
+          float fb[4], gb[4], o[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            fb[k] = -hx[k];
+            gb[k] = -hy[k];
+          }
+          flux_vjp(q.e, a.gamma, fb, gb, o);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) at(ub + k * pl + bo, g) = q.u[k] + o[k];
+        }
+      });
+  __syncthreads();
+  // u_bar += D_2^T G2 (G2 of components 0, 1 and 2, 3 as two complex lines)
+  line_derivative<true>(X2, Pg, P, a.gq, a.dq, a.d);
+  walk_b<kLoadBatch>(
+      M.w,
+      [&](unsigned g) {
+        return make_float4(at(ub + bo, g), at(ub + pl + bo, g), at(ub + 2 * pl + bo, g), at(ub + 3 * pl + bo, g));
+      },
+      [&](unsigned g, unsigned l, float4 o) {
+        const float2 v0 = at(z, l), v1 = at(z1, l);
+        at(ub + bo, g) = o.x + v0.x;
+        at(ub + pl + bo, g) = o.y + v0.y;
+        at(ub + 2 * pl + bo, g) = o.z + v1.x;
+        at(ub + 3 * pl + bo, g) = o.w + v1.y;
+      });
+}
+
 // ---------------------------------------------------------------- network reverse mode
 
 // Reverse mode of the classifier network (Sec. 5.1) at the features of the

@@ -790,6 +790,34 @@ def test_schedules_give_identical_stages(env, case, layout):
     s.close()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_reverse_q2_pass_schedules_agree(env, layout):
+    """The viscous right-hand side's reverse mode with its q2 pass fused with
+    the q2 transpose (on tiles of all four components) agrees with the split
+    one (the pass, then fc_diff_adj) to FP32 rounding -- the transposes'
+    tail folds sum over a tile-dependent number of lanes, so the two are not
+    bit-identical: u_bar and mu_bar within 1e-6 of their largest value, on
+    the uneven patches and the annulus."""
+    api, ctx, torch = env
+    for case in ("uneven", "annulus"):
+        ps, u, mu, ref = rhs_case(case)
+        s, D, H = mkset(api, ctx, ps, layout)
+        rng = np.random.default_rng(31)
+        rb = D(rng.standard_normal((4, ps.plane)).astype(np.float32))
+        outs = []
+        for sched in (0, 1):
+            s.set_schedule(sched)
+            ub = torch.zeros(4 * s.plane, device="cuda:0")
+            mub = torch.zeros(s.plane, device="cuda:0")
+            api.fcsd_rhs_adj(s, D(u), D(ps.metric), D(mu), ref, G, rb, ub, mub)
+            outs.append((H(ub), H(mub)))
+        du = np.abs(outs[0][0] - outs[1][0]).max() / np.abs(outs[0][0]).max()
+        dm = np.abs(outs[0][1] - outs[1][1]).max() / np.abs(outs[0][1]).max()
+        say("reverse q2 split vs fused", case, layout, "u_bar", du, "mu_bar", dm)
+        assert du <= 1e-6 and dm <= 1e-6
+        s.close()
+
+
 def test_persistent_schedule_steps_with_network(env):
     """Five full steps of the 16-sector annulus (network, viscosity, step
     size, glue and inflow every stage, graph replay) give bit-identical
