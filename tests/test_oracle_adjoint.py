@@ -87,3 +87,39 @@ def test_adjoint_with_filter_matches_central_differences():
     # the filter changes the gradient (it is in the differentiated map)
     L0, g0, _ = adjoint.gradient(cfg, steps, replay=replay)
     assert np.abs(g - g0).max() > 1e-6 * np.abs(g0).max()
+
+
+@pytest.mark.slow
+def test_frozen_decisions_against_the_free_rollout():
+    """How far the derivative of the frozen branch (decisions -- step sizes,
+    classes, maximisers -- fixed at the base run, what the hand-written
+    adjoint computes) is from a central difference of the free rollout,
+    whose step sizes and decisions follow the parameter, on the annulus at
+    40 x 40 over two steps.  The perturbation amplitudes change the rollout
+    mostly through the state: within 3 % (a class or maximiser that flips
+    inside +-h makes the free difference depend on h).  The inflow Mach
+    number also sets the step size through the wave speeds of the CFL
+    condition, which the frozen branch leaves out: there the free
+    derivative is about a third of the frozen one, and smooth (the same at
+    h = 1e-4 and 1e-5)."""
+    cfg = small_annulus_cfg(40)
+    steps = 2
+    L, g, run = adjoint.gradient(cfg, steps)
+    free = {}
+    for h in (1e-4, 1e-5):
+        lp = adjoint.loss_at(cfg, steps, cfg.mach + h, cfg.pert.amp, None)
+        lm = adjoint.loss_at(cfg, steps, cfg.mach - h, cfg.pert.amp, None)
+        free[h] = (lp - lm) / (2 * h)
+    print("d/dM frozen", g[0], "free", free)
+    assert abs(free[1e-4] - free[1e-5]) <= 1e-6 * abs(free[1e-4])
+    assert 0.2 < free[1e-4] / g[0] < 0.5
+    for k in (0, 5):
+        h = 1e-4
+        a = cfg.pert.amp.copy()
+        a[k] += h
+        lp = adjoint.loss_at(cfg, steps, cfg.mach, a, None)
+        a[k] -= 2 * h
+        lm = adjoint.loss_at(cfg, steps, cfg.mach, a, None)
+        fd = (lp - lm) / (2 * h)
+        print("d/da", k, "frozen", g[1 + k], "free", fd)
+        assert abs(fd - g[1 + k]) <= 3e-2 * abs(g[1 + k])
