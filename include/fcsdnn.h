@@ -165,7 +165,13 @@ enum {
  * bit 0 of the word fcsd_stage_errors reads.  Synchronises the context's
  * stream and drops captured step graphs. */
 fcsd_status fcsd_set_schedule(fcsd_set* set, int schedule);
-/* Read and clear the persistent schedule's error word (blocking read). */
+/* Read and clear the set's device error word (blocking read).  Bit 0: a
+ * persistent stage's dependency wait gave up.  Bit 1: the network weights
+ * of a sdnn_infer call (also inside fcsd_step) let the operands of its
+ * fp16 matrix products reach the fp16 range -- a bound from the weights,
+ * with the features in [-1, 1], on the weights and every hidden activation
+ * is 65000 or more (or not finite) -- so its classes and logits are not to
+ * be trusted. */
 fcsd_status fcsd_stage_errors(fcsd_set* set, int32_t* flags);
 
 /* Bytes of device workspace an operation needs (op: FCSD_WS_*). */
@@ -427,6 +433,10 @@ typedef struct {
  * clamped to the line) rescaled to [-1, 1] feeds the 16-64-64-4 ReLU
  * network; tau = 1 + argmax (lowest index on ties), 2D class = min of the two
  * directions.  logits (nullable): FP32 [2][plane][4] network outputs.
+ * The products run on the fp16 matrix cores with every operand split into
+ * an fp16 high part and a scaled fp16 low part (FP32 accuracy); weights that
+ * could take an operand out of the fp16 range set bit 1 of the set's error
+ * word (fcsd_stage_errors).
  * ws: fcsd_workspace_size(FCSD_WS_AV) bytes. */
 fcsd_status sdnn_infer(fcsd_ctx* ctx, const fcsd_set* set, const float* u, float gamma,
                        const fcsd_mlp* w, int8_t* tau, float* logits, int64_t plane,

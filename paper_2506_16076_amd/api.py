@@ -164,8 +164,9 @@ class PatchSet:
         self.schedule = int(schedule)
 
     def stage_errors(self) -> int:
-        """Read and clear the persistent schedule's error word (bit 0: a
-        dependency wait gave up)."""
+        """Read and clear the set's device error word (bit 0: a persistent
+        stage's dependency wait gave up; bit 1: network weights that can take
+        the operands of its fp16 products out of the fp16 range)."""
         v = ctypes.c_int32(0)
         self.ctx.check(lib().fcsd_stage_errors(self.h, ctypes.byref(v)), "fcsd_stage_errors")
         return int(v.value)

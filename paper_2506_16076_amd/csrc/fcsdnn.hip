@@ -583,6 +583,11 @@ void filter_table(const PlanDev& P, double alpha, int p, std::vector<float>& t) 
     fcsd_host_fmul_embedded(P.N, P.Lx, P.L, P.nst, P.rad, alpha, p, t.data());
 }
 
+// The set's device error word, after the stage queue's head and per-patch
+// counters: bit 0 a persistent stage's dependency wait gave up, bit 1 the
+// network's weights let its split fp16 operands leave the fp16 range.
+unsigned* set_error_word(const fcsd_set* s) { return s->d_ctr + 1 + 2 * (size_t)s->npatch; }
+
 // Task queue of the persistent stage kernel from the current tile sets:
 // every A task (q1 tiles in launch order), then the B tasks (q2 tiles with
 // two complex lines per grid line) patch by patch in the order in which the
@@ -956,7 +961,7 @@ extern "C" fcsd_status fcsd_set_schedule(fcsd_set* s, int schedule) {
 extern "C" fcsd_status fcsd_stage_errors(fcsd_set* s, int32_t* flags) {
   if (!s || !flags) return FCSD_EINVAL;
   fcsd_ctx* ctx = s->ctx;
-  unsigned* e = s->d_ctr + 1 + 2 * (size_t)s->npatch;
+  unsigned* e = set_error_word(s);
   unsigned v = 0;
   HIPCHK(ctx, hipMemcpyAsync(&v, e, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipMemsetAsync(e, 0, sizeof(v), ctx->stream));
@@ -1217,7 +1222,7 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
     g.skipA = flux == FLUX_INVISCID;
     g.ctr = s->d_ctr;
     g.need = s->d_need;
-    g.err = s->d_ctr + 1 + 2 * (size_t)np;
+    g.err = set_error_word(s);
     // counters to zero with a fill kernel (no memset node in a captured step)
     const long long nw = 1 + 2 * (long long)np;
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(nw)), dim3(kBlock), 0, ctx->stream, (float*)s->d_ctr, 0.0f, nw);
@@ -1414,7 +1419,7 @@ fcsd_status sdnn_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, float ga
   // blocks stride over the chunks so each loads the weights into LDS once
   const int grid = std::min(s->nchunks, 2048);
   hipLaunchKernelGGL(k_sdnn, dim3(grid), dim3(kBlock), 0, ctx->stream, s->d_chunks, s->nchunks, s->d_patches,
-                     (const float*)phi, m, (signed char*)tau, logits, (long long)s->plane);
+                     (const float*)phi, m, (signed char*)tau, logits, (long long)s->plane, set_error_word(s));
   return launch_check(ctx, "sdnn_infer");
 }
 

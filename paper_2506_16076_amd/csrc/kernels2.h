@@ -584,24 +584,31 @@ __device__ __forceinline__ void mlp_load(MlpLds& L, const MlpPtr& w) {
 }
 
 // relu(m + c 2^-11) of two output tiles, split into the hi and scaled-lo
-// half8 operands of a chunk pair (tile a in slots 0..3, tile b in 4..7)
+// half8 operands of a chunk pair (tile a in slots 0..3, tile b in 4..7);
+// neighbouring slots are converted together (one packed conversion each)
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
 template <bool RELU>
 __device__ __forceinline__ void finish_pair(const floatx4 ma, const floatx4 ca, const floatx4 mb,
                                             const floatx4 cb, half8& h, half8& l) {
+  float x[8];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    float x = ma[v] + ca[v] * kLoUnscale, y = mb[v] + cb[v] * kLoUnscale;
-    if (RELU) {
-      x = fmaxf(x, 0.f);
-      y = fmaxf(y, 0.f);
-    }
-    _Float16 t0, t1, t2, t3;
-    split1(x, t0, t1);
-    split1(y, t2, t3);
-    h[v] = t0;
-    l[v] = t1;
-    h[4 + v] = t2;
-    l[4 + v] = t3;
+    x[v] = ma[v] + ca[v] * kLoUnscale;
+    x[4 + v] = mb[v] + cb[v] * kLoUnscale;
+  }
+  if (RELU) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) x[v] = fmaxf(x[v], 0.f);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const half2v hh = __builtin_convertvector(float2v{x[2 * q], x[2 * q + 1]}, half2v);
+    h[2 * q] = hh[0];
+    h[2 * q + 1] = hh[1];
+    // (x - hi) 2^11, exact before its rounding to fp16
+    l[2 * q] = (_Float16)__builtin_fmaf((float)hh[0], -kLoScale, x[2 * q] * kLoScale);
+    l[2 * q + 1] = (_Float16)__builtin_fmaf((float)hh[1], -kLoScale, x[2 * q + 1] * kLoScale);
   }
 }
 
@@ -667,34 +674,100 @@ __device__ __forceinline__ floatx4 mlp16(const MlpLds& L, const float x[4], int 
   return o;
 }
 
+// min and max of finite values (the window samples) without the NaN
+// quieting of the operands that fminf / fmaxf add
+__device__ __forceinline__ float fmin2(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float fmax2(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float fmin3(float a, float b, float c) {
+  float r;
+  asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ float fmax3(float a, float b, float c) {
+  float r;
+  asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// Minimum and maximum over the four lanes 16 g + r (g = 0..3) of window r:
+// an exchange between neighbouring rows of 16 lanes, then between the two
+// halves of the wavefront (min and max are symmetric, so every lane ends
+// with the reduction over all four).
+__device__ __forceinline__ void window_minmax(float& lo, float& hi) {
+  auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(lo), false, false);
+  auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(hi), __float_as_uint(hi), false, false);
+  lo = fmin2(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  hi = fmax2(__uint_as_float(b[0]), __uint_as_float(b[1]));
+  a = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(lo), false, false);
+  b = __builtin_amdgcn_permlane32_swap(__float_as_uint(hi), __float_as_uint(hi), false, false);
+  lo = fmin2(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  hi = fmax2(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
+// Element offset of point (i, j) from the patch's first storage element
+// (BLK: 8x4-blocked storage, else row-major).
+template <bool BLK>
+__device__ __forceinline__ unsigned poff(const PatchDev& P, int i, int j) {
+  return BLK ? ((__umul24((unsigned)(j >> 2), (unsigned)P.nb1) + (unsigned)(i >> 3)) << 5) +
+                   (unsigned)(((j & 3) << 3) + (i & 7))
+             : (unsigned)(j * P.n1 + i);
+}
+
+// base[o] as the uniform base plus a 32-bit byte offset
+__device__ __forceinline__ float ld_off(const float* __restrict__ base, unsigned o) {
+  return *(const float*)((const char*)base + (o << 2));
+}
+
 // This lane's samples t = g + 4 s (s = 0..3) of the 16-sample window at
 // offsets -8..7 (clamped) along a line, rescaled to [-1, 1] with the min and
-// max of the whole window (exchanged among the window's four lanes; min/max
-// are exact, so the features equal a sequential evaluation's).
-template <int DIR>
-__device__ __forceinline__ void window4(const float* __restrict__ phi, const PatchDev& P, int i, int j, int g,
-                                        float x[4]) {
+// max of the whole window.  `base`: the patch's first storage element.
+// `edge` (uniform over the wavefront): some window of the wavefront reaches
+// past an end of its line; otherwise no sample needs clamping and the four
+// are read at fixed distances.
+template <int DIR, bool BLK>
+__device__ __forceinline__ void window4(const float* __restrict__ base, const PatchDev& P, int i, int j, int g,
+                                        bool edge, float x[4]) {
 #pragma clang fp contract(off)
-  float lo = 3.4e38f, hi = -3.4e38f;
   const int pos = DIR == 1 ? i : j, n = DIR == 1 ? P.n1 : P.n2;
+  if (edge) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    int k = pos - 8 + g + 4 * s;
-    k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
-    x[s] = phi[DIR == 1 ? pidx(P, k, j) : pidx(P, i, k)];
-    lo = fminf(lo, x[s]);
-    hi = fmaxf(hi, x[s]);
+    for (int s = 0; s < 4; ++s) {
+      int k = pos - 8 + g + 4 * s;
+      k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+      x[s] = ld_off(base, DIR == 1 ? poff<BLK>(P, k, j) : poff<BLK>(P, i, k));
+    }
+  } else if (DIR == 1) {
+    // along q1, samples k and k + 8 lie one block (blocked) or 8 apart
+    const int k0 = pos - 8 + g;
+    const unsigned o0 = poff<BLK>(P, k0, j), o1 = poff<BLK>(P, k0 + 4, j);
+    x[0] = ld_off(base, o0);
+    x[1] = ld_off(base, o1);
+    x[2] = ld_off(base, o0 + (BLK ? 32u : 8u));
+    x[3] = ld_off(base, o1 + (BLK ? 32u : 8u));
+  } else {
+    // along q2, samples k and k + 4 lie one block row (blocked) or 4 rows apart
+    const unsigned o0 = poff<BLK>(P, i, pos - 8 + g);
+    const unsigned st = BLK ? (unsigned)P.nb1 << 5 : 4u * (unsigned)P.n1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x[s] = ld_off(base, o0 + s * st);
   }
-  lo = fminf(lo, __shfl_xor(lo, 16));
-  hi = fmaxf(hi, __shfl_xor(hi, 16));
-  lo = fminf(lo, __shfl_xor(lo, 32));
-  hi = fmaxf(hi, __shfl_xor(hi, 32));
+  float lo = fmin2(fmin3(x[0], x[1], x[2]), x[3]);
+  float hi = fmax2(fmax3(x[0], x[1], x[2]), x[3]);
+  window_minmax(lo, hi);
   const float rng = hi - lo;
   if (rng <= 1e-6f * fmaxf(1.0f, fabsf(hi))) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) x[s] = 0.f;
   } else {
-    const float sc = 2.0f / rng;
+    const float sc = 2.0f * __builtin_amdgcn_rcpf(rng);
 #pragma unroll
     for (int s = 0; s < 4; ++s) x[s] = (x[s] - lo) * sc - 1.0f;
   }
@@ -709,66 +782,120 @@ __device__ __forceinline__ int argmax4(floatx4 o) {
   return best;
 }
 
+// Largest magnitude that the split operands take, bounded from the weights:
+// the weights themselves and every hidden activation, with the features in
+// [-1, 1] (|h1_j| <= |b1_j| + sum_k |W1_kj|, |h2_m| <= |b2_m| +
+// sum_j |W2_jm| |h1_j|).  Run by one workgroup; at or above kHalfSafe the
+// fp16 high parts could overflow, and bit 1 of *err is set.
+constexpr float kHalfSafe = 65000.0f;
+__device__ void sdnn_range_check(const MlpPtr& w, unsigned* err) {
+  __shared__ float B1[64];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  if (t < 64) {
+    float s = fabsf(w.b1[t]), m = 0.f;
+    for (int k = 0; k < 16; ++k) {
+      s += fabsf(w.W1[k * 64 + t]);
+      m = fmaxf(m, fabsf(w.W1[k * 64 + t]));
+    }
+    B1[t] = s;
+    if (!(fmaxf(m, s) < kHalfSafe)) bad = 1;
+  }
+  __syncthreads();
+  if (t < 64) {
+    float s = fabsf(w.b2[t]), m = 0.f;
+    for (int k = 0; k < 64; ++k) {
+      s += fabsf(w.W2[k * 64 + t]) * B1[k];
+      m = fmaxf(m, fabsf(w.W2[k * 64 + t]));
+    }
+    for (int n = 0; n < 4; ++n) m = fmaxf(m, fabsf(w.W3[t * 4 + n]));
+    if (!(fmaxf(m, s) < kHalfSafe)) bad = 1;
+  }
+  __syncthreads();
+  if (t == 0 && bad) atomicOr(err, 2u);
+}
+
+// The points of one chunk, 16 consecutive storage elements per wavefront
+// at a time (BLK: the patch's storage layout).
+template <bool BLK>
+__device__ __forceinline__ void sdnn_chunk(const MlpLds& L, const ChunkDev ck, const PatchDev& P,
+                                           const float* __restrict__ phi, signed char* tau, float* logits,
+                                           long long pl, int wv, int g, int r) {
+  const int np = pstore(P);
+  const float* base = phi + P.off;
+  for (int q = wv; q < kChunk / 16; q += kBlock / 64) {
+    const int k0 = ck.start + 16 * q;  // uniform across the wavefront
+    if (k0 >= np) break;
+    const int kk = k0 + r;
+    int i = 0, j = 0;
+    bool valid;
+    if (BLK) {
+      // chunks start at multiples of 16, so the wavefront's points are one
+      // half of an 8x4 block, whose position is uniform
+      const int blk = k0 >> 5, bj = blk / P.nb1, bi = blk - bj * P.nb1;
+      const int e = (k0 & 16) + r;
+      i = (bi << 3) + (e & 7);
+      j = (bj << 2) + (e >> 3);
+      valid = i < P.n1 && j < P.n2;
+    } else {
+      valid = kk < np && pdecode(P, kk, i, j);
+    }
+    // lanes without a point evaluate a valid one (every lane takes part
+    // in the matrix products) and write nothing
+    i = i < P.n1 ? i : P.n1 - 1;
+    j = j < P.n2 ? j : P.n2 - 1;
+    const long long gi = P.off + kk;
+    // 16 points that all lie outside D~ (the strips next to internal
+    // sides) have class 0 and zero logits: the products are skipped
+    if (!__any(valid && in_dtilde(P, i, j))) {
+      if (g == 0 && valid) {
+        tau[gi] = (signed char)0;
+        if (logits) {
+          *(float4*)&logits[4 * gi] = make_float4(0.f, 0.f, 0.f, 0.f);
+          *(float4*)&logits[4 * (pl + gi)] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+      continue;
+    }
+    float x[4];
+    window4<1, BLK>(base, P, i, j, g, __any(i < 8 || i > P.n1 - 8), x);
+    const floatx4 o1 = mlp16(L, x, g, r);
+    window4<2, BLK>(base, P, i, j, g, __any(j < 8 || j > P.n2 - 8), x);
+    const floatx4 o2 = mlp16(L, x, g, r);
+    if (g == 0 && valid) {
+      const bool in = in_dtilde(P, i, j);
+      const int a1 = argmax4(o1), a2 = argmax4(o2);
+      tau[gi] = in ? (signed char)(1 + (a1 < a2 ? a1 : a2)) : (signed char)0;
+      if (logits) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        *(float4*)&logits[4 * gi] = in ? make_float4(o1[0], o1[1], o1[2], o1[3]) : z;
+        *(float4*)&logits[4 * (pl + gi)] = in ? make_float4(o2[0], o2[1], o2[2], o2[3]) : z;
+      }
+    }
+  }
+}
+
 // Network classes of every point: tau = 1 + min over the two directions of
-// the argmax class (0 outside D~).  Blocks stride over the point chunks; each
-// wavefront takes 16 consecutive points of a chunk at a time.
-__global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
-                                                 const float* phi, MlpPtr w, signed char* tau,
-                                                 float* logits, long long pl) {
+// the argmax class (0 outside D~).  Blocks stride over the point chunks;
+// each wavefront takes 16 consecutive points of a chunk at a time.  Block 0
+// also bounds the split operands' range from the weights (bit 1 of *err).
+__global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* __restrict__ chunks, int nchunks,
+                                                 const PatchDev* __restrict__ patches, const float* phi, MlpPtr w,
+                                                 signed char* tau, float* logits, long long pl, unsigned* err) {
   __shared__ MlpLds L;
   mlp_load(L, w);
+  if (blockIdx.x == 0) sdnn_range_check(w, err);
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, r = lane & 15;
   for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {
     const ChunkDev ck = chunks[cb];
     const PatchDev P = patches[ck.patch];
-    const int np = pstore(P);
-    for (int q = wv; q < kChunk / 16; q += kBlock / 64) {
-      const int k0 = ck.start + 16 * q;
-      if (k0 >= np) break;  // uniform across the wavefront
-      const int kk = k0 + r;
-      int i = 0, j = 0;
-      const bool valid = kk < np && pdecode(P, kk, i, j);
-      // lanes without a point evaluate a valid one (every lane takes part
-      // in the matrix products) and write nothing
-      i = i < P.n1 ? i : P.n1 - 1;
-      j = j < P.n2 ? j : P.n2 - 1;
-      // 16 points that all lie outside D~ (the strips next to internal
-      // sides) have class 0 and zero logits: the products are skipped
-      if (!__any(valid && in_dtilde(P, i, j))) {
-        if (g == 0 && valid) {
-          const long long gi = P.off + kk;
-          tau[gi] = (signed char)0;
-          if (logits) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              logits[4 * gi + v] = 0.f;
-              logits[4 * (pl + gi) + v] = 0.f;
-            }
-          }
-        }
-        continue;
-      }
-      float x[4];
-      window4<1>(phi, P, i, j, g, x);
-      const floatx4 o1 = mlp16(L, x, g, r);
-      window4<2>(phi, P, i, j, g, x);
-      const floatx4 o2 = mlp16(L, x, g, r);
-      if (g == 0 && valid) {
-        const long long gi = P.off + kk;
-        const bool in = in_dtilde(P, i, j);
-        const int a1 = argmax4(o1), a2 = argmax4(o2);
-        tau[gi] = in ? (signed char)(1 + (a1 < a2 ? a1 : a2)) : (signed char)0;
-        if (logits) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            logits[4 * gi + v] = in ? o1[v] : 0.f;
-            logits[4 * (pl + gi) + v] = in ? o2[v] : 0.f;
-          }
-        }
-      }
-    }
+    if (P.nb1)
+      sdnn_chunk<true>(L, ck, P, phi, tau, logits, pl, wv, g, r);
+    else
+      sdnn_chunk<false>(L, ck, P, phi, tau, logits, pl, wv, g, r);
   }
 }
 

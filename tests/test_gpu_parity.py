@@ -652,20 +652,46 @@ def test_state_monitor(env):
 
 # ------------------------------------------------------------------ viscosity
 
-def test_network_classes(env):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_network_classes(env, layout):
     """sdnn_infer against the oracle's FP64 classifier: logits of both
     directions within the FP32 bound of every window, classes equal wherever
-    the FP64 top-two gap exceeds twice it (near ties counted)."""
+    the FP64 top-two gap exceeds twice it (near ties counted); both storage
+    layouts (their window gathers differ)."""
+    api, ctx, torch = env
+    cfg = synth.config(1, n=48)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, layout)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    tau = torch.zeros(s.plane, dtype=torch.int8, device="cuda:0")
+    logits = torch.zeros(8 * s.plane, device="cuda:0")
+    api.sdnn_infer(s, D(cfg.u0), G, W, tau, logits)
+    # [2][plane][4] -> per (direction, class) planes -> host [2][plane][4]
+    lg = logits.view(2, s.plane, 4).permute(0, 2, 1).contiguous().view(8, s.plane)
+    gl = H(lg).reshape(2, 4, ps.plane).transpose(0, 2, 1)
+    decision_check(ps, cfg.u0, cfg.mlp, H(tau), logits_gpu=gl, label=f"network layout {layout}")
+    assert s.stage_errors() == 0
+    s.close()
+
+
+def test_network_range_flag(env):
+    """Weights that let a hidden activation reach the fp16 range set bit 1
+    of the set's error word (the split products would overflow); ordinary
+    weights leave it clear, and reading the word clears it."""
     api, ctx, torch = env
     cfg = synth.config(1, n=48)
     ps = cfg.ps
     s = api.PatchSet.from_layout(ctx, ps)
-    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    u = dev(torch, cfg.u0)
     tau = torch.zeros(ps.plane, dtype=torch.int8, device="cuda:0")
-    logits = torch.zeros(8 * ps.plane, device="cuda:0")
-    api.sdnn_infer(s, dev(torch, cfg.u0), G, W, tau, logits)
-    gl = host(logits).reshape(2, ps.plane, 4)
-    decision_check(ps, cfg.u0, cfg.mlp, host(tau), logits_gpu=gl, label="network")
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    api.sdnn_infer(s, u, G, W, tau)
+    assert s.stage_errors() == 0
+    big = dict(cfg.mlp)
+    big["W1"] = cfg.mlp["W1"] * 3e4
+    api.sdnn_infer(s, u, G, {k: dev(torch, v) for k, v in big.items()}, tau)
+    assert s.stage_errors() == 2
+    assert s.stage_errors() == 0
     s.close()
 
 
