@@ -505,7 +505,7 @@ struct MlpPtr {
 
 // The 16-64-64-4 classifier on the fp16 matrix cores with FP32 accuracy
 // (operands split into fp16 high and 2^11-scaled low parts, products summed
-// in FP32; see mlp16).  A wavefront evaluates 16 windows at once, as the transposed
+// in FP32; see mlp16x2).  A wavefront evaluates 16 windows at once, as the transposed
 // products H1^T = W1^T X^T, H2^T = W2^T relu(H1^T), O^T = W3^T relu(H2^T)
 // with windows along the columns.  Lane l = 16 g + r holds column r (window
 // r) and, after each product, rows 4 g + v (v = 0..3) of every 16-row tile
@@ -612,66 +612,88 @@ __device__ __forceinline__ void finish_pair(const floatx4 ma, const floatx4 ca, 
   }
 }
 
-// Logits of 16 windows; lane 16 g + r supplies features 4 s + g (s = 0..3)
-// of window r in x[s]; lanes 0..15 receive the four logits of window r.
+// Logits of two sets of 16 windows (the two directions at the same 16
+// points); lane 16 g + r supplies features 4 s + g (s = 0..3) of window r in
+// x0[s] and x1[s]; lanes 0..15 receive the four logits of window r of each.
 // Each product is computed transposed (windows along the columns), so the
-// D layout of one layer's output is the B layout of the next.
-__device__ __forceinline__ floatx4 mlp16(const MlpLds& L, const float x[4], int g, int r) {
-  half4 xh, xl;
+// D layout of one layer's output is the B layout of the next.  The layers of
+// the two evaluations are interleaved (the matrix products of one overlap
+// the vector work of the other) and share each read of the weights from
+// LDS.
+__device__ __forceinline__ void mlp16x2(const MlpLds& L, const float x0[4], const float x1[4], int g, int r,
+                                        floatx4& o0, floatx4& o1) {
+  half4 xh[2];
+  half8 xb[2];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    _Float16 t0, t1;
-    split1(x[e], t0, t1);
-    xh[e] = t0;
-    xl[e] = t1;
+  for (int d = 0; d < 2; ++d) {
+    const float* x = d ? x1 : x0;
+    half4 xl;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      _Float16 t0, t1;
+      split1(x[e], t0, t1);
+      xh[d][e] = t0;
+      xl[e] = t1;
+    }
+    xb[d] = half8{xh[d][0], xh[d][1], xh[d][2], xh[d][3], xl[0], xl[1], xl[2], xl[3]};
   }
-  const half8 xb = half8{xh[0], xh[1], xh[2], xh[3], xl[0], xl[1], xl[2], xl[3]};
-  half8 ah[2], al[2];
+  half8 ah[2][2], al[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
-    floatx4 m[2], c[2];
+    floatx4 m[2][2], c[2][2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = 2 * p + u;
-      m[u] = floatx4{L.b1[16 * t + 4 * g], L.b1[16 * t + 4 * g + 1], L.b1[16 * t + 4 * g + 2],
-                     L.b1[16 * t + 4 * g + 3]};
-      c[u] = floatx4{0.f, 0.f, 0.f, 0.f};
-      m[u] = __builtin_amdgcn_mfma_f32_16x16x16f16(L.W1h[t][g][r], xh, m[u], 0, 0, 0);
-      c[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W1c[t][g][r], xb, c[u], 0, 0, 0);
-    }
-    finish_pair<true>(m[0], c[0], m[1], c[1], ah[p], al[p]);
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = 2 * p + u;
+        m[d][u] = floatx4{L.b1[16 * t + 4 * g], L.b1[16 * t + 4 * g + 1], L.b1[16 * t + 4 * g + 2],
+                          L.b1[16 * t + 4 * g + 3]};
+        c[d][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+        m[d][u] = __builtin_amdgcn_mfma_f32_16x16x16f16(L.W1h[t][g][r], xh[d], m[d][u], 0, 0, 0);
+        c[d][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W1c[t][g][r], xb[d], c[d][u], 0, 0, 0);
+      }
+#pragma unroll
+    for (int d = 0; d < 2; ++d) finish_pair<true>(m[d][0], c[d][0], m[d][1], c[d][1], ah[d][p], al[d][p]);
   }
-  half8 bh[2], bl[2];
+  half8 bh[2][2], bl[2][2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    floatx4 m[2], c[2];
+    floatx4 m[2][2], c[2][2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int mt = 2 * q + u;
-      m[u] = floatx4{L.b2[16 * mt + 4 * g], L.b2[16 * mt + 4 * g + 1], L.b2[16 * mt + 4 * g + 2],
-                     L.b2[16 * mt + 4 * g + 3]};
-      c[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < 2; ++d)
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        m[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2h[mt][p][g][r], ah[p], m[u], 0, 0, 0);
-        c[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2l[mt][p][g][r], ah[p], c[u], 0, 0, 0);
-        c[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2h[mt][p][g][r], al[p], c[u], 0, 0, 0);
+      for (int u = 0; u < 2; ++u) {
+        const int mt = 2 * q + u;
+        m[d][u] = floatx4{L.b2[16 * mt + 4 * g], L.b2[16 * mt + 4 * g + 1], L.b2[16 * mt + 4 * g + 2],
+                          L.b2[16 * mt + 4 * g + 3]};
+        c[d][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          m[d][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2h[mt][p][g][r], ah[d][p], m[d][u], 0, 0, 0);
+          c[d][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2l[mt][p][g][r], ah[d][p], c[d][u], 0, 0, 0);
+          c[d][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W2h[mt][p][g][r], al[d][p], c[d][u], 0, 0, 0);
+        }
       }
+#pragma unroll
+    for (int d = 0; d < 2; ++d) finish_pair<true>(m[d][0], c[d][0], m[d][1], c[d][1], bh[d][q], bl[d][q]);
+  }
+  floatx4 m[2], c[2];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    m[d] = g == 0 ? floatx4{L.b3[0], L.b3[1], L.b3[2], L.b3[3]} : floatx4{0.f, 0.f, 0.f, 0.f};
+    c[d] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      m[d] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3h[p][g][r], bh[d][p], m[d], 0, 0, 0);
+      c[d] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3l[p][g][r], bh[d][p], c[d], 0, 0, 0);
+      c[d] = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3h[p][g][r], bl[d][p], c[d], 0, 0, 0);
     }
-    finish_pair<true>(m[0], c[0], m[1], c[1], bh[q], bl[q]);
   }
-  floatx4 m = g == 0 ? floatx4{L.b3[0], L.b3[1], L.b3[2], L.b3[3]} : floatx4{0.f, 0.f, 0.f, 0.f};
-  floatx4 c = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    m = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3h[p][g][r], bh[p], m, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3l[p][g][r], bh[p], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(L.W3h[p][g][r], bl[p], c, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) {
+    o0[v] = m[0][v] + c[0][v] * kLoUnscale;
+    o1[v] = m[1][v] + c[1][v] * kLoUnscale;
   }
-  floatx4 o;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) o[v] = m[v] + c[v] * kLoUnscale;
-  return o;
 }
 
 // min and max of finite values (the window samples) without the NaN
@@ -858,11 +880,11 @@ __device__ __forceinline__ void sdnn_chunk(const MlpLds& L, const ChunkDev ck, c
       }
       continue;
     }
-    float x[4];
-    window4<1, BLK>(base, P, i, j, g, __any(i < 8 || i > P.n1 - 8), x);
-    const floatx4 o1 = mlp16(L, x, g, r);
-    window4<2, BLK>(base, P, i, j, g, __any(j < 8 || j > P.n2 - 8), x);
-    const floatx4 o2 = mlp16(L, x, g, r);
+    float x1[4], x2[4];
+    window4<1, BLK>(base, P, i, j, g, __any(i < 8 || i > P.n1 - 8), x1);
+    window4<2, BLK>(base, P, i, j, g, __any(j < 8 || j > P.n2 - 8), x2);
+    floatx4 o1, o2;
+    mlp16x2(L, x1, x2, g, r, o1, o2);
     if (g == 0 && valid) {
       const bool in = in_dtilde(P, i, j);
       const int a1 = argmax4(o1), a2 = argmax4(o2);
