@@ -867,6 +867,36 @@ def test_persistent_schedule_steps_with_network(env):
     s.close()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_schedules_give_identical_steps_and_records(env, layout):
+    """Uneven independent patches: five steps with the network (graph
+    replay), the last one recorded, give states and step records
+    bit-identical under the split, fused, persistent and wide fused
+    schedules."""
+    api, ctx, torch = env
+    cfg = synth.config(2, npatch=8, nmax=136, seed=31)
+    ps = cfg.ps
+    s, D, H = mkset(api, ctx, ps, layout)
+    W = {k: dev(torch, v) for k, v in cfg.mlp.items()}
+    res, recs = [], []
+    for sched in (0, 1, 2, 3):
+        s.set_schedule(sched)
+        u = D(cfg.u0)
+        st = api.Stepper(s, u, D(ps.metric), cfg.ref, W=W)
+        for k in range(4):
+            st.step(use_graph=(k > 0))
+        rec = st.new_record().zero_()
+        st.step(record=rec)
+        res.append(H(u))
+        recs.append(rec.cpu().numpy())
+    assert s.stage_errors() == 0
+    say("schedules, uneven set, layout", layout, "change", float(np.abs(res[0] - H(D(cfg.u0))).max()))
+    assert np.all(np.isfinite(res[0]))
+    assert all(np.array_equal(res[0], r) for r in res[1:])
+    assert all(np.array_equal(recs[0], r) for r in recs[1:])
+    s.close()
+
+
 def test_ten_steps_square(env):
     api, ctx, torch = env
     cfg = synth.config(0)
