@@ -331,6 +331,10 @@ __device__ __forceinline__ void walk_b(Walk w, Pre&& pre, Post&& post) {
 // km[pos] (CONJ: by its conjugate, the transposed operator) and apply the
 // first inverse stage, which works on the same R contiguous samples without
 // twiddles, before storing: one LDS round trip and one barrier fewer.
+// Largest radix whose stage reads all its twiddles before the butterfly
+// (larger ones would need more registers than the line kernels have).
+constexpr int kTwPre = 12;
+
 template <int R, bool INV, bool MUL, bool CONJ>
 __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
   if (!X.active) return;
@@ -359,21 +363,38 @@ __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
     for (int t = 0; t < R; ++t) x[t] = ld_lds(X.z, a + t * leg);
     // j = 0 reads twiddle 1 + 0i: the product is exact, so no branch
     if (!INV) {
+      // up to radix kTwPre the twiddles (multipliers) are read before the
+      // butterfly, so that their LDS latency overlaps it
+      constexpr bool kPre = R <= kTwPre;
+      float2 w[R];
+      if (kPre) {
+#pragma unroll
+        for (int q = MUL ? 0 : 1; q < R; ++q) w[q] = MUL ? ld_lds(X.km, kq + 8u * q) : ld_lds(X.tw, q * tq);
+      }
       Dft<R, false>::run(x);
       if (MUL) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          const float2 k = ld_lds(X.km, kq + 8u * q);
+          const float2 k = kPre ? w[q] : ld_lds(X.km, kq + 8u * q);
           x[q] = CONJ ? cmulc(x[q], k) : cmul(x[q], k);
         }
         Dft<R, true>::run(x);
       } else {
 #pragma unroll
-        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], ld_lds(X.tw, q * tq));
+        for (int q = 1; q < R; ++q) x[q] = cmul(x[q], kPre ? w[q] : ld_lds(X.tw, q * tq));
       }
     } else {
+      if (R <= kTwPre) {
+        // every twiddle read before the first product
+        float2 w[R];
 #pragma unroll
-      for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], ld_lds(X.tw, q * tq));
+        for (int q = 1; q < R; ++q) w[q] = ld_lds(X.tw, q * tq);
+#pragma unroll
+        for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], w[q]);
+      } else {
+#pragma unroll
+        for (int q = 1; q < R; ++q) x[q] = cmulc(x[q], ld_lds(X.tw, q * tq));
+      }
       Dft<R, true>::run(x);
     }
 #pragma unroll
