@@ -76,7 +76,7 @@ def recorded_traffic(kernel, npts):
 # again (FP32)
 FILTER_BYTES = 64
 
-PASS_KERNEL = {"A": "k_dev_diff<1>", "B1": "k_passB1", "B2": "k_passB2", "C": "k_passC", "Bf": "k_passB",
+PASS_KERNEL = {"A": "k_dev_diff2<1>", "B1": "k_passB1", "B2": "k_passB2", "C": "k_passC", "Bf": "k_passB",
                "Bw": "k_passB4", "stage": "k_stage"}
 # passes of a stage under each schedule (Bf: passes B1 and B2 in one launch)
 SCHED_PASSES = {"split": ["A", "B1", "B2", "C"], "fused": ["A", "Bf", "C"], "persistent": ["A", "Bf", "C"],

@@ -1249,7 +1249,7 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
     if (walls && (passes & 3u))
       if ((st = wall_theta_derivs(ctx, s, u, ref, gamma, patch))) return st;
     if (passes & 1u) {
-      if ((st = launch_lines(s, 1, k_dev_diff<1>, a, patch))) return st;
+      if ((st = launch_lines(s, 1, k_dev_diff2<1>, a, patch, 2))) return st;
       if (walls) {
         const ChunkDev* ch;
         int n;
@@ -2351,7 +2351,7 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
     if (!given1) {
       b.out = w;
       b.plans = s->dir[0].d_plans;
-      if ((st = launch_lines(s, 1, k_dev_diff<1>, b))) return st;
+      if ((st = launch_lines(s, 1, k_dev_diff2<1>, b, -1, 2))) return st;
       if (walls)
         hipLaunchKernelGGL(k_energy_rule, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream, s->d_wchunks,
                            s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, D1TH, w);
@@ -2359,7 +2359,7 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
     if (!given2) {
       b.out = w + 4 * pl;
       b.plans = s->dir[1].d_plans;
-      if ((st = launch_lines(s, 2, k_dev_diff<2>, b))) return st;
+      if ((st = launch_lines(s, 2, k_dev_diff2<2>, b, -1, 2))) return st;
       if (walls)
         hipLaunchKernelGGL(k_energy_rule, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream, s->d_wchunks,
                            s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, D2TH, w + 4 * pl);

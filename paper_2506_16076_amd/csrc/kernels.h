@@ -280,6 +280,44 @@ __global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
   dev_diff_tile<DIR>(a, T, lds_z);
 }
 
+// d_DIR (e - e_ref) of the four state fields into out on a tile that holds
+// two complex lines per grid line: (e0, e1) and (e2, e3) are loaded
+// together, transformed together and stored in one walk.
+template <int DIR>
+__device__ __forceinline__ void dev_diff2_tile(const PassArgs& a, const TileDev& T, float2* lds) {
+  const PlanDev P = a.plans[T.plan];
+  const PlanDev* Pg = a.plans + T.plan;
+  TileDev T2 = T;
+  T2.nl = 2 * T.nl;
+  const LineCtx X = line_setup(lds, T2, P, a.tw, a.km);
+  float2* __restrict__ z = X.z;
+  const int N = P.N, nl = T.nl, ld = T.ld;
+  const long long pl = a.plane;
+  const TileMem M = tile_mem<DIR>(P, T, nl, ld);
+  __syncthreads();
+  const float* u = a.u + M.base;
+  load_differenced<DIR, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, u, u + pl, a.eref[0], a.eref[1], a.d);
+  load_differenced<DIR, kDiffBatch>(X, M.w, M.gmax, N, nl, nl, P.nb1, P.n1, u + 2 * pl, u + 3 * pl, a.eref[2],
+                                    a.eref[3], a.d);
+  FCSD_DIFF_AND_TRANSFORM(a)
+  float2* zb = z + nl;
+  float* o = a.out + M.base;
+  walk(M.w, [&](unsigned g, unsigned l) {
+    const float2 v = at(z, l), w = at(zb, l);
+    at(o, g) = v.x;
+    at(o + pl, g) = v.y;
+    at(o + 2 * pl, g) = w.x;
+    at(o + 3 * pl, g) = w.y;
+  });
+}
+
+template <int DIR>
+__global__ void FCSD_LINE_BOUNDS k_dev_diff2(PassArgs a) {
+  const TileDev T = a.tiles[blockIdx.x];
+  if (T.nl == 0) return;
+  dev_diff2_tile<DIR>(a, T, lds_z);
+}
+
 // Point inputs of all eight H fields (loaded once per point; inputs a flux
 // mode does not use read the metric instead, so every load is issued).
 struct HIn4 {
