@@ -71,8 +71,8 @@ enum { MODE_SET = 0, MODE_ADD = 1, MODE_RK = 2 };
 constexpr int kLoadBatch = 12;  // load phases (two floats each)
 constexpr int kEpiBatch = 8;    // epilogues (point inputs)
 constexpr int kEpiBatchH = 4;   // H epilogue (thirteen inputs per point)
-constexpr int kEpiBatchC = 6;   // stage-update epilogue (six inputs per point)
-constexpr int kDiffBatch = 6;   // differencing loads (four floats each)
+constexpr int kEpiBatchC = 8;   // stage-update epilogue (six inputs per point)
+constexpr int kDiffBatch = 8;   // differencing loads (four floats each)
 enum { FLUX_FULL = 0, FLUX_VISC = 1, FLUX_INVISCID = 2 };
 
 // SSPRK(5,4) Shu-Osher coefficients (five stages, fourth order)
