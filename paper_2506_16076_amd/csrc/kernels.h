@@ -280,6 +280,17 @@ __global__ void FCSD_LINE_BOUNDS k_dev_diff(PassArgs a) {
   dev_diff_tile<DIR>(a, T, lds_z);
 }
 
+// Plain load of a pair of planes into complex line c0 + c of the tile (the
+// differences then come from difference_ext in LDS: two floats per element
+// in flight instead of four, for fields without a reference to subtract).
+__device__ __forceinline__ void load_plain(const LineCtx& X, const Walk& w, int c0, const float* __restrict__ A,
+                                           const float* __restrict__ B) {
+  float2* __restrict__ z = X.z + c0;
+  walk_b<kLoadBatch>(
+      w, [&](unsigned g) { return make_float2(at(A, g), at(B, g)); },
+      [&](unsigned, unsigned l, float2 v) { at(z, l) = v; });
+}
+
 // d_DIR (e - e_ref) of the four state fields into out on a tile that holds
 // two complex lines per grid line: (e0, e1) and (e2, e3) are loaded
 // together, transformed together and stored in one walk.
@@ -471,10 +482,11 @@ __device__ __forceinline__ void passB_tile(const PassArgs& a, const TileDev& T, 
     __syncthreads();
     if (half == 1) break;
     // components 2 and 3 from the stored H
-    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, H + 4 * pl, H + 5 * pl, 0.f, 0.f, a.d);
-    load_differenced<2, kDiffBatch>(X, M.w, M.gmax, N, nl, nl, P.nb1, P.n1, H + 6 * pl, H + 7 * pl, 0.f, 0.f,
-                                    a.d);
-    FCSD_DIFF_AND_TRANSFORM(a)
+    load_plain(X, M.w, 0, H + 4 * pl, H + 5 * pl);
+    load_plain(X, M.w, nl, H + 6 * pl, H + 7 * pl);
+    __syncthreads();
+    difference_ext(X, P, a.dq + P.dq, a.d);
+    fft_apply<false>(X, Pg, P);
   }
 }
 
@@ -846,8 +858,10 @@ __device__ __forceinline__ void passC_tile(const PassArgs& a, const TileDev& Tin
   for (int comp = 0; comp < 4; ++comp) {
     const float* A = a.H + (2 * comp) * pl + M.base;
     const float* B = a.H + (2 * comp + 1) * pl + M.base;
-    load_differenced<1, kDiffBatch>(X, M.w, M.gmax, N, nl, 0, P.nb1, P.n1, A, B, 0.f, 0.f, a.d);
-    FCSD_DIFF_AND_TRANSFORM(a)
+    load_plain(X, M.w, 0, A, B);
+    __syncthreads();
+    difference_ext(X, P, a.dq + P.dq, a.d);
+    fft_apply<false>(X, Pg, P);
     const long long fo = comp * pl + M.base;
     // point inputs: the q1 metric row, r2 and the SSPRK registers of the
     // stage; every load is issued (registers the stage does not use read r2)
