@@ -177,6 +177,7 @@ struct fcsd_set {
   size_t stage_lds = 0;
   int stage_threads = 0;
   bool wide_ok = false;                   // the q2 tiles of four complex lines per grid line fit the LDS
+  bool a_wide = false;                    // pass A on the q1 tiles of two complex lines per grid line
 };
 
 namespace {
@@ -588,6 +589,15 @@ void filter_table(const PlanDev& P, double alpha, int p, std::vector<float>& t) 
 // network's weights let its split fp16 operands leave the fp16 range.
 unsigned* set_error_word(const fcsd_set* s) { return s->d_ctr + 1 + 2 * (size_t)s->npatch; }
 
+// Pass A runs on the q1 tiles of two complex lines per grid line (the four
+// state fields in one round) when those tiles keep within the q1 tiles' LDS
+// (a launch takes its largest tile's LDS; long lines, whose two-line tiles
+// need more, would halve the workgroups per CU for the whole pass).
+bool pick_a_wide(const fcsd_set* s) {
+  const TileSet &one = s->dir[0].ts[0], &two = s->dir[0].ts[1];
+  return two.lds <= std::max(one.lds, one.budget);
+}
+
 // Task queue of the persistent stage kernel from the current tile sets:
 // every A task (q1 tiles in launch order), then the B tasks (q2 tiles with
 // two complex lines per grid line) patch by patch in the order in which the
@@ -767,6 +777,7 @@ extern "C" fcsd_status fcsd_set_create(fcsd_ctx* ctx, int npatch, const fcsd_pat
                       "storage's smallest tile)");
     // the wide fused q2 pass (four complex lines per grid line) is optional
     s->wide_ok = s->dir[1].ts[2].lds <= (size_t)maxlds;
+    s->a_wide = pick_a_wide(s.get());
   }
   // per-patch descriptors and point chunks
   std::vector<PatchDev> pd;
@@ -932,6 +943,7 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const
   }
   if ((r = build_stage_tasks(s))) return r;
   s->wide_ok = s->dir[1].ts[2].lds <= (size_t)maxlds;
+  s->a_wide = pick_a_wide(s);
   if ((s->schedule == FCSD_SCHED_PERSISTENT && s->stage_grid == 0) ||
       (s->schedule == FCSD_SCHED_FUSED_WIDE && !s->wide_ok))
     s->schedule = FCSD_SCHED_FUSED;
@@ -1249,7 +1261,8 @@ fcsd_status rhs_passes(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const f
     if (walls && (passes & 3u))
       if ((st = wall_theta_derivs(ctx, s, u, ref, gamma, patch))) return st;
     if (passes & 1u) {
-      if ((st = launch_lines(s, 1, k_dev_diff2<1>, a, patch, 2))) return st;
+      st = s->a_wide ? launch_lines(s, 1, k_dev_diff2<1>, a, patch, 2) : launch_lines(s, 1, k_dev_diff<1>, a, patch);
+      if (st) return st;
       if (walls) {
         const ChunkDev* ch;
         int n;
@@ -2351,7 +2364,8 @@ fcsd_status rhs_adj_impl(fcsd_ctx* ctx, const fcsd_set* s, const float* u, const
     if (!given1) {
       b.out = w;
       b.plans = s->dir[0].d_plans;
-      if ((st = launch_lines(s, 1, k_dev_diff2<1>, b, -1, 2))) return st;
+      if ((st = s->a_wide ? launch_lines(s, 1, k_dev_diff2<1>, b, -1, 2) : launch_lines(s, 1, k_dev_diff<1>, b)))
+        return st;
       if (walls)
         hipLaunchKernelGGL(k_energy_rule, dim3(chunk_grid(s->nwchunks)), dim3(kBlock), 0, ctx->stream, s->d_wchunks,
                            s->nwchunks, s->d_patches, u, pl, gamma - 1.0f, D1TH, w);
