@@ -2586,9 +2586,10 @@ extern "C" fcsd_status fcsd_step_adj(fcsd_ctx* ctx, const fcsd_set* s, const fcs
   float* uib = UIB;
   for (int k = 4; k >= 0; --k) {
     float* tgt = k > 0 ? uib : U0B;
-    if (k > 0) hipLaunchKernelGGL(k_fill, dim3(b4), dim3(kBlock), 0, sm, uib, 0.f, n4);
+    // the stage's u_i cotangent starts from its register-update share
+    // (written, not accumulated)
     hipLaunchKernelGGL(k_rk_adj, dim3(b4), dim3(kBlock), 0, sm, k, a->dt_dev, (const float*)yb, U0B, uib, ACCB, RB,
-                       n4);
+                       n4, true);
     if ((st = launch_check(ctx, "step_adj rk"))) return st;
     const float* g1 = have && mu ? a->record + kRecD1 * pl + k * n4 : nullptr;
     const float* g2 = have && mu ? a->record + kRecD2 * pl + k * n4 : nullptr;

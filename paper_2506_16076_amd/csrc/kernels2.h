@@ -430,12 +430,37 @@ __global__ void __launch_bounds__(kBlock) k_rk(int stage, const float* dtp, cons
 // reverse of k_rk; rhs_bar is overwritten (each stage's r is used once)
 __global__ void __launch_bounds__(kBlock) k_rk_adj(int stage, const float* dtp, const float* ob,
                                                    float* u0b, float* uib, float* accb, float* rb,
-                                                   long long n4) {
+                                                   long long n4, bool fresh = false) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n4) return;
   const RkCoef K = rk_coef(stage);
   const float dt = dtp[0];
   const float y = ob[g];
+  if (fresh && stage > 0) {
+    // uib starts at zero (written, not accumulated): the same values as
+    // accumulating into a zero-filled uib, without the fill and its read
+    if (stage == 1) {
+      u0b[g] += K.a0 * y;
+      uib[g] = K.ai * y;
+      rb[g] = K.b * dt * y;
+    } else if (stage == 2) {
+      const float ab = accb[g];
+      u0b[g] += K.a0 * y;
+      uib[g] = K.ai * y + K.acc_i * ab;
+      rb[g] = K.b * dt * y;
+      accb[g] = 0.f;
+    } else if (stage == 3) {
+      const float ab = accb[g];
+      u0b[g] += K.a0 * y;
+      uib[g] = K.ai * y + K.acc_i * ab;
+      rb[g] = dt * (K.b * y + K.acc_b * ab);
+    } else {
+      accb[g] += y;
+      uib[g] = K.ai * y;
+      rb[g] = K.b * dt * y;
+    }
+    return;
+  }
   if (stage == 0) {
     u0b[g] += y;
     rb[g] = K.b * dt * y;
