@@ -948,63 +948,85 @@ __global__ void __launch_bounds__(kBlock) k_sdnn(const ChunkDev* __restrict__ ch
 
 // ---------------------------------------------------------------- 7x7 max
 
-// max over i-3..i+3 (clamped) with the first maximiser
-__global__ void __launch_bounds__(kBlock) k_rowmax(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
-                                                   const float* S, float* rmax, int* rarg) {
+// max over i-3..i+3 (clamped) with the first maximiser.  The seven samples
+// are loaded together at clamped indices (32-bit offsets from the patch's
+// first storage element; BLK: 8x4-blocked storage); scanning them in order
+// with a strict comparison keeps the first maximiser of the clamped range
+// i-3..i+3 (a clamped duplicate repeats an end value at the same index).
+template <bool BLK>
+__device__ __forceinline__ void rowmax_point(const PatchDev& P, int k, const float* __restrict__ S, float* rmax,
+                                             int* rarg) {
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+  const float* base = S + P.off;
+  float v[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) v[q] = ld_off(base, poff<BLK>(P, min(max(i + q - 3, 0), P.n1 - 1), j));
+  float best = v[0];
+  int bi = max(i - 3, 0);
+#pragma unroll
+  for (int q = 1; q < 7; ++q)
+    if (v[q] > best) {
+      best = v[q];
+      bi = min(i + q - 3, P.n1 - 1);
+    }
+  (rmax + P.off)[k] = best;
+  (rarg + P.off)[k] = bi;
+}
+
+__global__ void __launch_bounds__(kBlock) k_rowmax(const ChunkDev* __restrict__ chunks, int nchunks,
+                                                   const PatchDev* __restrict__ patches, const float* S, float* rmax,
+                                                   int* rarg) {
   for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
     const PatchDev P = patches[ck.patch];
     const int k = ck.start + threadIdx.x;
-    int i, j;
-    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-    // the seven samples are loaded together at clamped indices; scanning
-    // them in order with a strict comparison keeps the first maximiser of
-    // the clamped range i-3..i+3 (a clamped duplicate repeats an end value
-    // at the same index)
-    float v[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) v[q] = S[pidx(P, min(max(i + q - 3, 0), P.n1 - 1), j)];
-    float best = v[0];
-    int bi = max(i - 3, 0);
-#pragma unroll
-    for (int q = 1; q < 7; ++q)
-      if (v[q] > best) {
-        best = v[q];
-        bi = min(i + q - 3, P.n1 - 1);
-      }
-    rmax[P.off + k] = best;
-    rarg[P.off + k] = bi;
+    if (P.nb1)
+      rowmax_point<true>(P, k, S, rmax, rarg);
+    else
+      rowmax_point<false>(P, k, S, rmax, rarg);
   });
 }
 
 // column pass of the 7x7 max and mu^ = R(tau) max S h^ on D~ (0 elsewhere)
-__global__ void __launch_bounds__(kBlock) k_muhat(const ChunkDev* chunks, int nchunks, const PatchDev* patches,
-                                                  const float* rmax, const int* rarg,
-                                                  const signed char* tau, float* muh, int* argmax) {
+template <bool BLK>
+__device__ __forceinline__ void muhat_point(const PatchDev& P, int k, const float* __restrict__ rmax,
+                                            const int* __restrict__ rarg, const signed char* tau, float* muh,
+                                            int* argmax) {
+  int i, j;
+  if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
+  const float* base = rmax + P.off;
+  float v[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) v[q] = ld_off(base, poff<BLK>(P, i, min(max(j + q - 3, 0), P.n2 - 1)));
+  float best = v[0];
+  int bj = max(j - 3, 0);
+#pragma unroll
+  for (int q = 1; q < 7; ++q)
+    if (v[q] > best) {
+      best = v[q];
+      bj = min(j + q - 3, P.n2 - 1);
+    }
+  if (argmax) (argmax + P.off)[k] = bj * P.n1 + (rarg + P.off)[poff<BLK>(P, i, bj)];
+  float m = 0.f;
+  if (in_dtilde(P, i, j)) {
+    const int t = (tau + P.off)[k];
+    const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
+    m = R * best * P.hhat;
+  }
+  (muh + P.off)[k] = m;
+}
+
+__global__ void __launch_bounds__(kBlock) k_muhat(const ChunkDev* __restrict__ chunks, int nchunks,
+                                                  const PatchDev* __restrict__ patches, const float* rmax,
+                                                  const int* rarg, const signed char* tau, float* muh,
+                                                  int* argmax) {
   for_chunks(chunks, nchunks, [&](const ChunkDev ck) {
     const PatchDev P = patches[ck.patch];
     const int k = ck.start + threadIdx.x;
-    int i, j;
-    if (k >= pstore(P) || !pdecode(P, k, i, j)) return;
-    float v[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) v[q] = rmax[pidx(P, i, min(max(j + q - 3, 0), P.n2 - 1))];
-    float best = v[0];
-    int bj = max(j - 3, 0);
-#pragma unroll
-    for (int q = 1; q < 7; ++q)
-      if (v[q] > best) {
-        best = v[q];
-        bj = min(j + q - 3, P.n2 - 1);
-      }
-    const long long g = P.off + k;
-    if (argmax) argmax[g] = bj * P.n1 + rarg[pidx(P, i, bj)];
-    float m = 0.f;
-    if (in_dtilde(P, i, j)) {
-      const int t = tau[g];
-      const float R = t == 1 ? 1.5f : (t == 2 ? 1.0f : (t == 3 ? 0.5f : 0.0f));
-      m = R * best * P.hhat;
-    }
-    muh[g] = m;
+    if (P.nb1)
+      muhat_point<true>(P, k, rmax, rarg, tau, muh, argmax);
+    else
+      muhat_point<false>(P, k, rmax, rarg, tau, muh, argmax);
   });
 }
 
