@@ -244,7 +244,7 @@ def main():
         print(json.dumps(oracle_configs()), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: the library runs on one GPU; --gpus must be 1 "
               "(multi-GPU sharding by whole patches is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
