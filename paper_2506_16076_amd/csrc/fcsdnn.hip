@@ -487,7 +487,13 @@ void build_tileset(const std::vector<PlanDev>& plans, TileSet& D, size_t budget,
       T.line0 = t * nl;
       T.nl = std::min(nl, P.nlines - T.line0);
       if (T.nl <= 0) continue;
+      // odd row stride (the line-fastest FFT accesses and the position-fastest
+      // loads both free of LDS bank conflicts), or the even one when only
+      // that keeps the tile within the budget: two workgroups per CU instead
+      // of one are worth far more than the conflicts (the q2 tiles of two
+      // complex lines per grid line on the longest lines: 83 KB odd, 79 KB even)
       T.ld = (fields * T.nl) | 1;
+      if (per_ld * T.ld + tables > budget && per_ld * (fields * T.nl) + tables <= budget) T.ld = fields * T.nl;
       D.tiles_by_patch.push_back(T);
       plds = std::max(plds, per_ld * T.ld + tables);
       cost += (long long)P.L * T.nl;
