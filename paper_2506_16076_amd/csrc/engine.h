@@ -324,6 +324,10 @@ __device__ __forceinline__ void walk_b(Walk w, Pre&& pre, Post&& post) {
   }
 }
 
+// Largest radix whose stage reads all its twiddles before the butterfly
+// (larger ones would need more registers than the line kernels have).
+constexpr int kTwPre = 12;
+
 // One radix-R stage.  Forward (DIF): block of M points, m = M/R, butterfly j
 // reads x_t = z[base + j + t m], y = DFT_R(x), y_q *= w_M^(j q), stores back.
 // Inverse (DIT): the exact reverse with conjugate twiddles.  MUL (last
@@ -331,10 +335,6 @@ __device__ __forceinline__ void walk_b(Walk w, Pre&& pre, Post&& post) {
 // km[pos] (CONJ: by its conjugate, the transposed operator) and apply the
 // first inverse stage, which works on the same R contiguous samples without
 // twiddles, before storing: one LDS round trip and one barrier fewer.
-// Largest radix whose stage reads all its twiddles before the butterfly
-// (larger ones would need more registers than the line kernels have).
-constexpr int kTwPre = 12;
-
 template <int R, bool INV, bool MUL, bool CONJ>
 __device__ __forceinline__ void fft_stage(const LineCtx& X, int L, int M) {
   if (!X.active) return;
