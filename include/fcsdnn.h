@@ -123,14 +123,19 @@ enum {
 };
 /* Re-split the line tiles of a set.  Three tile sets: [0] q1 lines (passes
  * A, C), [1] q2 lines (pass B2, transposes), [2] q2 lines holding two
- * complex lines per grid line (pass B1).  For each, the workgroup LDS
- * budget in bytes (8 KB .. 160 KB; default 64 KB or the FCSD_LDS_BUDGET
- * environment variable at creation) and the workgroup size (64, 128, 256,
- * 512 or 1024 threads; default 256); and the launch order of all tiles.
- * Larger budgets mean more lines per tile, fewer workgroups per compute
- * unit; larger workgroups put more threads on each line.  Synchronises the
- * context's stream and drops captured step graphs.  Returns FCSD_EINVAL for
- * an out-of-range argument.  Used by the autotuner. */
+ * complex lines per grid line (pass B1, the fused B pass).  For each, the
+ * workgroup LDS budget in bytes (8 KB .. 160 KB; default 64 KB or the
+ * FCSD_LDS_BUDGET environment variable at creation) and the workgroup size
+ * (64, 128, 256, 512 or 1024 threads; default 256); and the launch order of
+ * all tiles.  Larger budgets mean more lines per tile, fewer workgroups per
+ * compute unit; larger workgroups put more threads on each line.  A tile
+ * whose smallest storage-aligned size exceeds its budget takes more (a
+ * launch takes its largest tile's LDS); the q2 tiles of four complex lines
+ * per grid line (the wide fused pass, the reverse mode's q2 pass) share the
+ * third budget and workgroup size, and when their tiles exceed it they are
+ * built for the device's whole LDS per workgroup with 1024 threads.
+ * Synchronises the context's stream and drops captured step graphs.  Returns
+ * FCSD_EINVAL for an out-of-range argument.  Used by the autotuner. */
 fcsd_status fcsd_set_tune(fcsd_set* set, const int lds_budget[3], const int threads[3], int order);
 
 /* How the line passes of one right-hand side or stage are launched (the

@@ -945,6 +945,18 @@ extern "C" fcsd_status fcsd_set_tune(fcsd_set* s, const int lds_budget[3], const
   for (int dir = 0; dir < 2; ++dir) {
     DirPlan& D = s->dir[dir];
     build_tiles(D, order, tile_align(s->layout, dir), s->d);
+    if (dir == 1) {
+      // q2 tiles of four complex lines per grid line (the wide fused pass,
+      // the reverse mode's q2 pass): when their tiles exceed the third
+      // budget (its smallest storage-aligned tiles do not fit), they are
+      // built for the device's whole LDS with 1024-thread workgroups
+      TileSet& W = D.ts[2];
+      if (W.lds > W.budget && W.budget < (size_t)maxlds) {
+        W.budget = (size_t)maxlds;
+        W.threads = 1024;
+        build_tileset(D.plans, W, W.budget, order, 4, tile_align(s->layout, dir), s->d);
+      }
+    }
     if ((r = upload_tiles(ctx, D))) return r;
   }
   if ((r = build_stage_tasks(s))) return r;
